@@ -1,0 +1,38 @@
+"""Brute-force enumeration over every field configuration of a tiny system.
+
+Eq. (obs): <O> = sum_C P(C) <<O>>_C with P(C) proportional to the weight of
+Eq. (partition_2).  For N L <= ~10 all 2^(N L) Ising configurations are summed
+exactly; the result is the Trotterised expectation value with no sampling
+error, which the tests compare with a Fock-space evaluation.
+"""
+import itertools
+
+import numpy as np
+
+from .measure import equal_time
+from .stable import green_scratch, log_weight
+
+
+def all_fields(model):
+    for bits in itertools.product((1.0, -1.0), repeat=model.L * model.N):
+        yield np.array(bits).reshape(model.L, model.N)
+
+
+def enumerate_observables(model, taus=(0,)):
+    """Exact weighted averages of (D, E_kin, E_pot) at each tau in taus."""
+    logw = []
+    obs = []
+    for f in all_fields(model):
+        logw.append(log_weight(model, f))
+        obs.append([equal_time(model, green_scratch(model, f, t)) for t in taus])
+    logw = np.array(logw)
+    w = np.exp(logw - logw.max())
+    obs = np.array(obs)                                # [configs, taus, 3]
+    return np.einsum("c,ctk->tk", w, obs) / w.sum()
+
+
+def enumerate_weights(model):
+    """Normalised P(C) over all configurations (in itertools order)."""
+    logw = np.array([log_weight(model, f) for f in all_fields(model)])
+    w = np.exp(logw - logw.max())
+    return w / w.sum()

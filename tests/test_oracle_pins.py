@@ -1,0 +1,287 @@
+"""Pins of the oracle against facts that do not come from the oracle itself.
+
+Each test fixes a part of the oracle with something independent: a published
+generator, a closed form, an exact enumeration against a Fock-space Trotter
+product, a matrix identity, or a 60-digit mpmath evaluation.  A plausible
+mistake (a dropped prefactor, a wrong sign of alpha, a transposed product, a
+wrong rotation of the measured G, a wrong chunk in the stabilisation) fails at
+least one of them.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+from fock import Fock
+from inputs import square_lattice, honeycomb_lattice
+from oracle import exact_small, hubbard, measure, philox, stable, sweep
+
+
+# ---------------------------------------------------------------- generator --
+@pytest.mark.parametrize("key,ctr", [((0, 0), (0, 0, 0, 0)), ((12345, 0), (7, 3, 41, 5)),
+                                     ((2**64 - 1, 17), (1, 2**63, 2**40 + 3, 99))])
+def test_philox_matches_numpy(key, ctr):
+    # numpy's Philox increments its 256-bit counter before producing a block
+    bg = np.random.Philox(key=np.array(key, dtype=np.uint64), counter=np.array(ctr, dtype=np.uint64))
+    raw = [int(x) for x in bg.random_raw(8)]
+    c1 = list(ctr)
+    c1[0] = (c1[0] + 1) % 2**64
+    assert list(philox.philox4x64_10(c1, key)) == raw[:4]
+    c2 = list(c1)
+    c2[0] += 1
+    assert list(philox.philox4x64_10(c2, key)) == raw[4:]
+    v = philox.philox4x64_10_vec(*[np.array([c], dtype=np.uint64) for c in c1], key)
+    assert [int(x[0]) for x in v] == raw[:4]
+
+
+def test_uniform_and_normal_ranges():
+    u = philox.uniforms(3, philox.TAG_FLIP, 5, 7, 1, 4096)
+    assert u.min() >= 0.0 and u.max() < 1.0
+    assert abs(u.mean() - 0.5) < 0.02
+    z = philox.normals(3, philox.TAG_INIT, 0, 1, 0, 20000)
+    assert abs(z.mean()) < 0.05 and abs(z.std() - 1.0) < 0.05
+
+
+# ----------------------------------------------------------- HS identities --
+@pytest.mark.parametrize("U,dtau", [(4.0, 0.1), (5.0, 0.1), (8.0, 0.05)])
+def test_hs_identities(U, dtau):
+    lam = hubbard.ising_coupling(U, dtau)
+    for n in (0, 1, 2):
+        lhs = np.exp(dtau * U / 2 * (n - 1) ** 2)
+        rhs = 0.5 * sum(np.exp(lam * s * (n - 1)) for s in (1, -1))
+        assert abs(lhs - rhs) < 1e-14 * lhs
+    c = hubbard.gauss_coupling(U, dtau)
+    x, w = np.polynomial.hermite_e.hermegauss(80)      # weight exp(-x^2/2)
+    for A in (-1.0, 0.0, 1.0, 2.0):
+        quad = np.sum(w * np.exp(c * x * A)) / np.sqrt(2 * np.pi)
+        assert abs(quad - np.exp(dtau * U / 2 * A * A)) < 1e-13
+
+
+# -------------------------------------------------------- U = 0 closed form --
+def _square_u0_green(L1, L2, beta):
+    """(1 + exp(-beta K))^-1 on the square lattice from plane waves and the
+    dispersion eps_k = -2 (cos kx + cos ky), not from an eigensolver."""
+    n = L1 * L2
+    xs = np.array([(i % L1, i // L1) for i in range(n)], dtype=float)
+    G = np.zeros((n, n), dtype=complex)
+    ekin = 0.0
+    for a in range(L1):
+        for b in range(L2):
+            k = np.array([2 * np.pi * a / L1, 2 * np.pi * b / L2])
+            eps = -2.0 * (np.cos(k[0]) + np.cos(k[1]))
+            ph = np.exp(1j * xs @ k)
+            occ_hole = 1.0 / (1.0 + np.exp(-beta * eps))      # 1 - f(eps)
+            G += np.outer(ph, ph.conj()) * occ_hole / n
+            ekin += 2.0 * eps / (np.exp(beta * eps) + 1.0) / n
+    return G.real, ekin
+
+
+@pytest.mark.parametrize("beta,trotter", [(2.0, "sym"), (40.0, "asym"), (40.0, "sym")])
+def test_u0_closed_form(beta, trotter):
+    lat = square_lattice(4, 4)
+    m = hubbard.hubbard_model(lat.K, 0.0, beta, 0.1, 10, trotter=trotter)
+    f = hubbard.init_field(m)
+    G0, ekin0 = _square_u0_green(4, 4, beta)
+    for tau in (0, 3, 10, m.L // 2 + 7, m.L):
+        G = stable.green_scratch(m, f, tau)
+        assert np.max(np.abs(G - G0)) < 1e-12
+        D, ekin, _ = measure.equal_time(m, G)
+        assert abs(ekin - ekin0) < 1e-12
+
+
+# ------------------------------------------------------------ atomic limit --
+def test_atomic_limit_double_occupancy():
+    """t = 0: D = 1 / (2 (1 + exp(beta U / 2))) exactly, for any dtau."""
+    U, beta = 4.0, 2.0
+    m = hubbard.hubbard_model(np.zeros((1, 1)), U, beta, beta / 8, 4)
+    res = exact_small.enumerate_observables(m, taus=(0, 5))
+    exact = 1.0 / (2.0 * (1.0 + np.exp(beta * U / 2)))
+    assert abs(exact - 0.0089931) < 1e-7
+    assert np.max(np.abs(res[:, 0] - exact)) < 1e-14
+    assert np.max(np.abs(res[:, 2] - U * exact)) < 1e-13
+
+
+# ------------------------------------------------- 2 sites x 4 slices exact --
+@pytest.mark.parametrize("trotter", ["sym", "asym"])
+def test_two_site_enumeration_equals_fock_trotter(trotter):
+    K = np.array([[0.0, -1.0], [-1.0, 0.0]])
+    U, dtau, L = 4.0, 0.25, 4
+    m = hubbard.hubbard_model(K, U, L * dtau, dtau, 2, trotter=trotter)
+    res = exact_small.enumerate_observables(m, taus=(0, 1, 2, 3))
+    F = Fock(K, U)
+    S = F.trotter(dtau) if trotter == "sym" else F.trotter_asym(dtau)
+    D = F.expect_with(S, F.double_occ(), L)
+    E = F.expect_with(S, F.kinetic(), L)
+    assert np.max(np.abs(res[:, 0] - D)) < 1e-13
+    assert np.max(np.abs(res[:, 1] - E)) < 1e-13
+
+
+def test_two_site_enumeration_detects_wrong_alpha():
+    """Planted mistake on the CPU: flipping the sign of alpha moves D away
+    from the Fock-space value, so the pin above is sensitive to it."""
+    K = np.array([[0.0, -1.0], [-1.0, 0.0]])
+    U, dtau, L = 4.0, 0.25, 4
+    m = hubbard.hubbard_model(K, U, L * dtau, dtau, 2)
+    m.alpha = +0.5
+    res = exact_small.enumerate_observables(m, taus=(0,))
+    F = Fock(K, U)
+    D = F.expect(F.double_occ(), dtau, L)
+    assert abs(res[0, 0] - D) > 1e-3
+
+
+# ---------------------------------------------------------------- invariants --
+@pytest.fixture(scope="module")
+def c1_like():
+    lat = square_lattice(4, 4)
+    m = hubbard.hubbard_model(lat.K, 4.0, 2.0, 0.1, 10, seed=0)
+    return m, hubbard.init_field(m)
+
+
+def test_sm_ratio_equals_determinant_ratio(c1_like):
+    m, f = c1_like
+    rng = np.random.default_rng(1)
+    for _ in range(6):
+        tau = int(rng.integers(1, m.L + 1))
+        i = int(rng.integers(0, m.N))
+        G = stable.green_scratch(m, f, tau)
+        s = f[tau - 1, i]
+        delta = np.exp(m.coupling * (-2 * s)) - 1.0
+        r = 1.0 + delta * (1.0 - G[i, i])
+        R = np.exp(m.n_col * m.coupling * m.alpha * (-2 * s)) * r ** m.n_col
+        f2 = f.copy()
+        f2[tau - 1, i] = -s
+        R_full = np.exp(stable.log_weight(m, f2) - stable.log_weight(m, f))
+        assert abs(R - R_full) < 1e-11 * max(1.0, abs(R_full))
+
+
+def test_sm_update_equals_scratch(c1_like):
+    m, f = c1_like
+    ch = sweep.Chain(m, f.copy())
+    tau, i = 7, 5
+    ch.G = stable.green_scratch(m, ch.field, tau)
+    assert ch._propose(tau, i, u=0.0, u1=0.0)        # u = 0 always accepts
+    assert np.max(np.abs(ch.G - stable.green_scratch(m, ch.field, tau))) < 1e-12
+
+
+def test_wrap_equals_scratch(c1_like):
+    m, f = c1_like
+    for tau in (1, 5, 11, 20):
+        Gm = stable.green_scratch(m, f, tau - 1)
+        Gw = m.B(f, tau) @ Gm @ m.B_inv(f, tau)
+        assert np.max(np.abs(Gw - stable.green_scratch(m, f, tau))) < 1e-11
+        Gd = m.B_inv(f, tau) @ stable.green_scratch(m, f, tau) @ m.B(f, tau)
+        assert np.max(np.abs(Gd - Gm)) < 1e-11
+
+
+def test_green_scratch_independent_of_n_wrap(c1_like):
+    m, f = c1_like
+    m5 = hubbard.hubbard_model(m.K, 4.0, 2.0, 0.1, 5, seed=0)
+    for tau in (0, 4, 13):
+        assert np.max(np.abs(stable.green_scratch(m, f, tau) - stable.green_scratch(m5, f, tau))) < 1e-12
+
+
+def test_stable_green_vs_mpmath():
+    """beta = 12, L = 120 on a 2x2 square: cond(1 + B) ~ 1e13; the stabilised
+    G agrees with a 60-digit evaluation, the plain inverse does not."""
+    import mpmath as mp
+    mp.mp.dps = 60
+    lat = square_lattice(2, 2)
+    m = hubbard.hubbard_model(lat.K, 4.0, 12.0, 0.1, 10, seed=4)
+    f = hubbard.init_field(m)
+    E = mp.expm(mp.matrix((-m.dtau * lat.K).tolist()))
+    lam = mp.acosh(mp.e ** (mp.mpf(m.dtau) * 4 / 2))
+    P = mp.eye(m.N)
+    for tau in range(1, m.L + 1):
+        Dg = mp.diag([mp.e ** (lam * int(s)) for s in f[tau - 1]])
+        P = Dg * E * P
+    Gmp = (mp.eye(m.N) + P) ** -1
+    Gref = np.array(Gmp.tolist(), dtype=float)
+    G = stable.green_scratch(m, f, 0)
+    assert np.max(np.abs(G - Gref)) < 1e-10
+    lin = np.abs(np.linalg.slogdet(np.eye(m.N) + np.array(P.tolist(), dtype=float))[1])
+    assert abs(stable.logdet_scratch(m, f) - float(mp.log(abs(mp.det(mp.eye(m.N) + P))))) < 1e-9 * lin
+
+
+def test_sweep_precision_and_scratch(c1_like):
+    m, f = c1_like
+    ch = sweep.Chain(m, f.copy()).init()
+    for _ in range(3):
+        ch.sweep()
+    assert np.mean(ch.prec) < 1e-8         # the paper's recommended mean precision
+    assert np.max(np.abs(ch.G - stable.green_scratch(m, ch.field, 0))) < 1e-10
+    d = ch.bins / ch.bins[3]
+    assert 0.0 < d[0] < 0.25 and d[1] < 0
+
+
+def test_half_filling_density(c1_like):
+    m, f = c1_like
+    for tau in (0, 9):
+        G = stable.green_scratch(m, f, tau)
+        # particle-hole symmetry of the sampling frame at mu = 0 is a property of
+        # the ensemble, not of one field; check only the range here
+        n = measure.density(m, G)
+        assert 0.0 < n < 2.0
+
+
+# ------------------------------------------------------------ MC sampler --
+def test_mc_histogram_matches_exact_weights():
+    """Stationarity of the sequential single-flip chain (section "The default:
+    sequential single spin flips"): the visited configurations of a 2-site x
+    4-slice chain follow W(C)/Z."""
+    K = np.array([[0.0, -1.0], [-1.0, 0.0]])
+    m = hubbard.hubbard_model(K, 4.0, 1.0, 0.25, 2, seed=11)
+    p = exact_small.enumerate_weights(m)
+    index = {tuple(fl.ravel()): j for j, fl in enumerate(exact_small.all_fields(m))}
+    ch = sweep.Chain(m, hubbard.init_field(m)).init()
+    counts = np.zeros(p.size)
+    n_sweeps = 4000
+    for _ in range(n_sweeps):
+        ch.sweep(measure=False)
+        counts[index[tuple(ch.field.ravel())]] += 1
+    # chi^2 per degree of freedom; successive sweeps are mildly correlated, so
+    # allow a factor of ~2 over the independent-sample value of 1
+    chi2 = np.sum((counts - n_sweeps * p) ** 2 / (n_sweeps * p)) / (p.size - 1)
+    assert chi2 < 2.0
+    # the same counts against a planted wrong weight (sign of alpha) fail clearly
+    m2 = hubbard.hubbard_model(K, 4.0, 1.0, 0.25, 2)
+    m2.alpha = 0.5
+    p2 = exact_small.enumerate_weights(m2)
+    chi2_wrong = np.sum((counts - n_sweeps * p2) ** 2 / (n_sweeps * p2)) / (p.size - 1)
+    assert chi2_wrong > 5.0
+
+
+# --------------------------------------------------------------- jackknife --
+def test_jackknife_reduces_to_mean_and_stderr():
+    x = np.random.default_rng(0).normal(size=37)
+    mean, err = measure.jackknife(x)
+    assert abs(mean - x.mean()) < 1e-14
+    assert abs(err - x.std(ddof=1) / np.sqrt(x.size)) < 1e-14
+
+
+# ---------------------------------------------------------------- lattices --
+def test_honeycomb_lattice_structure():
+    lat = honeycomb_lattice(3, 3)
+    K = lat.K
+    assert np.allclose(K, K.T)
+    assert np.all(np.sum(K != 0, axis=1) == 3)            # coordination 3
+    s = lat.sublattice_sign()
+    assert np.all(K * np.outer(s, s) >= 0)                 # hops only between sublattices
+    w = np.linalg.eigvalsh(K)
+    assert abs(w.min() + 3.0) < 1e-12 and abs(w.max() - 3.0) < 1e-12
+
+
+# ------------------------------------------------------------------ golden --
+def test_oracle_golden_trajectory():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "square4x4_U4_b2_3sweeps.json")
+    g = json.load(open(path))
+    lat = square_lattice(4, 4)
+    m = hubbard.hubbard_model(lat.K, 4.0, 2.0, 0.1, 10, trotter="sym", seed=0)
+    ch = sweep.Chain(m, hubbard.init_field(m)).init()
+    for _ in range(3):
+        ch.sweep()
+    assert ch.accepted == g["accepted"] and ch.proposals == g["proposals"]
+    assert np.array_equal(ch.field.astype(int), np.array(g["field"]))
+    assert np.max(np.abs(ch.G - np.array(g["G0"]))) < 1e-12
+    assert np.max(np.abs(ch.bins - np.array(g["bins"]))) < 1e-10
