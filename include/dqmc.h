@@ -1,0 +1,152 @@
+/*
+ * dqmc.h -- C ABI of the MI355X (gfx950) determinant quantum Monte Carlo sweep.
+ *
+ * The library runs the Monte Carlo sweep of the finite-temperature
+ * auxiliary-field (BSS) method documented in ALF 1.0 (arXiv:1704.00131):
+ * weight ratios from the equal-time Green's function, Sherman-Morrison updates
+ * of G, wraps G -> B_tau G B_tau^-1, QR/UDV-stabilised recomputation of G every
+ * n_wrap slices, and equal-time measurements.  All arithmetic is FP64 on the
+ * GPU; the host side only checks arguments and enqueues kernels.
+ *
+ * Conventions shared by all calls
+ * -------------------------------
+ *  - Every function returns a dqmc_status and never throws.  On failure the
+ *    text of the last error is available from dqmc_last_error().
+ *  - Matrices are row-major FP64, n x n, leading dimension n.
+ *  - The field is FP64 [n_slices][n]: field[(tau-1)*n + i] is the
+ *    Hubbard-Stratonovich field of vertex i on slice tau (the paper's nsigma
+ *    array, section "The SU(2)-Hubbard model on a square lattice").  An Ising
+ *    field holds +1.0 / -1.0, a Gaussian field any real value.
+ *  - Device buffers are allocated and owned by the caller (for example torch
+ *    tensors); they must stay alive while they are bound.  The library never
+ *    allocates or frees device memory of its own.  Host inputs are copied
+ *    during the call that receives them.
+ *  - All device work of a context is enqueued on the stream given to
+ *    dqmc_bind(); calls that return host data synchronise that stream.
+ */
+#ifndef DQMC_H
+#define DQMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DQMC_OK = 0,
+  DQMC_E_ARG = 1,          /* invalid argument, detected on the host before any launch      */
+  DQMC_E_UNSUPPORTED = 2,  /* valid in the paper's general model but not built here          */
+  DQMC_E_DEVICE = 3,       /* a HIP call failed                                              */
+  DQMC_E_NUMERIC = 4,      /* NaN/Inf in G, vanishing QR scale, or precision above threshold */
+  DQMC_E_NOMEM = 5,        /* host allocation failed                                         */
+  DQMC_E_STATE = 6         /* call out of order (not bound / not initialised / poisoned)     */
+} dqmc_status;
+
+typedef enum { DQMC_FIELD_ISING = 0, DQMC_FIELD_GAUSS = 1 } dqmc_field_kind;
+typedef enum { DQMC_TROTTER_ASYM = 0, DQMC_TROTTER_SYM = 1 } dqmc_trotter;
+
+/*
+ * Model of one Markov chain (section "Definition of the Hamiltonian",
+ * Eqs. (general_ham_t) and (general_ham_v), with M_T = 1, N_fl = 1 and one
+ * single-site vertex per orbital, V^(k) = e_k e_k^T).
+ *
+ * The slice propagator sampled is B_tau = exp(V_tau) exp(-dtau K) with
+ * exp(V_tau) = diag(exp(coupling * field[tau])); its determinant product equals
+ * that of Eq. (Green_eq) and of a symmetric split.  The configuration weight is
+ * exp(n_col * coupling * alpha * sum(field)) det(1 + B(beta,0))^n_col
+ * (Eq. (partition_2)), times exp(-sum(field^2)/2) for a Gaussian field.
+ */
+typedef struct {
+  int32_t n;               /* N_dim, number of orbitals, 1 <= n <= 1024                       */
+  int32_t n_slices;        /* L_Trotter; |beta - n_slices*dtau| <= 1e-12*beta                  */
+  double beta, dtau;
+  int32_t n_wrap;          /* slices between stabilisations; n_slices % n_wrap == 0            */
+  int32_t n_col;           /* N_col (N_SUN): weight carries det(...)^n_col, 1 or 2             */
+  dqmc_field_kind field;
+  double coupling;         /* lambda (Ising) or c (Gaussian)                                  */
+  double alpha;            /* the constant of (V + alpha) in Eq. (general_ham_v)              */
+  double u_int;            /* U, used only by the potential-energy estimator E_pot = U D     */
+  dqmc_trotter trotter;    /* SYM: measure exp(-dtau K/2) G exp(+dtau K/2)                    */
+  double prec_threshold;   /* max |G_wrapped - G_scratch| tolerated; <= 0: never trip         */
+  double prop_width;       /* Gaussian local move phi' = phi + prop_width*(2u-1)              */
+  uint64_t seed;           /* Philox key of the chain                                         */
+} dqmc_model;
+
+typedef struct { size_t G, field, slots, work; } dqmc_sizes;     /* bytes of each device buffer */
+typedef struct { void *G, *field, *slots, *work; } dqmc_buffers; /* caller-owned device memory  */
+
+typedef struct {
+  uint64_t proposals, accepted;  /* cumulative since dqmc_init                               */
+  double prec_mean, prec_max;    /* wrapped vs recomputed G over all stabilisations so far   */
+  uint64_t n_prec;               /* number of stabilisations counted                         */
+  double seconds;                /* host wall time of the last dqmc_sweep call               */
+} dqmc_stats;
+
+typedef struct dqmc_ctx dqmc_ctx;
+
+/* Byte sizes of the device buffers for a model.  G: n*n doubles; field:
+ * n_slices*n doubles; slots: the UDV storage of Algorithm 1,
+ * (n_slices/n_wrap + 1) * (2 n^2 + n) doubles; work: scratch.  DQMC_E_ARG on
+ * an inconsistent model. */
+dqmc_status dqmc_query_sizes(const dqmc_model* model, dqmc_sizes* out);
+
+/* Create a context.  K: n*n host hopping matrix (Eq. (general_ham_t), the
+ * paper's T), must be symmetric (DQMC_E_ARG otherwise) and is copied.
+ * vertex_site: NULL or the identity map 0..n-1 (one vertex per orbital);
+ * anything else is DQMC_E_UNSUPPORTED.  No device work happens here. */
+dqmc_status dqmc_create(const dqmc_model* model, const double* K, const int32_t* vertex_site,
+                        dqmc_ctx** out);
+
+/* Bind caller-owned device buffers (sizes from dqmc_query_sizes, 256-byte
+ * aligned) and the hipStream_t on which all later work is enqueued (NULL = the
+ * null stream).  Computes exp(+-dtau K) and exp(+-dtau K/2) on the device. */
+dqmc_status dqmc_bind(dqmc_ctx* ctx, const dqmc_buffers* buf, void* hip_stream);
+
+/* Field configuration in and out (the paper's confin / confout): field_host is
+ * n_slices*n doubles; sweep_counter is the chain's position in its random
+ * stream.  Setting the state invalidates G until dqmc_init. */
+dqmc_status dqmc_set_state(dqmc_ctx* ctx, const double* field_host, uint64_t sweep_counter);
+dqmc_status dqmc_get_state(dqmc_ctx* ctx, double* field_host, uint64_t* sweep_counter);
+
+/* Random start of the field from the chain's seed (s = +1 iff u < 1/2, or
+ * phi ~ N(0,1)), sweep counter 0. */
+dqmc_status dqmc_random_field(dqmc_ctx* ctx);
+
+/* Algorithm 1 set-up: fill the storage with the left UDV forms of
+ * B(beta, tau_k) and compute G(0) from scratch (section "Stabilization").
+ * Clears the statistics, bins and the error flag. */
+dqmc_status dqmc_init(dqmc_ctx* ctx);
+
+/* n_sweeps sweeps (upward then downward pass, every field visited twice,
+ * Algorithm 1).  measure != 0 accumulates the equal-time estimators on every
+ * slice of both passes.  stats may be NULL.  DQMC_E_NUMERIC if the device
+ * flagged a numerical failure; the context then needs dqmc_init. */
+dqmc_status dqmc_sweep(dqmc_ctx* ctx, int32_t n_sweeps, int32_t measure, dqmc_stats* stats);
+
+/* Bin sums: sums_host[0..3] = sum of D, sum of E_kin, sum of E_pot (per site)
+ * and the number of measurements.  dqmc_reset_bins zeroes them. */
+dqmc_status dqmc_read_bins(dqmc_ctx* ctx, double* sums_host);
+dqmc_status dqmc_reset_bins(dqmc_ctx* ctx);
+
+/* Test hook: G(tau) = (1 + B(tau,0) B(beta,tau))^-1 recomputed from scratch
+ * for the current field into the device buffer G_dev (n*n doubles), using the
+ * same stabilised products as the sweep.  Does not change the chain. */
+dqmc_status dqmc_green_scratch(dqmc_ctx* ctx, int32_t tau, double* G_dev);
+
+/* log|det(1 + B(beta,0))| of the current field from scratch. */
+dqmc_status dqmc_logdet(dqmc_ctx* ctx, double* logdet);
+
+const char* dqmc_last_error(const dqmc_ctx* ctx);
+void dqmc_destroy(dqmc_ctx* ctx);
+
+/* Coupling of the exact two-valued Hubbard-Stratonovich identity,
+ * cosh(lambda) = exp(dtau U / 2) (DQMC_FIELD_ISING), or of the Gaussian
+ * identity, c = sqrt(dtau U) (DQMC_FIELD_GAUSS). */
+dqmc_status dqmc_hubbard_coupling(double U, double dtau, dqmc_field_kind kind, double* coupling);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DQMC_H */

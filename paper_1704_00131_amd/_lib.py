@@ -1,0 +1,92 @@
+"""ctypes declarations of the C ABI in include/dqmc.h (argument marshalling only)."""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdqmc_gfx950.so")
+
+DQMC_OK = 0
+STATUS_NAMES = {0: "DQMC_OK", 1: "DQMC_E_ARG", 2: "DQMC_E_UNSUPPORTED", 3: "DQMC_E_DEVICE",
+                4: "DQMC_E_NUMERIC", 5: "DQMC_E_NOMEM", 6: "DQMC_E_STATE"}
+FIELD_ISING, FIELD_GAUSS = 0, 1
+TROTTER_ASYM, TROTTER_SYM = 0, 1
+
+
+class Model(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("n_slices", ctypes.c_int32),
+                ("beta", ctypes.c_double), ("dtau", ctypes.c_double),
+                ("n_wrap", ctypes.c_int32), ("n_col", ctypes.c_int32),
+                ("field", ctypes.c_int), ("coupling", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("u_int", ctypes.c_double),
+                ("trotter", ctypes.c_int), ("prec_threshold", ctypes.c_double),
+                ("prop_width", ctypes.c_double), ("seed", ctypes.c_uint64)]
+
+
+class Sizes(ctypes.Structure):
+    _fields_ = [("G", ctypes.c_size_t), ("field", ctypes.c_size_t),
+                ("slots", ctypes.c_size_t), ("work", ctypes.c_size_t)]
+
+
+class Buffers(ctypes.Structure):
+    _fields_ = [("G", ctypes.c_void_p), ("field", ctypes.c_void_p),
+                ("slots", ctypes.c_void_p), ("work", ctypes.c_void_p)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("proposals", ctypes.c_uint64), ("accepted", ctypes.c_uint64),
+                ("prec_mean", ctypes.c_double), ("prec_max", ctypes.c_double),
+                ("n_prec", ctypes.c_uint64), ("seconds", ctypes.c_double)]
+
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "dqmc_query_sizes": (ctypes.c_int, [ctypes.POINTER(Model), ctypes.POINTER(Sizes)]),
+    "dqmc_create": (ctypes.c_int, [ctypes.POINTER(Model), ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.POINTER(ctypes.c_void_p)]),
+    "dqmc_bind": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Buffers), ctypes.c_void_p]),
+    "dqmc_set_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64]),
+    "dqmc_get_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
+    "dqmc_random_field": (ctypes.c_int, [ctypes.c_void_p]),
+    "dqmc_init": (ctypes.c_int, [ctypes.c_void_p]),
+    "dqmc_sweep": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Stats)]),
+    "dqmc_read_bins": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "dqmc_reset_bins": (ctypes.c_int, [ctypes.c_void_p]),
+    "dqmc_green_scratch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "dqmc_logdet": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+    "dqmc_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "dqmc_destroy": (None, [ctypes.c_void_p]),
+    "dqmc_hubbard_coupling": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                             ctypes.POINTER(ctypes.c_double)]),
+}
+
+_lib = None
+
+
+class DQMCError(RuntimeError):
+    def __init__(self, status, msg=""):
+        self.status = status
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+
+
+def load():
+    """Load the in-tree HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("HIP library %s is missing: run `python -m paper_1704_00131_amd.build`" % LIB_PATH)
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def check(status, ctx=None):
+    if status != DQMC_OK:
+        msg = ""
+        if ctx is not None:
+            raw = load().dqmc_last_error(ctx)
+            msg = raw.decode() if raw else ""
+        raise DQMCError(status, msg)

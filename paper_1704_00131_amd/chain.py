@@ -1,0 +1,112 @@
+"""Python face of one DQMC chain: torch supplies the device buffers and the
+stream, the C ABI does all of the work."""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import Buffers, Model, Sizes, Stats, check
+
+
+def hubbard_coupling(U: float, dtau: float, field: str = "ising") -> float:
+    out = ctypes.c_double()
+    kind = _lib.FIELD_ISING if field == "ising" else _lib.FIELD_GAUSS
+    check(_lib.load().dqmc_hubbard_coupling(U, dtau, kind, ctypes.byref(out)))
+    return out.value
+
+
+def make_model(n, beta, dtau, n_wrap, coupling, U=0.0, field="ising", trotter="sym", seed=0,
+               alpha=-0.5, n_col=2, prec_threshold=0.0, prop_width=1.0) -> Model:
+    L = int(round(beta / dtau))
+    return Model(n=n, n_slices=L, beta=beta, dtau=dtau, n_wrap=n_wrap, n_col=n_col,
+                 field=_lib.FIELD_ISING if field == "ising" else _lib.FIELD_GAUSS,
+                 coupling=coupling, alpha=alpha, u_int=U,
+                 trotter=_lib.TROTTER_SYM if trotter == "sym" else _lib.TROTTER_ASYM,
+                 prec_threshold=prec_threshold, prop_width=prop_width, seed=seed)
+
+
+def _dev_buffer(nbytes, device):
+    return torch.empty(max(1, (nbytes + 7) // 8), dtype=torch.float64, device=device)
+
+
+class Chain:
+    """One Markov chain bound to caller-owned torch device buffers."""
+
+    def __init__(self, model: Model, K: np.ndarray, device="cuda", stream=None):
+        lib = _lib.load()
+        self.lib = lib
+        self.model = model
+        self.N = model.n
+        self.L = model.n_slices
+        sizes = Sizes()
+        check(lib.dqmc_query_sizes(ctypes.byref(model), ctypes.byref(sizes)))
+        self.sizes = sizes
+        Kc = np.ascontiguousarray(K, dtype=np.float64)
+        ctx = ctypes.c_void_p()
+        check(lib.dqmc_create(ctypes.byref(model), Kc.ctypes.data, None, ctypes.byref(ctx)))
+        self.ctx = ctx
+        self.device = torch.device(device)
+        self.G = _dev_buffer(sizes.G, self.device).view(-1)[: self.N * self.N].view(self.N, self.N)
+        self.field = _dev_buffer(sizes.field, self.device)
+        self.slots = _dev_buffer(sizes.slots, self.device)
+        self.work = _dev_buffer(sizes.work, self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        bufs = Buffers(self.G.data_ptr(), self.field.data_ptr(), self.slots.data_ptr(), self.work.data_ptr())
+        check(lib.dqmc_bind(ctx, ctypes.byref(bufs), ctypes.c_void_p(self.stream.cuda_stream)), ctx)
+
+    def _chk(self, status):
+        check(status, self.ctx)
+
+    def random_field(self):
+        self._chk(self.lib.dqmc_random_field(self.ctx))
+        return self
+
+    def set_state(self, field: np.ndarray, sweep_counter: int = 0):
+        f = np.ascontiguousarray(field, dtype=np.float64).reshape(self.L, self.N)
+        self._chk(self.lib.dqmc_set_state(self.ctx, f.ctypes.data, sweep_counter))
+        return self
+
+    def get_state(self):
+        f = np.empty((self.L, self.N))
+        ctr = ctypes.c_uint64()
+        self._chk(self.lib.dqmc_get_state(self.ctx, f.ctypes.data, ctypes.byref(ctr)))
+        return f, ctr.value
+
+    def init(self):
+        self._chk(self.lib.dqmc_init(self.ctx))
+        return self
+
+    def sweep(self, n_sweeps=1, measure=True) -> Stats:
+        st = Stats()
+        self._chk(self.lib.dqmc_sweep(self.ctx, n_sweeps, 1 if measure else 0, ctypes.byref(st)))
+        return st
+
+    def read_bins(self) -> np.ndarray:
+        out = np.zeros(4)
+        self._chk(self.lib.dqmc_read_bins(self.ctx, out.ctypes.data))
+        return out
+
+    def reset_bins(self):
+        self._chk(self.lib.dqmc_reset_bins(self.ctx))
+
+    def green_scratch(self, tau: int) -> torch.Tensor:
+        out = torch.empty(self.N, self.N, dtype=torch.float64, device=self.device)
+        self._chk(self.lib.dqmc_green_scratch(self.ctx, tau, ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def logdet(self) -> float:
+        out = ctypes.c_double()
+        self._chk(self.lib.dqmc_logdet(self.ctx, ctypes.byref(out)))
+        return out.value
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.dqmc_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,95 @@
+// Device helpers shared by the gfx950 kernels: MFMA operand layout, Philox
+// draws, block reductions and a coherent double max.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// v_mfma_f64_16x16x4_f64 (CDNA3/CDNA4).  For a wave of 64 lanes:
+//   A operand (16 x 4):  lane l holds A[l % 16][l / 16]
+//   B operand (4 x 16):  lane l holds B[l / 16][l % 16]
+//   C/D (16 x 16):       lane l, register r holds C[l / 16 + 4 r][l % 16]
+// (checked on gfx950 with an in-bounds probe of known operands).
+__device__ __forceinline__ v4d mfma_f64_16x16x4(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------- Philox ----
+// Philox4x64-10 of Salmon, Moraes, Dror and Shaw (SC'11): ten rounds, each two
+// 64x64->128-bit products with the multipliers M0, M1; the key is bumped by the
+// Weyl constants W0, W1 between rounds.
+struct Philox4 { uint64_t w[4]; };
+
+__device__ __forceinline__ Philox4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                                 uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+    uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+    uint64_t n0 = hi1 ^ c1 ^ k0;
+    uint64_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    k0 += W0; k1 += W1;
+  }
+  Philox4 out;
+  out.w[0] = c0; out.w[1] = c1; out.w[2] = c2; out.w[3] = c3;
+  return out;
+}
+
+// Stream tags of the counter (tag, sweep, (tau << 1) | direction, site).
+enum { TAG_INIT = 0, TAG_FLIP = 1, TAG_GAUSS = 2, TAG_LANGEVIN = 3 };
+
+__device__ __forceinline__ double unit_double(uint64_t w) {
+  return (double)(w >> 11) * 0x1.0p-53;
+}
+
+// ------------------------------------------------------------ reductions ----
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  // red: LDS scratch of NT/64 doubles
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) s += red[i];
+  return s;
+}
+
+template <int NT>
+__device__ __forceinline__ double block_max(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double s = red[0];
+#pragma unroll
+  for (int i = 1; i < NT / 64; ++i) s = fmax(s, red[i]);
+  return s;
+}
+
+// max of non-negative doubles through their ordered bit patterns
+__device__ __forceinline__ void atomic_max_nonneg(double* addr, double v) {
+  if (!(v >= 0.0)) v = __longlong_as_double(0x7ff8000000000000ll);  // NaN propagates as the largest
+  atomicMax(reinterpret_cast<unsigned long long*>(addr), (unsigned long long)__double_as_longlong(v));
+}
+
+// Scale modes of the GEMM epilogue and loaders.
+enum { SC_NONE = 0, SC_VAL = 1, SC_EXP = 2, SC_INV_BIG = 3, SC_SMALL = 4, SC_INV = 5 };
+
+__device__ __forceinline__ double scale_of(int mode, const double* v, double coef, int i) {
+  switch (mode) {
+    case SC_VAL: return v[i];
+    case SC_EXP: return exp(coef * v[i]);
+    case SC_INV_BIG: return 1.0 / fmax(v[i], 1.0);
+    case SC_SMALL: return fmin(v[i], 1.0);
+    case SC_INV: return 1.0 / v[i];
+    default: return 1.0;
+  }
+}

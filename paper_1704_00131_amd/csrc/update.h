@@ -1,0 +1,206 @@
+// Sequential single-flip updates of one slice, in blocks of up to 32 sites
+// (section "Updating schemes", "The default: sequential single spin flips").
+//
+// Flip at site p of slice tau (from Eq. (Green_eq) and the matrix determinant
+// lemma; the paper states the fast update's O(N^2) cost):
+//   Delta = exp(coupling (s' - s)) - 1,  r = 1 + Delta (1 - G_pp),
+//   R = exp(N_col coupling alpha (s' - s)) r^N_col  (x exp(-(s'^2 - s^2)/2) for
+//   a Gaussian field),  accept iff u < R,
+//   G <- G - (Delta/r) G[:,p] (e_p - G[p,:])      (Sherman-Morrison).
+//
+// Blocking (a regrouping of the same arithmetic, exact up to rounding): the
+// decisions of a block S of consecutive sites only read G[S,S], so the
+// sequential Sherman-Morrison steps run on the |S| x |S| block in LDS, while
+// the full matrix is carried as
+//   G_cur = G - G[:,S] Phi (E_S^T - G[S,:]),
+// where each accepted step adds gamma a b^T to Phi with
+//   a = e_j - Phi (e_j - G[S,p]),  b = e_j + Phi^T G[p,S]^T,  gamma = Delta/r.
+// After the block, G <- G - G[:,S] W with W = Phi (E_S^T - G[S,:]): one
+// rank-|S| MFMA update of G instead of |S| rank-1 passes over it.
+#pragma once
+#include "device_common.h"
+
+struct DecideArgs {
+  double* G; int N; int s0; int bb;
+  double* field_row;                 // field of slice tau (N values)
+  const unsigned long long* sweep_ctr;
+  unsigned long long seed, slot;     // Philox key word 0; counter word 2 = (tau << 1) | dir
+  double coupling, alpha; int n_col; int gauss; double prop_width;
+  double* Phi;                       // 32 x 32
+  double* Gcol;                      // N x 32: G[:, S]
+  double* W;                         // 32 x N: Phi scattered into columns S, zeros elsewhere
+  unsigned long long* counters;      // [0] proposals, [1] accepted
+  int* err;
+};
+
+__device__ __forceinline__ double ipow(double r, int n) {
+  double p = 1.0;
+  for (int k = 0; k < n; ++k) p *= r;
+  return p;
+}
+
+__global__ __launch_bounds__(64) void k_block_decide(DecideArgs a) {
+  __shared__ double g[32][33], c[32][33], Ph[32][33];
+  __shared__ double uu[32], u1[32], sv[32], av[32], bv[32], colj[32], rowj[32];
+  const int lane = threadIdx.x, bb = a.bb, s0 = a.s0, N = a.N;
+  for (int e = lane; e < 32 * 32; e += 64) {
+    const int x = e >> 5, y = e & 31;
+    const double v = (x < bb && y < bb) ? a.G[(size_t)(s0 + x) * N + s0 + y] : 0.0;
+    g[x][y] = v;
+    c[x][y] = v;
+    Ph[x][y] = 0.0;
+  }
+  if (lane < bb) {
+    const Philox4 w = philox4x64_10(TAG_FLIP, *a.sweep_ctr, a.slot, (unsigned long long)(s0 + lane), a.seed, 0ull);
+    uu[lane] = unit_double(w.w[0]);
+    u1[lane] = unit_double(w.w[1]);
+    sv[lane] = a.field_row[s0 + lane];
+  }
+  __syncthreads();
+  int nacc = 0;
+  for (int j = 0; j < bb; ++j) {
+    const double s = sv[j];
+    double s_new, extra;
+    if (a.gauss) { s_new = s + a.prop_width * (2.0 * u1[j] - 1.0); extra = -0.5 * (s_new * s_new - s * s); }
+    else { s_new = -s; extra = 0.0; }
+    const double delta = exp(a.coupling * (s_new - s)) - 1.0;
+    const double r = 1.0 + delta * (1.0 - c[j][j]);
+    const double R = exp(a.n_col * a.coupling * a.alpha * (s_new - s) + extra) * ipow(r, a.n_col);
+    if (!(uu[j] < R)) continue;          // uniform across the wave
+    const double gam = delta / r;
+    if (lane < 32) {
+      const int x = lane;
+      double acc = 0.0;
+      for (int y = 0; y < bb; ++y) acc += Ph[x][y] * ((y == j ? 1.0 : 0.0) - g[y][j]);
+      av[x] = (x == j ? 1.0 : 0.0) - acc;
+      colj[x] = c[x][j];
+    } else {
+      const int y = lane - 32;
+      double acc = 0.0;
+      for (int x = 0; x < bb; ++x) acc += Ph[x][y] * g[j][x];
+      bv[y] = (y == j ? 1.0 : 0.0) + acc;
+      rowj[y] = (y == j ? 1.0 : 0.0) - c[j][y];
+    }
+    __syncthreads();
+    for (int e = lane; e < 32 * 32; e += 64) {
+      const int x = e >> 5, y = e & 31;
+      Ph[x][y] += gam * av[x] * bv[y];
+      c[x][y] -= gam * colj[x] * rowj[y];
+    }
+    if (lane == 0) sv[j] = s_new;
+    ++nacc;
+    __syncthreads();
+  }
+  // outputs
+  if (lane < bb) a.field_row[s0 + lane] = sv[lane];
+  for (int e = lane; e < 32 * 32; e += 64) a.Phi[e] = Ph[e >> 5][e & 31];
+  for (int e = lane; e < N * 32; e += 64) {
+    const int row = e >> 5, x = e & 31;
+    a.Gcol[e] = (x < bb) ? a.G[(size_t)row * N + s0 + x] : 0.0;
+  }
+  for (int e = lane; e < 32 * N; e += 64) {
+    const int x = e / N, y = e % N;
+    const int yy = y - s0;
+    a.W[e] = (yy >= 0 && yy < bb) ? Ph[x][yy] : 0.0;
+  }
+  if (lane == 0) {
+    atomicAdd(&a.counters[0], (unsigned long long)bb);
+    atomicAdd(&a.counters[1], (unsigned long long)nacc);
+  }
+}
+
+// --------------------------------------------------------- measurements ----
+// Equal-time estimators per site (section "Observables"): with d_i the
+// diagonal of the measured Green's function,
+//   D = (1/N) sum_i d_i (1 - d_i),  E_kin = (n_col/N)(Tr K - Tr(K G)),  E_pot = U D.
+// For a symmetric split d_i = sum_b T1[i][b] Einvh[b][i] with T1 = exp(-dtau K/2) G.
+__global__ __launch_bounds__(1024) void k_measure(const double* G, const double* T1, const double* Ehinv,
+                                                  const double* K, int N, double trK, double n_col, double u_int,
+                                                  double* bins, int* err) {
+  __shared__ double red[16];
+  double sd = 0.0, skg = 0.0, bad = 0.0;
+  for (int i = threadIdx.x; i < N; i += 1024) {
+    double d;
+    if (T1) {
+      d = 0.0;
+      for (int b = 0; b < N; ++b) d += T1[(size_t)i * N + b] * Ehinv[(size_t)b * N + i];
+    } else {
+      d = G[(size_t)i * N + i];
+    }
+    sd += d * (1.0 - d);
+  }
+  for (size_t e = threadIdx.x; e < (size_t)N * N; e += 1024) {
+    const int a = (int)(e / N), b = (int)(e % N);
+    const double gv = G[(size_t)b * N + a];
+    skg += K[e] * gv;
+    if (!isfinite(gv)) bad = 1.0;
+  }
+  sd = block_sum<1024>(sd, red);
+  skg = block_sum<1024>(skg, red);
+  bad = block_sum<1024>(bad, red);
+  if (threadIdx.x == 0) {
+    const double D = sd / N;
+    bins[0] += D;
+    bins[1] += n_col / N * (trK - skg);
+    bins[2] += u_int * D;
+    bins[3] += 1.0;
+    if (bad > 0.0) atomicOr(err, 1);
+  }
+}
+
+// max |G - Gs| into prec_slot (zero on entry), G <- Gs, NaN/Inf check.
+__global__ __launch_bounds__(256) void k_prec_replace(double* G, const double* Gs, size_t count, double* prec_slot,
+                                                      int* err) {
+  __shared__ double red[8];
+  double m = 0.0, bad = 0.0;
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (size_t)gridDim.x * 256) {
+    const double gs = Gs[e];
+    const double d = fabs(G[e] - gs);
+    m = fmax(m, d);
+    if (!isfinite(gs)) bad = 1.0;
+    G[e] = gs;
+  }
+  m = block_max<256>(m, red);
+  bad = block_max<256>(bad, red);
+  if (threadIdx.x == 0) {
+    atomic_max_nonneg(prec_slot, m);
+    if (bad > 0.0) atomicOr(err, 1);
+  }
+}
+
+// End of a sweep: fold the per-stabilisation precision values into the
+// running totals, check the threshold, advance the sweep counter.
+__global__ void k_finish_sweep(double* prec_hist, int n_hist, double* prec_tot, double threshold,
+                               unsigned long long* counters, int* err) {
+  if (threadIdx.x != 0) return;
+  double s = prec_tot[0], mx = prec_tot[1], cnt = prec_tot[2];
+  for (int k = 0; k < n_hist; ++k) {
+    const double p = prec_hist[k];
+    s += p;
+    mx = fmax(mx, p);
+    cnt += 1.0;
+    if (!(p == p)) atomicOr(err, 1);
+    if (threshold > 0.0 && p > threshold) atomicOr(err, 8);
+    prec_hist[k] = 0.0;
+  }
+  prec_tot[0] = s;
+  prec_tot[1] = mx;
+  prec_tot[2] = cnt;
+  counters[2] += 1ull;
+}
+
+// Random start of the field (s = +1 iff u < 1/2, or phi ~ N(0,1) by
+// Box-Muller on (1 - u0, u1), cosine branch); draws (INIT, 0, tau << 1, site).
+__global__ void k_random_field(double* field, int L, int N, unsigned long long seed, int gauss) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= L * N) return;
+  const int tau = e / N + 1, i = e % N;
+  const Philox4 w = philox4x64_10(TAG_INIT, 0ull, (unsigned long long)tau << 1, (unsigned long long)i, seed, 0ull);
+  const double u0 = unit_double(w.w[0]);
+  if (!gauss) {
+    field[e] = (u0 < 0.5) ? 1.0 : -1.0;
+  } else {
+    const double u1 = unit_double(w.w[1]);
+    field[e] = sqrt(-2.0 * log(1.0 - u0)) * cos(2.0 * M_PI * u1);
+  }
+}

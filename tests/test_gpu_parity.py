@@ -1,0 +1,93 @@
+"""Parity of the HIP path with the oracle (element by element, same seeded
+inputs, same Philox draws).  Tolerances: 1e-9 max-abs on G, ratios and
+observables per configuration; bit-exact field decisions."""
+import numpy as np
+import pytest
+
+from gpu_util import maxabs, pair
+from oracle import hubbard as ohub
+from oracle import stable as ostable
+from oracle import sweep as osweep
+
+pytestmark = pytest.mark.gpu
+
+TOL_G = 1e-9
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+@pytest.mark.parametrize("kind,L1,L2,field", [("square", 4, 4, "ising"), ("honeycomb", 6, 6, "ising"),
+                                              ("square", 5, 5, "gauss")])
+def test_random_field_matches_oracle(kind, L1, L2, field):
+    _log(f"random field {kind} {L1}x{L2} {field}")
+    om, ch, _ = pair(kind, L1, L2, 4.0, 2.0, 0.1, 10, seed=7, field=field)
+    ch.random_field()
+    f, ctr = ch.get_state()
+    fo = ohub.init_field(om)
+    assert ctr == 0
+    if field == "ising":
+        assert np.array_equal(f, fo)
+    else:
+        assert maxabs(f, fo) < 1e-13
+
+
+@pytest.mark.parametrize("kind,L1,L2,beta,trotter", [("square", 4, 4, 2.0, "sym"), ("honeycomb", 6, 6, 4.0, "asym"),
+                                                     ("square", 2, 2, 12.0, "asym")])
+def test_green_scratch_and_logdet(kind, L1, L2, beta, trotter):
+    _log(f"green scratch {kind} {L1}x{L2} beta={beta}")
+    om, ch, _ = pair(kind, L1, L2, 4.0, beta, 0.1, 10, trotter=trotter, seed=3)
+    ch.random_field()
+    f, _ = ch.get_state()
+    for tau in sorted({0, 1, 7, om.L // 2, om.L - 3, om.L}):
+        G = ch.green_scratch(tau).cpu().numpy()
+        assert maxabs(G, ostable.green_scratch(om, f, tau)) < 1e-10, tau
+    assert abs(ch.logdet() - ostable.logdet_scratch(om, f)) < 1e-9 * max(1.0, abs(ostable.logdet_scratch(om, f)))
+
+
+def _trajectory(kind, L1, L2, U, beta, n_wrap, trotter, seed, sweeps, field="ising"):
+    om, ch, _ = pair(kind, L1, L2, U, beta, 0.1, n_wrap, trotter=trotter, seed=seed, field=field)
+    ch.random_field().init()
+    f0, _ = ch.get_state()
+    oc = osweep.Chain(om, f0).init()
+    assert maxabs(ch.G.cpu().numpy(), oc.G) < 1e-10
+    for s in range(sweeps):
+        st = ch.sweep(1, measure=True)
+        oc.sweep(measure=True)
+        f, ctr = ch.get_state()
+        assert oc.min_tie > 1e-9, "near-tie in the oracle's decisions; pick another seed"
+        assert ctr == s + 1
+        assert np.array_equal(f, oc.field), f"field differs after sweep {s}"
+        assert maxabs(ch.G.cpu().numpy(), oc.G) < TOL_G, f"G differs after sweep {s}"
+        assert st.accepted == oc.accepted and st.proposals == oc.proposals
+    bins = ch.read_bins()
+    assert maxabs(bins, oc.bins) < TOL_G * max(1.0, oc.bins[3])
+    # max|G_wrapped - G_scratch| is a rounding-error magnitude; each side's own
+    # value differs, both must stay at the oracle's scale
+    assert st.prec_max < max(1e-8, 10.0 * max(oc.prec))
+    return ch, oc
+
+
+def test_sweep_parity_square4x4_full_run():
+    """4x4 square, U=4, beta=2, L=20, symmetric split, seed 0: the full
+    200-sweep run with measurements on every slice."""
+    _log("trajectory square 4x4 200 sweeps")
+    _trajectory("square", 4, 4, 4.0, 2.0, 10, "sym", 0, 200)
+
+
+def test_sweep_parity_honeycomb_ragged():
+    """N = 72 (two full 32-site blocks and a ragged one), asymmetric split."""
+    _log("trajectory honeycomb 6x6 3 sweeps")
+    _trajectory("honeycomb", 6, 6, 4.0, 4.0, 10, "asym", 5, 3)
+
+
+def test_sweep_parity_gauss_field():
+    _log("trajectory gauss 4x4 2 sweeps")
+    _trajectory("square", 4, 4, 4.0, 2.0, 5, "sym", 2, 2, field="gauss")
+
+
+def test_sweep_parity_honeycomb12_one_sweep():
+    """Honeycomb 12x12 (N = 288), U=4, beta=10, L=100: one sweep."""
+    _log("trajectory honeycomb 12x12 1 sweep")
+    _trajectory("honeycomb", 12, 12, 4.0, 10.0, 10, "asym", 0, 1)
