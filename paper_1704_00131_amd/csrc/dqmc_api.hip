@@ -52,7 +52,9 @@ struct dqmc_ctx {
   double *Vall = nullptr, *VTall = nullptr, *Zq = nullptr, *Rt = nullptr;
   double *X = nullptr, *RHS = nullptr, *Gs = nullptr, *T1 = nullptr;
   UDVp cur{}, uid{}, hA{}, hB{};
-  double *Phi = nullptr, *Gcol = nullptr, *Wb = nullptr;
+  double *G2 = nullptr, *Gcur = nullptr;   // second G buffer of the out-of-place block updates
+  double *field_alt = nullptr;             // field rows written by the upward pass
+  std::vector<unsigned char> row_alt;      // host mirror: row tau currently in field_alt
   double *norms = nullptr;
   int *piv = nullptr, *ipiv = nullptr;
   double *bins = nullptr, *prec_hist = nullptr, *prec_tot = nullptr, *logdet = nullptr;
@@ -92,7 +94,8 @@ size_t layout_work(dqmc_ctx* c, bool assign) {
   c->X = P(NN); c->RHS = P(NN); c->Gs = P(NN); c->T1 = P(NN);
   UDVp* us[4] = {&c->cur, &c->uid, &c->hA, &c->hB};
   for (UDVp* u : us) { u->Q = P(NN); u->D = P(N); u->T = P(NN); }
-  c->Phi = P(kBlock * kBlock); c->Gcol = P(N * kBlock); c->Wb = P(N * kBlock);
+  c->G2 = P(NN);
+  c->field_alt = P((size_t)c->L * N);
   c->norms = P(N);
   double* pv = P(N); double* ipv = P(N);
   c->piv = reinterpret_cast<int*>(pv); c->ipiv = reinterpret_cast<int*>(ipv);
@@ -140,13 +143,20 @@ dqmc_status expm(dqmc_ctx* c, double x, double* out) {
   return DQMC_OK;
 }
 
-inline double* field_row(dqmc_ctx* c, int tau) { return c->field + (size_t)(tau - 1) * c->N; }
+// Current location of field row tau: the upward pass writes its rows to
+// field_alt, the downward pass writes them back to the caller's field buffer
+// (so no launch reads and writes the same sites).
+inline double* field_row(dqmc_ctx* c, int tau) {
+  double* base = (!c->row_alt.empty() && c->row_alt[tau - 1]) ? c->field_alt : c->field;
+  return base + (size_t)(tau - 1) * c->N;
+}
 
 // G(tau) = B_tau G(tau-1) B_tau^-1 = diag(v) E G Einv diag(1/v), v = exp(coupling s_tau)
 dqmc_status wrap_up(dqmc_ctx* c, int tau) {
   const int N = c->N;
-  if (dqmc_status s = gemm(c, gemm_args(N, N, N, c->E, N, 0, c->G, N, 0, c->T1, N))) return s;
+  if (dqmc_status s = gemm(c, gemm_args(N, N, N, c->E, N, 0, c->Gcur, N, 0, c->T1, N))) return s;
   GemmArgs g = gemm_args(N, N, N, c->T1, N, 0, c->Einv, N, 0, c->G, N);
+  c->Gcur = c->G;
   g.rs = field_row(c, tau); g.rs_mode = SC_EXP; g.rs_coef = c->m.coupling;
   g.cs = field_row(c, tau); g.cs_mode = SC_EXP; g.cs_coef = -c->m.coupling;
   return gemm(c, g);
@@ -155,35 +165,38 @@ dqmc_status wrap_up(dqmc_ctx* c, int tau) {
 // G(tau-1) = B_tau^-1 G(tau) B_tau = Einv diag(1/v) G diag(v) E, written to dst
 dqmc_status wrap_down(dqmc_ctx* c, int tau, double* dst) {
   const int N = c->N;
-  GemmArgs g1 = gemm_args(N, N, N, c->G, N, 0, c->E, N, 0, c->T1, N);
+  GemmArgs g1 = gemm_args(N, N, N, c->Gcur, N, 0, c->E, N, 0, c->T1, N);
   g1.ks = field_row(c, tau); g1.ks_mode = SC_EXP; g1.ks_coef = c->m.coupling;
   if (dqmc_status s = gemm(c, g1)) return s;
   GemmArgs g2 = gemm_args(N, N, N, c->Einv, N, 0, c->T1, N, 0, dst, N);
   g2.ks = field_row(c, tau); g2.ks_mode = SC_EXP; g2.ks_coef = -c->m.coupling;
-  return gemm(c, g2);
+  if (dqmc_status s = gemm(c, g2)) return s;
+  c->Gcur = dst;
+  return DQMC_OK;
 }
 
+// Sequential flips of slice tau, one fused launch per block of 32 sites; G
+// alternates between the two buffers, the field row moves to the other buffer.
 dqmc_status update_slice(dqmc_ctx* c, int tau, int dir) {
   const int N = c->N;
+  const double* fin = field_row(c, tau);
+  c->row_alt[tau - 1] ^= 1;
+  double* fout = field_row(c, tau);
+  const int tiles = ((N + 31) / 32) * ((N + 31) / 32);
   for (int s0 = 0; s0 < N; s0 += kBlock) {
-    const int bb = std::min(kBlock, N - s0);
-    DecideArgs a;
-    a.G = c->G; a.N = N; a.s0 = s0; a.bb = bb;
-    a.field_row = field_row(c, tau);
+    BlockArgs a;
+    a.Gin = c->Gcur;
+    a.Gout = (c->Gcur == c->G) ? c->G2 : c->G;
+    a.N = N; a.s0 = s0; a.bb = std::min(kBlock, N - s0);
+    a.field_in = fin; a.field_out = fout;
     a.sweep_ctr = c->counters + 2;
     a.seed = c->m.seed; a.slot = ((unsigned long long)tau << 1) | (unsigned long long)dir;
     a.coupling = c->m.coupling; a.alpha = c->m.alpha; a.n_col = c->m.n_col;
     a.gauss = c->m.field == DQMC_FIELD_GAUSS; a.prop_width = c->m.prop_width;
-    a.Phi = c->Phi; a.Gcol = c->Gcol; a.W = c->Wb;
-    a.counters = c->counters; a.err = c->err_flag;
-    hipLaunchKernelGGL(k_block_decide, dim3(1), dim3(64), 0, c->stream, a);
+    a.counters = c->counters;
+    hipLaunchKernelGGL(k_block_update, dim3(tiles), dim3(256), 0, c->stream, a);
     HIPCHK(hipGetLastError());
-    // W <- W - Phi G[S,:]
-    if (dqmc_status s = gemm(c, gemm_args(kBlock, N, bb, c->Phi, kBlock, 0, c->G + (size_t)s0 * N, N, 0,
-                                          c->Wb, N, -1.0, 1.0))) return s;
-    // G <- G - G[:,S] W
-    if (dqmc_status s = gemm(c, gemm_args(N, N, kBlock, c->Gcol, kBlock, 0, c->Wb, N, 0, c->G, N, -1.0, 1.0)))
-      return s;
+    c->Gcur = a.Gout;
   }
   return DQMC_OK;
 }
@@ -357,9 +370,10 @@ dqmc_status copy_udv(dqmc_ctx* c, UDVp dst, UDVp src) {
 
 dqmc_status stabilise(dqmc_ctx* c, int hist_index) {
   const size_t NN = (size_t)c->N * c->N;
-  hipLaunchKernelGGL(k_prec_replace, dim3(std::min<size_t>(grid1(NN), 1024)), dim3(256), 0, c->stream, c->G, c->Gs,
-                     NN, c->prec_hist + hist_index, c->err_flag);
+  hipLaunchKernelGGL(k_prec_replace, dim3(std::min<size_t>(grid1(NN), 1024)), dim3(256), 0, c->stream, c->Gcur,
+                     c->G, c->Gs, NN, c->prec_hist + hist_index, c->err_flag);
   HIPCHK(hipGetLastError());
+  c->Gcur = c->G;
   return DQMC_OK;
 }
 
@@ -367,10 +381,10 @@ dqmc_status measure(dqmc_ctx* c) {
   const int N = c->N;
   const double* T1 = nullptr;
   if (c->m.trotter == DQMC_TROTTER_SYM) {
-    if (dqmc_status s = gemm(c, gemm_args(N, N, N, c->Eh, N, 0, c->G, N, 0, c->T1, N))) return s;
+    if (dqmc_status s = gemm(c, gemm_args(N, N, N, c->Eh, N, 0, c->Gcur, N, 0, c->T1, N))) return s;
     T1 = c->T1;
   }
-  hipLaunchKernelGGL(k_measure, dim3(1), dim3(1024), 0, c->stream, c->G, T1, c->Ehinv, c->Kd, N, c->trK,
+  hipLaunchKernelGGL(k_measure, dim3(1), dim3(1024), 0, c->stream, c->Gcur, T1, c->Ehinv, c->Kd, N, c->trK,
                      (double)c->m.n_col, c->m.u_int, c->bins, c->err_flag);
   HIPCHK(hipGetLastError());
   return DQMC_OK;
@@ -380,6 +394,8 @@ dqmc_status measure(dqmc_ctx* c) {
 dqmc_status sweep_once(dqmc_ctx* c, bool meas) {
   const int L = c->L, nw = c->nw, nk = c->nk;
   int hist = 0;
+  c->row_alt.assign(L, 0);
+  c->Gcur = c->G;
   for (int tau = 1; tau <= L; ++tau) {
     if (dqmc_status s = wrap_up(c, tau)) return s;
     if (dqmc_status s = update_slice(c, tau, 0)) return s;
@@ -401,7 +417,7 @@ dqmc_status sweep_once(dqmc_ctx* c, bool meas) {
       if (dqmc_status s = measure(c)) return s;
     if ((tau - 1) % nw == 0) {
       const int k = (tau - 1) / nw;
-      // G <- wrapped G(tau-1), compared against the recomputed one below
+      // wrapped G(tau-1), compared against the recomputed one below
       if (dqmc_status s = wrap_down(c, tau, c->G)) return s;
       UDVp prev = (k + 1 == nk) ? c->uid : c->slot(k + 1);
       if (dqmc_status s = left_step(c, prev, tau - 1, tau - 1 + nw, c->cur)) return s;
@@ -416,6 +432,7 @@ dqmc_status sweep_once(dqmc_ctx* c, bool meas) {
   hipLaunchKernelGGL(k_finish_sweep, dim3(1), dim3(64), 0, c->stream, c->prec_hist, hist, c->prec_tot,
                      c->m.prec_threshold, c->counters, c->err_flag);
   HIPCHK(hipGetLastError());
+  c->row_alt.clear();
   return DQMC_OK;
 }
 

@@ -20,17 +20,17 @@
 #pragma once
 #include "device_common.h"
 
-struct DecideArgs {
-  double* G; int N; int s0; int bb;
-  double* field_row;                 // field of slice tau (N values)
+struct BlockArgs {
+  const double* Gin;                 // G before the block (N x N)
+  double* Gout;                      // G after the block (N x N, distinct from Gin)
+  int N; int s0; int bb;
+  const double* field_in;            // field of slice tau before the block (N values)
+  double* field_out;                 // field of slice tau after the block (may equal field_in only for
+                                     // sites outside this block; distinct buffer otherwise)
   const unsigned long long* sweep_ctr;
   unsigned long long seed, slot;     // Philox key word 0; counter word 2 = (tau << 1) | dir
   double coupling, alpha; int n_col; int gauss; double prop_width;
-  double* Phi;                       // 32 x 32
-  double* Gcol;                      // N x 32: G[:, S]
-  double* W;                         // 32 x N: Phi scattered into columns S, zeros elsewhere
   unsigned long long* counters;      // [0] proposals, [1] accepted
-  int* err;
 };
 
 __device__ __forceinline__ double ipow(double r, int n) {
@@ -39,73 +39,108 @@ __device__ __forceinline__ double ipow(double r, int n) {
   return p;
 }
 
-__global__ __launch_bounds__(64) void k_block_decide(DecideArgs a) {
-  __shared__ double g[32][33], c[32][33], Ph[32][33];
-  __shared__ double uu[32], u1[32], sv[32], av[32], bv[32], colj[32], rowj[32];
-  const int lane = threadIdx.x, bb = a.bb, s0 = a.s0, N = a.N;
-  for (int e = lane; e < 32 * 32; e += 64) {
+// One workgroup per 32 x 32 tile (I, J) of G.  Every workgroup runs the same
+// sequential decisions of block S on G[S,S] (identical arithmetic, identical
+// results), then writes
+//   Gout[I,J] = Gin[I,J] - Gin[I,S] Phi (E_S^T[:,J] - Gin[S,J]).
+// Workgroup 0 also writes the block's field values and the counters.
+__global__ __launch_bounds__(256) void k_block_update(BlockArgs a) {
+  __shared__ double g[32][33], c[32][33], Ph[32][33], GIS[32][33], GSJ[32][33], Wt[32][33];
+  __shared__ double dlt[32], pre[32], snew[32], sold[32], uu[32], av[32], bv[32], colj[32], rowj[32];
+  __shared__ int accf[32];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int bb = a.bb, s0 = a.s0, N = a.N;
+  const int tilesN = (N + 31) >> 5;
+  const int I0 = (blockIdx.x / tilesN) << 5, J0 = (blockIdx.x % tilesN) << 5;
+  for (int e = tid; e < 1024; e += 256) {
     const int x = e >> 5, y = e & 31;
-    const double v = (x < bb && y < bb) ? a.G[(size_t)(s0 + x) * N + s0 + y] : 0.0;
+    const double v = (x < bb && y < bb) ? a.Gin[(size_t)(s0 + x) * N + s0 + y] : 0.0;
     g[x][y] = v;
     c[x][y] = v;
     Ph[x][y] = 0.0;
+    GIS[x][y] = (I0 + x < N && y < bb) ? a.Gin[(size_t)(I0 + x) * N + s0 + y] : 0.0;
+    GSJ[x][y] = (x < bb && J0 + y < N) ? a.Gin[(size_t)(s0 + x) * N + J0 + y] : 0.0;
   }
-  if (lane < bb) {
-    const Philox4 w = philox4x64_10(TAG_FLIP, *a.sweep_ctr, a.slot, (unsigned long long)(s0 + lane), a.seed, 0ull);
-    uu[lane] = unit_double(w.w[0]);
-    u1[lane] = unit_double(w.w[1]);
-    sv[lane] = a.field_row[s0 + lane];
+  if (tid < 32) {
+    accf[tid] = 0;
+    if (tid < bb) {
+      const Philox4 r = philox4x64_10(TAG_FLIP, *a.sweep_ctr, a.slot, (unsigned long long)(s0 + tid), a.seed, 0ull);
+      const double u0 = unit_double(r.w[0]), u1 = unit_double(r.w[1]);
+      const double s = a.field_in[s0 + tid];
+      double sn, extra;
+      if (a.gauss) { sn = s + a.prop_width * (2.0 * u1 - 1.0); extra = -0.5 * (sn * sn - s * s); }
+      else { sn = -s; extra = 0.0; }
+      uu[tid] = u0;
+      sold[tid] = s;
+      snew[tid] = sn;
+      dlt[tid] = exp(a.coupling * (sn - s)) - 1.0;
+      pre[tid] = exp(a.n_col * a.coupling * a.alpha * (sn - s) + extra);
+    }
   }
   __syncthreads();
   int nacc = 0;
   for (int j = 0; j < bb; ++j) {
-    const double s = sv[j];
-    double s_new, extra;
-    if (a.gauss) { s_new = s + a.prop_width * (2.0 * u1[j] - 1.0); extra = -0.5 * (s_new * s_new - s * s); }
-    else { s_new = -s; extra = 0.0; }
-    const double delta = exp(a.coupling * (s_new - s)) - 1.0;
-    const double r = 1.0 + delta * (1.0 - c[j][j]);
-    const double R = exp(a.n_col * a.coupling * a.alpha * (s_new - s) + extra) * ipow(r, a.n_col);
-    if (!(uu[j] < R)) continue;          // uniform across the wave
-    const double gam = delta / r;
-    if (lane < 32) {
-      const int x = lane;
+    const double r = 1.0 + dlt[j] * (1.0 - c[j][j]);
+    const double R = pre[j] * ipow(r, a.n_col);
+    if (!(uu[j] < R)) continue;          // uniform across the workgroup
+    const double gam = dlt[j] / r;
+    if (tid < 32) {
+      const int x = tid;
       double acc = 0.0;
       for (int y = 0; y < bb; ++y) acc += Ph[x][y] * ((y == j ? 1.0 : 0.0) - g[y][j]);
       av[x] = (x == j ? 1.0 : 0.0) - acc;
       colj[x] = c[x][j];
-    } else {
-      const int y = lane - 32;
+    } else if (tid < 64) {
+      const int y = tid - 32;
       double acc = 0.0;
       for (int x = 0; x < bb; ++x) acc += Ph[x][y] * g[j][x];
       bv[y] = (y == j ? 1.0 : 0.0) + acc;
       rowj[y] = (y == j ? 1.0 : 0.0) - c[j][y];
     }
     __syncthreads();
-    for (int e = lane; e < 32 * 32; e += 64) {
+    for (int e = tid; e < 1024; e += 256) {
       const int x = e >> 5, y = e & 31;
       Ph[x][y] += gam * av[x] * bv[y];
       c[x][y] -= gam * colj[x] * rowj[y];
     }
-    if (lane == 0) sv[j] = s_new;
+    if (tid == 0) accf[j] = 1;
     ++nacc;
     __syncthreads();
   }
-  // outputs
-  if (lane < bb) a.field_row[s0 + lane] = sv[lane];
-  for (int e = lane; e < 32 * 32; e += 64) a.Phi[e] = Ph[e >> 5][e & 31];
-  for (int e = lane; e < N * 32; e += 64) {
-    const int row = e >> 5, x = e & 31;
-    a.Gcol[e] = (x < bb) ? a.G[(size_t)row * N + s0 + x] : 0.0;
+  // W tile = Phi (E_S^T[:, J] - G[S, J])  (32 x 32 x 32 on MFMA)
+  const int wr = w >> 1, wc = w & 1;
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k0 = 0; k0 < 32; k0 += 4) {
+    const int z = k0 + (lane >> 4), y = wc * 16 + (lane & 15);
+    const double av_ = Ph[wr * 16 + (lane & 15)][z];
+    const double bz = ((s0 + z == J0 + y) ? 1.0 : 0.0) - GSJ[z][y];
+    acc = mfma_f64_16x16x4(av_, bz, acc);
   }
-  for (int e = lane; e < 32 * N; e += 64) {
-    const int x = e / N, y = e % N;
-    const int yy = y - s0;
-    a.W[e] = (yy >= 0 && yy < bb) ? Ph[x][yy] : 0.0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) Wt[wr * 16 + (lane >> 4) + 4 * r][wc * 16 + (lane & 15)] = acc[r];
+  __syncthreads();
+  v4d acc2 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k0 = 0; k0 < 32; k0 += 4) {
+    const double av_ = GIS[wr * 16 + (lane & 15)][k0 + (lane >> 4)];
+    const double bw = Wt[k0 + (lane >> 4)][wc * 16 + (lane & 15)];
+    acc2 = mfma_f64_16x16x4(av_, bw, acc2);
   }
-  if (lane == 0) {
-    atomicAdd(&a.counters[0], (unsigned long long)bb);
-    atomicAdd(&a.counters[1], (unsigned long long)nacc);
+  const int col = J0 + wc * 16 + (lane & 15);
+  if (col < N) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = I0 + wr * 16 + (lane >> 4) + 4 * r;
+      if (row < N) a.Gout[(size_t)row * N + col] = a.Gin[(size_t)row * N + col] - acc2[r];
+    }
+  }
+  if (blockIdx.x == 0) {
+    if (tid < bb) a.field_out[s0 + tid] = accf[tid] ? snew[tid] : sold[tid];
+    if (tid == 0) {
+      atomicAdd(&a.counters[0], (unsigned long long)bb);
+      atomicAdd(&a.counters[1], (unsigned long long)nacc);
+    }
   }
 }
 
@@ -113,32 +148,37 @@ __global__ __launch_bounds__(64) void k_block_decide(DecideArgs a) {
 // Equal-time estimators per site (section "Observables"): with d_i the
 // diagonal of the measured Green's function,
 //   D = (1/N) sum_i d_i (1 - d_i),  E_kin = (n_col/N)(Tr K - Tr(K G)),  E_pot = U D.
-// For a symmetric split d_i = sum_b T1[i][b] Einvh[b][i] with T1 = exp(-dtau K/2) G.
+// For a symmetric split d_i = sum_b T1[i][b] Ehinv[b][i] with
+// T1 = exp(-dtau K/2) G (Ehinv is symmetric, so the sum runs along row i of
+// both).  K is symmetric, so Tr(K G) = sum_e K[e] G[e].  One workgroup; each
+// wave walks rows with coalesced loads.
 __global__ __launch_bounds__(1024) void k_measure(const double* G, const double* T1, const double* Ehinv,
                                                   const double* K, int N, double trK, double n_col, double u_int,
                                                   double* bins, int* err) {
   __shared__ double red[16];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   double sd = 0.0, skg = 0.0, bad = 0.0;
-  for (int i = threadIdx.x; i < N; i += 1024) {
+  for (int i = w; i < N; i += 16) {
     double d;
     if (T1) {
-      d = 0.0;
-      for (int b = 0; b < N; ++b) d += T1[(size_t)i * N + b] * Ehinv[(size_t)b * N + i];
+      double p = 0.0;
+      for (int b = lane; b < N; b += 64) p += T1[(size_t)i * N + b] * Ehinv[(size_t)i * N + b];
+      for (int o = 32; o > 0; o >>= 1) p += __shfl_xor(p, o, 64);
+      d = p;
     } else {
       d = G[(size_t)i * N + i];
     }
-    sd += d * (1.0 - d);
+    if (lane == 0) sd += d * (1.0 - d);
   }
-  for (size_t e = threadIdx.x; e < (size_t)N * N; e += 1024) {
-    const int a = (int)(e / N), b = (int)(e % N);
-    const double gv = G[(size_t)b * N + a];
+  for (size_t e = tid; e < (size_t)N * N; e += 1024) {
+    const double gv = G[e];
     skg += K[e] * gv;
     if (!isfinite(gv)) bad = 1.0;
   }
   sd = block_sum<1024>(sd, red);
   skg = block_sum<1024>(skg, red);
   bad = block_sum<1024>(bad, red);
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
     const double D = sd / N;
     bins[0] += D;
     bins[1] += n_col / N * (trK - skg);
@@ -148,14 +188,14 @@ __global__ __launch_bounds__(1024) void k_measure(const double* G, const double*
   }
 }
 
-// max |G - Gs| into prec_slot (zero on entry), G <- Gs, NaN/Inf check.
-__global__ __launch_bounds__(256) void k_prec_replace(double* G, const double* Gs, size_t count, double* prec_slot,
-                                                      int* err) {
+// max |Gw - Gs| into prec_slot (zero on entry), G <- Gs, NaN/Inf check.
+__global__ __launch_bounds__(256) void k_prec_replace(const double* Gw, double* G, const double* Gs, size_t count,
+                                                      double* prec_slot, int* err) {
   __shared__ double red[8];
   double m = 0.0, bad = 0.0;
   for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (size_t)gridDim.x * 256) {
     const double gs = Gs[e];
-    const double d = fabs(G[e] - gs);
+    const double d = fabs(Gw[e] - gs);
     m = fmax(m, d);
     if (!isfinite(gs)) bad = 1.0;
     G[e] = gs;
