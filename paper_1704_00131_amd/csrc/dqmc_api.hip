@@ -215,7 +215,7 @@ dqmc_status qr_udv(dqmc_ctx* c, double* M, const double* T_in, UDVp out) {
     const int nbw = std::min(nb, N - j0), h = N - j0;
     double* V = c->Vall + (size_t)j0 * N;
     double* VT = c->VTall + (size_t)j0 * N;
-    const size_t lds = sizeof(double) * ((size_t)h * (nbw + 1) + nbw + 2 * nbw * nbw + 8 + nbw);
+    const size_t lds = sizeof(double) * qr_panel_lds(h, nbw);
     hipLaunchKernelGGL(k_qr_panel, dim3(1), dim3(256), lds, c->stream, Ap, N, j0, nbw, V, VT);
     HIPCHK(hipGetLastError());
     const int ntr = N - j0 - nbw;
@@ -284,7 +284,7 @@ dqmc_status lu_solve(dqmc_ctx* c, double* X, double* RHS, double* logdet) {
   const int N = c->N, nb = c->nb;
   for (int j0 = 0; j0 < N; j0 += nb) {
     const int nbw = std::min(nb, N - j0), h = N - j0;
-    const size_t lds = sizeof(double) * ((size_t)h * (nbw + 1) + 8);
+    const size_t lds = sizeof(double) * lu_panel_lds(h, nbw);
     hipLaunchKernelGGL(k_lu_panel, dim3(1), dim3(256), lds, c->stream, X, N, j0, nbw, c->ipiv, c->err_flag);
     HIPCHK(hipGetLastError());
     hipLaunchKernelGGL(k_lu_swap, dim3(grid1((size_t)(N - nbw) + N)), dim3(256), 0, c->stream, X, N, j0, nbw,
@@ -505,7 +505,8 @@ dqmc_status dqmc_create(const dqmc_model* m, const double* K, const int32_t* ver
   if (!c) return DQMC_E_NOMEM;
   c->m = *m;
   c->N = N; c->L = m->n_slices; c->nw = m->n_wrap; c->nk = m->n_slices / m->n_wrap;
-  c->nb = (N <= 400) ? 32 : 16;
+  // panel width: 32 columns while a full-height panel fits in LDS, else 16
+  c->nb = (qr_panel_lds(N, 32) * sizeof(double) <= 150 * 1024) ? 32 : 16;
   c->K.assign(K, K + (size_t)N * N);
   double tr = 0.0, n1 = 0.0;
   for (int j = 0; j < N; ++j) {

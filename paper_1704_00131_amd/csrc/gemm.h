@@ -9,12 +9,13 @@
 // exp(coupling * field) for the interaction exponential), so no separate
 // scaling pass over HBM is needed.
 //
-// Tiling: one workgroup of 256 threads (4 waves) computes a 32 x 32 tile of C;
-// each wave owns a 16 x 16 quadrant held in one v_mfma_f64_16x16x4 accumulator.
-// K is walked in chunks of 16, staged through LDS (both operands stored
-// k-major so that the 16 lanes feeding one MFMA row read consecutive
-// addresses), with the next chunk prefetched into registers while the current
-// one is multiplied.
+// Tiling: one workgroup of 256 threads (4 waves) computes a TILE x TILE tile
+// of C (TILE = 16 or 32, chosen per launch so that small products still
+// spread over many CUs); the four waves split K and their partial
+// accumulators are summed through LDS.  Operands are read straight from
+// global memory in the v_mfma_f64_16x16x4 lane layout: the 16 lanes feeding
+// one MFMA row share a 128-byte line across four k-steps, so the L1 serves
+// most loads and no LDS staging is needed for these L2-resident matrices.
 #pragma once
 #include "device_common.h"
 
@@ -29,92 +30,77 @@ struct GemmArgs {
   const double* ks; double ks_coef; int ks_mode;
 };
 
-namespace gemm_cfg {
-constexpr int TM = 32, TN = 32, TK = 16, NT = 256;
-constexpr int PAD = 1;
-}
-
+template <int TILE>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
-  using namespace gemm_cfg;
-  __shared__ double As[2][TK][TM + PAD];
-  __shared__ double Bs[2][TK][TN + PAD];
-
-  const int tilesN = (g.N + TN - 1) / TN;
-  const int bi = blockIdx.x / tilesN, bj = blockIdx.x % tilesN;
-  const int i0 = bi * TM, j0 = bj * TN;
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int wr = w >> 1, wc = w & 1;
-
-  // each thread moves 2 elements of each operand per chunk (32*16 = 512)
-  double ra[2], rb[2];
-  int ai[2], ak[2], bk[2], bj_[2];
+  constexpr int NB = TILE / 16;
+  __shared__ double red[3][NB * NB][4][64];
+  const int tilesN = (g.N + TILE - 1) / TILE;
+  const int i0 = (blockIdx.x / tilesN) * TILE, j0 = (blockIdx.x % tilesN) * TILE;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int l16 = lane & 15, lk = lane >> 4;
+  // contiguous K range of this wave, a multiple of 4 long
+  const int kq = ((g.K + 15) / 16) * 4;
+  const int kb = w * kq, ke = min(g.K, kb + kq);
+  v4d acc[NB][NB];
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int e = t + NT * q;
-    if (!g.transA) { ai[q] = e / TK; ak[q] = e % TK; } else { ak[q] = e / TM; ai[q] = e % TM; }
-    if (!g.transB) { bk[q] = e / TN; bj_[q] = e % TN; } else { bj_[q] = e / TK; bk[q] = e % TK; }
-  }
-
-  auto load = [&](int k0) {
+  for (int a = 0; a < NB; ++a)
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int i = i0 + ai[q], k = k0 + ak[q];
+    for (int b = 0; b < NB; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+  for (int k0 = kb; k0 < ke; k0 += 4) {
+    const int k = k0 + lk;
+    const bool kin = k < ke;
+    const double ksc = (kin && g.ks_mode) ? scale_of(g.ks_mode, g.ks, g.ks_coef, k) : 1.0;
+    double av[NB], bv[NB];
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+      const int row = i0 + a * 16 + l16;
       double v = 0.0;
-      if (i < g.M && k < g.K) {
-        v = g.transA ? g.A[(size_t)k * g.lda + i] : g.A[(size_t)i * g.lda + k];
-        if (g.ks_mode) v *= scale_of(g.ks_mode, g.ks, g.ks_coef, k);
-      }
-      ra[q] = v;
-      const int kb = k0 + bk[q], j = j0 + bj_[q];
-      double u = 0.0;
-      if (kb < g.K && j < g.N) u = g.transB ? g.B[(size_t)j * g.ldb + kb] : g.B[(size_t)kb * g.ldb + j];
-      rb[q] = u;
+      if (kin && row < g.M) v = g.transA ? g.A[(size_t)k * g.lda + row] : g.A[(size_t)row * g.lda + k];
+      av[a] = v * ksc;
     }
-  };
-  auto store = [&](int buf) {
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      As[buf][ak[q]][ai[q]] = ra[q];
-      Bs[buf][bk[q]][bj_[q]] = rb[q];
+    for (int b = 0; b < NB; ++b) {
+      const int col = j0 + b * 16 + l16;
+      double v = 0.0;
+      if (kin && col < g.N) v = g.transB ? g.B[(size_t)col * g.ldb + k] : g.B[(size_t)k * g.ldb + col];
+      bv[b] = v;
     }
-  };
-
-  v4d acc = {0.0, 0.0, 0.0, 0.0};
-  const int nchunks = (g.K + TK - 1) / TK;
-  if (nchunks > 0) {
-    load(0);
-    store(0);
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) acc[a][b] = mfma_f64_16x16x4(av[a], bv[b], acc[a][b]);
+  }
+  if (w > 0) {
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) red[w - 1][a * NB + b][r][lane] = acc[a][b][r];
   }
   __syncthreads();
-  int cur = 0;
-  for (int c = 0; c < nchunks; ++c) {
-    const bool more = (c + 1) < nchunks;
-    if (more) load((c + 1) * TK);
+  if (w != 0) return;
 #pragma unroll
-    for (int kk = 0; kk < TK; kk += 4) {
-      const double a = As[cur][kk + (lane >> 4)][wr * 16 + (lane & 15)];
-      const double b = Bs[cur][kk + (lane >> 4)][wc * 16 + (lane & 15)];
-      acc = mfma_f64_16x16x4(a, b, acc);
+  for (int a = 0; a < NB; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int col = j0 + b * 16 + l16;
+      if (col >= g.N) continue;
+      const double cf = g.cs_mode ? scale_of(g.cs_mode, g.cs, g.cs_coef, col) : 1.0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = i0 + a * 16 + lk + 4 * r;
+        if (row >= g.M) continue;
+        const double sum = acc[a][b][r] + red[0][a * NB + b][r][lane] + red[1][a * NB + b][r][lane] +
+                           red[2][a * NB + b][r][lane];
+        const double rf = g.rs_mode ? scale_of(g.rs_mode, g.rs, g.rs_coef, row) : 1.0;
+        double v = g.alpha * (rf * sum * cf);
+        double* cp = g.C + (size_t)row * g.ldc + col;
+        if (g.beta != 0.0) v += g.beta * (*cp);
+        if (row == col) v += g.diag_add;
+        *cp = v;
+      }
     }
-    if (more) store(cur ^ 1);
-    __syncthreads();
-    cur ^= 1;
-  }
-
-  const int col = j0 + wc * 16 + (lane & 15);
-  if (col >= g.N) return;
-  const double cf = g.cs_mode ? scale_of(g.cs_mode, g.cs, g.cs_coef, col) : 1.0;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int row = i0 + wr * 16 + (lane >> 4) + 4 * r;
-    if (row >= g.M) continue;
-    const double rf = g.rs_mode ? scale_of(g.rs_mode, g.rs, g.rs_coef, row) : 1.0;
-    double v = g.alpha * (rf * acc[r] * cf);
-    double* cp = g.C + (size_t)row * g.ldc + col;
-    if (g.beta != 0.0) v += g.beta * (*cp);
-    if (row == col) v += g.diag_add;
-    *cp = v;
-  }
 }
 
 static inline GemmArgs gemm_args(int M, int N, int K, const double* A, int lda, int transA,
@@ -133,9 +119,13 @@ static inline GemmArgs gemm_args(int M, int N, int K, const double* A, int lda, 
 }
 
 static inline hipError_t launch_gemm(const GemmArgs& g, hipStream_t s) {
-  using namespace gemm_cfg;
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
-  const int tiles = ((g.M + TM - 1) / TM) * ((g.N + TN - 1) / TN);
-  hipLaunchKernelGGL(k_gemm, dim3(tiles), dim3(NT), 0, s, g);
+  const int t32 = ((g.M + 31) / 32) * ((g.N + 31) / 32);
+  if (t32 >= 192) {
+    hipLaunchKernelGGL(k_gemm<32>, dim3(t32), dim3(256), 0, s, g);
+  } else {
+    const int t16 = ((g.M + 15) / 16) * ((g.N + 15) / 16);
+    hipLaunchKernelGGL(k_gemm<16>, dim3(t16), dim3(256), 0, s, g);
+  }
   return hipGetLastError();
 }

@@ -77,24 +77,41 @@ __global__ void k_permute_cols(double* dst, const double* src, const int* piv, i
 }
 
 // ---------------------------------------------------------- QR panel ----
-// Panel rows j0..n-1, columns j0..j0+nbw-1 of A (ld n).  Writes R back into the
-// panel (zeros below the diagonal), V (h x nbw, ld nbw) and VT = V T (h x nbw).
-// LDS: h*(nbw+1) + nbw + nbw*nbw + nbw*nbw + 64 doubles.
+// Panel rows j0..n-1, columns j0..j0+nbw-1 (nbw <= 32) of A (ld n).  Writes R
+// back into the panel (zeros below the diagonal), V (h x nbw, ld nbw) and
+// VT = V T (h x nbw).  Householder convention of LAPACK's dlarfg: for
+// x = (x0, x'), beta = -sign(x0) |x|, tau = (beta - x0)/beta,
+// v = (1, x' / (x0 - beta)); tau = 0 when x' = 0.
+// LDS: qr_panel_lds(h) doubles.
+__host__ __device__ inline size_t qr_panel_lds(int h, int nbw) {
+  return (size_t)h * (nbw + 1) + 32 + 2 * 32 * 33 + 8 * 33 + 8 + 32;
+}
+
+// value of the unit lower trapezoidal V at (r, a) from the panel (pitch nbw + 1)
+__device__ __forceinline__ double vpan(const double* pan, int r, int a, int h, int nbw) {
+  if (r >= h || a >= nbw) return 0.0;
+  return r == a ? 1.0 : (r > a ? pan[r * (nbw + 1) + a] : 0.0);
+}
+
 __global__ __launch_bounds__(256) void k_qr_panel(double* A, int n, int j0, int nbw, double* Vout,
                                                   double* VTout) {
   extern __shared__ double smem[];
-  const int h = n - j0, P = nbw + 1, tid = threadIdx.x;
+  constexpr int PT = 33;
+  const int P = nbw + 1;
+  const int h = n - j0, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   double* pan = smem;
   double* tau = pan + (size_t)h * P;
-  double* T = tau + nbw;
-  double* Y = T + nbw * nbw;
-  double* red = Y + nbw * nbw;     // 8
-  double* wv = red + 8;            // nbw
-  for (int e = tid; e < h * nbw; e += 256) {
-    const int r = e / nbw, c = e % nbw;
-    pan[r * P + c] = A[(size_t)(j0 + r) * n + j0 + c];
+  double* T = tau + 32;        // 32 x 33
+  double* Y = T + 32 * PT;     // 32 x 33
+  double* part = Y + 32 * PT;  // 8 x 33
+  double* red = part + 8 * PT; // 8
+  double* wv = red + 8;        // 32
+  for (int e = tid; e < h * 32; e += 256) {
+    const int r = e >> 5, q = e & 31;
+    if (q < nbw) pan[r * P + q] = A[(size_t)(j0 + r) * n + j0 + q];
   }
   __syncthreads();
+  const int q = tid & 31, rc = tid >> 5;
   for (int c = 0; c < nbw && c < h; ++c) {
     double s = 0.0;
     for (int r = c + 1 + tid; r < h; r += 256) { const double x = pan[r * P + c]; s += x * x; }
@@ -111,61 +128,78 @@ __global__ __launch_bounds__(256) void k_qr_panel(double* A, int n, int j0, int 
     for (int r = c + 1 + tid; r < h; r += 256) pan[r * P + c] *= scal;
     __syncthreads();
     if (tid == 0) { pan[c * P + c] = beta; tau[c] = tc; }
-    if (tc != 0.0) {
-      for (int q = c + 1 + (tid >> 6); q < nbw; q += 4) {
-        double acc = 0.0;
-        for (int r = c + 1 + (tid & 63); r < h; r += 64) acc += pan[r * P + c] * pan[r * P + q];
-        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-        if ((tid & 63) == 0) wv[q] = tc * (pan[c * P + q] + acc);
+    if (tc != 0.0 && c + 1 < nbw) {
+      // w_q = tau (A[c][q] + sum_{r>c} v_r A[r][q]) for q > c: 8 row chunks per column
+      double acc = 0.0;
+      if (q > c && q < nbw)
+        for (int r = c + 1 + rc; r < h; r += 8) acc += pan[r * P + c] * pan[r * P + q];
+      part[rc * PT + q] = acc;
+      __syncthreads();
+      if (tid > c && tid < nbw) {
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) t += part[k * PT + tid];
+        wv[tid] = tc * (pan[c * P + tid] + t);
       }
       __syncthreads();
-      const int nq = nbw - c - 1;
-      if (nq > 0) {
-        for (int e = tid; e < (h - c) * nq; e += 256) {
-          const int r = c + e / nq, q = c + 1 + e % nq;
+      if (q > c && q < nbw) {
+        const double wq = wv[q];
+        for (int r = c + rc; r < h; r += 8) {
           const double vr = (r == c) ? 1.0 : pan[r * P + c];
-          pan[r * P + q] -= vr * wv[q];
+          pan[r * P + q] -= vr * wq;
         }
       }
     }
     __syncthreads();
   }
-  // Gram matrix Y = V^T V (V unit lower trapezoidal)
-  for (int e = tid; e < nbw * nbw; e += 256) {
-    const int a = e / nbw, b = e % nbw;
-    double acc = 0.0;
-    const int r0 = a > b ? a : b;
-    for (int r = r0; r < h; ++r) {
-      const double va = (r == a) ? 1.0 : pan[r * P + a];
-      const double vb = (r == b) ? 1.0 : pan[r * P + b];
-      acc += va * vb;
+  // Gram matrix Y = V^T V (32 x 32 padded), one 16 x 16 quadrant per wave
+  const int wr = w >> 1, wc = w & 1;
+  {
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < h; k0 += 4) {
+      const int k = k0 + (lane >> 4);
+      const double a = vpan(pan, k, wr * 16 + (lane & 15), h, nbw);
+      const double b = vpan(pan, k, wc * 16 + (lane & 15), h, nbw);
+      acc = mfma_f64_16x16x4(a, b, acc);
     }
-    Y[e] = acc;
-    T[e] = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Y[(wr * 16 + (lane >> 4) + 4 * r) * PT + wc * 16 + (lane & 15)] = acc[r];
   }
+  for (int e = tid; e < 32 * 32; e += 256) T[(e >> 5) * PT + (e & 31)] = 0.0;
   __syncthreads();
-  // forward column-wise T: T[i][i] = tau_i, T[0:i, i] = -tau_i T[0:i, 0:i] Y[0:i, i]
+  // forward column-wise T (dlarft): T[i][i] = tau_i, T[0:i, i] = -tau_i T[0:i, 0:i] Y[0:i, i]
   for (int i = 0; i < nbw; ++i) {
     if (tid < i) {
       double acc = 0.0;
-      for (int k = tid; k < i; ++k) acc += T[tid * nbw + k] * Y[k * nbw + i];
-      T[tid * nbw + i] = -tau[i] * acc;
+      for (int k = tid; k < i; ++k) acc += T[tid * PT + k] * Y[k * PT + i];
+      T[tid * PT + i] = -tau[i] * acc;
     }
-    if (tid == 0) T[i * nbw + i] = tau[i];
+    if (tid == 0) T[i * PT + i] = tau[i];
     __syncthreads();
   }
-  // outputs
-  for (int e = tid; e < h * nbw; e += 256) {
-    const int r = e / nbw, b = e % nbw;
-    const double v = (r == b) ? 1.0 : (r > b ? pan[r * P + b] : 0.0);
-    Vout[e] = v;
-    double acc = 0.0;
-    const int amax = r < b ? r : b;       // V[r][a] nonzero for a <= r; T[a][b] for a <= b
-    for (int a = 0; a <= amax; ++a) {
-      const double va = (r == a) ? 1.0 : pan[r * P + a];
-      acc += va * T[a * nbw + b];
+  // VT = V T (h x 32), 16 x 16 output tiles distributed over the waves
+  const int ntile = ((h + 15) >> 4) * 2;
+  for (int t = w; t < ntile; t += 4) {
+    const int tr = t >> 1, tc = t & 1;
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k0 = 0; k0 < 32; k0 += 4) {
+      const int k = k0 + (lane >> 4);
+      const double a = vpan(pan, tr * 16 + (lane & 15), k, h, nbw);
+      const double b = T[k * PT + tc * 16 + (lane & 15)];
+      acc = mfma_f64_16x16x4(a, b, acc);
     }
-    VTout[e] = acc;
+    const int col = tc * 16 + (lane & 15);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = tr * 16 + (lane >> 4) + 4 * r;
+      if (row < h && col < nbw) VTout[(size_t)row * nbw + col] = acc[r];
+    }
+  }
+  for (int e = tid; e < h * 32; e += 256) {
+    const int r = e >> 5, b = e & 31;
+    if (b >= nbw) continue;
+    Vout[(size_t)r * nbw + b] = vpan(pan, r, b, h, nbw);
     A[(size_t)(j0 + r) * n + j0 + b] = (r <= b) ? pan[r * P + b] : 0.0;
   }
 }
@@ -184,21 +218,26 @@ __global__ void k_build_rt(const double* R, const int* piv, int n, double* Rt, d
 }
 
 // ----------------------------------------------------------- LU panel ----
-// Partial pivoting over rows j0..n-1 of the panel columns j0..j0+nbw-1 of X
-// (ld n); ipiv[j0+c] = global pivot row.  Rows are swapped inside the panel
-// only; k_lu_swap applies the interchanges elsewhere.
+// Partial pivoting over rows j0..n-1 of the panel columns j0..j0+nbw-1
+// (nbw <= 32) of X (ld n); ipiv[j0+c] = global pivot row (ties: lowest row).
+// Rows are swapped inside the panel only; k_lu_swap applies the interchanges
+// elsewhere.  LDS: lu_panel_lds(h) doubles.
+__host__ __device__ inline size_t lu_panel_lds(int h, int nbw) { return (size_t)h * (nbw + 1) + 16; }
+
 __global__ __launch_bounds__(256) void k_lu_panel(double* X, int n, int j0, int nbw, int* ipiv, int* err) {
   extern __shared__ double smem[];
-  const int h = n - j0, P = nbw + 1, tid = threadIdx.x;
+  const int P = nbw + 1;
+  const int h = n - j0, tid = threadIdx.x;
   double* pan = smem;
   double* rv = pan + (size_t)h * P;     // 4 values
   int* ri = reinterpret_cast<int*>(rv + 4);
   __shared__ int piv_s;
-  for (int e = tid; e < h * nbw; e += 256) {
-    const int r = e / nbw, c = e % nbw;
-    pan[r * P + c] = X[(size_t)(j0 + r) * n + j0 + c];
+  for (int e = tid; e < h * 32; e += 256) {
+    const int r = e >> 5, q = e & 31;
+    if (q < nbw) pan[r * P + q] = X[(size_t)(j0 + r) * n + j0 + q];
   }
   __syncthreads();
+  const int q = tid & 31, rc = tid >> 5;
   for (int c = 0; c < nbw && c < h; ++c) {
     double best = -1.0;
     int bi = 0x7fffffff;
@@ -216,37 +255,32 @@ __global__ __launch_bounds__(256) void k_lu_panel(double* X, int n, int j0, int 
     if (tid == 0) {
       double b = rv[0];
       int i = ri[0];
-      for (int w = 1; w < 4; ++w)
-        if (rv[w] > b || (rv[w] == b && ri[w] < i)) { b = rv[w]; i = ri[w]; }
+      for (int k = 1; k < 4; ++k)
+        if (rv[k] > b || (rv[k] == b && ri[k] < i)) { b = rv[k]; i = ri[k]; }
       piv_s = i;
       ipiv[j0 + c] = j0 + i;
       if (!(b > 0.0)) atomicOr(err, 4);
     }
     __syncthreads();
     const int p = piv_s;
-    if (p != c) {
-      for (int q = tid; q < nbw; q += 256) {
-        const double t = pan[c * P + q];
-        pan[c * P + q] = pan[p * P + q];
-        pan[p * P + q] = t;
-      }
-      __syncthreads();
+    if (p != c && tid < nbw) {
+      const double t = pan[c * P + tid];
+      pan[c * P + tid] = pan[p * P + tid];
+      pan[p * P + tid] = t;
     }
+    __syncthreads();
     const double inv = 1.0 / pan[c * P + c];
     for (int r = c + 1 + tid; r < h; r += 256) pan[r * P + c] *= inv;
     __syncthreads();
-    const int nq = nbw - c - 1;
-    if (nq > 0) {
-      for (int e = tid; e < (h - c - 1) * nq; e += 256) {
-        const int r = c + 1 + e / nq, q = c + 1 + e % nq;
-        pan[r * P + q] -= pan[r * P + c] * pan[c * P + q];
-      }
+    if (q > c && q < nbw) {
+      const double u = pan[c * P + q];
+      for (int r = c + 1 + rc; r < h; r += 8) pan[r * P + q] -= pan[r * P + c] * u;
     }
     __syncthreads();
   }
-  for (int e = tid; e < h * nbw; e += 256) {
-    const int r = e / nbw, c = e % nbw;
-    X[(size_t)(j0 + r) * n + j0 + c] = pan[r * P + c];
+  for (int e = tid; e < h * 32; e += 256) {
+    const int r = e >> 5, b = e & 31;
+    if (b < nbw) X[(size_t)(j0 + r) * n + j0 + b] = pan[r * P + b];
   }
 }
 
@@ -278,30 +312,41 @@ __global__ void k_lu_swap(double* X, int n, int j0, int nbw, const int* ipiv, do
 
 // Solve Tri * Z = Bm in place for a block of nrow <= 32 rows: Tri is the
 // nrow x nrow diagonal block (ld ldt), lower with unit diagonal or upper with
-// its own diagonal.  One thread per column of Bm.
+// its own diagonal.  One thread per column of Bm; the column stays in
+// registers (fully unrolled over a 32-row block padded with identity rows).
 __global__ __launch_bounds__(256) void k_trsm_block(const double* Tri, int ldt, double* Bm, int ldb, int nrow,
                                                     int ncol, int upper) {
   __shared__ double t[32][33];
-  for (int e = threadIdx.x; e < nrow * nrow; e += 256) t[e / nrow][e % nrow] = Tri[(size_t)(e / nrow) * ldt + e % nrow];
+  for (int e = threadIdx.x; e < 32 * 32; e += 256) {
+    const int r = e >> 5, k = e & 31;
+    t[r][k] = (r < nrow && k < nrow) ? Tri[(size_t)r * ldt + k] : (r == k ? 1.0 : 0.0);
+  }
   __syncthreads();
   const int col = blockIdx.x * blockDim.x + threadIdx.x;
   if (col >= ncol) return;
   double z[32];
-  for (int r = 0; r < nrow; ++r) z[r] = Bm[(size_t)r * ldb + col];
+#pragma unroll
+  for (int r = 0; r < 32; ++r) z[r] = (r < nrow) ? Bm[(size_t)r * ldb + col] : 0.0;
   if (!upper) {
-    for (int r = 0; r < nrow; ++r) {
+#pragma unroll
+    for (int r = 1; r < 32; ++r) {
       double v = z[r];
+#pragma unroll
       for (int k = 0; k < r; ++k) v -= t[r][k] * z[k];
       z[r] = v;
     }
   } else {
-    for (int r = nrow - 1; r >= 0; --r) {
+#pragma unroll
+    for (int r = 31; r >= 0; --r) {
       double v = z[r];
-      for (int k = r + 1; k < nrow; ++k) v -= t[r][k] * z[k];
+#pragma unroll
+      for (int k = r + 1; k < 32; ++k) v -= t[r][k] * z[k];
       z[r] = v / t[r][r];
     }
   }
-  for (int r = 0; r < nrow; ++r) Bm[(size_t)r * ldb + col] = z[r];
+#pragma unroll
+  for (int r = 0; r < 32; ++r)
+    if (r < nrow) Bm[(size_t)r * ldb + col] = z[r];
 }
 
 // out += sum_i log|U_ii| (one workgroup)

@@ -84,21 +84,31 @@ __global__ __launch_bounds__(256) void k_block_update(BlockArgs a) {
     const double R = pre[j] * ipow(r, a.n_col);
     if (!(uu[j] < R)) continue;          // uniform across the workgroup
     const double gam = dlt[j] / r;
-    if (tid < 32) {
-      const int x = tid;
-      double acc = 0.0;
-      for (int y = 0; y < bb; ++y) acc += Ph[x][y] * ((y == j ? 1.0 : 0.0) - g[y][j]);
-      av[x] = (x == j ? 1.0 : 0.0) - acc;
-      colj[x] = c[x][j];
-    } else if (tid < 64) {
-      const int y = tid - 32;
-      double acc = 0.0;
-      for (int x = 0; x < bb; ++x) acc += Ph[x][y] * g[j][x];
-      bv[y] = (y == j ? 1.0 : 0.0) + acc;
-      rowj[y] = (y == j ? 1.0 : 0.0) - c[j][y];
+    {
+      // a = e_j - Phi (e_j - g[:,j]),  b = e_j + Phi^T g[j,:]^T: thread (x, q)
+      // sums 4 of the 32 terms, 8 threads per x reduce by shuffles
+      const int x = tid >> 3, q = tid & 7;
+      double pa = 0.0, pb = 0.0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int y = 4 * q + k;
+        pa += Ph[x][y] * ((y == j ? 1.0 : 0.0) - g[y][j]);
+        pb += Ph[y][x] * g[j][y];
+      }
+      pa += __shfl_xor(pa, 1, 64); pb += __shfl_xor(pb, 1, 64);
+      pa += __shfl_xor(pa, 2, 64); pb += __shfl_xor(pb, 2, 64);
+      pa += __shfl_xor(pa, 4, 64); pb += __shfl_xor(pb, 4, 64);
+      if (q == 0) {
+        av[x] = (x == j ? 1.0 : 0.0) - pa;
+        bv[x] = (x == j ? 1.0 : 0.0) + pb;
+        colj[x] = c[x][j];
+        rowj[x] = (x == j ? 1.0 : 0.0) - c[j][x];
+      }
     }
     __syncthreads();
-    for (int e = tid; e < 1024; e += 256) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int e = tid + 256 * k;
       const int x = e >> 5, y = e & 31;
       Ph[x][y] += gam * av[x] * bv[y];
       c[x][y] -= gam * colj[x] * rowj[y];
