@@ -1,14 +1,25 @@
 """Benchmark of the DQMC sweep on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
 
 A step is one full sweep (upward and downward pass over all L slices with
 wraps, sequential single-flip updates, QR/UDV stabilisation every n_wrap
 slices and equal-time measurements on every slice) of the honeycomb 12x12
 Hubbard chain (N = 288, U = 4, beta = 10, dtau = 0.1, L = 100, n_wrap = 10,
-Ising field, seed 0).  Prints one JSON line.
+Ising field, seed 0).  The field and G live in HBM before the timed region.
+
+Prints one JSON line with
+  value      HS-field proposals per second over the timed sweeps,
+  roofline   the fused block-update kernel (the sweep's dominant kernel) against
+             the 8 TB/s HBM peak: algorithmic bytes = accepted flips x
+             (16 N^2 + 16 N) over the summed HIP-event time of its launches,
+             traffic = HBM bytes per launch from the committed rocprofv3
+             FETCH_SIZE / WRITE_SIZE summary (null if the kernel source changed
+             since those counters were taken),
+  cpu_baseline  the CPU oracle on one sweep of the same chain.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -18,6 +29,46 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "HS-field updates/s & sweeps/s at |G−G_oracle|≤1e-9; batched vs plain, 1 GPU"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_1704_00131_amd", "csrc", "update.h")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "block_update_pmc_honeycomb12.json")
+
+
+def kernel_source_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_per_launch():
+    """HBM bytes per block-update launch from the committed counter summary,
+    scaled by the copy-kernel calibration, or None if stale/missing."""
+    try:
+        with open(PMC_SUMMARY) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return float(d["hbm_bytes_per_launch"])
+
+
+def cpu_baseline(lat, w, field):
+    """The oracle, as it stands, on one sweep of the same chain."""
+    from oracle import hubbard, sweep
+    try:
+        import threadpoolctl
+        info = threadpoolctl.threadpool_info()
+        cores = max([i.get("num_threads", 1) for i in info] or [1])
+    except Exception:
+        cores = 1
+    om = hubbard.hubbard_model(lat.K, w.U, w.beta, w.dtau, w.n_wrap, trotter=w.trotter, seed=w.seed)
+    ch = sweep.Chain(om, field).init()
+    t0 = time.perf_counter()
+    ch.sweep(measure=True)
+    dt = time.perf_counter() - t0
+    return {"value": ch.proposals / dt, "unit": "HS-field updates/s", "cores": int(cores), "kind": "oracle",
+            "sample": "one oracle sweep (%d proposals, %d accepted) of the same honeycomb 12x12 chain from its "
+                      "initial field, NumPy/SciPy FP64, %.1f s" % (ch.proposals, ch.accepted, dt)}
 
 
 def main():
@@ -32,7 +83,6 @@ def main():
               "in this build (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_1704_00131_amd as pa
@@ -40,22 +90,35 @@ def main():
 
     w = WORKLOADS["honeycomb12_U4_b10"]
     lat = w.lattice()
-    L = w.n_slices
+    N = lat.n
     lam = pa.hubbard_coupling(w.U, w.dtau)
-    model = pa.make_model(lat.n, w.beta, w.dtau, w.n_wrap, lam, U=w.U, trotter=w.trotter, seed=w.seed)
+    model = pa.make_model(N, w.beta, w.dtau, w.n_wrap, lam, U=w.U, trotter=w.trotter, seed=w.seed)
     ch = pa.Chain(model, lat.K, device="cuda:0")
-    ch.random_field().init()
+    ch.random_field()
+    field0, _ = ch.get_state()
+    ch.init()
     for _ in range(args.warmup):
         ch.sweep(1, measure=True)
     st0 = ch.sweep(0, measure=True)
+    ch.timing("block_update", True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     st = ch.sweep(args.steps, measure=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    k_ms, k_launches, _ = ch.timing_read()
+    ch.timing("block_update", False)
     dt = t1 - t0
     proposals = st.proposals - st0.proposals
     accepted = st.accepted - st0.accepted
+
+    bytes_alg = accepted * (16.0 * N * N + 16.0 * N)
+    achieved = bytes_alg / (k_ms * 1e-3) / 1e9 if k_ms > 0 else 0.0
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_per_launch(),
+                "kernel": "k_block_update", "launches": k_launches,
+                "avg_launch_us": 1e3 * k_ms / max(1, k_launches),
+                "algorithmic_bytes_per_launch": bytes_alg / max(1, k_launches)}
     out = {
         "metric": METRIC,
         "value": proposals / dt,
@@ -70,12 +133,15 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "honeycomb 12x12 Hubbard, N=288, U=4, beta=10, dtau=0.1, L=100, n_wrap=10, "
-                               "Ising field, seed 0, one chain",
+                               "Ising field, seed 0, one chain, measurements on every slice",
                    "sweeps_per_s": args.steps / dt,
                    "accepted_updates_per_s": accepted / dt,
                    "acceptance": accepted / max(1, proposals),
                    "prec_mean": st.prec_mean, "prec_max": st.prec_max},
+        "roofline": roofline,
     }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(lat, w, field0)
     print(json.dumps(out))
 
 

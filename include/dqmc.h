@@ -138,6 +138,16 @@ dqmc_status dqmc_green_scratch(dqmc_ctx* ctx, int32_t tau, double* G_dev);
 /* log|det(1 + B(beta,0))| of the current field from scratch. */
 dqmc_status dqmc_logdet(dqmc_ctx* ctx, double* logdet);
 
+/* Per-launch timing of one kernel of the sweep, for roofline reports: while
+ * enabled, every launch of the selected kernel on the context's stream is
+ * bracketed by two HIP events.  dqmc_timing_read synchronises the stream,
+ * returns the summed event time (ms) and the launch count since the last read,
+ * and clears them.  kernel: DQMC_KERNEL_BLOCK_UPDATE (the fused block update)
+ * or DQMC_KERNEL_GEMM (the MFMA product). */
+typedef enum { DQMC_KERNEL_BLOCK_UPDATE = 0, DQMC_KERNEL_GEMM = 1 } dqmc_kernel;
+dqmc_status dqmc_timing_enable(dqmc_ctx* ctx, dqmc_kernel kernel, int32_t enable);
+dqmc_status dqmc_timing_read(dqmc_ctx* ctx, double* total_ms, uint64_t* launches, double* flops);
+
 const char* dqmc_last_error(const dqmc_ctx* ctx);
 void dqmc_destroy(dqmc_ctx* ctx);
 

@@ -10,6 +10,7 @@ STATUS_NAMES = {0: "DQMC_OK", 1: "DQMC_E_ARG", 2: "DQMC_E_UNSUPPORTED", 3: "DQMC
                 4: "DQMC_E_NUMERIC", 5: "DQMC_E_NOMEM", 6: "DQMC_E_STATE"}
 FIELD_ISING, FIELD_GAUSS = 0, 1
 TROTTER_ASYM, TROTTER_SYM = 0, 1
+KERNEL_BLOCK_UPDATE, KERNEL_GEMM = 0, 1
 
 
 class Model(ctypes.Structure):
@@ -53,6 +54,9 @@ SIGNATURES = {
     "dqmc_reset_bins": (ctypes.c_int, [ctypes.c_void_p]),
     "dqmc_green_scratch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "dqmc_logdet": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+    "dqmc_timing_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int32]),
+    "dqmc_timing_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_double)]),
     "dqmc_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "dqmc_destroy": (None, [ctypes.c_void_p]),
     "dqmc_hubbard_coupling": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_int,

@@ -100,6 +100,17 @@ class Chain:
         self._chk(self.lib.dqmc_logdet(self.ctx, ctypes.byref(out)))
         return out.value
 
+    def timing(self, kernel: str = "block_update", enable: bool = True):
+        k = _lib.KERNEL_BLOCK_UPDATE if kernel == "block_update" else _lib.KERNEL_GEMM
+        self._chk(self.lib.dqmc_timing_enable(self.ctx, k, 1 if enable else 0))
+
+    def timing_read(self):
+        ms = ctypes.c_double()
+        n = ctypes.c_uint64()
+        fl = ctypes.c_double()
+        self._chk(self.lib.dqmc_timing_read(self.ctx, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(fl)))
+        return ms.value, n.value, fl.value
+
     def close(self):
         if getattr(self, "ctx", None):
             self.lib.dqmc_destroy(self.ctx)

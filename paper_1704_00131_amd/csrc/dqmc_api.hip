@@ -61,6 +61,15 @@ struct dqmc_ctx {
   unsigned long long* counters = nullptr;   // proposals, accepted, sweep counter
   int* err_flag = nullptr;
   size_t work_doubles = 0;
+  // optional per-launch event timing of one kernel
+  bool timing = false;
+  int timing_kernel = 0;
+  std::vector<hipEvent_t> ev;
+  size_t ev_used = 0;
+  double timed_flops = 0.0;
+  ~dqmc_ctx() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
 
   UDVp slot(int k) const {
     const size_t per = 2 * (size_t)N * N + N;
@@ -111,9 +120,29 @@ size_t layout_work(dqmc_ctx* c, bool assign) {
 inline unsigned grid1(size_t n, unsigned bs = 256) { return (unsigned)((n + bs - 1) / bs); }
 
 // ---------------------------------------------------------- device steps --
-dqmc_status gemm(dqmc_ctx* c, const GemmArgs& g) {
-  HIPCHK(launch_gemm(g, c->stream));
+dqmc_status timing_begin(dqmc_ctx* c, int kernel) {
+  if (!c->timing || c->timing_kernel != kernel) return DQMC_OK;
+  while (c->ev.size() < c->ev_used + 2) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    c->ev.push_back(e);
+  }
+  HIPCHK(hipEventRecord(c->ev[c->ev_used], c->stream));
   return DQMC_OK;
+}
+
+dqmc_status timing_end(dqmc_ctx* c, int kernel) {
+  if (!c->timing || c->timing_kernel != kernel) return DQMC_OK;
+  HIPCHK(hipEventRecord(c->ev[c->ev_used + 1], c->stream));
+  c->ev_used += 2;
+  return DQMC_OK;
+}
+
+dqmc_status gemm(dqmc_ctx* c, const GemmArgs& g) {
+  if (dqmc_status s = timing_begin(c, DQMC_KERNEL_GEMM)) return s;
+  HIPCHK(launch_gemm(g, c->stream));
+  if (c->timing && c->timing_kernel == DQMC_KERNEL_GEMM) c->timed_flops += 2.0 * g.M * (double)g.N * g.K;
+  return timing_end(c, DQMC_KERNEL_GEMM);
 }
 
 // exp(x K) by scaling and squaring of a degree-18 Taylor polynomial in Horner
@@ -194,14 +223,71 @@ dqmc_status update_slice(dqmc_ctx* c, int tau, int dir) {
     a.coupling = c->m.coupling; a.alpha = c->m.alpha; a.n_col = c->m.n_col;
     a.gauss = c->m.field == DQMC_FIELD_GAUSS; a.prop_width = c->m.prop_width;
     a.counters = c->counters;
+    if (dqmc_status s = timing_begin(c, DQMC_KERNEL_BLOCK_UPDATE)) return s;
     hipLaunchKernelGGL(k_block_update, dim3(tiles), dim3(256), 0, c->stream, a);
     HIPCHK(hipGetLastError());
+    if (dqmc_status s = timing_end(c, DQMC_KERNEL_BLOCK_UPDATE)) return s;
     c->Gcur = a.Gout;
   }
   return DQMC_OK;
 }
 
 // ---------------------------------------------------- UDV stabilisation --
+template <int NBW, int MAXR>
+void qr_panel_launch(dqmc_ctx* c, double* Ap, int j0, int nbw, double* V, double* VT) {
+  const int h = c->N - j0;
+  hipLaunchKernelGGL((k_qr_panel<NBW, MAXR>), dim3(1), dim3(256), sizeof(double) * qr_panel_lds<NBW>(h), c->stream,
+                     Ap, c->N, j0, nbw, V, VT);
+}
+
+template <int NBW>
+void qr_panel_pick(dqmc_ctx* c, double* Ap, int j0, int nbw, double* V, double* VT) {
+  const int rows = (c->N - j0 + (256 / NBW) - 1) / (256 / NBW);   // rows per thread
+  if (rows <= 8) qr_panel_launch<NBW, 8>(c, Ap, j0, nbw, V, VT);
+  else if (rows <= 16) qr_panel_launch<NBW, 16>(c, Ap, j0, nbw, V, VT);
+  else if (rows <= 24) qr_panel_launch<NBW, 24>(c, Ap, j0, nbw, V, VT);
+  else if (rows <= 32) qr_panel_launch<NBW, 32>(c, Ap, j0, nbw, V, VT);
+  else if (rows <= 40) qr_panel_launch<NBW, 40>(c, Ap, j0, nbw, V, VT);
+  else qr_panel_launch<NBW, 48>(c, Ap, j0, nbw, V, VT);
+}
+
+dqmc_status launch_qr_panel(dqmc_ctx* c, double* Ap, int j0, int nbw, double* V, double* VT) {
+  if (c->nb == 32) qr_panel_pick<32>(c, Ap, j0, nbw, V, VT);
+  else if (c->nb == 16) qr_panel_pick<16>(c, Ap, j0, nbw, V, VT);
+  else qr_panel_pick<8>(c, Ap, j0, nbw, V, VT);
+  HIPCHK(hipGetLastError());
+  return DQMC_OK;
+}
+
+dqmc_status launch_lu_panel(dqmc_ctx* c, double* X, int j0, int nbw) {
+  const int h = c->N - j0;
+  hipLaunchKernelGGL(k_lu_panel, dim3(1), dim3(256), sizeof(double) * lu_panel_lds(h, nbw), c->stream, X, c->N, j0,
+                     nbw, c->ipiv, c->err_flag);
+  HIPCHK(hipGetLastError());
+  return DQMC_OK;
+}
+
+template <int NBW>
+hipError_t lds_limit_qr() {
+  const void* fns[] = {reinterpret_cast<const void*>(k_qr_panel<NBW, 8>), reinterpret_cast<const void*>(k_qr_panel<NBW, 16>),
+                       reinterpret_cast<const void*>(k_qr_panel<NBW, 24>), reinterpret_cast<const void*>(k_qr_panel<NBW, 32>),
+                       reinterpret_cast<const void*>(k_qr_panel<NBW, 40>), reinterpret_cast<const void*>(k_qr_panel<NBW, 48>)};
+  for (const void* f : fns) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 156 * 1024);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+dqmc_status set_lds_limits(dqmc_ctx* c) {
+  HIPCHK(lds_limit_qr<32>());
+  HIPCHK(lds_limit_qr<16>());
+  HIPCHK(lds_limit_qr<8>());
+  HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(k_lu_panel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             156 * 1024));
+  return DQMC_OK;
+}
+
 // QR of M (N x N, overwritten) with column pre-pivoting: M P = Q R.  Writes
 // Q, D = |diag R| and T_out = D^-1 R P^T T_in.
 dqmc_status qr_udv(dqmc_ctx* c, double* M, const double* T_in, UDVp out) {
@@ -215,9 +301,7 @@ dqmc_status qr_udv(dqmc_ctx* c, double* M, const double* T_in, UDVp out) {
     const int nbw = std::min(nb, N - j0), h = N - j0;
     double* V = c->Vall + (size_t)j0 * N;
     double* VT = c->VTall + (size_t)j0 * N;
-    const size_t lds = sizeof(double) * qr_panel_lds(h, nbw);
-    hipLaunchKernelGGL(k_qr_panel, dim3(1), dim3(256), lds, c->stream, Ap, N, j0, nbw, V, VT);
-    HIPCHK(hipGetLastError());
+    if (dqmc_status s = launch_qr_panel(c, Ap, j0, nbw, V, VT)) return s;
     const int ntr = N - j0 - nbw;
     if (ntr > 0) {
       double* At = Ap + (size_t)j0 * N + j0 + nbw;
@@ -284,9 +368,7 @@ dqmc_status lu_solve(dqmc_ctx* c, double* X, double* RHS, double* logdet) {
   const int N = c->N, nb = c->nb;
   for (int j0 = 0; j0 < N; j0 += nb) {
     const int nbw = std::min(nb, N - j0), h = N - j0;
-    const size_t lds = sizeof(double) * lu_panel_lds(h, nbw);
-    hipLaunchKernelGGL(k_lu_panel, dim3(1), dim3(256), lds, c->stream, X, N, j0, nbw, c->ipiv, c->err_flag);
-    HIPCHK(hipGetLastError());
+    if (dqmc_status s = launch_lu_panel(c, X, j0, nbw)) return s;
     hipLaunchKernelGGL(k_lu_swap, dim3(grid1((size_t)(N - nbw) + N)), dim3(256), 0, c->stream, X, N, j0, nbw,
                        c->ipiv, RHS, N, N);
     HIPCHK(hipGetLastError());
@@ -505,8 +587,9 @@ dqmc_status dqmc_create(const dqmc_model* m, const double* K, const int32_t* ver
   if (!c) return DQMC_E_NOMEM;
   c->m = *m;
   c->N = N; c->L = m->n_slices; c->nw = m->n_wrap; c->nk = m->n_slices / m->n_wrap;
-  // panel width: 32 columns while a full-height panel fits in LDS, else 16
-  c->nb = (qr_panel_lds(N, 32) * sizeof(double) <= 150 * 1024) ? 32 : 16;
+  // panel width: the register panels hold up to 48 rows per thread in
+  // 256/nb row groups
+  c->nb = (N <= 8 * 48) ? 32 : (N <= 16 * 48 ? 16 : 8);
   c->K.assign(K, K + (size_t)N * N);
   double tr = 0.0, n1 = 0.0;
   for (int j = 0; j < N; ++j) {
@@ -532,10 +615,7 @@ dqmc_status dqmc_bind(dqmc_ctx* c, const dqmc_buffers* b, void* stream) {
   c->work_doubles = layout_work(c, true);
   const int N = c->N;
   // the panel kernels keep up to ~150 KB of a panel in LDS
-  HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(k_qr_panel),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, 156 * 1024));
-  HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(k_lu_panel),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, 156 * 1024));
+  if (dqmc_status s = set_lds_limits(c)) return s;
   HIPCHK(hipMemcpyAsync(c->Kd, c->K.data(), sizeof(double) * N * N, hipMemcpyHostToDevice, c->stream));
   if (dqmc_status s = expm(c, -c->m.dtau, c->E)) return s;
   if (dqmc_status s = expm(c, +c->m.dtau, c->Einv)) return s;
@@ -704,6 +784,32 @@ dqmc_status dqmc_logdet(dqmc_ctx* c, double* logdet) {
   HIPCHK(hipMemcpyAsync(logdet, c->logdet, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   return read_flag(c);
+}
+
+dqmc_status dqmc_timing_enable(dqmc_ctx* c, dqmc_kernel kernel, int32_t enable) {
+  if (!c || (kernel != DQMC_KERNEL_BLOCK_UPDATE && kernel != DQMC_KERNEL_GEMM)) return DQMC_E_ARG;
+  c->timing = enable != 0;
+  c->timing_kernel = kernel;
+  c->ev_used = 0;
+  c->timed_flops = 0.0;
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_timing_read(dqmc_ctx* c, double* total_ms, uint64_t* launches, double* flops) {
+  if (!c || !total_ms || !launches) return DQMC_E_ARG;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  double tot = 0.0;
+  for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]));
+    tot += ms;
+  }
+  *total_ms = tot;
+  *launches = c->ev_used / 2;
+  if (flops) *flops = c->timed_flops;
+  c->ev_used = 0;
+  c->timed_flops = 0.0;
+  return DQMC_OK;
 }
 
 const char* dqmc_last_error(const dqmc_ctx* c) { return c ? c->err.c_str() : "null context"; }

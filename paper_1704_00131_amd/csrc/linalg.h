@@ -77,46 +77,61 @@ __global__ void k_permute_cols(double* dst, const double* src, const int* piv, i
 }
 
 // ---------------------------------------------------------- QR panel ----
-// Panel rows j0..n-1, columns j0..j0+nbw-1 (nbw <= 32) of A (ld n).  Writes R
-// back into the panel (zeros below the diagonal), V (h x nbw, ld nbw) and
-// VT = V T (h x nbw).  Householder convention of LAPACK's dlarfg: for
-// x = (x0, x'), beta = -sign(x0) |x|, tau = (beta - x0)/beta,
-// v = (1, x' / (x0 - beta)); tau = 0 when x' = 0.
-// LDS: qr_panel_lds(h) doubles.
-__host__ __device__ inline size_t qr_panel_lds(int h, int nbw) {
-  return (size_t)h * (nbw + 1) + 32 + 2 * 32 * 33 + 8 * 33 + 8 + 32;
+// Panel rows j0..n-1, columns j0..j0+nbw-1 (nbw <= NBW) of A (ld n).  Writes R
+// back into the panel (zeros below the diagonal), V (h x nbw, ld nbw, unit
+// lower trapezoidal) and VT = V T (h x nbw).  Householder convention of
+// LAPACK's dlarfg: for x = (x0, x'), beta = -sign(x0) |x|,
+// tau = (beta - x0)/beta, v = (1, x' / (x0 - beta)); tau = 0 when x' = 0.
+//
+// Thread (q, rg) keeps column q of the panel for rows r = rg + RG i in
+// registers (RG = 256 / NBW row groups, up to MAXR rows each); LDS carries only
+// the current reflector, the per-column partial sums and the small T, Y.
+template <int NBW>
+__host__ __device__ inline size_t qr_panel_lds(int h) {
+  return (size_t)h * (NBW + 1) + (size_t)h + (256 / NBW) * (NBW + 2) + 3 * 32 * 33 + 64;
 }
 
-// value of the unit lower trapezoidal V at (r, a) from the panel (pitch nbw + 1)
-__device__ __forceinline__ double vpan(const double* pan, int r, int a, int h, int nbw) {
-  if (r >= h || a >= nbw) return 0.0;
-  return r == a ? 1.0 : (r > a ? pan[r * (nbw + 1) + a] : 0.0);
-}
-
+template <int NBW, int MAXR>
 __global__ __launch_bounds__(256) void k_qr_panel(double* A, int n, int j0, int nbw, double* Vout,
                                                   double* VTout) {
+  constexpr int RG = 256 / NBW, PT = 33, PV = NBW + 1;
   extern __shared__ double smem[];
-  constexpr int PT = 33;
-  const int P = nbw + 1;
   const int h = n - j0, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  double* pan = smem;
-  double* tau = pan + (size_t)h * P;
-  double* T = tau + 32;        // 32 x 33
-  double* Y = T + 32 * PT;     // 32 x 33
-  double* part = Y + 32 * PT;  // 8 x 33
-  double* red = part + 8 * PT; // 8
-  double* wv = red + 8;        // 32
-  for (int e = tid; e < h * 32; e += 256) {
-    const int r = e >> 5, q = e & 31;
-    if (q < nbw) pan[r * P + q] = A[(size_t)(j0 + r) * n + j0 + q];
+  const int q = tid % NBW, rg = tid / NBW;
+  double* vsh = smem;                       // h x PV: V at the end
+  double* vbuf = vsh + (size_t)h * PV;      // h: current reflector
+  double* part = vbuf + h;                  // RG x PV partial sums
+  double* T = part + RG * PV;               // 32 x 33
+  double* Y = T + 32 * PT;                  // 32 x 33
+  double* normp = Y + 32 * PT;             // RG partial norms
+  double* misc = normp + RG;               // tau[32], wv[32]
+  double* tau = misc;
+  double* wv = misc + 32;
+  double a[MAXR], va[MAXR];
+#pragma unroll
+  for (int i = 0; i < MAXR; ++i) {
+    const int r = rg + RG * i;
+    a[i] = (r < h && q < nbw) ? A[(size_t)(j0 + r) * n + j0 + q] : 0.0;
   }
-  __syncthreads();
-  const int q = tid & 31, rc = tid >> 5;
+  for (int e = tid; e < 32 * PT; e += 256) { T[e] = 0.0; Y[e] = 0.0; }
+  __shared__ double x0s;
   for (int c = 0; c < nbw && c < h; ++c) {
+    // 1. norm of the column below the diagonal, and its diagonal entry
+    if (q == c) {
+      double s = 0.0;
+#pragma unroll
+      for (int i = 0; i < MAXR; ++i) {
+        const int r = rg + RG * i;
+        if (r > c && r < h) s += a[i] * a[i];
+        if (r == c) x0s = a[i];
+      }
+      normp[rg] = s;
+    }
+    __syncthreads();
     double s = 0.0;
-    for (int r = c + 1 + tid; r < h; r += 256) { const double x = pan[r * P + c]; s += x * x; }
-    s = block_sum<256>(s, red);
-    const double x0 = pan[c * P + c];
+#pragma unroll
+    for (int k = 0; k < RG; ++k) s += normp[k];
+    const double x0 = x0s;
     double beta, tc, scal;
     if (s == 0.0) { tc = 0.0; beta = x0; scal = 0.0; }
     else {
@@ -125,82 +140,90 @@ __global__ __launch_bounds__(256) void k_qr_panel(double* A, int n, int j0, int 
       tc = (beta - x0) / beta;
       scal = 1.0 / (x0 - beta);
     }
-    for (int r = c + 1 + tid; r < h; r += 256) pan[r * P + c] *= scal;
-    __syncthreads();
-    if (tid == 0) { pan[c * P + c] = beta; tau[c] = tc; }
-    if (tc != 0.0 && c + 1 < nbw) {
-      // w_q = tau (A[c][q] + sum_{r>c} v_r A[r][q]) for q > c: 8 row chunks per column
-      double acc = 0.0;
-      if (q > c && q < nbw)
-        for (int r = c + 1 + rc; r < h; r += 8) acc += pan[r * P + c] * pan[r * P + q];
-      part[rc * PT + q] = acc;
-      __syncthreads();
-      if (tid > c && tid < nbw) {
-        double t = 0.0;
+    // 2. the reflector v (v_c = 1) into LDS; column c keeps v below the diagonal and beta on it
+    if (q == c) {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) t += part[k * PT + tid];
-        wv[tid] = tc * (pan[c * P + tid] + t);
-      }
-      __syncthreads();
-      if (q > c && q < nbw) {
-        const double wq = wv[q];
-        for (int r = c + rc; r < h; r += 8) {
-          const double vr = (r == c) ? 1.0 : pan[r * P + c];
-          pan[r * P + q] -= vr * wq;
+      for (int i = 0; i < MAXR; ++i) {
+        const int r = rg + RG * i;
+        if (r < h) {
+          if (r > c) { a[i] *= scal; vbuf[r] = a[i]; }
+          else if (r == c) { a[i] = beta; vbuf[r] = 1.0; }
         }
       }
     }
+    if (tid == 0) tau[c] = tc;
     __syncthreads();
-  }
-  // Gram matrix Y = V^T V (32 x 32 padded), one 16 x 16 quadrant per wave
-  const int wr = w >> 1, wc = w & 1;
-  {
-    v4d acc = {0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < h; k0 += 4) {
-      const int k = k0 + (lane >> 4);
-      const double a = vpan(pan, k, wr * 16 + (lane & 15), h, nbw);
-      const double b = vpan(pan, k, wc * 16 + (lane & 15), h, nbw);
-      acc = mfma_f64_16x16x4(a, b, acc);
-    }
+    // 3. partial v^T A[:, q] over rows >= c for every other column q
+    if (q != c && q < nbw) {
+      double p = 0.0;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) Y[(wr * 16 + (lane >> 4) + 4 * r) * PT + wc * 16 + (lane & 15)] = acc[r];
+      for (int i = 0; i < MAXR; ++i) {
+        const int r = rg + RG * i;
+        const double v = (r >= c && r < h) ? vbuf[r] : 0.0;
+        va[i] = v;
+        p += v * a[i];
+      }
+      part[rg * PV + q] = p;
+    }
+    __syncthreads();
+    if (tid < nbw && tid != c) {
+      double t = 0.0;
+#pragma unroll
+      for (int k = 0; k < RG; ++k) t += part[k * PV + tid];
+      if (tid > c) wv[tid] = tc * t;
+      else Y[tid * PT + c] = t;            // v_q^T v_c for q < c
+    }
+    __syncthreads();
+    // 4. apply H = I - tau v v^T to the trailing columns
+    if (q > c && q < nbw && tc != 0.0) {
+      const double wq = wv[q];
+#pragma unroll
+      for (int i = 0; i < MAXR; ++i) a[i] -= va[i] * wq;
+    }
   }
-  for (int e = tid; e < 32 * 32; e += 256) T[(e >> 5) * PT + (e & 31)] = 0.0;
+  // V into LDS (unit lower trapezoidal) and to global; R back into A
+#pragma unroll
+  for (int i = 0; i < MAXR; ++i) {
+    const int r = rg + RG * i;
+    if (r < h && q < nbw) {
+      const double v = (r == q) ? 1.0 : (r > q ? a[i] : 0.0);
+      vsh[r * PV + q] = v;
+      Vout[(size_t)r * nbw + q] = v;
+      A[(size_t)(j0 + r) * n + j0 + q] = (r <= q) ? a[i] : 0.0;
+    }
+  }
   __syncthreads();
   // forward column-wise T (dlarft): T[i][i] = tau_i, T[0:i, i] = -tau_i T[0:i, 0:i] Y[0:i, i]
   for (int i = 0; i < nbw; ++i) {
-    if (tid < i) {
-      double acc = 0.0;
-      for (int k = tid; k < i; ++k) acc += T[tid * PT + k] * Y[k * PT + i];
-      T[tid * PT + i] = -tau[i] * acc;
-    }
+    const int t = tid >> 3, part8 = tid & 7;
+    double acc = 0.0;
+    if (t < i)
+      for (int k = t + part8; k < i; k += 8) acc += T[t * PT + k] * Y[k * PT + i];
+    acc += __shfl_xor(acc, 1, 64);
+    acc += __shfl_xor(acc, 2, 64);
+    acc += __shfl_xor(acc, 4, 64);
+    if (t < i && part8 == 0) T[t * PT + i] = -tau[i] * acc;
     if (tid == 0) T[i * PT + i] = tau[i];
     __syncthreads();
   }
-  // VT = V T (h x 32), 16 x 16 output tiles distributed over the waves
-  const int ntile = ((h + 15) >> 4) * 2;
+  // VT = V T (h x nbw), 16 x 16 output tiles over the waves
+  const int ntile = ((h + 15) >> 4) * ((nbw + 15) >> 4);
+  const int tcn = (nbw + 15) >> 4;
   for (int t = w; t < ntile; t += 4) {
-    const int tr = t >> 1, tc = t & 1;
+    const int tr = t / tcn, tcl = t % tcn;
     v4d acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int k0 = 0; k0 < 32; k0 += 4) {
-      const int k = k0 + (lane >> 4);
-      const double a = vpan(pan, tr * 16 + (lane & 15), k, h, nbw);
-      const double b = T[k * PT + tc * 16 + (lane & 15)];
-      acc = mfma_f64_16x16x4(a, b, acc);
+    for (int k0 = 0; k0 < nbw; k0 += 4) {
+      const int k = k0 + (lane >> 4), row = tr * 16 + (lane & 15);
+      const double av_ = (row < h && k < nbw) ? vsh[row * PV + k] : 0.0;
+      const double bv_ = (k < nbw) ? T[k * PT + tcl * 16 + (lane & 15)] : 0.0;
+      acc = mfma_f64_16x16x4(av_, bv_, acc);
     }
-    const int col = tc * 16 + (lane & 15);
+    const int col = tcl * 16 + (lane & 15);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = tr * 16 + (lane >> 4) + 4 * r;
       if (row < h && col < nbw) VTout[(size_t)row * nbw + col] = acc[r];
     }
-  }
-  for (int e = tid; e < h * 32; e += 256) {
-    const int r = e >> 5, b = e & 31;
-    if (b >= nbw) continue;
-    Vout[(size_t)r * nbw + b] = vpan(pan, r, b, h, nbw);
-    A[(size_t)(j0 + r) * n + j0 + b] = (r <= b) ? pan[r * P + b] : 0.0;
   }
 }
 
