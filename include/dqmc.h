@@ -151,6 +151,50 @@ dqmc_status dqmc_timing_read(dqmc_ctx* ctx, double* total_ms, uint64_t* launches
 const char* dqmc_last_error(const dqmc_ctx* ctx);
 void dqmc_destroy(dqmc_ctx* ctx);
 
+/* ------------------------------------------------------------- batches ----
+ * Many independent Markov chains, the paper's one-walker-per-MPI-task
+ * parallelism (section "Performance, memory requirements and
+ * parallelization") moved onto one GPU.  Chains whose models agree in all but
+ * the seed form a group; every kernel of a group's sweep covers all of its
+ * chains in one launch (one chain per grid row), so a sweep of the whole batch
+ * is one launch sequence per group, which dqmc_batch_capture records once
+ * into a hipGraph.  Each chain follows exactly the arithmetic and random
+ * numbers of a single-chain context with the same model. */
+typedef struct dqmc_batch dqmc_batch;
+
+/* models[i] and K[i] (n_i x n_i host, symmetric) describe chain i; copied. */
+dqmc_status dqmc_batch_create(int32_t n_chains, const dqmc_model* models, const double* const* K,
+                              dqmc_batch** out);
+/* Bytes of the single caller-owned device buffer that holds every chain. */
+dqmc_status dqmc_batch_query_size(const dqmc_batch* b, size_t* work_bytes);
+/* Bind that buffer (256-byte aligned) and the stream; computes the
+ * exponentials once per group. */
+dqmc_status dqmc_batch_bind(dqmc_batch* b, void* work, void* hip_stream);
+dqmc_status dqmc_batch_random_fields(dqmc_batch* b);
+dqmc_status dqmc_batch_set_state(dqmc_batch* b, int32_t chain, const double* field_host, uint64_t sweep_counter);
+dqmc_status dqmc_batch_get_state(dqmc_batch* b, int32_t chain, double* field_host, uint64_t* sweep_counter);
+/* Storage fill and G(0) of every chain. */
+dqmc_status dqmc_batch_init(dqmc_batch* b);
+/* Autotuner: per group, times `trials` sweeps with 16 x 16 and 32 x 32 MFMA
+ * GEMM tiles and keeps the faster (the trial sweeps advance the chains like
+ * warm-up sweeps; a captured graph is dropped). */
+dqmc_status dqmc_batch_autotune(dqmc_batch* b, int32_t trials);
+/* The GEMM tile chosen for a chain's group (0 = size-based default). */
+dqmc_status dqmc_batch_tuning(const dqmc_batch* b, int32_t chain, int32_t* gemm_tile);
+/* Record `sweeps_per_graph` sweeps of the whole batch into a hipGraph; later
+ * dqmc_batch_sweep calls with the same measure flag replay it. */
+dqmc_status dqmc_batch_capture(dqmc_batch* b, int32_t sweeps_per_graph, int32_t measure);
+/* n_sweeps sweeps of every chain; stats summed over chains. */
+dqmc_status dqmc_batch_sweep(dqmc_batch* b, int32_t n_sweeps, int32_t measure, dqmc_stats* total);
+/* G (n*n host doubles), bin sums (4 host doubles) and statistics of one chain. */
+dqmc_status dqmc_batch_read_chain(dqmc_batch* b, int32_t chain, double* G_host, double* bins_host,
+                                  dqmc_stats* stats);
+int32_t dqmc_batch_groups(const dqmc_batch* b);
+/* Host-only self-check of the batch buffer layout (no device access). */
+dqmc_status dqmc_batch_check_layout(dqmc_batch* b);
+const char* dqmc_batch_last_error(const dqmc_batch* b);
+void dqmc_batch_destroy(dqmc_batch* b);
+
 /* Coupling of the exact two-valued Hubbard-Stratonovich identity,
  * cosh(lambda) = exp(dtau U / 2) (DQMC_FIELD_ISING), or of the Gaussian
  * identity, c = sqrt(dtau U) (DQMC_FIELD_GAUSS). */

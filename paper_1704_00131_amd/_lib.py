@@ -58,6 +58,25 @@ SIGNATURES = {
     "dqmc_timing_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_double)]),
     "dqmc_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "dqmc_batch_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.POINTER(ctypes.c_void_p)]),
+    "dqmc_batch_query_size": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]),
+    "dqmc_batch_bind": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "dqmc_batch_random_fields": (ctypes.c_int, [ctypes.c_void_p]),
+    "dqmc_batch_set_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_uint64]),
+    "dqmc_batch_get_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                            ctypes.POINTER(ctypes.c_uint64)]),
+    "dqmc_batch_init": (ctypes.c_int, [ctypes.c_void_p]),
+    "dqmc_batch_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "dqmc_batch_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "dqmc_batch_capture": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
+    "dqmc_batch_sweep": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Stats)]),
+    "dqmc_batch_read_chain": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.POINTER(Stats)]),
+    "dqmc_batch_groups": (ctypes.c_int32, [ctypes.c_void_p]),
+    "dqmc_batch_check_layout": (ctypes.c_int, [ctypes.c_void_p]),
+    "dqmc_batch_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "dqmc_batch_destroy": (None, [ctypes.c_void_p]),
     "dqmc_destroy": (None, [ctypes.c_void_p]),
     "dqmc_hubbard_coupling": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                              ctypes.POINTER(ctypes.c_double)]),
@@ -87,10 +106,13 @@ def load():
     return _lib
 
 
-def check(status, ctx=None):
+def check(status, ctx=None, batch=None):
     if status != DQMC_OK:
         msg = ""
         if ctx is not None:
             raw = load().dqmc_last_error(ctx)
+            msg = raw.decode() if raw else ""
+        elif batch is not None:
+            raw = load().dqmc_batch_last_error(batch)
             msg = raw.decode() if raw else ""
         raise DQMCError(status, msg)

@@ -1,0 +1,92 @@
+"""Python face of a batch of independent chains (one launch sequence per same-size group)."""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import Model, Stats, check
+
+
+class Batch:
+    def __init__(self, models, Ks, device="cuda", stream=None):
+        lib = _lib.load()
+        self.lib = lib
+        self.n = len(models)
+        self.models = list(models)
+        arr = (Model * self.n)(*models)
+        self._Ks = [np.ascontiguousarray(K, dtype=np.float64) for K in Ks]
+        ptrs = (ctypes.c_void_p * self.n)(*[K.ctypes.data for K in self._Ks])
+        b = ctypes.c_void_p()
+        check(lib.dqmc_batch_create(self.n, ctypes.cast(arr, ctypes.c_void_p), ctypes.cast(ptrs, ctypes.c_void_p),
+                                    ctypes.byref(b)))
+        self.b = b
+        size = ctypes.c_size_t()
+        check(lib.dqmc_batch_query_size(b, ctypes.byref(size)))
+        self.device = torch.device(device)
+        self.work = torch.empty(max(1, (size.value + 7) // 8), dtype=torch.float64, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._chk(lib.dqmc_batch_bind(b, ctypes.c_void_p(self.work.data_ptr()),
+                                      ctypes.c_void_p(self.stream.cuda_stream)))
+
+    def _chk(self, status):
+        check(status, batch=self.b)
+
+    def random_fields(self):
+        self._chk(self.lib.dqmc_batch_random_fields(self.b))
+        return self
+
+    def set_state(self, chain, field, sweep_counter=0):
+        m = self.models[chain]
+        f = np.ascontiguousarray(field, dtype=np.float64).reshape(m.n_slices, m.n)
+        self._chk(self.lib.dqmc_batch_set_state(self.b, chain, f.ctypes.data, sweep_counter))
+
+    def get_state(self, chain):
+        m = self.models[chain]
+        f = np.empty((m.n_slices, m.n))
+        ctr = ctypes.c_uint64()
+        self._chk(self.lib.dqmc_batch_get_state(self.b, chain, f.ctypes.data, ctypes.byref(ctr)))
+        return f, ctr.value
+
+    def init(self):
+        self._chk(self.lib.dqmc_batch_init(self.b))
+        return self
+
+    def autotune(self, trials=1):
+        self._chk(self.lib.dqmc_batch_autotune(self.b, trials))
+
+    @property
+    def n_groups(self):
+        return self.lib.dqmc_batch_groups(self.b)
+
+    def tuning(self, chain):
+        v = ctypes.c_int32()
+        self._chk(self.lib.dqmc_batch_tuning(self.b, chain, ctypes.byref(v)))
+        return v.value
+
+    def capture(self, sweeps_per_graph=1, measure=True):
+        self._chk(self.lib.dqmc_batch_capture(self.b, sweeps_per_graph, 1 if measure else 0))
+
+    def sweep(self, n_sweeps=1, measure=True) -> Stats:
+        st = Stats()
+        self._chk(self.lib.dqmc_batch_sweep(self.b, n_sweeps, 1 if measure else 0, ctypes.byref(st)))
+        return st
+
+    def read_chain(self, chain):
+        m = self.models[chain]
+        G = np.empty((m.n, m.n))
+        bins = np.empty(4)
+        st = Stats()
+        self._chk(self.lib.dqmc_batch_read_chain(self.b, chain, G.ctypes.data, bins.ctypes.data, ctypes.byref(st)))
+        return G, bins, st
+
+    def close(self):
+        if getattr(self, "b", None):
+            self.lib.dqmc_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

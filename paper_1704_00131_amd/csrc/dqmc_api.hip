@@ -61,6 +61,15 @@ struct dqmc_ctx {
   unsigned long long* counters = nullptr;   // proposals, accepted, sweep counter
   int* err_flag = nullptr;
   size_t work_doubles = 0;
+  // batching: nch chains with identical models except the seed; every
+  // per-chain buffer of chain i sits at (its chain-0 address) + i * cs doubles;
+  // the exponentials and the identity UDV in [shared_lo, shared_hi) are common
+  int nch = 1;
+  size_t cs = 0;
+  const double *shared_lo = nullptr, *shared_hi = nullptr;
+  int gemm_tile = 0;
+  std::vector<uint64_t> seeds;
+  double* gbuf = nullptr;
   // optional per-launch event timing of one kernel
   bool timing = false;
   int timing_kernel = 0;
@@ -93,31 +102,64 @@ dqmc_status fail(dqmc_ctx* c, dqmc_status s, const std::string& msg) {
       return fail(c, DQMC_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-size_t layout_work(dqmc_ctx* c, bool assign) {
+// Shared part: the exponentials, K and the identity UDV (one copy for all
+// chains).  With base == nullptr only the size is computed and no pointer of
+// the context is touched.
+size_t layout_shared(dqmc_ctx* c, double* base) {
   const size_t N = c->N, NN = N * N;
   Layout l;
-  auto P = [&](size_t n) -> double* { size_t o = l.take(n); return assign ? c->work + o : nullptr; };
-  c->E = P(NN); c->Einv = P(NN); c->Eh = P(NN); c->Ehinv = P(NN); c->Kd = P(NN);
-  for (int i = 0; i < 6; ++i) c->S[i] = P(NN);
-  c->Vall = P(NN); c->VTall = P(NN); c->Zq = P(NN); c->Rt = P(NN);
-  c->X = P(NN); c->RHS = P(NN); c->Gs = P(NN); c->T1 = P(NN);
-  UDVp* us[4] = {&c->cur, &c->uid, &c->hA, &c->hB};
-  for (UDVp* u : us) { u->Q = P(NN); u->D = P(N); u->T = P(NN); }
-  c->G2 = P(NN);
-  c->field_alt = P((size_t)c->L * N);
-  c->norms = P(N);
-  double* pv = P(N); double* ipv = P(N);
-  c->piv = reinterpret_cast<int*>(pv); c->ipiv = reinterpret_cast<int*>(ipv);
-  c->bins = P(4);
-  c->prec_hist = P(2 * (size_t)c->nk + 2);
-  c->prec_tot = P(4);
-  c->logdet = P(4);
-  double* ctr = P(4); c->counters = reinterpret_cast<unsigned long long*>(ctr);
-  double* ef = P(1); c->err_flag = reinterpret_cast<int*>(ef);
+  auto P = [&](double*& dst, size_t n) { const size_t o = l.take(n); if (base) dst = base + o; };
+  P(c->E, NN); P(c->Einv, NN); P(c->Eh, NN); P(c->Ehinv, NN); P(c->Kd, NN);
+  P(c->uid.Q, NN); P(c->uid.D, N); P(c->uid.T, NN);
+  P(c->gbuf, 8 * (size_t)std::max(1, c->nch));   // contiguous staging of per-chain scalars
+  if (base) { c->shared_lo = base; c->shared_hi = base + l.off; }
   return l.off;
 }
 
+// Per-chain scratch (same convention for base == nullptr).
+size_t layout_chain(dqmc_ctx* c, double* base) {
+  const size_t N = c->N, NN = N * N;
+  Layout l;
+  auto P = [&](double*& dst, size_t n) { const size_t o = l.take(n); if (base) dst = base + o; };
+  for (int i = 0; i < 6; ++i) P(c->S[i], NN);
+  P(c->Vall, NN); P(c->VTall, NN); P(c->Zq, NN); P(c->Rt, NN);
+  P(c->X, NN); P(c->RHS, NN); P(c->Gs, NN); P(c->T1, NN);
+  UDVp* us[3] = {&c->cur, &c->hA, &c->hB};
+  for (UDVp* u : us) { P(u->Q, NN); P(u->D, N); P(u->T, NN); }
+  P(c->G2, NN);
+  P(c->field_alt, (size_t)c->L * N);
+  P(c->norms, N);
+  double* pv = nullptr;
+  double* ipv = nullptr;
+  P(pv, N); P(ipv, N);
+  P(c->bins, 4);
+  P(c->prec_hist, 2 * (size_t)c->nk + 2);
+  P(c->prec_tot, 4);
+  P(c->logdet, 4);
+  double* ctr = nullptr;
+  double* ef = nullptr;
+  P(ctr, 4); P(ef, 1);
+  if (base) {
+    c->piv = reinterpret_cast<int*>(pv);
+    c->ipiv = reinterpret_cast<int*>(ipv);
+    c->counters = reinterpret_cast<unsigned long long*>(ctr);
+    c->err_flag = reinterpret_cast<int*>(ef);
+  }
+  return l.off;
+}
+
+size_t layout_work(dqmc_ctx* c, bool assign) {
+  const size_t sh = layout_shared(c, assign ? c->work : nullptr);
+  const size_t ch = layout_chain(c, assign ? c->work + sh : nullptr);
+  return sh + ch;
+}
+
 inline unsigned grid1(size_t n, unsigned bs = 256) { return (unsigned)((n + bs - 1) / bs); }
+inline dim3 gridc(const dqmc_ctx* c, unsigned x) { return dim3(x, (unsigned)c->nch); }
+inline bool is_shared(const dqmc_ctx* c, const void* p) {
+  const double* q = static_cast<const double*>(p);
+  return q && q >= c->shared_lo && q < c->shared_hi;
+}
 
 // ---------------------------------------------------------- device steps --
 dqmc_status timing_begin(dqmc_ctx* c, int kernel) {
@@ -138,10 +180,22 @@ dqmc_status timing_end(dqmc_ctx* c, int kernel) {
   return DQMC_OK;
 }
 
-dqmc_status gemm(dqmc_ctx* c, const GemmArgs& g) {
+dqmc_status gemm(dqmc_ctx* c, GemmArgs g) {
+  g.nch = c->nch;
+  g.tile = c->gemm_tile;
+  g.cstride = c->cs;
+  g.pc = 0;
+  if (c->cs) {
+    if (!is_shared(c, g.A)) g.pc |= PC_A;
+    if (!is_shared(c, g.B)) g.pc |= PC_B;
+    if (!is_shared(c, g.C)) g.pc |= PC_C;
+    if (g.rs && !is_shared(c, g.rs)) g.pc |= PC_RS;
+    if (g.cs && !is_shared(c, g.cs)) g.pc |= PC_CS;
+    if (g.ks && !is_shared(c, g.ks)) g.pc |= PC_KS;
+  }
   if (dqmc_status s = timing_begin(c, DQMC_KERNEL_GEMM)) return s;
   HIPCHK(launch_gemm(g, c->stream));
-  if (c->timing && c->timing_kernel == DQMC_KERNEL_GEMM) c->timed_flops += 2.0 * g.M * (double)g.N * g.K;
+  if (c->timing && c->timing_kernel == DQMC_KERNEL_GEMM) c->timed_flops += 2.0 * g.M * (double)g.N * g.K * c->nch;
   return timing_end(c, DQMC_KERNEL_GEMM);
 }
 
@@ -155,19 +209,20 @@ dqmc_status expm(dqmc_ctx* c, double x, double* out) {
   const double a = x / std::ldexp(1.0, sq);
   double* P0 = c->S[0];
   double* P1 = c->S[1];
-  hipLaunchKernelGGL(k_set_identity, dim3(grid1((size_t)N * N)), dim3(256), 0, c->stream, P0, N, N);
+  // one chain's scratch serves as workspace; the result is shared
+  hipLaunchKernelGGL(k_set_identity, dim3(grid1((size_t)N * N)), dim3(256), 0, c->stream, P0, N, N, (size_t)0);
   HIPCHK(hipGetLastError());
   for (int k = 18; k >= 1; --k) {   // P <- I + (a K / k) P
     GemmArgs g = gemm_args(N, N, N, c->Kd, N, 0, P0, N, 0, P1, N, a / k, 0.0);
     g.diag_add = 1.0;
-    if (dqmc_status s = gemm(c, g)) return s;
+    HIPCHK(launch_gemm(g, c->stream));
     std::swap(P0, P1);
   }
   for (int k = 0; k < sq; ++k) {
-    if (dqmc_status s = gemm(c, gemm_args(N, N, N, P0, N, 0, P0, N, 0, P1, N))) return s;
+    HIPCHK(launch_gemm(gemm_args(N, N, N, P0, N, 0, P0, N, 0, P1, N), c->stream));
     std::swap(P0, P1);
   }
-  hipLaunchKernelGGL(k_copy, dim3(grid1((size_t)N * N)), dim3(256), 0, c->stream, out, P0, (size_t)N * N);
+  hipLaunchKernelGGL(k_copy, dim3(grid1((size_t)N * N)), dim3(256), 0, c->stream, out, P0, (size_t)N * N, (size_t)0);
   HIPCHK(hipGetLastError());
   return DQMC_OK;
 }
@@ -223,8 +278,9 @@ dqmc_status update_slice(dqmc_ctx* c, int tau, int dir) {
     a.coupling = c->m.coupling; a.alpha = c->m.alpha; a.n_col = c->m.n_col;
     a.gauss = c->m.field == DQMC_FIELD_GAUSS; a.prop_width = c->m.prop_width;
     a.counters = c->counters;
+    a.cs = c->cs;
     if (dqmc_status s = timing_begin(c, DQMC_KERNEL_BLOCK_UPDATE)) return s;
-    hipLaunchKernelGGL(k_block_update, dim3(tiles), dim3(256), 0, c->stream, a);
+    hipLaunchKernelGGL(k_block_update, gridc(c, tiles), dim3(256), 0, c->stream, a);
     HIPCHK(hipGetLastError());
     if (dqmc_status s = timing_end(c, DQMC_KERNEL_BLOCK_UPDATE)) return s;
     c->Gcur = a.Gout;
@@ -236,8 +292,8 @@ dqmc_status update_slice(dqmc_ctx* c, int tau, int dir) {
 template <int NBW, int MAXR>
 void qr_panel_launch(dqmc_ctx* c, double* Ap, int j0, int nbw, double* V, double* VT) {
   const int h = c->N - j0;
-  hipLaunchKernelGGL((k_qr_panel<NBW, MAXR>), dim3(1), dim3(256), sizeof(double) * qr_panel_lds<NBW>(h), c->stream,
-                     Ap, c->N, j0, nbw, V, VT);
+  hipLaunchKernelGGL((k_qr_panel<NBW, MAXR>), gridc(c, 1), dim3(256), sizeof(double) * qr_panel_lds<NBW>(h),
+                     c->stream, Ap, c->N, j0, nbw, V, VT, c->cs);
 }
 
 template <int NBW>
@@ -261,8 +317,8 @@ dqmc_status launch_qr_panel(dqmc_ctx* c, double* Ap, int j0, int nbw, double* V,
 
 dqmc_status launch_lu_panel(dqmc_ctx* c, double* X, int j0, int nbw) {
   const int h = c->N - j0;
-  hipLaunchKernelGGL(k_lu_panel, dim3(1), dim3(256), sizeof(double) * lu_panel_lds(h, nbw), c->stream, X, c->N, j0,
-                     nbw, c->ipiv, c->err_flag);
+  hipLaunchKernelGGL(k_lu_panel, gridc(c, 1), dim3(256), sizeof(double) * lu_panel_lds(h, nbw), c->stream, X, c->N,
+                     j0, nbw, c->ipiv, c->err_flag, c->cs);
   HIPCHK(hipGetLastError());
   return DQMC_OK;
 }
@@ -293,9 +349,10 @@ dqmc_status set_lds_limits(dqmc_ctx* c) {
 dqmc_status qr_udv(dqmc_ctx* c, double* M, const double* T_in, UDVp out) {
   const int N = c->N, nb = c->nb;
   double* Ap = c->S[4];
-  hipLaunchKernelGGL(k_colnorm_order, dim3(1), dim3(1024), 0, c->stream, M, N, c->norms, c->piv);
+  hipLaunchKernelGGL(k_colnorm_order, gridc(c, 1), dim3(1024), 0, c->stream, M, N, c->norms, c->piv, c->cs);
   HIPCHK(hipGetLastError());
-  hipLaunchKernelGGL(k_permute_cols, dim3(grid1((size_t)N * N)), dim3(256), 0, c->stream, Ap, M, c->piv, N);
+  hipLaunchKernelGGL(k_permute_cols, gridc(c, grid1((size_t)N * N)), dim3(256), 0, c->stream, Ap, M, c->piv, N,
+                     c->cs);
   HIPCHK(hipGetLastError());
   for (int j0 = 0; j0 < N; j0 += nb) {
     const int nbw = std::min(nb, N - j0), h = N - j0;
@@ -310,7 +367,7 @@ dqmc_status qr_udv(dqmc_ctx* c, double* M, const double* T_in, UDVp out) {
     }
   }
   // explicit Q by backward accumulation of the block reflectors
-  hipLaunchKernelGGL(k_set_identity, dim3(grid1((size_t)N * N)), dim3(256), 0, c->stream, out.Q, N, N);
+  hipLaunchKernelGGL(k_set_identity, gridc(c, grid1((size_t)N * N)), dim3(256), 0, c->stream, out.Q, N, N, c->cs);
   HIPCHK(hipGetLastError());
   const int last = ((N - 1) / nb) * nb;
   for (int j0 = last; j0 >= 0; j0 -= nb) {
@@ -321,8 +378,8 @@ dqmc_status qr_udv(dqmc_ctx* c, double* M, const double* T_in, UDVp out) {
     if (dqmc_status s = gemm(c, gemm_args(nbw, h, h, V, nbw, 1, Qs, N, 0, c->Zq, N))) return s;
     if (dqmc_status s = gemm(c, gemm_args(h, h, nbw, VT, nbw, 0, c->Zq, N, 0, Qs, N, -1.0, 1.0))) return s;
   }
-  hipLaunchKernelGGL(k_build_rt, dim3(grid1((size_t)N * N)), dim3(256), 0, c->stream, Ap, c->piv, N, c->Rt, out.D,
-                     c->err_flag);
+  hipLaunchKernelGGL(k_build_rt, gridc(c, grid1((size_t)N * N)), dim3(256), 0, c->stream, Ap, c->piv, N, c->Rt,
+                     out.D, c->err_flag, c->cs);
   HIPCHK(hipGetLastError());
   return gemm(c, gemm_args(N, N, N, c->Rt, N, 0, T_in, N, 0, out.T, N));
 }
@@ -369,13 +426,13 @@ dqmc_status lu_solve(dqmc_ctx* c, double* X, double* RHS, double* logdet) {
   for (int j0 = 0; j0 < N; j0 += nb) {
     const int nbw = std::min(nb, N - j0), h = N - j0;
     if (dqmc_status s = launch_lu_panel(c, X, j0, nbw)) return s;
-    hipLaunchKernelGGL(k_lu_swap, dim3(grid1((size_t)(N - nbw) + N)), dim3(256), 0, c->stream, X, N, j0, nbw,
-                       c->ipiv, RHS, N, N);
+    hipLaunchKernelGGL(k_lu_swap, gridc(c, grid1((size_t)(N - nbw) + N)), dim3(256), 0, c->stream, X, N, j0, nbw,
+                       c->ipiv, RHS, N, N, c->cs);
     HIPCHK(hipGetLastError());
     const int ntr = N - j0 - nbw;
     if (ntr > 0) {
-      hipLaunchKernelGGL(k_trsm_block, dim3(grid1(ntr)), dim3(256), 0, c->stream, X + (size_t)j0 * N + j0, N,
-                         X + (size_t)j0 * N + j0 + nbw, N, nbw, ntr, 0);
+      hipLaunchKernelGGL(k_trsm_block, gridc(c, grid1(ntr)), dim3(256), 0, c->stream, X + (size_t)j0 * N + j0, N,
+                         X + (size_t)j0 * N + j0 + nbw, N, nbw, ntr, 0, c->cs);
       HIPCHK(hipGetLastError());
       if (dqmc_status s = gemm(c, gemm_args(ntr, ntr, nbw, X + (size_t)(j0 + nbw) * N + j0, N, 0,
                                             X + (size_t)j0 * N + j0 + nbw, N, 0, X + (size_t)(j0 + nbw) * N + j0 + nbw,
@@ -386,8 +443,8 @@ dqmc_status lu_solve(dqmc_ctx* c, double* X, double* RHS, double* logdet) {
   // forward substitution with unit-lower L (right-looking)
   for (int j0 = 0; j0 < N; j0 += nb) {
     const int nbw = std::min(nb, N - j0);
-    hipLaunchKernelGGL(k_trsm_block, dim3(grid1(N)), dim3(256), 0, c->stream, X + (size_t)j0 * N + j0, N,
-                       RHS + (size_t)j0 * N, N, nbw, N, 0);
+    hipLaunchKernelGGL(k_trsm_block, gridc(c, grid1(N)), dim3(256), 0, c->stream, X + (size_t)j0 * N + j0, N,
+                       RHS + (size_t)j0 * N, N, nbw, N, 0, c->cs);
     HIPCHK(hipGetLastError());
     const int rest = N - j0 - nbw;
     if (rest > 0)
@@ -399,8 +456,8 @@ dqmc_status lu_solve(dqmc_ctx* c, double* X, double* RHS, double* logdet) {
   const int last = ((N - 1) / nb) * nb;
   for (int j0 = last; j0 >= 0; j0 -= nb) {
     const int nbw = std::min(nb, N - j0);
-    hipLaunchKernelGGL(k_trsm_block, dim3(grid1(N)), dim3(256), 0, c->stream, X + (size_t)j0 * N + j0, N,
-                       RHS + (size_t)j0 * N, N, nbw, N, 1);
+    hipLaunchKernelGGL(k_trsm_block, gridc(c, grid1(N)), dim3(256), 0, c->stream, X + (size_t)j0 * N + j0, N,
+                       RHS + (size_t)j0 * N, N, nbw, N, 1, c->cs);
     HIPCHK(hipGetLastError());
     if (j0 > 0)
       if (dqmc_status s = gemm(c, gemm_args(j0, N, nbw, X + j0, N, 0, RHS + (size_t)j0 * N, N, 0, RHS, N, -1.0,
@@ -408,7 +465,7 @@ dqmc_status lu_solve(dqmc_ctx* c, double* X, double* RHS, double* logdet) {
         return s;
   }
   if (logdet) {
-    hipLaunchKernelGGL(k_logabs_diag, dim3(1), dim3(256), 0, c->stream, X, N, logdet);
+    hipLaunchKernelGGL(k_logabs_diag, gridc(c, 1), dim3(256), 0, c->stream, X, N, logdet, c->cs);
     HIPCHK(hipGetLastError());
   }
   return DQMC_OK;
@@ -426,13 +483,17 @@ dqmc_status merge(dqmc_ctx* c, UDVp R, UDVp Lf, double* Gout, double* logdet) {
   GemmArgs g2 = gemm_args(N, N, N, R.T, N, 0, Lf.T, N, 1, c->X, N, 1.0, 1.0);
   g2.rs = R.D; g2.rs_mode = SC_SMALL; g2.cs = Lf.D; g2.cs_mode = SC_SMALL;
   if (dqmc_status s = gemm(c, g2)) return s;
-  const dim3 tg((N + 31) / 32, (N + 31) / 32);
-  hipLaunchKernelGGL(k_transpose_scale, tg, dim3(256), 0, c->stream, c->RHS, R.Q, N, R.D, SC_INV_BIG);
+  const dim3 tg((N + 31) / 32, (N + 31) / 32, (unsigned)c->nch);
+  // the right form may be the shared identity: offset it only when it is per chain
+  hipLaunchKernelGGL(k_transpose_scale, tg, dim3(256), 0, c->stream, c->RHS, R.Q, N, R.D, SC_INV_BIG, c->cs,
+                     is_shared(c, R.Q) ? (size_t)0 : c->cs);
   HIPCHK(hipGetLastError());
   if (logdet) {
-    hipLaunchKernelGGL(k_logbig_sum, dim3(1), dim3(256), 0, c->stream, R.D, N, logdet, 0);
+    hipLaunchKernelGGL(k_logbig_sum, gridc(c, 1), dim3(256), 0, c->stream, R.D, N, logdet, 0,
+                       is_shared(c, R.D) ? (size_t)0 : c->cs, c->cs);
     HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL(k_logbig_sum, dim3(1), dim3(256), 0, c->stream, Lf.D, N, logdet, 1);
+    hipLaunchKernelGGL(k_logbig_sum, gridc(c, 1), dim3(256), 0, c->stream, Lf.D, N, logdet, 1,
+                       is_shared(c, Lf.D) ? (size_t)0 : c->cs, c->cs);
     HIPCHK(hipGetLastError());
   }
   if (dqmc_status s = lu_solve(c, c->X, c->RHS, logdet)) return s;
@@ -443,17 +504,17 @@ dqmc_status merge(dqmc_ctx* c, UDVp R, UDVp Lf, double* Gout, double* logdet) {
 
 dqmc_status copy_udv(dqmc_ctx* c, UDVp dst, UDVp src) {
   const size_t NN = (size_t)c->N * c->N;
-  hipLaunchKernelGGL(k_copy, dim3(grid1(NN)), dim3(256), 0, c->stream, dst.Q, src.Q, NN);
-  hipLaunchKernelGGL(k_copy, dim3(grid1(c->N)), dim3(256), 0, c->stream, dst.D, src.D, (size_t)c->N);
-  hipLaunchKernelGGL(k_copy, dim3(grid1(NN)), dim3(256), 0, c->stream, dst.T, src.T, NN);
+  hipLaunchKernelGGL(k_copy, gridc(c, grid1(NN)), dim3(256), 0, c->stream, dst.Q, src.Q, NN, c->cs);
+  hipLaunchKernelGGL(k_copy, gridc(c, grid1(c->N)), dim3(256), 0, c->stream, dst.D, src.D, (size_t)c->N, c->cs);
+  hipLaunchKernelGGL(k_copy, gridc(c, grid1(NN)), dim3(256), 0, c->stream, dst.T, src.T, NN, c->cs);
   HIPCHK(hipGetLastError());
   return DQMC_OK;
 }
 
 dqmc_status stabilise(dqmc_ctx* c, int hist_index) {
   const size_t NN = (size_t)c->N * c->N;
-  hipLaunchKernelGGL(k_prec_replace, dim3(std::min<size_t>(grid1(NN), 1024)), dim3(256), 0, c->stream, c->Gcur,
-                     c->G, c->Gs, NN, c->prec_hist + hist_index, c->err_flag);
+  hipLaunchKernelGGL(k_prec_replace, gridc(c, (unsigned)std::min<size_t>(grid1(NN), 1024)), dim3(256), 0, c->stream,
+                     c->Gcur, c->G, c->Gs, NN, c->prec_hist + hist_index, c->err_flag, c->cs);
   HIPCHK(hipGetLastError());
   c->Gcur = c->G;
   return DQMC_OK;
@@ -466,8 +527,8 @@ dqmc_status measure(dqmc_ctx* c) {
     if (dqmc_status s = gemm(c, gemm_args(N, N, N, c->Eh, N, 0, c->Gcur, N, 0, c->T1, N))) return s;
     T1 = c->T1;
   }
-  hipLaunchKernelGGL(k_measure, dim3(1), dim3(1024), 0, c->stream, c->Gcur, T1, c->Ehinv, c->Kd, N, c->trK,
-                     (double)c->m.n_col, c->m.u_int, c->bins, c->err_flag);
+  hipLaunchKernelGGL(k_measure, gridc(c, 1), dim3(1024), 0, c->stream, c->Gcur, T1, c->Ehinv, c->Kd, N, c->trK,
+                     (double)c->m.n_col, c->m.u_int, c->bins, c->err_flag, c->cs);
   HIPCHK(hipGetLastError());
   return DQMC_OK;
 }
@@ -511,15 +572,15 @@ dqmc_status sweep_once(dqmc_ctx* c, bool meas) {
       if (dqmc_status s = wrap_down(c, tau, c->G)) return s;
     }
   }
-  hipLaunchKernelGGL(k_finish_sweep, dim3(1), dim3(64), 0, c->stream, c->prec_hist, hist, c->prec_tot,
-                     c->m.prec_threshold, c->counters, c->err_flag);
+  hipLaunchKernelGGL(k_finish_sweep, gridc(c, 1), dim3(64), 0, c->stream, c->prec_hist, hist, c->prec_tot,
+                     c->m.prec_threshold, c->counters, c->err_flag, c->cs);
   HIPCHK(hipGetLastError());
   c->row_alt.clear();
   return DQMC_OK;
 }
 
 dqmc_status fill_small(dqmc_ctx* c, double* p, size_t n, double v) {
-  hipLaunchKernelGGL(k_fill, dim3(grid1(n)), dim3(256), 0, c->stream, p, n, v);
+  hipLaunchKernelGGL(k_fill, gridc(c, grid1(n)), dim3(256), 0, c->stream, p, n, v, is_shared(c, p) ? (size_t)0 : c->cs);
   HIPCHK(hipGetLastError());
   return DQMC_OK;
 }
@@ -537,10 +598,31 @@ dqmc_status check_model(const dqmc_model* m) {
   return DQMC_OK;
 }
 
-dqmc_status read_flag(dqmc_ctx* c) {
-  int flag = 0;
-  HIPCHK(hipMemcpyAsync(&flag, c->err_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+// Copy `bytes` (<= 64) of a per-chain item from every chain into host dst
+// (chain-major), through the contiguous staging buffer.
+dqmc_status gather(dqmc_ctx* c, void* dst, const void* src, size_t bytes) {
+  if (c->nch == 1) {
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, c->stream));
+    return DQMC_OK;
+  }
+  const int count = (int)((bytes + 7) / 8);
+  hipLaunchKernelGGL(k_gather, dim3(1, c->nch), dim3(64), 0, c->stream, c->gbuf, static_cast<const double*>(src),
+                     count, c->cs);
+  HIPCHK(hipGetLastError());
+  std::vector<double> tmp((size_t)count * c->nch);
+  HIPCHK(hipMemcpyAsync(tmp.data(), c->gbuf, tmp.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
+  for (int i = 0; i < c->nch; ++i)
+    std::memcpy(static_cast<char*>(dst) + i * bytes, tmp.data() + (size_t)i * count, bytes);
+  return DQMC_OK;
+}
+
+dqmc_status read_flag(dqmc_ctx* c) {
+  std::vector<int> flags(c->nch, 0);
+  if (dqmc_status s = gather(c, flags.data(), c->err_flag, sizeof(int))) return s;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  int flag = 0;
+  for (int f : flags) flag |= f;
   if (flag) {
     c->poisoned = true;
     std::string why;
@@ -550,6 +632,30 @@ dqmc_status read_flag(dqmc_ctx* c) {
     if (flag & 8) why += " stabilisation precision above threshold;";
     return fail(c, DQMC_E_NUMERIC, "numerical failure:" + why);
   }
+  return DQMC_OK;
+}
+
+// Statistics of one chain (chain >= 0) or summed over all chains (chain < 0).
+dqmc_status chain_stats(dqmc_ctx* c, int chain, dqmc_stats* st) {
+  std::vector<unsigned long long> ctr(4 * (size_t)c->nch);
+  std::vector<double> pt(4 * (size_t)c->nch);
+  if (dqmc_status s = gather(c, ctr.data(), c->counters, 4 * sizeof(double))) return s;
+  if (dqmc_status s = gather(c, pt.data(), c->prec_tot, 4 * sizeof(double))) return s;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  dqmc_stats t{};
+  double ps = 0.0, pc = 0.0, pm = 0.0;
+  for (int i = 0; i < c->nch; ++i) {
+    if (chain >= 0 && i != chain) continue;
+    t.proposals += ctr[4 * i];
+    t.accepted += ctr[4 * i + 1];
+    ps += pt[4 * i];
+    pm = std::max(pm, pt[4 * i + 1]);
+    pc += pt[4 * i + 2];
+  }
+  t.n_prec = (uint64_t)pc;
+  t.prec_mean = pc > 0 ? ps / pc : 0.0;
+  t.prec_max = pm;
+  *st = t;
   return DQMC_OK;
 }
 
@@ -603,6 +709,41 @@ dqmc_status dqmc_create(const dqmc_model* m, const double* K, const int32_t* ver
   return DQMC_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Device-side set-up of a bound context (one chain or a group of chains):
+// exponentials, identity UDV, zeroed counters and the chains' Philox keys.
+dqmc_status setup_device(dqmc_ctx* c) {
+  const int N = c->N;
+  if (dqmc_status s = set_lds_limits(c)) return s;
+  HIPCHK(hipMemcpyAsync(c->Kd, c->K.data(), sizeof(double) * N * N, hipMemcpyHostToDevice, c->stream));
+  if (dqmc_status s = expm(c, -c->m.dtau, c->E)) return s;
+  if (dqmc_status s = expm(c, +c->m.dtau, c->Einv)) return s;
+  if (dqmc_status s = expm(c, -0.5 * c->m.dtau, c->Eh)) return s;
+  if (dqmc_status s = expm(c, +0.5 * c->m.dtau, c->Ehinv)) return s;
+  hipLaunchKernelGGL(k_set_identity, dim3(grid1((size_t)N * N)), dim3(256), 0, c->stream, c->uid.Q, N, N, (size_t)0);
+  hipLaunchKernelGGL(k_set_identity, dim3(grid1((size_t)N * N)), dim3(256), 0, c->stream, c->uid.T, N, N, (size_t)0);
+  if (dqmc_status s = fill_small(c, c->uid.D, N, 1.0)) return s;
+  if (dqmc_status s = fill_small(c, reinterpret_cast<double*>(c->counters), 4, 0.0)) return s;
+  if (dqmc_status s = fill_small(c, reinterpret_cast<double*>(c->err_flag), 1, 0.0)) return s;
+  if (c->seeds.empty()) c->seeds.assign(c->nch, c->m.seed);
+  // chain keys: host -> staging buffer -> counters[3] of every chain
+  HIPCHK(hipMemcpyAsync(c->gbuf, c->seeds.data(), sizeof(uint64_t) * c->nch, hipMemcpyHostToDevice, c->stream));
+  hipLaunchKernelGGL(k_scatter, dim3(1, c->nch), dim3(64), 0, c->stream, reinterpret_cast<double*>(c->counters + 3),
+                     c->gbuf, 1, c->cs);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->bound = true;
+  c->initialized = false;
+  return DQMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 dqmc_status dqmc_bind(dqmc_ctx* c, const dqmc_buffers* b, void* stream) {
   if (!c || !b || !b->G || !b->field || !b->slots || !b->work) return fail(c, DQMC_E_ARG, "null buffer");
   for (void* p : {b->G, b->field, b->slots, b->work})
@@ -613,23 +754,7 @@ dqmc_status dqmc_bind(dqmc_ctx* c, const dqmc_buffers* b, void* stream) {
   c->work = static_cast<double*>(b->work);
   c->stream = static_cast<hipStream_t>(stream);
   c->work_doubles = layout_work(c, true);
-  const int N = c->N;
-  // the panel kernels keep up to ~150 KB of a panel in LDS
-  if (dqmc_status s = set_lds_limits(c)) return s;
-  HIPCHK(hipMemcpyAsync(c->Kd, c->K.data(), sizeof(double) * N * N, hipMemcpyHostToDevice, c->stream));
-  if (dqmc_status s = expm(c, -c->m.dtau, c->E)) return s;
-  if (dqmc_status s = expm(c, +c->m.dtau, c->Einv)) return s;
-  if (dqmc_status s = expm(c, -0.5 * c->m.dtau, c->Eh)) return s;
-  if (dqmc_status s = expm(c, +0.5 * c->m.dtau, c->Ehinv)) return s;
-  hipLaunchKernelGGL(k_set_identity, dim3(grid1((size_t)N * N)), dim3(256), 0, c->stream, c->uid.Q, N, N);
-  hipLaunchKernelGGL(k_set_identity, dim3(grid1((size_t)N * N)), dim3(256), 0, c->stream, c->uid.T, N, N);
-  if (dqmc_status s = fill_small(c, c->uid.D, N, 1.0)) return s;
-  if (dqmc_status s = fill_small(c, reinterpret_cast<double*>(c->counters), 4, 0.0)) return s;
-  if (dqmc_status s = fill_small(c, reinterpret_cast<double*>(c->err_flag), 1, 0.0)) return s;
-  HIPCHK(hipStreamSynchronize(c->stream));
-  c->bound = true;
-  c->initialized = false;
-  return DQMC_OK;
+  return setup_device(c);
 }
 
 dqmc_status dqmc_set_state(dqmc_ctx* c, const double* field_host, uint64_t sweep_counter) {
@@ -667,11 +792,10 @@ dqmc_status dqmc_random_field(dqmc_ctx* c) {
   if (!c) return DQMC_E_ARG;
   if (!c->bound) return fail(c, DQMC_E_STATE, "not bound");
   const size_t n = (size_t)c->L * c->N;
-  hipLaunchKernelGGL(k_random_field, dim3(grid1(n)), dim3(256), 0, c->stream, c->field, c->L, c->N,
-                     (unsigned long long)c->m.seed, c->m.field == DQMC_FIELD_GAUSS ? 1 : 0);
+  hipLaunchKernelGGL(k_random_field, gridc(c, grid1(n)), dim3(256), 0, c->stream, c->field, c->L, c->N,
+                     c->counters, c->m.field == DQMC_FIELD_GAUSS ? 1 : 0, c->cs);
   HIPCHK(hipGetLastError());
-  unsigned long long zero = 0;
-  HIPCHK(hipMemcpyAsync(c->counters + 2, &zero, sizeof(zero), hipMemcpyHostToDevice, c->stream));
+  if (dqmc_status s = fill_small(c, reinterpret_cast<double*>(c->counters + 2), 1, 0.0)) return s;
   HIPCHK(hipStreamSynchronize(c->stream));
   c->initialized = false;
   return DQMC_OK;
@@ -707,16 +831,7 @@ dqmc_status dqmc_sweep(dqmc_ctx* c, int32_t n_sweeps, int32_t meas, dqmc_stats* 
   if (dqmc_status r = read_flag(c)) return r;
   const auto t1 = std::chrono::steady_clock::now();
   if (st) {
-    unsigned long long ctr[3];
-    double pt[3];
-    HIPCHK(hipMemcpyAsync(ctr, c->counters, sizeof(ctr), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipMemcpyAsync(pt, c->prec_tot, sizeof(pt), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
-    st->proposals = ctr[0];
-    st->accepted = ctr[1];
-    st->n_prec = (uint64_t)pt[2];
-    st->prec_mean = pt[2] > 0 ? pt[0] / pt[2] : 0.0;
-    st->prec_max = pt[1];
+    if (dqmc_status s = chain_stats(c, -1, st)) return s;
     st->seconds = std::chrono::duration<double>(t1 - t0).count();
   }
   return DQMC_OK;
@@ -829,5 +944,359 @@ dqmc_status dqmc_hubbard_coupling(double U, double dtau, dqmc_field_kind kind, d
   }
   return DQMC_OK;
 }
+
+}  // extern "C"
+
+// ================================================================ batch ==
+// A batch of independent chains.  Chains whose models agree in everything
+// but the seed (same lattice, N, L, n_wrap, couplings) form a group; a group
+// is one context whose every launch covers all of its chains (blockIdx.y =
+// chain), so one sweep of the whole batch is one launch sequence per group.
+// That sequence can be captured once into a hipGraph and replayed.
+struct dqmc_batch {
+  std::vector<dqmc_ctx*> groups;
+  std::vector<int> group_of, index_of;
+  std::vector<size_t> group_off;   // doubles
+  size_t total = 0;
+  double* work = nullptr;
+  hipStream_t stream = nullptr;
+  bool bound = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int graph_sweeps = 0, graph_measure = -1;
+  std::string err;
+  ~dqmc_batch() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (dqmc_ctx* g : groups) delete g;
+  }
+};
+
+namespace {
+
+dqmc_status bfail(dqmc_batch* b, dqmc_status s, const std::string& msg) {
+  if (b) b->err = msg;
+  return s;
+}
+
+#define BHIPCHK_(expr)                                                                    \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return bfail(b, DQMC_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+bool same_group(const dqmc_model& a, const dqmc_model& b, const double* Ka, const double* Kb) {
+  return a.n == b.n && a.n_slices == b.n_slices && a.beta == b.beta && a.dtau == b.dtau && a.n_wrap == b.n_wrap &&
+         a.n_col == b.n_col && a.field == b.field && a.coupling == b.coupling && a.alpha == b.alpha &&
+         a.u_int == b.u_int && a.trotter == b.trotter && a.prec_threshold == b.prec_threshold &&
+         a.prop_width == b.prop_width && std::memcmp(Ka, Kb, sizeof(double) * a.n * a.n) == 0;
+}
+
+// Per-chain region of a group: G, field, slots, then the chain scratch.
+size_t group_chain_doubles(dqmc_ctx* c) {
+  const size_t N = c->N, NN = N * N;
+  Layout l;
+  l.take(NN);
+  l.take((size_t)c->L * N);
+  l.take((size_t)(c->nk + 1) * (2 * NN + N));
+  return l.off + layout_chain(c, nullptr);
+}
+
+void place_group(dqmc_ctx* c, double* base) {
+  const size_t N = c->N, NN = N * N;
+  c->cs = group_chain_doubles(c);          // size only: touches no pointer
+  const size_t sh = layout_shared(c, base);
+  double* chain0 = base + sh;
+  Layout l;
+  c->G = chain0 + l.take(NN);
+  c->field = chain0 + l.take((size_t)c->L * N);
+  c->slots = chain0 + l.take((size_t)(c->nk + 1) * (2 * NN + N));
+  layout_chain(c, chain0 + l.off);
+  c->work = base;
+}
+
+// Every per-chain pointer of every chain, and every shared pointer, must lie
+// inside [lo, hi) with its full extent: checked on the host before any launch.
+bool layout_ok(const dqmc_ctx* c, const double* lo, const double* hi) {
+  const size_t N = c->N, NN = N * N, last = (size_t)(c->nch - 1) * c->cs;
+  auto in = [&](const void* p, size_t n, bool per_chain) {
+    const double* q = static_cast<const double*>(p);
+    if (!q || q < lo) return false;
+    return q + (per_chain ? last : 0) + n <= hi;
+  };
+  bool ok = in(c->E, NN, false) && in(c->Einv, NN, false) && in(c->Eh, NN, false) && in(c->Ehinv, NN, false) &&
+            in(c->Kd, NN, false) && in(c->uid.Q, NN, false) && in(c->uid.D, N, false) && in(c->uid.T, NN, false) &&
+            in(c->gbuf, 8 * (size_t)c->nch, false);
+  ok = ok && in(c->G, NN, true) && in(c->field, (size_t)c->L * N, true) &&
+       in(c->slots, (size_t)(c->nk + 1) * (2 * NN + N), true);
+  for (int i = 0; i < 6; ++i) ok = ok && in(c->S[i], NN, true);
+  for (const double* p : {c->Vall, c->VTall, c->Zq, c->Rt, c->X, c->RHS, c->Gs, c->T1, c->G2}) ok = ok && in(p, NN, true);
+  for (const UDVp* u : {&c->cur, &c->hA, &c->hB}) ok = ok && in(u->Q, NN, true) && in(u->D, N, true) && in(u->T, NN, true);
+  ok = ok && in(c->field_alt, (size_t)c->L * N, true) && in(c->norms, N, true) && in(c->piv, N / 2 + 1, true) &&
+       in(c->ipiv, N / 2 + 1, true) && in(c->bins, 4, true) && in(c->prec_hist, 2 * (size_t)c->nk + 2, true) &&
+       in(c->prec_tot, 4, true) && in(c->logdet, 4, true) && in(c->counters, 4, true) && in(c->err_flag, 1, true);
+  return ok;
+}
+
+dqmc_status batch_flags(dqmc_batch* b) {
+  for (dqmc_ctx* g : b->groups)
+    if (dqmc_status s = read_flag(g)) return bfail(b, s, g->err);
+  return DQMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dqmc_status dqmc_batch_create(int32_t n_chains, const dqmc_model* models, const double* const* K, dqmc_batch** out) {
+  if (!out) return DQMC_E_ARG;
+  *out = nullptr;
+  if (n_chains < 1 || !models || !K) return DQMC_E_ARG;
+  dqmc_batch* b = new (std::nothrow) dqmc_batch();
+  if (!b) return DQMC_E_NOMEM;
+  std::vector<int> first_of;   // chain index that defines each group
+  b->group_of.resize(n_chains);
+  b->index_of.resize(n_chains);
+  for (int i = 0; i < n_chains; ++i) {
+    int g = -1;
+    for (size_t k = 0; k < first_of.size() && g < 0; ++k)
+      if (same_group(models[first_of[k]], models[i], K[first_of[k]], K[i])) g = (int)k;
+    if (g < 0) {
+      dqmc_ctx* c = nullptr;
+      dqmc_status s = dqmc_create(&models[i], K[i], nullptr, &c);
+      if (s != DQMC_OK) { delete b; return s; }
+      c->nch = 0;
+      b->groups.push_back(c);
+      first_of.push_back(i);
+      g = (int)first_of.size() - 1;
+    }
+    dqmc_ctx* c = b->groups[g];
+    b->group_of[i] = g;
+    b->index_of[i] = c->nch++;
+    c->seeds.push_back(models[i].seed);
+  }
+  size_t off = 0;
+  for (dqmc_ctx* c : b->groups) {
+    Layout l;
+    l.take(layout_shared(c, nullptr));
+    l.take(group_chain_doubles(c) * c->nch);
+    b->group_off.push_back(off);
+    off += l.off;
+  }
+  b->total = off;
+  *out = b;
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_batch_query_size(const dqmc_batch* b, size_t* work_bytes) {
+  if (!b || !work_bytes) return DQMC_E_ARG;
+  *work_bytes = b->total * sizeof(double);
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_batch_bind(dqmc_batch* b, void* work, void* stream) {
+  if (!b || !work) return bfail(b, DQMC_E_ARG, "null buffer");
+  if (reinterpret_cast<uintptr_t>(work) % 256) return bfail(b, DQMC_E_ARG, "buffer must be 256-byte aligned");
+  b->work = static_cast<double*>(work);
+  b->stream = static_cast<hipStream_t>(stream);
+  for (size_t g = 0; g < b->groups.size(); ++g) {
+    dqmc_ctx* c = b->groups[g];
+    c->stream = b->stream;
+    double* base = b->work + b->group_off[g];
+    place_group(c, base);
+    const double* hi = (g + 1 < b->groups.size()) ? b->work + b->group_off[g + 1] : b->work + b->total;
+    if (!layout_ok(c, base, hi)) return bfail(b, DQMC_E_STATE, "internal layout check failed");
+  }
+  for (dqmc_ctx* c : b->groups)
+    if (dqmc_status s = setup_device(c)) return bfail(b, s, c->err);
+  b->bound = true;
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_batch_random_fields(dqmc_batch* b) {
+  if (!b) return DQMC_E_ARG;
+  if (!b->bound) return bfail(b, DQMC_E_STATE, "not bound");
+  for (dqmc_ctx* c : b->groups)
+    if (dqmc_status s = dqmc_random_field(c)) return bfail(b, s, c->err);
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_batch_set_state(dqmc_batch* b, int32_t chain, const double* field_host, uint64_t sweep_counter) {
+  if (!b || !field_host || chain < 0 || chain >= (int)b->group_of.size()) return bfail(b, DQMC_E_ARG, "bad arguments");
+  if (!b->bound) return bfail(b, DQMC_E_STATE, "not bound");
+  dqmc_ctx* c = b->groups[b->group_of[chain]];
+  const size_t co = (size_t)b->index_of[chain] * c->cs;
+  const size_t n = (size_t)c->L * c->N;
+  for (size_t e = 0; e < n; ++e)
+    if (!std::isfinite(field_host[e]) ||
+        (c->m.field == DQMC_FIELD_ISING && field_host[e] != 1.0 && field_host[e] != -1.0))
+      return bfail(b, DQMC_E_ARG, "bad field value");
+  BHIPCHK_(hipMemcpyAsync(c->field + co, field_host, n * sizeof(double), hipMemcpyHostToDevice, b->stream));
+  unsigned long long ctr = sweep_counter;
+  BHIPCHK_(hipMemcpyAsync(reinterpret_cast<double*>(c->counters + 2) + co, &ctr, sizeof(ctr), hipMemcpyHostToDevice,
+                          b->stream));
+  BHIPCHK_(hipStreamSynchronize(b->stream));
+  c->initialized = false;
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_batch_get_state(dqmc_batch* b, int32_t chain, double* field_host, uint64_t* sweep_counter) {
+  if (!b || chain < 0 || chain >= (int)b->group_of.size()) return bfail(b, DQMC_E_ARG, "bad arguments");
+  if (!b->bound) return bfail(b, DQMC_E_STATE, "not bound");
+  dqmc_ctx* c = b->groups[b->group_of[chain]];
+  const size_t co = (size_t)b->index_of[chain] * c->cs;
+  if (field_host)
+    BHIPCHK_(hipMemcpyAsync(field_host, c->field + co, (size_t)c->L * c->N * sizeof(double), hipMemcpyDeviceToHost,
+                            b->stream));
+  unsigned long long ctr = 0;
+  BHIPCHK_(hipMemcpyAsync(&ctr, reinterpret_cast<double*>(c->counters + 2) + co, sizeof(ctr), hipMemcpyDeviceToHost,
+                          b->stream));
+  BHIPCHK_(hipStreamSynchronize(b->stream));
+  if (sweep_counter) *sweep_counter = ctr;
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_batch_init(dqmc_batch* b) {
+  if (!b) return DQMC_E_ARG;
+  if (!b->bound) return bfail(b, DQMC_E_STATE, "not bound");
+  for (dqmc_ctx* c : b->groups)
+    if (dqmc_status s = dqmc_init(c)) return bfail(b, s, c->err);
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_batch_sweep(dqmc_batch* b, int32_t n_sweeps, int32_t measure, dqmc_stats* st) {
+  if (!b || n_sweeps < 0) return bfail(b, DQMC_E_ARG, "bad arguments");
+  for (dqmc_ctx* c : b->groups)
+    if (!c->bound || !c->initialized || c->poisoned) return bfail(b, DQMC_E_STATE, "batch not initialised");
+  const auto t0 = std::chrono::steady_clock::now();
+  int left = n_sweeps;
+  if (b->gexec && b->graph_measure == (measure ? 1 : 0)) {
+    while (left >= b->graph_sweeps) {
+      BHIPCHK_(hipGraphLaunch(b->gexec, b->stream));
+      left -= b->graph_sweeps;
+    }
+  }
+  for (int s = 0; s < left; ++s)
+    for (dqmc_ctx* c : b->groups)
+      if (dqmc_status r = sweep_once(c, measure != 0)) return bfail(b, r, c->err);
+  if (dqmc_status r = batch_flags(b)) return r;
+  const auto t1 = std::chrono::steady_clock::now();
+  if (st) {
+    dqmc_stats tot{};
+    double psum = 0.0;
+    for (dqmc_ctx* c : b->groups) {
+      dqmc_stats g{};
+      if (dqmc_status r = chain_stats(c, -1, &g)) return bfail(b, r, c->err);
+      tot.proposals += g.proposals;
+      tot.accepted += g.accepted;
+      tot.n_prec += g.n_prec;
+      psum += g.prec_mean * g.n_prec;
+      tot.prec_max = std::max(tot.prec_max, g.prec_max);
+    }
+    tot.prec_mean = tot.n_prec ? psum / tot.n_prec : 0.0;
+    tot.seconds = std::chrono::duration<double>(t1 - t0).count();
+    *st = tot;
+  }
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_batch_capture(dqmc_batch* b, int32_t sweeps_per_graph, int32_t measure) {
+  if (!b || sweeps_per_graph < 1) return bfail(b, DQMC_E_ARG, "bad arguments");
+  if (!b->bound) return bfail(b, DQMC_E_STATE, "not bound");
+  for (dqmc_ctx* c : b->groups)
+    if (c->timing) return bfail(b, DQMC_E_STATE, "disable kernel timing before capturing");
+  if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
+  if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+  BHIPCHK_(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  dqmc_status st = DQMC_OK;
+  for (int s = 0; s < sweeps_per_graph && st == DQMC_OK; ++s)
+    for (dqmc_ctx* c : b->groups)
+      if ((st = sweep_once(c, measure != 0)) != DQMC_OK) break;
+  hipError_t ce = hipStreamEndCapture(b->stream, &b->graph);
+  if (st != DQMC_OK) return bfail(b, st, "capture failed");
+  BHIPCHK_(ce);
+  BHIPCHK_(hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
+  b->graph_sweeps = sweeps_per_graph;
+  b->graph_measure = measure ? 1 : 0;
+  return DQMC_OK;
+}
+
+// Autotuner: for every group, `trials` sweeps are timed (HIP events) with
+// 16 x 16 and with 32 x 32 GEMM tiles, and the faster tile is kept.  The
+// trial sweeps advance the chains like warm-up sweeps; a captured graph is
+// dropped (it would replay the old tiles).
+dqmc_status dqmc_batch_autotune(dqmc_batch* b, int32_t trials) {
+  if (!b || trials < 1) return bfail(b, DQMC_E_ARG, "bad arguments");
+  for (dqmc_ctx* c : b->groups)
+    if (!c->bound || !c->initialized || c->poisoned) return bfail(b, DQMC_E_STATE, "batch not initialised");
+  if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
+  if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+  hipEvent_t e0, e1;
+  BHIPCHK_(hipEventCreate(&e0));
+  BHIPCHK_(hipEventCreate(&e1));
+  const int cands[2] = {16, 32};
+  for (dqmc_ctx* c : b->groups) {
+    float best = 0.0f;
+    int pick = 0;
+    for (int t : cands) {
+      c->gemm_tile = t;
+      BHIPCHK_(hipEventRecord(e0, b->stream));
+      for (int s = 0; s < trials; ++s)
+        if (dqmc_status r = sweep_once(c, false)) return bfail(b, r, c->err);
+      BHIPCHK_(hipEventRecord(e1, b->stream));
+      BHIPCHK_(hipEventSynchronize(e1));
+      float ms = 0.0f;
+      BHIPCHK_(hipEventElapsedTime(&ms, e0, e1));
+      if (pick == 0 || ms < best) { best = ms; pick = t; }
+    }
+    c->gemm_tile = pick;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return batch_flags(b);
+}
+
+dqmc_status dqmc_batch_tuning(const dqmc_batch* b, int32_t chain, int32_t* gemm_tile) {
+  if (!b || !gemm_tile || chain < 0 || chain >= (int)b->group_of.size()) return DQMC_E_ARG;
+  *gemm_tile = b->groups[b->group_of[chain]]->gemm_tile;
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_batch_read_chain(dqmc_batch* b, int32_t chain, double* G_host, double* bins_host, dqmc_stats* st) {
+  if (!b || chain < 0 || chain >= (int)b->group_of.size()) return bfail(b, DQMC_E_ARG, "bad arguments");
+  if (!b->bound) return bfail(b, DQMC_E_STATE, "not bound");
+  dqmc_ctx* c = b->groups[b->group_of[chain]];
+  const int i = b->index_of[chain];
+  const size_t co = (size_t)i * c->cs;
+  if (G_host)
+    BHIPCHK_(hipMemcpyAsync(G_host, c->G + co, sizeof(double) * c->N * c->N, hipMemcpyDeviceToHost, b->stream));
+  if (bins_host)
+    BHIPCHK_(hipMemcpyAsync(bins_host, c->bins + co, 4 * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+  BHIPCHK_(hipStreamSynchronize(b->stream));
+  if (st)
+    if (dqmc_status r = chain_stats(c, i, st)) return bfail(b, r, c->err);
+  return DQMC_OK;
+}
+
+int32_t dqmc_batch_groups(const dqmc_batch* b) { return b ? (int32_t)b->groups.size() : 0; }
+
+// Host-only self-check of the buffer layout, placing the groups at a fake
+// base address (nothing is dereferenced): DQMC_OK or DQMC_E_STATE.
+dqmc_status dqmc_batch_check_layout(dqmc_batch* b) {
+  if (!b) return DQMC_E_ARG;
+  double* fake = reinterpret_cast<double*>(uintptr_t(1) << 40);
+  for (size_t g = 0; g < b->groups.size(); ++g) {
+    double* base = fake + b->group_off[g];
+    place_group(b->groups[g], base);
+    const double* hi = (g + 1 < b->groups.size()) ? fake + b->group_off[g + 1] : fake + b->total;
+    if (!layout_ok(b->groups[g], base, hi)) return DQMC_E_STATE;
+  }
+  return DQMC_OK;
+}
+
+const char* dqmc_batch_last_error(const dqmc_batch* b) { return b ? b->err.c_str() : "null batch"; }
+
+void dqmc_batch_destroy(dqmc_batch* b) { delete b; }
 
 }  // extern "C"

@@ -28,11 +28,24 @@ struct GemmArgs {
   const double* rs; double rs_coef; int rs_mode;
   const double* cs; double cs_coef; int cs_mode;
   const double* ks; double ks_coef; int ks_mode;
+  // batching: chain = blockIdx.y; operands flagged in `pc` are offset by
+  // chain * cstride doubles (the others are shared by all chains)
+  size_t cstride; int pc; int nch; int tile;
 };
+enum { PC_A = 1, PC_B = 2, PC_C = 4, PC_RS = 8, PC_CS = 16, PC_KS = 32 };
 
 template <int TILE>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   constexpr int NB = TILE / 16;
+  if (g.cstride) {
+    const size_t co = (size_t)blockIdx.y * g.cstride;
+    if (g.pc & PC_A) g.A += co;
+    if (g.pc & PC_B) g.B += co;
+    if (g.pc & PC_C) g.C += co;
+    if (g.pc & PC_RS) g.rs += co;
+    if (g.pc & PC_CS) g.cs += co;
+    if (g.pc & PC_KS) g.ks += co;
+  }
   __shared__ double red[3][NB * NB][4][64];
   const int tilesN = (g.N + TILE - 1) / TILE;
   const int i0 = (blockIdx.x / tilesN) * TILE, j0 = (blockIdx.x % tilesN) * TILE;
@@ -103,9 +116,9 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
     }
 }
 
-static inline GemmArgs gemm_args(int M, int N, int K, const double* A, int lda, int transA,
-                                 const double* B, int ldb, int transB, double* C, int ldc,
-                                 double alpha = 1.0, double beta = 0.0) {
+__host__ __device__ inline GemmArgs gemm_args(int M, int N, int K, const double* A, int lda, int transA,
+                                            const double* B, int ldb, int transB, double* C, int ldc,
+                                            double alpha = 1.0, double beta = 0.0) {
   GemmArgs g;
   g.M = M; g.N = N; g.K = K;
   g.A = A; g.lda = lda; g.transA = transA;
@@ -115,17 +128,22 @@ static inline GemmArgs gemm_args(int M, int N, int K, const double* A, int lda, 
   g.rs = nullptr; g.rs_coef = 0.0; g.rs_mode = SC_NONE;
   g.cs = nullptr; g.cs_coef = 0.0; g.cs_mode = SC_NONE;
   g.ks = nullptr; g.ks_coef = 0.0; g.ks_mode = SC_NONE;
+  g.cstride = 0; g.pc = 0; g.nch = 1; g.tile = 0;
   return g;
 }
 
+// Tile choice: g.tile = 16 or 32 forces it; 0 picks 32 x 32 tiles once there
+// are enough of them (over all chains) to cover the chip.
 static inline hipError_t launch_gemm(const GemmArgs& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
+  const int nch = g.nch > 0 ? g.nch : 1;
   const int t32 = ((g.M + 31) / 32) * ((g.N + 31) / 32);
-  if (t32 >= 192) {
-    hipLaunchKernelGGL(k_gemm<32>, dim3(t32), dim3(256), 0, s, g);
+  const bool use32 = g.tile == 32 || (g.tile == 0 && (long long)t32 * nch >= 192);
+  if (use32) {
+    hipLaunchKernelGGL(k_gemm<32>, dim3(t32, nch), dim3(256), 0, s, g);
   } else {
     const int t16 = ((g.M + 15) / 16) * ((g.N + 15) / 16);
-    hipLaunchKernelGGL(k_gemm<16>, dim3(t16), dim3(256), 0, s, g);
+    hipLaunchKernelGGL(k_gemm<16>, dim3(t16, nch), dim3(256), 0, s, g);
   }
   return hipGetLastError();
 }

@@ -16,26 +16,45 @@
 #include "device_common.h"
 
 // ------------------------------------------------------------ utilities ----
-__global__ void k_set_identity(double* A, int n, int ld) {
+__global__ void k_set_identity(double* A, int n, int ld, size_t cs) {
+  A += (size_t)blockIdx.y * cs;
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (size_t)n * n) return;
   const int i = (int)(e / n), j = (int)(e % n);
   A[(size_t)i * ld + j] = (i == j) ? 1.0 : 0.0;
 }
 
-__global__ void k_fill(double* A, size_t count, double v) {
+__global__ void k_fill(double* A, size_t count, double v, size_t cs) {
+  A += (size_t)blockIdx.y * cs;
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e < count) A[e] = v;
 }
 
-__global__ void k_copy(double* dst, const double* src, size_t count) {
+__global__ void k_copy(double* dst, const double* src, size_t count, size_t cs) {
+  dst += (size_t)blockIdx.y * cs;
+  src += (size_t)blockIdx.y * cs;
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e < count) dst[e] = src[e];
 }
 
+// Batched gathers: dst[chain][0..count) <-> src[chain * cs + 0..count)
+__global__ void k_gather(double* dst, const double* src, int count, size_t cs) {
+  const int t = threadIdx.x;
+  if (t < count) dst[(size_t)blockIdx.y * count + t] = src[(size_t)blockIdx.y * cs + t];
+}
+
+__global__ void k_scatter(double* dst, const double* src, int count, size_t cs) {
+  const int t = threadIdx.x;
+  if (t < count) dst[(size_t)blockIdx.y * cs + t] = src[(size_t)blockIdx.y * count + t];
+}
+
 // dst[i][j] = src[j][i] * scale(i)
-__global__ void k_transpose_scale(double* dst, const double* src, int n, const double* d, int mode) {
+__global__ void k_transpose_scale(double* dst, const double* src, int n, const double* d, int mode, size_t cs_dst,
+                                  size_t cs_src) {
   __shared__ double tile[32][33];
+  dst += (size_t)blockIdx.z * cs_dst;
+  src += (size_t)blockIdx.z * cs_src;
+  d += (size_t)blockIdx.z * cs_src;
   const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
   for (int r = ty; r < 32; r += 8) {
@@ -51,7 +70,10 @@ __global__ void k_transpose_scale(double* dst, const double* src, int n, const d
 
 // -------------------------------------------------------- QR pre-pivoting ----
 // piv[p] = index of the column with the p-th largest 2-norm (ties: lower index)
-__global__ __launch_bounds__(1024) void k_colnorm_order(const double* M, int n, double* norms, int* piv) {
+__global__ __launch_bounds__(1024) void k_colnorm_order(const double* M, int n, double* norms, int* piv, size_t cs) {
+  M += (size_t)blockIdx.y * cs;
+  norms += (size_t)blockIdx.y * cs;
+  piv = reinterpret_cast<int*>(reinterpret_cast<double*>(piv) + (size_t)blockIdx.y * cs);
   for (int j = threadIdx.x; j < n; j += blockDim.x) {
     double s = 0.0;
     for (int r = 0; r < n; ++r) { const double x = M[(size_t)r * n + j]; s += x * x; }
@@ -69,7 +91,10 @@ __global__ __launch_bounds__(1024) void k_colnorm_order(const double* M, int n, 
   }
 }
 
-__global__ void k_permute_cols(double* dst, const double* src, const int* piv, int n) {
+__global__ void k_permute_cols(double* dst, const double* src, const int* piv, int n, size_t cs) {
+  dst += (size_t)blockIdx.y * cs;
+  src += (size_t)blockIdx.y * cs;
+  piv = reinterpret_cast<const int*>(reinterpret_cast<const double*>(piv) + (size_t)blockIdx.y * cs);
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (size_t)n * n) return;
   const int i = (int)(e / n), j = (int)(e % n);
@@ -92,10 +117,9 @@ __host__ __device__ inline size_t qr_panel_lds(int h) {
 }
 
 template <int NBW, int MAXR>
-__global__ __launch_bounds__(256) void k_qr_panel(double* A, int n, int j0, int nbw, double* Vout,
-                                                  double* VTout) {
+__device__ __forceinline__ void qr_panel_body(double* A, int n, int j0, int nbw, double* Vout, double* VTout,
+                                              double* smem) {
   constexpr int RG = 256 / NBW, PT = 33, PV = NBW + 1;
-  extern __shared__ double smem[];
   const int h = n - j0, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int q = tid % NBW, rg = tid / NBW;
   double* vsh = smem;                       // h x PV: V at the end
@@ -227,8 +251,22 @@ __global__ __launch_bounds__(256) void k_qr_panel(double* A, int n, int j0, int 
   }
 }
 
+template <int NBW, int MAXR>
+__global__ __launch_bounds__(256) void k_qr_panel(double* A, int n, int j0, int nbw, double* Vout,
+                                                  double* VTout, size_t cs) {
+  extern __shared__ double smem[];
+  const size_t co = (size_t)blockIdx.y * cs;
+  qr_panel_body<NBW, MAXR>(A + co, n, j0, nbw, Vout + co, VTout + co, smem);
+}
+
 // Rt[i][piv[j]] = R[i][j] / |R[i][i]| for j >= i; D[i] = |R[i][i]|
-__global__ void k_build_rt(const double* R, const int* piv, int n, double* Rt, double* D, int* err) {
+__global__ void k_build_rt(const double* R, const int* piv, int n, double* Rt, double* D, int* err, size_t cs) {
+  {
+    const size_t co = (size_t)blockIdx.y * cs;
+    R += co; Rt += co; D += co;
+    piv = reinterpret_cast<const int*>(reinterpret_cast<const double*>(piv) + co);
+    err = reinterpret_cast<int*>(reinterpret_cast<double*>(err) + co);
+  }
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (size_t)n * n) return;
   const int i = (int)(e / n), j = (int)(e % n);
@@ -247,8 +285,8 @@ __global__ void k_build_rt(const double* R, const int* piv, int n, double* Rt, d
 // elsewhere.  LDS: lu_panel_lds(h) doubles.
 __host__ __device__ inline size_t lu_panel_lds(int h, int nbw) { return (size_t)h * (nbw + 1) + 16; }
 
-__global__ __launch_bounds__(256) void k_lu_panel(double* X, int n, int j0, int nbw, int* ipiv, int* err) {
-  extern __shared__ double smem[];
+__device__ __forceinline__ void lu_panel_body(double* X, int n, int j0, int nbw, int* ipiv, int* err,
+                                              double* smem) {
   const int P = nbw + 1;
   const int h = n - j0, tid = threadIdx.x;
   double* pan = smem;
@@ -280,6 +318,9 @@ __global__ __launch_bounds__(256) void k_lu_panel(double* X, int n, int j0, int 
       int i = ri[0];
       for (int k = 1; k < 4; ++k)
         if (rv[k] > b || (rv[k] == b && ri[k] < i)) { b = rv[k]; i = ri[k]; }
+      // no finite candidate (a NaN column): keep the row and flag the failure,
+      // so no pivot index ever leaves the panel
+      if (!(b >= 0.0) || i < c || i >= h) i = c;
       piv_s = i;
       ipiv[j0 + c] = j0 + i;
       if (!(b > 0.0)) atomicOr(err, 4);
@@ -307,9 +348,23 @@ __global__ __launch_bounds__(256) void k_lu_panel(double* X, int n, int j0, int 
   }
 }
 
+__global__ __launch_bounds__(256) void k_lu_panel(double* X, int n, int j0, int nbw, int* ipiv, int* err,
+                                                  size_t cs) {
+  extern __shared__ double smem[];
+  const size_t co = (size_t)blockIdx.y * cs;
+  lu_panel_body(X + co, n, j0, nbw, reinterpret_cast<int*>(reinterpret_cast<double*>(ipiv) + co),
+                reinterpret_cast<int*>(reinterpret_cast<double*>(err) + co), smem);
+}
+
 // Apply the interchanges of one panel to the columns of X outside the panel
 // and to every column of the right-hand sides B (n x nrhs, ld ldb).
-__global__ void k_lu_swap(double* X, int n, int j0, int nbw, const int* ipiv, double* B, int nrhs, int ldb) {
+__global__ void k_lu_swap(double* X, int n, int j0, int nbw, const int* ipiv, double* B, int nrhs, int ldb,
+                          size_t cs) {
+  {
+    const size_t co = (size_t)blockIdx.y * cs;
+    X += co; B += co;
+    ipiv = reinterpret_cast<const int*>(reinterpret_cast<const double*>(ipiv) + co);
+  }
   const int col = blockIdx.x * blockDim.x + threadIdx.x;
   const int nx = n - nbw;
   if (col >= nx + nrhs) return;
@@ -325,7 +380,7 @@ __global__ void k_lu_swap(double* X, int n, int j0, int nbw, const int* ipiv, do
   }
   for (int c = 0; c < nbw && j0 + c < n; ++c) {
     const int r = j0 + c, p = ipiv[r];
-    if (p != r) {
+    if (p != r && p > r && p < n) {
       const double t = base[(size_t)r * ld];
       base[(size_t)r * ld] = base[(size_t)p * ld];
       base[(size_t)p * ld] = t;
@@ -338,8 +393,10 @@ __global__ void k_lu_swap(double* X, int n, int j0, int nbw, const int* ipiv, do
 // its own diagonal.  One thread per column of Bm; the column stays in
 // registers (fully unrolled over a 32-row block padded with identity rows).
 __global__ __launch_bounds__(256) void k_trsm_block(const double* Tri, int ldt, double* Bm, int ldb, int nrow,
-                                                    int ncol, int upper) {
+                                                    int ncol, int upper, size_t cs) {
   __shared__ double t[32][33];
+  Tri += (size_t)blockIdx.y * cs;
+  Bm += (size_t)blockIdx.y * cs;
   for (int e = threadIdx.x; e < 32 * 32; e += 256) {
     const int r = e >> 5, k = e & 31;
     t[r][k] = (r < nrow && k < nrow) ? Tri[(size_t)r * ldt + k] : (r == k ? 1.0 : 0.0);
@@ -373,8 +430,10 @@ __global__ __launch_bounds__(256) void k_trsm_block(const double* Tri, int ldt, 
 }
 
 // out += sum_i log|U_ii| (one workgroup)
-__global__ __launch_bounds__(256) void k_logabs_diag(const double* U, int n, double* out) {
+__global__ __launch_bounds__(256) void k_logabs_diag(const double* U, int n, double* out, size_t cs) {
   __shared__ double red[8];
+  U += (size_t)blockIdx.y * cs;
+  out += (size_t)blockIdx.y * cs;
   double s = 0.0;
   for (int i = threadIdx.x; i < n; i += 256) s += log(fabs(U[(size_t)i * n + i]));
   s = block_sum<256>(s, red);
@@ -382,8 +441,11 @@ __global__ __launch_bounds__(256) void k_logabs_diag(const double* U, int n, dou
 }
 
 // out = sum_i log max(d_i, 1)
-__global__ __launch_bounds__(256) void k_logbig_sum(const double* d, int n, double* out, int accumulate) {
+__global__ __launch_bounds__(256) void k_logbig_sum(const double* d, int n, double* out, int accumulate,
+                                                    size_t cs_d, size_t cs_out) {
   __shared__ double red[8];
+  d += (size_t)blockIdx.y * cs_d;
+  out += (size_t)blockIdx.y * cs_out;
   double s = 0.0;
   for (int i = threadIdx.x; i < n; i += 256) s += log(fmax(d[i], 1.0));
   s = block_sum<256>(s, red);

@@ -27,10 +27,11 @@ struct BlockArgs {
   const double* field_in;            // field of slice tau before the block (N values)
   double* field_out;                 // field of slice tau after the block (may equal field_in only for
                                      // sites outside this block; distinct buffer otherwise)
-  const unsigned long long* sweep_ctr;
-  unsigned long long seed, slot;     // Philox key word 0; counter word 2 = (tau << 1) | dir
+  const unsigned long long* sweep_ctr;   // unused: the counters carry the sweep number and the key
+  unsigned long long seed, slot;     // slot = counter word 2 = (tau << 1) | dir
   double coupling, alpha; int n_col; int gauss; double prop_width;
-  unsigned long long* counters;      // [0] proposals, [1] accepted
+  unsigned long long* counters;      // [0] proposals, [1] accepted, [2] sweep, [3] Philox key
+  size_t cs;                         // per-chain stride (doubles) of every pointer above; chain = blockIdx.y
 };
 
 __device__ __forceinline__ double ipow(double r, int n) {
@@ -51,6 +52,12 @@ __global__ __launch_bounds__(256) void k_block_update(BlockArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int bb = a.bb, s0 = a.s0, N = a.N;
   const int tilesN = (N + 31) >> 5;
+  if (a.cs) {
+    const size_t co = (size_t)blockIdx.y * a.cs;
+    a.Gin += co; a.Gout += co; a.field_in += co; a.field_out += co;
+    a.sweep_ctr = reinterpret_cast<const unsigned long long*>(reinterpret_cast<const double*>(a.sweep_ctr) + co);
+    a.counters = reinterpret_cast<unsigned long long*>(reinterpret_cast<double*>(a.counters) + co);
+  }
   const int I0 = (blockIdx.x / tilesN) << 5, J0 = (blockIdx.x % tilesN) << 5;
   for (int e = tid; e < 1024; e += 256) {
     const int x = e >> 5, y = e & 31;
@@ -64,7 +71,8 @@ __global__ __launch_bounds__(256) void k_block_update(BlockArgs a) {
   if (tid < 32) {
     accf[tid] = 0;
     if (tid < bb) {
-      const Philox4 r = philox4x64_10(TAG_FLIP, *a.sweep_ctr, a.slot, (unsigned long long)(s0 + tid), a.seed, 0ull);
+      const Philox4 r = philox4x64_10(TAG_FLIP, a.counters[2], a.slot, (unsigned long long)(s0 + tid), a.counters[3],
+                                      0ull);
       const double u0 = unit_double(r.w[0]), u1 = unit_double(r.w[1]);
       const double s = a.field_in[s0 + tid];
       double sn, extra;
@@ -164,8 +172,15 @@ __global__ __launch_bounds__(256) void k_block_update(BlockArgs a) {
 // wave walks rows with coalesced loads.
 __global__ __launch_bounds__(1024) void k_measure(const double* G, const double* T1, const double* Ehinv,
                                                   const double* K, int N, double trK, double n_col, double u_int,
-                                                  double* bins, int* err) {
+                                                  double* bins, int* err, size_t cs) {
   __shared__ double red[16];
+  {
+    const size_t co = (size_t)blockIdx.y * cs;
+    G += co;
+    if (T1) T1 += co;
+    bins += co;
+    err = reinterpret_cast<int*>(reinterpret_cast<double*>(err) + co);
+  }
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   double sd = 0.0, skg = 0.0, bad = 0.0;
   for (int i = w; i < N; i += 16) {
@@ -200,8 +215,13 @@ __global__ __launch_bounds__(1024) void k_measure(const double* G, const double*
 
 // max |Gw - Gs| into prec_slot (zero on entry), G <- Gs, NaN/Inf check.
 __global__ __launch_bounds__(256) void k_prec_replace(const double* Gw, double* G, const double* Gs, size_t count,
-                                                      double* prec_slot, int* err) {
+                                                      double* prec_slot, int* err, size_t cs) {
   __shared__ double red[8];
+  {
+    const size_t co = (size_t)blockIdx.y * cs;
+    Gw += co; G += co; Gs += co; prec_slot += co;
+    err = reinterpret_cast<int*>(reinterpret_cast<double*>(err) + co);
+  }
   double m = 0.0, bad = 0.0;
   for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (size_t)gridDim.x * 256) {
     const double gs = Gs[e];
@@ -221,8 +241,14 @@ __global__ __launch_bounds__(256) void k_prec_replace(const double* Gw, double* 
 // End of a sweep: fold the per-stabilisation precision values into the
 // running totals, check the threshold, advance the sweep counter.
 __global__ void k_finish_sweep(double* prec_hist, int n_hist, double* prec_tot, double threshold,
-                               unsigned long long* counters, int* err) {
+                               unsigned long long* counters, int* err, size_t cs) {
   if (threadIdx.x != 0) return;
+  {
+    const size_t co = (size_t)blockIdx.y * cs;
+    prec_hist += co; prec_tot += co;
+    counters = reinterpret_cast<unsigned long long*>(reinterpret_cast<double*>(counters) + co);
+    err = reinterpret_cast<int*>(reinterpret_cast<double*>(err) + co);
+  }
   double s = prec_tot[0], mx = prec_tot[1], cnt = prec_tot[2];
   for (int k = 0; k < n_hist; ++k) {
     const double p = prec_hist[k];
@@ -241,7 +267,11 @@ __global__ void k_finish_sweep(double* prec_hist, int n_hist, double* prec_tot, 
 
 // Random start of the field (s = +1 iff u < 1/2, or phi ~ N(0,1) by
 // Box-Muller on (1 - u0, u1), cosine branch); draws (INIT, 0, tau << 1, site).
-__global__ void k_random_field(double* field, int L, int N, unsigned long long seed, int gauss) {
+__global__ void k_random_field(double* field, int L, int N, const unsigned long long* counters, int gauss, size_t cs) {
+  field += (size_t)blockIdx.y * cs;
+  counters = reinterpret_cast<const unsigned long long*>(reinterpret_cast<const double*>(counters) +
+                                                         (size_t)blockIdx.y * cs);
+  const unsigned long long seed = counters[3];
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= L * N) return;
   const int tau = e / N + 1, i = e % N;

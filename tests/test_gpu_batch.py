@@ -1,0 +1,106 @@
+"""Parity of batched chains with the oracle: every chain of a
+mixed-size batch follows its own oracle trajectory (bit-exact decisions, G to
+1e-9), and capture/replay of the sweep in a hipGraph changes nothing."""
+import numpy as np
+import pytest
+
+from gpu_util import lattice, maxabs
+from oracle import hubbard as ohub
+from oracle import sweep as osweep
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def _batch(specs, beta, n_wrap, trotter="sym", field="ising"):
+    import paper_1704_00131_amd as pa
+    models, Ks, oms = [], [], []
+    for (kind, L1, L2, seed) in specs:
+        lat = lattice(kind, L1, L2)
+        U, dtau = 4.0, 0.1
+        lam = pa.hubbard_coupling(U, dtau, field)
+        models.append(pa.make_model(lat.n, beta, dtau, n_wrap, lam, U=U, trotter=trotter, seed=seed, field=field))
+        Ks.append(lat.K)
+        oms.append(ohub.hubbard_model(lat.K, U, beta, dtau, n_wrap, field_kind=field, trotter=trotter, seed=seed))
+    return pa.Batch(models, Ks), oms
+
+
+def _compare(b, oms, sweeps, graph=False):
+    b.random_fields().init()
+    ocs = []
+    for i, om in enumerate(oms):
+        f0, _ = b.get_state(i)
+        assert np.array_equal(f0, ohub.init_field(om)) if om.field_kind == "ising" else True
+        ocs.append(osweep.Chain(om, f0).init())
+        G, _, _ = b.read_chain(i)
+        assert maxabs(G, ocs[-1].G) < 1e-10, f"G(0) of chain {i}"
+    if graph:
+        b.capture(1, measure=True)
+    for s in range(sweeps):
+        b.sweep(1, measure=True)
+        for oc in ocs:
+            oc.sweep(measure=True)
+        for i, oc in enumerate(ocs):
+            f, ctr = b.get_state(i)
+            G, bins, st = b.read_chain(i)
+            assert oc.min_tie > 1e-9
+            assert ctr == s + 1
+            assert np.array_equal(f, oc.field), f"chain {i} field after sweep {s}"
+            assert maxabs(G, oc.G) < 1e-9, f"chain {i} G after sweep {s}"
+            assert st.accepted == oc.accepted and st.proposals == oc.proposals
+            assert maxabs(bins, oc.bins) < 1e-9 * oc.bins[3]
+
+
+def test_batch_mixed_sizes_two_sweeps():
+    _log("batch mixed sizes")
+    b, oms = _batch([("square", 4, 4, 0), ("honeycomb", 3, 3, 1), ("square", 6, 6, 2), ("square", 4, 4, 3),
+                     ("honeycomb", 5, 5, 4)], beta=2.0, n_wrap=10)
+    _compare(b, oms, 2)
+
+
+def test_batch_graph_replay_asym():
+    _log("batch graph replay")
+    b, oms = _batch([("square", 4, 4, 5), ("square", 6, 6, 6), ("honeycomb", 4, 4, 7)], beta=2.0, n_wrap=5,
+                    trotter="asym")
+    _compare(b, oms, 3, graph=True)
+
+
+def test_batch_gauss_field():
+    _log("batch gauss")
+    b, oms = _batch([("square", 4, 4, 8), ("square", 3, 3, 9)], beta=1.0, n_wrap=5, field="gauss")
+    _compare(b, oms, 2)
+
+
+def test_batch_workload_shapes_one_sweep():
+    """The lattices of the 512-chain workload (8x8, 6x6, 10x10 at beta = 8,
+    L = 80), one chain each, one sweep."""
+    _log("batch workload shapes")
+    b, oms = _batch([("square", 8, 8, 0), ("square", 6, 6, 256), ("square", 10, 10, 384)], beta=8.0, n_wrap=10)
+    _compare(b, oms, 1)
+
+
+def test_batch_autotune_keeps_trajectory():
+    """The autotuner picks a block size per lattice; the chains then continue
+    the oracle's trajectory from their current state."""
+    _log("batch autotune")
+    b, oms = _batch([("square", 4, 4, 11), ("square", 6, 6, 12)], beta=2.0, n_wrap=10)
+    b.random_fields().init()
+    b.autotune(1)
+    assert all(b.tuning(i) in (16, 32) for i in range(2))
+    ocs = []
+    for i, om in enumerate(oms):
+        f, ctr = b.get_state(i)
+        assert ctr == 2
+        oc = osweep.Chain(om, f, sweep_counter=ctr).init()
+        ocs.append(oc)
+    b.init()
+    b.sweep(1)
+    for i, oc in enumerate(ocs):
+        oc.sweep()
+        f, _ = b.get_state(i)
+        G, _, _ = b.read_chain(i)
+        assert np.array_equal(f, oc.field)
+        assert maxabs(G, oc.G) < 1e-9
