@@ -25,7 +25,8 @@ class Batch:
         check(lib.dqmc_batch_query_size(b, ctypes.byref(size)))
         self.device = torch.device(device)
         self.work = torch.empty(max(1, (size.value + 7) // 8), dtype=torch.float64, device=self.device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # a stream of its own (default priority): the legacy default stream cannot be captured into a graph
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
         self._chk(lib.dqmc_batch_bind(b, ctypes.c_void_p(self.work.data_ptr()),
                                       ctypes.c_void_p(self.stream.cuda_stream)))
 

@@ -1204,6 +1204,7 @@ dqmc_status dqmc_batch_sweep(dqmc_batch* b, int32_t n_sweeps, int32_t measure, d
 dqmc_status dqmc_batch_capture(dqmc_batch* b, int32_t sweeps_per_graph, int32_t measure) {
   if (!b || sweeps_per_graph < 1) return bfail(b, DQMC_E_ARG, "bad arguments");
   if (!b->bound) return bfail(b, DQMC_E_STATE, "not bound");
+  if (!b->stream) return bfail(b, DQMC_E_ARG, "graph capture needs a stream other than the null stream");
   for (dqmc_ctx* c : b->groups)
     if (c->timing) return bfail(b, DQMC_E_STATE, "disable kernel timing before capturing");
   if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
