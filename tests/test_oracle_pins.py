@@ -285,3 +285,42 @@ def test_oracle_golden_trajectory():
     assert np.array_equal(ch.field.astype(int), np.array(g["field"]))
     assert np.max(np.abs(ch.G - np.array(g["G0"]))) < 1e-12
     assert np.max(np.abs(ch.bins - np.array(g["bins"]))) < 1e-10
+
+
+# ------------------------------------------------------------- gradient --
+def test_gradient_matches_finite_differences():
+    """d log det / d phi = c (1 - G(tau)_ii) against central differences
+    (h = 1e-5) of the stabilised log det on a 3x3 square with a Gaussian field."""
+    from oracle import gradient
+    lat = square_lattice(3, 3)
+    m = hubbard.hubbard_model(lat.K, 4.0, 2.0, 0.1, 5, field_kind="gauss", seed=3)
+    f = hubbard.init_field(m)
+    g = gradient.grad_logdet(m, f)
+    rng = np.random.default_rng(0)
+    for _ in range(8):
+        tau = int(rng.integers(1, m.L + 1))
+        i = int(rng.integers(0, m.N))
+        fd = gradient.fd_logdet(m, f, tau, i)
+        assert abs(fd - g[tau - 1, i]) < 1e-7 * max(1.0, abs(g[tau - 1, i]))
+
+
+def test_gradient_atomic_closed_form():
+    """t = 0, one site: det(1 + B) = 1 + exp(c sum_tau phi_tau), so the
+    gradient is c e^x / (1 + e^x) for every slice (x = c sum phi)."""
+    from oracle import gradient
+    m = hubbard.hubbard_model(np.zeros((1, 1)), 4.0, 1.0, 0.1, 5, field_kind="gauss", seed=1)
+    f = hubbard.init_field(m)
+    x = m.coupling * f.sum()
+    g = gradient.grad_logdet(m, f)
+    assert np.max(np.abs(g - m.coupling * np.exp(x) / (1 + np.exp(x)))) < 1e-13
+
+
+def test_langevin_step_is_the_stated_update():
+    from oracle import gradient, philox
+    lat = square_lattice(2, 2)
+    m = hubbard.hubbard_model(lat.K, 4.0, 1.0, 0.1, 5, field_kind="gauss", seed=5)
+    f = hubbard.init_field(m)
+    new = gradient.langevin_step(m, f, 1e-3, 7)
+    xi = philox.normals(5, philox.TAG_LANGEVIN, 7, 3, 0, m.N)
+    dlw = gradient.grad_log_weight(m, f)
+    assert np.max(np.abs(new[2] - (f[2] + 1e-3 * dlw[2] + np.sqrt(2e-3) * xi))) < 1e-15
