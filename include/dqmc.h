@@ -138,6 +138,28 @@ dqmc_status dqmc_green_scratch(dqmc_ctx* ctx, int32_t tau, double* G_dev);
 /* log|det(1 + B(beta,0))| of the current field from scratch. */
 dqmc_status dqmc_logdet(dqmc_ctx* ctx, double* logdet);
 
+/* Gradient of log|det(1 + B(beta,0))| (one colour) with respect to the field,
+ * read as a continuous variable:
+ *   grad[tau-1][i] = d log det / d phi_{i,tau} = coupling (1 - G(tau)_ii),
+ * which follows from Eq. (Green_eq) with B_tau of Eq. (partition_2) and the
+ * cyclic trace (the paper's code has no continuous fields: a reading).  G(tau)
+ * comes from an upward pass without updates that wraps G(0) slice by slice and
+ * recomputes it every n_wrap slices from the stored left forms (the
+ * checkpoints) and a running right form; no product of all L slices is kept.
+ * grad_dev: device buffer of L*n doubles, row-major [L][n], owned by the
+ * caller.  prec (host, may be NULL): max |wrapped - recomputed| over the
+ * pass.  Needs an initialised chain (after dqmc_init or a sweep); the chain's
+ * G, field and stored forms are unchanged. */
+dqmc_status dqmc_grad_logdet(dqmc_ctx* ctx, double* grad_dev, double* prec);
+
+/* n_steps unadjusted Langevin steps of a Gaussian field, step k using
+ * Philox counter (tag 3, first_step + k, tau << 1, site):
+ *   phi <- phi + eps (-phi + n_col coupling alpha + n_col grad) + sqrt(2 eps) xi,
+ * xi standard normal (Box-Muller, cosine branch), grad as in dqmc_grad_logdet.
+ * After each step the stored forms and G(0) are rebuilt from the new field.
+ * DQMC_E_UNSUPPORTED for an Ising field; eps must be positive and finite. */
+dqmc_status dqmc_langevin(dqmc_ctx* ctx, double eps, int32_t n_steps, uint64_t first_step);
+
 /* Per-launch timing of one kernel of the sweep, for roofline reports: while
  * enabled, every launch of the selected kernel on the context's stream is
  * bracketed by two HIP events.  dqmc_timing_read synchronises the stream,
@@ -189,6 +211,12 @@ dqmc_status dqmc_batch_sweep(dqmc_batch* b, int32_t n_sweeps, int32_t measure, d
 /* G (n*n host doubles), bin sums (4 host doubles) and statistics of one chain. */
 dqmc_status dqmc_batch_read_chain(dqmc_batch* b, int32_t chain, double* G_host, double* bins_host,
                                   dqmc_stats* stats);
+/* Gradient pass (as dqmc_grad_logdet) of every chain, kept on the device. */
+dqmc_status dqmc_batch_grad_logdet(dqmc_batch* b);
+/* The last gradient of one chain: L*n host doubles [L][n]; prec may be NULL. */
+dqmc_status dqmc_batch_read_grad(dqmc_batch* b, int32_t chain, double* grad_host, double* prec);
+/* n_steps Langevin steps (as dqmc_langevin) of every chain; Gaussian fields only. */
+dqmc_status dqmc_batch_langevin(dqmc_batch* b, double eps, int32_t n_steps, uint64_t first_step);
 int32_t dqmc_batch_groups(const dqmc_batch* b);
 /* Host-only self-check of the batch buffer layout (no device access). */
 dqmc_status dqmc_batch_check_layout(dqmc_batch* b);

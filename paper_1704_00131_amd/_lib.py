@@ -54,6 +54,8 @@ SIGNATURES = {
     "dqmc_reset_bins": (ctypes.c_int, [ctypes.c_void_p]),
     "dqmc_green_scratch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "dqmc_logdet": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+    "dqmc_grad_logdet": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+    "dqmc_langevin": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int32, ctypes.c_uint64]),
     "dqmc_timing_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int32]),
     "dqmc_timing_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_double)]),
@@ -73,6 +75,10 @@ SIGNATURES = {
     "dqmc_batch_sweep": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Stats)]),
     "dqmc_batch_read_chain": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.POINTER(Stats)]),
+    "dqmc_batch_grad_logdet": (ctypes.c_int, [ctypes.c_void_p]),
+    "dqmc_batch_read_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                            ctypes.POINTER(ctypes.c_double)]),
+    "dqmc_batch_langevin": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int32, ctypes.c_uint64]),
     "dqmc_batch_groups": (ctypes.c_int32, [ctypes.c_void_p]),
     "dqmc_batch_check_layout": (ctypes.c_int, [ctypes.c_void_p]),
     "dqmc_batch_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),

@@ -81,6 +81,22 @@ class Batch:
         self._chk(self.lib.dqmc_batch_read_chain(self.b, chain, G.ctypes.data, bins.ctypes.data, ctypes.byref(st)))
         return G, bins, st
 
+    def grad_logdet(self):
+        """Gradient pass of every chain (kept on the device; see read_grad)."""
+        self._chk(self.lib.dqmc_batch_grad_logdet(self.b))
+        return self
+
+    def read_grad(self, chain):
+        m = self.models[chain]
+        g = np.empty((m.n_slices, m.n))
+        prec = ctypes.c_double()
+        self._chk(self.lib.dqmc_batch_read_grad(self.b, chain, g.ctypes.data, ctypes.byref(prec)))
+        return g, prec.value
+
+    def langevin(self, eps, n_steps=1, first_step=0):
+        self._chk(self.lib.dqmc_batch_langevin(self.b, eps, n_steps, first_step))
+        return self
+
     def close(self):
         if getattr(self, "b", None):
             self.lib.dqmc_batch_destroy(self.b)

@@ -100,6 +100,25 @@ class Chain:
         self._chk(self.lib.dqmc_logdet(self.ctx, ctypes.byref(out)))
         return out.value
 
+    def load_field(self, phi: torch.Tensor):
+        """Device-to-device copy of a [L, N] float64 field into the bound field
+        buffer (call init() afterwards)."""
+        with torch.cuda.stream(self.stream):
+            self.field.view(-1)[: self.L * self.N].copy_(phi.detach().reshape(-1).to(torch.float64))
+        return self
+
+    def grad_logdet(self):
+        """d log det(1 + B(beta,0)) / d phi as a [L, N] device tensor, and the
+        gradient pass's max |wrapped - recomputed| G."""
+        out = torch.empty(self.L, self.N, dtype=torch.float64, device=self.device)
+        prec = ctypes.c_double()
+        self._chk(self.lib.dqmc_grad_logdet(self.ctx, ctypes.c_void_p(out.data_ptr()), ctypes.byref(prec)))
+        return out, prec.value
+
+    def langevin(self, eps: float, n_steps: int = 1, first_step: int = 0):
+        self._chk(self.lib.dqmc_langevin(self.ctx, eps, n_steps, first_step))
+        return self
+
     def timing(self, kernel: str = "block_update", enable: bool = True):
         k = _lib.KERNEL_BLOCK_UPDATE if kernel == "block_update" else _lib.KERNEL_GEMM
         self._chk(self.lib.dqmc_timing_enable(self.ctx, k, 1 if enable else 0))

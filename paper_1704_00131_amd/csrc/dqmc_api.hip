@@ -17,6 +17,7 @@
 #include "gemm.h"
 #include "linalg.h"
 #include "update.h"
+#include "adjoint.h"
 
 namespace {
 
@@ -58,6 +59,7 @@ struct dqmc_ctx {
   double *norms = nullptr;
   int *piv = nullptr, *ipiv = nullptr;
   double *bins = nullptr, *prec_hist = nullptr, *prec_tot = nullptr, *logdet = nullptr;
+  double *grad = nullptr, *gprec = nullptr;   // gradient rows [L][N] and the gradient pass's precision
   unsigned long long* counters = nullptr;   // proposals, accepted, sweep counter
   int* err_flag = nullptr;
   size_t work_doubles = 0;
@@ -136,6 +138,8 @@ size_t layout_chain(dqmc_ctx* c, double* base) {
   P(c->prec_hist, 2 * (size_t)c->nk + 2);
   P(c->prec_tot, 4);
   P(c->logdet, 4);
+  P(c->grad, (size_t)c->L * N);
+  P(c->gprec, 4);
   double* ctr = nullptr;
   double* ef = nullptr;
   P(ctr, 4); P(ef, 1);
@@ -235,12 +239,13 @@ inline double* field_row(dqmc_ctx* c, int tau) {
   return base + (size_t)(tau - 1) * c->N;
 }
 
-// G(tau) = B_tau G(tau-1) B_tau^-1 = diag(v) E G Einv diag(1/v), v = exp(coupling s_tau)
-dqmc_status wrap_up(dqmc_ctx* c, int tau) {
+// G(tau) = B_tau G(tau-1) B_tau^-1 = diag(v) E G Einv diag(1/v), v = exp(coupling s_tau),
+// from Gcur into dst (which may be Gcur itself)
+dqmc_status wrap_up(dqmc_ctx* c, int tau, double* dst) {
   const int N = c->N;
   if (dqmc_status s = gemm(c, gemm_args(N, N, N, c->E, N, 0, c->Gcur, N, 0, c->T1, N))) return s;
-  GemmArgs g = gemm_args(N, N, N, c->T1, N, 0, c->Einv, N, 0, c->G, N);
-  c->Gcur = c->G;
+  GemmArgs g = gemm_args(N, N, N, c->T1, N, 0, c->Einv, N, 0, dst, N);
+  c->Gcur = dst;
   g.rs = field_row(c, tau); g.rs_mode = SC_EXP; g.rs_coef = c->m.coupling;
   g.cs = field_row(c, tau); g.cs_mode = SC_EXP; g.cs_coef = -c->m.coupling;
   return gemm(c, g);
@@ -540,7 +545,7 @@ dqmc_status sweep_once(dqmc_ctx* c, bool meas) {
   c->row_alt.assign(L, 0);
   c->Gcur = c->G;
   for (int tau = 1; tau <= L; ++tau) {
-    if (dqmc_status s = wrap_up(c, tau)) return s;
+    if (dqmc_status s = wrap_up(c, tau, c->G)) return s;
     if (dqmc_status s = update_slice(c, tau, 0)) return s;
     if (tau % nw == 0) {
       const int k = tau / nw;
@@ -596,6 +601,65 @@ dqmc_status check_model(const dqmc_model* m) {
   if (m->trotter != DQMC_TROTTER_ASYM && m->trotter != DQMC_TROTTER_SYM) return DQMC_E_ARG;
   if (!std::isfinite(m->coupling) || !std::isfinite(m->alpha)) return DQMC_E_ARG;
   return DQMC_OK;
+}
+
+// Left storage and G(0) from the current field: slot k = UDV of
+// B(beta, k n_wrap)^T for k = nk-1 .. 0, then G = (1 + B(beta,0))^-1.
+dqmc_status reanchor(dqmc_ctx* c) {
+  for (int k = c->nk - 1; k >= 0; --k) {
+    UDVp prev = (k + 1 == c->nk) ? c->uid : c->slot(k + 1);
+    if (dqmc_status s = left_step(c, prev, k * c->nw, (k + 1) * c->nw, c->slot(k))) return s;
+  }
+  return merge(c, c->uid, c->slot(0), c->G, nullptr);
+}
+
+// Gradient pass: the upward pass of Algorithm 1 without updates.  G(tau) for
+// tau = 1..L is wrapped from G(0) in the second G buffer and, every n_wrap
+// slices, recomputed from a running right form and the stored left forms
+// (the checkpoints), so no product of L slices is ever stored; row tau of
+// the gradient is coupling (1 - G(tau)_ii).  G, the field and the stored
+// left forms are left as they were; gprec holds max |wrapped - recomputed|.
+dqmc_status grad_pass(dqmc_ctx* c) {
+  const int N = c->N, L = c->L, nw = c->nw, nk = c->nk;
+  const size_t NN = (size_t)N * N;
+  c->row_alt.clear();
+  if (dqmc_status s = fill_small(c, c->gprec, 1, 0.0)) return s;
+  hipLaunchKernelGGL(k_copy, gridc(c, grid1(NN)), dim3(256), 0, c->stream, c->G2, c->G, NN, c->cs);
+  HIPCHK(hipGetLastError());
+  c->Gcur = c->G2;
+  UDVp right = c->uid;
+  UDVp bufs[2] = {c->hA, c->hB};
+  int b = 0;
+  for (int tau = 1; tau <= L; ++tau) {
+    if (dqmc_status s = wrap_up(c, tau, c->G2)) return s;
+    if (tau % nw == 0) {
+      const int k = tau / nw;
+      if (dqmc_status s = right_step(c, right, tau - nw, tau, bufs[b])) return s;
+      right = bufs[b];
+      b ^= 1;
+      UDVp left = (k == nk) ? c->uid : c->slot(k);
+      if (dqmc_status s = merge(c, right, left, c->Gs, nullptr)) return s;
+      hipLaunchKernelGGL(k_prec_replace, gridc(c, (unsigned)std::min<size_t>(grid1(NN), 1024)), dim3(256), 0,
+                         c->stream, c->G2, c->G2, c->Gs, NN, c->gprec, c->err_flag, c->cs);
+      HIPCHK(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_grad_diag, gridc(c, grid1(N)), dim3(256), 0, c->stream, c->G2, N, c->m.coupling,
+                       c->grad + (size_t)(tau - 1) * N, c->cs);
+    HIPCHK(hipGetLastError());
+  }
+  c->Gcur = c->G;
+  return DQMC_OK;
+}
+
+// One Langevin step of every chain: gradient pass, field update, then the
+// left storage and G(0) of the new field.
+dqmc_status langevin_once(dqmc_ctx* c, double eps, uint64_t step) {
+  if (dqmc_status s = grad_pass(c)) return s;
+  const size_t n = (size_t)c->L * c->N;
+  hipLaunchKernelGGL(k_langevin, gridc(c, grid1(n)), dim3(256), 0, c->stream, c->field, c->grad, c->L, c->N, eps,
+                     c->m.coupling, c->m.alpha, (double)c->m.n_col, (unsigned long long)step, c->counters, c->cs);
+  HIPCHK(hipGetLastError());
+  return reanchor(c);
 }
 
 // Copy `bytes` (<= 64) of a per-chain item from every chain into host dst
@@ -810,12 +874,7 @@ dqmc_status dqmc_init(dqmc_ctx* c) {
   if (dqmc_status s = fill_small(c, c->prec_tot, 4, 0.0)) return s;
   if (dqmc_status s = fill_small(c, reinterpret_cast<double*>(c->counters), 2, 0.0)) return s;
   if (dqmc_status s = fill_small(c, reinterpret_cast<double*>(c->err_flag), 1, 0.0)) return s;
-  // left storage: slot k = UDV of B(beta, tau_k)^T, k = nk-1 .. 0
-  for (int k = c->nk - 1; k >= 0; --k) {
-    UDVp prev = (k + 1 == c->nk) ? c->uid : c->slot(k + 1);
-    if (dqmc_status s = left_step(c, prev, k * c->nw, (k + 1) * c->nw, c->slot(k))) return s;
-  }
-  if (dqmc_status s = merge(c, c->uid, c->slot(0), c->G, nullptr)) return s;
+  if (dqmc_status s = reanchor(c)) return s;
   if (dqmc_status s = read_flag(c)) return s;
   c->poisoned = false;
   c->initialized = true;
@@ -898,6 +957,26 @@ dqmc_status dqmc_logdet(dqmc_ctx* c, double* logdet) {
   if (dqmc_status s = merge(c, c->uid, left, c->Gs, c->logdet)) return s;
   HIPCHK(hipMemcpyAsync(logdet, c->logdet, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
+  return read_flag(c);
+}
+
+dqmc_status dqmc_grad_logdet(dqmc_ctx* c, double* grad_dev, double* prec) {
+  if (!c || !grad_dev) return fail(c, DQMC_E_ARG, "null argument");
+  if (!c->bound || !c->initialized || c->poisoned) return fail(c, DQMC_E_STATE, "context not initialised");
+  if (dqmc_status s = grad_pass(c)) return s;
+  HIPCHK(hipMemcpyAsync(grad_dev, c->grad, (size_t)c->L * c->N * sizeof(double), hipMemcpyDeviceToDevice,
+                        c->stream));
+  if (prec) HIPCHK(hipMemcpyAsync(prec, c->gprec, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return read_flag(c);
+}
+
+dqmc_status dqmc_langevin(dqmc_ctx* c, double eps, int32_t n_steps, uint64_t first_step) {
+  if (!c || n_steps < 0 || !(eps > 0.0) || !std::isfinite(eps)) return fail(c, DQMC_E_ARG, "bad arguments");
+  if (c->m.field != DQMC_FIELD_GAUSS) return fail(c, DQMC_E_UNSUPPORTED, "Langevin steps need a Gaussian field");
+  if (!c->bound || !c->initialized || c->poisoned) return fail(c, DQMC_E_STATE, "context not initialised");
+  for (int k = 0; k < n_steps; ++k)
+    if (dqmc_status s = langevin_once(c, eps, first_step + (uint64_t)k)) return s;
   return read_flag(c);
 }
 
@@ -1035,7 +1114,8 @@ bool layout_ok(const dqmc_ctx* c, const double* lo, const double* hi) {
   for (const UDVp* u : {&c->cur, &c->hA, &c->hB}) ok = ok && in(u->Q, NN, true) && in(u->D, N, true) && in(u->T, NN, true);
   ok = ok && in(c->field_alt, (size_t)c->L * N, true) && in(c->norms, N, true) && in(c->piv, N / 2 + 1, true) &&
        in(c->ipiv, N / 2 + 1, true) && in(c->bins, 4, true) && in(c->prec_hist, 2 * (size_t)c->nk + 2, true) &&
-       in(c->prec_tot, 4, true) && in(c->logdet, 4, true) && in(c->counters, 4, true) && in(c->err_flag, 1, true);
+       in(c->prec_tot, 4, true) && in(c->logdet, 4, true) && in(c->grad, (size_t)c->L * N, true) && in(c->gprec, 4, true) &&
+       in(c->counters, 4, true) && in(c->err_flag, 1, true);
   return ok;
 }
 
@@ -1280,6 +1360,39 @@ dqmc_status dqmc_batch_read_chain(dqmc_batch* b, int32_t chain, double* G_host, 
   return DQMC_OK;
 }
 
+dqmc_status dqmc_batch_grad_logdet(dqmc_batch* b) {
+  if (!b) return DQMC_E_ARG;
+  for (dqmc_ctx* c : b->groups)
+    if (!c->bound || !c->initialized || c->poisoned) return bfail(b, DQMC_E_STATE, "batch not initialised");
+  for (dqmc_ctx* c : b->groups)
+    if (dqmc_status s = grad_pass(c)) return bfail(b, s, c->err);
+  return batch_flags(b);
+}
+
+dqmc_status dqmc_batch_read_grad(dqmc_batch* b, int32_t chain, double* grad_host, double* prec) {
+  if (!b || !grad_host || chain < 0 || chain >= (int)b->group_of.size()) return bfail(b, DQMC_E_ARG, "bad arguments");
+  if (!b->bound) return bfail(b, DQMC_E_STATE, "not bound");
+  dqmc_ctx* c = b->groups[b->group_of[chain]];
+  const size_t co = (size_t)b->index_of[chain] * c->cs;
+  BHIPCHK_(hipMemcpyAsync(grad_host, c->grad + co, (size_t)c->L * c->N * sizeof(double), hipMemcpyDeviceToHost,
+                          b->stream));
+  if (prec) BHIPCHK_(hipMemcpyAsync(prec, c->gprec + co, sizeof(double), hipMemcpyDeviceToHost, b->stream));
+  BHIPCHK_(hipStreamSynchronize(b->stream));
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_batch_langevin(dqmc_batch* b, double eps, int32_t n_steps, uint64_t first_step) {
+  if (!b || n_steps < 0 || !(eps > 0.0) || !std::isfinite(eps)) return bfail(b, DQMC_E_ARG, "bad arguments");
+  for (dqmc_ctx* c : b->groups) {
+    if (!c->bound || !c->initialized || c->poisoned) return bfail(b, DQMC_E_STATE, "batch not initialised");
+    if (c->m.field != DQMC_FIELD_GAUSS) return bfail(b, DQMC_E_UNSUPPORTED, "Langevin steps need a Gaussian field");
+  }
+  for (int k = 0; k < n_steps; ++k)
+    for (dqmc_ctx* c : b->groups)
+      if (dqmc_status s = langevin_once(c, eps, first_step + (uint64_t)k)) return bfail(b, s, c->err);
+  return batch_flags(b);
+}
+
 int32_t dqmc_batch_groups(const dqmc_batch* b) { return b ? (int32_t)b->groups.size() : 0; }
 
 // Host-only self-check of the buffer layout, placing the groups at a fake
@@ -1293,6 +1406,9 @@ dqmc_status dqmc_batch_check_layout(dqmc_batch* b) {
     const double* hi = (g + 1 < b->groups.size()) ? fake + b->group_off[g + 1] : fake + b->total;
     if (!layout_ok(b->groups[g], base, hi)) return DQMC_E_STATE;
   }
+  // a bound batch gets its real placement back
+  if (b->work)
+    for (size_t g = 0; g < b->groups.size(); ++g) place_group(b->groups[g], b->work + b->group_off[g]);
   return DQMC_OK;
 }
 
