@@ -12,4 +12,4 @@ section or equation of the ALF 1.0 documentation (arXiv:1704.00131) that it
 follows; where the paper is silent the reading taken is stated in the
 docstring.
 """
-from . import philox, hubbard, stable, sweep, measure, exact_small, gradient  # noqa: F401
+from . import philox, hubbard, stable, sweep, measure, exact_small, gradient, timedisplaced  # noqa: F401

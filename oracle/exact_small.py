@@ -11,6 +11,7 @@ import numpy as np
 
 from .measure import equal_time
 from .stable import green_scratch, log_weight
+from .timedisplaced import tdgf_measure
 
 
 def all_fields(model):
@@ -36,3 +37,16 @@ def enumerate_weights(model):
     logw = np.array([log_weight(model, f) for f in all_fields(model)])
     w = np.exp(logw - logw.max())
     return w / w.sum()
+
+
+def enumerate_szsz(model, lat, kvec, taus):
+    """Exact weighted average of S_ab(K, tau) (time-displaced estimator) at
+    each tau in taus: [len(taus), norb, norb] complex."""
+    logw = []
+    obs = []
+    for f in all_fields(model):
+        logw.append(log_weight(model, f))
+        obs.append(tdgf_measure(model, lat, kvec, f, taus))
+    logw = np.array(logw)
+    w = np.exp(logw - logw.max())
+    return np.einsum("c,ctab->tab", w, np.array(obs)) / w.sum()

@@ -80,6 +80,8 @@ class Fock:
         return float(np.trace(P @ O) / np.trace(P))
 
     def expect_tau(self, A, B, dtau, L, n):
-        S = self.trotter(dtau)
+        return self.expect_tau_with(self.trotter(dtau), A, B, L, n)
+
+    def expect_tau_with(self, S, A, B, L, n):
         Z = np.trace(np.linalg.matrix_power(S, L))
         return float(np.trace(np.linalg.matrix_power(S, L - n) @ A @ np.linalg.matrix_power(S, n) @ B) / Z)

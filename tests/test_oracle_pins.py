@@ -324,3 +324,75 @@ def test_langevin_step_is_the_stated_update():
     xi = philox.normals(5, philox.TAG_LANGEVIN, 7, 3, 0, m.N)
     dlw = gradient.grad_log_weight(m, f)
     assert np.max(np.abs(new[2] - (f[2] + 1e-3 * dlw[2] + np.sqrt(2e-3) * xi))) < 1e-15
+
+
+# ------------------------------------------------------ time-displaced G --
+def _td_model(trotter="sym", beta=1.0, seed=4):
+    lat = square_lattice(3, 3)
+    m = hubbard.hubbard_model(lat.K, 4.0, beta, 0.1, 5, trotter=trotter, seed=seed)
+    return lat, m, hubbard.init_field(m)
+
+
+def test_tdgf_stable_forms_equal_definitions():
+    """The stabilised GT0 / G0T / GTT against B'(tau,0) G(0),
+    -(1 - G(0)) B'(tau,0)^-1 and the plain inverse, on a well conditioned case."""
+    from oracle import timedisplaced as td
+    lat, m, f = _td_model()
+    for tau in (0, 1, 4, 5, 7, 10):
+        a = td.tdgf_scratch(m, f, tau)
+        b = td.tdgf_naive(m, f, tau)
+        for x, y in zip(a, b):
+            assert np.max(np.abs(x - y)) < 1e-11
+
+
+def test_tdgf_boundaries():
+    """GT0(0) = G(0), G0T(0) = G(0) - 1, GT0(beta) = 1 - G(0), G0T(beta) = -G(0)."""
+    from oracle import timedisplaced as td
+    lat, m, f = _td_model(beta=4.0)
+    G0 = stable.green_scratch(m, f, 0)
+    I = np.eye(m.N)
+    GT0, G0T, GTT = td.tdgf_scratch(m, f, 0)
+    assert np.max(np.abs(GT0 - G0)) < 1e-12 and np.max(np.abs(G0T - (G0 - I))) < 1e-12
+    GT0, G0T, GTT = td.tdgf_scratch(m, f, m.L)
+    assert np.max(np.abs(GT0 - (I - G0))) < 1e-10 and np.max(np.abs(G0T + G0)) < 1e-10
+    assert np.max(np.abs(GTT - G0)) < 1e-10
+
+
+@pytest.mark.parametrize("trotter", ["sym", "asym"])
+def test_total_sz_correlation_is_conserved(trotter):
+    """S^z_tot commutes with every slice propagator, so for one configuration
+    sum_ab S_ab(K = 0, tau) does not depend on tau."""
+    from oracle import timedisplaced as td
+    lat = honeycomb_lattice(2, 2)
+    m = hubbard.hubbard_model(lat.K, 4.0, 2.0, 0.1, 5, trotter=trotter, seed=9)
+    f = hubbard.init_field(m)
+    S = td.tdgf_measure(m, lat, np.zeros(2), f, taus=(0, 3, 10, 11, 20))
+    tot = S.sum(axis=(1, 2))
+    assert np.max(np.abs(tot - tot[0])) < 1e-10
+    assert abs(tot[0].imag) < 1e-12
+
+
+@pytest.mark.parametrize("trotter", ["sym", "asym"])
+def test_szsz_enumeration_equals_fock(trotter):
+    """4-site honeycomb ring (2 cells x 2 orbitals) x 2 slices: the exact
+    weighted average of the time-displaced estimator at K = g2/2 against
+    Tr(S^(L-n) S^z_x S^n S^z_y) / Tr(S^L) in Fock space, Fourier transformed."""
+    from oracle import exact_small
+    lat = honeycomb_lattice(1, 2)
+    U, dtau, L = 4.0, 0.25, 2
+    m = hubbard.hubbard_model(lat.K, U, L * dtau, dtau, 1, trotter=trotter)
+    g1, g2 = lat.reciprocal()
+    kvec = 0.5 * g2
+    got = exact_small.enumerate_szsz(m, lat, kvec, taus=(0, 1, 2))
+    F = Fock(lat.K, U)
+    S = F.trotter(dtau) if trotter == "sym" else F.trotter_asym(dtau)
+    R = lat.cell_pos[lat.cell_of]
+    ph = np.exp(-1j * (R @ kvec))
+    for t, n in enumerate((0, 1, 2)):
+        want = np.zeros((2, 2), dtype=complex)
+        for x in range(4):
+            for y in range(4):
+                c = F.expect_tau_with(S, F.sz(x), F.sz(y), L, n)
+                want[lat.orb_of[x], lat.orb_of[y]] += ph[x] * np.conj(ph[y]) * c
+        want /= lat.n_cells
+        assert np.max(np.abs(got[t] - want)) < 1e-12, (trotter, n, got[t], want)
