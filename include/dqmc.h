@@ -120,9 +120,12 @@ dqmc_status dqmc_random_field(dqmc_ctx* ctx);
 dqmc_status dqmc_init(dqmc_ctx* ctx);
 
 /* n_sweeps sweeps (upward then downward pass, every field visited twice,
- * Algorithm 1).  measure != 0 accumulates the equal-time estimators on every
- * slice of both passes.  stats may be NULL.  DQMC_E_NUMERIC if the device
- * flagged a numerical failure; the context then needs dqmc_init. */
+ * Algorithm 1).  measure: bit 0 accumulates the equal-time estimators on
+ * every slice of both passes; bit 1 runs the time-displaced pass
+ * (dqmc_td_measure, needs dqmc_td_setup) at the start of every sweep, as the
+ * paper does for its time-displaced observables.  stats may be NULL.
+ * DQMC_E_NUMERIC if the device flagged a numerical failure; the context then
+ * needs dqmc_init. */
 dqmc_status dqmc_sweep(dqmc_ctx* ctx, int32_t n_sweeps, int32_t measure, dqmc_stats* stats);
 
 /* Bin sums: sums_host[0..3] = sum of D, sum of E_kin, sum of E_pot (per site)
@@ -159,6 +162,31 @@ dqmc_status dqmc_grad_logdet(dqmc_ctx* ctx, double* grad_dev, double* prec);
  * After each step the stored forms and G(0) are rebuilt from the new field.
  * DQMC_E_UNSUPPORTED for an Ising field; eps must be positive and finite. */
 dqmc_status dqmc_langevin(dqmc_ctx* ctx, double eps, int32_t n_steps, uint64_t first_step);
+
+/* ---- time-displaced Green's functions (section "Measuring time displaced
+ * observables"; Eq. (s_corr)) ----
+ * GT0(tau) = B(tau,0) G(0), G0T(tau) = -(1 - G(0)) B(tau,0)^-1 and
+ * GTT(tau) = G(tau) for tau = 0..L, propagated slice by slice from the state at
+ * the start of a sweep and re-anchored every n_wrap slices from the stabilised
+ * forms through the bounded matrix of the equal-time merge (the paper does not
+ * give the stable formulas: a reading).  Measured on them, per tau,
+ *   S_ab(K, tau) = (1/n_cells) sum_{x in a, y in b} p_x conj(p_y) <S^z_x(tau) S^z_y(0)>,
+ *   4 <S^z_x(tau) S^z_y(0)> = (1 - 2 GTT_xx)(1 - 2 G00_yy) - 2 G0T_yx GT0_xy,
+ * with the symmetric split's rotation applied as for the equal-time G.
+ *
+ * dqmc_td_setup: norb orbitals per cell (1..4); orb_of[n] the orbital of each
+ * site; phase[2n] = (cos, sin) of -K.R_cell(x) for each site x; n_cells the
+ * number of unit cells.  Host arrays, copied.  Zeroes the time-displaced bins. */
+dqmc_status dqmc_td_setup(dqmc_ctx* ctx, int32_t norb, const int32_t* orb_of, const double* phase, int32_t n_cells);
+/* One time-displaced pass of the current configuration (an initialised chain
+ * at the start of a sweep); adds S to the bins.  S_host (may be NULL):
+ * (L+1)*norb*norb*2 doubles [tau][a][b][re, im].  prec (may be NULL): 2 host
+ * doubles, the largest |propagated - re-anchored| of GTT and of GT0 / G0T.
+ * The chain's G, field and stored forms are unchanged. */
+dqmc_status dqmc_td_measure(dqmc_ctx* ctx, double* S_host, double* prec);
+/* Bin sums of S in the layout of dqmc_td_measure and the number of passes
+ * summed (count, may be NULL).  Zeroed by dqmc_init and dqmc_reset_bins. */
+dqmc_status dqmc_td_read_bins(dqmc_ctx* ctx, double* sums_host, double* count);
 
 /* Per-launch timing of one kernel of the sweep, for roofline reports: while
  * enabled, every launch of the selected kernel on the context's stream is

@@ -77,9 +77,10 @@ class Chain:
         self._chk(self.lib.dqmc_init(self.ctx))
         return self
 
-    def sweep(self, n_sweeps=1, measure=True) -> Stats:
+    def sweep(self, n_sweeps=1, measure=True, time_displaced=False) -> Stats:
         st = Stats()
-        self._chk(self.lib.dqmc_sweep(self.ctx, n_sweeps, 1 if measure else 0, ctypes.byref(st)))
+        flags = (1 if measure else 0) | (2 if time_displaced else 0)
+        self._chk(self.lib.dqmc_sweep(self.ctx, n_sweeps, flags, ctypes.byref(st)))
         return st
 
     def read_bins(self) -> np.ndarray:
@@ -118,6 +119,29 @@ class Chain:
     def langevin(self, eps: float, n_steps: int = 1, first_step: int = 0):
         self._chk(self.lib.dqmc_langevin(self.ctx, eps, n_steps, first_step))
         return self
+
+    def td_setup(self, orb_of, phase, n_cells: int):
+        """Momentum and orbitals of the time-displaced S^z-S^z measurement:
+        orb_of [N] ints, phase [N] complex exp(-i K.R_cell(x))."""
+        orb = np.ascontiguousarray(orb_of, dtype=np.int32)
+        ph = np.ascontiguousarray(np.stack([np.real(phase), np.imag(phase)], axis=1), dtype=np.float64)
+        self.td_norb = int(orb.max()) + 1
+        self._chk(self.lib.dqmc_td_setup(self.ctx, self.td_norb, orb.ctypes.data, ph.ctypes.data, n_cells))
+        return self
+
+    def td_measure(self):
+        """S_ab(K, tau) [L+1, norb, norb] complex of the current configuration and
+        the pass's precision (GTT, GT0/G0T)."""
+        raw = np.empty((self.L + 1, self.td_norb, self.td_norb, 2))
+        prec = np.zeros(2)
+        self._chk(self.lib.dqmc_td_measure(self.ctx, raw.ctypes.data, prec.ctypes.data))
+        return raw[..., 0] + 1j * raw[..., 1], prec
+
+    def td_read_bins(self):
+        raw = np.empty((self.L + 1, self.td_norb, self.td_norb, 2))
+        cnt = ctypes.c_double()
+        self._chk(self.lib.dqmc_td_read_bins(self.ctx, raw.ctypes.data, ctypes.byref(cnt)))
+        return raw[..., 0] + 1j * raw[..., 1], cnt.value
 
     def timing(self, kernel: str = "block_update", enable: bool = True):
         k = _lib.KERNEL_BLOCK_UPDATE if kernel == "block_update" else _lib.KERNEL_GEMM

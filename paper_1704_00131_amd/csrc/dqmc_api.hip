@@ -18,6 +18,7 @@
 #include "linalg.h"
 #include "update.h"
 #include "adjoint.h"
+#include "timedisplaced.h"
 
 namespace {
 
@@ -60,6 +61,14 @@ struct dqmc_ctx {
   int *piv = nullptr, *ipiv = nullptr;
   double *bins = nullptr, *prec_hist = nullptr, *prec_tot = nullptr, *logdet = nullptr;
   double *grad = nullptr, *gprec = nullptr;   // gradient rows [L][N] and the gradient pass's precision
+  // time-displaced pass: GT0 and H = G0T^T (two buffers each), the 2N-column
+  // right-hand sides of the re-anchoring solve, S(K, tau) of the current
+  // configuration and its bin sums, partial records, A_a(0); the momentum
+  // phases and orbital map are shared
+  double *TD[4] = {}, *RHS2 = nullptr, *tdS = nullptr, *tdbins = nullptr, *tdpart = nullptr, *a00 = nullptr;
+  double* kph = nullptr;
+  int* korb = nullptr;
+  int td_norb = 0, td_cells = 0;
   unsigned long long* counters = nullptr;   // proposals, accepted, sweep counter
   int* err_flag = nullptr;
   size_t work_doubles = 0;
@@ -114,6 +123,10 @@ size_t layout_shared(dqmc_ctx* c, double* base) {
   P(c->E, NN); P(c->Einv, NN); P(c->Eh, NN); P(c->Ehinv, NN); P(c->Kd, NN);
   P(c->uid.Q, NN); P(c->uid.D, N); P(c->uid.T, NN);
   P(c->gbuf, 8 * (size_t)std::max(1, c->nch));   // contiguous staging of per-chain scalars
+  P(c->kph, 2 * N);
+  double* ko = nullptr;
+  P(ko, N / 2 + 1);
+  if (base) c->korb = reinterpret_cast<int*>(ko);
   if (base) { c->shared_lo = base; c->shared_hi = base + l.off; }
   return l.off;
 }
@@ -140,6 +153,12 @@ size_t layout_chain(dqmc_ctx* c, double* base) {
   P(c->logdet, 4);
   P(c->grad, (size_t)c->L * N);
   P(c->gprec, 4);
+  for (int i = 0; i < 4; ++i) P(c->TD[i], NN);
+  P(c->RHS2, 2 * NN);
+  P(c->tdS, (size_t)(c->L + 1) * kTdStride);
+  P(c->tdbins, (size_t)(c->L + 1) * kTdStride + 4);
+  P(c->tdpart, (size_t)((N + kTdRows - 1) / kTdRows) * kTdPart);
+  P(c->a00, 2 * kTdMaxOrb);
   double* ctr = nullptr;
   double* ef = nullptr;
   P(ctr, 4); P(ef, 1);
@@ -424,15 +443,15 @@ dqmc_status left_step(dqmc_ctx* c, UDVp in, int lo, int hi, UDVp out) {
   return qr_udv(c, const_cast<double*>(src), in.T, out);
 }
 
-// Solve X Y = RHS in place (blocked LU with partial pivoting).  If logdet is
-// given, adds log|det X|.
-dqmc_status lu_solve(dqmc_ctx* c, double* X, double* RHS, double* logdet) {
+// Solve X Y = RHS in place (blocked LU with partial pivoting); RHS is
+// N x nrhs with leading dimension ldb.  If logdet is given, adds log|det X|.
+dqmc_status lu_solve(dqmc_ctx* c, double* X, double* RHS, int nrhs, int ldb, double* logdet) {
   const int N = c->N, nb = c->nb;
   for (int j0 = 0; j0 < N; j0 += nb) {
     const int nbw = std::min(nb, N - j0), h = N - j0;
     if (dqmc_status s = launch_lu_panel(c, X, j0, nbw)) return s;
-    hipLaunchKernelGGL(k_lu_swap, gridc(c, grid1((size_t)(N - nbw) + N)), dim3(256), 0, c->stream, X, N, j0, nbw,
-                       c->ipiv, RHS, N, N, c->cs);
+    hipLaunchKernelGGL(k_lu_swap, gridc(c, grid1((size_t)(N - nbw) + nrhs)), dim3(256), 0, c->stream, X, N, j0, nbw,
+                       c->ipiv, RHS, nrhs, ldb, c->cs);
     HIPCHK(hipGetLastError());
     const int ntr = N - j0 - nbw;
     if (ntr > 0) {
@@ -448,25 +467,26 @@ dqmc_status lu_solve(dqmc_ctx* c, double* X, double* RHS, double* logdet) {
   // forward substitution with unit-lower L (right-looking)
   for (int j0 = 0; j0 < N; j0 += nb) {
     const int nbw = std::min(nb, N - j0);
-    hipLaunchKernelGGL(k_trsm_block, gridc(c, grid1(N)), dim3(256), 0, c->stream, X + (size_t)j0 * N + j0, N,
-                       RHS + (size_t)j0 * N, N, nbw, N, 0, c->cs);
+    hipLaunchKernelGGL(k_trsm_block, gridc(c, grid1(nrhs)), dim3(256), 0, c->stream, X + (size_t)j0 * N + j0, N,
+                       RHS + (size_t)j0 * ldb, ldb, nbw, nrhs, 0, c->cs);
     HIPCHK(hipGetLastError());
     const int rest = N - j0 - nbw;
     if (rest > 0)
-      if (dqmc_status s = gemm(c, gemm_args(rest, N, nbw, X + (size_t)(j0 + nbw) * N + j0, N, 0,
-                                            RHS + (size_t)j0 * N, N, 0, RHS + (size_t)(j0 + nbw) * N, N, -1.0, 1.0)))
+      if (dqmc_status s = gemm(c, gemm_args(rest, nrhs, nbw, X + (size_t)(j0 + nbw) * N + j0, N, 0,
+                                            RHS + (size_t)j0 * ldb, ldb, 0, RHS + (size_t)(j0 + nbw) * ldb, ldb, -1.0,
+                                            1.0)))
         return s;
   }
   // back substitution with U
   const int last = ((N - 1) / nb) * nb;
   for (int j0 = last; j0 >= 0; j0 -= nb) {
     const int nbw = std::min(nb, N - j0);
-    hipLaunchKernelGGL(k_trsm_block, gridc(c, grid1(N)), dim3(256), 0, c->stream, X + (size_t)j0 * N + j0, N,
-                       RHS + (size_t)j0 * N, N, nbw, N, 1, c->cs);
+    hipLaunchKernelGGL(k_trsm_block, gridc(c, grid1(nrhs)), dim3(256), 0, c->stream, X + (size_t)j0 * N + j0, N,
+                       RHS + (size_t)j0 * ldb, ldb, nbw, nrhs, 1, c->cs);
     HIPCHK(hipGetLastError());
     if (j0 > 0)
-      if (dqmc_status s = gemm(c, gemm_args(j0, N, nbw, X + j0, N, 0, RHS + (size_t)j0 * N, N, 0, RHS, N, -1.0,
-                                            1.0)))
+      if (dqmc_status s = gemm(c, gemm_args(j0, nrhs, nbw, X + j0, N, 0, RHS + (size_t)j0 * ldb, ldb, 0, RHS, ldb,
+                                            -1.0, 1.0)))
         return s;
   }
   if (logdet) {
@@ -501,7 +521,7 @@ dqmc_status merge(dqmc_ctx* c, UDVp R, UDVp Lf, double* Gout, double* logdet) {
                        is_shared(c, Lf.D) ? (size_t)0 : c->cs, c->cs);
     HIPCHK(hipGetLastError());
   }
-  if (dqmc_status s = lu_solve(c, c->X, c->RHS, logdet)) return s;
+  if (dqmc_status s = lu_solve(c, c->X, c->RHS, N, N, logdet)) return s;
   GemmArgs g3 = gemm_args(N, N, N, Lf.Q, N, 0, c->RHS, N, 0, Gout, N);
   g3.ks = Lf.D; g3.ks_mode = SC_INV_BIG;
   return gemm(c, g3);
@@ -539,8 +559,13 @@ dqmc_status measure(dqmc_ctx* c) {
 }
 
 // One sweep (Algorithm 1): upward pass tau = 1..L, downward pass tau = L..1.
-dqmc_status sweep_once(dqmc_ctx* c, bool meas) {
+// meas: bit 0 = equal-time estimators on every slice, bit 1 = the
+// time-displaced pass at the start of the sweep.
+dqmc_status td_pass(dqmc_ctx* c);
+dqmc_status sweep_once(dqmc_ctx* c, int meas) {
   const int L = c->L, nw = c->nw, nk = c->nk;
+  if (meas & 2)
+    if (dqmc_status s = td_pass(c)) return s;
   int hist = 0;
   c->row_alt.assign(L, 0);
   c->Gcur = c->G;
@@ -556,12 +581,12 @@ dqmc_status sweep_once(dqmc_ctx* c, bool meas) {
       if (dqmc_status s = copy_udv(c, c->slot(k), c->cur)) return s;
       if (dqmc_status s = stabilise(c, hist++)) return s;
     }
-    if (meas)
+    if (meas & 1)
       if (dqmc_status s = measure(c)) return s;
   }
   for (int tau = L; tau >= 1; --tau) {
     if (dqmc_status s = update_slice(c, tau, 1)) return s;
-    if (meas)
+    if (meas & 1)
       if (dqmc_status s = measure(c)) return s;
     if ((tau - 1) % nw == 0) {
       const int k = (tau - 1) / nw;
@@ -660,6 +685,119 @@ dqmc_status langevin_once(dqmc_ctx* c, double eps, uint64_t step) {
                      c->m.coupling, c->m.alpha, (double)c->m.n_col, (unsigned long long)step, c->counters, c->cs);
   HIPCHK(hipGetLastError());
   return reanchor(c);
+}
+
+// --------------------------------------------------- time-displaced pass --
+// Re-anchoring at a checkpoint from the right form R of B(tau,0) and the left
+// form Lf of B(beta,tau)^T.  With X the bounded matrix of the merge,
+//   [Y1 | Y2] = X^-1 [D_Rb^-1 Q_R^T | D_Rs T_R],
+//   GTT = Q_L D_Lb^-1 Y1,  GT0 = Q_L D_Lb^-1 Y2,  G0T^T = -Y1^T D_Ls T_L,
+// each replacing its propagated value (largest deviation into gprec[0] for
+// GTT, gprec[1] for GT0 and G0T).
+dqmc_status td_anchor(dqmc_ctx* c, UDVp R, UDVp Lf, double* gt0, double* h) {
+  const int N = c->N;
+  const size_t NN = (size_t)N * N;
+  GemmArgs g1 = gemm_args(N, N, N, R.Q, N, 1, Lf.Q, N, 0, c->X, N);
+  g1.rs = R.D; g1.rs_mode = SC_INV_BIG; g1.cs = Lf.D; g1.cs_mode = SC_INV_BIG;
+  if (dqmc_status s = gemm(c, g1)) return s;
+  GemmArgs g2 = gemm_args(N, N, N, R.T, N, 0, Lf.T, N, 1, c->X, N, 1.0, 1.0);
+  g2.rs = R.D; g2.rs_mode = SC_SMALL; g2.cs = Lf.D; g2.cs_mode = SC_SMALL;
+  if (dqmc_status s = gemm(c, g2)) return s;
+  const unsigned t = (unsigned)((N + 31) / 32);
+  hipLaunchKernelGGL(k_td_rhs, dim3(t, t, (unsigned)c->nch), dim3(256), 0, c->stream, c->RHS2, R.Q, R.T, R.D, N,
+                     c->cs, is_shared(c, R.Q) ? (size_t)0 : c->cs);
+  HIPCHK(hipGetLastError());
+  if (dqmc_status s = lu_solve(c, c->X, c->RHS2, 2 * N, 2 * N, nullptr)) return s;
+  const unsigned pg = (unsigned)std::min<size_t>(grid1(NN), 1024);
+  GemmArgs g3 = gemm_args(N, N, N, Lf.Q, N, 0, c->RHS2, 2 * N, 0, c->Gs, N);
+  g3.ks = Lf.D; g3.ks_mode = SC_INV_BIG;
+  if (dqmc_status s = gemm(c, g3)) return s;
+  hipLaunchKernelGGL(k_prec_replace, gridc(c, pg), dim3(256), 0, c->stream, c->G2, c->G2, c->Gs, NN, c->gprec,
+                     c->err_flag, c->cs);
+  GemmArgs g4 = gemm_args(N, N, N, Lf.Q, N, 0, c->RHS2 + N, 2 * N, 0, c->X, N);
+  g4.ks = Lf.D; g4.ks_mode = SC_INV_BIG;
+  if (dqmc_status s = gemm(c, g4)) return s;
+  hipLaunchKernelGGL(k_prec_replace, gridc(c, pg), dim3(256), 0, c->stream, gt0, gt0, c->X, NN, c->gprec + 1,
+                     c->err_flag, c->cs);
+  GemmArgs g5 = gemm_args(N, N, N, c->RHS2, 2 * N, 1, Lf.T, N, 0, c->RHS, N, -1.0);
+  g5.ks = Lf.D; g5.ks_mode = SC_SMALL;
+  if (dqmc_status s = gemm(c, g5)) return s;
+  hipLaunchKernelGGL(k_prec_replace, gridc(c, pg), dim3(256), 0, c->stream, h, h, c->RHS, NN, c->gprec + 1,
+                     c->err_flag, c->cs);
+  HIPCHK(hipGetLastError());
+  return DQMC_OK;
+}
+
+// S_ab(K, tau) of the current GT0, H = G0T^T and GTT.  With the symmetric
+// Trotter split the estimator takes the rotated exp(-dtau K/2) (.) exp(+dtau K/2)
+// matrices (for H the rotation is exp(+dtau K/2) H exp(-dtau K/2)).
+dqmc_status td_measure(dqmc_ctx* c, int tau, const double* gt0, const double* h, const double* gtt) {
+  const int N = c->N;
+  if (c->m.trotter == DQMC_TROTTER_SYM) {
+    if (dqmc_status s = gemm(c, gemm_args(N, N, N, c->Eh, N, 0, gt0, N, 0, c->T1, N))) return s;
+    if (dqmc_status s = gemm(c, gemm_args(N, N, N, c->T1, N, 0, c->Ehinv, N, 0, c->Gs, N))) return s;
+    if (dqmc_status s = gemm(c, gemm_args(N, N, N, c->Ehinv, N, 0, h, N, 0, c->T1, N))) return s;
+    if (dqmc_status s = gemm(c, gemm_args(N, N, N, c->T1, N, 0, c->Eh, N, 0, c->X, N))) return s;
+    if (dqmc_status s = gemm(c, gemm_args(N, N, N, c->Eh, N, 0, gtt, N, 0, c->T1, N))) return s;
+    if (dqmc_status s = gemm(c, gemm_args(N, N, N, c->T1, N, 0, c->Ehinv, N, 0, c->RHS, N))) return s;
+    gt0 = c->Gs; h = c->X; gtt = c->RHS;
+  }
+  const int nblk = (N + kTdRows - 1) / kTdRows;
+  hipLaunchKernelGGL(k_td_partial, gridc(c, (unsigned)nblk), dim3(256), 0, c->stream, gt0, h, gtt, c->kph, c->korb,
+                     N, c->tdpart, c->cs);
+  HIPCHK(hipGetLastError());
+  const size_t off = (size_t)tau * kTdStride;
+  hipLaunchKernelGGL(k_td_finish, gridc(c, 1), dim3(64), 0, c->stream, c->tdpart, nblk, 1.0 / c->td_cells, c->a00,
+                     c->tdS + off, c->tdbins + off, c->tdbins + (size_t)(c->L + 1) * kTdStride, tau == 0 ? 1 : 0,
+                     c->cs);
+  HIPCHK(hipGetLastError());
+  return DQMC_OK;
+}
+
+// Time-displaced pass from the state at the start of a sweep (G = G(0), left
+// forms stored): for tau = 1..L, GTT is wrapped, GT0 and H propagated, all
+// three re-anchored every n_wrap slices from a running right form and the
+// stored left forms, and S(K, tau) measured at tau = 0..L.  The chain's G,
+// field and stored forms are left unchanged.
+dqmc_status td_pass(dqmc_ctx* c) {
+  const int N = c->N, L = c->L, nw = c->nw, nk = c->nk;
+  const size_t NN = (size_t)N * N;
+  if (c->td_norb < 1) return fail(c, DQMC_E_STATE, "time-displaced measurement not set up");
+  c->row_alt.clear();
+  if (dqmc_status s = fill_small(c, c->gprec, 2, 0.0)) return s;
+  hipLaunchKernelGGL(k_copy, gridc(c, grid1(NN)), dim3(256), 0, c->stream, c->G2, c->G, NN, c->cs);
+  const unsigned t = (unsigned)((N + 31) / 32);
+  hipLaunchKernelGGL(k_td_init, dim3(t, t, (unsigned)c->nch), dim3(256), 0, c->stream, c->G, c->TD[0], c->TD[2], N,
+                     c->cs);
+  HIPCHK(hipGetLastError());
+  double *gt0 = c->TD[0], *gt0_alt = c->TD[1], *h = c->TD[2], *h_alt = c->TD[3];
+  c->Gcur = c->G2;
+  if (dqmc_status s = td_measure(c, 0, gt0, h, c->G2)) return s;
+  UDVp right = c->uid;
+  UDVp bufs[2] = {c->hA, c->hB};
+  int b = 0;
+  for (int tau = 1; tau <= L; ++tau) {
+    if (dqmc_status s = wrap_up(c, tau, c->G2)) return s;
+    GemmArgs ga = gemm_args(N, N, N, c->E, N, 0, gt0, N, 0, gt0_alt, N);
+    ga.rs = field_row(c, tau); ga.rs_mode = SC_EXP; ga.rs_coef = c->m.coupling;
+    if (dqmc_status s = gemm(c, ga)) return s;
+    std::swap(gt0, gt0_alt);
+    GemmArgs gh = gemm_args(N, N, N, c->Einv, N, 0, h, N, 0, h_alt, N);
+    gh.rs = field_row(c, tau); gh.rs_mode = SC_EXP; gh.rs_coef = -c->m.coupling;
+    if (dqmc_status s = gemm(c, gh)) return s;
+    std::swap(h, h_alt);
+    if (tau % nw == 0) {
+      const int k = tau / nw;
+      if (dqmc_status s = right_step(c, right, tau - nw, tau, bufs[b])) return s;
+      right = bufs[b];
+      b ^= 1;
+      UDVp left = (k == nk) ? c->uid : c->slot(k);
+      if (dqmc_status s = td_anchor(c, right, left, gt0, h)) return s;
+    }
+    if (dqmc_status s = td_measure(c, tau, gt0, h, c->G2)) return s;
+  }
+  c->Gcur = c->G;
+  return DQMC_OK;
 }
 
 // Copy `bytes` (<= 64) of a per-chain item from every chain into host dst
@@ -870,6 +1008,7 @@ dqmc_status dqmc_init(dqmc_ctx* c) {
   if (!c->bound) return fail(c, DQMC_E_STATE, "not bound");
   // statistics, bins, flag
   if (dqmc_status s = fill_small(c, c->bins, 4, 0.0)) return s;
+  if (dqmc_status s = fill_small(c, c->tdbins, (size_t)(c->L + 1) * kTdStride + 4, 0.0)) return s;
   if (dqmc_status s = fill_small(c, c->prec_hist, 2 * (size_t)c->nk + 2, 0.0)) return s;
   if (dqmc_status s = fill_small(c, c->prec_tot, 4, 0.0)) return s;
   if (dqmc_status s = fill_small(c, reinterpret_cast<double*>(c->counters), 2, 0.0)) return s;
@@ -884,9 +1023,11 @@ dqmc_status dqmc_init(dqmc_ctx* c) {
 dqmc_status dqmc_sweep(dqmc_ctx* c, int32_t n_sweeps, int32_t meas, dqmc_stats* st) {
   if (!c || n_sweeps < 0) return fail(c, DQMC_E_ARG, "bad arguments");
   if (!c->bound || !c->initialized || c->poisoned) return fail(c, DQMC_E_STATE, "context not initialised");
+  if (meas & ~3) return fail(c, DQMC_E_ARG, "unknown measurement flags");
+  if ((meas & 2) && c->td_norb < 1) return fail(c, DQMC_E_STATE, "time-displaced measurement not set up");
   const auto t0 = std::chrono::steady_clock::now();
   for (int s = 0; s < n_sweeps; ++s)
-    if (dqmc_status r = sweep_once(c, meas != 0)) return r;
+    if (dqmc_status r = sweep_once(c, meas)) return r;
   if (dqmc_status r = read_flag(c)) return r;
   const auto t1 = std::chrono::steady_clock::now();
   if (st) {
@@ -908,6 +1049,7 @@ dqmc_status dqmc_reset_bins(dqmc_ctx* c) {
   if (!c) return DQMC_E_ARG;
   if (!c->bound) return fail(c, DQMC_E_STATE, "not bound");
   if (dqmc_status s = fill_small(c, c->bins, 4, 0.0)) return s;
+  if (dqmc_status s = fill_small(c, c->tdbins, (size_t)(c->L + 1) * kTdStride + 4, 0.0)) return s;
   HIPCHK(hipStreamSynchronize(c->stream));
   return DQMC_OK;
 }
@@ -978,6 +1120,62 @@ dqmc_status dqmc_langevin(dqmc_ctx* c, double eps, int32_t n_steps, uint64_t fir
   for (int k = 0; k < n_steps; ++k)
     if (dqmc_status s = langevin_once(c, eps, first_step + (uint64_t)k)) return s;
   return read_flag(c);
+}
+
+dqmc_status dqmc_td_setup(dqmc_ctx* c, int32_t norb, const int32_t* orb_of, const double* phase, int32_t n_cells) {
+  if (!c || !orb_of || !phase || norb < 1 || norb > kTdMaxOrb || n_cells < 1)
+    return fail(c, DQMC_E_ARG, "bad arguments");
+  if (!c->bound) return fail(c, DQMC_E_STATE, "not bound");
+  for (int i = 0; i < c->N; ++i) {
+    if (orb_of[i] < 0 || orb_of[i] >= norb) return fail(c, DQMC_E_ARG, "orbital index out of range");
+    if (!std::isfinite(phase[2 * i]) || !std::isfinite(phase[2 * i + 1])) return fail(c, DQMC_E_ARG, "bad phase");
+  }
+  HIPCHK(hipMemcpyAsync(c->kph, phase, 2 * sizeof(double) * c->N, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->korb, orb_of, sizeof(int32_t) * c->N, hipMemcpyHostToDevice, c->stream));
+  if (dqmc_status s = fill_small(c, c->tdbins, (size_t)(c->L + 1) * kTdStride + 4, 0.0)) return s;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->td_norb = norb;
+  c->td_cells = n_cells;
+  return DQMC_OK;
+}
+
+// Copies S(K, tau) for tau = 0..L out of the device layout (stride kTdStride,
+// entry (a * kTdMaxOrb + b) * 2) into [L+1][norb][norb][2].
+static void td_compact(const dqmc_ctx* c, const double* dev_layout, double* out) {
+  const int no = c->td_norb;
+  for (int t = 0; t <= c->L; ++t)
+    for (int a = 0; a < no; ++a)
+      for (int b = 0; b < no; ++b)
+        for (int r = 0; r < 2; ++r)
+          out[(((size_t)t * no + a) * no + b) * 2 + r] = dev_layout[(size_t)t * kTdStride + (a * kTdMaxOrb + b) * 2 + r];
+}
+
+dqmc_status dqmc_td_measure(dqmc_ctx* c, double* S_host, double* prec) {
+  if (!c) return DQMC_E_ARG;
+  if (!c->bound || !c->initialized || c->poisoned) return fail(c, DQMC_E_STATE, "context not initialised");
+  if (dqmc_status s = td_pass(c)) return s;
+  std::vector<double> raw;
+  if (S_host) {
+    raw.resize((size_t)(c->L + 1) * kTdStride);
+    HIPCHK(hipMemcpyAsync(raw.data(), c->tdS, raw.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  }
+  double pr[2] = {0.0, 0.0};
+  if (prec) HIPCHK(hipMemcpyAsync(pr, c->gprec, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (S_host) td_compact(c, raw.data(), S_host);
+  if (prec) { prec[0] = pr[0]; prec[1] = pr[1]; }
+  return read_flag(c);
+}
+
+dqmc_status dqmc_td_read_bins(dqmc_ctx* c, double* sums_host, double* count) {
+  if (!c || !sums_host) return DQMC_E_ARG;
+  if (!c->bound || c->td_norb < 1) return fail(c, DQMC_E_STATE, "time-displaced measurement not set up");
+  std::vector<double> raw((size_t)(c->L + 1) * kTdStride + 1);
+  HIPCHK(hipMemcpyAsync(raw.data(), c->tdbins, raw.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  td_compact(c, raw.data(), sums_host);
+  if (count) *count = raw.back();
+  return DQMC_OK;
 }
 
 dqmc_status dqmc_timing_enable(dqmc_ctx* c, dqmc_kernel kernel, int32_t enable) {
@@ -1115,6 +1313,11 @@ bool layout_ok(const dqmc_ctx* c, const double* lo, const double* hi) {
   ok = ok && in(c->field_alt, (size_t)c->L * N, true) && in(c->norms, N, true) && in(c->piv, N / 2 + 1, true) &&
        in(c->ipiv, N / 2 + 1, true) && in(c->bins, 4, true) && in(c->prec_hist, 2 * (size_t)c->nk + 2, true) &&
        in(c->prec_tot, 4, true) && in(c->logdet, 4, true) && in(c->grad, (size_t)c->L * N, true) && in(c->gprec, 4, true) &&
+       in(c->TD[0], NN, true) && in(c->TD[1], NN, true) && in(c->TD[2], NN, true) && in(c->TD[3], NN, true) &&
+       in(c->RHS2, 2 * NN, true) && in(c->tdS, (size_t)(c->L + 1) * kTdStride, true) &&
+       in(c->tdbins, (size_t)(c->L + 1) * kTdStride + 4, true) &&
+       in(c->tdpart, (size_t)((N + kTdRows - 1) / kTdRows) * kTdPart, true) && in(c->a00, 2 * kTdMaxOrb, true) &&
+       in(c->kph, 2 * N, false) && in(c->korb, N / 2 + 1, false) &&
        in(c->counters, 4, true) && in(c->err_flag, 1, true);
   return ok;
 }
@@ -1259,7 +1462,7 @@ dqmc_status dqmc_batch_sweep(dqmc_batch* b, int32_t n_sweeps, int32_t measure, d
   }
   for (int s = 0; s < left; ++s)
     for (dqmc_ctx* c : b->groups)
-      if (dqmc_status r = sweep_once(c, measure != 0)) return bfail(b, r, c->err);
+      if (dqmc_status r = sweep_once(c, measure ? 1 : 0)) return bfail(b, r, c->err);
   if (dqmc_status r = batch_flags(b)) return r;
   const auto t1 = std::chrono::steady_clock::now();
   if (st) {
@@ -1293,7 +1496,7 @@ dqmc_status dqmc_batch_capture(dqmc_batch* b, int32_t sweeps_per_graph, int32_t 
   dqmc_status st = DQMC_OK;
   for (int s = 0; s < sweeps_per_graph && st == DQMC_OK; ++s)
     for (dqmc_ctx* c : b->groups)
-      if ((st = sweep_once(c, measure != 0)) != DQMC_OK) break;
+      if ((st = sweep_once(c, measure ? 1 : 0)) != DQMC_OK) break;
   hipError_t ce = hipStreamEndCapture(b->stream, &b->graph);
   if (st != DQMC_OK) return bfail(b, st, "capture failed");
   BHIPCHK_(ce);
@@ -1324,7 +1527,7 @@ dqmc_status dqmc_batch_autotune(dqmc_batch* b, int32_t trials) {
       c->gemm_tile = t;
       BHIPCHK_(hipEventRecord(e0, b->stream));
       for (int s = 0; s < trials; ++s)
-        if (dqmc_status r = sweep_once(c, false)) return bfail(b, r, c->err);
+        if (dqmc_status r = sweep_once(c, 0)) return bfail(b, r, c->err);
       BHIPCHK_(hipEventRecord(e1, b->stream));
       BHIPCHK_(hipEventSynchronize(e1));
       float ms = 0.0f;

@@ -1,0 +1,174 @@
+// Time-displaced Green's functions and the S^z-S^z correlation at one
+// momentum (section "Measuring time displaced observables"; Eq. (s_corr)).
+//
+// Propagation between checkpoints, with B_tau = diag(v_tau) E:
+//   GT0(tau) = B_tau GT0(tau-1),
+//   H(tau)   = G0T(tau)^T = B_tau^-T H(tau-1) = diag(1/v_tau) E^-1 H(tau-1),
+// so both are left products on the MFMA GEMM and H keeps G0T transposed,
+// which makes the estimator below a coalesced elementwise product.
+//
+// Estimator per configuration (two sampling-frame colours; S^z maps to
+// (n_1 + n_2 - 1)/2 under the partial particle-hole map):
+//   4 <S^z_x(tau) S^z_y(0)> = (1 - 2 GTT_xx)(1 - 2 G00_yy) - 2 G0T_yx GT0_xy,
+//   S_ab(K,tau) = (1/N_cells) sum_{x in a, y in b} p_x conj(p_y) <S^z_x(tau) S^z_y(0)>,
+// p_x = exp(-i K.R_x).  With A_a(tau) = sum_{x in a} p_x (1 - 2 GTT_xx) and
+// C_ab = sum_{x in a, y in b} p_x conj(p_y) H_xy GT0_xy:
+//   S_ab = (0.25 A_a(tau) conj(A_b(0)) - 0.5 C_ab) / N_cells.
+#pragma once
+#include "device_common.h"
+
+constexpr int kTdMaxOrb = 4;          // orbitals per unit cell
+constexpr int kTdRows = 8;            // rows of the product per workgroup
+constexpr int kTdPart = 2 * kTdMaxOrb * kTdMaxOrb + 2 * kTdMaxOrb;   // doubles per partial record
+constexpr int kTdStride = 2 * kTdMaxOrb * kTdMaxOrb;                 // doubles per tau of S
+
+// GT0 = G, H = G^T - 1 (tau = 0); 32 x 32 tiles through LDS, grid (t, t, chains).
+__global__ __launch_bounds__(256) void k_td_init(const double* G, double* GT0, double* H, int n, size_t cs) {
+  __shared__ double tile[32][33];
+  const size_t co = (size_t)blockIdx.z * cs;
+  G += co; GT0 += co; H += co;
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r = ty; r < 32; r += 8) {
+    const int i = by + r, j = bx + tx;
+    double v = 0.0;
+    if (i < n && j < n) {
+      v = G[(size_t)i * n + j];
+      GT0[(size_t)i * n + j] = v;
+    }
+    tile[r][tx] = v;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int i = bx + r, j = by + tx;   // H[i][j] = G[j][i] - delta_ij
+    if (i < n && j < n) H[(size_t)i * n + j] = tile[tx][r] - (i == j ? 1.0 : 0.0);
+  }
+}
+
+// Right-hand sides of the re-anchoring solve, n x 2n with leading dimension 2n:
+//   [ D_b^-1 Q^T | D_s T ],  D_b = max(D, 1), D_s = min(D, 1).
+// Grid (t, t, chains); cs_src = 0 when the right form is the shared identity.
+__global__ __launch_bounds__(256) void k_td_rhs(double* R2, const double* Q, const double* T, const double* D, int n,
+                                                size_t cs_dst, size_t cs_src) {
+  __shared__ double tile[32][33];
+  R2 += (size_t)blockIdx.z * cs_dst;
+  Q += (size_t)blockIdx.z * cs_src;
+  T += (size_t)blockIdx.z * cs_src;
+  D += (size_t)blockIdx.z * cs_src;
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const size_t ld = 2 * (size_t)n;
+  for (int r = ty; r < 32; r += 8) {
+    const int i = by + r, j = bx + tx;
+    tile[r][tx] = (i < n && j < n) ? Q[(size_t)i * n + j] : 0.0;
+    if (i < n && j < n) R2[(size_t)i * ld + n + j] = fmin(D[i], 1.0) * T[(size_t)i * n + j];
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int i = bx + r, j = by + tx;   // left half [i][j] = Q[j][i] / D_b[i]
+    if (i < n && j < n) R2[(size_t)i * ld + j] = tile[tx][r] / fmax(D[i], 1.0);
+  }
+}
+
+// Partial sums of C_ab and A_a over kTdRows rows per workgroup; grid
+// (ceil(n / kTdRows), chains), 256 threads.  phase: [n][2] (re, im) of
+// exp(-i K.R_x); orb: [n] orbital of each site (< norb <= kTdMaxOrb).
+__global__ __launch_bounds__(256) void k_td_partial(const double* GT0, const double* H, const double* GTT,
+                                                    const double* phase, const int* orb, int n, double* part,
+                                                    size_t cs) {
+  __shared__ double red[4][kTdPart];
+  {
+    const size_t co = (size_t)blockIdx.y * cs;
+    GT0 += co; H += co; GTT += co; part += co;
+  }
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  double acc[kTdPart];
+#pragma unroll
+  for (int k = 0; k < kTdPart; ++k) acc[k] = 0.0;
+  const int x0 = blockIdx.x * kTdRows;
+  for (int dx = 0; dx < kTdRows; ++dx) {
+    const int x = x0 + dx;
+    if (x >= n) break;
+    // row sum over y of conj(p_y) H_xy GT0_xy, split by the orbital of y
+    double rr[kTdMaxOrb], ri[kTdMaxOrb];
+#pragma unroll
+    for (int b = 0; b < kTdMaxOrb; ++b) { rr[b] = 0.0; ri[b] = 0.0; }
+    const double* hx = H + (size_t)x * n;
+    const double* gx = GT0 + (size_t)x * n;
+    for (int y = tid; y < n; y += 256) {
+      const double p = hx[y] * gx[y];
+      const double cr = phase[2 * y], ci = -phase[2 * y + 1];
+      const int ob = orb[y];
+#pragma unroll
+      for (int b = 0; b < kTdMaxOrb; ++b) {
+        const double m = (ob == b) ? p : 0.0;
+        rr[b] += m * cr;
+        ri[b] += m * ci;
+      }
+    }
+    const double pr = phase[2 * x], pi = phase[2 * x + 1];
+    const int oa = orb[x];
+#pragma unroll
+    for (int a = 0; a < kTdMaxOrb; ++a) {
+      const double s = (oa == a) ? 1.0 : 0.0;
+#pragma unroll
+      for (int b = 0; b < kTdMaxOrb; ++b) {
+        acc[2 * (a * kTdMaxOrb + b)] += s * (pr * rr[b] - pi * ri[b]);
+        acc[2 * (a * kTdMaxOrb + b) + 1] += s * (pr * ri[b] + pi * rr[b]);
+      }
+    }
+    if (tid == 0) {
+      const double d = 1.0 - 2.0 * GTT[(size_t)x * n + x];
+#pragma unroll
+      for (int a = 0; a < kTdMaxOrb; ++a) {
+        const double s = (oa == a) ? d : 0.0;
+        acc[2 * kTdMaxOrb * kTdMaxOrb + 2 * a] += s * pr;
+        acc[2 * kTdMaxOrb * kTdMaxOrb + 2 * a + 1] += s * pi;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kTdPart; ++k) {
+    double v = acc[k];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0) red[w][k] = v;
+  }
+  __syncthreads();
+  if (tid < kTdPart) part[(size_t)blockIdx.x * kTdPart + tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+}
+
+// Sums the partial records in a fixed order and forms S_ab(K, tau): writes
+// out[0 .. kTdStride) (entry (a * kTdMaxOrb + b) * 2 + {re, im}) and adds it to
+// bins.  At tau = 0 it first stores A_a(0) in a00 (and counts one pass in
+// *count).  One workgroup of 64 threads per chain.
+__global__ __launch_bounds__(64) void k_td_finish(const double* part, int nblk, double inv_cells, double* a00,
+                                                  double* out, double* bins, double* count, int first, size_t cs) {
+  __shared__ double tot[kTdPart];
+  {
+    const size_t co = (size_t)blockIdx.y * cs;
+    part += co; a00 += co; out += co; bins += co; count += co;
+  }
+  const int tid = threadIdx.x;
+  if (tid < kTdPart) {
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * kTdPart + tid];
+    tot[tid] = s;
+  }
+  __syncthreads();
+  const double* A = tot + 2 * kTdMaxOrb * kTdMaxOrb;
+  if (first && tid < 2 * kTdMaxOrb) a00[tid] = A[tid];
+  if (first && tid == 0) count[0] += 1.0;
+  const double* A0 = first ? A : a00;   // a00 of an earlier launch when tau > 0
+  if (tid < kTdMaxOrb * kTdMaxOrb) {
+    const int a = tid / kTdMaxOrb, b = tid % kTdMaxOrb;
+    const double ar = A[2 * a], ai = A[2 * a + 1];
+    const double br = A0[2 * b], bi = -A0[2 * b + 1];   // conj(A_b(0))
+    const double dr = ar * br - ai * bi, di = ar * bi + ai * br;
+    const double sr = (0.25 * dr - 0.5 * tot[2 * tid]) * inv_cells;
+    const double si = (0.25 * di - 0.5 * tot[2 * tid + 1]) * inv_cells;
+    out[2 * tid] = sr;
+    out[2 * tid + 1] = si;
+    bins[2 * tid] += sr;
+    bins[2 * tid + 1] += si;
+  }
+}

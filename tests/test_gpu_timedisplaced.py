@@ -1,0 +1,81 @@
+"""Parity of the time-displaced pass with the oracle: S^z-S^z at K = (4 pi/3, 0)
+for every tau against the oracle's from-scratch GT0 / G0T / GTT, both Trotter
+splits, a ragged size, the 18x18 honeycomb shape at sampled tau, bins over
+sweeps, and the chain left untouched."""
+import numpy as np
+import pytest
+
+from gpu_util import maxabs, pair
+from oracle import hubbard as ohub
+from oracle import sweep as osweep
+from oracle import timedisplaced as otd
+
+pytestmark = pytest.mark.gpu
+
+KVEC = np.array([4.0 * np.pi / 3.0, 0.0])
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def _setup(kind, L1, L2, U, beta, n_wrap, trotter, seed):
+    om, ch, lat = pair(kind, L1, L2, U, beta, 0.1, n_wrap, trotter=trotter, seed=seed)
+    ph = np.exp(-1j * (lat.cell_pos[lat.cell_of] @ KVEC))
+    ch.td_setup(lat.orb_of, ph, lat.n_cells)
+    ch.random_field()
+    f0, _ = ch.get_state()
+    ch.init()
+    return om, ch, lat, f0
+
+
+@pytest.mark.parametrize("kind,L1,L2,beta,n_wrap,trotter", [
+    ("honeycomb", 3, 3, 2.0, 5, "asym"),
+    ("honeycomb", 3, 3, 2.0, 5, "sym"),
+    ("honeycomb", 5, 5, 1.6, 4, "asym"),
+    ("square", 6, 6, 1.0, 10, "sym"),
+])
+def test_td_all_tau_matches_oracle(kind, L1, L2, beta, n_wrap, trotter):
+    _log(f"td {kind} {L1}x{L2} beta={beta} n_wrap={n_wrap} {trotter}")
+    om, ch, lat, f0 = _setup(kind, L1, L2, 4.0, beta, n_wrap, trotter, seed=2)
+    S, prec = ch.td_measure()
+    want = otd.tdgf_measure(om, lat, KVEC, f0)
+    assert S.shape == want.shape
+    assert maxabs(S, want) < 1e-9
+    assert max(prec) < 1e-9
+    # the chain is unchanged
+    assert maxabs(ch.G.cpu().numpy(), osweep.Chain(om, f0).init().G) < 1e-10
+
+
+def test_td_bins_over_sweeps_and_trajectory():
+    """Sweeps with the time-displaced pass accumulate the start-of-sweep S and
+    follow the same trajectory as sweeps without it."""
+    _log("td bins over sweeps")
+    om, ch, lat, f0 = _setup("honeycomb", 3, 3, 4.0, 1.0, 5, "asym", seed=3)
+    oc = osweep.Chain(om, f0).init()
+    want = np.zeros((om.L + 1, 2, 2), dtype=complex)
+    for s in range(3):
+        want += otd.tdgf_measure(om, lat, KVEC, oc.field)
+        oc.sweep(measure=True)
+    ch.sweep(3, measure=True, time_displaced=True)
+    sums, count = ch.td_read_bins()
+    assert count == 3
+    assert maxabs(sums, want) < 3e-9
+    f, _ = ch.get_state()
+    assert np.array_equal(f, oc.field)
+    assert maxabs(ch.G.cpu().numpy(), oc.G) < 1e-9
+
+
+def test_td_honeycomb18_sampled_tau():
+    """The 18x18 honeycomb workload (N = 648, U = 5, beta = 20, L = 200,
+    n_wrap = 10): one pass, sampled tau against the oracle."""
+    _log("td honeycomb 18x18")
+    om, ch, lat, f0 = _setup("honeycomb", 18, 18, 5.0, 20.0, 10, "asym", seed=0)
+    S, prec = ch.td_measure()
+    _log(f"precision {prec}")
+    assert max(prec) < 1e-8
+    _, _, G00 = otd.tdgf_scratch(om, f0, 0)
+    for tau in (0, 7, 100, 200):
+        GT0, G0T, GTT = otd.tdgf_scratch(om, f0, tau)
+        want = otd.szsz_k(om, lat, KVEC, GT0, G0T, GTT, G00)
+        assert maxabs(S[tau], want) < 1e-9, tau
