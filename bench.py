@@ -1,6 +1,6 @@
 """Benchmark of the DQMC sweep on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-extras]
 
 A step is one full sweep (upward and downward pass over all L slices with
 wraps, sequential single-flip updates, QR/UDV stabilisation every n_wrap
@@ -16,7 +16,13 @@ Prints one JSON line with
              traffic = HBM bytes per launch from the committed rocprofv3
              FETCH_SIZE / WRITE_SIZE summary (null if the kernel source changed
              since those counters were taken),
-  cpu_baseline  the CPU oracle on one sweep of the same chain.
+  cpu_baseline  the CPU oracle on one sweep of the same chain,
+  config.extras the other workloads of the path, each timed the same way:
+             the 512-chain mixed-size batch (captured sweeps) and the
+             batched-vs-plain sweep rate at N = 64; gradient passes and
+             Langevin steps of 64 Gaussian-field chains (10x10, beta = 4);
+             the time-displaced pass of the 18x18 honeycomb chain (N = 648,
+             U = 5, beta = 20, L = 200) with its MFMA GEMM rate.
 """
 import argparse
 import hashlib
@@ -71,12 +77,106 @@ def cpu_baseline(lat, w, field):
                       "initial field, NumPy/SciPy FP64, %.1f s" % (ch.proposals, ch.accepted, dt)}
 
 
+def _sync_time(torch, fn):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, r
+
+
+def _square_batch(pa, layout, beta, field="ising", U=4.0, dtau=0.1, n_wrap=10):
+    from inputs import square_lattice
+    lam = pa.hubbard_coupling(U, dtau, field)
+    models, Ks = [], []
+    for (seed, L1, L2) in layout:
+        lat = square_lattice(L1, L2)
+        models.append(pa.make_model(lat.n, beta, dtau, n_wrap, lam, U=U, field=field, seed=seed))
+        Ks.append(lat.K)
+    return pa.Batch(models, Ks)
+
+
+def bench_batched(torch, pa):
+    """512 chains (256 x 8x8, 128 x 6x6, 128 x 10x10; U = 4, beta = 8, L = 80):
+    autotuned, one sweep per captured graph.  Batched vs plain at N = 64:
+    256 chains of 8x8 in one batch against one 8x8 chain per launch sequence."""
+    from inputs import batched_chain_layout, square_lattice
+    out = {}
+    lam = pa.hubbard_coupling(4.0, 0.1)
+    lat = square_lattice(8, 8)
+    ch = pa.Chain(pa.make_model(64, 8.0, 0.1, 10, lam, U=4.0, seed=0), lat.K)
+    ch.random_field().init()
+    ch.sweep(1)
+    dt, _ = _sync_time(torch, lambda: ch.sweep(2))
+    plain = 2 / dt
+    ch.close()
+    for name, lay in (("n64x256", [l for l in batched_chain_layout(512) if l[1] == 8]),
+                      ("batch512", list(batched_chain_layout(512)))):
+        b = _square_batch(pa, lay, 8.0)
+        b.random_fields().init()
+        b.autotune(1)
+        b.capture(1, measure=True)
+        b.sweep(1)
+        st0 = b.sweep(0)
+        dt, st = _sync_time(torch, lambda: b.sweep(2))
+        out[name] = {"chains": len(lay), "sweeps_per_s": 2 / dt, "chain_sweeps_per_s": 2 * len(lay) / dt,
+                     "updates_per_s": (st.proposals - st0.proposals) / dt,
+                     "gemm_tiles": sorted({b.tuning(i) for i in range(len(lay))})}
+        b.close()
+    out["plain_n64_sweeps_per_s"] = plain
+    out["batched_vs_plain_n64"] = out["n64x256"]["chain_sweeps_per_s"] / plain
+    return out
+
+
+def bench_gradient(torch, pa):
+    """64 Gaussian-field chains, 10x10 square, U = 4, beta = 4, L = 40: gradient
+    passes and Langevin steps (eps = 1e-3) of the whole batch, and one Monte
+    Carlo step = one local sweep + 10 Langevin steps."""
+    b = _square_batch(pa, [(s, 10, 10) for s in range(64)], 4.0, field="gauss")
+    b.random_fields().init()
+    b.grad_logdet()
+    dtg, _ = _sync_time(torch, lambda: [b.grad_logdet() for _ in range(3)])
+    dtl, _ = _sync_time(torch, lambda: b.langevin(1e-3, 3, first_step=0))
+    dtm, _ = _sync_time(torch, lambda: (b.sweep(1, measure=False), b.langevin(1e-3, 10, first_step=3)))
+    b.close()
+    return {"chains": 64, "gradients_per_s": 3 * 64 / dtg, "gradient_entries_per_s": 3 * 64 * 40 * 100 / dtg,
+            "langevin_steps_per_s": 3 * 64 / dtl, "mc_steps_per_s": 64 / dtm}
+
+
+def bench_time_displaced(torch, pa):
+    """Honeycomb 18x18 (N = 648), U = 5, beta = 20, L = 200, n_wrap = 10: one
+    time-displaced pass (S^z-S^z at K = (4 pi / 3, 0) for all tau) and one
+    sweep with it."""
+    import numpy as np
+    from inputs import WORKLOADS
+    w = WORKLOADS["honeycomb18_U5_b20"]
+    lat = w.lattice()
+    lam = pa.hubbard_coupling(w.U, w.dtau)
+    ch = pa.Chain(pa.make_model(lat.n, w.beta, w.dtau, w.n_wrap, lam, U=w.U, trotter=w.trotter, seed=w.seed), lat.K)
+    ph = np.exp(-1j * (lat.cell_pos[lat.cell_of] @ np.array([4.0 * np.pi / 3.0, 0.0])))
+    ch.td_setup(lat.orb_of, ph, lat.n_cells)
+    ch.random_field().init()
+    ch.td_measure()
+    dt, (S, prec) = _sync_time(torch, ch.td_measure)
+    ch.timing("gemm", True)
+    ch.td_measure()
+    ms, launches, flops = ch.timing_read()
+    ch.timing("gemm", False)
+    dts, st = _sync_time(torch, lambda: ch.sweep(1, measure=True, time_displaced=True))
+    ch.close()
+    tf = flops / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+    return {"N": lat.n, "L": w.n_slices, "td_pass_s": dt, "td_prec": list(prec),
+            "gemm_tflops": tf, "gemm_frac_of_fp64_mfma_peak": tf / 78.6, "gemm_share_of_pass": ms * 1e-3 / dt,
+            "sweep_with_td_s": dts, "updates_per_s": st.proposals / dts}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the sweep of one chain does not shard across GPUs "
@@ -107,7 +207,10 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     k_ms, k_launches, _ = ch.timing_read()
-    ch.timing("block_update", False)
+    ch.timing("gemm", True)
+    ch.sweep(1, measure=True)
+    g_ms, g_launches, g_flops = ch.timing_read()
+    ch.timing("gemm", False)
     dt = t1 - t0
     proposals = st.proposals - st0.proposals
     accepted = st.accepted - st0.accepted
@@ -137,9 +240,15 @@ def main():
                    "sweeps_per_s": args.steps / dt,
                    "accepted_updates_per_s": accepted / dt,
                    "acceptance": accepted / max(1, proposals),
-                   "prec_mean": st.prec_mean, "prec_max": st.prec_max},
+                   "prec_mean": st.prec_mean, "prec_max": st.prec_max,
+                   "gemm_tflops": g_flops / (g_ms * 1e-3) / 1e12 if g_ms > 0 else 0.0,
+                   "gemm_share_of_sweep": g_ms * 1e-3 / (dt / args.steps)},
         "roofline": roofline,
     }
+    ch.close()
+    if not args.no_extras:
+        out["config"]["extras"] = {"batched": bench_batched(torch, pa), "gradient": bench_gradient(torch, pa),
+                                   "time_displaced": bench_time_displaced(torch, pa)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(lat, w, field0)
     print(json.dumps(out))

@@ -304,7 +304,10 @@ dqmc_status update_slice(dqmc_ctx* c, int tau, int dir) {
     a.counters = c->counters;
     a.cs = c->cs;
     if (dqmc_status s = timing_begin(c, DQMC_KERNEL_BLOCK_UPDATE)) return s;
-    hipLaunchKernelGGL(k_block_update, gridc(c, tiles), dim3(256), 0, c->stream, a);
+    if (c->m.n_col == 2)
+      hipLaunchKernelGGL(k_block_update<2>, gridc(c, tiles), dim3(256), 0, c->stream, a);
+    else
+      hipLaunchKernelGGL(k_block_update<1>, gridc(c, tiles), dim3(256), 0, c->stream, a);
     HIPCHK(hipGetLastError());
     if (dqmc_status s = timing_end(c, DQMC_KERNEL_BLOCK_UPDATE)) return s;
     c->Gcur = a.Gout;

@@ -40,93 +40,159 @@ __device__ __forceinline__ double ipow(double r, int n) {
   return p;
 }
 
-// One workgroup per 32 x 32 tile (I, J) of G.  Every workgroup runs the same
-// sequential decisions of block S on G[S,S] (identical arithmetic, identical
-// results), then writes
-//   Gout[I,J] = Gin[I,J] - Gin[I,S] Phi (E_S^T[:,J] - Gin[S,J]).
+// Both halves of a double read from one lane (uniform lane index).
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// One workgroup per 32 x 32 tile (I, J) of G.  Every workgroup takes the same
+// sequential decisions of block S (identical arithmetic, identical results),
+// then writes Gout[I,J] = Gin[I,J] - Gin[I,S] Phi (E_S^T[:,J] - Gin[S,J]).
+//
+// Decisions (wave 0 alone, no workgroup barrier): lane x keeps row x of the
+// current c = G_cur[S,S] in registers and the draws of site x.  Site i reads
+// c_ii from lane i; an accepted flip updates only the trailing block,
+//   c[x][y] += gamma c[x][i] c[i][y]   (x, y > i; row i broadcast by readlane),
+// since later decisions read only entries past i.  Row i and column i are
+// therefore frozen after site i, and the final c holds the records
+//   T_A[i][k] = gamma_i V_i[k] = -gamma_i c[i][k],
+//   T_B[i][k] = -gamma_i U_i[k] = -gamma_i c[k][i]        (k > i).
+//
+// With the vectors of the Phi recursion in the header, U_i = c a_i and
+// V_i = (1 - c_0)^T b_i, so the recursions for a and b become triangular:
+//   A (1 + T_A) = 1,  B (1 + T_B) = 1,  Phi = A diag(gamma) B^T,
+// solved row by row by the 64 lanes of wave 0 (A on lanes 0-31, B on 32-63).
 // Workgroup 0 also writes the block's field values and the counters.
+template <int NCOL>
 __global__ __launch_bounds__(256) void k_block_update(BlockArgs a) {
-  __shared__ double g[32][33], c[32][33], Ph[32][33], GIS[32][33], GSJ[32][33], Wt[32][33];
-  __shared__ double dlt[32], pre[32], snew[32], sold[32], uu[32], av[32], bv[32], colj[32], rowj[32];
-  __shared__ int accf[32];
+  constexpr int TS = 34;   // row stride of the records (16-byte aligned rows)
+  __shared__ double GIS[32][33], GSJ[32][33], Ph[32][33], Wt[32][33], AB[2][32][33];
+  __shared__ __attribute__((aligned(16))) double Tt[2][32][TS];   // Tt[0][k][m] = T_A[m][k], Tt[1][k][m] = T_B[m][k]
+  __shared__ double gam[32];
+  __shared__ int accf[32], nacc_s;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int bb = a.bb, s0 = a.s0, N = a.N;
   const int tilesN = (N + 31) >> 5;
   if (a.cs) {
     const size_t co = (size_t)blockIdx.y * a.cs;
     a.Gin += co; a.Gout += co; a.field_in += co; a.field_out += co;
-    a.sweep_ctr = reinterpret_cast<const unsigned long long*>(reinterpret_cast<const double*>(a.sweep_ctr) + co);
     a.counters = reinterpret_cast<unsigned long long*>(reinterpret_cast<double*>(a.counters) + co);
   }
   const int I0 = (blockIdx.x / tilesN) << 5, J0 = (blockIdx.x % tilesN) << 5;
-  for (int e = tid; e < 1024; e += 256) {
-    const int x = e >> 5, y = e & 31;
-    const double v = (x < bb && y < bb) ? a.Gin[(size_t)(s0 + x) * N + s0 + y] : 0.0;
-    g[x][y] = v;
-    c[x][y] = v;
-    Ph[x][y] = 0.0;
-    GIS[x][y] = (I0 + x < N && y < bb) ? a.Gin[(size_t)(I0 + x) * N + s0 + y] : 0.0;
-    GSJ[x][y] = (x < bb && J0 + y < N) ? a.Gin[(size_t)(s0 + x) * N + J0 + y] : 0.0;
+  const int wr = w >> 1, wc = w & 1;
+  // this thread's four output elements of Gin, fetched early
+  const int col = J0 + wc * 16 + (lane & 15);
+  double gin[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = I0 + wr * 16 + (lane >> 4) + 4 * r;
+    gin[r] = (row < N && col < N) ? a.Gin[(size_t)row * N + col] : 0.0;
   }
-  if (tid < 32) {
-    accf[tid] = 0;
-    if (tid < bb) {
-      const Philox4 r = philox4x64_10(TAG_FLIP, a.counters[2], a.slot, (unsigned long long)(s0 + tid), a.counters[3],
+  if (w == 0) {
+    const int x = lane & 31;
+    double c[32];
+#pragma unroll
+    for (int y = 0; y < 32; ++y) c[y] = (x < bb && y < bb) ? a.Gin[(size_t)(s0 + x) * N + s0 + y] : 0.0;
+    // draws and ratio constants of site x
+    double u = 2.0, dl = 0.0, pr = 0.0, sold = 0.0, snew = 0.0;
+    if (x < bb) {
+      const Philox4 r = philox4x64_10(TAG_FLIP, a.counters[2], a.slot, (unsigned long long)(s0 + x), a.counters[3],
                                       0ull);
       const double u0 = unit_double(r.w[0]), u1 = unit_double(r.w[1]);
-      const double s = a.field_in[s0 + tid];
-      double sn, extra;
-      if (a.gauss) { sn = s + a.prop_width * (2.0 * u1 - 1.0); extra = -0.5 * (sn * sn - s * s); }
-      else { sn = -s; extra = 0.0; }
-      uu[tid] = u0;
-      sold[tid] = s;
-      snew[tid] = sn;
-      dlt[tid] = exp(a.coupling * (sn - s)) - 1.0;
-      pre[tid] = exp(a.n_col * a.coupling * a.alpha * (sn - s) + extra);
+      sold = a.field_in[s0 + x];
+      double extra;
+      if (a.gauss) { snew = sold + a.prop_width * (2.0 * u1 - 1.0); extra = -0.5 * (snew * snew - sold * sold); }
+      else { snew = -sold; extra = 0.0; }
+      u = u0;
+      dl = exp(a.coupling * (snew - sold)) - 1.0;
+      pr = exp(NCOL * a.coupling * a.alpha * (snew - sold) + extra);
+    }
+    int nacc = 0, myacc = 0;
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+      if (i < bb) {
+        const double cii = readlane_d(c[i], i);
+        const double dli = readlane_d(dl, i);
+        const double r = 1.0 + dli * (1.0 - cii);
+        const double R = readlane_d(pr, i) * (NCOL == 2 ? r * r : r);
+        double gi = 0.0;
+        if (readlane_d(u, i) < R) {            // uniform across the wave
+          gi = dli / r;
+          ++nacc;
+          if (lane == i) myacc = 1;
+          if (x > i) {
+            const double f = gi * c[i];
+#pragma unroll
+            for (int y = i + 1; y < 32; ++y) c[y] = fma(f, readlane_d(c[y], i), c[y]);
+          }
+        }
+        if (lane == 0) gam[i] = gi;
+      } else if (lane == 0) {
+        gam[i] = 0.0;
+      }
+    }
+    if (lane < 32) accf[lane] = myacc;
+    if (lane == 0) nacc_s = nacc;
+    // records: upper part of row x scaled by -gamma_x, lower part (column
+    // entries c[x][m], m < x) by -gamma_m
+    const double gx = gam[x];
+#pragma unroll
+    for (int y = 0; y < 32; ++y) {
+      const double v = (y > x) ? -gx * c[y] : ((y < x) ? -gam[y] * c[y] : 0.0);
+      if (lane < 32) {
+        Tt[1][x][y] = v;          // row x of c: T_B[y][x] for y < x
+        Tt[0][y][x] = v;          // column view: T_A[x][y] for y > x
+      }
+    }
+    if (blockIdx.x == 0 && lane < bb) a.field_out[s0 + lane] = myacc ? snew : sold;
+  } else {
+    for (int e = tid - 64; e < 1024; e += 192) {
+      const int x = e >> 5, y = e & 31;
+      GIS[x][y] = (I0 + x < N && y < bb) ? a.Gin[(size_t)(I0 + x) * N + s0 + y] : 0.0;
+      GSJ[x][y] = (x < bb && J0 + y < N) ? a.Gin[(size_t)(s0 + x) * N + J0 + y] : 0.0;
     }
   }
   __syncthreads();
-  int nacc = 0;
-  for (int j = 0; j < bb; ++j) {
-    const double r = 1.0 + dlt[j] * (1.0 - c[j][j]);
-    const double R = pre[j] * ipow(r, a.n_col);
-    if (!(uu[j] < R)) continue;          // uniform across the workgroup
-    const double gam = dlt[j] / r;
-    {
-      // a = e_j - Phi (e_j - g[:,j]),  b = e_j + Phi^T g[j,:]^T: thread (x, q)
-      // sums 4 of the 32 terms, 8 threads per x reduce by shuffles
-      const int x = tid >> 3, q = tid & 7;
-      double pa = 0.0, pb = 0.0;
+  if (w == 0) {
+    // row x of A (lanes 0-31) or of B (lanes 32-63): R[k] = delta_xk - sum_{m<k} T[m][k] R[m]
+    const int x = lane & 31, h = lane >> 5;
+    double R[32];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int y = 4 * q + k;
-        pa += Ph[x][y] * ((y == j ? 1.0 : 0.0) - g[y][j]);
-        pb += Ph[y][x] * g[j][y];
-      }
-      pa += __shfl_xor(pa, 1, 64); pb += __shfl_xor(pb, 1, 64);
-      pa += __shfl_xor(pa, 2, 64); pb += __shfl_xor(pb, 2, 64);
-      pa += __shfl_xor(pa, 4, 64); pb += __shfl_xor(pb, 4, 64);
-      if (q == 0) {
-        av[x] = (x == j ? 1.0 : 0.0) - pa;
-        bv[x] = (x == j ? 1.0 : 0.0) + pb;
-        colj[x] = c[x][j];
-        rowj[x] = (x == j ? 1.0 : 0.0) - c[j][x];
-      }
-    }
-    __syncthreads();
+    for (int k = 0; k < 32; ++k) {
+      double v0 = (x == k) ? 1.0 : 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int e = tid + 256 * k;
-      const int x = e >> 5, y = e & 31;
-      Ph[x][y] += gam * av[x] * bv[y];
-      c[x][y] -= gam * colj[x] * rowj[y];
+      for (int m = 0; m + 3 < k; m += 4) {
+        v0 = fma(-Tt[h][k][m], R[m], v0);
+        v1 = fma(-Tt[h][k][m + 1], R[m + 1], v1);
+        v2 = fma(-Tt[h][k][m + 2], R[m + 2], v2);
+        v3 = fma(-Tt[h][k][m + 3], R[m + 3], v3);
+      }
+#pragma unroll
+      for (int m = k & ~3; m < k; ++m) v0 = fma(-Tt[h][k][m], R[m], v0);
+      R[k] = (v0 + v1) + (v2 + v3);
     }
-    if (tid == 0) accf[j] = 1;
-    ++nacc;
-    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 32; ++k) AB[h][x][k] = R[k];
   }
+  __syncthreads();
+  {
+    // Phi = A diag(gamma) B^T  (32 x 32 x 32 on MFMA)
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k0 = 0; k0 < 32; k0 += 4) {
+      const int k = k0 + (lane >> 4);
+      const double av_ = AB[0][wr * 16 + (lane & 15)][k] * gam[k];
+      const double bv_ = AB[1][wc * 16 + (lane & 15)][k];
+      acc = mfma_f64_16x16x4(av_, bv_, acc);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Ph[wr * 16 + (lane >> 4) + 4 * r][wc * 16 + (lane & 15)] = acc[r];
+  }
+  __syncthreads();
   // W tile = Phi (E_S^T[:, J] - G[S, J])  (32 x 32 x 32 on MFMA)
-  const int wr = w >> 1, wc = w & 1;
   v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int k0 = 0; k0 < 32; k0 += 4) {
@@ -145,20 +211,16 @@ __global__ __launch_bounds__(256) void k_block_update(BlockArgs a) {
     const double bw = Wt[k0 + (lane >> 4)][wc * 16 + (lane & 15)];
     acc2 = mfma_f64_16x16x4(av_, bw, acc2);
   }
-  const int col = J0 + wc * 16 + (lane & 15);
   if (col < N) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = I0 + wr * 16 + (lane >> 4) + 4 * r;
-      if (row < N) a.Gout[(size_t)row * N + col] = a.Gin[(size_t)row * N + col] - acc2[r];
+      if (row < N) a.Gout[(size_t)row * N + col] = gin[r] - acc2[r];
     }
   }
-  if (blockIdx.x == 0) {
-    if (tid < bb) a.field_out[s0 + tid] = accf[tid] ? snew[tid] : sold[tid];
-    if (tid == 0) {
-      atomicAdd(&a.counters[0], (unsigned long long)bb);
-      atomicAdd(&a.counters[1], (unsigned long long)nacc);
-    }
+  if (blockIdx.x == 0 && tid == 0) {
+    atomicAdd(&a.counters[0], (unsigned long long)bb);
+    atomicAdd(&a.counters[1], (unsigned long long)nacc_s);
   }
 }
 
