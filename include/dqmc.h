@@ -138,6 +138,15 @@ dqmc_status dqmc_reset_bins(dqmc_ctx* ctx);
  * same stabilised products as the sweep.  Does not change the chain. */
 dqmc_status dqmc_green_scratch(dqmc_ctx* ctx, int32_t tau, double* G_dev);
 
+/* Test hook: the weight ratio R of changing the field of `site` on slice tau
+ * (1..L) to s_new, with everything else fixed (section "Updating schemes";
+ * Eq. (Green_eq) and the matrix determinant lemma): with Delta =
+ * exp(coupling (s_new - s)) - 1 and G(tau) recomputed from scratch,
+ *   r = 1 + Delta (1 - G(tau)_ii),
+ *   R = exp(n_col coupling alpha (s_new - s)) r^n_col  (x exp(-(s_new^2 - s^2)/2) Gaussian).
+ * R: one host double.  Single chains; s_new must be +-1 for an Ising field. */
+dqmc_status dqmc_ratio(dqmc_ctx* ctx, int32_t tau, int32_t site, double s_new, double* R);
+
 /* log|det(1 + B(beta,0))| of the current field from scratch. */
 dqmc_status dqmc_logdet(dqmc_ctx* ctx, double* logdet);
 
@@ -225,9 +234,10 @@ dqmc_status dqmc_batch_set_state(dqmc_batch* b, int32_t chain, const double* fie
 dqmc_status dqmc_batch_get_state(dqmc_batch* b, int32_t chain, double* field_host, uint64_t* sweep_counter);
 /* Storage fill and G(0) of every chain. */
 dqmc_status dqmc_batch_init(dqmc_batch* b);
-/* Autotuner: per group, times `trials` sweeps with 16 x 16 and 32 x 32 MFMA
- * GEMM tiles and keeps the faster (the trial sweeps advance the chains like
- * warm-up sweeps; a captured graph is dropped). */
+/* Autotuner: per group, times `trials` sweeps with each GEMM kernel (16 x 16
+ * and 32 x 32 direct MFMA tiles, 64 x 64 LDS-staged tiles) and keeps the
+ * fastest (the trial sweeps advance the chains like warm-up sweeps; a
+ * captured graph is dropped). */
 dqmc_status dqmc_batch_autotune(dqmc_batch* b, int32_t trials);
 /* The GEMM tile chosen for a chain's group (0 = size-based default). */
 dqmc_status dqmc_batch_tuning(const dqmc_batch* b, int32_t chain, int32_t* gemm_tile);

@@ -157,3 +157,11 @@ def log_weight(model, field) -> float:
     N_col log|det(1 + B'(beta,0))| (the determinant power is real and
     non-negative in the sampling frame, so the sign is one)."""
     return model.prefactor_log(field) + model.n_col * logdet_scratch(model, field)
+
+
+def weight_ratio(model, field, tau: int, i: int, s_new: float) -> float:
+    """W(C') / W(C) for the field of site i on slice tau changed to s_new, from
+    the two weights (Eq. (partition_2)) evaluated from scratch."""
+    f2 = np.array(field, dtype=np.float64)
+    f2[tau - 1, i] = s_new
+    return float(np.exp(log_weight(model, f2) - log_weight(model, field)))

@@ -96,6 +96,11 @@ class Chain:
         self._chk(self.lib.dqmc_green_scratch(self.ctx, tau, ctypes.c_void_p(out.data_ptr())))
         return out
 
+    def ratio(self, tau: int, site: int, s_new: float) -> float:
+        out = ctypes.c_double()
+        self._chk(self.lib.dqmc_ratio(self.ctx, tau, site, s_new, ctypes.byref(out)))
+        return out.value
+
     def logdet(self) -> float:
         out = ctypes.c_double()
         self._chk(self.lib.dqmc_logdet(self.ctx, ctypes.byref(out)))

@@ -61,6 +61,7 @@ struct dqmc_ctx {
   int *piv = nullptr, *ipiv = nullptr;
   double *bins = nullptr, *prec_hist = nullptr, *prec_tot = nullptr, *logdet = nullptr;
   double *grad = nullptr, *gprec = nullptr;   // gradient rows [L][N] and the gradient pass's precision
+  double* mpart = nullptr;                     // partial sums of the equal-time estimators
   // time-displaced pass: GT0 and H = G0T^T (two buffers each), the 2N-column
   // right-hand sides of the re-anchoring solve, S(K, tau) of the current
   // configuration and its bin sums, partial records, A_a(0); the momentum
@@ -153,6 +154,7 @@ size_t layout_chain(dqmc_ctx* c, double* base) {
   P(c->logdet, 4);
   P(c->grad, (size_t)c->L * N);
   P(c->gprec, 4);
+  P(c->mpart, 4 * (size_t)((N + kMeasRows - 1) / kMeasRows));
   for (int i = 0; i < 4; ++i) P(c->TD[i], NN);
   P(c->RHS2, 2 * NN);
   P(c->tdS, (size_t)(c->L + 1) * kTdStride);
@@ -368,6 +370,7 @@ dqmc_status set_lds_limits(dqmc_ctx* c) {
   HIPCHK(lds_limit_qr<8>());
   HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(k_lu_panel), hipFuncAttributeMaxDynamicSharedMemorySize,
                              156 * 1024));
+  HIPCHK(gemm64_set_lds());
   return DQMC_OK;
 }
 
@@ -451,7 +454,7 @@ dqmc_status left_step(dqmc_ctx* c, UDVp in, int lo, int hi, UDVp out) {
 dqmc_status lu_solve(dqmc_ctx* c, double* X, double* RHS, int nrhs, int ldb, double* logdet) {
   const int N = c->N, nb = c->nb;
   for (int j0 = 0; j0 < N; j0 += nb) {
-    const int nbw = std::min(nb, N - j0), h = N - j0;
+    const int nbw = std::min(nb, N - j0);
     if (dqmc_status s = launch_lu_panel(c, X, j0, nbw)) return s;
     hipLaunchKernelGGL(k_lu_swap, gridc(c, grid1((size_t)(N - nbw) + nrhs)), dim3(256), 0, c->stream, X, N, j0, nbw,
                        c->ipiv, RHS, nrhs, ldb, c->cs);
@@ -555,8 +558,15 @@ dqmc_status measure(dqmc_ctx* c) {
     if (dqmc_status s = gemm(c, gemm_args(N, N, N, c->Eh, N, 0, c->Gcur, N, 0, c->T1, N))) return s;
     T1 = c->T1;
   }
-  hipLaunchKernelGGL(k_measure, gridc(c, 1), dim3(1024), 0, c->stream, c->Gcur, T1, c->Ehinv, c->Kd, N, c->trK,
-                     (double)c->m.n_col, c->m.u_int, c->bins, c->err_flag, c->cs);
+  const bool one = N <= kMeasSmallN;
+  const int rows = one ? N : kMeasRows;
+  const int nblk = (N + rows - 1) / rows;
+  hipLaunchKernelGGL(k_measure_part, gridc(c, (unsigned)nblk), dim3(256), 0, c->stream, c->Gcur, T1, c->Ehinv, c->Kd,
+                     N, rows, c->mpart, one ? 1 : 0, c->trK, (double)c->m.n_col, c->m.u_int, c->bins, c->err_flag,
+                     c->cs);
+  if (!one)
+    hipLaunchKernelGGL(k_measure_finish, gridc(c, 1), dim3(64), 0, c->stream, c->mpart, nblk, N, c->trK,
+                       (double)c->m.n_col, c->m.u_int, c->bins, c->err_flag, c->cs);
   HIPCHK(hipGetLastError());
   return DQMC_OK;
 }
@@ -1088,6 +1098,23 @@ dqmc_status dqmc_green_scratch(dqmc_ctx* c, int32_t tau, double* G_dev) {
   return read_flag(c);
 }
 
+dqmc_status dqmc_ratio(dqmc_ctx* c, int32_t tau, int32_t site, double s_new, double* R) {
+  if (!c || !R || tau < 1 || site < 0 || !std::isfinite(s_new)) return fail(c, DQMC_E_ARG, "bad arguments");
+  if (!c->bound) return fail(c, DQMC_E_STATE, "not bound");
+  if (c->nch != 1) return fail(c, DQMC_E_UNSUPPORTED, "single chains only");
+  if (tau > c->L || site >= c->N) return fail(c, DQMC_E_ARG, "tau or site out of range");
+  if (c->m.field == DQMC_FIELD_ISING && s_new != 1.0 && s_new != -1.0)
+    return fail(c, DQMC_E_ARG, "Ising field values are +-1");
+  if (dqmc_status s = dqmc_green_scratch(c, tau, c->Gs)) return s;
+  hipLaunchKernelGGL(k_ratio, dim3(1), dim3(64), 0, c->stream, c->Gs, c->N, site,
+                     c->field + (size_t)(tau - 1) * c->N, s_new, c->m.coupling, c->m.alpha, c->m.n_col,
+                     c->m.field == DQMC_FIELD_GAUSS ? 1 : 0, c->logdet + 1);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(R, c->logdet + 1, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return DQMC_OK;
+}
+
 dqmc_status dqmc_logdet(dqmc_ctx* c, double* logdet) {
   if (!c || !logdet) return DQMC_E_ARG;
   if (!c->bound) return fail(c, DQMC_E_STATE, "not bound");
@@ -1316,6 +1343,7 @@ bool layout_ok(const dqmc_ctx* c, const double* lo, const double* hi) {
   ok = ok && in(c->field_alt, (size_t)c->L * N, true) && in(c->norms, N, true) && in(c->piv, N / 2 + 1, true) &&
        in(c->ipiv, N / 2 + 1, true) && in(c->bins, 4, true) && in(c->prec_hist, 2 * (size_t)c->nk + 2, true) &&
        in(c->prec_tot, 4, true) && in(c->logdet, 4, true) && in(c->grad, (size_t)c->L * N, true) && in(c->gprec, 4, true) &&
+       in(c->mpart, 4 * (size_t)((N + kMeasRows - 1) / kMeasRows), true) &&
        in(c->TD[0], NN, true) && in(c->TD[1], NN, true) && in(c->TD[2], NN, true) && in(c->TD[3], NN, true) &&
        in(c->RHS2, 2 * NN, true) && in(c->tdS, (size_t)(c->L + 1) * kTdStride, true) &&
        in(c->tdbins, (size_t)(c->L + 1) * kTdStride + 4, true) &&
@@ -1510,7 +1538,8 @@ dqmc_status dqmc_batch_capture(dqmc_batch* b, int32_t sweeps_per_graph, int32_t 
 }
 
 // Autotuner: for every group, `trials` sweeps are timed (HIP events) with
-// 16 x 16 and with 32 x 32 GEMM tiles, and the faster tile is kept.  The
+// each GEMM kernel (16 x 16 and 32 x 32 direct tiles, 64 x 64 LDS-staged) and
+// the fastest is kept.  The
 // trial sweeps advance the chains like warm-up sweeps; a captured graph is
 // dropped (it would replay the old tiles).
 dqmc_status dqmc_batch_autotune(dqmc_batch* b, int32_t trials) {
@@ -1522,7 +1551,7 @@ dqmc_status dqmc_batch_autotune(dqmc_batch* b, int32_t trials) {
   hipEvent_t e0, e1;
   BHIPCHK_(hipEventCreate(&e0));
   BHIPCHK_(hipEventCreate(&e1));
-  const int cands[2] = {16, 32};
+  const int cands[3] = {16, 32, 64};
   for (dqmc_ctx* c : b->groups) {
     float best = 0.0f;
     int pick = 0;

@@ -34,7 +34,7 @@ struct GemmArgs {
 };
 enum { PC_A = 1, PC_B = 2, PC_C = 4, PC_RS = 8, PC_CS = 16, PC_KS = 32 };
 
-template <int TILE>
+template <int TILE, int UNR>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   constexpr int NB = TILE / 16;
   if (g.cstride) {
@@ -59,29 +59,45 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   for (int a = 0; a < NB; ++a)
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
-  for (int k0 = kb; k0 < ke; k0 += 4) {
-    const int k = k0 + lk;
-    const bool kin = k < ke;
-    const double ksc = (kin && g.ks_mode) ? scale_of(g.ks_mode, g.ks, g.ks_coef, k) : 1.0;
-    double av[NB], bv[NB];
+  // K in chunks of UNR steps of 4: all loads of a chunk are issued before its
+  // MFMAs, so their latencies overlap (UNR = 1 keeps the register count low
+  // for launches whose many workgroups already hide the latency)
+  for (int kc = kb; kc < ke; kc += 4 * UNR) {
+    double av[UNR][NB], bv[UNR][NB];
+    // unconditional loads from clamped addresses, masked afterwards, so the
+    // loads of the chunk issue back to back
 #pragma unroll
-    for (int a = 0; a < NB; ++a) {
-      const int row = i0 + a * 16 + l16;
-      double v = 0.0;
-      if (kin && row < g.M) v = g.transA ? g.A[(size_t)k * g.lda + row] : g.A[(size_t)row * g.lda + k];
-      av[a] = v * ksc;
+    for (int u = 0; u < UNR; ++u) {
+      const int k = kc + 4 * u + lk, kk = min(k, g.K - 1);
+#pragma unroll
+      for (int a = 0; a < NB; ++a) {
+        const int row = min(i0 + a * 16 + l16, g.M - 1);
+        av[u][a] = g.transA ? g.A[(size_t)kk * g.lda + row] : g.A[(size_t)row * g.lda + kk];
+      }
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int col = min(j0 + b * 16 + l16, g.N - 1);
+        bv[u][b] = g.transB ? g.B[(size_t)col * g.ldb + kk] : g.B[(size_t)kk * g.ldb + col];
+      }
     }
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const int col = j0 + b * 16 + l16;
-      double v = 0.0;
-      if (kin && col < g.N) v = g.transB ? g.B[(size_t)col * g.ldb + k] : g.B[(size_t)k * g.ldb + col];
-      bv[b] = v;
+    for (int u = 0; u < UNR; ++u) {
+      const int k = kc + 4 * u + lk;
+      const bool kin = k < ke;
+      const double ksc = (kin && g.ks_mode) ? scale_of(g.ks_mode, g.ks, g.ks_coef, k) : 1.0;
+#pragma unroll
+      for (int a = 0; a < NB; ++a) av[u][a] = (kin && i0 + a * 16 + l16 < g.M) ? av[u][a] * ksc : 0.0;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) bv[u][b] = (kin && j0 + b * 16 + l16 < g.N) ? bv[u][b] : 0.0;
     }
 #pragma unroll
-    for (int a = 0; a < NB; ++a)
+    for (int u = 0; u < UNR; ++u) {
+      if (kc + 4 * u >= ke) break;   // uniform: short K ranges skip the empty steps
 #pragma unroll
-      for (int b = 0; b < NB; ++b) acc[a][b] = mfma_f64_16x16x4(av[a], bv[b], acc[a][b]);
+      for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[a][b] = mfma_f64_16x16x4(av[u][a], bv[u][b], acc[a][b]);
+    }
   }
   if (w > 0) {
 #pragma unroll
@@ -116,6 +132,183 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
     }
 }
 
+// Large products: a 64 x 64 tile per workgroup, K in steps of 32 staged
+// through LDS with double buffering (the loads of step t+1 are in flight while
+// the four waves run the MFMAs of step t).  Wave (wr, wc) owns the 32 x 32
+// quarter (wr, wc) and computes it with v_mfma_f64_4x4x4f64, which on gfx950
+// runs at twice the FP64 rate of the 16 x 16 x 4 form.  Its lane layout (4
+// blocks b of 4 x 4, checked on gfx950 with an in-bounds probe):
+//   A(m, k) of block b in lane m + 4b + 16k,  B(k, n) in lane n + 4b + 16k,
+//   D(m, n) in lane n + 4b + 16m,
+// so with the same A in all four blocks one instruction yields the 4 x 16
+// strip D[m0 + l/16][n0 + l%16] from A[m0 + l%4][k + l/16] and
+// B[k + l/16][n0 + l%16]: 8 x 2 strips per wave and 4-step of K.
+// LDS layouts are chosen per transpose so that both the coalesced stores and
+// the operand reads are free of (or at worst two-way) bank conflicts.
+// Tiles are placed XCD-aware: workgroups are dealt round-robin to the eight
+// XCDs, so consecutive logical tiles (sharing rows of A) go to workgroups on
+// the same XCD and its L2 keeps those rows.  Same operand conventions,
+// scalings and batching as k_gemm.  Dynamic LDS: gemm64_lds().
+constexpr int kG64 = 64, kGBK = 32, kGXcd = 8;
+// strides (doubles) and sizes of the four layouts
+constexpr int kSA = kGBK + 4;    // A row-major [i][k]
+constexpr int kSAt = kG64 + 8;   // A^T        [k][i]
+constexpr int kSB = kG64 + 16;   // B row-major [k][j]
+constexpr int kSBt = kGBK + 4;   // B^T        [j][k]
+constexpr int kGAsz = (kG64 * kSA > kGBK * kSAt) ? kG64 * kSA : kGBK * kSAt;
+constexpr int kGBsz = (kGBK * kSB > kG64 * kSBt) ? kGBK * kSB : kG64 * kSBt;
+__host__ __device__ inline size_t gemm64_lds() { return sizeof(double) * 2 * (kGAsz + kGBsz); }
+template <int TA, int TB>
+__global__ void k_gemm64(GemmArgs g, int ntiles);
+
+// Unconditional loads from clamped addresses (so all sixteen issue back to
+// back), masked and scaled afterwards.
+template <int TA, int TB>
+__device__ __forceinline__ void gemm64_load(const GemmArgs& g, int m0, int n0, int k0, double (&ra)[8],
+                                            double (&rb)[8]) {
+  const int t = threadIdx.x;
+  if (!TA) {          // A[row][k]: 32 k contiguous per row, 8 rows per pass
+    const int k = k0 + (t & 31), kk = min(k, g.K - 1);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) ra[q] = g.A[(size_t)min(m0 + (t >> 5) + 8 * q, g.M - 1) * g.lda + kk];
+  } else {                  // element (row, k) at A[k][row]: 64 rows contiguous, 4 k per pass
+    const int row = min(m0 + (t & 63), g.M - 1);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) ra[q] = g.A[(size_t)min(k0 + (t >> 6) + 4 * q, g.K - 1) * g.lda + row];
+  }
+  if (!TB) {          // B[k][col]: 64 cols contiguous, 4 k per pass
+    const int col = min(n0 + (t & 63), g.N - 1);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) rb[q] = g.B[(size_t)min(k0 + (t >> 6) + 4 * q, g.K - 1) * g.ldb + col];
+  } else {                  // element (k, col) at B[col][k]: 32 k contiguous, 8 cols per pass
+    const int kk = min(k0 + (t & 31), g.K - 1);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) rb[q] = g.B[(size_t)min(n0 + (t >> 5) + 8 * q, g.N - 1) * g.ldb + kk];
+  }
+}
+
+// Zero outside the matrices and apply the k scaling (after the loads landed).
+template <int TA, int TB>
+__device__ __forceinline__ void gemm64_mask(const GemmArgs& g, int m0, int n0, int k0, double (&ra)[8],
+                                            double (&rb)[8]) {
+  const int t = threadIdx.x;
+  if (!TA) {
+    const int k = k0 + (t & 31);
+    const double ksc = (g.ks_mode && k < g.K) ? scale_of(g.ks_mode, g.ks, g.ks_coef, k) : 1.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) ra[q] = (m0 + (t >> 5) + 8 * q < g.M && k < g.K) ? ra[q] * ksc : 0.0;
+  } else {
+    const bool rin = m0 + (t & 63) < g.M;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int k = k0 + (t >> 6) + 4 * q;
+      const double ksc = (g.ks_mode && k < g.K) ? scale_of(g.ks_mode, g.ks, g.ks_coef, k) : 1.0;
+      ra[q] = (rin && k < g.K) ? ra[q] * ksc : 0.0;
+    }
+  }
+  if (!TB) {
+    const bool cin = n0 + (t & 63) < g.N;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) rb[q] = (cin && k0 + (t >> 6) + 4 * q < g.K) ? rb[q] : 0.0;
+  } else {
+    const bool kin = k0 + (t & 31) < g.K;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) rb[q] = (kin && n0 + (t >> 5) + 8 * q < g.N) ? rb[q] : 0.0;
+  }
+}
+
+template <int TA, int TB>
+__device__ __forceinline__ void gemm64_store(double* As, double* Bs, const double (&ra)[8], const double (&rb)[8]) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    if (!TA) As[((t >> 5) + 8 * q) * kSA + (t & 31)] = ra[q];
+    else As[((t >> 6) + 4 * q) * kSAt + (t & 63)] = ra[q];
+    if (!TB) Bs[((t >> 6) + 4 * q) * kSB + (t & 63)] = rb[q];
+    else Bs[((t >> 5) + 8 * q) * kSBt + (t & 31)] = rb[q];
+  }
+}
+
+template <int TA, int TB>
+__global__ __launch_bounds__(256) void k_gemm64(GemmArgs g, int ntiles) {
+  // physical workgroup -> logical tile: each XCD (physical id mod 8) gets a
+  // contiguous range of tiles
+  const int per = (ntiles + kGXcd - 1) / kGXcd;
+  const int tile = (blockIdx.x % kGXcd) * per + blockIdx.x / kGXcd;
+  if (tile >= ntiles) return;
+  if (g.cstride) {
+    const size_t co = (size_t)blockIdx.y * g.cstride;
+    if (g.pc & PC_A) g.A += co;
+    if (g.pc & PC_B) g.B += co;
+    if (g.pc & PC_C) g.C += co;
+    if (g.pc & PC_RS) g.rs += co;
+    if (g.pc & PC_CS) g.cs += co;
+    if (g.pc & PC_KS) g.ks += co;
+  }
+  extern __shared__ double sm64[];   // buffer b: A at sm64 + b (kGAsz + kGBsz), B right after it
+  const int tilesN = (g.N + kG64 - 1) / kG64;
+  const int m0 = (tile / tilesN) * kG64, n0 = (tile % tilesN) * kG64;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = w >> 1, wc = w & 1, l4 = lane & 3, l16 = lane & 15, lk = lane >> 4;
+  // operand offsets within a buffer (k added per step)
+  const int ia = wr * 32 + l4;        // A row of strip 0
+  const int jb = wc * 32 + l16;       // B column of strip 0
+  double acc[8][2];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) { acc[r][0] = 0.0; acc[r][1] = 0.0; }
+  const int nt = (g.K + kGBK - 1) / kGBK;
+  double ra[8], rb[8];
+  gemm64_load<TA, TB>(g, m0, n0, 0, ra, rb);
+  gemm64_mask<TA, TB>(g, m0, n0, 0, ra, rb);
+  gemm64_store<TA, TB>(sm64, sm64 + kGAsz, ra, rb);
+  __syncthreads();
+  for (int t = 0; t < nt; ++t) {
+    const int cur = t & 1;
+    if (t + 1 < nt) gemm64_load<TA, TB>(g, m0, n0, (t + 1) * kGBK, ra, rb);
+    const double* A_ = sm64 + cur * (kGAsz + kGBsz);
+    const double* B_ = A_ + kGAsz;
+#pragma unroll
+    for (int k4 = 0; k4 < kGBK; k4 += 4) {
+      const int k = k4 + lk;
+      double bv[2], av[8];
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+        bv[c] = TB ? B_[(jb + 16 * c) * kSBt + k] : B_[k * kSB + jb + 16 * c];
+#pragma unroll
+      for (int r = 0; r < 8; ++r)
+        av[r] = TA ? A_[k * kSAt + ia + 4 * r] : A_[(ia + 4 * r) * kSA + k];
+#pragma unroll
+      for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) acc[r][c] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[r], bv[c], acc[r][c], 0, 0, 0);
+    }
+    if (t + 1 < nt) {
+      double* An = sm64 + (cur ^ 1) * (kGAsz + kGBsz);
+      gemm64_mask<TA, TB>(g, m0, n0, (t + 1) * kGBK, ra, rb);
+      gemm64_store<TA, TB>(An, An + kGAsz, ra, rb);
+    }
+    __syncthreads();
+  }
+  // acc[r][c] in lane l is D[m0 + wr*32 + 4r + l/16][n0 + wc*32 + 16c + l%16]
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int col = n0 + wc * 32 + 16 * c + l16;
+    if (col >= g.N) continue;
+    const double cf = g.cs_mode ? scale_of(g.cs_mode, g.cs, g.cs_coef, col) : 1.0;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int row = m0 + wr * 32 + 4 * r + lk;
+      if (row >= g.M) continue;
+      const double rf = g.rs_mode ? scale_of(g.rs_mode, g.rs, g.rs_coef, row) : 1.0;
+      double v = g.alpha * (rf * acc[r][c] * cf);
+      double* cp = g.C + (size_t)row * g.ldc + col;
+      if (g.beta != 0.0) v += g.beta * (*cp);
+      if (row == col) v += g.diag_add;
+      *cp = v;
+    }
+  }
+}
+
 __host__ __device__ inline GemmArgs gemm_args(int M, int N, int K, const double* A, int lda, int transA,
                                             const double* B, int ldb, int transB, double* C, int ldc,
                                             double alpha = 1.0, double beta = 0.0) {
@@ -132,18 +325,43 @@ __host__ __device__ inline GemmArgs gemm_args(int M, int N, int K, const double*
   return g;
 }
 
-// Tile choice: g.tile = 16 or 32 forces it; 0 picks 32 x 32 tiles once there
-// are enough of them (over all chains) to cover the chip.
+// Raise the dynamic LDS limit of the four k_gemm64 instances (once per device).
+static inline hipError_t gemm64_set_lds() {
+  const void* fns[] = {reinterpret_cast<const void*>(k_gemm64<0, 0>), reinterpret_cast<const void*>(k_gemm64<0, 1>),
+                       reinterpret_cast<const void*>(k_gemm64<1, 0>), reinterpret_cast<const void*>(k_gemm64<1, 1>)};
+  for (const void* f : fns) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)gemm64_lds());
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Tile choice: g.tile = 16, 32 or 64 forces it (64: the LDS-staged kernel, an
+// autotuner candidate); 0 picks 32 x 32 tiles once there are enough of them
+// (over all chains) to cover the chip, else 16 x 16.
 static inline hipError_t launch_gemm(const GemmArgs& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
   const int nch = g.nch > 0 ? g.nch : 1;
+  const int t64 = ((g.M + 63) / 64) * ((g.N + 63) / 64);
+  if (g.tile == 64) {
+    const unsigned blocks = (unsigned)(((t64 + kGXcd - 1) / kGXcd) * kGXcd);
+    const dim3 grid(blocks, nch);
+    if (!g.transA && !g.transB) hipLaunchKernelGGL((k_gemm64<0, 0>), grid, dim3(256), gemm64_lds(), s, g, t64);
+    else if (!g.transA) hipLaunchKernelGGL((k_gemm64<0, 1>), grid, dim3(256), gemm64_lds(), s, g, t64);
+    else if (!g.transB) hipLaunchKernelGGL((k_gemm64<1, 0>), grid, dim3(256), gemm64_lds(), s, g, t64);
+    else hipLaunchKernelGGL((k_gemm64<1, 1>), grid, dim3(256), gemm64_lds(), s, g, t64);
+    return hipGetLastError();
+  }
   const int t32 = ((g.M + 31) / 32) * ((g.N + 31) / 32);
   const bool use32 = g.tile == 32 || (g.tile == 0 && (long long)t32 * nch >= 192);
+  const bool deep = nch == 1 && g.K >= 128;   // long K on few workgroups: chunked loads
   if (use32) {
-    hipLaunchKernelGGL(k_gemm<32>, dim3(t32, nch), dim3(256), 0, s, g);
+    if (deep) hipLaunchKernelGGL((k_gemm<32, 8>), dim3(t32, nch), dim3(256), 0, s, g);
+    else hipLaunchKernelGGL((k_gemm<32, 1>), dim3(t32, nch), dim3(256), 0, s, g);
   } else {
     const int t16 = ((g.M + 15) / 16) * ((g.N + 15) / 16);
-    hipLaunchKernelGGL(k_gemm<16>, dim3(t16, nch), dim3(256), 0, s, g);
+    if (deep) hipLaunchKernelGGL((k_gemm<16, 8>), dim3(t16, nch), dim3(256), 0, s, g);
+    else hipLaunchKernelGGL((k_gemm<16, 1>), dim3(t16, nch), dim3(256), 0, s, g);
   }
   return hipGetLastError();
 }

@@ -230,49 +230,100 @@ __global__ __launch_bounds__(256) void k_block_update(BlockArgs a) {
 //   D = (1/N) sum_i d_i (1 - d_i),  E_kin = (n_col/N)(Tr K - Tr(K G)),  E_pot = U D.
 // For a symmetric split d_i = sum_b T1[i][b] Ehinv[b][i] with
 // T1 = exp(-dtau K/2) G (Ehinv is symmetric, so the sum runs along row i of
-// both).  K is symmetric, so Tr(K G) = sum_e K[e] G[e].  One workgroup; each
-// wave walks rows with coalesced loads.
-__global__ __launch_bounds__(1024) void k_measure(const double* G, const double* T1, const double* Ehinv,
-                                                  const double* K, int N, double trK, double n_col, double u_int,
-                                                  double* bins, int* err, size_t cs) {
-  __shared__ double red[16];
+// both).  K is symmetric, so Tr(K G) = sum_e K[e] G[e].
+//
+// k_measure_part gives each workgroup `rows` rows (one wave per row at a time,
+// coalesced) and writes the partial sums (sum d (1 - d), sum K.G, non-finite
+// flag); k_measure_finish adds the partials in a fixed order and updates the
+// bins.  For small N a single workgroup covers all rows and finishes itself
+// (fin != 0), one launch per measurement.
+constexpr int kMeasRows = 16, kMeasSmallN = 128;
+
+__device__ __forceinline__ void measure_bins(double sd, double skg, double bad, int N, double trK, double n_col,
+                                             double u_int, double* bins, int* err) {
+  const double D = sd / N;
+  bins[0] += D;
+  bins[1] += n_col / N * (trK - skg);
+  bins[2] += u_int * D;
+  bins[3] += 1.0;
+  if (bad > 0.0) atomicOr(err, 1);
+}
+
+__global__ __launch_bounds__(256) void k_measure_part(const double* G, const double* T1, const double* Ehinv,
+                                                      const double* K, int N, int rows, double* part, int fin,
+                                                      double trK, double n_col, double u_int, double* bins, int* err,
+                                                      size_t cs) {
+  __shared__ double red[4];
   {
     const size_t co = (size_t)blockIdx.y * cs;
     G += co;
     if (T1) T1 += co;
+    part += co;
     bins += co;
     err = reinterpret_cast<int*>(reinterpret_cast<double*>(err) + co);
   }
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int r0 = blockIdx.x * rows;
   double sd = 0.0, skg = 0.0, bad = 0.0;
-  for (int i = w; i < N; i += 16) {
+  for (int i = r0 + w; i < min(N, r0 + rows); i += 4) {
+    const double* gi = G + (size_t)i * N;
+    const double* ki = K + (size_t)i * N;
+    double p = 0.0;
+    for (int b = lane; b < N; b += 64) {
+      const double gv = gi[b];
+      skg += ki[b] * gv;
+      if (!isfinite(gv)) bad = 1.0;
+      if (T1) p += T1[(size_t)i * N + b] * Ehinv[(size_t)i * N + b];
+    }
     double d;
     if (T1) {
-      double p = 0.0;
-      for (int b = lane; b < N; b += 64) p += T1[(size_t)i * N + b] * Ehinv[(size_t)i * N + b];
       for (int o = 32; o > 0; o >>= 1) p += __shfl_xor(p, o, 64);
       d = p;
     } else {
-      d = G[(size_t)i * N + i];
+      d = gi[i];
     }
     if (lane == 0) sd += d * (1.0 - d);
   }
-  for (size_t e = tid; e < (size_t)N * N; e += 1024) {
-    const double gv = G[e];
-    skg += K[e] * gv;
-    if (!isfinite(gv)) bad = 1.0;
-  }
-  sd = block_sum<1024>(sd, red);
-  skg = block_sum<1024>(skg, red);
-  bad = block_sum<1024>(bad, red);
+  sd = block_sum<256>(sd, red);
+  skg = block_sum<256>(skg, red);
+  bad = block_sum<256>(bad, red);
   if (tid == 0) {
-    const double D = sd / N;
-    bins[0] += D;
-    bins[1] += n_col / N * (trK - skg);
-    bins[2] += u_int * D;
-    bins[3] += 1.0;
-    if (bad > 0.0) atomicOr(err, 1);
+    if (fin) {
+      measure_bins(sd, skg, bad, N, trK, n_col, u_int, bins, err);
+    } else {
+      part[4 * blockIdx.x] = sd;
+      part[4 * blockIdx.x + 1] = skg;
+      part[4 * blockIdx.x + 2] = bad;
+    }
   }
+}
+
+__global__ __launch_bounds__(64) void k_measure_finish(const double* part, int nblk, int N, double trK, double n_col,
+                                                       double u_int, double* bins, int* err, size_t cs) {
+  const size_t co = (size_t)blockIdx.y * cs;
+  part += co;
+  bins += co;
+  err = reinterpret_cast<int*>(reinterpret_cast<double*>(err) + co);
+  if (threadIdx.x != 0) return;
+  double sd = 0.0, skg = 0.0, bad = 0.0;
+  for (int b = 0; b < nblk; ++b) {
+    sd += part[4 * b];
+    skg += part[4 * b + 1];
+    bad += part[4 * b + 2];
+  }
+  measure_bins(sd, skg, bad, N, trK, n_col, u_int, bins, err);
+}
+
+// Weight ratio of one proposed change s -> s_new at a site, from G(tau) (the
+// same formulas as the sweep's decisions); one thread.
+__global__ void k_ratio(const double* G, int N, int site, const double* field_row, double s_new, double coupling,
+                        double alpha, int n_col, int gauss, double* out) {
+  if (threadIdx.x != 0) return;
+  const double s = field_row[site];
+  const double extra = gauss ? -0.5 * (s_new * s_new - s * s) : 0.0;
+  const double dl = exp(coupling * (s_new - s)) - 1.0;
+  const double r = 1.0 + dl * (1.0 - G[(size_t)site * N + site]);
+  out[0] = exp(n_col * coupling * alpha * (s_new - s) + extra) * ipow(r, n_col);
 }
 
 // max |Gw - Gs| into prec_slot (zero on entry), G <- Gs, NaN/Inf check.

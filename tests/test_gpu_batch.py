@@ -83,20 +83,31 @@ def test_batch_workload_shapes_one_sweep():
 
 
 def test_batch_autotune_keeps_trajectory():
-    """The autotuner picks a block size per lattice; the chains then continue
-    the oracle's trajectory from their current state."""
+    """The autotuner times one sweep with each GEMM kernel (16 x 16, 32 x 32,
+    64 x 64 LDS-staged); those sweeps follow the oracle's trajectory, and after
+    the pick the chains continue it."""
     _log("batch autotune")
-    b, oms = _batch([("square", 4, 4, 11), ("square", 6, 6, 12)], beta=2.0, n_wrap=10)
+    b, oms = _batch([("square", 4, 4, 11), ("square", 6, 6, 12), ("honeycomb", 5, 5, 13)], beta=2.0, n_wrap=10)
     b.random_fields().init()
-    b.autotune(1)
-    assert all(b.tuning(i) in (16, 32) for i in range(2))
     ocs = []
     for i, om in enumerate(oms):
-        f, ctr = b.get_state(i)
-        assert ctr == 2
-        oc = osweep.Chain(om, f, sweep_counter=ctr).init()
+        f0, _ = b.get_state(i)
+        oc = osweep.Chain(om, f0).init()
+        for _ in range(3):
+            oc.sweep(measure=False)
         ocs.append(oc)
+    b.autotune(1)
+    assert all(b.tuning(i) in (16, 32, 64) for i in range(3))
+    for i, oc in enumerate(ocs):
+        f, ctr = b.get_state(i)
+        G, _, _ = b.read_chain(i)
+        assert ctr == 3
+        assert oc.min_tie > 1e-9
+        assert np.array_equal(f, oc.field), f"chain {i} after the trial sweeps"
+        assert maxabs(G, oc.G) < 1e-9
     b.init()
+    for oc in ocs:
+        oc.init()
     b.sweep(1)
     for i, oc in enumerate(ocs):
         oc.sweep()

@@ -91,3 +91,20 @@ def test_sweep_parity_honeycomb12_one_sweep():
     """Honeycomb 12x12 (N = 288), U=4, beta=10, L=100: one sweep."""
     _log("trajectory honeycomb 12x12 1 sweep")
     _trajectory("honeycomb", 12, 12, 4.0, 10.0, 10, "asym", 0, 1)
+
+
+@pytest.mark.parametrize("field", ["ising", "gauss"])
+def test_ratio_hook_equals_weight_ratio(field):
+    """dqmc_ratio against W(C')/W(C) of two from-scratch weights (oracle)."""
+    from oracle.stable import weight_ratio
+    print(f"ratio hook {field}", flush=True)
+    om, ch, lat = pair("square", 4, 4, 4.0, 2.0, 0.1, 10, seed=6, field=field)
+    ch.random_field()
+    f0, _ = ch.get_state()
+    rng = np.random.default_rng(2)
+    for _ in range(5):
+        tau, i = int(rng.integers(1, om.L + 1)), int(rng.integers(0, om.N))
+        s_new = -f0[tau - 1, i] if field == "ising" else float(f0[tau - 1, i] + rng.uniform(-1, 1))
+        got = ch.ratio(tau, i, s_new)
+        want = weight_ratio(om, f0, tau, i, s_new)
+        assert abs(got - want) < 1e-9 * max(1.0, abs(want)), (tau, i, got, want)
