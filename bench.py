@@ -177,6 +177,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--profile-extra", choices=["batched", "gradient", "time_displaced"],
+                    help="run only this extra workload and print its figures (for rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the sweep of one chain does not shard across GPUs "
@@ -187,6 +189,11 @@ def main():
 
     import paper_1704_00131_amd as pa
     from inputs import WORKLOADS
+
+    if args.profile_extra:
+        fn = {"batched": bench_batched, "gradient": bench_gradient, "time_displaced": bench_time_displaced}
+        print(json.dumps({args.profile_extra: fn[args.profile_extra](torch, pa)}))
+        return
 
     w = WORKLOADS["honeycomb12_U4_b10"]
     lat = w.lattice()

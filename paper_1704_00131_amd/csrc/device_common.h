@@ -74,6 +74,58 @@ __device__ __forceinline__ double block_max(double v, double* red) {
   return s;
 }
 
+// ------------------------------------------------- DPP wave reductions ----
+// Whole-wave reductions on VALU data-parallel moves instead of LDS permutes:
+// xor-1 and xor-2 quad permutes, the half-row and row mirrors (max/sum over
+// 8 and 16 lanes), then row_bcast15 / row_bcast31 carry the row results up;
+// lane 63 ends with the wave's result, read with readlane.  OLD is what a
+// lane outside the row mask receives (the identity of the operation).
+template <int CTRL, int RM>
+__device__ __forceinline__ double dpp_d(double v, double old) {
+  const long long b = __double_as_longlong(v), o = __double_as_longlong(old);
+  const int lo = __builtin_amdgcn_update_dpp((int)o, (int)b, CTRL, RM, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(b >> 32), CTRL, RM, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ double wave_max_d(double v) {
+  const double ni = -INFINITY;
+  v = fmax(v, dpp_d<0xB1, 0xF>(v, ni));
+  v = fmax(v, dpp_d<0x4E, 0xF>(v, ni));
+  v = fmax(v, dpp_d<0x141, 0xF>(v, ni));
+  v = fmax(v, dpp_d<0x140, 0xF>(v, ni));
+  v = fmax(v, dpp_d<0x142, 0xA>(v, ni));
+  v = fmax(v, dpp_d<0x143, 0xC>(v, ni));
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+  v += dpp_d<0xB1, 0xF>(v, 0.0);
+  v += dpp_d<0x4E, 0xF>(v, 0.0);
+  v += dpp_d<0x141, 0xF>(v, 0.0);
+  v += dpp_d<0x140, 0xF>(v, 0.0);
+  v += dpp_d<0x142, 0xA>(v, 0.0);
+  v += dpp_d<0x143, 0xC>(v, 0.0);
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ int wave_min_i(int v) {
+  const int big = 0x7fffffff;
+  v = min(v, __builtin_amdgcn_update_dpp(big, v, 0xB1, 0xF, 0xF, false));
+  v = min(v, __builtin_amdgcn_update_dpp(big, v, 0x4E, 0xF, 0xF, false));
+  v = min(v, __builtin_amdgcn_update_dpp(big, v, 0x141, 0xF, 0xF, false));
+  v = min(v, __builtin_amdgcn_update_dpp(big, v, 0x140, 0xF, 0xF, false));
+  v = min(v, __builtin_amdgcn_update_dpp(big, v, 0x142, 0xA, 0xF, false));
+  v = min(v, __builtin_amdgcn_update_dpp(big, v, 0x143, 0xC, 0xF, false));
+  return __builtin_amdgcn_readlane(v, 63);
+}
+
 // max of non-negative doubles through their ordered bit patterns
 __device__ __forceinline__ void atomic_max_nonneg(double* addr, double v) {
   if (!(v >= 0.0)) v = __longlong_as_double(0x7ff8000000000000ll);  // NaN propagates as the largest

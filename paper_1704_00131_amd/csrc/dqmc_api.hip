@@ -344,10 +344,26 @@ dqmc_status launch_qr_panel(dqmc_ctx* c, double* Ap, int j0, int nbw, double* V,
   return DQMC_OK;
 }
 
+template <int NBW, int MAXR>
+void lu_panel_reg(dqmc_ctx* c, double* X, int j0, int nbw) {
+  hipLaunchKernelGGL((k_lu_panel_reg<NBW, MAXR>), gridc(c, 1), dim3(256), 0, c->stream, X, c->N, j0, nbw, c->ipiv,
+                     c->err_flag, c->cs);
+}
+
+// Panel LU of columns j0 .. j0 + nbw (nbw <= c->nb): the register-resident
+// kernel, with ceil(h / 256) rows per thread.
 dqmc_status launch_lu_panel(dqmc_ctx* c, double* X, int j0, int nbw) {
-  const int h = c->N - j0;
-  hipLaunchKernelGGL(k_lu_panel, gridc(c, 1), dim3(256), sizeof(double) * lu_panel_lds(h, nbw), c->stream, X, c->N,
-                     j0, nbw, c->ipiv, c->err_flag, c->cs);
+  const int h = c->N - j0, maxr = (h + 255) / 256;
+  if (c->nb == 32 && maxr == 1) lu_panel_reg<32, 1>(c, X, j0, nbw);
+  else if (c->nb == 32 && maxr == 2) lu_panel_reg<32, 2>(c, X, j0, nbw);
+  else if (c->nb == 16 && maxr == 1) lu_panel_reg<16, 1>(c, X, j0, nbw);
+  else if (c->nb == 16 && maxr == 2) lu_panel_reg<16, 2>(c, X, j0, nbw);
+  else if (c->nb == 16 && maxr == 3) lu_panel_reg<16, 3>(c, X, j0, nbw);
+  else if (c->nb == 8 && maxr == 1) lu_panel_reg<8, 1>(c, X, j0, nbw);
+  else if (c->nb == 8 && maxr == 2) lu_panel_reg<8, 2>(c, X, j0, nbw);
+  else if (c->nb == 8 && maxr == 3) lu_panel_reg<8, 3>(c, X, j0, nbw);
+  else if (c->nb == 8 && maxr == 4) lu_panel_reg<8, 4>(c, X, j0, nbw);
+  else return fail(c, DQMC_E_UNSUPPORTED, "no LU panel kernel for this size");
   HIPCHK(hipGetLastError());
   return DQMC_OK;
 }
@@ -368,8 +384,6 @@ dqmc_status set_lds_limits(dqmc_ctx* c) {
   HIPCHK(lds_limit_qr<32>());
   HIPCHK(lds_limit_qr<16>());
   HIPCHK(lds_limit_qr<8>());
-  HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(k_lu_panel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                             156 * 1024));
   HIPCHK(gemm64_set_lds());
   return DQMC_OK;
 }

@@ -279,81 +279,110 @@ __global__ void k_build_rt(const double* R, const int* piv, int n, double* Rt, d
 }
 
 // ----------------------------------------------------------- LU panel ----
-// Partial pivoting over rows j0..n-1 of the panel columns j0..j0+nbw-1
-// (nbw <= 32) of X (ld n); ipiv[j0+c] = global pivot row (ties: lowest row).
-// Rows are swapped inside the panel only; k_lu_swap applies the interchanges
-// elsewhere.  LDS: lu_panel_lds(h) doubles.
-__host__ __device__ inline size_t lu_panel_lds(int h, int nbw) { return (size_t)h * (nbw + 1) + 16; }
-
-__device__ __forceinline__ void lu_panel_body(double* X, int n, int j0, int nbw, int* ipiv, int* err,
-                                              double* smem) {
-  const int P = nbw + 1;
-  const int h = n - j0, tid = threadIdx.x;
-  double* pan = smem;
-  double* rv = pan + (size_t)h * P;     // 4 values
-  int* ri = reinterpret_cast<int*>(rv + 4);
-  __shared__ int piv_s;
-  for (int e = tid; e < h * 32; e += 256) {
-    const int r = e >> 5, q = e & 31;
-    if (q < nbw) pan[r * P + q] = X[(size_t)(j0 + r) * n + j0 + q];
+// Register-resident panel LU with partial pivoting of columns j0..j0+nbw-1 of
+// X (ld n) over rows j0..n-1: the pivot is the largest |a| among the
+// remaining rows, ties to the lowest position; ipiv[j0+c] = global pivot row;
+// multipliers by the pivot's reciprocal.  k_lu_swap applies the interchanges
+// outside the panel.  Thread t keeps rows t,
+// t + 256, ... (MAXR of them, NBW columns each) in registers for the whole
+// panel; column c is picked out of the registers by selects, so every
+// register index is static.  Pivoting is virtual: each held row carries its
+// current position, a pivot step swaps two positions, and the rows are
+// written back to their final positions.  Per column: a wave argmax on DPP
+// moves, one barrier, the pivot row broadcast through LDS, a second barrier,
+// then the elimination in registers.  Columns c >= nbw (a ragged last panel) are left
+// out.
+template <int NBW, int MAXR>
+__global__ __launch_bounds__(256) void k_lu_panel_reg(double* X, int n, int j0, int nbw, int* ipiv, int* err,
+                                                      size_t cs) {
+  __shared__ double cand_v[4], prow[NBW];
+  __shared__ int cand_i[4];
+  {
+    const size_t co = (size_t)blockIdx.y * cs;
+    X += co;
+    ipiv = reinterpret_cast<int*>(reinterpret_cast<double*>(ipiv) + co);
+    err = reinterpret_cast<int*>(reinterpret_cast<double*>(err) + co);
   }
-  __syncthreads();
-  const int q = tid & 31, rc = tid >> 5;
-  for (int c = 0; c < nbw && c < h; ++c) {
+  const int h = n - j0, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  double a[MAXR][NBW];
+  int pos[MAXR];
+#pragma unroll
+  for (int i = 0; i < MAXR; ++i) {
+    const int r = tid + 256 * i;
+    pos[i] = (r < h) ? r : 0x7fffffff;
+#pragma unroll
+    for (int q = 0; q < NBW; ++q) a[i][q] = (r < h && q < nbw) ? X[(size_t)(j0 + r) * n + j0 + q] : 0.0;
+  }
+  const int ncol = min(nbw, h);
+  for (int c = 0; c < ncol; ++c) {
+    double colv[MAXR];
+#pragma unroll
+    for (int i = 0; i < MAXR; ++i) {
+      double v = 0.0;
+#pragma unroll
+      for (int q = 0; q < NBW; ++q) v = (q == c) ? a[i][q] : v;
+      colv[i] = v;
+    }
+    // argmax over positions >= c
     double best = -1.0;
     int bi = 0x7fffffff;
-    for (int r = c + tid; r < h; r += 256) {
-      const double v = fabs(pan[r * P + c]);
-      if (v > best || (v == best && r < bi)) { best = v; bi = r; }
+#pragma unroll
+    for (int i = 0; i < MAXR; ++i) {
+      if (pos[i] >= c && pos[i] < h) {
+        const double v = fabs(colv[i]);
+        if (v > best || (v == best && pos[i] < bi)) { best = v; bi = pos[i]; }
+      }
     }
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ob = __shfl_xor(best, o, 64);
-      const int oi = __shfl_xor(bi, o, 64);
-      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-    }
-    if ((tid & 63) == 0) { rv[tid >> 6] = best; ri[tid >> 6] = bi; }
+    // wave argmax on DPP: the largest value, then the lowest position holding it
+    const double wm = wave_max_d(best);
+    const int wi = wave_min_i((best == wm && best >= 0.0) ? bi : 0x7fffffff);
+    if (lane == 0) { cand_v[w] = wm; cand_i[w] = wi; }
     __syncthreads();
+    double b = cand_v[0];
+    int pp = cand_i[0];
+#pragma unroll
+    for (int k = 1; k < 4; ++k)
+      if (cand_v[k] > b || (cand_v[k] == b && cand_i[k] < pp)) { b = cand_v[k]; pp = cand_i[k]; }
+    // no finite candidate (a NaN column): keep the row and flag the failure
+    if (!(b >= 0.0) || pp < c || pp >= h) pp = c;
     if (tid == 0) {
-      double b = rv[0];
-      int i = ri[0];
-      for (int k = 1; k < 4; ++k)
-        if (rv[k] > b || (rv[k] == b && ri[k] < i)) { b = rv[k]; i = ri[k]; }
-      // no finite candidate (a NaN column): keep the row and flag the failure,
-      // so no pivot index ever leaves the panel
-      if (!(b >= 0.0) || i < c || i >= h) i = c;
-      piv_s = i;
-      ipiv[j0 + c] = j0 + i;
+      ipiv[j0 + c] = j0 + pp;
       if (!(b > 0.0)) atomicOr(err, 4);
     }
-    __syncthreads();
-    const int p = piv_s;
-    if (p != c && tid < nbw) {
-      const double t = pan[c * P + tid];
-      pan[c * P + tid] = pan[p * P + tid];
-      pan[p * P + tid] = t;
+    // the row at position pp becomes the pivot row (position c); the row at
+    // position c moves to pp
+#pragma unroll
+    for (int i = 0; i < MAXR; ++i) {
+      if (pos[i] == pp) {
+#pragma unroll
+        for (int q = 0; q < NBW; ++q) prow[q] = a[i][q];
+        pos[i] = c;
+      } else if (pos[i] == c) {
+        pos[i] = pp;
+      }
     }
     __syncthreads();
-    const double inv = 1.0 / pan[c * P + c];
-    for (int r = c + 1 + tid; r < h; r += 256) pan[r * P + c] *= inv;
-    __syncthreads();
-    if (q > c && q < nbw) {
-      const double u = pan[c * P + q];
-      for (int r = c + 1 + rc; r < h; r += 8) pan[r * P + q] -= pan[r * P + c] * u;
+    const double inv = 1.0 / prow[c];
+#pragma unroll
+    for (int i = 0; i < MAXR; ++i) {
+      if (pos[i] > c && pos[i] < h) {
+        const double l = colv[i] * inv;
+#pragma unroll
+        for (int q = 0; q < NBW; ++q) {
+          if (q == c) a[i][q] = l;
+          else if (q > c) a[i][q] -= l * prow[q];
+        }
+      }
     }
-    __syncthreads();
   }
-  for (int e = tid; e < h * 32; e += 256) {
-    const int r = e >> 5, b = e & 31;
-    if (b < nbw) X[(size_t)(j0 + r) * n + j0 + b] = pan[r * P + b];
+#pragma unroll
+  for (int i = 0; i < MAXR; ++i) {
+    if (pos[i] < h) {
+#pragma unroll
+      for (int q = 0; q < NBW; ++q)
+        if (q < nbw) X[(size_t)(j0 + pos[i]) * n + j0 + q] = a[i][q];
+    }
   }
-}
-
-__global__ __launch_bounds__(256) void k_lu_panel(double* X, int n, int j0, int nbw, int* ipiv, int* err,
-                                                  size_t cs) {
-  extern __shared__ double smem[];
-  const size_t co = (size_t)blockIdx.y * cs;
-  lu_panel_body(X + co, n, j0, nbw, reinterpret_cast<int*>(reinterpret_cast<double*>(ipiv) + co),
-                reinterpret_cast<int*>(reinterpret_cast<double*>(err) + co), smem);
 }
 
 // Apply the interchanges of one panel to the columns of X outside the panel
