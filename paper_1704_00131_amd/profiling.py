@@ -4,6 +4,9 @@ part of the compute path).
     python -m paper_1704_00131_amd.profiling copy
         a plain 64 MiB device-to-device copy, three times: the kernel whose
         FETCH_SIZE / WRITE_SIZE counters calibrate the HBM byte counts
+    python -m paper_1704_00131_amd.profiling stats OUT TITLE COMMAND KERNEL_STATS_CSV
+        a short text table of the kernels with the largest total time from a
+        rocprofv3 --kernel-trace --stats CSV, headed by the command that made it
     python -m paper_1704_00131_amd.profiling summarize OUT KERNEL SRC FETCH_DB WRITE_DB COPY_FETCH_DB COPY_WRITE_DB
         per-dispatch averages of FETCH_SIZE and WRITE_SIZE (KiB) of KERNEL from
         two rocprofv3 --pmc result databases, scaled by the copy kernel's
@@ -37,7 +40,7 @@ def _values(db, counter, kernel_prefix=None):
     con.close()
     if kernel_prefix is None:
         return [v for _, v in rows]
-    return [v for n, v in rows if n.startswith(kernel_prefix)]
+    return [v for n, v in rows if kernel_prefix in n]
 
 
 def summarize(out, kernel, src, fetch_db, write_db, copy_fetch_db, copy_write_db):
@@ -61,9 +64,26 @@ def summarize(out, kernel, src, fetch_db, write_db, copy_fetch_db, copy_write_db
     print(json.dumps(d))
 
 
+def stats(out, title, command, csv_path, top=14):
+    import csv
+    rows = list(csv.DictReader(open(csv_path)))
+    total = sum(float(r["TotalDurationNs"]) for r in rows)
+    lines = ["# %s" % title, "#", "# command: %s" % command,
+             "# total kernel time %.1f ms over %d kernels; times in microseconds" % (total / 1e6, len(rows)), "",
+             "| kernel | calls | total ms | avg us | min us | max us | share |", "|---|---|---|---|---|---|---|"]
+    for r in rows[:top]:
+        lines.append("| `%s` | %d | %.2f | %.2f | %.2f | %.2f | %.1f%% |" % (
+            r["Name"].replace("|", "/"), int(r["Calls"]), float(r["TotalDurationNs"]) / 1e6,
+            float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "copy":
         copy()
+    elif sys.argv[1] == "stats":
+        stats(*sys.argv[2:6])
     elif sys.argv[1] == "summarize":
         summarize(*sys.argv[2:9])
     else:
