@@ -63,13 +63,16 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
 //
 // With the vectors of the Phi recursion in the header, U_i = c a_i and
 // V_i = (1 - c_0)^T b_i, so the recursions for a and b become triangular:
-//   A (1 + T_A) = 1,  B (1 + T_B) = 1,  Phi = A diag(gamma) B^T,
-// solved row by row by the 64 lanes of wave 0 (A on lanes 0-31, B on 32-63).
+//   A (1 + T_A) = 1,  B (1 + T_B) = 1,  Phi = A diag(gamma) B^T.
+// Each workgroup needs Phi only inside Gin[I,S] Phi (E_S^T[:,J] - Gin[S,J]) =
+// X diag(gamma) Z with X = Gin[I,S] A and Z = B^T (E_S^T[:,J] - Gin[S,J]), so it
+// solves the two triangular systems for its own tile (one lane per row of X
+// and of Z^T in wave 0) and finishes with one MFMA product.
 // Workgroup 0 also writes the block's field values and the counters.
 template <int NCOL>
 __global__ __launch_bounds__(256) void k_block_update(BlockArgs a) {
   constexpr int TS = 34;   // row stride of the records (16-byte aligned rows)
-  __shared__ double GIS[32][33], GSJ[32][33], Ph[32][33], Wt[32][33], AB[2][32][33];
+  __shared__ double AB[2][32][33];   // right-hand sides, then X and Z^T
   __shared__ __attribute__((aligned(16))) double Tt[2][32][TS];   // Tt[0][k][m] = T_A[m][k], Tt[1][k][m] = T_B[m][k]
   __shared__ double gam[32];
   __shared__ int accf[32], nacc_s;
@@ -149,20 +152,25 @@ __global__ __launch_bounds__(256) void k_block_update(BlockArgs a) {
     }
     if (blockIdx.x == 0 && lane < bb) a.field_out[s0 + lane] = myacc ? snew : sold;
   } else {
+    // right-hand sides of the two triangular systems below:
+    // AB[0][x][k] = Gin[I0+x][s0+k],  AB[1][y][k] = delta - Gin[s0+k][J0+y]
     for (int e = tid - 64; e < 1024; e += 192) {
       const int x = e >> 5, y = e & 31;
-      GIS[x][y] = (I0 + x < N && y < bb) ? a.Gin[(size_t)(I0 + x) * N + s0 + y] : 0.0;
-      GSJ[x][y] = (x < bb && J0 + y < N) ? a.Gin[(size_t)(s0 + x) * N + J0 + y] : 0.0;
+      AB[0][x][y] = (I0 + x < N && y < bb) ? a.Gin[(size_t)(I0 + x) * N + s0 + y] : 0.0;
+      const double gsj = (x < bb && J0 + y < N) ? a.Gin[(size_t)(s0 + x) * N + J0 + y] : 0.0;
+      AB[1][y][x] = ((s0 + x == J0 + y) ? 1.0 : 0.0) - gsj;
     }
   }
   __syncthreads();
   if (w == 0) {
-    // row x of A (lanes 0-31) or of B (lanes 32-63): R[k] = delta_xk - sum_{m<k} T[m][k] R[m]
+    // X = GIS A (lanes 0-31, row x) and Z^T = (E_S^T[:,J] - G[S,J])^T B (lanes
+    // 32-63): the triangular recurrences R[k] = rhs[k] - sum_{m<k} R[m] T[m][k]
+    // with T = T_A or T_B, four independent partial sums per lane
     const int x = lane & 31, h = lane >> 5;
     double R[32];
 #pragma unroll
     for (int k = 0; k < 32; ++k) {
-      double v0 = (x == k) ? 1.0 : 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+      double v0 = AB[h][x][k], v1 = 0.0, v2 = 0.0, v3 = 0.0;
 #pragma unroll
       for (int m = 0; m + 3 < k; m += 4) {
         v0 = fma(-Tt[h][k][m], R[m], v0);
@@ -178,38 +186,14 @@ __global__ __launch_bounds__(256) void k_block_update(BlockArgs a) {
     for (int k = 0; k < 32; ++k) AB[h][x][k] = R[k];
   }
   __syncthreads();
-  {
-    // Phi = A diag(gamma) B^T  (32 x 32 x 32 on MFMA)
-    v4d acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int k0 = 0; k0 < 32; k0 += 4) {
-      const int k = k0 + (lane >> 4);
-      const double av_ = AB[0][wr * 16 + (lane & 15)][k] * gam[k];
-      const double bv_ = AB[1][wc * 16 + (lane & 15)][k];
-      acc = mfma_f64_16x16x4(av_, bv_, acc);
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) Ph[wr * 16 + (lane >> 4) + 4 * r][wc * 16 + (lane & 15)] = acc[r];
-  }
-  __syncthreads();
-  // W tile = Phi (E_S^T[:, J] - G[S, J])  (32 x 32 x 32 on MFMA)
-  v4d acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int k0 = 0; k0 < 32; k0 += 4) {
-    const int z = k0 + (lane >> 4), y = wc * 16 + (lane & 15);
-    const double av_ = Ph[wr * 16 + (lane & 15)][z];
-    const double bz = ((s0 + z == J0 + y) ? 1.0 : 0.0) - GSJ[z][y];
-    acc = mfma_f64_16x16x4(av_, bz, acc);
-  }
-#pragma unroll
-  for (int r = 0; r < 4; ++r) Wt[wr * 16 + (lane >> 4) + 4 * r][wc * 16 + (lane & 15)] = acc[r];
-  __syncthreads();
+  // Gout tile = Gin - X diag(gamma) Z  (32 x 32 x 32 on MFMA)
   v4d acc2 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int k0 = 0; k0 < 32; k0 += 4) {
-    const double av_ = GIS[wr * 16 + (lane & 15)][k0 + (lane >> 4)];
-    const double bw = Wt[k0 + (lane >> 4)][wc * 16 + (lane & 15)];
-    acc2 = mfma_f64_16x16x4(av_, bw, acc2);
+    const int k = k0 + (lane >> 4);
+    const double av_ = AB[0][wr * 16 + (lane & 15)][k] * gam[k];
+    const double bv_ = AB[1][wc * 16 + (lane & 15)][k];
+    acc2 = mfma_f64_16x16x4(av_, bv_, acc2);
   }
   if (col < N) {
 #pragma unroll
