@@ -325,21 +325,20 @@ void qr_panel_launch(dqmc_ctx* c, double* Ap, int j0, int nbw, double* V, double
                      c->stream, Ap, c->N, j0, nbw, V, VT, c->cs);
 }
 
-template <int NBW>
-void qr_panel_pick(dqmc_ctx* c, double* Ap, int j0, int nbw, double* V, double* VT) {
-  const int rows = (c->N - j0 + (256 / NBW) - 1) / (256 / NBW);   // rows per thread
-  if (rows <= 8) qr_panel_launch<NBW, 8>(c, Ap, j0, nbw, V, VT);
-  else if (rows <= 16) qr_panel_launch<NBW, 16>(c, Ap, j0, nbw, V, VT);
-  else if (rows <= 24) qr_panel_launch<NBW, 24>(c, Ap, j0, nbw, V, VT);
-  else if (rows <= 32) qr_panel_launch<NBW, 32>(c, Ap, j0, nbw, V, VT);
-  else if (rows <= 40) qr_panel_launch<NBW, 40>(c, Ap, j0, nbw, V, VT);
-  else qr_panel_launch<NBW, 48>(c, Ap, j0, nbw, V, VT);
-}
-
+// rows per lane = ceil(h / 64), rounded up to the instantiated counts; the
+// panel width is 32 for N <= 384, 16 for N <= 768, 8 above (set in create)
 dqmc_status launch_qr_panel(dqmc_ctx* c, double* Ap, int j0, int nbw, double* V, double* VT) {
-  if (c->nb == 32) qr_panel_pick<32>(c, Ap, j0, nbw, V, VT);
-  else if (c->nb == 16) qr_panel_pick<16>(c, Ap, j0, nbw, V, VT);
-  else qr_panel_pick<8>(c, Ap, j0, nbw, V, VT);
+  const int rows = (c->N - j0 + 63) / 64;
+  if (c->nb == 32 && rows <= 2) qr_panel_launch<32, 2>(c, Ap, j0, nbw, V, VT);
+  else if (c->nb == 32 && rows <= 4) qr_panel_launch<32, 4>(c, Ap, j0, nbw, V, VT);
+  else if (c->nb == 32 && rows <= 6) qr_panel_launch<32, 6>(c, Ap, j0, nbw, V, VT);
+  else if (c->nb == 16 && rows <= 4) qr_panel_launch<16, 4>(c, Ap, j0, nbw, V, VT);
+  else if (c->nb == 16 && rows <= 8) qr_panel_launch<16, 8>(c, Ap, j0, nbw, V, VT);
+  else if (c->nb == 16 && rows <= 12) qr_panel_launch<16, 12>(c, Ap, j0, nbw, V, VT);
+  else if (c->nb == 8 && rows <= 4) qr_panel_launch<8, 4>(c, Ap, j0, nbw, V, VT);
+  else if (c->nb == 8 && rows <= 8) qr_panel_launch<8, 8>(c, Ap, j0, nbw, V, VT);
+  else if (c->nb == 8 && rows <= 16) qr_panel_launch<8, 16>(c, Ap, j0, nbw, V, VT);
+  else return fail(c, DQMC_E_UNSUPPORTED, "no QR panel kernel for this size");
   HIPCHK(hipGetLastError());
   return DQMC_OK;
 }
@@ -368,11 +367,11 @@ dqmc_status launch_lu_panel(dqmc_ctx* c, double* X, int j0, int nbw) {
   return DQMC_OK;
 }
 
-template <int NBW>
+template <int NBW, int R1, int R2, int R3>
 hipError_t lds_limit_qr() {
-  const void* fns[] = {reinterpret_cast<const void*>(k_qr_panel<NBW, 8>), reinterpret_cast<const void*>(k_qr_panel<NBW, 16>),
-                       reinterpret_cast<const void*>(k_qr_panel<NBW, 24>), reinterpret_cast<const void*>(k_qr_panel<NBW, 32>),
-                       reinterpret_cast<const void*>(k_qr_panel<NBW, 40>), reinterpret_cast<const void*>(k_qr_panel<NBW, 48>)};
+  const void* fns[] = {reinterpret_cast<const void*>(k_qr_panel<NBW, R1>),
+                       reinterpret_cast<const void*>(k_qr_panel<NBW, R2>),
+                       reinterpret_cast<const void*>(k_qr_panel<NBW, R3>)};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 156 * 1024);
     if (e != hipSuccess) return e;
@@ -381,9 +380,9 @@ hipError_t lds_limit_qr() {
 }
 
 dqmc_status set_lds_limits(dqmc_ctx* c) {
-  HIPCHK(lds_limit_qr<32>());
-  HIPCHK(lds_limit_qr<16>());
-  HIPCHK(lds_limit_qr<8>());
+  HIPCHK((lds_limit_qr<32, 2, 4, 6>()));
+  HIPCHK((lds_limit_qr<16, 4, 8, 12>()));
+  HIPCHK((lds_limit_qr<8, 4, 8, 16>()));
   HIPCHK(gemm64_set_lds());
   return DQMC_OK;
 }

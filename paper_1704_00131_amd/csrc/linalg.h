@@ -102,118 +102,132 @@ __global__ void k_permute_cols(double* dst, const double* src, const int* piv, i
 }
 
 // ---------------------------------------------------------- QR panel ----
-// Panel rows j0..n-1, columns j0..j0+nbw-1 (nbw <= NBW) of A (ld n).  Writes R
-// back into the panel (zeros below the diagonal), V (h x nbw, ld nbw, unit
-// lower trapezoidal) and VT = V T (h x nbw).  Householder convention of
-// LAPACK's dlarfg: for x = (x0, x'), beta = -sign(x0) |x|,
+// Householder QR of one panel (columns j0..j0+nbw-1, rows j0..n-1 of A, ld n)
+// by one workgroup, with the compact-WY output V (h x nbw, ld nbw, unit lower
+// trapezoidal), VT = V T (T upper triangular, forward column-wise, the dlarft
+// convention) and R in place (zeros below the diagonal).  Householder
+// convention of LAPACK's dlarfg: for x = (x0, x'), beta = -sign(x0) |x|,
 // tau = (beta - x0)/beta, v = (1, x' / (x0 - beta)); tau = 0 when x' = 0.
 //
-// Thread (q, rg) keeps column q of the panel for rows r = rg + RG i in
-// registers (RG = 256 / NBW row groups, up to MAXR rows each); LDS carries only
-// the current reflector, the per-column partial sums and the small T, Y.
+// Layout: wave w owns the columns w*NBW/4 .. (w+1)*NBW/4 - 1 of the panel and
+// lane l the rows l, l + 64, ... (MAXR of them), in registers.  Per column c:
+// the owning wave forms the reflector (norm by a DPP wave sum), writes it to
+// LDS (two alternating buffers) and the workgroup passes one barrier; every
+// wave then takes the dot products with its own columns by DPP wave sums, so
+// no LDS or barrier is needed for them, and applies the reflector in
+// registers (v_q^T v_c for q < c goes to Y for the T recurrence).
 template <int NBW>
 __host__ __device__ inline size_t qr_panel_lds(int h) {
-  return (size_t)h * (NBW + 1) + (size_t)h + (256 / NBW) * (NBW + 2) + 3 * 32 * 33 + 64;
+  return (size_t)h * (NBW + 1) + 2 * (size_t)h + 2 * 32 * 33 + 64;
 }
 
 template <int NBW, int MAXR>
-__device__ __forceinline__ void qr_panel_body(double* A, int n, int j0, int nbw, double* Vout, double* VTout,
-                                              double* smem) {
-  constexpr int RG = 256 / NBW, PT = 33, PV = NBW + 1;
+__global__ __launch_bounds__(256) void k_qr_panel(double* A, int n, int j0, int nbw, double* Vout,
+                                                  double* VTout, size_t cs) {
+  extern __shared__ double smem[];
+  constexpr int CPW = NBW / 4, PT = 33, PV = NBW + 1;
+  {
+    const size_t co = (size_t)blockIdx.y * cs;
+    A += co; Vout += co; VTout += co;
+  }
   const int h = n - j0, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int q = tid % NBW, rg = tid / NBW;
   double* vsh = smem;                       // h x PV: V at the end
-  double* vbuf = vsh + (size_t)h * PV;      // h: current reflector
-  double* part = vbuf + h;                  // RG x PV partial sums
-  double* T = part + RG * PV;               // 32 x 33
+  double* vbuf = vsh + (size_t)h * PV;      // 2 x h: reflectors of even / odd columns
+  double* T = vbuf + 2 * (size_t)h;         // 32 x 33
   double* Y = T + 32 * PT;                  // 32 x 33
-  double* normp = Y + 32 * PT;             // RG partial norms
-  double* misc = normp + RG;               // tau[32], wv[32]
-  double* tau = misc;
-  double* wv = misc + 32;
-  double a[MAXR], va[MAXR];
+  double* tau = Y + 32 * PT;                // 32
+  double a[MAXR][CPW];
 #pragma unroll
   for (int i = 0; i < MAXR; ++i) {
-    const int r = rg + RG * i;
-    a[i] = (r < h && q < nbw) ? A[(size_t)(j0 + r) * n + j0 + q] : 0.0;
+    const int r = lane + 64 * i;
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+      const int q = w * CPW + j;
+      a[i][j] = (r < h && q < nbw) ? A[(size_t)(j0 + r) * n + j0 + q] : 0.0;
+    }
   }
   for (int e = tid; e < 32 * PT; e += 256) { T[e] = 0.0; Y[e] = 0.0; }
-  __shared__ double x0s;
-  for (int c = 0; c < nbw && c < h; ++c) {
-    // 1. norm of the column below the diagonal, and its diagonal entry
-    if (q == c) {
-      double s = 0.0;
+  const int ncol = min(nbw, h);
+  for (int c = 0; c < ncol; ++c) {
+    double* vb = vbuf + (c & 1) * (size_t)h;
+    const int cw = c / CPW, cj = c % CPW;
+    if (w == cw) {
+      double colv[MAXR];
+      double s = 0.0, x0 = 0.0;
 #pragma unroll
       for (int i = 0; i < MAXR; ++i) {
-        const int r = rg + RG * i;
-        if (r > c && r < h) s += a[i] * a[i];
-        if (r == c) x0s = a[i];
+        double v = 0.0;
+#pragma unroll
+        for (int j = 0; j < CPW; ++j) v = (j == cj) ? a[i][j] : v;
+        colv[i] = v;
+        const int r = lane + 64 * i;
+        if (r > c && r < h) s += v * v;
+        if (r == c) x0 = v;
       }
-      normp[rg] = s;
-    }
-    __syncthreads();
-    double s = 0.0;
-#pragma unroll
-    for (int k = 0; k < RG; ++k) s += normp[k];
-    const double x0 = x0s;
-    double beta, tc, scal;
-    if (s == 0.0) { tc = 0.0; beta = x0; scal = 0.0; }
-    else {
-      const double nrm = sqrt(x0 * x0 + s);
-      beta = (x0 >= 0.0) ? -nrm : nrm;
-      tc = (beta - x0) / beta;
-      scal = 1.0 / (x0 - beta);
-    }
-    // 2. the reflector v (v_c = 1) into LDS; column c keeps v below the diagonal and beta on it
-    if (q == c) {
+      s = wave_sum_d(s);
+      x0 = wave_sum_d(x0);   // exactly one lane holds it
+      double beta, tc, scal;
+      if (s == 0.0) { tc = 0.0; beta = x0; scal = 0.0; }
+      else {
+        const double nrm = sqrt(x0 * x0 + s);
+        beta = (x0 >= 0.0) ? -nrm : nrm;
+        tc = (beta - x0) / beta;
+        scal = 1.0 / (x0 - beta);
+      }
+      // reflector v (v_c = 1, zero above c) into LDS; column c keeps v below
+      // the diagonal and beta on it
 #pragma unroll
       for (int i = 0; i < MAXR; ++i) {
-        const int r = rg + RG * i;
+        const int r = lane + 64 * i;
         if (r < h) {
-          if (r > c) { a[i] *= scal; vbuf[r] = a[i]; }
-          else if (r == c) { a[i] = beta; vbuf[r] = 1.0; }
+          const double v = (r > c) ? colv[i] * scal : (r == c ? 1.0 : 0.0);
+          vb[r] = v;
+          const double nv = (r > c) ? v : (r == c ? beta : colv[i]);
+#pragma unroll
+          for (int j = 0; j < CPW; ++j) if (j == cj) a[i][j] = nv;
         }
       }
+      if (lane == 0) tau[c] = tc;
     }
-    if (tid == 0) tau[c] = tc;
     __syncthreads();
-    // 3. partial v^T A[:, q] over rows >= c for every other column q
-    if (q != c && q < nbw) {
-      double p = 0.0;
+    const double tc = tau[c];
+    double vr[MAXR];
 #pragma unroll
-      for (int i = 0; i < MAXR; ++i) {
-        const int r = rg + RG * i;
-        const double v = (r >= c && r < h) ? vbuf[r] : 0.0;
-        va[i] = v;
-        p += v * a[i];
+    for (int i = 0; i < MAXR; ++i) {
+      const int r = lane + 64 * i;
+      vr[i] = (r >= c && r < h) ? vb[r] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+      const int q = w * CPW + j;
+      if (q < nbw && q != c) {
+        double p = 0.0;
+#pragma unroll
+        for (int i = 0; i < MAXR; ++i) p = fma(vr[i], a[i][j], p);
+        p = wave_sum_d(p);
+        if (q > c) {
+          const double wq = tc * p;
+#pragma unroll
+          for (int i = 0; i < MAXR; ++i) a[i][j] -= vr[i] * wq;
+        } else if (lane == 0) {
+          Y[q * PT + c] = p;             // v_q^T v_c for q < c
+        }
       }
-      part[rg * PV + q] = p;
-    }
-    __syncthreads();
-    if (tid < nbw && tid != c) {
-      double t = 0.0;
-#pragma unroll
-      for (int k = 0; k < RG; ++k) t += part[k * PV + tid];
-      if (tid > c) wv[tid] = tc * t;
-      else Y[tid * PT + c] = t;            // v_q^T v_c for q < c
-    }
-    __syncthreads();
-    // 4. apply H = I - tau v v^T to the trailing columns
-    if (q > c && q < nbw && tc != 0.0) {
-      const double wq = wv[q];
-#pragma unroll
-      for (int i = 0; i < MAXR; ++i) a[i] -= va[i] * wq;
     }
   }
   // V into LDS (unit lower trapezoidal) and to global; R back into A
 #pragma unroll
   for (int i = 0; i < MAXR; ++i) {
-    const int r = rg + RG * i;
-    if (r < h && q < nbw) {
-      const double v = (r == q) ? 1.0 : (r > q ? a[i] : 0.0);
-      vsh[r * PV + q] = v;
-      Vout[(size_t)r * nbw + q] = v;
-      A[(size_t)(j0 + r) * n + j0 + q] = (r <= q) ? a[i] : 0.0;
+    const int r = lane + 64 * i;
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+      const int q = w * CPW + j;
+      if (r < h && q < nbw) {
+        const double v = (r == q) ? 1.0 : (r > q ? a[i][j] : 0.0);
+        vsh[r * PV + q] = v;
+        Vout[(size_t)r * nbw + q] = v;
+        A[(size_t)(j0 + r) * n + j0 + q] = (r <= q) ? a[i][j] : 0.0;
+      }
     }
   }
   __syncthreads();
@@ -249,14 +263,6 @@ __device__ __forceinline__ void qr_panel_body(double* A, int n, int j0, int nbw,
       if (row < h && col < nbw) VTout[(size_t)row * nbw + col] = acc[r];
     }
   }
-}
-
-template <int NBW, int MAXR>
-__global__ __launch_bounds__(256) void k_qr_panel(double* A, int n, int j0, int nbw, double* Vout,
-                                                  double* VTout, size_t cs) {
-  extern __shared__ double smem[];
-  const size_t co = (size_t)blockIdx.y * cs;
-  qr_panel_body<NBW, MAXR>(A + co, n, j0, nbw, Vout + co, VTout + co, smem);
 }
 
 // Rt[i][piv[j]] = R[i][j] / |R[i][i]| for j >= i; D[i] = |R[i][i]|
