@@ -62,6 +62,7 @@ struct dqmc_ctx {
   double *bins = nullptr, *prec_hist = nullptr, *prec_tot = nullptr, *logdet = nullptr;
   double *grad = nullptr, *gprec = nullptr;   // gradient rows [L][N] and the gradient pass's precision
   double* mpart = nullptr;                     // partial sums of the equal-time estimators
+  double* draws = nullptr;                     // (u, Delta, prefactor, s_new) per site of the current pass
   // time-displaced pass: GT0 and H = G0T^T (two buffers each), the 2N-column
   // right-hand sides of the re-anchoring solve, S(K, tau) of the current
   // configuration and its bin sums, partial records, A_a(0); the momentum
@@ -155,6 +156,7 @@ size_t layout_chain(dqmc_ctx* c, double* base) {
   P(c->grad, (size_t)c->L * N);
   P(c->gprec, 4);
   P(c->mpart, 4 * (size_t)((N + kMeasRows - 1) / kMeasRows));
+  P(c->draws, 4 * (size_t)c->L * N);
   for (int i = 0; i < 4; ++i) P(c->TD[i], NN);
   P(c->RHS2, 2 * NN);
   P(c->tdS, (size_t)(c->L + 1) * kTdStride);
@@ -299,10 +301,7 @@ dqmc_status update_slice(dqmc_ctx* c, int tau, int dir) {
     a.Gout = (c->Gcur == c->G) ? c->G2 : c->G;
     a.N = N; a.s0 = s0; a.bb = std::min(kBlock, N - s0);
     a.field_in = fin; a.field_out = fout;
-    a.sweep_ctr = c->counters + 2;
-    a.seed = c->m.seed; a.slot = ((unsigned long long)tau << 1) | (unsigned long long)dir;
-    a.coupling = c->m.coupling; a.alpha = c->m.alpha; a.n_col = c->m.n_col;
-    a.gauss = c->m.field == DQMC_FIELD_GAUSS; a.prop_width = c->m.prop_width;
+    a.draws = c->draws + 4 * (size_t)(tau - 1) * N;
     a.counters = c->counters;
     a.cs = c->cs;
     if (dqmc_status s = timing_begin(c, DQMC_KERNEL_BLOCK_UPDATE)) return s;
@@ -392,7 +391,10 @@ dqmc_status set_lds_limits(dqmc_ctx* c) {
 dqmc_status qr_udv(dqmc_ctx* c, double* M, const double* T_in, UDVp out) {
   const int N = c->N, nb = c->nb;
   double* Ap = c->S[4];
-  hipLaunchKernelGGL(k_colnorm_order, gridc(c, 1), dim3(1024), 0, c->stream, M, N, c->norms, c->piv, c->cs);
+  // column norms (partial rows in Zq, free until the trailing updates), then the ranks
+  const int nrb = (N + kColRows - 1) / kColRows;
+  hipLaunchKernelGGL(k_colnorm_part, gridc(c, (unsigned)nrb), dim3(256), 0, c->stream, M, N, c->Zq, c->cs);
+  hipLaunchKernelGGL(k_colnorm_order, gridc(c, 1), dim3(1024), 0, c->stream, c->Zq, nrb, N, c->norms, c->piv, c->cs);
   HIPCHK(hipGetLastError());
   hipLaunchKernelGGL(k_permute_cols, gridc(c, grid1((size_t)N * N)), dim3(256), 0, c->stream, Ap, M, c->piv, N,
                      c->cs);
@@ -584,6 +586,18 @@ dqmc_status measure(dqmc_ctx* c) {
   return DQMC_OK;
 }
 
+// Draws of every site of the coming pass, from the field as it stands (all
+// rows at the same place: the caller's buffer before the upward pass, the
+// second buffer before the downward pass).
+dqmc_status pass_draws(dqmc_ctx* c, int dir) {
+  const size_t n = (size_t)c->L * c->N;
+  hipLaunchKernelGGL(k_pass_draws, gridc(c, grid1(n)), dim3(256), 0, c->stream, field_row(c, 1), c->L, c->N,
+                     (unsigned long long)dir, c->m.coupling, c->m.alpha, c->m.n_col,
+                     c->m.field == DQMC_FIELD_GAUSS ? 1 : 0, c->m.prop_width, c->counters, c->draws, c->cs);
+  HIPCHK(hipGetLastError());
+  return DQMC_OK;
+}
+
 // One sweep (Algorithm 1): upward pass tau = 1..L, downward pass tau = L..1.
 // meas: bit 0 = equal-time estimators on every slice, bit 1 = the
 // time-displaced pass at the start of the sweep.
@@ -595,6 +609,7 @@ dqmc_status sweep_once(dqmc_ctx* c, int meas) {
   int hist = 0;
   c->row_alt.assign(L, 0);
   c->Gcur = c->G;
+  if (dqmc_status s = pass_draws(c, 0)) return s;
   for (int tau = 1; tau <= L; ++tau) {
     if (dqmc_status s = wrap_up(c, tau, c->G)) return s;
     if (dqmc_status s = update_slice(c, tau, 0)) return s;
@@ -610,6 +625,7 @@ dqmc_status sweep_once(dqmc_ctx* c, int meas) {
     if (meas & 1)
       if (dqmc_status s = measure(c)) return s;
   }
+  if (dqmc_status s = pass_draws(c, 1)) return s;
   for (int tau = L; tau >= 1; --tau) {
     if (dqmc_status s = update_slice(c, tau, 1)) return s;
     if (meas & 1)
@@ -1357,6 +1373,7 @@ bool layout_ok(const dqmc_ctx* c, const double* lo, const double* hi) {
        in(c->ipiv, N / 2 + 1, true) && in(c->bins, 4, true) && in(c->prec_hist, 2 * (size_t)c->nk + 2, true) &&
        in(c->prec_tot, 4, true) && in(c->logdet, 4, true) && in(c->grad, (size_t)c->L * N, true) && in(c->gprec, 4, true) &&
        in(c->mpart, 4 * (size_t)((N + kMeasRows - 1) / kMeasRows), true) &&
+       in(c->draws, 4 * (size_t)c->L * N, true) &&
        in(c->TD[0], NN, true) && in(c->TD[1], NN, true) && in(c->TD[2], NN, true) && in(c->TD[3], NN, true) &&
        in(c->RHS2, 2 * NN, true) && in(c->tdS, (size_t)(c->L + 1) * kTdStride, true) &&
        in(c->tdbins, (size_t)(c->L + 1) * kTdStride + 4, true) &&

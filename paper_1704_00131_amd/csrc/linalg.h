@@ -69,14 +69,31 @@ __global__ void k_transpose_scale(double* dst, const double* src, int n, const d
 }
 
 // -------------------------------------------------------- QR pre-pivoting ----
-// piv[p] = index of the column with the p-th largest 2-norm (ties: lower index)
-__global__ __launch_bounds__(1024) void k_colnorm_order(const double* M, int n, double* norms, int* piv, size_t cs) {
+// Column norms in two steps: k_colnorm_part sums the squares of kColRows rows
+// per workgroup (threads over columns, coalesced), k_colnorm_order adds the
+// partial rows in a fixed order and ranks the columns.
+constexpr int kColRows = 16;
+
+__global__ __launch_bounds__(256) void k_colnorm_part(const double* M, int n, double* part, size_t cs) {
   M += (size_t)blockIdx.y * cs;
+  part += (size_t)blockIdx.y * cs;
+  const int r0 = blockIdx.x * kColRows, r1 = min(n, r0 + kColRows);
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    double s = 0.0;
+    for (int r = r0; r < r1; ++r) { const double x = M[(size_t)r * n + j]; s += x * x; }
+    part[(size_t)blockIdx.x * n + j] = s;
+  }
+}
+
+// piv[p] = index of the column with the p-th largest 2-norm (ties: lower index)
+__global__ __launch_bounds__(1024) void k_colnorm_order(const double* part, int nblk, int n, double* norms, int* piv,
+                                                        size_t cs) {
+  part += (size_t)blockIdx.y * cs;
   norms += (size_t)blockIdx.y * cs;
   piv = reinterpret_cast<int*>(reinterpret_cast<double*>(piv) + (size_t)blockIdx.y * cs);
   for (int j = threadIdx.x; j < n; j += blockDim.x) {
     double s = 0.0;
-    for (int r = 0; r < n; ++r) { const double x = M[(size_t)r * n + j]; s += x * x; }
+    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * n + j];
     norms[j] = (s == s) ? s : INFINITY;   // a NaN column sorts first; ranks stay a permutation
   }
   __syncthreads();

@@ -27,12 +27,42 @@ struct BlockArgs {
   const double* field_in;            // field of slice tau before the block (N values)
   double* field_out;                 // field of slice tau after the block (may equal field_in only for
                                      // sites outside this block; distinct buffer otherwise)
-  const unsigned long long* sweep_ctr;   // unused: the counters carry the sweep number and the key
-  unsigned long long seed, slot;     // slot = counter word 2 = (tau << 1) | dir
-  double coupling, alpha; int n_col; int gauss; double prop_width;
+  const double* draws;               // slice tau of k_pass_draws' output: (u, Delta, prefactor, s_new) per site
   unsigned long long* counters;      // [0] proposals, [1] accepted, [2] sweep, [3] Philox key
   size_t cs;                         // per-chain stride (doubles) of every pointer above; chain = blockIdx.y
 };
+
+// Draws and ratio constants of every site of one pass (upward or downward
+// half of a sweep), computed before the pass: each site is visited once per
+// pass, so they depend only on the field at the start of the pass.  For site
+// i of slice tau, from Philox counter (TAG_FLIP, sweep, (tau << 1) | dir, i):
+//   u = u0; s_new = -s (Ising) or s + width (2 u1 - 1) (Gaussian);
+//   Delta = exp(coupling (s_new - s)) - 1;
+//   prefactor = exp(n_col coupling alpha (s_new - s) [- (s_new^2 - s^2)/2]).
+// out[(tau-1) N + i][0..3] = (u, Delta, prefactor, s_new); grid (ceil(L N / 256), chains).
+__global__ __launch_bounds__(256) void k_pass_draws(const double* field, int L, int N, unsigned long long dir,
+                                                    double coupling, double alpha, int n_col, int gauss,
+                                                    double prop_width, const unsigned long long* counters,
+                                                    double* out, size_t cs) {
+  const size_t co = (size_t)blockIdx.y * cs;
+  field += co;
+  out += co;
+  counters = reinterpret_cast<const unsigned long long*>(reinterpret_cast<const double*>(counters) + co);
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= L * N) return;
+  const int tau = e / N + 1, i = e % N;
+  const Philox4 r = philox4x64_10(TAG_FLIP, counters[2], ((unsigned long long)tau << 1) | dir, (unsigned long long)i,
+                                  counters[3], 0ull);
+  const double u0 = unit_double(r.w[0]), u1 = unit_double(r.w[1]);
+  const double s = field[e];
+  double sn, extra;
+  if (gauss) { sn = s + prop_width * (2.0 * u1 - 1.0); extra = -0.5 * (sn * sn - s * s); }
+  else { sn = -s; extra = 0.0; }
+  out[4 * (size_t)e] = u0;
+  out[4 * (size_t)e + 1] = exp(coupling * (sn - s)) - 1.0;
+  out[4 * (size_t)e + 2] = exp(n_col * coupling * alpha * (sn - s) + extra);
+  out[4 * (size_t)e + 3] = sn;
+}
 
 __device__ __forceinline__ double ipow(double r, int n) {
   double p = 1.0;
@@ -81,7 +111,7 @@ __global__ __launch_bounds__(256) void k_block_update(BlockArgs a) {
   const int tilesN = (N + 31) >> 5;
   if (a.cs) {
     const size_t co = (size_t)blockIdx.y * a.cs;
-    a.Gin += co; a.Gout += co; a.field_in += co; a.field_out += co;
+    a.Gin += co; a.Gout += co; a.field_in += co; a.field_out += co; a.draws += co;
     a.counters = reinterpret_cast<unsigned long long*>(reinterpret_cast<double*>(a.counters) + co);
   }
   const int I0 = (blockIdx.x / tilesN) << 5, J0 = (blockIdx.x % tilesN) << 5;
@@ -99,19 +129,12 @@ __global__ __launch_bounds__(256) void k_block_update(BlockArgs a) {
     double c[32];
 #pragma unroll
     for (int y = 0; y < 32; ++y) c[y] = (x < bb && y < bb) ? a.Gin[(size_t)(s0 + x) * N + s0 + y] : 0.0;
-    // draws and ratio constants of site x
+    // draws and ratio constants of site x (from k_pass_draws)
     double u = 2.0, dl = 0.0, pr = 0.0, sold = 0.0, snew = 0.0;
     if (x < bb) {
-      const Philox4 r = philox4x64_10(TAG_FLIP, a.counters[2], a.slot, (unsigned long long)(s0 + x), a.counters[3],
-                                      0ull);
-      const double u0 = unit_double(r.w[0]), u1 = unit_double(r.w[1]);
+      const double* d = a.draws + 4 * (size_t)(s0 + x);
+      u = d[0]; dl = d[1]; pr = d[2]; snew = d[3];
       sold = a.field_in[s0 + x];
-      double extra;
-      if (a.gauss) { snew = sold + a.prop_width * (2.0 * u1 - 1.0); extra = -0.5 * (snew * snew - sold * sold); }
-      else { snew = -sold; extra = 0.0; }
-      u = u0;
-      dl = exp(a.coupling * (snew - sold)) - 1.0;
-      pr = exp(NCOL * a.coupling * a.alpha * (snew - sold) + extra);
     }
     int nacc = 0, myacc = 0;
 #pragma unroll
