@@ -74,6 +74,14 @@ __device__ __forceinline__ double block_max(double v, double* red) {
   return s;
 }
 
+// Both halves of a double read from one lane (uniform lane index).
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // ------------------------------------------------- DPP wave reductions ----
 // Whole-wave reductions on VALU data-parallel moves instead of LDS permutes:
 // xor-1 and xor-2 quad permutes, the half-row and row mirrors (max/sum over

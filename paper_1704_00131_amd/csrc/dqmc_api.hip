@@ -344,23 +344,24 @@ dqmc_status launch_qr_panel(dqmc_ctx* c, double* Ap, int j0, int nbw, double* V,
 
 template <int NBW, int MAXR>
 void lu_panel_reg(dqmc_ctx* c, double* X, int j0, int nbw) {
-  hipLaunchKernelGGL((k_lu_panel_reg<NBW, MAXR>), gridc(c, 1), dim3(256), 0, c->stream, X, c->N, j0, nbw, c->ipiv,
-                     c->err_flag, c->cs);
+  const int h = c->N - j0;
+  hipLaunchKernelGGL((k_lu_panel_reg<NBW, MAXR>), gridc(c, 1), dim3(256), sizeof(double) * 2 * (size_t)h, c->stream, X,
+                     c->N, j0, nbw, c->ipiv, c->err_flag, c->cs);
 }
 
-// Panel LU of columns j0 .. j0 + nbw (nbw <= c->nb): the register-resident
-// kernel, with ceil(h / 256) rows per thread.
+// Panel LU of columns j0 .. j0 + nbw (nbw <= c->nb): rows per lane =
+// ceil(h / 64), rounded up to the instantiated counts.
 dqmc_status launch_lu_panel(dqmc_ctx* c, double* X, int j0, int nbw) {
-  const int h = c->N - j0, maxr = (h + 255) / 256;
-  if (c->nb == 32 && maxr == 1) lu_panel_reg<32, 1>(c, X, j0, nbw);
-  else if (c->nb == 32 && maxr == 2) lu_panel_reg<32, 2>(c, X, j0, nbw);
-  else if (c->nb == 16 && maxr == 1) lu_panel_reg<16, 1>(c, X, j0, nbw);
-  else if (c->nb == 16 && maxr == 2) lu_panel_reg<16, 2>(c, X, j0, nbw);
-  else if (c->nb == 16 && maxr == 3) lu_panel_reg<16, 3>(c, X, j0, nbw);
-  else if (c->nb == 8 && maxr == 1) lu_panel_reg<8, 1>(c, X, j0, nbw);
-  else if (c->nb == 8 && maxr == 2) lu_panel_reg<8, 2>(c, X, j0, nbw);
-  else if (c->nb == 8 && maxr == 3) lu_panel_reg<8, 3>(c, X, j0, nbw);
-  else if (c->nb == 8 && maxr == 4) lu_panel_reg<8, 4>(c, X, j0, nbw);
+  const int rows = (c->N - j0 + 63) / 64;
+  if (c->nb == 32 && rows <= 2) lu_panel_reg<32, 2>(c, X, j0, nbw);
+  else if (c->nb == 32 && rows <= 4) lu_panel_reg<32, 4>(c, X, j0, nbw);
+  else if (c->nb == 32 && rows <= 6) lu_panel_reg<32, 6>(c, X, j0, nbw);
+  else if (c->nb == 16 && rows <= 4) lu_panel_reg<16, 4>(c, X, j0, nbw);
+  else if (c->nb == 16 && rows <= 8) lu_panel_reg<16, 8>(c, X, j0, nbw);
+  else if (c->nb == 16 && rows <= 12) lu_panel_reg<16, 12>(c, X, j0, nbw);
+  else if (c->nb == 8 && rows <= 4) lu_panel_reg<8, 4>(c, X, j0, nbw);
+  else if (c->nb == 8 && rows <= 8) lu_panel_reg<8, 8>(c, X, j0, nbw);
+  else if (c->nb == 8 && rows <= 16) lu_panel_reg<8, 16>(c, X, j0, nbw);
   else return fail(c, DQMC_E_UNSUPPORTED, "no LU panel kernel for this size");
   HIPCHK(hipGetLastError());
   return DQMC_OK;

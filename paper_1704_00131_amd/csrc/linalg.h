@@ -302,24 +302,27 @@ __global__ void k_build_rt(const double* R, const int* piv, int n, double* Rt, d
 }
 
 // ----------------------------------------------------------- LU panel ----
-// Register-resident panel LU with partial pivoting of columns j0..j0+nbw-1 of
-// X (ld n) over rows j0..n-1: the pivot is the largest |a| among the
-// remaining rows, ties to the lowest position; ipiv[j0+c] = global pivot row;
-// multipliers by the pivot's reciprocal.  k_lu_swap applies the interchanges
-// outside the panel.  Thread t keeps rows t,
-// t + 256, ... (MAXR of them, NBW columns each) in registers for the whole
-// panel; column c is picked out of the registers by selects, so every
-// register index is static.  Pivoting is virtual: each held row carries its
-// current position, a pivot step swaps two positions, and the rows are
-// written back to their final positions.  Per column: a wave argmax on DPP
-// moves, one barrier, the pivot row broadcast through LDS, a second barrier,
-// then the elimination in registers.  Columns c >= nbw (a ragged last panel) are left
-// out.
+// Panel LU with partial pivoting of columns j0..j0+nbw-1 of X (ld n) over rows
+// j0..n-1: the pivot is the largest |a| among the remaining rows, ties to the
+// lowest position; ipiv[j0+c] = global pivot row; multipliers by the pivot's
+// reciprocal.  k_lu_swap applies the interchanges outside the panel.
+//
+// Layout: wave w owns the columns w*NBW/4 .. (w+1)*NBW/4 - 1 and lane l the rows
+// l, l + 64, ... (MAXR of them), in registers; every wave holds the same rows
+// in the same lanes.  Pivoting is virtual: each held row carries its current
+// position, a pivot step swaps two positions (every wave keeps the same copy),
+// and the rows are written back to their final positions.  Per column c the
+// owning wave finds the pivot (DPP wave max, then the lowest position holding
+// it), forms the multipliers of its rows and publishes them with the pivot's
+// lane and register through LDS (two alternating buffers); after one barrier
+// every wave reads the pivot row from its own registers by readlane and
+// eliminates its columns.  Columns c >= nbw (a ragged last panel) are left out.
 template <int NBW, int MAXR>
 __global__ __launch_bounds__(256) void k_lu_panel_reg(double* X, int n, int j0, int nbw, int* ipiv, int* err,
                                                       size_t cs) {
-  __shared__ double cand_v[4], prow[NBW];
-  __shared__ int cand_i[4];
+  extern __shared__ double smem[];   // 2 x h multipliers
+  constexpr int CPW = NBW / 4;
+  __shared__ int piv_s[2][3];        // pivot position, lane, register
   {
     const size_t co = (size_t)blockIdx.y * cs;
     X += co;
@@ -327,74 +330,91 @@ __global__ __launch_bounds__(256) void k_lu_panel_reg(double* X, int n, int j0, 
     err = reinterpret_cast<int*>(reinterpret_cast<double*>(err) + co);
   }
   const int h = n - j0, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  double a[MAXR][NBW];
+  double a[MAXR][CPW];
   int pos[MAXR];
 #pragma unroll
   for (int i = 0; i < MAXR; ++i) {
-    const int r = tid + 256 * i;
+    const int r = lane + 64 * i;
     pos[i] = (r < h) ? r : 0x7fffffff;
 #pragma unroll
-    for (int q = 0; q < NBW; ++q) a[i][q] = (r < h && q < nbw) ? X[(size_t)(j0 + r) * n + j0 + q] : 0.0;
+    for (int j = 0; j < CPW; ++j) {
+      const int q = w * CPW + j;
+      a[i][j] = (r < h && q < nbw) ? X[(size_t)(j0 + r) * n + j0 + q] : 0.0;
+    }
   }
   const int ncol = min(nbw, h);
   for (int c = 0; c < ncol; ++c) {
-    double colv[MAXR];
+    double* lb = smem + (c & 1) * (size_t)h;
+    int* ps = piv_s[c & 1];
+    const int cw = c / CPW, cj = c % CPW;
+    if (w == cw) {
+      double colv[MAXR];
+      double best = -1.0;
+      int bi = 0x7fffffff;
 #pragma unroll
-    for (int i = 0; i < MAXR; ++i) {
-      double v = 0.0;
+      for (int i = 0; i < MAXR; ++i) {
+        double v = 0.0;
 #pragma unroll
-      for (int q = 0; q < NBW; ++q) v = (q == c) ? a[i][q] : v;
-      colv[i] = v;
-    }
-    // argmax over positions >= c
-    double best = -1.0;
-    int bi = 0x7fffffff;
-#pragma unroll
-    for (int i = 0; i < MAXR; ++i) {
-      if (pos[i] >= c && pos[i] < h) {
-        const double v = fabs(colv[i]);
-        if (v > best || (v == best && pos[i] < bi)) { best = v; bi = pos[i]; }
-      }
-    }
-    // wave argmax on DPP: the largest value, then the lowest position holding it
-    const double wm = wave_max_d(best);
-    const int wi = wave_min_i((best == wm && best >= 0.0) ? bi : 0x7fffffff);
-    if (lane == 0) { cand_v[w] = wm; cand_i[w] = wi; }
-    __syncthreads();
-    double b = cand_v[0];
-    int pp = cand_i[0];
-#pragma unroll
-    for (int k = 1; k < 4; ++k)
-      if (cand_v[k] > b || (cand_v[k] == b && cand_i[k] < pp)) { b = cand_v[k]; pp = cand_i[k]; }
-    // no finite candidate (a NaN column): keep the row and flag the failure
-    if (!(b >= 0.0) || pp < c || pp >= h) pp = c;
-    if (tid == 0) {
-      ipiv[j0 + c] = j0 + pp;
-      if (!(b > 0.0)) atomicOr(err, 4);
-    }
-    // the row at position pp becomes the pivot row (position c); the row at
-    // position c moves to pp
-#pragma unroll
-    for (int i = 0; i < MAXR; ++i) {
-      if (pos[i] == pp) {
-#pragma unroll
-        for (int q = 0; q < NBW; ++q) prow[q] = a[i][q];
-        pos[i] = c;
-      } else if (pos[i] == c) {
-        pos[i] = pp;
-      }
-    }
-    __syncthreads();
-    const double inv = 1.0 / prow[c];
-#pragma unroll
-    for (int i = 0; i < MAXR; ++i) {
-      if (pos[i] > c && pos[i] < h) {
-        const double l = colv[i] * inv;
-#pragma unroll
-        for (int q = 0; q < NBW; ++q) {
-          if (q == c) a[i][q] = l;
-          else if (q > c) a[i][q] -= l * prow[q];
+        for (int j = 0; j < CPW; ++j) v = (j == cj) ? a[i][j] : v;
+        colv[i] = v;
+        if (pos[i] >= c && pos[i] < h) {
+          const double av = fabs(v);
+          if (av > best || (av == best && pos[i] < bi)) { best = av; bi = pos[i]; }
         }
+      }
+      const double wm = wave_max_d(best);
+      int pp = wave_min_i((best == wm && best >= 0.0) ? bi : 0x7fffffff);
+      // no finite candidate (a NaN column): keep the row and flag the failure
+      if (!(wm >= 0.0) || pp < c || pp >= h) pp = c;
+      // the lane and register holding position pp, and the pivot value
+      int hit = -1;
+      double pv = 0.0;
+#pragma unroll
+      for (int i = 0; i < MAXR; ++i)
+        if (pos[i] == pp) { hit = i; pv = colv[i]; }
+      const unsigned long long mask = __ballot(hit >= 0);
+      const int hl = __ffsll((long long)mask) - 1;
+      const int hs = __builtin_amdgcn_readlane(hit, hl);
+      const double pivot = readlane_d(pv, hl);
+      const double inv = 1.0 / pivot;
+      // multipliers of the rows that stay below the pivot (position > c after the swap)
+#pragma unroll
+      for (int i = 0; i < MAXR; ++i) {
+        const int r = lane + 64 * i;
+        const int np = (pos[i] == pp) ? c : (pos[i] == c ? pp : pos[i]);
+        const double l = (np > c && np < h) ? colv[i] * inv : 0.0;
+        if (r < h) lb[r] = l;
+        if (np > c && np < h) {
+#pragma unroll
+          for (int j = 0; j < CPW; ++j) if (j == cj) a[i][j] = l;
+        }
+      }
+      if (lane == 0) {
+        ps[0] = pp; ps[1] = hl; ps[2] = hs;
+        ipiv[j0 + c] = j0 + pp;
+        if (!(wm > 0.0)) atomicOr(err, 4);
+      }
+    }
+    __syncthreads();
+    const int pp = ps[0], hl = ps[1], hs = ps[2];
+#pragma unroll
+    for (int i = 0; i < MAXR; ++i) pos[i] = (pos[i] == pp) ? c : (pos[i] == c ? pp : pos[i]);
+    double lr[MAXR];
+#pragma unroll
+    for (int i = 0; i < MAXR; ++i) {
+      const int r = lane + 64 * i;
+      lr[i] = (r < h) ? lb[r] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+      const int q = w * CPW + j;
+      if (q > c && q < nbw) {
+        double pr = 0.0;
+#pragma unroll
+        for (int i = 0; i < MAXR; ++i) pr = (i == hs) ? a[i][j] : pr;
+        const double u = readlane_d(pr, hl);
+#pragma unroll
+        for (int i = 0; i < MAXR; ++i) a[i][j] -= lr[i] * u;   // lr = 0 for rows not below the pivot
       }
     }
   }
@@ -402,8 +422,10 @@ __global__ __launch_bounds__(256) void k_lu_panel_reg(double* X, int n, int j0, 
   for (int i = 0; i < MAXR; ++i) {
     if (pos[i] < h) {
 #pragma unroll
-      for (int q = 0; q < NBW; ++q)
-        if (q < nbw) X[(size_t)(j0 + pos[i]) * n + j0 + q] = a[i][q];
+      for (int j = 0; j < CPW; ++j) {
+        const int q = w * CPW + j;
+        if (q < nbw) X[(size_t)(j0 + pos[i]) * n + j0 + q] = a[i][j];
+      }
     }
   }
 }

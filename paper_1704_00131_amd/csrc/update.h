@@ -70,13 +70,6 @@ __device__ __forceinline__ double ipow(double r, int n) {
   return p;
 }
 
-// Both halves of a double read from one lane (uniform lane index).
-__device__ __forceinline__ double readlane_d(double v, int l) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
 
 // One workgroup per 32 x 32 tile (I, J) of G.  Every workgroup takes the same
 // sequential decisions of block S (identical arithmetic, identical results),
