@@ -123,6 +123,26 @@ __device__ __forceinline__ double wave_sum_d(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// K independent wave sums, each DPP round applied to all K values before the
+// next, so their latencies overlap; every lane gets the K totals.
+template <int K>
+__device__ __forceinline__ void wave_sum_d_n(double (&v)[K]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_d<0xB1, 0xF>(v[k], 0.0);
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_d<0x4E, 0xF>(v[k], 0.0);
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_d<0x141, 0xF>(v[k], 0.0);
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_d<0x140, 0xF>(v[k], 0.0);
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_d<0x142, 0xA>(v[k], 0.0);
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_d<0x143, 0xC>(v[k], 0.0);
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = readlane_d(v[k], 63);
+}
+
 __device__ __forceinline__ int wave_min_i(int v) {
   const int big = 0x7fffffff;
   v = min(v, __builtin_amdgcn_update_dpp(big, v, 0xB1, 0xF, 0xF, false));

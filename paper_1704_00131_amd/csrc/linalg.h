@@ -181,8 +181,10 @@ __global__ __launch_bounds__(256) void k_qr_panel(double* A, int n, int j0, int 
         if (r > c && r < h) s += v * v;
         if (r == c) x0 = v;
       }
-      s = wave_sum_d(s);
-      x0 = wave_sum_d(x0);   // exactly one lane holds it
+      double sx[2] = {s, x0};
+      wave_sum_d_n<2>(sx);   // x0: exactly one lane holds it
+      s = sx[0];
+      x0 = sx[1];
       double beta, tc, scal;
       if (s == 0.0) { tc = 0.0; beta = x0; scal = 0.0; }
       else {
@@ -214,21 +216,24 @@ __global__ __launch_bounds__(256) void k_qr_panel(double* A, int n, int j0, int 
       const int r = lane + 64 * i;
       vr[i] = (r >= c && r < h) ? vb[r] : 0.0;
     }
+    // dot products of v with all own columns at once (their wave sums overlap)
+    double p[CPW];
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+      p[j] = 0.0;
+#pragma unroll
+      for (int i = 0; i < MAXR; ++i) p[j] = fma(vr[i], a[i][j], p[j]);
+    }
+    wave_sum_d_n<CPW>(p);
 #pragma unroll
     for (int j = 0; j < CPW; ++j) {
       const int q = w * CPW + j;
-      if (q < nbw && q != c) {
-        double p = 0.0;
+      if (q > c && q < nbw) {
+        const double wq = tc * p[j];
 #pragma unroll
-        for (int i = 0; i < MAXR; ++i) p = fma(vr[i], a[i][j], p);
-        p = wave_sum_d(p);
-        if (q > c) {
-          const double wq = tc * p;
-#pragma unroll
-          for (int i = 0; i < MAXR; ++i) a[i][j] -= vr[i] * wq;
-        } else if (lane == 0) {
-          Y[q * PT + c] = p;             // v_q^T v_c for q < c
-        }
+        for (int i = 0; i < MAXR; ++i) a[i][j] -= vr[i] * wq;
+      } else if (q < c && lane == 0) {
+        Y[q * PT + c] = p[j];            // v_q^T v_c for q < c
       }
     }
   }
