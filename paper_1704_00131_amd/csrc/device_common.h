@@ -143,6 +143,83 @@ __device__ __forceinline__ void wave_sum_d_n(double (&v)[K]) {
   for (int k = 0; k < K; ++k) v[k] = readlane_d(v[k], 63);
 }
 
+// ------------------------------------------- several sums in one pass ----
+// Lane exchanges that write every lane: DPP quad permutes (xor 1, xor 2), the
+// half-row mirror (lane i of 8 <-> 7 - i), a row rotation by 8 (xor 8), and the
+// gfx950 permlane swaps across rows (xor 16) and halves (xor 32).
+template <int CTRL>
+__device__ __forceinline__ double dpp_all(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// v + (v of the lane 16 away): permlane16_swap of v with itself leaves the
+// even-row data in one result and the odd-row data in the other.
+__device__ __forceinline__ double add_xor16(double v) {
+  const long long b = __double_as_longlong(v);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)b, (unsigned)b, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+  const double x = __longlong_as_double(((long long)hi[0] << 32) | lo[0]);
+  const double y = __longlong_as_double(((long long)hi[1] << 32) | lo[1]);
+  return x + y;
+}
+
+__device__ __forceinline__ double add_xor32(double v) {
+  const long long b = __double_as_longlong(v);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)b, (unsigned)b, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+  const double x = __longlong_as_double(((long long)hi[0] << 32) | lo[0]);
+  const double y = __longlong_as_double(((long long)hi[1] << 32) | lo[1]);
+  return x + y;
+}
+
+// One halving step of a multi-sum: lanes whose BIT is 0 keep the first half of
+// the values, the others the second half, and each adds its partner's copy of
+// the kept half (the partner of CTRL differs in BIT and in no earlier one).
+template <int CTRL, int BIT, int N>
+__device__ __forceinline__ void split_half(double* x, int lane) {
+  const bool up = (lane >> BIT) & 1;
+#pragma unroll
+  for (int k = 0; k < N / 2; ++k) {
+    const double lo = x[k], hi = x[k + N / 2];
+    const double send = up ? lo : hi;
+    const double keep = up ? hi : lo;
+    x[k] = keep + dpp_all<CTRL>(send);
+  }
+}
+
+// K (2, 4 or 8) wave sums at once by recursive halving: the split steps leave
+// one value per lane, value j in the lane whose bits (2, 0, 1) spell j from the
+// top; the rest of the lanes are summed by exchanges, and every lane reads the
+// K totals from the lanes that hold them.  About 10 exchanges for K = 8 where
+// K separate reductions take 6 K.
+template <int K>
+__device__ __forceinline__ void wave_sums(double (&v)[K]) {
+  static_assert(K == 2 || K == 4 || K == 8, "K must be 2, 4 or 8");
+  const int lane = threadIdx.x & 63;
+  double x[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) x[k] = v[k];
+  split_half<0x141, 2, K>(x, lane);                       // half-row mirror: bit 2
+  if constexpr (K >= 4) split_half<0xB1, 0, K / 2>(x, lane);   // xor 1: bit 0
+  if constexpr (K >= 8) split_half<0x4E, 1, K / 4>(x, lane);   // xor 2: bit 1
+  double t = x[0];
+  if constexpr (K < 4) t += dpp_all<0xB1>(t);      // xor 1
+  if constexpr (K < 8) t += dpp_all<0x4E>(t);      // xor 2
+  t += dpp_all<0x128>(t);                           // row rotate by 8: xor 8
+  t = add_xor16(t);
+  t = add_xor32(t);
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    int l = ((j / (K / 2)) & 1) << 2;
+    if constexpr (K >= 4) l |= (j / (K / 4)) & 1;
+    if constexpr (K >= 8) l |= (j & 1) << 1;
+    v[j] = readlane_d(t, l);
+  }
+}
+
 __device__ __forceinline__ int wave_min_i(int v) {
   const int big = 0x7fffffff;
   v = min(v, __builtin_amdgcn_update_dpp(big, v, 0xB1, 0xF, 0xF, false));

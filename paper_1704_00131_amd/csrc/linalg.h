@@ -122,69 +122,71 @@ __global__ void k_permute_cols(double* dst, const double* src, const int* piv, i
 // Householder QR of one panel (columns j0..j0+nbw-1, rows j0..n-1 of A, ld n)
 // by one workgroup, with the compact-WY output V (h x nbw, ld nbw, unit lower
 // trapezoidal), VT = V T (T upper triangular, forward column-wise, the dlarft
-// convention) and R in place (zeros below the diagonal).  Householder
-// convention of LAPACK's dlarfg: for x = (x0, x'), beta = -sign(x0) |x|,
+// convention) and the R entries on and above the diagonal in place (entries
+// below it are left as they are: nothing reads them).  Householder convention
+// of LAPACK's dlarfg: for x = (x0, x'), beta = -sign(x0) |x|,
 // tau = (beta - x0)/beta, v = (1, x' / (x0 - beta)); tau = 0 when x' = 0.
 //
-// Layout: wave w owns the columns w*NBW/4 .. (w+1)*NBW/4 - 1 of the panel and
-// lane l the rows l, l + 64, ... (MAXR of them), in registers.  Per column c:
-// the owning wave forms the reflector (norm by a DPP wave sum), writes it to
-// LDS (two alternating buffers) and the workgroup passes one barrier; every
-// wave then takes the dot products with its own columns by DPP wave sums, so
-// no LDS or barrier is needed for them, and applies the reflector in
-// registers (v_q^T v_c for q < c goes to Y for the T recurrence).
+// Layout: the panel is staged in LDS (vsh, h x (NBW+1)) by coalesced loads;
+// wave w owns the columns w*NBW/4 .. (w+1)*NBW/4 - 1 and lane l the rows
+// l, l + 64, ... (MAXR of them), in registers.  Per column c: the owning wave
+// reads column c from vsh, forms the reflector (norm and x0 by one two-value
+// wave sum) and writes v_c over column c of vsh, where it stays as column c of
+// V; one barrier; every wave takes the dot products of v_c with all its own
+// columns in one multi-value wave sum and applies the reflector in registers,
+// and the owner of column c+1 writes that column back to vsh for the next
+// step.  After the loop: Y = V^T V by MFMA, the T recurrence
+// T[t][i] = -tau_i sum_{k<i} T[t][k] Y[k][i] row by row (each lane one row,
+// the two halves of the wave splitting k), and VT = V T by MFMA.
 template <int NBW>
 __host__ __device__ inline size_t qr_panel_lds(int h) {
-  return (size_t)h * (NBW + 1) + 2 * (size_t)h + 2 * 32 * 33 + 64;
+  return (size_t)h * (NBW + 1) + 2 * (size_t)NBW * (NBW + 1) + 2 * NBW;
 }
 
 template <int NBW, int MAXR>
 __global__ __launch_bounds__(256) void k_qr_panel(double* A, int n, int j0, int nbw, double* Vout,
                                                   double* VTout, size_t cs) {
   extern __shared__ double smem[];
-  constexpr int CPW = NBW / 4, PT = 33, PV = NBW + 1;
+  constexpr int CPW = NBW / 4, PV = NBW + 1, PY = NBW + 1;
   {
     const size_t co = (size_t)blockIdx.y * cs;
     A += co; Vout += co; VTout += co;
   }
-  const int h = n - j0, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  double* vsh = smem;                       // h x PV: V at the end
-  double* vbuf = vsh + (size_t)h * PV;      // 2 x h: reflectors of even / odd columns
-  double* T = vbuf + 2 * (size_t)h;         // 32 x 33
-  double* Y = T + 32 * PT;                  // 32 x 33
-  double* tau = Y + 32 * PT;                // 32
+  const int h = n - j0, tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  double* vsh = smem;                       // h x PV: the panel, then V
+  double* Ym = vsh + (size_t)h * PV;        // NBW x PY: strictly upper V^T V
+  double* Tm = Ym + NBW * PY;               // NBW x PY: T
+  double* tau = Tm + NBW * PY;              // NBW
+  double* bet = tau + NBW;                  // NBW: diagonal of R
+  for (int e = tid; e < h * NBW; e += 256) {
+    const int r = e / NBW, q = e % NBW;
+    vsh[r * PV + q] = (q < nbw) ? A[(size_t)(j0 + r) * n + j0 + q] : 0.0;
+  }
+  for (int e = tid; e < NBW * PY; e += 256) Ym[e] = 0.0;
+  if (tid < NBW) { tau[tid] = 0.0; bet[tid] = 0.0; }   // columns >= nbw stay inert
+  __syncthreads();
   double a[MAXR][CPW];
 #pragma unroll
   for (int i = 0; i < MAXR; ++i) {
     const int r = lane + 64 * i;
 #pragma unroll
-    for (int j = 0; j < CPW; ++j) {
-      const int q = w * CPW + j;
-      a[i][j] = (r < h && q < nbw) ? A[(size_t)(j0 + r) * n + j0 + q] : 0.0;
-    }
+    for (int j = 0; j < CPW; ++j) a[i][j] = (r < h) ? vsh[r * PV + w * CPW + j] : 0.0;
   }
-  for (int e = tid; e < 32 * PT; e += 256) { T[e] = 0.0; Y[e] = 0.0; }
   const int ncol = min(nbw, h);
   for (int c = 0; c < ncol; ++c) {
-    double* vb = vbuf + (c & 1) * (size_t)h;
-    const int cw = c / CPW, cj = c % CPW;
-    if (w == cw) {
+    if (w == c / CPW) {
       double colv[MAXR];
-      double s = 0.0, x0 = 0.0;
+      double sx[2] = {0.0, 0.0};   // sum of squares below c, x0
 #pragma unroll
       for (int i = 0; i < MAXR; ++i) {
-        double v = 0.0;
-#pragma unroll
-        for (int j = 0; j < CPW; ++j) v = (j == cj) ? a[i][j] : v;
-        colv[i] = v;
         const int r = lane + 64 * i;
-        if (r > c && r < h) s += v * v;
-        if (r == c) x0 = v;
+        colv[i] = (r < h) ? vsh[r * PV + c] : 0.0;
+        if (r > c) sx[0] = fma(colv[i], colv[i], sx[0]);
+        if (r == c) sx[1] = colv[i];
       }
-      double sx[2] = {s, x0};
-      wave_sum_d_n<2>(sx);   // x0: exactly one lane holds it
-      s = sx[0];
-      x0 = sx[1];
+      wave_sums<2>(sx);
+      const double s = sx[0], x0 = sx[1];
       double beta, tc, scal;
       if (s == 0.0) { tc = 0.0; beta = x0; scal = 0.0; }
       else {
@@ -193,20 +195,12 @@ __global__ __launch_bounds__(256) void k_qr_panel(double* A, int n, int j0, int 
         tc = (beta - x0) / beta;
         scal = 1.0 / (x0 - beta);
       }
-      // reflector v (v_c = 1, zero above c) into LDS; column c keeps v below
-      // the diagonal and beta on it
 #pragma unroll
       for (int i = 0; i < MAXR; ++i) {
         const int r = lane + 64 * i;
-        if (r < h) {
-          const double v = (r > c) ? colv[i] * scal : (r == c ? 1.0 : 0.0);
-          vb[r] = v;
-          const double nv = (r > c) ? v : (r == c ? beta : colv[i]);
-#pragma unroll
-          for (int j = 0; j < CPW; ++j) if (j == cj) a[i][j] = nv;
-        }
+        if (r < h) vsh[r * PV + c] = (r > c) ? colv[i] * scal : (r == c ? 1.0 : 0.0);
       }
-      if (lane == 0) tau[c] = tc;
+      if (lane == 0) { tau[c] = tc; bet[c] = beta; }
     }
     __syncthreads();
     const double tc = tau[c];
@@ -214,9 +208,8 @@ __global__ __launch_bounds__(256) void k_qr_panel(double* A, int n, int j0, int 
 #pragma unroll
     for (int i = 0; i < MAXR; ++i) {
       const int r = lane + 64 * i;
-      vr[i] = (r >= c && r < h) ? vb[r] : 0.0;
+      vr[i] = (r < h) ? vsh[r * PV + c] : 0.0;
     }
-    // dot products of v with all own columns at once (their wave sums overlap)
     double p[CPW];
 #pragma unroll
     for (int j = 0; j < CPW; ++j) {
@@ -224,65 +217,105 @@ __global__ __launch_bounds__(256) void k_qr_panel(double* A, int n, int j0, int 
 #pragma unroll
       for (int i = 0; i < MAXR; ++i) p[j] = fma(vr[i], a[i][j], p[j]);
     }
-    wave_sum_d_n<CPW>(p);
+    wave_sums<CPW>(p);
 #pragma unroll
     for (int j = 0; j < CPW; ++j) {
       const int q = w * CPW + j;
       if (q > c && q < nbw) {
         const double wq = tc * p[j];
 #pragma unroll
-        for (int i = 0; i < MAXR; ++i) a[i][j] -= vr[i] * wq;
-      } else if (q < c && lane == 0) {
-        Y[q * PT + c] = p[j];            // v_q^T v_c for q < c
+        for (int i = 0; i < MAXR; ++i) a[i][j] = fma(-vr[i], wq, a[i][j]);
+        if (q == c + 1) {
+#pragma unroll
+          for (int i = 0; i < MAXR; ++i) {
+            const int r = lane + 64 * i;
+            if (r < h) vsh[r * PV + q] = a[i][j];
+          }
+        }
       }
     }
   }
-  // V into LDS (unit lower trapezoidal) and to global; R back into A
+  // R on and above the diagonal (rows < nbw <= 64 live in the first row group)
 #pragma unroll
-  for (int i = 0; i < MAXR; ++i) {
-    const int r = lane + 64 * i;
+  for (int j = 0; j < CPW; ++j) {
+    const int q = w * CPW + j;
+    if (q < nbw && lane <= q) A[(size_t)(j0 + lane) * n + j0 + q] = (lane == q) ? bet[q] : a[0][j];
+  }
+  __syncthreads();
+  // Y = V^T V, upper 16 x 16 tiles (I <= J) on waves 0..2, four accumulators
+  constexpr int NT = (NBW + 15) / 16;
+  {
+    int I = -1, J = -1;
+    if (NT == 1) { if (w == 0) { I = 0; J = 0; } }
+    else if (w < 3) { I = (w == 2) ? 1 : 0; J = (w == 0) ? 0 : 1; }
+    if (I >= 0) {
+      const int m = lane & 15, kk = lane >> 4;
+      const int ca = I * 16 + m, cb = J * 16 + m;
+      v4d acc[4];
 #pragma unroll
-    for (int j = 0; j < CPW; ++j) {
-      const int q = w * CPW + j;
-      if (r < h && q < nbw) {
-        const double v = (r == q) ? 1.0 : (r > q ? a[i][j] : 0.0);
-        vsh[r * PV + q] = v;
-        Vout[(size_t)r * nbw + q] = v;
-        A[(size_t)(j0 + r) * n + j0 + q] = (r <= q) ? a[i][j] : 0.0;
+      for (int u = 0; u < 4; ++u) acc[u] = v4d{0.0, 0.0, 0.0, 0.0};
+      for (int r0 = 0; r0 < h; r0 += 16) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int r = r0 + 4 * u + kk;
+          const double av = (r < h && ca < NBW) ? vsh[r * PV + ca] : 0.0;
+          const double bv = (r < h && cb < NBW) ? vsh[r * PV + cb] : 0.0;
+          acc[u] = mfma_f64_16x16x4(av, bv, acc[u]);
+        }
+      }
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int k = I * 16 + kk + 4 * rr, i = J * 16 + m;
+        const double y = (acc[0][rr] + acc[1][rr]) + (acc[2][rr] + acc[3][rr]);
+        if (k < NBW && i < NBW) Ym[k * PY + i] = (k < i) ? y : 0.0;
       }
     }
   }
   __syncthreads();
-  // forward column-wise T (dlarft): T[i][i] = tau_i, T[0:i, i] = -tau_i T[0:i, 0:i] Y[0:i, i]
-  for (int i = 0; i < nbw; ++i) {
-    const int t = tid >> 3, part8 = tid & 7;
-    double acc = 0.0;
-    if (t < i)
-      for (int k = t + part8; k < i; k += 8) acc += T[t * PT + k] * Y[k * PT + i];
-    acc += __shfl_xor(acc, 1, 64);
-    acc += __shfl_xor(acc, 2, 64);
-    acc += __shfl_xor(acc, 4, 64);
-    if (t < i && part8 == 0) T[t * PT + i] = -tau[i] * acc;
-    if (tid == 0) T[i * PT + i] = tau[i];
-    __syncthreads();
-  }
-  // VT = V T (h x nbw), 16 x 16 output tiles over the waves
-  const int ntile = ((h + 15) >> 4) * ((nbw + 15) >> 4);
-  const int tcn = (nbw + 15) >> 4;
-  for (int t = w; t < ntile; t += 4) {
-    const int tr = t / tcn, tcl = t % tcn;
-    v4d acc = {0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < nbw; k0 += 4) {
-      const int k = k0 + (lane >> 4), row = tr * 16 + (lane & 15);
-      const double av_ = (row < h && k < nbw) ? vsh[row * PV + k] : 0.0;
-      const double bv_ = (k < nbw) ? T[k * PT + tcl * 16 + (lane & 15)] : 0.0;
-      acc = mfma_f64_16x16x4(av_, bv_, acc);
-    }
-    const int col = tcl * 16 + (lane & 15);
+  // T rows: lane (t, half) holds T[t][2 m + half] in ts[m]
+  if (w == 0) {
+    const int t = lane & 31, half = lane >> 5;
+    double ts[NBW / 2];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = tr * 16 + (lane >> 4) + 4 * r;
-      if (row < h && col < nbw) VTout[(size_t)row * nbw + col] = acc[r];
+    for (int m = 0; m < NBW / 2; ++m) ts[m] = 0.0;
+#pragma unroll
+    for (int i = 0; i < NBW; ++i) {
+      double acc = 0.0;
+#pragma unroll
+      for (int m = 0; m < (i + 1) / 2; ++m) acc = fma(ts[m], Ym[(2 * m + half) * PY + i], acc);
+      const double tot = add_xor32(acc);
+      const double ti = tau[i];
+      const double val = (i > t) ? -ti * tot : (i == t ? ti : 0.0);
+      if (half == (i & 1)) ts[i / 2] = val;
+    }
+    if (t < NBW) {
+#pragma unroll
+      for (int m = 0; m < NBW / 2; ++m) Tm[t * PY + 2 * m + half] = ts[m];
+    }
+  }
+  // V to global, coalesced
+  for (int e = tid; e < h * NBW; e += 256) {
+    const int r = e / NBW, q = e % NBW;
+    if (q < nbw) Vout[(size_t)r * nbw + q] = vsh[r * PV + q];
+  }
+  __syncthreads();
+  // VT = V T (h x nbw), 16 x 16 output tiles over the waves
+  const int ntile = ((h + 15) >> 4) * NT;
+  for (int tt = w; tt < ntile; tt += 4) {
+    const int tr = tt / NT, tcl = tt % NT;
+    const int row = tr * 16 + (lane & 15), col = tcl * 16 + (lane & 15), kk = lane >> 4;
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k0 = 0; k0 < NBW; k0 += 4) {
+      const int k = k0 + kk;
+      const double av = (row < h) ? vsh[row * PV + k] : 0.0;
+      const double bv = (col < NBW) ? Tm[k * PY + col] : 0.0;
+      acc = mfma_f64_16x16x4(av, bv, acc);
+    }
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const int orow = tr * 16 + kk + 4 * rr;
+      if (orow < h && col < nbw) VTout[(size_t)orow * nbw + col] = acc[rr];
     }
   }
 }
