@@ -191,12 +191,27 @@ __device__ __forceinline__ void split_half(double* x, int lane) {
 }
 
 // K (2, 4 or 8) wave sums at once by recursive halving: the split steps leave
-// one value per lane, value j in the lane whose bits (2, 0, 1) spell j from the
-// top; the rest of the lanes are summed by exchanges, and every lane reads the
-// K totals from the lanes that hold them.  About 10 exchanges for K = 8 where
-// K separate reductions take 6 K.
+// one value per lane, value wave_sums_index<K>(lane) (lane bits 2, 0, 1 spell
+// it from the top); the remaining lanes are summed by exchanges.  Returns the
+// lane's total; every lane also reads all K totals into v.  About 10
+// exchanges for K = 8 where K separate reductions take 6 K.
 template <int K>
-__device__ __forceinline__ void wave_sums(double (&v)[K]) {
+__device__ __forceinline__ int wave_sums_index(int lane) {
+  int j = ((lane >> 2) & 1) * (K / 2);
+  if constexpr (K >= 4) j += (lane & 1) * (K / 4);
+  if constexpr (K >= 8) j += (lane >> 1) & 1;
+  return j;
+}
+
+// true for exactly one lane per value: lanes 0..7 with the unused bits clear
+template <int K>
+__device__ __forceinline__ bool wave_sums_holder(int lane) {
+  constexpr int unused = (K == 8) ? 0 : (K == 4 ? 2 : 3);
+  return lane < 8 && (lane & unused) == 0;
+}
+
+template <int K>
+__device__ __forceinline__ double wave_sums(double (&v)[K]) {
   static_assert(K == 2 || K == 4 || K == 8, "K must be 2, 4 or 8");
   const int lane = threadIdx.x & 63;
   double x[K];
@@ -218,6 +233,7 @@ __device__ __forceinline__ void wave_sums(double (&v)[K]) {
     if constexpr (K >= 8) l |= (j & 1) << 1;
     v[j] = readlane_d(t, l);
   }
+  return t;
 }
 
 __device__ __forceinline__ int wave_min_i(int v) {

@@ -319,8 +319,7 @@ dqmc_status update_slice(dqmc_ctx* c, int tau, int dir) {
 // ---------------------------------------------------- UDV stabilisation --
 template <int NBW, int MAXR>
 void qr_panel_launch(dqmc_ctx* c, double* Ap, int j0, int nbw, double* V, double* VT) {
-  const int h = c->N - j0;
-  hipLaunchKernelGGL((k_qr_panel<NBW, MAXR>), gridc(c, 1), dim3(256), sizeof(double) * qr_panel_lds<NBW>(h),
+  hipLaunchKernelGGL((k_qr_panel<NBW, MAXR>), gridc(c, 1), dim3(256), sizeof(double) * qr_panel_lds<NBW>(64 * MAXR),
                      c->stream, Ap, c->N, j0, nbw, V, VT, c->cs);
 }
 

@@ -127,149 +127,138 @@ __global__ void k_permute_cols(double* dst, const double* src, const int* piv, i
 // of LAPACK's dlarfg: for x = (x0, x'), beta = -sign(x0) |x|,
 // tau = (beta - x0)/beta, v = (1, x' / (x0 - beta)); tau = 0 when x' = 0.
 //
-// Layout: the panel is staged in LDS (vsh, h x (NBW+1)) by coalesced loads;
-// wave w owns the columns w*NBW/4 .. (w+1)*NBW/4 - 1 and lane l the rows
-// l, l + 64, ... (MAXR of them), in registers.  Per column c: the owning wave
-// reads column c from vsh, forms the reflector (norm and x0 by one two-value
-// wave sum) and writes v_c over column c of vsh, where it stays as column c of
-// V; one barrier; every wave takes the dot products of v_c with all its own
-// columns in one multi-value wave sum and applies the reflector in registers,
-// and the owner of column c+1 writes that column back to vsh for the next
-// step.  After the loop: Y = V^T V by MFMA, the T recurrence
+// Layout: the panel comes in by coalesced loads through LDS (vsh, 64 MAXR
+// rows of NBW+1, zero below row h); wave w owns the columns
+// w*NBW/4 .. (w+1)*NBW/4 - 1 and lane l the rows l, l + 64, ... (MAXR of
+// them), in registers.  The column loop runs over the owning wave and,
+// unrolled, over its columns, so the owner addresses its column without
+// selects; as NBW <= 32, only the first row group holds rows at or above the
+// diagonal.  Per column c: the owner forms the reflector from its registers
+// (norm and x0 in one two-value wave sum), keeps v in its registers and writes
+// it to column c of vsh, where it stays as column c of V; one barrier; every
+// wave takes the dot products of v_c with all its own columns in one
+// multi-value wave sum and applies the reflector to the columns right of c
+// (a zero multiplier for the others, so no branches), and the lanes that hold
+// the sums for columns left of c (v_q below their diagonal) record v_q^T v_c
+// in Y.  After the loop: the T recurrence
 // T[t][i] = -tau_i sum_{k<i} T[t][k] Y[k][i] row by row (each lane one row,
 // the two halves of the wave splitting k), and VT = V T by MFMA.
 template <int NBW>
-__host__ __device__ inline size_t qr_panel_lds(int h) {
-  return (size_t)h * (NBW + 1) + 2 * (size_t)NBW * (NBW + 1) + 2 * NBW;
+__host__ __device__ inline size_t qr_panel_lds(int rows) {
+  return (size_t)rows * (NBW + 1) + 2 * (size_t)NBW * (NBW + 1) + 2 * NBW;
 }
 
 template <int NBW, int MAXR>
 __global__ __launch_bounds__(256) void k_qr_panel(double* A, int n, int j0, int nbw, double* Vout,
                                                   double* VTout, size_t cs) {
   extern __shared__ double smem[];
-  constexpr int CPW = NBW / 4, PV = NBW + 1, PY = NBW + 1;
+  constexpr int CPW = NBW / 4, PV = NBW + 1, PY = NBW + 1, NE = MAXR * NBW / 4, HR = 64 * MAXR;
+  static_assert(NBW <= 32, "rows at or above the diagonal must sit in the first row group");
   {
     const size_t co = (size_t)blockIdx.y * cs;
     A += co; Vout += co; VTout += co;
   }
   const int h = n - j0, tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  double* vsh = smem;                       // h x PV: the panel, then V
-  double* Ym = vsh + (size_t)h * PV;        // NBW x PY: strictly upper V^T V
+  double* vsh = smem;                       // HR x PV: the panel, then V
+  double* Ym = vsh + HR * PV;               // NBW x PY: strictly upper V^T V
   double* Tm = Ym + NBW * PY;               // NBW x PY: T
   double* tau = Tm + NBW * PY;              // NBW
   double* bet = tau + NBW;                  // NBW: diagonal of R
-  for (int e = tid; e < h * NBW; e += 256) {
-    const int r = e / NBW, q = e % NBW;
-    vsh[r * PV + q] = (q < nbw) ? A[(size_t)(j0 + r) * n + j0 + q] : 0.0;
+  {
+    double t[NE];
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+      const int e = tid + 256 * u, r = e / NBW, q = e % NBW;
+      t[u] = (r < h && q < nbw) ? A[(size_t)(j0 + r) * n + j0 + q] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+      const int e = tid + 256 * u, r = e / NBW, q = e % NBW;
+      vsh[r * PV + q] = t[u];
+    }
   }
   for (int e = tid; e < NBW * PY; e += 256) Ym[e] = 0.0;
   if (tid < NBW) { tau[tid] = 0.0; bet[tid] = 0.0; }   // columns >= nbw stay inert
   __syncthreads();
   double a[MAXR][CPW];
 #pragma unroll
-  for (int i = 0; i < MAXR; ++i) {
-    const int r = lane + 64 * i;
+  for (int i = 0; i < MAXR; ++i)
 #pragma unroll
-    for (int j = 0; j < CPW; ++j) a[i][j] = (r < h) ? vsh[r * PV + w * CPW + j] : 0.0;
-  }
+    for (int j = 0; j < CPW; ++j) a[i][j] = vsh[(lane + 64 * i) * PV + w * CPW + j];
   const int ncol = min(nbw, h);
-  for (int c = 0; c < ncol; ++c) {
-    if (w == c / CPW) {
-      double colv[MAXR];
-      double sx[2] = {0.0, 0.0};   // sum of squares below c, x0
+  for (int cw = 0; cw < 4; ++cw) {
 #pragma unroll
-      for (int i = 0; i < MAXR; ++i) {
-        const int r = lane + 64 * i;
-        colv[i] = (r < h) ? vsh[r * PV + c] : 0.0;
-        if (r > c) sx[0] = fma(colv[i], colv[i], sx[0]);
-        if (r == c) sx[1] = colv[i];
-      }
-      wave_sums<2>(sx);
-      const double s = sx[0], x0 = sx[1];
-      double beta, tc, scal;
-      if (s == 0.0) { tc = 0.0; beta = x0; scal = 0.0; }
-      else {
-        const double nrm = sqrt(x0 * x0 + s);
-        beta = (x0 >= 0.0) ? -nrm : nrm;
-        tc = (beta - x0) / beta;
-        scal = 1.0 / (x0 - beta);
-      }
+    for (int cj = 0; cj < CPW; ++cj) {
+      const int c = cw * CPW + cj;
+      if (c >= ncol) break;
+      double vr[MAXR];
+      if (w == cw) {
+        // sum of squares below c, x0 (rows at or above c are in group 0)
+        double sx[2] = {0.0, (lane == c) ? a[0][cj] : 0.0};
+        sx[0] = (lane > c) ? a[0][cj] * a[0][cj] : 0.0;
 #pragma unroll
-      for (int i = 0; i < MAXR; ++i) {
-        const int r = lane + 64 * i;
-        if (r < h) vsh[r * PV + c] = (r > c) ? colv[i] * scal : (r == c ? 1.0 : 0.0);
-      }
-      if (lane == 0) { tau[c] = tc; bet[c] = beta; }
-    }
-    __syncthreads();
-    const double tc = tau[c];
-    double vr[MAXR];
-#pragma unroll
-    for (int i = 0; i < MAXR; ++i) {
-      const int r = lane + 64 * i;
-      vr[i] = (r < h) ? vsh[r * PV + c] : 0.0;
-    }
-    double p[CPW];
-#pragma unroll
-    for (int j = 0; j < CPW; ++j) {
-      p[j] = 0.0;
-#pragma unroll
-      for (int i = 0; i < MAXR; ++i) p[j] = fma(vr[i], a[i][j], p[j]);
-    }
-    wave_sums<CPW>(p);
-#pragma unroll
-    for (int j = 0; j < CPW; ++j) {
-      const int q = w * CPW + j;
-      if (q > c && q < nbw) {
-        const double wq = tc * p[j];
-#pragma unroll
-        for (int i = 0; i < MAXR; ++i) a[i][j] = fma(-vr[i], wq, a[i][j]);
-        if (q == c + 1) {
-#pragma unroll
-          for (int i = 0; i < MAXR; ++i) {
-            const int r = lane + 64 * i;
-            if (r < h) vsh[r * PV + q] = a[i][j];
-          }
+        for (int i = 1; i < MAXR; ++i) sx[0] = fma(a[i][cj], a[i][cj], sx[0]);
+        wave_sums<2>(sx);
+        const double s = sx[0], x0 = sx[1];
+        double beta, tc, scal;
+        if (s == 0.0) { tc = 0.0; beta = x0; scal = 0.0; }
+        else {
+          const double nrm = sqrt(x0 * x0 + s);
+          beta = (x0 >= 0.0) ? -nrm : nrm;
+          tc = (beta - x0) / beta;
+          scal = 1.0 / (x0 - beta);
         }
+        {
+          const double x = a[0][cj];
+          vr[0] = (lane > c) ? x * scal : (lane == c ? 1.0 : 0.0);
+          a[0][cj] = (lane > c) ? vr[0] : (lane == c ? beta : x);
+        }
+#pragma unroll
+        for (int i = 1; i < MAXR; ++i) {
+          vr[i] = a[i][cj] * scal;
+          a[i][cj] = vr[i];
+        }
+#pragma unroll
+        for (int i = 0; i < MAXR; ++i) vsh[(lane + 64 * i) * PV + c] = vr[i];
+        if (lane == 0) { tau[c] = tc; bet[c] = beta; }
+      }
+      __syncthreads();
+      const double tc = tau[c];
+      if (w != cw) {
+#pragma unroll
+        for (int i = 0; i < MAXR; ++i) vr[i] = vsh[(lane + 64 * i) * PV + c];
+      }
+      double p[CPW];
+#pragma unroll
+      for (int j = 0; j < CPW; ++j) {
+        p[j] = 0.0;
+#pragma unroll
+        for (int i = 0; i < MAXR; ++i) p[j] = fma(vr[i], a[i][j], p[j]);
+      }
+      const double tl = wave_sums<CPW>(p);
+      {
+        // one holder lane per sum: v_q^T v_c for the columns left of c
+        const int q = w * CPW + wave_sums_index<CPW>(lane);
+        if (wave_sums_holder<CPW>(lane) && q < c) Ym[q * PY + c] = tl;
+      }
+      double tv[MAXR];
+#pragma unroll
+      for (int i = 0; i < MAXR; ++i) tv[i] = tc * vr[i];
+#pragma unroll
+      for (int j = 0; j < CPW; ++j) {
+        const int q = w * CPW + j;
+        const double pj = (q > c && q < nbw) ? p[j] : 0.0;   // uniform
+#pragma unroll
+        for (int i = 0; i < MAXR; ++i) a[i][j] = fma(-tv[i], pj, a[i][j]);
       }
     }
   }
-  // R on and above the diagonal (rows < nbw <= 64 live in the first row group)
+  // R on and above the diagonal (rows < nbw <= 32 live in the first row group)
 #pragma unroll
   for (int j = 0; j < CPW; ++j) {
     const int q = w * CPW + j;
-    if (q < nbw && lane <= q) A[(size_t)(j0 + lane) * n + j0 + q] = (lane == q) ? bet[q] : a[0][j];
-  }
-  __syncthreads();
-  // Y = V^T V, upper 16 x 16 tiles (I <= J) on waves 0..2, four accumulators
-  constexpr int NT = (NBW + 15) / 16;
-  {
-    int I = -1, J = -1;
-    if (NT == 1) { if (w == 0) { I = 0; J = 0; } }
-    else if (w < 3) { I = (w == 2) ? 1 : 0; J = (w == 0) ? 0 : 1; }
-    if (I >= 0) {
-      const int m = lane & 15, kk = lane >> 4;
-      const int ca = I * 16 + m, cb = J * 16 + m;
-      v4d acc[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) acc[u] = v4d{0.0, 0.0, 0.0, 0.0};
-      for (int r0 = 0; r0 < h; r0 += 16) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int r = r0 + 4 * u + kk;
-          const double av = (r < h && ca < NBW) ? vsh[r * PV + ca] : 0.0;
-          const double bv = (r < h && cb < NBW) ? vsh[r * PV + cb] : 0.0;
-          acc[u] = mfma_f64_16x16x4(av, bv, acc[u]);
-        }
-      }
-#pragma unroll
-      for (int rr = 0; rr < 4; ++rr) {
-        const int k = I * 16 + kk + 4 * rr, i = J * 16 + m;
-        const double y = (acc[0][rr] + acc[1][rr]) + (acc[2][rr] + acc[3][rr]);
-        if (k < NBW && i < NBW) Ym[k * PY + i] = (k < i) ? y : 0.0;
-      }
-    }
+    if (q < nbw && lane <= q) A[(size_t)(j0 + lane) * n + j0 + q] = a[0][j];
   }
   __syncthreads();
   // T rows: lane (t, half) holds T[t][2 m + half] in ts[m]
@@ -292,30 +281,49 @@ __global__ __launch_bounds__(256) void k_qr_panel(double* A, int n, int j0, int 
 #pragma unroll
       for (int m = 0; m < NBW / 2; ++m) Tm[t * PY + 2 * m + half] = ts[m];
     }
-  }
-  // V to global, coalesced
-  for (int e = tid; e < h * NBW; e += 256) {
-    const int r = e / NBW, q = e % NBW;
-    if (q < nbw) Vout[(size_t)r * nbw + q] = vsh[r * PV + q];
+  } else {
+    // V to global, coalesced, by the other three waves
+    const int t3 = tid - 64;
+#pragma unroll
+    for (int u = 0; u < (NE * 4 + 2) / 3; ++u) {
+      const int e = t3 + 192 * u, r = e / NBW, q = e % NBW;
+      if (r < h && q < nbw) Vout[(size_t)r * nbw + q] = vsh[r * PV + q];
+    }
   }
   __syncthreads();
-  // VT = V T (h x nbw), 16 x 16 output tiles over the waves
-  const int ntile = ((h + 15) >> 4) * NT;
-  for (int tt = w; tt < ntile; tt += 4) {
-    const int tr = tt / NT, tcl = tt % NT;
-    const int row = tr * 16 + (lane & 15), col = tcl * 16 + (lane & 15), kk = lane >> 4;
-    v4d acc = {0.0, 0.0, 0.0, 0.0};
+  // VT = V T (h x nbw): wave w takes the 16-row tiles w, w + 4, ...; the T
+  // operands of all column tiles stay in registers
+  constexpr int NT = (NBW + 15) / 16, KS = NBW / 4;
+  const int m16 = lane & 15, kk = lane >> 4;
+  double tb[KS][NT];
 #pragma unroll
-    for (int k0 = 0; k0 < NBW; k0 += 4) {
-      const int k = k0 + kk;
-      const double av = (row < h) ? vsh[row * PV + k] : 0.0;
-      const double bv = (col < NBW) ? Tm[k * PY + col] : 0.0;
-      acc = mfma_f64_16x16x4(av, bv, acc);
+  for (int k = 0; k < KS; ++k)
+#pragma unroll
+    for (int tc = 0; tc < NT; ++tc) {
+      const int col = tc * 16 + m16;
+      tb[k][tc] = (col < NBW) ? Tm[(4 * k + kk) * PY + col] : 0.0;
     }
+  const int nrt = (h + 15) >> 4;
+  for (int tr = w; tr < nrt; tr += 4) {
+    const int row = tr * 16 + m16;
+    double av[KS];
 #pragma unroll
-    for (int rr = 0; rr < 4; ++rr) {
-      const int orow = tr * 16 + kk + 4 * rr;
-      if (orow < h && col < nbw) VTout[(size_t)orow * nbw + col] = acc[rr];
+    for (int k = 0; k < KS; ++k) av[k] = vsh[row * PV + 4 * k + kk];
+    v4d acc[NT];
+#pragma unroll
+    for (int tc = 0; tc < NT; ++tc) acc[tc] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < KS; ++k)
+#pragma unroll
+      for (int tc = 0; tc < NT; ++tc) acc[tc] = mfma_f64_16x16x4(av[k], tb[k][tc], acc[tc]);
+#pragma unroll
+    for (int tc = 0; tc < NT; ++tc) {
+      const int col = tc * 16 + m16;
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int orow = tr * 16 + kk + 4 * rr;
+        if (orow < h && col < nbw) VTout[(size_t)orow * nbw + col] = acc[tc][rr];
+      }
     }
   }
 }
