@@ -155,24 +155,65 @@ __device__ __forceinline__ double dpp_all(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// v + (v of the lane 16 away): permlane16_swap of v with itself leaves the
-// even-row data in one result and the odd-row data in the other.
-__device__ __forceinline__ double add_xor16(double v) {
+template <int CTRL>
+__device__ __forceinline__ int dpp_all_i(int v) {
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
+}
+
+// The pair (v of this lane, v of the lane 16 / 32 away) in some order:
+// permlane16_swap of v with itself leaves the even-row data in one result and
+// the odd-row data in the other; permlane32_swap does the same for the halves.
+__device__ __forceinline__ void pair_xor16(double v, double& x, double& y) {
   const long long b = __double_as_longlong(v);
   const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)b, (unsigned)b, false, false);
   const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
-  const double x = __longlong_as_double(((long long)hi[0] << 32) | lo[0]);
-  const double y = __longlong_as_double(((long long)hi[1] << 32) | lo[1]);
+  x = __longlong_as_double(((long long)hi[0] << 32) | lo[0]);
+  y = __longlong_as_double(((long long)hi[1] << 32) | lo[1]);
+}
+
+__device__ __forceinline__ void pair_xor32(double v, double& x, double& y) {
+  const long long b = __double_as_longlong(v);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)b, (unsigned)b, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+  x = __longlong_as_double(((long long)hi[0] << 32) | lo[0]);
+  y = __longlong_as_double(((long long)hi[1] << 32) | lo[1]);
+}
+
+__device__ __forceinline__ double add_xor16(double v) {
+  double x, y;
+  pair_xor16(v, x, y);
   return x + y;
 }
 
 __device__ __forceinline__ double add_xor32(double v) {
-  const long long b = __double_as_longlong(v);
-  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)b, (unsigned)b, false, false);
-  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
-  const double x = __longlong_as_double(((long long)hi[0] << 32) | lo[0]);
-  const double y = __longlong_as_double(((long long)hi[1] << 32) | lo[1]);
+  double x, y;
+  pair_xor32(v, x, y);
   return x + y;
+}
+
+// Whole-wave max / min with the result in every lane (no readlane): xor 1,
+// xor 2, the half-row mirror, xor 8, then the permlane swaps.
+__device__ __forceinline__ double wave_max_all(double v) {
+  v = fmax(v, dpp_all<0xB1>(v));
+  v = fmax(v, dpp_all<0x4E>(v));
+  v = fmax(v, dpp_all<0x141>(v));
+  v = fmax(v, dpp_all<0x128>(v));
+  double x, y;
+  pair_xor16(v, x, y);
+  v = fmax(x, y);
+  pair_xor32(v, x, y);
+  return fmax(x, y);
+}
+
+__device__ __forceinline__ int wave_min_all_i(int v) {
+  v = min(v, dpp_all_i<0xB1>(v));
+  v = min(v, dpp_all_i<0x4E>(v));
+  v = min(v, dpp_all_i<0x141>(v));
+  v = min(v, dpp_all_i<0x128>(v));
+  const auto a = __builtin_amdgcn_permlane16_swap((unsigned)v, (unsigned)v, false, false);
+  v = min((int)a[0], (int)a[1]);
+  const auto b = __builtin_amdgcn_permlane32_swap((unsigned)v, (unsigned)v, false, false);
+  return min((int)b[0], (int)b[1]);
 }
 
 // One halving step of a multi-sum: lanes whose BIT is 0 keep the first half of

@@ -343,8 +343,7 @@ dqmc_status launch_qr_panel(dqmc_ctx* c, double* Ap, int j0, int nbw, double* V,
 
 template <int NBW, int MAXR>
 void lu_panel_reg(dqmc_ctx* c, double* X, int j0, int nbw) {
-  const int h = c->N - j0;
-  hipLaunchKernelGGL((k_lu_panel_reg<NBW, MAXR>), gridc(c, 1), dim3(256), sizeof(double) * 2 * (size_t)h, c->stream, X,
+  hipLaunchKernelGGL((k_lu_panel_reg<NBW, MAXR>), gridc(c, 1), dim3(256), sizeof(double) * 2 * 64 * MAXR, c->stream, X,
                      c->N, j0, nbw, c->ipiv, c->err_flag, c->cs);
 }
 

@@ -357,17 +357,20 @@ __global__ void k_build_rt(const double* R, const int* piv, int n, double* Rt, d
 // l, l + 64, ... (MAXR of them), in registers; every wave holds the same rows
 // in the same lanes.  Pivoting is virtual: each held row carries its current
 // position, a pivot step swaps two positions (every wave keeps the same copy),
-// and the rows are written back to their final positions.  Per column c the
-// owning wave finds the pivot (DPP wave max, then the lowest position holding
-// it), forms the multipliers of its rows and publishes them with the pivot's
-// lane and register through LDS (two alternating buffers); after one barrier
-// every wave reads the pivot row from its own registers by readlane and
-// eliminates its columns.  Columns c >= nbw (a ragged last panel) are left out.
+// and the rows are written back to their final positions.  The column loop
+// runs over the owning wave and, unrolled, over its columns, so the owner
+// addresses its column without selects.  Per column c the owner finds the
+// pivot (wave max, then the lowest position holding it, both left in every
+// lane), forms the multipliers of its rows and publishes them with the
+// pivot's lane and register through LDS (two alternating buffers); after one
+// barrier every wave reads the pivot row from its own registers (a uniform
+// register index) by readlane and eliminates its columns, with a zero
+// multiplier for columns at or left of c, so no branches.
 template <int NBW, int MAXR>
 __global__ __launch_bounds__(256) void k_lu_panel_reg(double* X, int n, int j0, int nbw, int* ipiv, int* err,
                                                       size_t cs) {
-  extern __shared__ double smem[];   // 2 x h multipliers
-  constexpr int CPW = NBW / 4;
+  extern __shared__ double smem[];   // 2 x 64 MAXR multipliers
+  constexpr int CPW = NBW / 4, HR = 64 * MAXR;
   __shared__ int piv_s[2][3];        // pivot position, lane, register
   {
     const size_t co = (size_t)blockIdx.y * cs;
@@ -375,7 +378,8 @@ __global__ __launch_bounds__(256) void k_lu_panel_reg(double* X, int n, int j0, 
     ipiv = reinterpret_cast<int*>(reinterpret_cast<double*>(ipiv) + co);
     err = reinterpret_cast<int*>(reinterpret_cast<double*>(err) + co);
   }
-  const int h = n - j0, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int h = n - j0, tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   double a[MAXR][CPW];
   int pos[MAXR];
 #pragma unroll
@@ -389,78 +393,71 @@ __global__ __launch_bounds__(256) void k_lu_panel_reg(double* X, int n, int j0, 
     }
   }
   const int ncol = min(nbw, h);
-  for (int c = 0; c < ncol; ++c) {
-    double* lb = smem + (c & 1) * (size_t)h;
-    int* ps = piv_s[c & 1];
-    const int cw = c / CPW, cj = c % CPW;
-    if (w == cw) {
-      double colv[MAXR];
-      double best = -1.0;
-      int bi = 0x7fffffff;
+  for (int cw = 0; cw < 4; ++cw) {
 #pragma unroll
-      for (int i = 0; i < MAXR; ++i) {
-        double v = 0.0;
+    for (int cj = 0; cj < CPW; ++cj) {
+      const int c = cw * CPW + cj;
+      if (c >= ncol) break;
+      double* lb = smem + (c & 1) * HR;
+      int* ps = piv_s[c & 1];
+      if (w == cw) {
+        double best = -1.0;
+        int bi = 0x7fffffff;
 #pragma unroll
-        for (int j = 0; j < CPW; ++j) v = (j == cj) ? a[i][j] : v;
-        colv[i] = v;
-        if (pos[i] >= c && pos[i] < h) {
-          const double av = fabs(v);
-          if (av > best || (av == best && pos[i] < bi)) { best = av; bi = pos[i]; }
+        for (int i = 0; i < MAXR; ++i) {
+          if (pos[i] >= c && pos[i] < h) {
+            const double av = fabs(a[i][cj]);
+            if (av > best || (av == best && pos[i] < bi)) { best = av; bi = pos[i]; }
+          }
+        }
+        const double wm = wave_max_all(best);
+        int pp = wave_min_all_i((best == wm && best >= 0.0) ? bi : 0x7fffffff);
+        pp = __builtin_amdgcn_readfirstlane(pp);
+        // no finite candidate (a NaN column): keep the row and flag the failure
+        if (!(wm >= 0.0) || pp < c || pp >= h) pp = c;
+        // the lane and register holding position pp, and the pivot value
+        int hit = -1;
+        double pv = 0.0;
+#pragma unroll
+        for (int i = 0; i < MAXR; ++i)
+          if (pos[i] == pp) { hit = i; pv = a[i][cj]; }
+        const unsigned long long mask = __ballot(hit >= 0);
+        const int hl = __ffsll((long long)mask) - 1;
+        const int hs = __builtin_amdgcn_readlane(hit, hl);
+        const double inv = 1.0 / readlane_d(pv, hl);
+        // multipliers of the rows that stay below the pivot (position > c after the swap)
+#pragma unroll
+        for (int i = 0; i < MAXR; ++i) {
+          const int np = (pos[i] == pp) ? c : (pos[i] == c ? pp : pos[i]);
+          const bool below = np > c && np < h;
+          const double l = below ? a[i][cj] * inv : 0.0;
+          lb[lane + 64 * i] = l;
+          a[i][cj] = below ? l : a[i][cj];
+        }
+        if (lane == 0) {
+          ps[0] = pp; ps[1] = hl; ps[2] = hs;
+          ipiv[j0 + c] = j0 + pp;
+          if (!(wm > 0.0)) atomicOr(err, 4);
         }
       }
-      const double wm = wave_max_d(best);
-      int pp = wave_min_i((best == wm && best >= 0.0) ? bi : 0x7fffffff);
-      // no finite candidate (a NaN column): keep the row and flag the failure
-      if (!(wm >= 0.0) || pp < c || pp >= h) pp = c;
-      // the lane and register holding position pp, and the pivot value
-      int hit = -1;
-      double pv = 0.0;
+      __syncthreads();
+      const int pp = __builtin_amdgcn_readfirstlane(ps[0]);
+      const int hl = __builtin_amdgcn_readfirstlane(ps[1]);
+      const int hs = __builtin_amdgcn_readfirstlane(ps[2]);
 #pragma unroll
-      for (int i = 0; i < MAXR; ++i)
-        if (pos[i] == pp) { hit = i; pv = colv[i]; }
-      const unsigned long long mask = __ballot(hit >= 0);
-      const int hl = __ffsll((long long)mask) - 1;
-      const int hs = __builtin_amdgcn_readlane(hit, hl);
-      const double pivot = readlane_d(pv, hl);
-      const double inv = 1.0 / pivot;
-      // multipliers of the rows that stay below the pivot (position > c after the swap)
+      for (int i = 0; i < MAXR; ++i) pos[i] = (pos[i] == pp) ? c : (pos[i] == c ? pp : pos[i]);
+      double lr[MAXR];
 #pragma unroll
-      for (int i = 0; i < MAXR; ++i) {
-        const int r = lane + 64 * i;
-        const int np = (pos[i] == pp) ? c : (pos[i] == c ? pp : pos[i]);
-        const double l = (np > c && np < h) ? colv[i] * inv : 0.0;
-        if (r < h) lb[r] = l;
-        if (np > c && np < h) {
+      for (int i = 0; i < MAXR; ++i) lr[i] = lb[lane + 64 * i];   // 0 for rows not below the pivot
 #pragma unroll
-          for (int j = 0; j < CPW; ++j) if (j == cj) a[i][j] = l;
-        }
-      }
-      if (lane == 0) {
-        ps[0] = pp; ps[1] = hl; ps[2] = hs;
-        ipiv[j0 + c] = j0 + pp;
-        if (!(wm > 0.0)) atomicOr(err, 4);
-      }
-    }
-    __syncthreads();
-    const int pp = ps[0], hl = ps[1], hs = ps[2];
-#pragma unroll
-    for (int i = 0; i < MAXR; ++i) pos[i] = (pos[i] == pp) ? c : (pos[i] == c ? pp : pos[i]);
-    double lr[MAXR];
-#pragma unroll
-    for (int i = 0; i < MAXR; ++i) {
-      const int r = lane + 64 * i;
-      lr[i] = (r < h) ? lb[r] : 0.0;
-    }
-#pragma unroll
-    for (int j = 0; j < CPW; ++j) {
-      const int q = w * CPW + j;
-      if (q > c && q < nbw) {
+      for (int j = 0; j < CPW; ++j) {
+        const int q = w * CPW + j;
         double pr = 0.0;
 #pragma unroll
-        for (int i = 0; i < MAXR; ++i) pr = (i == hs) ? a[i][j] : pr;
-        const double u = readlane_d(pr, hl);
+        for (int i = 0; i < MAXR; ++i) pr = (i == hs) ? a[i][j] : pr;   // uniform index
+        const double u = (q > c && q < nbw) ? readlane_d(pr, hl) : 0.0;
 #pragma unroll
-        for (int i = 0; i < MAXR; ++i) a[i][j] -= lr[i] * u;   // lr = 0 for rows not below the pivot
+        for (int i = 0; i < MAXR; ++i) a[i][j] = fma(-lr[i], u, a[i][j]);
       }
     }
   }
