@@ -96,7 +96,7 @@ template <int NCOL>
 __global__ __launch_bounds__(256) void k_block_update(BlockArgs a) {
   constexpr int TS = 34;   // row stride of the records (16-byte aligned rows)
   __shared__ double AB[2][32][33];   // right-hand sides, then X and Z^T
-  __shared__ __attribute__((aligned(16))) double Tt[2][32][TS];   // Tt[0][k][m] = T_A[m][k], Tt[1][k][m] = T_B[m][k]
+  __shared__ __attribute__((aligned(16))) double Tr[2][32][TS];   // Tr[0][m][k] = T_A[m][k], Tr[1][m][k] = T_B[m][k]
   __shared__ double gam[32];
   __shared__ int accf[32], nacc_s;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -130,40 +130,44 @@ __global__ __launch_bounds__(256) void k_block_update(BlockArgs a) {
       sold = a.field_in[s0 + x];
     }
     int nacc = 0, myacc = 0;
+    double mygam = 0.0;
 #pragma unroll
     for (int i = 0; i < 32; ++i) {
+      __builtin_amdgcn_sched_barrier(0);   // keeps the per-site scalars from piling up in SGPRs
       if (i < bb) {
         const double cii = readlane_d(c[i], i);
         const double dli = readlane_d(dl, i);
         const double r = 1.0 + dli * (1.0 - cii);
         const double R = readlane_d(pr, i) * (NCOL == 2 ? r * r : r);
-        double gi = 0.0;
         if (readlane_d(u, i) < R) {            // uniform across the wave
-          gi = dli / r;
+          const double gi = dli / r;
           ++nacc;
-          if (lane == i) myacc = 1;
-          if (x > i) {
-            const double f = gi * c[i];
+          if (x == i) { myacc = 1; mygam = gi; }
+          // row i broadcast, then the rank-1 update of the rows below i (a
+          // zero factor keeps the frozen rows as they are)
+          const double f = (x > i) ? gi * c[i] : 0.0;
 #pragma unroll
-            for (int y = i + 1; y < 32; ++y) c[y] = fma(f, readlane_d(c[y], i), c[y]);
+          for (int y0 = i + 1; y0 < 32; y0 += 8) {
+            double ci[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) if (y0 + t < 32) ci[t] = readlane_d(c[y0 + t], i);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int t = 0; t < 8; ++t) if (y0 + t < 32) c[y0 + t] = fma(f, ci[t], c[y0 + t]);
           }
         }
-        if (lane == 0) gam[i] = gi;
-      } else if (lane == 0) {
-        gam[i] = 0.0;
       }
     }
-    if (lane < 32) accf[lane] = myacc;
+    if (lane < 32) { accf[lane] = myacc; gam[lane] = mygam; }
     if (lane == 0) nacc_s = nacc;
     // records: upper part of row x scaled by -gamma_x, lower part (column
     // entries c[x][m], m < x) by -gamma_m
     const double gx = gam[x];
 #pragma unroll
     for (int y = 0; y < 32; ++y) {
-      const double v = (y > x) ? -gx * c[y] : ((y < x) ? -gam[y] * c[y] : 0.0);
       if (lane < 32) {
-        Tt[1][x][y] = v;          // row x of c: T_B[y][x] for y < x
-        Tt[0][y][x] = v;          // column view: T_A[x][y] for y > x
+        Tr[0][x][y] = (y > x) ? -gx * c[y] : 0.0;       // row x of c: T_A[x][y] for y > x
+        Tr[1][y][x] = (y < x) ? -gam[y] * c[y] : 0.0;   // column view: T_B[y][x] for y < x
       }
     }
     if (blockIdx.x == 0 && lane < bb) a.field_out[s0 + lane] = myacc ? snew : sold;
@@ -181,22 +185,28 @@ __global__ __launch_bounds__(256) void k_block_update(BlockArgs a) {
   if (w == 0) {
     // X = GIS A (lanes 0-31, row x) and Z^T = (E_S^T[:,J] - G[S,J])^T B (lanes
     // 32-63): the triangular recurrences R[k] = rhs[k] - sum_{m<k} R[m] T[m][k]
-    // with T = T_A or T_B, four independent partial sums per lane
+    // with T = T_A or T_B, right-looking: once R[m] is final it is taken out of
+    // every later entry, with the row T[m][.] read as one broadcast per half
+    // row m + 1 is fetched while row m is applied (scheduling fences keep
+    // the loads ahead of the FMAs that do not need them)
     const int x = lane & 31, h = lane >> 5;
-    double R[32];
+    double R[32], cur[32], nxt[32];
 #pragma unroll
-    for (int k = 0; k < 32; ++k) {
-      double v0 = AB[h][x][k], v1 = 0.0, v2 = 0.0, v3 = 0.0;
+    for (int k = 0; k < 32; ++k) R[k] = AB[h][x][k];
 #pragma unroll
-      for (int m = 0; m + 3 < k; m += 4) {
-        v0 = fma(-Tt[h][k][m], R[m], v0);
-        v1 = fma(-Tt[h][k][m + 1], R[m + 1], v1);
-        v2 = fma(-Tt[h][k][m + 2], R[m + 2], v2);
-        v3 = fma(-Tt[h][k][m + 3], R[m + 3], v3);
+    for (int k = 1; k < 32; ++k) cur[k] = Tr[h][0][k];
+#pragma unroll
+    for (int m = 0; m < 31; ++m) {
+      if (m + 1 < 31) {
+#pragma unroll
+        for (int k = m + 2; k < 32; ++k) nxt[k] = Tr[h][m + 1][k];
       }
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int m = k & ~3; m < k; ++m) v0 = fma(-Tt[h][k][m], R[m], v0);
-      R[k] = (v0 + v1) + (v2 + v3);
+      for (int k = m + 1; k < 32; ++k) R[k] = fma(-R[m], cur[k], R[k]);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int k = m + 2; k < 32; ++k) cur[k] = nxt[k];
     }
 #pragma unroll
     for (int k = 0; k < 32; ++k) AB[h][x][k] = R[k];
