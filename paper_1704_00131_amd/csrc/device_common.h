@@ -160,6 +160,22 @@ __device__ __forceinline__ int dpp_all_i(int v) {
   return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
 }
 
+// lane S of each quad to the whole quad
+template <int S>
+__device__ __forceinline__ double quad_bcast_d(double v) {
+  return dpp_all<S * 0x55>(v);
+}
+
+// the same for a lane index known only after unrolling
+__device__ __forceinline__ double quad_bcast_d(double v, int s) {
+  switch (s & 3) {
+    case 0: return quad_bcast_d<0>(v);
+    case 1: return quad_bcast_d<1>(v);
+    case 2: return quad_bcast_d<2>(v);
+    default: return quad_bcast_d<3>(v);
+  }
+}
+
 // The pair (v of this lane, v of the lane 16 / 32 away) in some order:
 // permlane16_swap of v with itself leaves the even-row data in one result and
 // the odd-row data in the other; permlane32_swap does the same for the halves.

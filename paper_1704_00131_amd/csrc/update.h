@@ -96,7 +96,9 @@ template <int NCOL>
 __global__ __launch_bounds__(256) void k_block_update(BlockArgs a) {
   constexpr int TS = 34;   // row stride of the records (16-byte aligned rows)
   __shared__ double AB[2][32][33];   // right-hand sides, then X and Z^T
-  __shared__ __attribute__((aligned(16))) double Tr[2][32][TS];   // Tr[0][m][k] = T_A[m][k], Tr[1][m][k] = T_B[m][k]
+  // records by rows, each row split by k mod 4: Tq[h][m][(k & 3) * 8 + (k >> 2)]
+  // = T_A[m][k] (h = 0) or T_B[m][k] (h = 1)
+  __shared__ __attribute__((aligned(16))) double Tq[2][32][TS];
   __shared__ double gam[32];
   __shared__ int accf[32], nacc_s;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -166,8 +168,8 @@ __global__ __launch_bounds__(256) void k_block_update(BlockArgs a) {
 #pragma unroll
     for (int y = 0; y < 32; ++y) {
       if (lane < 32) {
-        Tr[0][x][y] = (y > x) ? -gx * c[y] : 0.0;       // row x of c: T_A[x][y] for y > x
-        Tr[1][y][x] = (y < x) ? -gam[y] * c[y] : 0.0;   // column view: T_B[y][x] for y < x
+        Tq[0][x][(y & 3) * 8 + (y >> 2)] = (y > x) ? -gx * c[y] : 0.0;       // row x of c: T_A[x][y], y > x
+        Tq[1][y][(x & 3) * 8 + (x >> 2)] = (y < x) ? -gam[y] * c[y] : 0.0;   // column view: T_B[y][x], y < x
       }
     }
     if (blockIdx.x == 0 && lane < bb) a.field_out[s0 + lane] = myacc ? snew : sold;
@@ -182,34 +184,38 @@ __global__ __launch_bounds__(256) void k_block_update(BlockArgs a) {
     }
   }
   __syncthreads();
-  if (w == 0) {
-    // X = GIS A (lanes 0-31, row x) and Z^T = (E_S^T[:,J] - G[S,J])^T B (lanes
-    // 32-63): the triangular recurrences R[k] = rhs[k] - sum_{m<k} R[m] T[m][k]
-    // with T = T_A or T_B, right-looking: once R[m] is final it is taken out of
-    // every later entry, with the row T[m][.] read as one broadcast per half
-    // row m + 1 is fetched while row m is applied (scheduling fences keep
-    // the loads ahead of the FMAs that do not need them)
-    const int x = lane & 31, h = lane >> 5;
-    double R[32], cur[32], nxt[32];
+  {
+    // X = GIS A (rows of X) and Z^T = (E_S^T[:,J] - G[S,J])^T B (rows of Z^T):
+    // the triangular recurrences R[k] = rhs[k] - sum_{m<k} R[m] T[m][k] with
+    // T = T_A or T_B, right-looking.  Four lanes (a quad) share one row, lane
+    // sub holding R[k] for k = sub mod 4; once R[m] is final its lane hands it
+    // to the quad by a DPP broadcast and each lane takes it out of its later
+    // entries.  Waves 0, 1 take the 32 rows of X, waves 2, 3 those of Z^T; the
+    // next record row is fetched while the current one is applied.
+    const int h = w >> 1, row = (tid >> 2) & 31, sub = tid & 3;
+    double rk[8], cur[8], nxt[8];
 #pragma unroll
-    for (int k = 0; k < 32; ++k) R[k] = AB[h][x][k];
+    for (int j = 0; j < 8; ++j) rk[j] = AB[h][row][4 * j + sub];
 #pragma unroll
-    for (int k = 1; k < 32; ++k) cur[k] = Tr[h][0][k];
+    for (int j = 0; j < 8; ++j) cur[j] = Tq[h][0][sub * 8 + j];
 #pragma unroll
     for (int m = 0; m < 31; ++m) {
+      const int jm = m >> 2;
       if (m + 1 < 31) {
 #pragma unroll
-        for (int k = m + 2; k < 32; ++k) nxt[k] = Tr[h][m + 1][k];
+        for (int j = (m + 1) >> 2; j < 8; ++j) nxt[j] = Tq[h][m + 1][sub * 8 + j];
       }
       __builtin_amdgcn_sched_barrier(0);
+      const double val = quad_bcast_d(rk[jm], m);   // R[m]
+      rk[jm] = fma(sub > (m & 3) ? -val : 0.0, cur[jm], rk[jm]);
 #pragma unroll
-      for (int k = m + 1; k < 32; ++k) R[k] = fma(-R[m], cur[k], R[k]);
+      for (int j = jm + 1; j < 8; ++j) rk[j] = fma(-val, cur[j], rk[j]);
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int k = m + 2; k < 32; ++k) cur[k] = nxt[k];
+      for (int j = (m + 1) >> 2; j < 8; ++j) cur[j] = nxt[j];
     }
 #pragma unroll
-    for (int k = 0; k < 32; ++k) AB[h][x][k] = R[k];
+    for (int j = 0; j < 8; ++j) AB[h][row][4 * j + sub] = rk[j];
   }
   __syncthreads();
   // Gout tile = Gin - X diag(gamma) Z  (32 x 32 x 32 on MFMA)
