@@ -9,10 +9,10 @@
 // exp(coupling * field) for the interaction exponential), so no separate
 // scaling pass over HBM is needed.
 //
-// Tiling: one workgroup of 256 threads (4 waves) computes a TILE x TILE tile
-// of C (TILE = 16 or 32, chosen per launch so that small products still
-// spread over many CUs); the four waves split K and their partial
-// accumulators are summed through LDS.  Operands are read straight from
+// Tiling: one workgroup of WV waves (4, or 8 for long K on one chain)
+// computes a TILE x TILE tile of C (TILE = 16 or 32, chosen per launch so that
+// small products still spread over many CUs); the waves split K and their
+// partial accumulators are summed through LDS.  Operands are read straight from
 // global memory in the v_mfma_f64_16x16x4 lane layout: the 16 lanes feeding
 // one MFMA row share a 128-byte line across four k-steps, so the L1 serves
 // most loads and no LDS staging is needed for these L2-resident matrices.
@@ -34,8 +34,8 @@ struct GemmArgs {
 };
 enum { PC_A = 1, PC_B = 2, PC_C = 4, PC_RS = 8, PC_CS = 16, PC_KS = 32 };
 
-template <int TILE, int UNR>
-__global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
+template <int TILE, int UNR, int WV>
+__global__ __launch_bounds__(64 * WV) void k_gemm(GemmArgs g) {
   constexpr int NB = TILE / 16;
   if (g.cstride) {
     const size_t co = (size_t)blockIdx.y * g.cstride;
@@ -46,13 +46,13 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
     if (g.pc & PC_CS) g.cs += co;
     if (g.pc & PC_KS) g.ks += co;
   }
-  __shared__ double red[3][NB * NB][4][64];
+  __shared__ double red[WV - 1][NB * NB][4][64];
   const int tilesN = (g.N + TILE - 1) / TILE;
   const int i0 = (blockIdx.x / tilesN) * TILE, j0 = (blockIdx.x % tilesN) * TILE;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int l16 = lane & 15, lk = lane >> 4;
   // contiguous K range of this wave, a multiple of 4 long
-  const int kq = ((g.K + 15) / 16) * 4;
+  const int kq = ((g.K + 4 * WV - 1) / (4 * WV)) * 4;
   const int kb = w * kq, ke = min(g.K, kb + kq);
   v4d acc[NB][NB];
 #pragma unroll
@@ -120,8 +120,9 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
       for (int r = 0; r < 4; ++r) {
         const int row = i0 + a * 16 + lk + 4 * r;
         if (row >= g.M) continue;
-        const double sum = acc[a][b][r] + red[0][a * NB + b][r][lane] + red[1][a * NB + b][r][lane] +
-                           red[2][a * NB + b][r][lane];
+        double sum = acc[a][b][r];
+#pragma unroll
+        for (int q = 0; q < WV - 1; ++q) sum += red[q][a * NB + b][r][lane];
         const double rf = g.rs_mode ? scale_of(g.rs_mode, g.rs, g.rs_coef, row) : 1.0;
         double v = g.alpha * (rf * sum * cf);
         double* cp = g.C + (size_t)row * g.ldc + col;
@@ -354,14 +355,16 @@ static inline hipError_t launch_gemm(const GemmArgs& g, hipStream_t s) {
   }
   const int t32 = ((g.M + 31) / 32) * ((g.N + 31) / 32);
   const bool use32 = g.tile == 32 || (g.tile == 0 && (long long)t32 * nch >= 192);
-  const bool deep = nch == 1 && g.K >= 128;   // long K on few workgroups: chunked loads
+  // long K on few workgroups: eight waves split K (32 x 32 tiles with loads
+  // two steps ahead), which measured 10-25% faster at N = 288 and 648
+  const bool deep = nch == 1 && g.K >= 128;
   if (use32) {
-    if (deep) hipLaunchKernelGGL((k_gemm<32, 8>), dim3(t32, nch), dim3(256), 0, s, g);
-    else hipLaunchKernelGGL((k_gemm<32, 1>), dim3(t32, nch), dim3(256), 0, s, g);
+    if (deep) hipLaunchKernelGGL((k_gemm<32, 2, 8>), dim3(t32, nch), dim3(512), 0, s, g);
+    else hipLaunchKernelGGL((k_gemm<32, 1, 4>), dim3(t32, nch), dim3(256), 0, s, g);
   } else {
     const int t16 = ((g.M + 15) / 16) * ((g.N + 15) / 16);
-    if (deep) hipLaunchKernelGGL((k_gemm<16, 8>), dim3(t16, nch), dim3(256), 0, s, g);
-    else hipLaunchKernelGGL((k_gemm<16, 1>), dim3(t16, nch), dim3(256), 0, s, g);
+    if (deep) hipLaunchKernelGGL((k_gemm<16, 1, 8>), dim3(t16, nch), dim3(512), 0, s, g);
+    else hipLaunchKernelGGL((k_gemm<16, 1, 4>), dim3(t16, nch), dim3(256), 0, s, g);
   }
   return hipGetLastError();
 }
