@@ -58,7 +58,7 @@ struct dqmc_ctx {
   double *field_alt = nullptr;             // field rows written by the upward pass
   std::vector<unsigned char> row_alt;      // host mirror: row tau currently in field_alt
   double *norms = nullptr;
-  int *piv = nullptr, *ipiv = nullptr;
+  int *piv = nullptr, *moves = nullptr;
   double *bins = nullptr, *prec_hist = nullptr, *prec_tot = nullptr, *logdet = nullptr;
   double *grad = nullptr, *gprec = nullptr;   // gradient rows [L][N] and the gradient pass's precision
   double* mpart = nullptr;                     // partial sums of the equal-time estimators
@@ -147,8 +147,8 @@ size_t layout_chain(dqmc_ctx* c, double* base) {
   P(c->field_alt, (size_t)c->L * N);
   P(c->norms, N);
   double* pv = nullptr;
-  double* ipv = nullptr;
-  P(pv, N); P(ipv, N);
+  double* mv = nullptr;
+  P(pv, N); P(mv, (kLuMoves + 1) / 2);
   P(c->bins, 4);
   P(c->prec_hist, 2 * (size_t)c->nk + 2);
   P(c->prec_tot, 4);
@@ -168,7 +168,7 @@ size_t layout_chain(dqmc_ctx* c, double* base) {
   P(ctr, 4); P(ef, 1);
   if (base) {
     c->piv = reinterpret_cast<int*>(pv);
-    c->ipiv = reinterpret_cast<int*>(ipv);
+    c->moves = reinterpret_cast<int*>(mv);
     c->counters = reinterpret_cast<unsigned long long*>(ctr);
     c->err_flag = reinterpret_cast<int*>(ef);
   }
@@ -344,7 +344,7 @@ dqmc_status launch_qr_panel(dqmc_ctx* c, double* Ap, int j0, int nbw, double* V,
 template <int NBW, int MAXR>
 void lu_panel_reg(dqmc_ctx* c, double* X, int j0, int nbw) {
   hipLaunchKernelGGL((k_lu_panel_reg<NBW, MAXR>), gridc(c, 1), dim3(256), sizeof(double) * 2 * 64 * MAXR, c->stream, X,
-                     c->N, j0, nbw, c->ipiv, c->err_flag, c->cs);
+                     c->N, j0, nbw, c->moves, c->err_flag, c->cs);
 }
 
 // Panel LU of columns j0 .. j0 + nbw (nbw <= c->nb): rows per lane =
@@ -471,7 +471,7 @@ dqmc_status lu_solve(dqmc_ctx* c, double* X, double* RHS, int nrhs, int ldb, dou
     const int nbw = std::min(nb, N - j0);
     if (dqmc_status s = launch_lu_panel(c, X, j0, nbw)) return s;
     hipLaunchKernelGGL(k_lu_swap, gridc(c, grid1((size_t)(N - nbw) + nrhs)), dim3(256), 0, c->stream, X, N, j0, nbw,
-                       c->ipiv, RHS, nrhs, ldb, c->cs);
+                       c->moves, RHS, nrhs, ldb, c->cs);
     HIPCHK(hipGetLastError());
     const int ntr = N - j0 - nbw;
     if (ntr > 0) {
@@ -1369,7 +1369,7 @@ bool layout_ok(const dqmc_ctx* c, const double* lo, const double* hi) {
   for (const double* p : {c->Vall, c->VTall, c->Zq, c->Rt, c->X, c->RHS, c->Gs, c->T1, c->G2}) ok = ok && in(p, NN, true);
   for (const UDVp* u : {&c->cur, &c->hA, &c->hB}) ok = ok && in(u->Q, NN, true) && in(u->D, N, true) && in(u->T, NN, true);
   ok = ok && in(c->field_alt, (size_t)c->L * N, true) && in(c->norms, N, true) && in(c->piv, N / 2 + 1, true) &&
-       in(c->ipiv, N / 2 + 1, true) && in(c->bins, 4, true) && in(c->prec_hist, 2 * (size_t)c->nk + 2, true) &&
+       in(c->moves, (kLuMoves + 1) / 2, true) && in(c->bins, 4, true) && in(c->prec_hist, 2 * (size_t)c->nk + 2, true) &&
        in(c->prec_tot, 4, true) && in(c->logdet, 4, true) && in(c->grad, (size_t)c->L * N, true) && in(c->gprec, 4, true) &&
        in(c->mpart, 4 * (size_t)((N + kMeasRows - 1) / kMeasRows), true) &&
        in(c->draws, 4 * (size_t)c->L * N, true) &&

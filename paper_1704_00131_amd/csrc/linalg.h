@@ -350,8 +350,10 @@ __global__ void k_build_rt(const double* R, const int* piv, int n, double* Rt, d
 // ----------------------------------------------------------- LU panel ----
 // Panel LU with partial pivoting of columns j0..j0+nbw-1 of X (ld n) over rows
 // j0..n-1: the pivot is the largest |a| among the remaining rows, ties to the
-// lowest position; ipiv[j0+c] = global pivot row; multipliers by the pivot's
-// reciprocal.  k_lu_swap applies the interchanges outside the panel.
+// lowest position; multipliers by the pivot's reciprocal.  The interchanges
+// of the panel, composed, are written as a list of row moves (moves[0] = count
+// K <= 2 nbw, then K pairs (destination row, source row), absolute rows), which
+// k_lu_swap applies outside the panel.
 //
 // Layout: wave w owns the columns w*NBW/4 .. (w+1)*NBW/4 - 1 and lane l the rows
 // l, l + 64, ... (MAXR of them), in registers; every wave holds the same rows
@@ -366,8 +368,10 @@ __global__ void k_build_rt(const double* R, const int* piv, int n, double* Rt, d
 // barrier every wave reads the pivot row from its own registers (a uniform
 // register index) by readlane and eliminates its columns, with a zero
 // multiplier for columns at or left of c, so no branches.
+constexpr int kLuMoves = 1 + 2 * 64;   // ints of the move list (count + pairs)
+
 template <int NBW, int MAXR>
-__global__ __launch_bounds__(256) void k_lu_panel_reg(double* X, int n, int j0, int nbw, int* ipiv, int* err,
+__global__ __launch_bounds__(256) void k_lu_panel_reg(double* X, int n, int j0, int nbw, int* moves, int* err,
                                                       size_t cs) {
   extern __shared__ double smem[];   // 2 x 64 MAXR multipliers
   constexpr int CPW = NBW / 4, HR = 64 * MAXR;
@@ -375,7 +379,7 @@ __global__ __launch_bounds__(256) void k_lu_panel_reg(double* X, int n, int j0, 
   {
     const size_t co = (size_t)blockIdx.y * cs;
     X += co;
-    ipiv = reinterpret_cast<int*>(reinterpret_cast<double*>(ipiv) + co);
+    moves = reinterpret_cast<int*>(reinterpret_cast<double*>(moves) + co);
     err = reinterpret_cast<int*>(reinterpret_cast<double*>(err) + co);
   }
   const int h = n - j0, tid = threadIdx.x, lane = tid & 63;
@@ -436,7 +440,6 @@ __global__ __launch_bounds__(256) void k_lu_panel_reg(double* X, int n, int j0, 
         }
         if (lane == 0) {
           ps[0] = pp; ps[1] = hl; ps[2] = hs;
-          ipiv[j0 + c] = j0 + pp;
           if (!(wm > 0.0)) atomicOr(err, 4);
         }
       }
@@ -471,16 +474,36 @@ __global__ __launch_bounds__(256) void k_lu_panel_reg(double* X, int n, int j0, 
       }
     }
   }
+  // the composed interchanges: original row r now sits at position pos(r);
+  // every wave holds the same positions, wave 0 lists the rows that moved
+  if (w == 0) {
+    int cnt = 0;
+#pragma unroll
+    for (int i = 0; i < MAXR; ++i) {
+      const int r = lane + 64 * i;
+      const bool moved = pos[i] < h && pos[i] != r;
+      const unsigned long long m = __ballot(moved);
+      const int at = cnt + __popcll(m & ((1ull << lane) - 1ull));
+      if (moved) {
+        moves[1 + 2 * at] = j0 + pos[i];
+        moves[2 + 2 * at] = j0 + r;
+      }
+      cnt += __popcll(m);
+    }
+    if (lane == 0) moves[0] = cnt;
+  }
 }
 
-// Apply the interchanges of one panel to the columns of X outside the panel
-// and to every column of the right-hand sides B (n x nrhs, ld ldb).
-__global__ void k_lu_swap(double* X, int n, int j0, int nbw, const int* ipiv, double* B, int nrhs, int ldb,
-                          size_t cs) {
+// Apply the interchanges of one panel (the move list of k_lu_panel_reg) to the
+// columns of X outside the panel and to every column of the right-hand sides B
+// (n x nrhs, ld ldb): one thread per column loads all moved rows first, so
+// their latencies overlap, then stores them at their destinations.
+__global__ __launch_bounds__(256) void k_lu_swap(double* X, int n, int j0, int nbw, const int* moves, double* B,
+                                                 int nrhs, int ldb, size_t cs) {
   {
     const size_t co = (size_t)blockIdx.y * cs;
     X += co; B += co;
-    ipiv = reinterpret_cast<const int*>(reinterpret_cast<const double*>(ipiv) + co);
+    moves = reinterpret_cast<const int*>(reinterpret_cast<const double*>(moves) + co);
   }
   const int col = blockIdx.x * blockDim.x + threadIdx.x;
   const int nx = n - nbw;
@@ -495,29 +518,36 @@ __global__ void k_lu_swap(double* X, int n, int j0, int nbw, const int* ipiv, do
     base = B + (col - nx);
     ld = ldb;
   }
-  for (int c = 0; c < nbw && j0 + c < n; ++c) {
-    const int r = j0 + c, p = ipiv[r];
-    if (p != r && p > r && p < n) {
-      const double t = base[(size_t)r * ld];
-      base[(size_t)r * ld] = base[(size_t)p * ld];
-      base[(size_t)p * ld] = t;
-    }
-  }
+  const int K = min(moves[0], 64);
+  double v[64];
+#pragma unroll
+  for (int k = 0; k < 64; ++k)
+    if (k < K) v[k] = base[(size_t)moves[2 + 2 * k] * ld];
+#pragma unroll
+  for (int k = 0; k < 64; ++k)
+    if (k < K) base[(size_t)moves[1 + 2 * k] * ld] = v[k];
 }
 
 // Solve Tri * Z = Bm in place for a block of nrow <= 32 rows: Tri is the
 // nrow x nrow diagonal block (ld ldt), lower with unit diagonal or upper with
 // its own diagonal.  One thread per column of Bm; the column stays in
-// registers (fully unrolled over a 32-row block padded with identity rows).
+// registers (a 32-row block padded with identity rows).  Right-looking: once
+// z[k] is final it is taken out of every later row, so the dependent chain is
+// one FMA per row; Tri is kept in LDS by columns (tt[k][r] = Tri[r][k]) for
+// 16-byte broadcast reads, and the upper case multiplies by the reciprocal
+// diagonal.
 __global__ __launch_bounds__(256) void k_trsm_block(const double* Tri, int ldt, double* Bm, int ldb, int nrow,
                                                     int ncol, int upper, size_t cs) {
-  __shared__ double t[32][33];
+  __shared__ __attribute__((aligned(16))) double tt[32][34];
+  __shared__ double dinv[32];
   Tri += (size_t)blockIdx.y * cs;
   Bm += (size_t)blockIdx.y * cs;
   for (int e = threadIdx.x; e < 32 * 32; e += 256) {
     const int r = e >> 5, k = e & 31;
-    t[r][k] = (r < nrow && k < nrow) ? Tri[(size_t)r * ldt + k] : (r == k ? 1.0 : 0.0);
+    tt[k][r] = (r < nrow && k < nrow) ? Tri[(size_t)r * ldt + k] : (r == k ? 1.0 : 0.0);
   }
+  __syncthreads();
+  if (threadIdx.x < 32) dinv[threadIdx.x] = 1.0 / tt[threadIdx.x][threadIdx.x];
   __syncthreads();
   const int col = blockIdx.x * blockDim.x + threadIdx.x;
   if (col >= ncol) return;
@@ -526,19 +556,15 @@ __global__ __launch_bounds__(256) void k_trsm_block(const double* Tri, int ldt, 
   for (int r = 0; r < 32; ++r) z[r] = (r < nrow) ? Bm[(size_t)r * ldb + col] : 0.0;
   if (!upper) {
 #pragma unroll
-    for (int r = 1; r < 32; ++r) {
-      double v = z[r];
+    for (int k = 0; k < 31; ++k)
 #pragma unroll
-      for (int k = 0; k < r; ++k) v -= t[r][k] * z[k];
-      z[r] = v;
-    }
+      for (int r = k + 1; r < 32; ++r) z[r] = fma(-tt[k][r], z[k], z[r]);
   } else {
 #pragma unroll
-    for (int r = 31; r >= 0; --r) {
-      double v = z[r];
+    for (int k = 31; k >= 0; --k) {
+      z[k] *= dinv[k];
 #pragma unroll
-      for (int k = r + 1; k < 32; ++k) v -= t[r][k] * z[k];
-      z[r] = v / t[r][r];
+      for (int r = 0; r < k; ++r) z[r] = fma(-tt[k][r], z[k], z[r]);
     }
   }
 #pragma unroll
