@@ -59,6 +59,8 @@ struct dqmc_ctx {
   std::vector<unsigned char> row_alt;      // host mirror: row tau currently in field_alt
   double *norms = nullptr;
   int *piv = nullptr, *moves = nullptr;
+  double* XA = nullptr;    // [X | right-hand sides] of the blocked LU solve, n x 3n
+  double* Mgj = nullptr;   // multipliers of one panel, n x 32
   double *bins = nullptr, *prec_hist = nullptr, *prec_tot = nullptr, *logdet = nullptr;
   double *grad = nullptr, *gprec = nullptr;   // gradient rows [L][N] and the gradient pass's precision
   double* mpart = nullptr;                     // partial sums of the equal-time estimators
@@ -67,7 +69,7 @@ struct dqmc_ctx {
   // right-hand sides of the re-anchoring solve, S(K, tau) of the current
   // configuration and its bin sums, partial records, A_a(0); the momentum
   // phases and orbital map are shared
-  double *TD[4] = {}, *RHS2 = nullptr, *tdS = nullptr, *tdbins = nullptr, *tdpart = nullptr, *a00 = nullptr;
+  double *TD[4] = {}, *tdS = nullptr, *tdbins = nullptr, *tdpart = nullptr, *a00 = nullptr;
   double* kph = nullptr;
   int* korb = nullptr;
   int td_norb = 0, td_cells = 0;
@@ -144,6 +146,8 @@ size_t layout_chain(dqmc_ctx* c, double* base) {
   UDVp* us[3] = {&c->cur, &c->hA, &c->hB};
   for (UDVp* u : us) { P(u->Q, NN); P(u->D, N); P(u->T, NN); }
   P(c->G2, NN);
+  P(c->XA, 3 * NN);
+  P(c->Mgj, 32 * N);
   P(c->field_alt, (size_t)c->L * N);
   P(c->norms, N);
   double* pv = nullptr;
@@ -158,7 +162,6 @@ size_t layout_chain(dqmc_ctx* c, double* base) {
   P(c->mpart, 4 * (size_t)((N + kMeasRows - 1) / kMeasRows));
   P(c->draws, 4 * (size_t)c->L * N);
   for (int i = 0; i < 4; ++i) P(c->TD[i], NN);
-  P(c->RHS2, 2 * NN);
   P(c->tdS, (size_t)(c->L + 1) * kTdStride);
   P(c->tdbins, (size_t)(c->L + 1) * kTdStride + 4);
   P(c->tdpart, (size_t)((N + kTdRows - 1) / kTdRows) * kTdPart);
@@ -342,24 +345,24 @@ dqmc_status launch_qr_panel(dqmc_ctx* c, double* Ap, int j0, int nbw, double* V,
 }
 
 template <int NBW, int MAXR>
-void lu_panel_reg(dqmc_ctx* c, double* X, int j0, int nbw) {
-  hipLaunchKernelGGL((k_lu_panel_reg<NBW, MAXR>), gridc(c, 1), dim3(256), sizeof(double) * 2 * 64 * MAXR, c->stream, X,
-                     c->N, j0, nbw, c->moves, c->err_flag, c->cs);
+void lu_panel(dqmc_ctx* c, double* XA, int ld, int j0, int nbw) {
+  hipLaunchKernelGGL((k_lu_panel<NBW, MAXR>), gridc(c, 1), dim3(256), sizeof(double) * 2 * 64 * MAXR, c->stream, XA,
+                     c->N, ld, j0, nbw, c->Mgj, 32, c->moves, c->err_flag, c->cs);
 }
 
-// Panel LU of columns j0 .. j0 + nbw (nbw <= c->nb): rows per lane =
-// ceil(h / 64), rounded up to the instantiated counts.
-dqmc_status launch_lu_panel(dqmc_ctx* c, double* X, int j0, int nbw) {
+// Panel step of the blocked LU solve: rows per lane = ceil(h / 64),
+// rounded up to the instantiated counts.
+dqmc_status launch_lu_panel(dqmc_ctx* c, double* XA, int ld, int j0, int nbw) {
   const int rows = (c->N - j0 + 63) / 64;
-  if (c->nb == 32 && rows <= 2) lu_panel_reg<32, 2>(c, X, j0, nbw);
-  else if (c->nb == 32 && rows <= 4) lu_panel_reg<32, 4>(c, X, j0, nbw);
-  else if (c->nb == 32 && rows <= 6) lu_panel_reg<32, 6>(c, X, j0, nbw);
-  else if (c->nb == 16 && rows <= 4) lu_panel_reg<16, 4>(c, X, j0, nbw);
-  else if (c->nb == 16 && rows <= 8) lu_panel_reg<16, 8>(c, X, j0, nbw);
-  else if (c->nb == 16 && rows <= 12) lu_panel_reg<16, 12>(c, X, j0, nbw);
-  else if (c->nb == 8 && rows <= 4) lu_panel_reg<8, 4>(c, X, j0, nbw);
-  else if (c->nb == 8 && rows <= 8) lu_panel_reg<8, 8>(c, X, j0, nbw);
-  else if (c->nb == 8 && rows <= 16) lu_panel_reg<8, 16>(c, X, j0, nbw);
+  if (c->nb == 32 && rows <= 2) lu_panel<32, 2>(c, XA, ld, j0, nbw);
+  else if (c->nb == 32 && rows <= 4) lu_panel<32, 4>(c, XA, ld, j0, nbw);
+  else if (c->nb == 32 && rows <= 6) lu_panel<32, 6>(c, XA, ld, j0, nbw);
+  else if (c->nb == 16 && rows <= 4) lu_panel<16, 4>(c, XA, ld, j0, nbw);
+  else if (c->nb == 16 && rows <= 8) lu_panel<16, 8>(c, XA, ld, j0, nbw);
+  else if (c->nb == 16 && rows <= 12) lu_panel<16, 12>(c, XA, ld, j0, nbw);
+  else if (c->nb == 8 && rows <= 4) lu_panel<8, 4>(c, XA, ld, j0, nbw);
+  else if (c->nb == 8 && rows <= 8) lu_panel<8, 8>(c, XA, ld, j0, nbw);
+  else if (c->nb == 8 && rows <= 16) lu_panel<8, 16>(c, XA, ld, j0, nbw);
   else return fail(c, DQMC_E_UNSUPPORTED, "no LU panel kernel for this size");
   HIPCHK(hipGetLastError());
   return DQMC_OK;
@@ -463,54 +466,38 @@ dqmc_status left_step(dqmc_ctx* c, UDVp in, int lo, int hi, UDVp out) {
   return qr_udv(c, const_cast<double*>(src), in.T, out);
 }
 
-// Solve X Y = RHS in place (blocked LU with partial pivoting); RHS is
-// N x nrhs with leading dimension ldb.  If logdet is given, adds log|det X|.
-dqmc_status lu_solve(dqmc_ctx* c, double* X, double* RHS, int nrhs, int ldb, double* logdet) {
-  const int N = c->N, nb = c->nb;
+// Solve X Y = R in place by blocked LU with partial pivoting, the forward
+// substitution carried along as extra columns: XA = [X | R] is
+// n x (n + nrhs) with leading dimension ld; Y replaces R.  If logdet is
+// given, adds log|det X|.
+dqmc_status lu_solve(dqmc_ctx* c, double* XA, int nrhs, int ld, double* logdet) {
+  const int N = c->N, nb = c->nb, ncols = N + nrhs;
   for (int j0 = 0; j0 < N; j0 += nb) {
-    const int nbw = std::min(nb, N - j0);
-    if (dqmc_status s = launch_lu_panel(c, X, j0, nbw)) return s;
-    hipLaunchKernelGGL(k_lu_swap, gridc(c, grid1((size_t)(N - nbw) + nrhs)), dim3(256), 0, c->stream, X, N, j0, nbw,
-                       c->moves, RHS, nrhs, ldb, c->cs);
+    const int nbw = std::min(nb, N - j0), rest = ncols - j0 - nbw;
+    if (dqmc_status s = launch_lu_panel(c, XA, ld, j0, nbw)) return s;
+    hipLaunchKernelGGL(k_lu_rowblock, gridc(c, grid1(rest)), dim3(256), 0, c->stream, XA, ld, j0, nbw, ncols,
+                       c->moves, c->cs);
     HIPCHK(hipGetLastError());
-    const int ntr = N - j0 - nbw;
-    if (ntr > 0) {
-      hipLaunchKernelGGL(k_trsm_block, gridc(c, grid1(ntr)), dim3(256), 0, c->stream, X + (size_t)j0 * N + j0, N,
-                         X + (size_t)j0 * N + j0 + nbw, N, nbw, ntr, 0, c->cs);
-      HIPCHK(hipGetLastError());
-      if (dqmc_status s = gemm(c, gemm_args(ntr, ntr, nbw, X + (size_t)(j0 + nbw) * N + j0, N, 0,
-                                            X + (size_t)j0 * N + j0 + nbw, N, 0, X + (size_t)(j0 + nbw) * N + j0 + nbw,
-                                            N, -1.0, 1.0)))
-        return s;
-    }
-  }
-  // forward substitution with unit-lower L (right-looking)
-  for (int j0 = 0; j0 < N; j0 += nb) {
-    const int nbw = std::min(nb, N - j0);
-    hipLaunchKernelGGL(k_trsm_block, gridc(c, grid1(nrhs)), dim3(256), 0, c->stream, X + (size_t)j0 * N + j0, N,
-                       RHS + (size_t)j0 * ldb, ldb, nbw, nrhs, 0, c->cs);
-    HIPCHK(hipGetLastError());
-    const int rest = N - j0 - nbw;
-    if (rest > 0)
-      if (dqmc_status s = gemm(c, gemm_args(rest, nrhs, nbw, X + (size_t)(j0 + nbw) * N + j0, N, 0,
-                                            RHS + (size_t)j0 * ldb, ldb, 0, RHS + (size_t)(j0 + nbw) * ldb, ldb, -1.0,
-                                            1.0)))
+    const int below = N - j0 - nbw;
+    if (below > 0)
+      if (dqmc_status s = gemm(c, gemm_args(below, rest, nbw, c->Mgj + (size_t)(j0 + nbw) * 32, 32, 0,
+                                            XA + (size_t)j0 * ld + j0 + nbw, ld, 0,
+                                            XA + (size_t)(j0 + nbw) * ld + j0 + nbw, ld, -1.0, 1.0)))
         return s;
   }
-  // back substitution with U
+  // back substitution, one diagonal block at a time from the last
   const int last = ((N - 1) / nb) * nb;
   for (int j0 = last; j0 >= 0; j0 -= nb) {
     const int nbw = std::min(nb, N - j0);
-    hipLaunchKernelGGL(k_trsm_block, gridc(c, grid1(nrhs)), dim3(256), 0, c->stream, X + (size_t)j0 * N + j0, N,
-                       RHS + (size_t)j0 * ldb, ldb, nbw, nrhs, 1, c->cs);
+    hipLaunchKernelGGL(k_lu_diag, gridc(c, grid1(nrhs)), dim3(256), 0, c->stream, XA, N, ld, j0, nb, nrhs, c->cs);
     HIPCHK(hipGetLastError());
     if (j0 > 0)
-      if (dqmc_status s = gemm(c, gemm_args(j0, nrhs, nbw, X + j0, N, 0, RHS + (size_t)j0 * ldb, ldb, 0, RHS, ldb,
+      if (dqmc_status s = gemm(c, gemm_args(j0, nrhs, nbw, XA + j0, ld, 0, XA + (size_t)j0 * ld + N, ld, 0, XA + N, ld,
                                             -1.0, 1.0)))
         return s;
   }
   if (logdet) {
-    hipLaunchKernelGGL(k_logabs_diag, gridc(c, 1), dim3(256), 0, c->stream, X, N, logdet, c->cs);
+    hipLaunchKernelGGL(k_logabs_diag, gridc(c, 1), dim3(256), 0, c->stream, XA, N, ld, logdet, c->cs);
     HIPCHK(hipGetLastError());
   }
   return DQMC_OK;
@@ -521,16 +508,16 @@ dqmc_status lu_solve(dqmc_ctx* c, double* X, double* RHS, int nrhs, int ldb, dou
 //   X = D_Rb^-1 (Q_R^T Q_L) D_Lb^-1 + D_Rs (T_R T_L^T) D_Ls
 //   G = Q_L D_Lb^-1 X^-1 D_Rb^-1 Q_R^T
 dqmc_status merge(dqmc_ctx* c, UDVp R, UDVp Lf, double* Gout, double* logdet) {
-  const int N = c->N;
-  GemmArgs g1 = gemm_args(N, N, N, R.Q, N, 1, Lf.Q, N, 0, c->X, N);
+  const int N = c->N, ld = 2 * N;   // XA = [X | D_Rb^-1 Q_R^T]
+  GemmArgs g1 = gemm_args(N, N, N, R.Q, N, 1, Lf.Q, N, 0, c->XA, ld);
   g1.rs = R.D; g1.rs_mode = SC_INV_BIG; g1.cs = Lf.D; g1.cs_mode = SC_INV_BIG;
   if (dqmc_status s = gemm(c, g1)) return s;
-  GemmArgs g2 = gemm_args(N, N, N, R.T, N, 0, Lf.T, N, 1, c->X, N, 1.0, 1.0);
+  GemmArgs g2 = gemm_args(N, N, N, R.T, N, 0, Lf.T, N, 1, c->XA, ld, 1.0, 1.0);
   g2.rs = R.D; g2.rs_mode = SC_SMALL; g2.cs = Lf.D; g2.cs_mode = SC_SMALL;
   if (dqmc_status s = gemm(c, g2)) return s;
   const dim3 tg((N + 31) / 32, (N + 31) / 32, (unsigned)c->nch);
   // the right form may be the shared identity: offset it only when it is per chain
-  hipLaunchKernelGGL(k_transpose_scale, tg, dim3(256), 0, c->stream, c->RHS, R.Q, N, R.D, SC_INV_BIG, c->cs,
+  hipLaunchKernelGGL(k_transpose_scale, tg, dim3(256), 0, c->stream, c->XA + N, ld, R.Q, N, R.D, SC_INV_BIG, c->cs,
                      is_shared(c, R.Q) ? (size_t)0 : c->cs);
   HIPCHK(hipGetLastError());
   if (logdet) {
@@ -541,8 +528,8 @@ dqmc_status merge(dqmc_ctx* c, UDVp R, UDVp Lf, double* Gout, double* logdet) {
                        is_shared(c, Lf.D) ? (size_t)0 : c->cs, c->cs);
     HIPCHK(hipGetLastError());
   }
-  if (dqmc_status s = lu_solve(c, c->X, c->RHS, N, N, logdet)) return s;
-  GemmArgs g3 = gemm_args(N, N, N, Lf.Q, N, 0, c->RHS, N, 0, Gout, N);
+  if (dqmc_status s = lu_solve(c, c->XA, N, ld, logdet)) return s;
+  GemmArgs g3 = gemm_args(N, N, N, Lf.Q, N, 0, c->XA + N, ld, 0, Gout, N);
   g3.ks = Lf.D; g3.ks_mode = SC_INV_BIG;
   return gemm(c, g3);
 }
@@ -736,31 +723,31 @@ dqmc_status langevin_once(dqmc_ctx* c, double eps, uint64_t step) {
 // each replacing its propagated value (largest deviation into gprec[0] for
 // GTT, gprec[1] for GT0 and G0T).
 dqmc_status td_anchor(dqmc_ctx* c, UDVp R, UDVp Lf, double* gt0, double* h) {
-  const int N = c->N;
+  const int N = c->N, ld = 3 * N;   // XA = [X | D_Rb^-1 Q_R^T | D_Rs T_R]
   const size_t NN = (size_t)N * N;
-  GemmArgs g1 = gemm_args(N, N, N, R.Q, N, 1, Lf.Q, N, 0, c->X, N);
+  GemmArgs g1 = gemm_args(N, N, N, R.Q, N, 1, Lf.Q, N, 0, c->XA, ld);
   g1.rs = R.D; g1.rs_mode = SC_INV_BIG; g1.cs = Lf.D; g1.cs_mode = SC_INV_BIG;
   if (dqmc_status s = gemm(c, g1)) return s;
-  GemmArgs g2 = gemm_args(N, N, N, R.T, N, 0, Lf.T, N, 1, c->X, N, 1.0, 1.0);
+  GemmArgs g2 = gemm_args(N, N, N, R.T, N, 0, Lf.T, N, 1, c->XA, ld, 1.0, 1.0);
   g2.rs = R.D; g2.rs_mode = SC_SMALL; g2.cs = Lf.D; g2.cs_mode = SC_SMALL;
   if (dqmc_status s = gemm(c, g2)) return s;
   const unsigned t = (unsigned)((N + 31) / 32);
-  hipLaunchKernelGGL(k_td_rhs, dim3(t, t, (unsigned)c->nch), dim3(256), 0, c->stream, c->RHS2, R.Q, R.T, R.D, N,
-                     c->cs, is_shared(c, R.Q) ? (size_t)0 : c->cs);
+  hipLaunchKernelGGL(k_td_rhs, dim3(t, t, (unsigned)c->nch), dim3(256), 0, c->stream, c->XA + N, ld, R.Q, R.T, R.D,
+                     N, c->cs, is_shared(c, R.Q) ? (size_t)0 : c->cs);
   HIPCHK(hipGetLastError());
-  if (dqmc_status s = lu_solve(c, c->X, c->RHS2, 2 * N, 2 * N, nullptr)) return s;
+  if (dqmc_status s = lu_solve(c, c->XA, 2 * N, ld, nullptr)) return s;
   const unsigned pg = (unsigned)std::min<size_t>(grid1(NN), 1024);
-  GemmArgs g3 = gemm_args(N, N, N, Lf.Q, N, 0, c->RHS2, 2 * N, 0, c->Gs, N);
+  GemmArgs g3 = gemm_args(N, N, N, Lf.Q, N, 0, c->XA + N, ld, 0, c->Gs, N);
   g3.ks = Lf.D; g3.ks_mode = SC_INV_BIG;
   if (dqmc_status s = gemm(c, g3)) return s;
   hipLaunchKernelGGL(k_prec_replace, gridc(c, pg), dim3(256), 0, c->stream, c->G2, c->G2, c->Gs, NN, c->gprec,
                      c->err_flag, c->cs);
-  GemmArgs g4 = gemm_args(N, N, N, Lf.Q, N, 0, c->RHS2 + N, 2 * N, 0, c->X, N);
+  GemmArgs g4 = gemm_args(N, N, N, Lf.Q, N, 0, c->XA + 2 * N, ld, 0, c->X, N);
   g4.ks = Lf.D; g4.ks_mode = SC_INV_BIG;
   if (dqmc_status s = gemm(c, g4)) return s;
   hipLaunchKernelGGL(k_prec_replace, gridc(c, pg), dim3(256), 0, c->stream, gt0, gt0, c->X, NN, c->gprec + 1,
                      c->err_flag, c->cs);
-  GemmArgs g5 = gemm_args(N, N, N, c->RHS2, 2 * N, 1, Lf.T, N, 0, c->RHS, N, -1.0);
+  GemmArgs g5 = gemm_args(N, N, N, c->XA + N, ld, 1, Lf.T, N, 0, c->RHS, N, -1.0);
   g5.ks = Lf.D; g5.ks_mode = SC_SMALL;
   if (dqmc_status s = gemm(c, g5)) return s;
   hipLaunchKernelGGL(k_prec_replace, gridc(c, pg), dim3(256), 0, c->stream, h, h, c->RHS, NN, c->gprec + 1,
@@ -1367,6 +1354,7 @@ bool layout_ok(const dqmc_ctx* c, const double* lo, const double* hi) {
        in(c->slots, (size_t)(c->nk + 1) * (2 * NN + N), true);
   for (int i = 0; i < 6; ++i) ok = ok && in(c->S[i], NN, true);
   for (const double* p : {c->Vall, c->VTall, c->Zq, c->Rt, c->X, c->RHS, c->Gs, c->T1, c->G2}) ok = ok && in(p, NN, true);
+  ok = ok && in(c->XA, 3 * NN, true) && in(c->Mgj, 32 * N, true);
   for (const UDVp* u : {&c->cur, &c->hA, &c->hB}) ok = ok && in(u->Q, NN, true) && in(u->D, N, true) && in(u->T, NN, true);
   ok = ok && in(c->field_alt, (size_t)c->L * N, true) && in(c->norms, N, true) && in(c->piv, N / 2 + 1, true) &&
        in(c->moves, (kLuMoves + 1) / 2, true) && in(c->bins, 4, true) && in(c->prec_hist, 2 * (size_t)c->nk + 2, true) &&
@@ -1374,7 +1362,7 @@ bool layout_ok(const dqmc_ctx* c, const double* lo, const double* hi) {
        in(c->mpart, 4 * (size_t)((N + kMeasRows - 1) / kMeasRows), true) &&
        in(c->draws, 4 * (size_t)c->L * N, true) &&
        in(c->TD[0], NN, true) && in(c->TD[1], NN, true) && in(c->TD[2], NN, true) && in(c->TD[3], NN, true) &&
-       in(c->RHS2, 2 * NN, true) && in(c->tdS, (size_t)(c->L + 1) * kTdStride, true) &&
+       in(c->tdS, (size_t)(c->L + 1) * kTdStride, true) &&
        in(c->tdbins, (size_t)(c->L + 1) * kTdStride + 4, true) &&
        in(c->tdpart, (size_t)((N + kTdRows - 1) / kTdRows) * kTdPart, true) && in(c->a00, 2 * kTdMaxOrb, true) &&
        in(c->kph, 2 * N, false) && in(c->korb, N / 2 + 1, false) &&

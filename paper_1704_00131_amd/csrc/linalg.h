@@ -49,8 +49,8 @@ __global__ void k_scatter(double* dst, const double* src, int count, size_t cs) 
 }
 
 // dst[i][j] = src[j][i] * scale(i)
-__global__ void k_transpose_scale(double* dst, const double* src, int n, const double* d, int mode, size_t cs_dst,
-                                  size_t cs_src) {
+__global__ void k_transpose_scale(double* dst, int ldd, const double* src, int n, const double* d, int mode,
+                                  size_t cs_dst, size_t cs_src) {
   __shared__ double tile[32][33];
   dst += (size_t)blockIdx.z * cs_dst;
   src += (size_t)blockIdx.z * cs_src;
@@ -64,7 +64,7 @@ __global__ void k_transpose_scale(double* dst, const double* src, int n, const d
   __syncthreads();
   for (int r = ty; r < 32; r += 8) {
     const int i = bx + r, j = by + tx;                       // write dst[i][j] = src[j][i]
-    if (i < n && j < n) dst[(size_t)i * n + j] = tile[tx][r] * scale_of(mode, d, 0.0, i);
+    if (i < n && j < n) dst[(size_t)i * ldd + j] = tile[tx][r] * scale_of(mode, d, 0.0, i);
   }
 }
 
@@ -347,38 +347,76 @@ __global__ void k_build_rt(const double* R, const int* piv, int n, double* Rt, d
   Rt[(size_t)i * n + piv[j]] = (j >= i) ? R[(size_t)i * n + j] / d : 0.0;
 }
 
-// ----------------------------------------------------------- LU panel ----
-// Panel LU with partial pivoting of columns j0..j0+nbw-1 of X (ld n) over rows
-// j0..n-1: the pivot is the largest |a| among the remaining rows, ties to the
-// lowest position; multipliers by the pivot's reciprocal.  The interchanges
-// of the panel, composed, are written as a list of row moves (moves[0] = count
-// K <= 2 nbw, then K pairs (destination row, source row), absolute rows), which
-// k_lu_swap applies outside the panel.
-//
-// Layout: wave w owns the columns w*NBW/4 .. (w+1)*NBW/4 - 1 and lane l the rows
-// l, l + 64, ... (MAXR of them), in registers; every wave holds the same rows
-// in the same lanes.  Pivoting is virtual: each held row carries its current
-// position, a pivot step swaps two positions (every wave keeps the same copy),
-// and the rows are written back to their final positions.  The column loop
-// runs over the owning wave and, unrolled, over its columns, so the owner
-// addresses its column without selects.  Per column c the owner finds the
-// pivot (wave max, then the lowest position holding it, both left in every
-// lane), forms the multipliers of its rows and publishes them with the
+// ------------------------------------------------- blocked LU solve ----
+// X Y = R for the bounded merge matrix X (n x n) and nrhs right-hand sides,
+// stored side by side as XA = [X | R] (n x (n + nrhs), leading dimension ld),
+// by LU with partial pivoting with the forward substitution carried along as
+// extra columns.  For each panel of nb columns j0..j0+nbw-1 (pivot: the
+// largest |a| among rows j0..n-1, ties to the lowest position):
+//   k_lu_panel     factors the panel into L11 U11 (diagonal block of XA) and
+//                  the multipliers L21 (rows below, into M) and lists the
+//                  composed row interchanges;
+//   k_lu_rowblock  applies the interchanges to the columns right of the panel
+//                  (the rest of X and all of R) and replaces the panel rows
+//                  there by U12 = L11^-1 (P XA)[panel rows, right];
+//   one product    XA[below, right] -= M U12 (the FP64 MFMA GEMM).
+// Then R holds L^-1 P R, and the back substitution runs block by block from
+// the last: k_lu_diag solves U_jj Y_j = R_j, and a product removes Y_j from
+// the rows above.  sum log|U_ii| is log|det X|.  Columns left of a panel are
+// never read again and are not updated.
+constexpr int kLuMoves = 1 + 2 * 64;   // ints of the move list (count + pairs)
+
+// z <- U^-1 z for a 32 x 32 upper triangular U given by columns in LDS
+// (tt[k][r] = U[r][k]), backward and right-looking: z[k] is finished (times
+// dinv[k], unless UNIT) and taken out of the rows above; column k - 1 is
+// fetched while column k is applied, and scheduling fences bound the live
+// registers.  A lower triangular solve runs through it with both index
+// orders reversed (the forward form of this loop spills on gfx950).
+template <bool UNIT>
+__device__ __forceinline__ void tri_solve_back(double (&z)[32], const double (*tt)[34], const double* dinv) {
+  double cur[32], nxt[32];
+#pragma unroll
+  for (int r = 0; r < 31; ++r) cur[r] = tt[31][r];
+#pragma unroll
+  for (int k = 31; k >= 0; --k) {
+    if (k > 0) {
+#pragma unroll
+      for (int r = 0; r < k - 1; ++r) nxt[r] = tt[k - 1][r];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if (!UNIT) z[k] *= dinv[k];
+#pragma unroll
+    for (int r = 0; r < k; ++r) z[r] = fma(-cur[r], z[k], z[r]);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int r = 0; r < k - 1; ++r) cur[r] = nxt[r];
+  }
+}
+
+// Panel factorisation.  Layout: wave w owns the columns w*NBW/4 .. (w+1)*NBW/4
+// - 1 and lane l the rows l, l + 64, ... (MAXR of them), in registers; every
+// wave holds the same rows in the same lanes.  Pivoting is virtual: each held
+// row carries its current position, a pivot step swaps two positions (every
+// wave keeps the same copy), and the rows are written to their final places.
+// The column loop runs over the owning wave and, unrolled, over its columns,
+// so the owner addresses its column without selects.  Per column c the owner
+// finds the pivot (wave max, then the lowest position holding it, both left in
+// every lane), forms the multipliers of its rows and publishes them with the
 // pivot's lane and register through LDS (two alternating buffers); after one
 // barrier every wave reads the pivot row from its own registers (a uniform
 // register index) by readlane and eliminates its columns, with a zero
-// multiplier for columns at or left of c, so no branches.
-constexpr int kLuMoves = 1 + 2 * 64;   // ints of the move list (count + pairs)
-
+// multiplier for columns at or left of c, so no branches.  The move list
+// (moves[0] = count K <= 2 nbw, then K pairs (destination, source), absolute
+// rows) is written for k_lu_rowblock.
 template <int NBW, int MAXR>
-__global__ __launch_bounds__(256) void k_lu_panel_reg(double* X, int n, int j0, int nbw, int* moves, int* err,
-                                                      size_t cs) {
+__global__ __launch_bounds__(256) void k_lu_panel(double* XA, int n, int ld, int j0, int nbw, double* M, int ldm,
+                                                  int* moves, int* err, size_t cs) {
   extern __shared__ double smem[];   // 2 x 64 MAXR multipliers
   constexpr int CPW = NBW / 4, HR = 64 * MAXR;
   __shared__ int piv_s[2][3];        // pivot position, lane, register
   {
     const size_t co = (size_t)blockIdx.y * cs;
-    X += co;
+    XA += co; M += co;
     moves = reinterpret_cast<int*>(reinterpret_cast<double*>(moves) + co);
     err = reinterpret_cast<int*>(reinterpret_cast<double*>(err) + co);
   }
@@ -386,16 +424,19 @@ __global__ __launch_bounds__(256) void k_lu_panel_reg(double* X, int n, int j0, 
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   double a[MAXR][CPW];
   int pos[MAXR];
+  // unconditional loads from clamped addresses (all in flight together), then
+  // zeros outside the panel
 #pragma unroll
   for (int i = 0; i < MAXR; ++i) {
-    const int r = lane + 64 * i;
+    const int r = lane + 64 * i, rc = min(r, h - 1);
     pos[i] = (r < h) ? r : 0x7fffffff;
 #pragma unroll
-    for (int j = 0; j < CPW; ++j) {
-      const int q = w * CPW + j;
-      a[i][j] = (r < h && q < nbw) ? X[(size_t)(j0 + r) * n + j0 + q] : 0.0;
-    }
+    for (int j = 0; j < CPW; ++j) a[i][j] = XA[(size_t)(j0 + rc) * ld + j0 + min(w * CPW + j, nbw - 1)];
   }
+#pragma unroll
+  for (int i = 0; i < MAXR; ++i)
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) a[i][j] = (lane + 64 * i < h && w * CPW + j < nbw) ? a[i][j] : 0.0;
   const int ncol = min(nbw, h);
   for (int cw = 0; cw < 4; ++cw) {
 #pragma unroll
@@ -464,13 +505,21 @@ __global__ __launch_bounds__(256) void k_lu_panel_reg(double* X, int n, int j0, 
       }
     }
   }
+  // diagonal block (L11 below, U11 on and above the diagonal) into XA,
+  // multipliers of the rows below into M
 #pragma unroll
   for (int i = 0; i < MAXR; ++i) {
     if (pos[i] < h) {
 #pragma unroll
       for (int j = 0; j < CPW; ++j) {
         const int q = w * CPW + j;
-        if (q < nbw) X[(size_t)(j0 + pos[i]) * n + j0 + q] = a[i][j];
+        if (q < nbw) {
+          if (pos[i] < nbw) {
+            XA[(size_t)(j0 + pos[i]) * ld + j0 + q] = a[i][j];
+          } else {
+            M[(size_t)(j0 + pos[i]) * ldm + q] = a[i][j];
+          }
+        }
       }
     }
   }
@@ -494,91 +543,102 @@ __global__ __launch_bounds__(256) void k_lu_panel_reg(double* X, int n, int j0, 
   }
 }
 
-// Apply the interchanges of one panel (the move list of k_lu_panel_reg) to the
-// columns of X outside the panel and to every column of the right-hand sides B
-// (n x nrhs, ld ldb): one thread per column loads all moved rows first, so
-// their latencies overlap, then stores them at their destinations.
-__global__ __launch_bounds__(256) void k_lu_swap(double* X, int n, int j0, int nbw, const int* moves, double* B,
-                                                 int nrhs, int ldb, size_t cs) {
+// Interchanges and U12 for the columns j0+nbw .. ncols-1 of XA, one thread per
+// column: the sources of the panel rows are loaded together, the rows moved
+// out of the panel are copied, and the panel rows are solved with L11 (unit
+// lower, kept in LDS by columns) right-looking and stored.
+__global__ __launch_bounds__(256) void k_lu_rowblock(double* XA, int ld, int j0, int nbw, int ncols,
+                                                     const int* moves, size_t cs) {
+  __shared__ __attribute__((aligned(16))) double lr[32][34];   // lr[k][r] = L11[31 - r][31 - k]
+  __shared__ int srcrow[32], od[32], os[32], nout_s;
   {
     const size_t co = (size_t)blockIdx.y * cs;
-    X += co; B += co;
+    XA += co;
     moves = reinterpret_cast<const int*>(reinterpret_cast<const double*>(moves) + co);
   }
-  const int col = blockIdx.x * blockDim.x + threadIdx.x;
-  const int nx = n - nbw;
-  if (col >= nx + nrhs) return;
-  double* base;
-  size_t ld;
-  if (col < nx) {
-    const int cc = col < j0 ? col : col + nbw;
-    base = X + cc;
-    ld = n;
-  } else {
-    base = B + (col - nx);
-    ld = ldb;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 32 * 32; e += 256) {
+    const int r = e >> 5, k = e & 31;
+    lr[31 - k][31 - r] = (k < r && r < nbw) ? XA[(size_t)(j0 + r) * ld + j0 + k] : (r == k ? 1.0 : 0.0);
   }
-  const int K = min(moves[0], 64);
-  double v[64];
+  if (tid < 64) {
+    const int K = min(moves[0], 64);
+    int dest = -1, src = -1;
+    if (tid < K) { dest = moves[1 + 2 * tid]; src = moves[2 + 2 * tid]; }
+    if (tid < 32) srcrow[tid] = j0 + min(tid, nbw - 1);   // rows past nbw: any valid row
+    __builtin_amdgcn_wave_barrier();   // the defaults land before the moves overwrite them
+    const bool inpanel = tid < K && dest < j0 + nbw;
+    if (inpanel) srcrow[dest - j0] = src;
+    const bool outside = tid < K && !inpanel;
+    const unsigned long long m = __ballot(outside);
+    const int at = __popcll(m & ((1ull << tid) - 1ull));
+    if (outside && at < 32) { od[at] = dest; os[at] = src; }
+    if (tid == 0) nout_s = min(__popcll(m), 32);
+  }
+  __syncthreads();
+  const int col = j0 + nbw + blockIdx.x * 256 + tid;
+  if (col >= ncols) return;
+  const int nout = nout_s;
+  double x[32];   // the panel rows in reversed order: x[31 - k] is row j0 + k
 #pragma unroll
-  for (int k = 0; k < 64; ++k)
-    if (k < K) v[k] = base[(size_t)moves[2 + 2 * k] * ld];
+  for (int k = 0; k < 32; ++k) x[31 - k] = XA[(size_t)srcrow[k] * ld + col];
 #pragma unroll
-  for (int k = 0; k < 64; ++k)
-    if (k < K) base[(size_t)moves[1 + 2 * k] * ld] = v[k];
+  for (int k = 0; k < 32; ++k) x[31 - k] = (k < nbw) ? x[31 - k] : 0.0;
+  // rows moved out of the panel, eight at a time: with pivot rows at or below
+  // their step, a row leaving the panel carries an original panel row, and
+  // panel rows are stored only at the end, so no source is overwritten first
+  for (int k0 = 0; k0 < nout; k0 += 8) {
+    double ov[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (k0 + k < nout) ov[k] = XA[(size_t)os[k0 + k] * ld + col];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (k0 + k < nout) XA[(size_t)od[k0 + k] * ld + col] = ov[k];
+  }
+  tri_solve_back<true>(x, lr, nullptr);
+#pragma unroll
+  for (int k = 0; k < 32; ++k)   // (this store order keeps the register count under the limit)
+    if (31 - k < nbw) XA[(size_t)(j0 + 31 - k) * ld + col] = x[k];
 }
 
-// Solve Tri * Z = Bm in place for a block of nrow <= 32 rows: Tri is the
-// nrow x nrow diagonal block (ld ldt), lower with unit diagonal or upper with
-// its own diagonal.  One thread per column of Bm; the column stays in
-// registers (a 32-row block padded with identity rows).  Right-looking: once
-// z[k] is final it is taken out of every later row, so the dependent chain is
-// one FMA per row; Tri is kept in LDS by columns (tt[k][r] = Tri[r][k]) for
-// 16-byte broadcast reads, and the upper case multiplies by the reciprocal
-// diagonal.
-__global__ __launch_bounds__(256) void k_trsm_block(const double* Tri, int ldt, double* Bm, int ldb, int nrow,
-                                                    int ncol, int upper, size_t cs) {
-  __shared__ __attribute__((aligned(16))) double tt[32][34];
+// U_jj Y_j = R_j for the diagonal block starting at row r0: grid (columns /
+// 256, chains); the right-hand sides start at column n of XA.  Right-looking
+// with the reciprocal diagonal; the block is kept in LDS by columns.
+__global__ __launch_bounds__(256) void k_lu_diag(double* XA, int n, int ld, int r0, int nb, int nrhs, size_t cs) {
+  __shared__ __attribute__((aligned(16))) double tt[32][34];   // tt[k][r] = U[r][k]
   __shared__ double dinv[32];
-  Tri += (size_t)blockIdx.y * cs;
-  Bm += (size_t)blockIdx.y * cs;
+  XA += (size_t)blockIdx.y * cs;
+  const int nrow = min(nb, n - r0);
+  const double* U = XA + (size_t)r0 * ld + r0;
+  double* B = XA + (size_t)r0 * ld + n;
   for (int e = threadIdx.x; e < 32 * 32; e += 256) {
     const int r = e >> 5, k = e & 31;
-    tt[k][r] = (r < nrow && k < nrow) ? Tri[(size_t)r * ldt + k] : (r == k ? 1.0 : 0.0);
+    tt[k][r] = (r < nrow && k < nrow && k >= r) ? U[(size_t)r * ld + k] : (r == k ? 1.0 : 0.0);
   }
   __syncthreads();
   if (threadIdx.x < 32) dinv[threadIdx.x] = 1.0 / tt[threadIdx.x][threadIdx.x];
   __syncthreads();
-  const int col = blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= ncol) return;
+  const int col = blockIdx.x * 256 + threadIdx.x;
+  if (col >= nrhs) return;
   double z[32];
 #pragma unroll
-  for (int r = 0; r < 32; ++r) z[r] = (r < nrow) ? Bm[(size_t)r * ldb + col] : 0.0;
-  if (!upper) {
+  for (int r = 0; r < 32; ++r) z[r] = B[(size_t)min(r, nrow - 1) * ld + col];
 #pragma unroll
-    for (int k = 0; k < 31; ++k)
-#pragma unroll
-      for (int r = k + 1; r < 32; ++r) z[r] = fma(-tt[k][r], z[k], z[r]);
-  } else {
-#pragma unroll
-    for (int k = 31; k >= 0; --k) {
-      z[k] *= dinv[k];
-#pragma unroll
-      for (int r = 0; r < k; ++r) z[r] = fma(-tt[k][r], z[k], z[r]);
-    }
-  }
+  for (int r = 0; r < 32; ++r) z[r] = (r < nrow) ? z[r] : 0.0;
+  tri_solve_back<false>(z, tt, dinv);
 #pragma unroll
   for (int r = 0; r < 32; ++r)
-    if (r < nrow) Bm[(size_t)r * ldb + col] = z[r];
+    if (r < nrow) B[(size_t)r * ld + col] = z[r];
 }
 
 // out += sum_i log|U_ii| (one workgroup)
-__global__ __launch_bounds__(256) void k_logabs_diag(const double* U, int n, double* out, size_t cs) {
+__global__ __launch_bounds__(256) void k_logabs_diag(const double* U, int n, int ld, double* out, size_t cs) {
   __shared__ double red[8];
   U += (size_t)blockIdx.y * cs;
   out += (size_t)blockIdx.y * cs;
   double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) s += log(fabs(U[(size_t)i * n + i]));
+  for (int i = threadIdx.x; i < n; i += 256) s += log(fabs(U[(size_t)i * ld + i]));
   s = block_sum<256>(s, red);
   if (threadIdx.x == 0) *out += s;
 }

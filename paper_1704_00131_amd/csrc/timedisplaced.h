@@ -45,11 +45,11 @@ __global__ __launch_bounds__(256) void k_td_init(const double* G, double* GT0, d
   }
 }
 
-// Right-hand sides of the re-anchoring solve, n x 2n with leading dimension 2n:
+// Right-hand sides of the re-anchoring solve, n x 2n with leading dimension ld:
 //   [ D_b^-1 Q^T | D_s T ],  D_b = max(D, 1), D_s = min(D, 1).
 // Grid (t, t, chains); cs_src = 0 when the right form is the shared identity.
-__global__ __launch_bounds__(256) void k_td_rhs(double* R2, const double* Q, const double* T, const double* D, int n,
-                                                size_t cs_dst, size_t cs_src) {
+__global__ __launch_bounds__(256) void k_td_rhs(double* R2, int ld_r, const double* Q, const double* T,
+                                                const double* D, int n, size_t cs_dst, size_t cs_src) {
   __shared__ double tile[32][33];
   R2 += (size_t)blockIdx.z * cs_dst;
   Q += (size_t)blockIdx.z * cs_src;
@@ -57,7 +57,7 @@ __global__ __launch_bounds__(256) void k_td_rhs(double* R2, const double* Q, con
   D += (size_t)blockIdx.z * cs_src;
   const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  const size_t ld = 2 * (size_t)n;
+  const size_t ld = (size_t)ld_r;
   for (int r = ty; r < 32; r += 8) {
     const int i = by + r, j = bx + tx;
     tile[r][tx] = (i < n && j < n) ? Q[(size_t)i * n + j] : 0.0;

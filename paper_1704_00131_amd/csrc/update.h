@@ -123,7 +123,9 @@ __global__ __launch_bounds__(256) void k_block_update(BlockArgs a) {
     const int x = lane & 31;
     double c[32];
 #pragma unroll
-    for (int y = 0; y < 32; ++y) c[y] = (x < bb && y < bb) ? a.Gin[(size_t)(s0 + x) * N + s0 + y] : 0.0;
+    for (int y = 0; y < 32; ++y) c[y] = a.Gin[(size_t)(s0 + min(x, bb - 1)) * N + s0 + min(y, bb - 1)];
+#pragma unroll
+    for (int y = 0; y < 32; ++y) c[y] = (x < bb && y < bb) ? c[y] : 0.0;   // loads above issue back to back
     // draws and ratio constants of site x (from k_pass_draws)
     double u = 2.0, dl = 0.0, pr = 0.0, sold = 0.0, snew = 0.0;
     if (x < bb) {
