@@ -562,9 +562,14 @@ dqmc_status measure(dqmc_ctx* c) {
   const bool one = N <= kMeasSmallN;
   const int rows = one ? N : kMeasRows;
   const int nblk = (N + rows - 1) / rows;
-  hipLaunchKernelGGL(k_measure_part, gridc(c, (unsigned)nblk), dim3(256), 0, c->stream, c->Gcur, T1, c->Ehinv, c->Kd,
-                     N, rows, c->mpart, one ? 1 : 0, c->trK, (double)c->m.n_col, c->m.u_int, c->bins, c->err_flag,
-                     c->cs);
+  if (T1)
+    hipLaunchKernelGGL(k_measure_part<true>, gridc(c, (unsigned)nblk), dim3(256), 0, c->stream, c->Gcur, T1, c->Ehinv,
+                       c->Kd, N, rows, c->mpart, one ? 1 : 0, c->trK, (double)c->m.n_col, c->m.u_int, c->bins,
+                       c->err_flag, c->cs);
+  else
+    hipLaunchKernelGGL(k_measure_part<false>, gridc(c, (unsigned)nblk), dim3(256), 0, c->stream, c->Gcur, T1,
+                       c->Ehinv, c->Kd, N, rows, c->mpart, one ? 1 : 0, c->trK, (double)c->m.n_col, c->m.u_int,
+                       c->bins, c->err_flag, c->cs);
   if (!one)
     hipLaunchKernelGGL(k_measure_finish, gridc(c, 1), dim3(64), 0, c->stream, c->mpart, nblk, N, c->trK,
                        (double)c->m.n_col, c->m.u_int, c->bins, c->err_flag, c->cs);

@@ -250,12 +250,14 @@ __global__ __launch_bounds__(256) void k_block_update(BlockArgs a) {
 // T1 = exp(-dtau K/2) G (Ehinv is symmetric, so the sum runs along row i of
 // both).  K is symmetric, so Tr(K G) = sum_e K[e] G[e].
 //
-// k_measure_part gives each workgroup `rows` rows (one wave per row at a time,
-// coalesced) and writes the partial sums (sum d (1 - d), sum K.G, non-finite
-// flag); k_measure_finish adds the partials in a fixed order and updates the
-// bins.  For small N a single workgroup covers all rows and finishes itself
-// (fin != 0), one launch per measurement.
-constexpr int kMeasRows = 16, kMeasSmallN = 128;
+// k_measure_part gives each workgroup `rows` rows (wave w takes rows
+// r0 + w, r0 + w + 4, ...; one row at a time across the wave, coalesced, with
+// the row's loads unconditional so they overlap) and writes the partial sums
+// (sum d (1 - d), sum K.G, non-finite flag); k_measure_finish adds the partials
+// and updates the bins.  For small N a single workgroup covers all rows and
+// finishes itself (fin != 0), one launch per measurement.  SYM: d_i from T1 and
+// Ehinv as above, else the diagonal of G.
+constexpr int kMeasRows = 4, kMeasSmallN = 128;
 
 __device__ __forceinline__ void measure_bins(double sd, double skg, double bad, int N, double trK, double n_col,
                                              double u_int, double* bins, int* err) {
@@ -267,45 +269,46 @@ __device__ __forceinline__ void measure_bins(double sd, double skg, double bad, 
   if (bad > 0.0) atomicOr(err, 1);
 }
 
+template <bool SYM>
 __global__ __launch_bounds__(256) void k_measure_part(const double* G, const double* T1, const double* Ehinv,
                                                       const double* K, int N, int rows, double* part, int fin,
                                                       double trK, double n_col, double u_int, double* bins, int* err,
                                                       size_t cs) {
-  __shared__ double red[4];
+  __shared__ double red[4][3];
   {
     const size_t co = (size_t)blockIdx.y * cs;
     G += co;
-    if (T1) T1 += co;
+    if (SYM) T1 += co;
     part += co;
     bins += co;
     err = reinterpret_cast<int*>(reinterpret_cast<double*>(err) + co);
   }
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int r0 = blockIdx.x * rows;
-  double sd = 0.0, skg = 0.0, bad = 0.0;
-  for (int i = r0 + w; i < min(N, r0 + rows); i += 4) {
+  const int r0 = blockIdx.x * rows, r1 = min(N, r0 + rows);
+  double sd = 0.0, skg = 0.0, bad = 0.0;   // this wave's rows (same in every lane)
+  for (int i = r0 + w; i < r1; i += 4) {
     const double* gi = G + (size_t)i * N;
     const double* ki = K + (size_t)i * N;
-    double p = 0.0;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};    // K.G, T1.Ehinv, non-finite
+#pragma unroll 4
     for (int b = lane; b < N; b += 64) {
       const double gv = gi[b];
-      skg += ki[b] * gv;
-      if (!isfinite(gv)) bad = 1.0;
-      if (T1) p += T1[(size_t)i * N + b] * Ehinv[(size_t)i * N + b];
+      v[0] = fma(ki[b], gv, v[0]);
+      if (!isfinite(gv)) v[2] = 1.0;
+      if (SYM) v[1] = fma(T1[(size_t)i * N + b], Ehinv[(size_t)i * N + b], v[1]);
     }
-    double d;
-    if (T1) {
-      for (int o = 32; o > 0; o >>= 1) p += __shfl_xor(p, o, 64);
-      d = p;
-    } else {
-      d = gi[i];
-    }
-    if (lane == 0) sd += d * (1.0 - d);
+    wave_sums<4>(v);
+    const double d = SYM ? v[1] : gi[i];
+    sd += d * (1.0 - d);
+    skg += v[0];
+    bad += v[2];
   }
-  sd = block_sum<256>(sd, red);
-  skg = block_sum<256>(skg, red);
-  bad = block_sum<256>(bad, red);
+  if (lane == 0) { red[w][0] = sd; red[w][1] = skg; red[w][2] = bad; }
+  __syncthreads();
   if (tid == 0) {
+    sd = (red[0][0] + red[1][0]) + (red[2][0] + red[3][0]);
+    skg = (red[0][1] + red[1][1]) + (red[2][1] + red[3][1]);
+    bad = (red[0][2] + red[1][2]) + (red[2][2] + red[3][2]);
     if (fin) {
       measure_bins(sd, skg, bad, N, trK, n_col, u_int, bins, err);
     } else {
@@ -316,20 +319,22 @@ __global__ __launch_bounds__(256) void k_measure_part(const double* G, const dou
   }
 }
 
+// One wave: lane l adds the partial records l, l + 64, ... and the wave sums
+// the lanes.
 __global__ __launch_bounds__(64) void k_measure_finish(const double* part, int nblk, int N, double trK, double n_col,
                                                        double u_int, double* bins, int* err, size_t cs) {
   const size_t co = (size_t)blockIdx.y * cs;
   part += co;
   bins += co;
   err = reinterpret_cast<int*>(reinterpret_cast<double*>(err) + co);
-  if (threadIdx.x != 0) return;
-  double sd = 0.0, skg = 0.0, bad = 0.0;
-  for (int b = 0; b < nblk; ++b) {
-    sd += part[4 * b];
-    skg += part[4 * b + 1];
-    bad += part[4 * b + 2];
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nblk; b += 64) {
+    v[0] += part[4 * b];
+    v[1] += part[4 * b + 1];
+    v[2] += part[4 * b + 2];
   }
-  measure_bins(sd, skg, bad, N, trK, n_col, u_int, bins, err);
+  wave_sums<4>(v);
+  if (threadIdx.x == 0) measure_bins(v[0], v[1], v[2], N, trK, n_col, u_int, bins, err);
 }
 
 // Weight ratio of one proposed change s -> s_new at a site, from G(tau) (the
