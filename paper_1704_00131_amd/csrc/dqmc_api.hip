@@ -159,7 +159,7 @@ size_t layout_chain(dqmc_ctx* c, double* base) {
   P(c->logdet, 4);
   P(c->grad, (size_t)c->L * N);
   P(c->gprec, 4);
-  P(c->mpart, 4 * (size_t)((N + kMeasRows - 1) / kMeasRows));
+  P(c->mpart, 4 * (size_t)((N + kMeasRows - 1) / kMeasRows) + 4);   // partials, then the counter
   P(c->draws, 4 * (size_t)c->L * N);
   for (int i = 0; i < 4; ++i) P(c->TD[i], NN);
   P(c->tdS, (size_t)(c->L + 1) * kTdStride);
@@ -559,20 +559,15 @@ dqmc_status measure(dqmc_ctx* c) {
     if (dqmc_status s = gemm(c, gemm_args(N, N, N, c->Eh, N, 0, c->Gcur, N, 0, c->T1, N))) return s;
     T1 = c->T1;
   }
-  const bool one = N <= kMeasSmallN;
-  const int rows = one ? N : kMeasRows;
+  const int rows = N <= kMeasSmallN ? N : kMeasRows;
   const int nblk = (N + rows - 1) / rows;
   if (T1)
     hipLaunchKernelGGL(k_measure_part<true>, gridc(c, (unsigned)nblk), dim3(256), 0, c->stream, c->Gcur, T1, c->Ehinv,
-                       c->Kd, N, rows, c->mpart, one ? 1 : 0, c->trK, (double)c->m.n_col, c->m.u_int, c->bins,
-                       c->err_flag, c->cs);
+                       c->Kd, N, rows, c->mpart, c->trK, (double)c->m.n_col, c->m.u_int, c->bins, c->err_flag, c->cs);
   else
     hipLaunchKernelGGL(k_measure_part<false>, gridc(c, (unsigned)nblk), dim3(256), 0, c->stream, c->Gcur, T1,
-                       c->Ehinv, c->Kd, N, rows, c->mpart, one ? 1 : 0, c->trK, (double)c->m.n_col, c->m.u_int,
-                       c->bins, c->err_flag, c->cs);
-  if (!one)
-    hipLaunchKernelGGL(k_measure_finish, gridc(c, 1), dim3(64), 0, c->stream, c->mpart, nblk, N, c->trK,
-                       (double)c->m.n_col, c->m.u_int, c->bins, c->err_flag, c->cs);
+                       c->Ehinv, c->Kd, N, rows, c->mpart, c->trK, (double)c->m.n_col, c->m.u_int, c->bins,
+                       c->err_flag, c->cs);
   HIPCHK(hipGetLastError());
   return DQMC_OK;
 }
@@ -963,6 +958,8 @@ dqmc_status setup_device(dqmc_ctx* c) {
   if (dqmc_status s = fill_small(c, c->uid.D, N, 1.0)) return s;
   if (dqmc_status s = fill_small(c, reinterpret_cast<double*>(c->counters), 4, 0.0)) return s;
   if (dqmc_status s = fill_small(c, reinterpret_cast<double*>(c->err_flag), 1, 0.0)) return s;
+  // measurement partials and their completion counter
+  if (dqmc_status s = fill_small(c, c->mpart, 4 * (size_t)((N + kMeasRows - 1) / kMeasRows) + 4, 0.0)) return s;
   if (c->seeds.empty()) c->seeds.assign(c->nch, c->m.seed);
   // chain keys: host -> staging buffer -> counters[3] of every chain
   HIPCHK(hipMemcpyAsync(c->gbuf, c->seeds.data(), sizeof(uint64_t) * c->nch, hipMemcpyHostToDevice, c->stream));
@@ -1364,7 +1361,7 @@ bool layout_ok(const dqmc_ctx* c, const double* lo, const double* hi) {
   ok = ok && in(c->field_alt, (size_t)c->L * N, true) && in(c->norms, N, true) && in(c->piv, N / 2 + 1, true) &&
        in(c->moves, (kLuMoves + 1) / 2, true) && in(c->bins, 4, true) && in(c->prec_hist, 2 * (size_t)c->nk + 2, true) &&
        in(c->prec_tot, 4, true) && in(c->logdet, 4, true) && in(c->grad, (size_t)c->L * N, true) && in(c->gprec, 4, true) &&
-       in(c->mpart, 4 * (size_t)((N + kMeasRows - 1) / kMeasRows), true) &&
+       in(c->mpart, 4 * (size_t)((N + kMeasRows - 1) / kMeasRows) + 4, true) &&
        in(c->draws, 4 * (size_t)c->L * N, true) &&
        in(c->TD[0], NN, true) && in(c->TD[1], NN, true) && in(c->TD[2], NN, true) && in(c->TD[3], NN, true) &&
        in(c->tdS, (size_t)(c->L + 1) * kTdStride, true) &&

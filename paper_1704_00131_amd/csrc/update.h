@@ -253,10 +253,11 @@ __global__ __launch_bounds__(256) void k_block_update(BlockArgs a) {
 // k_measure_part gives each workgroup `rows` rows (wave w takes rows
 // r0 + w, r0 + w + 4, ...; one row at a time across the wave, coalesced, with
 // the row's loads unconditional so they overlap) and writes the partial sums
-// (sum d (1 - d), sum K.G, non-finite flag); k_measure_finish adds the partials
-// and updates the bins.  For small N a single workgroup covers all rows and
-// finishes itself (fin != 0), one launch per measurement.  SYM: d_i from T1 and
-// Ehinv as above, else the diagonal of G.
+// (sum d (1 - d), sum K.G, non-finite flag); the workgroup that finishes last
+// (a counter after the partials, taken with a device-scope atomic behind a
+// release fence, and reset by that workgroup) adds the partials with one wave
+// and updates the bins.  For small N a single workgroup covers all rows
+// (nblk == 1).  SYM: d_i from T1 and Ehinv as above, else the diagonal of G.
 constexpr int kMeasRows = 4, kMeasSmallN = 128;
 
 __device__ __forceinline__ void measure_bins(double sd, double skg, double bad, int N, double trK, double n_col,
@@ -271,10 +272,10 @@ __device__ __forceinline__ void measure_bins(double sd, double skg, double bad, 
 
 template <bool SYM>
 __global__ __launch_bounds__(256) void k_measure_part(const double* G, const double* T1, const double* Ehinv,
-                                                      const double* K, int N, int rows, double* part, int fin,
-                                                      double trK, double n_col, double u_int, double* bins, int* err,
-                                                      size_t cs) {
+                                                      const double* K, int N, int rows, double* part, double trK,
+                                                      double n_col, double u_int, double* bins, int* err, size_t cs) {
   __shared__ double red[4][3];
+  __shared__ int last_s;
   {
     const size_t co = (size_t)blockIdx.y * cs;
     G += co;
@@ -305,36 +306,29 @@ __global__ __launch_bounds__(256) void k_measure_part(const double* G, const dou
   }
   if (lane == 0) { red[w][0] = sd; red[w][1] = skg; red[w][2] = bad; }
   __syncthreads();
+  const int nblk = gridDim.x;
+  unsigned int* counter = reinterpret_cast<unsigned int*>(part + 4 * (size_t)nblk);
   if (tid == 0) {
-    sd = (red[0][0] + red[1][0]) + (red[2][0] + red[3][0]);
-    skg = (red[0][1] + red[1][1]) + (red[2][1] + red[3][1]);
-    bad = (red[0][2] + red[1][2]) + (red[2][2] + red[3][2]);
-    if (fin) {
-      measure_bins(sd, skg, bad, N, trK, n_col, u_int, bins, err);
-    } else {
-      part[4 * blockIdx.x] = sd;
-      part[4 * blockIdx.x + 1] = skg;
-      part[4 * blockIdx.x + 2] = bad;
-    }
+    part[4 * blockIdx.x] = (red[0][0] + red[1][0]) + (red[2][0] + red[3][0]);
+    part[4 * blockIdx.x + 1] = (red[0][1] + red[1][1]) + (red[2][1] + red[3][1]);
+    part[4 * blockIdx.x + 2] = (red[0][2] + red[1][2]) + (red[2][2] + red[3][2]);
+    __threadfence();
+    last_s = (atomicAdd(counter, 1u) == (unsigned)nblk - 1u);
   }
-}
-
-// One wave: lane l adds the partial records l, l + 64, ... and the wave sums
-// the lanes.
-__global__ __launch_bounds__(64) void k_measure_finish(const double* part, int nblk, int N, double trK, double n_col,
-                                                       double u_int, double* bins, int* err, size_t cs) {
-  const size_t co = (size_t)blockIdx.y * cs;
-  part += co;
-  bins += co;
-  err = reinterpret_cast<int*>(reinterpret_cast<double*>(err) + co);
+  __syncthreads();
+  if (!last_s || w != 0) return;
+  __threadfence();
   double v[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int b = threadIdx.x; b < nblk; b += 64) {
-    v[0] += part[4 * b];
-    v[1] += part[4 * b + 1];
-    v[2] += part[4 * b + 2];
+  for (int b = lane; b < nblk; b += 64) {
+    v[0] += __builtin_nontemporal_load(part + 4 * b);
+    v[1] += __builtin_nontemporal_load(part + 4 * b + 1);
+    v[2] += __builtin_nontemporal_load(part + 4 * b + 2);
   }
   wave_sums<4>(v);
-  if (threadIdx.x == 0) measure_bins(v[0], v[1], v[2], N, trK, n_col, u_int, bins, err);
+  if (lane == 0) {
+    measure_bins(v[0], v[1], v[2], N, trK, n_col, u_int, bins, err);
+    *counter = 0u;   // ready for the next measurement (kernel boundaries order it)
+  }
 }
 
 // Weight ratio of one proposed change s -> s_new at a site, from G(tau) (the
