@@ -409,8 +409,9 @@ dqmc_status qr_udv(dqmc_ctx* c, double* M, const double* T_in, UDVp out) {
     const int ntr = N - j0 - nbw;
     if (ntr > 0) {
       double* At = Ap + (size_t)j0 * N + j0 + nbw;
-      if (dqmc_status s = gemm(c, gemm_args(nbw, ntr, h, VT, nbw, 1, At, N, 0, c->Zq, N))) return s;
-      if (dqmc_status s = gemm(c, gemm_args(h, ntr, nbw, V, nbw, 0, c->Zq, N, 0, At, N, -1.0, 1.0))) return s;
+      hipLaunchKernelGGL(k_apply_wy, gridc(c, (unsigned)((ntr + 15) / 16)), dim3(256), 0, c->stream, V, VT, nbw, At,
+                         N, h, ntr, nbw, c->cs, c->cs);
+      HIPCHK(hipGetLastError());
     }
   }
   // explicit Q by backward accumulation of the block reflectors
@@ -422,8 +423,9 @@ dqmc_status qr_udv(dqmc_ctx* c, double* M, const double* T_in, UDVp out) {
     double* V = c->Vall + (size_t)j0 * N;
     double* VT = c->VTall + (size_t)j0 * N;
     double* Qs = out.Q + (size_t)j0 * N + j0;
-    if (dqmc_status s = gemm(c, gemm_args(nbw, h, h, V, nbw, 1, Qs, N, 0, c->Zq, N))) return s;
-    if (dqmc_status s = gemm(c, gemm_args(h, h, nbw, VT, nbw, 0, c->Zq, N, 0, Qs, N, -1.0, 1.0))) return s;
+    hipLaunchKernelGGL(k_apply_wy, gridc(c, (unsigned)((h + 15) / 16)), dim3(256), 0, c->stream, VT, V, nbw, Qs, N,
+                       h, h, nbw, c->cs, c->cs);
+    HIPCHK(hipGetLastError());
   }
   hipLaunchKernelGGL(k_build_rt, gridc(c, grid1((size_t)N * N)), dim3(256), 0, c->stream, Ap, c->piv, N, c->Rt,
                      out.D, c->err_flag, c->cs);

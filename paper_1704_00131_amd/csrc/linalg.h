@@ -88,20 +88,23 @@ __global__ __launch_bounds__(256) void k_colnorm_part(const double* M, int n, do
 // piv[p] = index of the column with the p-th largest 2-norm (ties: lower index)
 __global__ __launch_bounds__(1024) void k_colnorm_order(const double* part, int nblk, int n, double* norms, int* piv,
                                                         size_t cs) {
+  __shared__ double sn[1024];   // n <= 1024: the norms, read back as LDS broadcasts by the ranking
   part += (size_t)blockIdx.y * cs;
   norms += (size_t)blockIdx.y * cs;
   piv = reinterpret_cast<int*>(reinterpret_cast<double*>(piv) + (size_t)blockIdx.y * cs);
   for (int j = threadIdx.x; j < n; j += blockDim.x) {
     double s = 0.0;
     for (int b = 0; b < nblk; ++b) s += part[(size_t)b * n + j];
-    norms[j] = (s == s) ? s : INFINITY;   // a NaN column sorts first; ranks stay a permutation
+    s = (s == s) ? s : INFINITY;   // a NaN column sorts first; ranks stay a permutation
+    norms[j] = s;
+    sn[j] = s;
   }
   __syncthreads();
   for (int j = threadIdx.x; j < n; j += blockDim.x) {
-    const double v = norms[j];
+    const double v = sn[j];
     int rank = 0;
     for (int i = 0; i < n; ++i) {
-      const double u = norms[i];
+      const double u = sn[i];
       rank += (u > v) || (u == v && i < j);
     }
     piv[rank] = j;
@@ -192,7 +195,7 @@ __global__ __launch_bounds__(256) void k_qr_panel(double* A, int n, int j0, int 
     for (int cj = 0; cj < CPW; ++cj) {
       const int c = cw * CPW + cj;
       if (c >= ncol) break;
-      double vr[MAXR];
+      double vr[MAXR], tc;   // the owner keeps v and tau in registers
       if (w == cw) {
         // sum of squares below c, x0 (rows at or above c are in group 0)
         double sx[2] = {0.0, (lane == c) ? a[0][cj] : 0.0};
@@ -201,7 +204,7 @@ __global__ __launch_bounds__(256) void k_qr_panel(double* A, int n, int j0, int 
         for (int i = 1; i < MAXR; ++i) sx[0] = fma(a[i][cj], a[i][cj], sx[0]);
         wave_sums<2>(sx);
         const double s = sx[0], x0 = sx[1];
-        double beta, tc, scal;
+        double beta, scal;
         if (s == 0.0) { tc = 0.0; beta = x0; scal = 0.0; }
         else {
           const double nrm = sqrt(x0 * x0 + s);
@@ -224,8 +227,8 @@ __global__ __launch_bounds__(256) void k_qr_panel(double* A, int n, int j0, int 
         if (lane == 0) { tau[c] = tc; bet[c] = beta; }
       }
       __syncthreads();
-      const double tc = tau[c];
       if (w != cw) {
+        tc = tau[c];
 #pragma unroll
         for (int i = 0; i < MAXR; ++i) vr[i] = vsh[(lane + 64 * i) * PV + c];
       }
@@ -323,6 +326,104 @@ __global__ __launch_bounds__(256) void k_qr_panel(double* A, int n, int j0, int 
       for (int rr = 0; rr < 4; ++rr) {
         const int orow = tr * 16 + kk + 4 * rr;
         if (orow < h && col < nbw) VTout[(size_t)orow * nbw + col] = acc[tc][rr];
+      }
+    }
+  }
+}
+
+// Block reflector applied in one launch: C <- C - P (S^T C) for an h x ncol
+// block C (ld ldc) and the h x nbw factors P, S (ld ldps, nbw <= 32): with
+// (P, S) = (V, VT) it is Q^T C for the trailing matrix of a QR panel, with
+// (VT, V) it is Q C for the accumulation of Q.  One workgroup per 16 columns
+// of C: the four waves split the rows for Z = S^T C (two 16 x 16 MFMA tiles
+// each, summed through LDS), then split the 16-row tiles of C for
+// C - P Z (the accumulator starts from C and P enters negated).  Operands are
+// read from clamped addresses and masked, so the loads issue back to back.
+__global__ __launch_bounds__(256) void k_apply_wy(const double* P, const double* S, int ldps, double* C, int ldc,
+                                                  int h, int ncol, int nbw, size_t cs_ps, size_t cs_c) {
+  __shared__ double zp[4][2][4][64];   // per-wave partial Z tiles in the MFMA D layout
+  __shared__ double Zs[32][17];        // Z: nbw x 16
+  P += (size_t)blockIdx.y * cs_ps;
+  S += (size_t)blockIdx.y * cs_ps;
+  C += (size_t)blockIdx.y * cs_c;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int m16 = lane & 15, kk = lane >> 4;
+  const int c0 = blockIdx.x * 16, col = c0 + m16, colc = min(col, ncol - 1);
+  const bool cin = col < ncol;
+  // Z = S^T C over this wave's quarter of the rows, k-steps of 4
+  const int kq = ((h + 15) / 16) * 4;
+  const int kb = w * kq, ke = min(h, kb + kq);
+  v4d z[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+  constexpr int U = 6;   // k-steps whose loads are issued together
+  for (int kc = kb; kc < ke; kc += 4 * U) {
+    double a[U][2], b[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int rc = min(kc + 4 * u + kk, h - 1);
+#pragma unroll
+      for (int t = 0; t < 2; ++t) a[u][t] = S[(size_t)rc * ldps + min(t * 16 + m16, nbw - 1)];
+      b[u] = C[(size_t)rc * ldc + colc];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool rin = kc + 4 * u + kk < ke;
+#pragma unroll
+      for (int t = 0; t < 2; ++t) a[u][t] = (rin && t * 16 + m16 < nbw) ? a[u][t] : 0.0;
+      b[u] = (rin && cin) ? b[u] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) z[t] = mfma_f64_16x16x4(a[u][t], b[u], z[t]);
+  }
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) zp[w][t][rr][lane] = z[t][rr];
+  __syncthreads();
+  if (w == 0) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const double v = (zp[0][t][rr][lane] + zp[1][t][rr][lane]) + (zp[2][t][rr][lane] + zp[3][t][rr][lane]);
+        Zs[t * 16 + kk + 4 * rr][m16] = v;   // D layout: row kk + 4 rr, column m16 of tile t
+      }
+  }
+  __syncthreads();
+  // C tile - P Z, 16-row tiles over the waves; K = nbw in steps of 4 (Z rows past nbw are zero)
+  double zb[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) zb[k] = (4 * k + kk < nbw) ? Zs[4 * k + kk][m16] : 0.0;
+  const int nrt = (h + 15) / 16;
+  for (int tr0 = w; tr0 < nrt; tr0 += 8) {   // two row tiles per round, their loads together
+    v4d acc[2];
+    double pa[2][8];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int r0 = (tr0 + 4 * q) * 16, pr = min(r0 + m16, h - 1);
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) acc[q][rr] = C[(size_t)min(r0 + kk + 4 * rr, h - 1) * ldc + colc];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) pa[q][k] = P[(size_t)pr * ldps + min(4 * k + kk, nbw - 1)];
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int k = 0; k < 8; ++k) pa[q][k] = (4 * k + kk < nbw) ? -pa[q][k] : 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) acc[q] = mfma_f64_16x16x4(pa[q][k], zb[k], acc[q]);
+    if (cin) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        if (tr0 + 4 * q >= nrt) break;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const int r = (tr0 + 4 * q) * 16 + kk + 4 * rr;
+          if (r < h) C[(size_t)r * ldc + col] = acc[q][rr];
+        }
       }
     }
   }
@@ -445,6 +546,10 @@ __global__ __launch_bounds__(256) void k_lu_panel(double* XA, int n, int ld, int
       if (c >= ncol) break;
       double* lb = smem + (c & 1) * HR;
       int* ps = piv_s[c & 1];
+      // the owner keeps its multipliers and pivot in registers; the other
+      // waves read them from LDS after the barrier
+      double lr[MAXR];
+      int pp, hl, hs;
       if (w == cw) {
         double best = -1.0;
         int bi = 0x7fffffff;
@@ -456,7 +561,7 @@ __global__ __launch_bounds__(256) void k_lu_panel(double* XA, int n, int ld, int
           }
         }
         const double wm = wave_max_all(best);
-        int pp = wave_min_all_i((best == wm && best >= 0.0) ? bi : 0x7fffffff);
+        pp = wave_min_all_i((best == wm && best >= 0.0) ? bi : 0x7fffffff);
         pp = __builtin_amdgcn_readfirstlane(pp);
         // no finite candidate (a NaN column): keep the row and flag the failure
         if (!(wm >= 0.0) || pp < c || pp >= h) pp = c;
@@ -467,8 +572,8 @@ __global__ __launch_bounds__(256) void k_lu_panel(double* XA, int n, int ld, int
         for (int i = 0; i < MAXR; ++i)
           if (pos[i] == pp) { hit = i; pv = a[i][cj]; }
         const unsigned long long mask = __ballot(hit >= 0);
-        const int hl = __ffsll((long long)mask) - 1;
-        const int hs = __builtin_amdgcn_readlane(hit, hl);
+        hl = __ffsll((long long)mask) - 1;
+        hs = __builtin_amdgcn_readlane(hit, hl);
         const double inv = 1.0 / readlane_d(pv, hl);
         // multipliers of the rows that stay below the pivot (position > c after the swap)
 #pragma unroll
@@ -477,6 +582,7 @@ __global__ __launch_bounds__(256) void k_lu_panel(double* XA, int n, int ld, int
           const bool below = np > c && np < h;
           const double l = below ? a[i][cj] * inv : 0.0;
           lb[lane + 64 * i] = l;
+          lr[i] = l;
           a[i][cj] = below ? l : a[i][cj];
         }
         if (lane == 0) {
@@ -485,14 +591,15 @@ __global__ __launch_bounds__(256) void k_lu_panel(double* XA, int n, int ld, int
         }
       }
       __syncthreads();
-      const int pp = __builtin_amdgcn_readfirstlane(ps[0]);
-      const int hl = __builtin_amdgcn_readfirstlane(ps[1]);
-      const int hs = __builtin_amdgcn_readfirstlane(ps[2]);
+      if (w != cw) {
+        pp = __builtin_amdgcn_readfirstlane(ps[0]);
+        hl = __builtin_amdgcn_readfirstlane(ps[1]);
+        hs = __builtin_amdgcn_readfirstlane(ps[2]);
+#pragma unroll
+        for (int i = 0; i < MAXR; ++i) lr[i] = lb[lane + 64 * i];   // 0 for rows not below the pivot
+      }
 #pragma unroll
       for (int i = 0; i < MAXR; ++i) pos[i] = (pos[i] == pp) ? c : (pos[i] == c ? pp : pos[i]);
-      double lr[MAXR];
-#pragma unroll
-      for (int i = 0; i < MAXR; ++i) lr[i] = lb[lane + 64 * i];   // 0 for rows not below the pivot
 #pragma unroll
       for (int j = 0; j < CPW; ++j) {
         const int q = w * CPW + j;
