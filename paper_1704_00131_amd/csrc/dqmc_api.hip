@@ -195,8 +195,10 @@ inline bool is_shared(const dqmc_ctx* c, const void* p) {
 dqmc_status timing_begin(dqmc_ctx* c, int kernel) {
   if (!c->timing || c->timing_kernel != kernel) return DQMC_OK;
   while (c->ev.size() < c->ev_used + 2) {
+    // Timing-only events: no system-scope fence (cache writeback) at record,
+    // which would otherwise be counted in every bracketed launch.
     hipEvent_t e;
-    HIPCHK(hipEventCreate(&e));
+    HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     c->ev.push_back(e);
   }
   HIPCHK(hipEventRecord(c->ev[c->ev_used], c->stream));
