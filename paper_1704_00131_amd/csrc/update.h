@@ -71,36 +71,47 @@ __device__ __forceinline__ double ipow(double r, int n) {
 }
 
 
-// One workgroup per 32 x 32 tile (I, J) of G.  Every workgroup takes the same
-// sequential decisions of block S (identical arithmetic, identical results),
-// then writes Gout[I,J] = Gin[I,J] - Gin[I,S] Phi (E_S^T[:,J] - Gin[S,J]).
+// One workgroup of four waves per 32 x 32 tile (I, J) of G.  Every workgroup
+// takes the same sequential decisions of block S (identical arithmetic,
+// identical results), then writes
+//   Gout[I,J] = Gin[I,J] - Gin[I,S] Phi (E_S^T[:,J] - Gin[S,J]).
 //
-// Decisions (wave 0 alone, no workgroup barrier): lane x keeps row x of the
-// current c = G_cur[S,S] in registers and the draws of site x.  Site i reads
-// c_ii from lane i; an accepted flip updates only the trailing block,
+// Decisions (wave 0 alone): lane x keeps row x of the current c = G_cur[S,S]
+// in registers and the draws of site x.  Site i reads c_ii from lane i; an
+// accepted flip updates only the trailing block,
 //   c[x][y] += gamma c[x][i] c[i][y]   (x, y > i; row i broadcast by readlane),
-// since later decisions read only entries past i.  Row i and column i are
-// therefore frozen after site i, and the final c holds the records
-//   T_A[i][k] = gamma_i V_i[k] = -gamma_i c[i][k],
-//   T_B[i][k] = -gamma_i U_i[k] = -gamma_i c[k][i]        (k > i).
+// since later decisions read only entries past i.  So column i is final
+// before site i (only earlier sites touch it) and row i after it, and the
+// records of the Phi recursion are
+//   T_A[m][k] = -gamma_m c[m][k],  T_B[m][k] = -gamma_m c[k][m]   (k > m).
 //
 // With the vectors of the Phi recursion in the header, U_i = c a_i and
 // V_i = (1 - c_0)^T b_i, so the recursions for a and b become triangular:
 //   A (1 + T_A) = 1,  B (1 + T_B) = 1,  Phi = A diag(gamma) B^T.
-// Each workgroup needs Phi only inside Gin[I,S] Phi (E_S^T[:,J] - Gin[S,J]) =
-// X diag(gamma) Z with X = Gin[I,S] A and Z = B^T (E_S^T[:,J] - Gin[S,J]), so it
-// solves the two triangular systems for its own tile (one lane per row of X
-// and of Z^T in wave 0) and finishes with one MFMA product.
-// Workgroup 0 also writes the block's field values and the counters.
+// The tile needs Phi only inside X diag(gamma) Z with X = Gin[I,S] A and
+// Z = B^T (E_S^T[:,J] - Gin[S,J]), that is
+//   X[r][k]   = Gin[I+r][S+k] + sum_{m<k} gamma_m X[r][m] c[m][k],
+//   Z^T[y][k] = (E_S^T[:,J] - Gin[S,J])[k][y] + sum_{m<k} gamma_m Z^T[y][m] c[k][m].
+// Both read c by columns only.  Wave 0 therefore stores each column of c in
+// LDS as soon as it is final (one store per lane) and gamma of each site once
+// decided, and waves 1 and 2 solve the two systems while the decisions go on:
+// wave 1 the rows of X, left-looking (entry k is one dot product with column
+// k), wave 2 the rows of Z^T, right-looking (a final entry m is taken out of
+// the later ones with column m).  Two lanes share a row, lane sub holding the
+// entries k = sub mod 2.  An LDS counter, stored by wave 0 with workgroup-scope
+// release one site behind its own stores (so the release finds them done and
+// wave 0 does not wait), tells the solving waves how far columns and gammas
+// are visible; they read it with acquire.  One MFMA product on all four waves
+// finishes the tile.  Workgroup 0 also writes the block's field values and
+// the counters.
 template <int NCOL>
 __global__ __launch_bounds__(256) void k_block_update(BlockArgs a) {
-  constexpr int TS = 34;   // row stride of the records (16-byte aligned rows)
-  __shared__ double AB[2][32][33];   // right-hand sides, then X and Z^T
-  // records by rows, each row split by k mod 4: Tq[h][m][(k & 3) * 8 + (k >> 2)]
-  // = T_A[m][k] (h = 0) or T_B[m][k] (h = 1)
-  __shared__ __attribute__((aligned(16))) double Tq[2][32][TS];
+  __shared__ double AB[2][32][33];   // rows of X and of Z^T, for the product
+  // columns of c, each split by row parity: colc[i][(x & 1) * 16 + (x >> 1)] = c[x][i]
+  __shared__ __attribute__((aligned(16))) double colc[32][32];
   __shared__ double gam[32];
-  __shared__ int accf[32], nacc_s;
+  // vis = v: columns 0..v-1 and gamma_0..gamma_{v-2} are visible
+  __shared__ int nacc_s, vis;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int bb = a.bb, s0 = a.s0, N = a.N;
   const int tilesN = (N + 31) >> 5;
@@ -119,22 +130,59 @@ __global__ __launch_bounds__(256) void k_block_update(BlockArgs a) {
     const int row = I0 + wr * 16 + (lane >> 4) + 4 * r;
     gin[r] = (row < N && col < N) ? a.Gin[(size_t)row * N + col] : 0.0;
   }
+  if (tid == 0) vis = 0;
+  const int x = lane & 31;               // wave 0: row of c (lanes x and x + 32 alike)
+  const int fr = lane >> 1, sub = lane & 1;   // waves 1, 2: row of X or Z^T, entry parity
+  double c[32];
+  double u = 2.0, dl = 0.0, pr = 0.0, sold = 0.0, snew = 0.0;
+  double R[16];                          // waves 1, 2: entries k = 2 j + sub of the row
   if (w == 0) {
-    const int x = lane & 31;
-    double c[32];
+    // G[S,S] through LDS (AB[1] is free until the product): two rows per
+    // load, zero outside the block
 #pragma unroll
-    for (int y = 0; y < 32; ++y) c[y] = a.Gin[(size_t)(s0 + min(x, bb - 1)) * N + s0 + min(y, bb - 1)];
-#pragma unroll
-    for (int y = 0; y < 32; ++y) c[y] = (x < bb && y < bb) ? c[y] : 0.0;   // loads above issue back to back
-    // draws and ratio constants of site x (from k_pass_draws)
-    double u = 2.0, dl = 0.0, pr = 0.0, sold = 0.0, snew = 0.0;
-    if (x < bb) {
-      const double* d = a.draws + 4 * (size_t)(s0 + x);
-      u = d[0]; dl = d[1]; pr = d[2]; snew = d[3];
-      sold = a.field_in[s0 + x];
+    for (int j = 0; j < 16; ++j) {
+      const int e = 64 * j + lane, rr = e >> 5, cc = e & 31;
+      c[j] = a.Gin[(size_t)(s0 + min(rr, bb - 1)) * N + s0 + min(cc, bb - 1)];
     }
+    // draws and ratio constants of site x (from k_pass_draws)
+    {
+      const double* d = a.draws + 4 * (size_t)(s0 + min(x, bb - 1));
+      u = d[0]; dl = d[1]; pr = d[2]; snew = d[3];
+      sold = a.field_in[s0 + min(x, bb - 1)];
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int e = 64 * j + lane, rr = e >> 5, cc = e & 31;
+      AB[1][rr][cc] = (rr < bb && cc < bb) ? c[j] : 0.0;
+    }
+  } else if (w == 1) {
+    // right-hand side of X, Gin[I0+r][s0+k], through LDS: two rows per load
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int e = 64 * j + lane, rr = e >> 5, cc = e & 31;
+      R[j] = a.Gin[(size_t)min(I0 + rr, N - 1) * N + s0 + min(cc, bb - 1)];
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int e = 64 * j + lane, rr = e >> 5, cc = e & 31;
+      AB[0][rr][cc] = (I0 + rr < N && cc < bb) ? R[j] : 0.0;
+    }
+  } else if (w == 2) {
+    // right-hand side of Z^T: delta - Gin[s0+k][J0+fr]
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int k = 2 * j + sub;
+      R[j] = a.Gin[(size_t)(s0 + min(k, bb - 1)) * N + min(J0 + fr, N - 1)];
+    }
+  }
+  __syncthreads();   // vis initialised (the loads above may still be in flight)
+  if (w == 0) {
+#pragma unroll
+    for (int y = 0; y < 32; ++y) c[y] = AB[1][x][y];
+    const int q = (x & 1) * 16 + (x >> 1);
+    colc[0][q] = c[0];                     // lanes x and x + 32 store the same value
+    gam[x] = 0.0;
     int nacc = 0, myacc = 0;
-    double mygam = 0.0;
 #pragma unroll
     for (int i = 0; i < 32; ++i) {
       __builtin_amdgcn_sched_barrier(0);   // keeps the per-site scalars from piling up in SGPRs
@@ -142,11 +190,15 @@ __global__ __launch_bounds__(256) void k_block_update(BlockArgs a) {
         const double cii = readlane_d(c[i], i);
         const double dli = readlane_d(dl, i);
         const double r = 1.0 + dli * (1.0 - cii);
-        const double R = readlane_d(pr, i) * (NCOL == 2 ? r * r : r);
-        if (readlane_d(u, i) < R) {            // uniform across the wave
+        const double Rt = readlane_d(pr, i) * (NCOL == 2 ? r * r : r);
+        // columns 0..i and gammas 0..i-1 were stored at the end of the last site
+        __hip_atomic_store(&vis, i + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        double gs = 0.0;
+        if (readlane_d(u, i) < Rt) {           // uniform across the wave
           const double gi = dli / r;
+          gs = gi;
           ++nacc;
-          if (x == i) { myacc = 1; mygam = gi; }
+          if (x == i) myacc = 1;
           // row i broadcast, then the rank-1 update of the rows below i (a
           // zero factor keeps the frozen rows as they are)
           const double f = (x > i) ? gi * c[i] : 0.0;
@@ -160,64 +212,73 @@ __global__ __launch_bounds__(256) void k_block_update(BlockArgs a) {
             for (int t = 0; t < 8; ++t) if (y0 + t < 32) c[y0 + t] = fma(f, ci[t], c[y0 + t]);
           }
         }
+        if (i + 1 < 32) colc[i + 1][q] = c[i + 1];   // column i + 1 is final now
+        gam[i] = gs;                         // gs is the same in every lane
       }
     }
-    if (lane < 32) { accf[lane] = myacc; gam[lane] = mygam; }
+    // gamma of the last site; also ends every wait when the block is empty
+    __hip_atomic_store(&vis, bb + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     if (lane == 0) nacc_s = nacc;
-    // records: upper part of row x scaled by -gamma_x, lower part (column
-    // entries c[x][m], m < x) by -gamma_m
-    const double gx = gam[x];
+    if (blockIdx.x == 0 && lane < bb) a.field_out[s0 + lane] = myacc ? snew : sold;
+  } else if (w == 1) {
+    // X, left-looking: step k needs column k and gamma_m for m < k (vis > k).
+    // P[j] = gamma_m X[fr][m] for the final entries m = 2 j + sub, else 0.
 #pragma unroll
-    for (int y = 0; y < 32; ++y) {
-      if (lane < 32) {
-        Tq[0][x][(y & 3) * 8 + (y >> 2)] = (y > x) ? -gx * c[y] : 0.0;       // row x of c: T_A[x][y], y > x
-        Tq[1][y][(x & 3) * 8 + (x >> 2)] = (y < x) ? -gam[y] * c[y] : 0.0;   // column view: T_B[y][x], y < x
+    for (int j = 0; j < 16; ++j) R[j] = AB[0][fr][2 * j + sub];
+    double P[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) P[j] = 0.0;
+    int seen = 0;
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+      if (k < bb) {
+        while (seen < k + 1) seen = __builtin_amdgcn_readfirstlane(
+            __hip_atomic_load(&vis, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP));
+        if (k > 0 && sub == ((k - 1) & 1)) P[(k - 1) >> 1] = gam[k - 1] * R[(k - 1) >> 1];
+        // sum over m < k of P[m] c[m][k]
+        double s4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int j = 0; 2 * j < k; ++j) s4[j & 3] = fma(P[j], colc[k][sub * 16 + j], s4[j & 3]);
+        double part = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+        part += dpp_all<0xB1>(part);           // both lanes of the row
+        if (sub == (k & 1)) R[k >> 1] += part;
       }
     }
-    if (blockIdx.x == 0 && lane < bb) a.field_out[s0 + lane] = myacc ? snew : sold;
-  } else {
-    // right-hand sides of the two triangular systems below:
-    // AB[0][x][k] = Gin[I0+x][s0+k],  AB[1][y][k] = delta - Gin[s0+k][J0+y]
-    for (int e = tid - 64; e < 1024; e += 192) {
-      const int x = e >> 5, y = e & 31;
-      AB[0][x][y] = (I0 + x < N && y < bb) ? a.Gin[(size_t)(I0 + x) * N + s0 + y] : 0.0;
-      const double gsj = (x < bb && J0 + y < N) ? a.Gin[(size_t)(s0 + x) * N + J0 + y] : 0.0;
-      AB[1][y][x] = ((s0 + x == J0 + y) ? 1.0 : 0.0) - gsj;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) AB[0][fr][2 * j + sub] = R[j];
+  } else if (w == 2) {
+    // Z^T, right-looking: step m needs column m and gamma_m (vis > m + 1); the
+    // last step would only touch entries past the block, which stay as they are
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int k = 2 * j + sub;
+      R[j] = ((s0 + k == J0 + fr) ? 1.0 : 0.0) - ((k < bb && J0 + fr < N) ? R[j] : 0.0);
     }
-  }
-  __syncthreads();
-  {
-    // X = GIS A (rows of X) and Z^T = (E_S^T[:,J] - G[S,J])^T B (rows of Z^T):
-    // the triangular recurrences R[k] = rhs[k] - sum_{m<k} R[m] T[m][k] with
-    // T = T_A or T_B, right-looking.  Four lanes (a quad) share one row, lane
-    // sub holding R[k] for k = sub mod 4; once R[m] is final its lane hands it
-    // to the quad by a DPP broadcast and each lane takes it out of its later
-    // entries.  Waves 0, 1 take the 32 rows of X, waves 2, 3 those of Z^T; the
-    // next record row is fetched while the current one is applied.
-    const int h = w >> 1, row = (tid >> 2) & 31, sub = tid & 3;
-    double rk[8], cur[8], nxt[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) rk[j] = AB[h][row][4 * j + sub];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) cur[j] = Tq[h][0][sub * 8 + j];
+    int seen = 0;
 #pragma unroll
     for (int m = 0; m < 31; ++m) {
-      const int jm = m >> 2;
-      if (m + 1 < 31) {
+      if (m + 1 < bb) {
+        const int jm = m >> 1;
+        while (seen < m + 1) seen = __builtin_amdgcn_readfirstlane(
+            __hip_atomic_load(&vis, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP));
+        double cur[16];
 #pragma unroll
-        for (int j = (m + 1) >> 2; j < 8; ++j) nxt[j] = Tq[h][m + 1][sub * 8 + j];
+        for (int j = jm; j < 16; ++j) cur[j] = colc[m][sub * 16 + j];
+        // Z^T[fr][m] from its owner lane (DPP quad permutes [0,0,2,2] / [1,1,3,3])
+        const double val = (m & 1) ? dpp_all<0xF5>(R[jm]) : dpp_all<0xA0>(R[jm]);
+        while (seen < m + 2) seen = __builtin_amdgcn_readfirstlane(
+            __hip_atomic_load(&vis, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP));
+        const double t = gam[m] * val;
+        R[jm] = fma(sub > (m & 1) ? t : 0.0, cur[jm], R[jm]);
+#pragma unroll
+        for (int j = jm + 1; j < 16; ++j) R[j] = fma(t, cur[j], R[j]);
       }
-      __builtin_amdgcn_sched_barrier(0);
-      const double val = quad_bcast_d(rk[jm], m);   // R[m]
-      rk[jm] = fma(sub > (m & 3) ? -val : 0.0, cur[jm], rk[jm]);
-#pragma unroll
-      for (int j = jm + 1; j < 8; ++j) rk[j] = fma(-val, cur[j], rk[j]);
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int j = (m + 1) >> 2; j < 8; ++j) cur[j] = nxt[j];
     }
+    // AB[1] held G[S,S] for wave 0 until its first release
+    while (seen < 1) seen = __builtin_amdgcn_readfirstlane(
+        __hip_atomic_load(&vis, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP));
 #pragma unroll
-    for (int j = 0; j < 8; ++j) AB[h][row][4 * j + sub] = rk[j];
+    for (int j = 0; j < 16; ++j) AB[1][fr][2 * j + sub] = R[j];
   }
   __syncthreads();
   // Gout tile = Gin - X diag(gamma) Z  (32 x 32 x 32 on MFMA)
