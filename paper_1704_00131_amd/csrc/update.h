@@ -247,8 +247,9 @@ __global__ __launch_bounds__(256) void k_block_update(BlockArgs a) {
 #pragma unroll
     for (int j = 0; j < 16; ++j) AB[0][fr][2 * j + sub] = R[j];
   } else if (w == 2) {
-    // Z^T, right-looking: step m needs column m and gamma_m (vis > m + 1); the
-    // last step would only touch entries past the block, which stay as they are
+    // Z^T, right-looking: step m needs column m and gamma_m (vis > m + 1),
+    // fetched together; the last step would only touch entries past the
+    // block, which stay as they are
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       const int k = 2 * j + sub;
@@ -259,16 +260,15 @@ __global__ __launch_bounds__(256) void k_block_update(BlockArgs a) {
     for (int m = 0; m < 31; ++m) {
       if (m + 1 < bb) {
         const int jm = m >> 1;
-        while (seen < m + 1) seen = __builtin_amdgcn_readfirstlane(
+        while (seen < m + 2) seen = __builtin_amdgcn_readfirstlane(
             __hip_atomic_load(&vis, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP));
+        const double g = gam[m];
         double cur[16];
 #pragma unroll
         for (int j = jm; j < 16; ++j) cur[j] = colc[m][sub * 16 + j];
         // Z^T[fr][m] from its owner lane (DPP quad permutes [0,0,2,2] / [1,1,3,3])
         const double val = (m & 1) ? dpp_all<0xF5>(R[jm]) : dpp_all<0xA0>(R[jm]);
-        while (seen < m + 2) seen = __builtin_amdgcn_readfirstlane(
-            __hip_atomic_load(&vis, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP));
-        const double t = gam[m] * val;
+        const double t = g * val;
         R[jm] = fma(sub > (m & 1) ? t : 0.0, cur[jm], R[jm]);
 #pragma unroll
         for (int j = jm + 1; j < 16; ++j) R[j] = fma(t, cur[j], R[j]);
