@@ -346,25 +346,24 @@ dqmc_status launch_qr_panel(dqmc_ctx* c, double* Ap, int j0, int nbw, double* V,
   return DQMC_OK;
 }
 
-template <int NBW, int MAXR>
+template <int NBW, int MR>
 void lu_panel(dqmc_ctx* c, double* XA, int ld, int j0, int nbw) {
-  hipLaunchKernelGGL((k_lu_panel<NBW, MAXR>), gridc(c, 1), dim3(256), sizeof(double) * 2 * 64 * MAXR, c->stream, XA,
-                     c->N, ld, j0, nbw, c->Mgj, 32, c->moves, c->err_flag, c->cs);
+  hipLaunchKernelGGL((k_lu_panel<NBW, MR>), gridc(c, 1), dim3(256), 0, c->stream, XA, c->N, ld, j0, nbw, c->Mgj,
+                     32, c->moves, c->err_flag, c->cs);
 }
 
-// Panel step of the blocked LU solve: rows per lane = ceil(h / 64),
-// rounded up to the instantiated counts.
+// Panel step of the blocked LU solve: rows per thread = ceil(h / 256).
 dqmc_status launch_lu_panel(dqmc_ctx* c, double* XA, int ld, int j0, int nbw) {
-  const int rows = (c->N - j0 + 63) / 64;
-  if (c->nb == 32 && rows <= 2) lu_panel<32, 2>(c, XA, ld, j0, nbw);
-  else if (c->nb == 32 && rows <= 4) lu_panel<32, 4>(c, XA, ld, j0, nbw);
-  else if (c->nb == 32 && rows <= 6) lu_panel<32, 6>(c, XA, ld, j0, nbw);
-  else if (c->nb == 16 && rows <= 4) lu_panel<16, 4>(c, XA, ld, j0, nbw);
-  else if (c->nb == 16 && rows <= 8) lu_panel<16, 8>(c, XA, ld, j0, nbw);
-  else if (c->nb == 16 && rows <= 12) lu_panel<16, 12>(c, XA, ld, j0, nbw);
+  const int rows = (c->N - j0 + 255) / 256;
+  if (c->nb == 32 && rows <= 1) lu_panel<32, 1>(c, XA, ld, j0, nbw);
+  else if (c->nb == 32 && rows <= 2) lu_panel<32, 2>(c, XA, ld, j0, nbw);
+  else if (c->nb == 16 && rows <= 1) lu_panel<16, 1>(c, XA, ld, j0, nbw);
+  else if (c->nb == 16 && rows <= 2) lu_panel<16, 2>(c, XA, ld, j0, nbw);
+  else if (c->nb == 16 && rows <= 3) lu_panel<16, 3>(c, XA, ld, j0, nbw);
+  else if (c->nb == 8 && rows <= 1) lu_panel<8, 1>(c, XA, ld, j0, nbw);
+  else if (c->nb == 8 && rows <= 2) lu_panel<8, 2>(c, XA, ld, j0, nbw);
+  else if (c->nb == 8 && rows <= 3) lu_panel<8, 3>(c, XA, ld, j0, nbw);
   else if (c->nb == 8 && rows <= 4) lu_panel<8, 4>(c, XA, ld, j0, nbw);
-  else if (c->nb == 8 && rows <= 8) lu_panel<8, 8>(c, XA, ld, j0, nbw);
-  else if (c->nb == 8 && rows <= 16) lu_panel<8, 16>(c, XA, ld, j0, nbw);
   else return fail(c, DQMC_E_UNSUPPORTED, "no LU panel kernel for this size");
   HIPCHK(hipGetLastError());
   return DQMC_OK;

@@ -13,6 +13,7 @@
 // H_1 ... H_nb = I - V T V^T, so that Q^T A = A - V (VT^T A) and
 // Q X = X - VT (V^T X).
 #pragma once
+#include <utility>
 #include "device_common.h"
 
 // ------------------------------------------------------------ utilities ----
@@ -494,160 +495,150 @@ __device__ __forceinline__ void tri_solve_back(double (&z)[32], const double (*t
   }
 }
 
-// Panel factorisation.  Layout: wave w owns the columns w*NBW/4 .. (w+1)*NBW/4
-// - 1 and lane l the rows l, l + 64, ... (MAXR of them), in registers; every
-// wave holds the same rows in the same lanes.  Pivoting is virtual: each held
-// row carries its current position, a pivot step swaps two positions (every
-// wave keeps the same copy), and the rows are written to their final places.
-// The column loop runs over the owning wave and, unrolled, over its columns,
-// so the owner addresses its column without selects.  Per column c the owner
-// finds the pivot (wave max, then the lowest position holding it, both left in
-// every lane), forms the multipliers of its rows and publishes them with the
-// pivot's lane and register through LDS (two alternating buffers); after one
-// barrier every wave reads the pivot row from its own registers (a uniform
-// register index) by readlane and eliminates its columns, with a zero
-// multiplier for columns at or left of c, so no branches.  The move list
-// (moves[0] = count K <= 2 nbw, then K pairs (destination, source), absolute
-// rows) is written for k_lu_rowblock.
-template <int NBW, int MAXR>
+// Panel factorisation (partial pivoting) of columns j0..j0+nbw-1, rows
+// j0..n-1 of XA.  Layout: thread t holds the rows 256 i + t (i < MR) of the
+// panel, all nbw columns, in registers, so column c of the unrolled column
+// loop is a compile-time register index.  Pivoting is virtual: each held row
+// carries its current position, a pivot step swaps two positions (every
+// thread applies the same swap), and the rows are written to their final
+// places at the end.  Per column c:
+//   - each thread forms a key for its candidate rows (position >= c): the bits
+//     of |a| (non-negative, so ordered like the value) with the low 11
+//     mantissa bits replaced by 2047 - position, so one maximum gives the
+//     largest value and, among values equal in the upper bits, the lowest
+//     position (a NaN entry never wins, as in a comparison-based search);
+//   - a wave maximum of the keys; the winning lane stores its key and its row
+//     (columns >= c) in LDS, one slot per wave, two alternating buffers;
+//   - one barrier; every thread reads the four keys, takes the largest, reads
+//     that wave's row as the pivot row, swaps the positions, and eliminates
+//     the rows that end below the pivot.
+// The move list (moves[0] = count K <= 2 nbw, then K pairs (destination,
+// source), absolute rows, in any order) is written for k_lu_rowblock.
+template <int NBW, int MR>
+struct LuShared {
+  double key[2][4];
+  int reg[2][4];
+  __attribute__((aligned(16))) double row[2][4][MR][NBW];
+};
+
+// Column C of the panel (a template parameter, so every register index is a
+// compile-time constant whatever the unroller decides).
+template <int NBW, int MR, int C>
+__device__ __forceinline__ void lu_column(double (&a)[MR][NBW], int (&pos)[MR], int h, int ncol, LuShared<NBW, MR>& sh,
+                                          int* err) {
+  if (C >= ncol) return;   // uniform
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  constexpr int buf = C & 1;
+  // candidate key of this thread (0 when it holds no row at or below C)
+  double best = 0.0;
+  int bi = 0;
+#pragma unroll
+  for (int i = 0; i < MR; ++i) {
+    const bool cand = pos[i] >= C && pos[i] < h;
+    const unsigned long long bits =
+        ((unsigned long long)__double_as_longlong(fabs(a[i][C])) & ~0x7ffull) | (unsigned long long)(0x7ff - pos[i]);
+    const double key = cand ? __longlong_as_double((long long)bits) : 0.0;
+    if (key > best) { best = key; bi = i; }
+  }
+  const double wmax = wave_max_all(best);
+  const unsigned long long win = __ballot(best == wmax);
+  const int wl = __ffsll((long long)win) - 1;
+  if (lane == wl) {
+    // all rows of the winning lane (no register selection), and which one won
+    sh.key[buf][w] = wmax;
+    sh.reg[buf][w] = bi;
+#pragma unroll
+    for (int i = 0; i < MR; ++i)
+#pragma unroll
+      for (int q = C; q < NBW; ++q) sh.row[buf][w][i][q] = a[i][q];
+  }
+  __syncthreads();
+  const double k0 = sh.key[buf][0], k1 = sh.key[buf][1], k2 = sh.key[buf][2], k3 = sh.key[buf][3];
+  const int w01 = (k1 > k0) ? 1 : 0, w23 = (k3 > k2) ? 3 : 2;
+  const double m01 = fmax(k0, k1), m23 = fmax(k2, k3);
+  const int ww = __builtin_amdgcn_readfirstlane((m23 > m01) ? w23 : w01);
+  const int wr = __builtin_amdgcn_readfirstlane(sh.reg[buf][ww]);
+  const double gk = fmax(m01, m23);
+  int pp = 0x7ff - (int)((unsigned long long)__double_as_longlong(gk) & 0x7ffull);
+  // no finite candidate (a NaN column): keep the row and flag the failure
+  if (!(gk > 0.0) || pp < C || pp >= h) {
+    pp = C;
+    if (tid == 0) atomicOr(err, 4);
+  }
+  double u[NBW];
+#pragma unroll
+  for (int q = C; q < NBW; ++q) u[q] = sh.row[buf][ww][wr][q];
+  if (tid == 0 && !(fabs(u[C]) > 0.0)) atomicOr(err, 4);
+  const double inv = 1.0 / u[C];
+#pragma unroll
+  for (int i = 0; i < MR; ++i) {
+    pos[i] = (pos[i] == pp) ? C : (pos[i] == C ? pp : pos[i]);
+    const bool below = pos[i] > C && pos[i] < h;
+    const double l = below ? a[i][C] * inv : 0.0;
+    a[i][C] = below ? l : a[i][C];
+#pragma unroll
+    for (int q = C + 1; q < NBW; ++q) a[i][q] = fma(-l, u[q], a[i][q]);
+  }
+}
+
+template <int NBW, int MR, int... C>
+__device__ __forceinline__ void lu_columns(std::integer_sequence<int, C...>, double (&a)[MR][NBW], int (&pos)[MR],
+                                           int h, int ncol, LuShared<NBW, MR>& sh, int* err) {
+  (lu_column<NBW, MR, C>(a, pos, h, ncol, sh, err), ...);
+}
+
+template <int NBW, int MR>
 __global__ __launch_bounds__(256) void k_lu_panel(double* XA, int n, int ld, int j0, int nbw, double* M, int ldm,
                                                   int* moves, int* err, size_t cs) {
-  extern __shared__ double smem[];   // 2 x 64 MAXR multipliers
-  constexpr int CPW = NBW / 4, HR = 64 * MAXR;
-  __shared__ int piv_s[2][3];        // pivot position, lane, register
+  __shared__ LuShared<NBW, MR> sh;
+  __shared__ int cnt_s;
   {
     const size_t co = (size_t)blockIdx.y * cs;
     XA += co; M += co;
     moves = reinterpret_cast<int*>(reinterpret_cast<double*>(moves) + co);
     err = reinterpret_cast<int*>(reinterpret_cast<double*>(err) + co);
   }
-  const int h = n - j0, tid = threadIdx.x, lane = tid & 63;
-  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  double a[MAXR][CPW];
-  int pos[MAXR];
+  const int h = n - j0, tid = threadIdx.x;
+  double a[MR][NBW];
+  int pos[MR];
   // unconditional loads from clamped addresses (all in flight together), then
   // zeros outside the panel
 #pragma unroll
-  for (int i = 0; i < MAXR; ++i) {
-    const int r = lane + 64 * i, rc = min(r, h - 1);
+  for (int i = 0; i < MR; ++i) {
+    const int r = 256 * i + tid, rc = min(r, h - 1);
     pos[i] = (r < h) ? r : 0x7fffffff;
 #pragma unroll
-    for (int j = 0; j < CPW; ++j) a[i][j] = XA[(size_t)(j0 + rc) * ld + j0 + min(w * CPW + j, nbw - 1)];
+    for (int q = 0; q < NBW; ++q) a[i][q] = XA[(size_t)(j0 + rc) * ld + j0 + min(q, nbw - 1)];
   }
 #pragma unroll
-  for (int i = 0; i < MAXR; ++i)
+  for (int i = 0; i < MR; ++i)
 #pragma unroll
-    for (int j = 0; j < CPW; ++j) a[i][j] = (lane + 64 * i < h && w * CPW + j < nbw) ? a[i][j] : 0.0;
-  const int ncol = min(nbw, h);
-  for (int cw = 0; cw < 4; ++cw) {
-#pragma unroll
-    for (int cj = 0; cj < CPW; ++cj) {
-      const int c = cw * CPW + cj;
-      if (c >= ncol) break;
-      double* lb = smem + (c & 1) * HR;
-      int* ps = piv_s[c & 1];
-      // the owner keeps its multipliers and pivot in registers; the other
-      // waves read them from LDS after the barrier
-      double lr[MAXR];
-      int pp, hl, hs;
-      if (w == cw) {
-        double best = -1.0;
-        int bi = 0x7fffffff;
-#pragma unroll
-        for (int i = 0; i < MAXR; ++i) {
-          if (pos[i] >= c && pos[i] < h) {
-            const double av = fabs(a[i][cj]);
-            if (av > best || (av == best && pos[i] < bi)) { best = av; bi = pos[i]; }
-          }
-        }
-        const double wm = wave_max_all(best);
-        pp = wave_min_all_i((best == wm && best >= 0.0) ? bi : 0x7fffffff);
-        pp = __builtin_amdgcn_readfirstlane(pp);
-        // no finite candidate (a NaN column): keep the row and flag the failure
-        if (!(wm >= 0.0) || pp < c || pp >= h) pp = c;
-        // the lane and register holding position pp, and the pivot value
-        int hit = -1;
-        double pv = 0.0;
-#pragma unroll
-        for (int i = 0; i < MAXR; ++i)
-          if (pos[i] == pp) { hit = i; pv = a[i][cj]; }
-        const unsigned long long mask = __ballot(hit >= 0);
-        hl = __ffsll((long long)mask) - 1;
-        hs = __builtin_amdgcn_readlane(hit, hl);
-        const double inv = 1.0 / readlane_d(pv, hl);
-        // multipliers of the rows that stay below the pivot (position > c after the swap)
-#pragma unroll
-        for (int i = 0; i < MAXR; ++i) {
-          const int np = (pos[i] == pp) ? c : (pos[i] == c ? pp : pos[i]);
-          const bool below = np > c && np < h;
-          const double l = below ? a[i][cj] * inv : 0.0;
-          lb[lane + 64 * i] = l;
-          lr[i] = l;
-          a[i][cj] = below ? l : a[i][cj];
-        }
-        if (lane == 0) {
-          ps[0] = pp; ps[1] = hl; ps[2] = hs;
-          if (!(wm > 0.0)) atomicOr(err, 4);
-        }
-      }
-      __syncthreads();
-      if (w != cw) {
-        pp = __builtin_amdgcn_readfirstlane(ps[0]);
-        hl = __builtin_amdgcn_readfirstlane(ps[1]);
-        hs = __builtin_amdgcn_readfirstlane(ps[2]);
-#pragma unroll
-        for (int i = 0; i < MAXR; ++i) lr[i] = lb[lane + 64 * i];   // 0 for rows not below the pivot
-      }
-#pragma unroll
-      for (int i = 0; i < MAXR; ++i) pos[i] = (pos[i] == pp) ? c : (pos[i] == c ? pp : pos[i]);
-#pragma unroll
-      for (int j = 0; j < CPW; ++j) {
-        const int q = w * CPW + j;
-        double pr = 0.0;
-#pragma unroll
-        for (int i = 0; i < MAXR; ++i) pr = (i == hs) ? a[i][j] : pr;   // uniform index
-        const double u = (q > c && q < nbw) ? readlane_d(pr, hl) : 0.0;
-#pragma unroll
-        for (int i = 0; i < MAXR; ++i) a[i][j] = fma(-lr[i], u, a[i][j]);
-      }
-    }
-  }
+    for (int q = 0; q < NBW; ++q) a[i][q] = (256 * i + tid < h && q < nbw) ? a[i][q] : 0.0;
+  if (tid == 0) cnt_s = 0;
+  lu_columns<NBW, MR>(std::make_integer_sequence<int, NBW>{}, a, pos, h, min(nbw, h), sh, err);
   // diagonal block (L11 below, U11 on and above the diagonal) into XA,
-  // multipliers of the rows below into M
+  // multipliers of the rows below into M, and the moved rows into the list
 #pragma unroll
-  for (int i = 0; i < MAXR; ++i) {
+  for (int i = 0; i < MR; ++i) {
+    const int r = 256 * i + tid;
     if (pos[i] < h) {
 #pragma unroll
-      for (int j = 0; j < CPW; ++j) {
-        const int q = w * CPW + j;
+      for (int q = 0; q < NBW; ++q) {
         if (q < nbw) {
-          if (pos[i] < nbw) {
-            XA[(size_t)(j0 + pos[i]) * ld + j0 + q] = a[i][j];
-          } else {
-            M[(size_t)(j0 + pos[i]) * ldm + q] = a[i][j];
-          }
+          if (pos[i] < nbw) XA[(size_t)(j0 + pos[i]) * ld + j0 + q] = a[i][q];
+          else M[(size_t)(j0 + pos[i]) * ldm + q] = a[i][q];
         }
       }
-    }
-  }
-  // the composed interchanges: original row r now sits at position pos(r);
-  // every wave holds the same positions, wave 0 lists the rows that moved
-  if (w == 0) {
-    int cnt = 0;
-#pragma unroll
-    for (int i = 0; i < MAXR; ++i) {
-      const int r = lane + 64 * i;
-      const bool moved = pos[i] < h && pos[i] != r;
-      const unsigned long long m = __ballot(moved);
-      const int at = cnt + __popcll(m & ((1ull << lane) - 1ull));
-      if (moved) {
+      if (pos[i] != r) {
+        const int at = atomicAdd(&cnt_s, 1);
         moves[1 + 2 * at] = j0 + pos[i];
         moves[2 + 2 * at] = j0 + r;
       }
-      cnt += __popcll(m);
     }
-    if (lane == 0) moves[0] = cnt;
   }
+  __syncthreads();
+  if (tid == 0) moves[0] = cnt_s;
 }
 
 // Interchanges and U12 for the columns j0+nbw .. ncols-1 of XA, one thread per
