@@ -348,7 +348,8 @@ dqmc_status launch_qr_panel(dqmc_ctx* c, double* Ap, int j0, int nbw, double* V,
 
 template <int NBW, int MR>
 void lu_panel(dqmc_ctx* c, double* XA, int ld, int j0, int nbw) {
-  hipLaunchKernelGGL((k_lu_panel<NBW, MR>), gridc(c, 1), dim3(256), 0, c->stream, XA, c->N, ld, j0, nbw, c->Mgj,
+  const size_t lds = sizeof(double) * (size_t)(c->N - j0) * (NBW + 1);   // the staged panel
+  hipLaunchKernelGGL((k_lu_panel<NBW, MR>), gridc(c, 1), dim3(256), lds, c->stream, XA, c->N, ld, j0, nbw, c->Mgj,
                      32, c->moves, c->err_flag, c->cs);
 }
 
@@ -381,7 +382,24 @@ hipError_t lds_limit_qr() {
   return hipSuccess;
 }
 
+template <int NBW, int MR>
+hipError_t lds_limit_lu() {
+  // the staged panel: at most 384 x 33, 768 x 17 or 1024 x 9 doubles (about
+  // 104 KB), beside a few KB of static LDS
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(k_lu_panel<NBW, MR>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, 120 * 1024);
+}
+
 dqmc_status set_lds_limits(dqmc_ctx* c) {
+  HIPCHK((lds_limit_lu<32, 1>()));
+  HIPCHK((lds_limit_lu<32, 2>()));
+  HIPCHK((lds_limit_lu<16, 1>()));
+  HIPCHK((lds_limit_lu<16, 2>()));
+  HIPCHK((lds_limit_lu<16, 3>()));
+  HIPCHK((lds_limit_lu<8, 1>()));
+  HIPCHK((lds_limit_lu<8, 2>()));
+  HIPCHK((lds_limit_lu<8, 3>()));
+  HIPCHK((lds_limit_lu<8, 4>()));
   HIPCHK((lds_limit_qr<32, 2, 4, 6>()));
   HIPCHK((lds_limit_qr<16, 4, 8, 12>()));
   HIPCHK((lds_limit_qr<8, 4, 8, 16>()));

@@ -593,6 +593,7 @@ __global__ __launch_bounds__(256) void k_lu_panel(double* XA, int n, int ld, int
                                                   int* moves, int* err, size_t cs) {
   __shared__ LuShared<NBW, MR> sh;
   __shared__ int cnt_s;
+  extern __shared__ double stage[];   // h rows of NBW + 1: the panel in, then the factors out
   {
     const size_t co = (size_t)blockIdx.y * cs;
     XA += co; M += co;
@@ -600,41 +601,59 @@ __global__ __launch_bounds__(256) void k_lu_panel(double* XA, int n, int ld, int
     err = reinterpret_cast<int*>(reinterpret_cast<double*>(err) + co);
   }
   const int h = n - j0, tid = threadIdx.x;
+  constexpr int PS = NBW + 1, NL = MR * NBW;   // stage row stride; loads per thread
+  // the panel through LDS: coalesced loads (consecutive threads along a row),
+  // all issued before the stores, zeros outside the panel
+  {
+    double t[NL];
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+      const int e = 256 * u + tid, r = e / NBW, q = e % NBW;
+      t[u] = XA[(size_t)(j0 + min(r, h - 1)) * ld + j0 + min(q, nbw - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+      const int e = 256 * u + tid, r = e / NBW, q = e % NBW;
+      if (r < h) stage[r * PS + q] = (q < nbw) ? t[u] : 0.0;
+    }
+  }
+  __syncthreads();
   double a[MR][NBW];
   int pos[MR];
-  // unconditional loads from clamped addresses (all in flight together), then
-  // zeros outside the panel
 #pragma unroll
   for (int i = 0; i < MR; ++i) {
-    const int r = 256 * i + tid, rc = min(r, h - 1);
+    const int r = 256 * i + tid;
     pos[i] = (r < h) ? r : 0x7fffffff;
 #pragma unroll
-    for (int q = 0; q < NBW; ++q) a[i][q] = XA[(size_t)(j0 + rc) * ld + j0 + min(q, nbw - 1)];
+    for (int q = 0; q < NBW; ++q) a[i][q] = (r < h) ? stage[r * PS + q] : 0.0;
   }
-#pragma unroll
-  for (int i = 0; i < MR; ++i)
-#pragma unroll
-    for (int q = 0; q < NBW; ++q) a[i][q] = (256 * i + tid < h && q < nbw) ? a[i][q] : 0.0;
   if (tid == 0) cnt_s = 0;
   lu_columns<NBW, MR>(std::make_integer_sequence<int, NBW>{}, a, pos, h, min(nbw, h), sh, err);
-  // diagonal block (L11 below, U11 on and above the diagonal) into XA,
-  // multipliers of the rows below into M, and the moved rows into the list
+  // every row to its final place in the stage (the stage rows were last read
+  // before the first column's barrier), and the moved rows into the list
 #pragma unroll
   for (int i = 0; i < MR; ++i) {
     const int r = 256 * i + tid;
     if (pos[i] < h) {
 #pragma unroll
-      for (int q = 0; q < NBW; ++q) {
-        if (q < nbw) {
-          if (pos[i] < nbw) XA[(size_t)(j0 + pos[i]) * ld + j0 + q] = a[i][q];
-          else M[(size_t)(j0 + pos[i]) * ldm + q] = a[i][q];
-        }
-      }
+      for (int q = 0; q < NBW; ++q) stage[pos[i] * PS + q] = a[i][q];
       if (pos[i] != r) {
         const int at = atomicAdd(&cnt_s, 1);
         moves[1 + 2 * at] = j0 + pos[i];
         moves[2 + 2 * at] = j0 + r;
       }
+    }
+  }
+  __syncthreads();
+  // diagonal block (L11 below, U11 on and above the diagonal) into XA,
+  // multipliers of the rows below into M, coalesced
+#pragma unroll
+  for (int u = 0; u < NL; ++u) {
+    const int e = 256 * u + tid, r = e / NBW, q = e % NBW;
+    if (r < h && q < nbw) {
+      const double v = stage[r * PS + q];
+      if (r < nbw) XA[(size_t)(j0 + r) * ld + j0 + q] = v;
+      else M[(size_t)(j0 + r) * ldm + q] = v;
     }
   }
   __syncthreads();
