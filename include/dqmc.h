@@ -198,11 +198,15 @@ dqmc_status dqmc_td_measure(dqmc_ctx* ctx, double* S_host, double* prec);
 dqmc_status dqmc_td_read_bins(dqmc_ctx* ctx, double* sums_host, double* count);
 
 /* Per-launch timing of one kernel of the sweep, for roofline reports: while
- * enabled, every launch of the selected kernel on the context's stream is
- * bracketed by two HIP events.  dqmc_timing_read synchronises the stream,
- * returns the summed event time (ms) and the launch count since the last read,
- * and clears them.  kernel: DQMC_KERNEL_BLOCK_UPDATE (the fused block update)
- * or DQMC_KERNEL_GEMM (the MFMA product). */
+ * enabled, launches of the selected kernel on the context's stream are
+ * bracketed by two HIP events: every launch for enable = 1, every enable-th
+ * launch for enable > 1 (a sample that keeps the event markers from slowing
+ * the timed work; a period coprime with the launches per slice visits every
+ * launch position).  0 disables; negative values are DQMC_E_ARG.
+ * dqmc_timing_read synchronises the stream, returns the summed event time (ms)
+ * and the number of bracketed launches since the last read (and, for the GEMM,
+ * their FLOPs), and clears them.  kernel: DQMC_KERNEL_BLOCK_UPDATE (the fused
+ * block update) or DQMC_KERNEL_GEMM (the MFMA product). */
 typedef enum { DQMC_KERNEL_BLOCK_UPDATE = 0, DQMC_KERNEL_GEMM = 1 } dqmc_kernel;
 dqmc_status dqmc_timing_enable(dqmc_ctx* ctx, dqmc_kernel kernel, int32_t enable);
 dqmc_status dqmc_timing_read(dqmc_ctx* ctx, double* total_ms, uint64_t* launches, double* flops);

@@ -148,9 +148,11 @@ class Chain:
         self._chk(self.lib.dqmc_td_read_bins(self.ctx, raw.ctypes.data, ctypes.byref(cnt)))
         return raw[..., 0] + 1j * raw[..., 1], cnt.value
 
-    def timing(self, kernel: str = "block_update", enable: bool = True):
+    def timing(self, kernel: str = "block_update", enable: bool = True, every: int = 1):
+        """Bracket launches of one kernel with HIP events: every launch, or every
+        `every`-th one (a rotating sample) when every > 1."""
         k = _lib.KERNEL_BLOCK_UPDATE if kernel == "block_update" else _lib.KERNEL_GEMM
-        self._chk(self.lib.dqmc_timing_enable(self.ctx, k, 1 if enable else 0))
+        self._chk(self.lib.dqmc_timing_enable(self.ctx, k, max(1, int(every)) if enable else 0))
 
     def timing_read(self):
         ms = ctypes.c_double()

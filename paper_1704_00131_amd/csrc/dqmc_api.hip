@@ -85,9 +85,10 @@ struct dqmc_ctx {
   int gemm_tile = 0;
   std::vector<uint64_t> seeds;
   double* gbuf = nullptr;
-  // optional per-launch event timing of one kernel
-  bool timing = false;
-  int timing_kernel = 0;
+  // optional per-launch event timing of one kernel (every timing_every-th launch)
+  bool timing = false, timing_open = false;
+  int timing_kernel = 0, timing_every = 1;
+  uint64_t timing_seen = 0;
   std::vector<hipEvent_t> ev;
   size_t ev_used = 0;
   double timed_flops = 0.0;
@@ -194,6 +195,8 @@ inline bool is_shared(const dqmc_ctx* c, const void* p) {
 // ---------------------------------------------------------- device steps --
 dqmc_status timing_begin(dqmc_ctx* c, int kernel) {
   if (!c->timing || c->timing_kernel != kernel) return DQMC_OK;
+  c->timing_open = (c->timing_seen++ % (uint64_t)c->timing_every) == 0;
+  if (!c->timing_open) return DQMC_OK;
   while (c->ev.size() < c->ev_used + 2) {
     // Timing-only events: no system-scope fence (cache writeback) at record,
     // which would otherwise be counted in every bracketed launch.
@@ -206,7 +209,8 @@ dqmc_status timing_begin(dqmc_ctx* c, int kernel) {
 }
 
 dqmc_status timing_end(dqmc_ctx* c, int kernel) {
-  if (!c->timing || c->timing_kernel != kernel) return DQMC_OK;
+  if (!c->timing || c->timing_kernel != kernel || !c->timing_open) return DQMC_OK;
+  c->timing_open = false;
   HIPCHK(hipEventRecord(c->ev[c->ev_used + 1], c->stream));
   c->ev_used += 2;
   return DQMC_OK;
@@ -227,7 +231,7 @@ dqmc_status gemm(dqmc_ctx* c, GemmArgs g) {
   }
   if (dqmc_status s = timing_begin(c, DQMC_KERNEL_GEMM)) return s;
   HIPCHK(launch_gemm(g, c->stream));
-  if (c->timing && c->timing_kernel == DQMC_KERNEL_GEMM) c->timed_flops += 2.0 * g.M * (double)g.N * g.K * c->nch;
+  if (c->timing_open && c->timing_kernel == DQMC_KERNEL_GEMM) c->timed_flops += 2.0 * g.M * (double)g.N * g.K * c->nch;
   return timing_end(c, DQMC_KERNEL_GEMM);
 }
 
@@ -1247,9 +1251,12 @@ dqmc_status dqmc_td_read_bins(dqmc_ctx* c, double* sums_host, double* count) {
 }
 
 dqmc_status dqmc_timing_enable(dqmc_ctx* c, dqmc_kernel kernel, int32_t enable) {
-  if (!c || (kernel != DQMC_KERNEL_BLOCK_UPDATE && kernel != DQMC_KERNEL_GEMM)) return DQMC_E_ARG;
+  if (!c || enable < 0 || (kernel != DQMC_KERNEL_BLOCK_UPDATE && kernel != DQMC_KERNEL_GEMM)) return DQMC_E_ARG;
   c->timing = enable != 0;
+  c->timing_open = false;
   c->timing_kernel = kernel;
+  c->timing_every = enable > 1 ? enable : 1;
+  c->timing_seen = 0;
   c->ev_used = 0;
   c->timed_flops = 0.0;
   return DQMC_OK;
