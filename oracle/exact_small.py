@@ -15,7 +15,11 @@ from .timedisplaced import tdgf_measure
 
 
 def all_fields(model):
-    for bits in itertools.product((1.0, -1.0), repeat=model.L * model.N):
+    """Every configuration: +-1 per vertex, or the four values eta(l) of
+    Eq. (HS_squares) for the four-valued field."""
+    from .hubbard import ETA4
+    values = ETA4 if model.field_kind == "ising4" else (1.0, -1.0)
+    for bits in itertools.product(values, repeat=model.L * model.N):
         yield np.array(bits).reshape(model.L, model.N)
 
 

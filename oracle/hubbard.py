@@ -14,6 +14,12 @@ the section "Formulation of the method" by the exact two-valued one, since
 
     exp(dtau U/2 (n-1)^2) = 1/2 sum_{s=+-1} exp(lambda s (n-1)),  cosh(lambda) = exp(dtau U/2)
 
+Four-valued field (the paper's approximate identity for perfect squares,
+Eq. (HS_squares), with lambda = U/2 and A = n - 1):
+    exp(dtau U/2 A^2) ~ 1/4 sum_{l=+-1,+-2} gamma(l) exp(c4 eta(l) A),  c4 = sqrt(dtau U / 2),
+the field storing eta(l) (the paper's type = 2 vertex sets phi = eta) and the
+weight carrying gamma(l) per vertex; the 1/4 is a constant and drops out.
+
 Continuous field (outside the paper, which lists continuous HS fields as not
 supported): exp(dtau U/2 A^2) = int dphi (2pi)^-1/2 exp(-phi^2/2) exp(c phi A)
 with c = sqrt(dtau U).
@@ -34,6 +40,24 @@ def gauss_coupling(U: float, dtau: float) -> float:
     return float(np.sqrt(dtau * U))
 
 
+def ising4_coupling(U: float, dtau: float) -> float:
+    """sqrt(dtau lambda) of Eq. (HS_squares) with lambda = U / 2."""
+    return float(np.sqrt(dtau * U / 2.0))
+
+
+# values of the four-valued field, in the order l = -2, -1, +1, +2 (Eq. (HS_squares))
+_S6 = float(np.sqrt(6.0))
+ETA4 = (-float(np.sqrt(2.0 * (3.0 + _S6))), -float(np.sqrt(2.0 * (3.0 - _S6))),
+        float(np.sqrt(2.0 * (3.0 - _S6))), float(np.sqrt(2.0 * (3.0 + _S6))))
+GAMMA4 = (1.0 - _S6 / 3.0, 1.0 + _S6 / 3.0, 1.0 + _S6 / 3.0, 1.0 - _S6 / 3.0)
+
+
+def ising4_index(phi) -> np.ndarray:
+    """Index (0..3, order l = -2, -1, +1, +2) of stored field values eta(l)."""
+    phi = np.asarray(phi, dtype=np.float64)
+    return (phi > ETA4[0]).astype(int) + (phi > ETA4[1]).astype(int) + (phi > ETA4[2]).astype(int)
+
+
 def expm_sym(K: np.ndarray, x: float) -> np.ndarray:
     """exp(x K) for symmetric K from its eigendecomposition, the way the
     paper's Operator type exponentiates a Hermitian matrix (table "operator":
@@ -50,7 +74,7 @@ class Model:
     beta: float
     dtau: float
     n_wrap: int
-    coupling: float          # lambda (ising) or c (gauss)
+    coupling: float          # lambda (ising), c (gauss) or c4 (ising4)
     U: float = 0.0           # only used by the potential-energy estimator
     alpha: float = -0.5
     n_col: int = 2
@@ -96,11 +120,13 @@ class Model:
         out = self.n_col * self.coupling * self.alpha * f.sum()
         if self.field_kind == "gauss":
             out -= 0.5 * np.sum(f * f)
+        if self.field_kind == "ising4":
+            out += float(np.sum(np.log(np.array(GAMMA4))[ising4_index(f)]))
         return float(out)
 
 
 def hubbard_model(K, U, beta, dtau, n_wrap, field_kind="ising", trotter="sym", seed=0) -> Model:
-    lam = ising_coupling(U, dtau) if field_kind == "ising" else gauss_coupling(U, dtau)
+    lam = {"ising": ising_coupling, "gauss": gauss_coupling, "ising4": ising4_coupling}[field_kind](U, dtau)
     return Model(K=K, beta=beta, dtau=dtau, n_wrap=n_wrap, coupling=lam, U=U,
                  field_kind=field_kind, trotter=trotter, seed=seed)
 
@@ -123,7 +149,8 @@ def green_naive(model: Model, field: np.ndarray, tau: int = 0) -> np.ndarray:
 def init_field(model: Model, seed: Optional[int] = None) -> np.ndarray:
     """Random start (section "Monte Carlo sampling": the run starts from a
     randomly chosen configuration): s = +1 iff u < 1/2 for an Ising field,
-    phi ~ N(0, 1) for a Gaussian field; draws addressed by (INIT, 0, tau, site)."""
+    eta(l) with index floor(4 u) for the four-valued field, phi ~ N(0, 1) for a
+    Gaussian field; draws addressed by (INIT, 0, tau, site)."""
     from . import philox
     seed = model.seed if seed is None else seed
     f = np.empty((model.L, model.N))
@@ -131,6 +158,9 @@ def init_field(model: Model, seed: Optional[int] = None) -> np.ndarray:
         if model.field_kind == "ising":
             u = philox.uniforms(seed, philox.TAG_INIT, 0, tau, 0, model.N)
             f[tau - 1] = np.where(u < 0.5, 1.0, -1.0)
+        elif model.field_kind == "ising4":
+            u = philox.uniforms(seed, philox.TAG_INIT, 0, tau, 0, model.N)
+            f[tau - 1] = np.array(ETA4)[np.floor(4.0 * u).astype(int)]
         else:
             f[tau - 1] = philox.normals(seed, philox.TAG_INIT, 0, tau, 0, model.N)
     return f

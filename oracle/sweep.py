@@ -34,7 +34,10 @@ Delta = exp(coupling (s' - s)) - 1, so
     G <- G - (Delta / r) G[:, i] (e_i - G[i, :])      (Sherman-Morrison)
 
 For a Gaussian field the move is phi' = phi + a (2 u1 - 1) and R carries the
-extra factor exp(-(phi'^2 - phi^2) / 2).
+extra factor exp(-(phi'^2 - phi^2) / 2).  For the four-valued field of
+Eq. (HS_squares) the move picks one of the three other values, index
+floor(3 u1) among them in increasing order (a symmetric proposal), and R
+carries gamma(l') / gamma(l).
 """
 import numpy as np
 
@@ -76,6 +79,14 @@ class Chain:
         if m.field_kind == "ising":
             s_new = -s
             extra = 0.0
+        elif m.field_kind == "ising4":
+            # one of the three other values of the four-valued field, equally likely
+            from .hubbard import ETA4, GAMMA4, ising4_index
+            k = int(ising4_index(s))
+            j = min(int(3.0 * u1), 2)
+            kn = j if j < k else j + 1
+            s_new = ETA4[kn]
+            extra = float(np.log(GAMMA4[kn])) - float(np.log(GAMMA4[k]))
         else:
             s_new = s + m.prop_width * (2.0 * u1 - 1.0)
             extra = -0.5 * (s_new * s_new - s * s)

@@ -57,6 +57,50 @@ def test_hs_identities(U, dtau):
         assert abs(quad - np.exp(dtau * U / 2 * A * A)) < 1e-13
 
 
+def test_hs4_identity_is_eighth_order():
+    """Eq. (HS_squares): 1/4 sum_l gamma(l) exp(x eta(l)) = exp(x^2) + O(x^8)
+    (the paper's O(dtau^4)): the moments sum_l gamma eta^(2k) are 4, 8, 48, 480
+    = 4 (2k)! / k!, so the series agrees through x^6, and halving x shrinks the
+    error by 2^8."""
+    g, e = np.array(hubbard.GAMMA4), np.array(hubbard.ETA4)
+    for k, want in enumerate((4.0, 8.0, 48.0, 480.0)):
+        assert abs(np.sum(g * e ** (2 * k)) - want) < 1e-12 * want
+    assert abs(np.sum(g * e)) < 1e-14 and abs(np.sum(g * e ** 3)) < 1e-12
+    err = [0.25 * np.sum(g * np.exp(x * e)) - np.exp(x * x) for x in (0.2, 0.1, 0.05)]
+    assert abs(err[0]) < 1e-7
+    for a, b in zip(err, err[1:]):
+        assert 240.0 < a / b < 275.0
+
+
+def test_two_site_enumeration_ising4_equals_fock_at_u_eff():
+    """With A = n - 1 in {-1, 0, 1}, the four-valued sum of Eq. (HS_squares) is
+    exactly exp(dtau U_eff / 2 A^2) with exp(dtau U_eff / 2) = 1/2 (gamma_1
+    cosh(c4 eta_1) + gamma_2 cosh(c4 eta_2)); the enumeration over all 4^(N L)
+    configurations must reproduce the Fock-space Trotter product at U_eff."""
+    K = np.array([[0.0, -1.0], [-1.0, 0.0]])
+    U, dtau, L = 4.0, 0.25, 3
+    m = hubbard.hubbard_model(K, U, L * dtau, dtau, 3, field_kind="ising4")
+    res = exact_small.enumerate_observables(m, taus=(0, 1))
+    g, e = hubbard.GAMMA4, hubbard.ETA4
+    F1 = 0.5 * (g[2] * np.cosh(m.coupling * e[2]) + g[3] * np.cosh(m.coupling * e[3]))
+    U_eff = 2.0 * np.log(F1) / dtau
+    assert abs(U_eff - U) < 1e-2 and U_eff != U       # next to exact (dtau^4), not exact
+    F = Fock(K, U_eff)
+    S = F.trotter(dtau)
+    D = F.expect_with(S, F.double_occ(), L)
+    E = F.expect_with(S, F.kinetic(), L)
+    assert np.max(np.abs(res[:, 0] - D)) < 1e-13
+    assert np.max(np.abs(res[:, 1] - E)) < 1e-13
+    # a planted mistake (gamma left out of the weight) breaks it
+    g_saved = hubbard.GAMMA4
+    try:
+        hubbard.GAMMA4 = (1.0, 1.0, 1.0, 1.0)
+        bad = exact_small.enumerate_observables(m, taus=(0,))
+    finally:
+        hubbard.GAMMA4 = g_saved
+    assert abs(bad[0, 0] - D) > 1e-3
+
+
 # -------------------------------------------------------- U = 0 closed form --
 def _square_u0_green(L1, L2, beta):
     """(1 + exp(-beta K))^-1 on the square lattice from plane waves and the
@@ -244,6 +288,32 @@ def test_mc_histogram_matches_exact_weights():
     m2 = hubbard.hubbard_model(K, 4.0, 1.0, 0.25, 2)
     m2.alpha = 0.5
     p2 = exact_small.enumerate_weights(m2)
+    chi2_wrong = np.sum((counts - n_sweeps * p2) ** 2 / (n_sweeps * p2)) / (p.size - 1)
+    assert chi2_wrong > 5.0
+
+
+def test_mc_histogram_ising4_matches_exact_weights():
+    """The same stationarity check for the four-valued field: the three-way
+    proposal of the other values is symmetric, so the chain must visit the
+    4^(N L) configurations of 2 sites x 2 slices with frequency W(C)/Z."""
+    K = np.array([[0.0, -1.0], [-1.0, 0.0]])
+    m = hubbard.hubbard_model(K, 4.0, 0.5, 0.25, 2, field_kind="ising4", seed=13)
+    p = exact_small.enumerate_weights(m)
+    index = {tuple(fl.ravel()): j for j, fl in enumerate(exact_small.all_fields(m))}
+    ch = sweep.Chain(m, hubbard.init_field(m)).init()
+    counts = np.zeros(p.size)
+    n_sweeps = 6000
+    for _ in range(n_sweeps):
+        ch.sweep(measure=False)
+        counts[index[tuple(ch.field.ravel())]] += 1
+    chi2 = np.sum((counts - n_sweeps * p) ** 2 / (n_sweeps * p)) / (p.size - 1)
+    assert chi2 < 2.0
+    g_saved = hubbard.GAMMA4
+    try:
+        hubbard.GAMMA4 = (1.0, 1.0, 1.0, 1.0)
+        p2 = exact_small.enumerate_weights(m)
+    finally:
+        hubbard.GAMMA4 = g_saved
     chi2_wrong = np.sum((counts - n_sweeps * p2) ** 2 / (n_sweeps * p2)) / (p.size - 1)
     assert chi2_wrong > 5.0
 
