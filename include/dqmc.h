@@ -44,7 +44,7 @@ typedef enum {
   DQMC_E_STATE = 6         /* call out of order (not bound / not initialised / poisoned)     */
 } dqmc_status;
 
-typedef enum { DQMC_FIELD_ISING = 0, DQMC_FIELD_GAUSS = 1 } dqmc_field_kind;
+typedef enum { DQMC_FIELD_ISING = 0, DQMC_FIELD_GAUSS = 1, DQMC_FIELD_ISING4 = 2 } dqmc_field_kind;
 typedef enum { DQMC_TROTTER_ASYM = 0, DQMC_TROTTER_SYM = 1 } dqmc_trotter;
 
 /*
@@ -57,6 +57,11 @@ typedef enum { DQMC_TROTTER_ASYM = 0, DQMC_TROTTER_SYM = 1 } dqmc_trotter;
  * that of Eq. (Green_eq) and of a symmetric split.  The configuration weight is
  * exp(n_col * coupling * alpha * sum(field)) det(1 + B(beta,0))^n_col
  * (Eq. (partition_2)), times exp(-sum(field^2)/2) for a Gaussian field.
+ * Field kinds: DQMC_FIELD_ISING stores +-1 (the exact two-valued identity);
+ * DQMC_FIELD_ISING4 stores eta(l), l = +-1, +-2, of the paper's four-valued
+ * identity (Eq. (HS_squares)), and the weight gains prod gamma(l); a flip
+ * proposes one of the three other values with probability 1/3 each;
+ * DQMC_FIELD_GAUSS stores a real phi (continuous field, Gaussian weight).
  */
 typedef struct {
   int32_t n;               /* N_dim, number of orbitals, 1 <= n <= 1024                       */
@@ -266,8 +271,9 @@ const char* dqmc_batch_last_error(const dqmc_batch* b);
 void dqmc_batch_destroy(dqmc_batch* b);
 
 /* Coupling of the exact two-valued Hubbard-Stratonovich identity,
- * cosh(lambda) = exp(dtau U / 2) (DQMC_FIELD_ISING), or of the Gaussian
- * identity, c = sqrt(dtau U) (DQMC_FIELD_GAUSS). */
+ * cosh(lambda) = exp(dtau U / 2) (DQMC_FIELD_ISING), of the Gaussian
+ * identity, c = sqrt(dtau U) (DQMC_FIELD_GAUSS), or of the four-valued
+ * identity of Eq. (HS_squares), sqrt(dtau U / 2) (DQMC_FIELD_ISING4). */
 dqmc_status dqmc_hubbard_coupling(double U, double dtau, dqmc_field_kind kind, double* coupling);
 
 #ifdef __cplusplus

@@ -8,7 +8,8 @@ LIB_PATH = os.path.join(HERE, "libdqmc_gfx950.so")
 DQMC_OK = 0
 STATUS_NAMES = {0: "DQMC_OK", 1: "DQMC_E_ARG", 2: "DQMC_E_UNSUPPORTED", 3: "DQMC_E_DEVICE",
                 4: "DQMC_E_NUMERIC", 5: "DQMC_E_NOMEM", 6: "DQMC_E_STATE"}
-FIELD_ISING, FIELD_GAUSS = 0, 1
+FIELD_ISING, FIELD_GAUSS, FIELD_ISING4 = 0, 1, 2
+FIELD_KINDS = {"ising": FIELD_ISING, "gauss": FIELD_GAUSS, "ising4": FIELD_ISING4}
 TROTTER_ASYM, TROTTER_SYM = 0, 1
 KERNEL_BLOCK_UPDATE, KERNEL_GEMM = 0, 1
 

@@ -11,8 +11,7 @@ from ._lib import Buffers, Model, Sizes, Stats, check
 
 def hubbard_coupling(U: float, dtau: float, field: str = "ising") -> float:
     out = ctypes.c_double()
-    kind = _lib.FIELD_ISING if field == "ising" else _lib.FIELD_GAUSS
-    check(_lib.load().dqmc_hubbard_coupling(U, dtau, kind, ctypes.byref(out)))
+    check(_lib.load().dqmc_hubbard_coupling(U, dtau, _lib.FIELD_KINDS[field], ctypes.byref(out)))
     return out.value
 
 
@@ -20,7 +19,7 @@ def make_model(n, beta, dtau, n_wrap, coupling, U=0.0, field="ising", trotter="s
                alpha=-0.5, n_col=2, prec_threshold=0.0, prop_width=1.0) -> Model:
     L = int(round(beta / dtau))
     return Model(n=n, n_slices=L, beta=beta, dtau=dtau, n_wrap=n_wrap, n_col=n_col,
-                 field=_lib.FIELD_ISING if field == "ising" else _lib.FIELD_GAUSS,
+                 field=_lib.FIELD_KINDS[field],
                  coupling=coupling, alpha=alpha, u_int=U,
                  trotter=_lib.TROTTER_SYM if trotter == "sym" else _lib.TROTTER_ASYM,
                  prec_threshold=prec_threshold, prop_width=prop_width, seed=seed)

@@ -597,6 +597,28 @@ dqmc_status measure(dqmc_ctx* c) {
   return DQMC_OK;
 }
 
+// The four-valued field's values eta(l) and log gamma(l), l = -2, -1, +1, +2
+// (Eq. (HS_squares)), computed on the host.
+Field4 field4_table() {
+  const double s6 = std::sqrt(6.0);
+  const double e1 = std::sqrt(2.0 * (3.0 - s6)), e2 = std::sqrt(2.0 * (3.0 + s6));
+  const double g1 = 1.0 + s6 / 3.0, g2 = 1.0 - s6 / 3.0;
+  Field4 t;
+  t.eta[0] = -e2; t.eta[1] = -e1; t.eta[2] = e1; t.eta[3] = e2;
+  t.lg[0] = std::log(g2); t.lg[1] = std::log(g1); t.lg[2] = std::log(g1); t.lg[3] = std::log(g2);
+  return t;
+}
+
+bool field_value_ok(dqmc_field_kind kind, double v) {
+  if (!std::isfinite(v)) return false;
+  if (kind == DQMC_FIELD_ISING) return v == 1.0 || v == -1.0;
+  if (kind == DQMC_FIELD_ISING4) {
+    const Field4 t = field4_table();
+    return v == t.eta[0] || v == t.eta[1] || v == t.eta[2] || v == t.eta[3];
+  }
+  return true;
+}
+
 // Draws of every site of the coming pass, from the field as it stands (all
 // rows at the same place: the caller's buffer before the upward pass, the
 // second buffer before the downward pass).
@@ -604,7 +626,7 @@ dqmc_status pass_draws(dqmc_ctx* c, int dir) {
   const size_t n = (size_t)c->L * c->N;
   hipLaunchKernelGGL(k_pass_draws, gridc(c, grid1(n)), dim3(256), 0, c->stream, field_row(c, 1), c->L, c->N,
                      (unsigned long long)dir, c->m.coupling, c->m.alpha, c->m.n_col,
-                     c->m.field == DQMC_FIELD_GAUSS ? 1 : 0, c->m.prop_width, c->counters, c->draws, c->cs);
+                     (int)c->m.field, c->m.prop_width, field4_table(), c->counters, c->draws, c->cs);
   HIPCHK(hipGetLastError());
   return DQMC_OK;
 }
@@ -675,7 +697,7 @@ dqmc_status check_model(const dqmc_model* m) {
   if (!(m->beta > 0.0) || !(m->dtau > 0.0)) return DQMC_E_ARG;
   if (std::fabs(m->beta - m->n_slices * m->dtau) > 1e-12 * m->beta) return DQMC_E_ARG;
   if (m->n_col < 1 || m->n_col > 2) return DQMC_E_ARG;
-  if (m->field != DQMC_FIELD_ISING && m->field != DQMC_FIELD_GAUSS) return DQMC_E_ARG;
+  if (m->field != DQMC_FIELD_ISING && m->field != DQMC_FIELD_GAUSS && m->field != DQMC_FIELD_ISING4) return DQMC_E_ARG;
   if (m->trotter != DQMC_TROTTER_ASYM && m->trotter != DQMC_TROTTER_SYM) return DQMC_E_ARG;
   if (!std::isfinite(m->coupling) || !std::isfinite(m->alpha)) return DQMC_E_ARG;
   return DQMC_OK;
@@ -1020,8 +1042,8 @@ dqmc_status dqmc_set_state(dqmc_ctx* c, const double* field_host, uint64_t sweep
   const size_t n = (size_t)c->L * c->N;
   for (size_t e = 0; e < n; ++e) {
     const double v = field_host[e];
-    if (!std::isfinite(v) || (c->m.field == DQMC_FIELD_ISING && v != 1.0 && v != -1.0))
-      return fail(c, DQMC_E_ARG, "field values must be +-1 (Ising) or finite (Gaussian)");
+    if (!field_value_ok(c->m.field, v))
+      return fail(c, DQMC_E_ARG, "field values must be +-1 (Ising), eta(l) (four-valued) or finite (Gaussian)");
   }
   HIPCHK(hipMemcpyAsync(c->field, field_host, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
   unsigned long long ctr = sweep_counter;
@@ -1050,7 +1072,7 @@ dqmc_status dqmc_random_field(dqmc_ctx* c) {
   if (!c->bound) return fail(c, DQMC_E_STATE, "not bound");
   const size_t n = (size_t)c->L * c->N;
   hipLaunchKernelGGL(k_random_field, gridc(c, grid1(n)), dim3(256), 0, c->stream, c->field, c->L, c->N,
-                     c->counters, c->m.field == DQMC_FIELD_GAUSS ? 1 : 0, c->cs);
+                     c->counters, (int)c->m.field, field4_table(), c->cs);
   HIPCHK(hipGetLastError());
   if (dqmc_status s = fill_small(c, reinterpret_cast<double*>(c->counters + 2), 1, 0.0)) return s;
   HIPCHK(hipStreamSynchronize(c->stream));
@@ -1145,12 +1167,11 @@ dqmc_status dqmc_ratio(dqmc_ctx* c, int32_t tau, int32_t site, double s_new, dou
   if (!c->bound) return fail(c, DQMC_E_STATE, "not bound");
   if (c->nch != 1) return fail(c, DQMC_E_UNSUPPORTED, "single chains only");
   if (tau > c->L || site >= c->N) return fail(c, DQMC_E_ARG, "tau or site out of range");
-  if (c->m.field == DQMC_FIELD_ISING && s_new != 1.0 && s_new != -1.0)
-    return fail(c, DQMC_E_ARG, "Ising field values are +-1");
+  if (!field_value_ok(c->m.field, s_new)) return fail(c, DQMC_E_ARG, "not a value of the field");
   if (dqmc_status s = dqmc_green_scratch(c, tau, c->Gs)) return s;
   hipLaunchKernelGGL(k_ratio, dim3(1), dim3(64), 0, c->stream, c->Gs, c->N, site,
                      c->field + (size_t)(tau - 1) * c->N, s_new, c->m.coupling, c->m.alpha, c->m.n_col,
-                     c->m.field == DQMC_FIELD_GAUSS ? 1 : 0, c->logdet + 1);
+                     (int)c->m.field, field4_table(), c->logdet + 1);
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(R, c->logdet + 1, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
@@ -1291,6 +1312,9 @@ dqmc_status dqmc_hubbard_coupling(double U, double dtau, dqmc_field_kind kind, d
   } else if (kind == DQMC_FIELD_GAUSS) {
     if (U < 0.0) return DQMC_E_ARG;
     *coupling = std::sqrt(dtau * U);
+  } else if (kind == DQMC_FIELD_ISING4) {
+    if (U < 0.0) return DQMC_E_ARG;
+    *coupling = std::sqrt(dtau * U / 2.0);
   } else {
     return DQMC_E_ARG;
   }
@@ -1490,9 +1514,7 @@ dqmc_status dqmc_batch_set_state(dqmc_batch* b, int32_t chain, const double* fie
   const size_t co = (size_t)b->index_of[chain] * c->cs;
   const size_t n = (size_t)c->L * c->N;
   for (size_t e = 0; e < n; ++e)
-    if (!std::isfinite(field_host[e]) ||
-        (c->m.field == DQMC_FIELD_ISING && field_host[e] != 1.0 && field_host[e] != -1.0))
-      return bfail(b, DQMC_E_ARG, "bad field value");
+    if (!field_value_ok(c->m.field, field_host[e])) return bfail(b, DQMC_E_ARG, "bad field value");
   BHIPCHK_(hipMemcpyAsync(c->field + co, field_host, n * sizeof(double), hipMemcpyHostToDevice, b->stream));
   unsigned long long ctr = sweep_counter;
   BHIPCHK_(hipMemcpyAsync(reinterpret_cast<double*>(c->counters + 2) + co, &ctr, sizeof(ctr), hipMemcpyHostToDevice,

@@ -32,17 +32,33 @@ struct BlockArgs {
   size_t cs;                         // per-chain stride (doubles) of every pointer above; chain = blockIdx.y
 };
 
+// The four-valued field of Eq. (HS_squares): eta(l) and log gamma(l) in the
+// order l = -2, -1, +1, +2 (the field stores eta; the host fills the table).
+// Field kinds: 0 Ising (+-1), 1 Gaussian, 2 four-valued.
+struct Field4 { double eta[4]; double lg[4]; };
+enum { FK_ISING = 0, FK_GAUSS = 1, FK_ISING4 = 2 };
+
+// index 0..3 of a stored four-valued field value (the values are distinct)
+__device__ __forceinline__ int field4_index(const Field4& t, double s) {
+  return (s > t.eta[0] ? 1 : 0) + (s > t.eta[1] ? 1 : 0) + (s > t.eta[2] ? 1 : 0);
+}
+__device__ __forceinline__ double field4_pick(const double (&v)[4], int k) {
+  return k == 0 ? v[0] : (k == 1 ? v[1] : (k == 2 ? v[2] : v[3]));
+}
+
 // Draws and ratio constants of every site of one pass (upward or downward
 // half of a sweep), computed before the pass: each site is visited once per
 // pass, so they depend only on the field at the start of the pass.  For site
 // i of slice tau, from Philox counter (TAG_FLIP, sweep, (tau << 1) | dir, i):
-//   u = u0; s_new = -s (Ising) or s + width (2 u1 - 1) (Gaussian);
+//   u = u0; s_new = -s (Ising), s + width (2 u1 - 1) (Gaussian), or the value of
+//   index floor(3 u1) among the three others in increasing order (four-valued);
 //   Delta = exp(coupling (s_new - s)) - 1;
-//   prefactor = exp(n_col coupling alpha (s_new - s) [- (s_new^2 - s^2)/2]).
+//   prefactor = exp(n_col coupling alpha (s_new - s) + extra), extra =
+//   -(s_new^2 - s^2)/2 (Gaussian), log gamma(l') - log gamma(l) (four-valued), 0.
 // out[(tau-1) N + i][0..3] = (u, Delta, prefactor, s_new); grid (ceil(L N / 256), chains).
 __global__ __launch_bounds__(256) void k_pass_draws(const double* field, int L, int N, unsigned long long dir,
-                                                    double coupling, double alpha, int n_col, int gauss,
-                                                    double prop_width, const unsigned long long* counters,
+                                                    double coupling, double alpha, int n_col, int kind,
+                                                    double prop_width, Field4 f4, const unsigned long long* counters,
                                                     double* out, size_t cs) {
   const size_t co = (size_t)blockIdx.y * cs;
   field += co;
@@ -56,8 +72,14 @@ __global__ __launch_bounds__(256) void k_pass_draws(const double* field, int L, 
   const double u0 = unit_double(r.w[0]), u1 = unit_double(r.w[1]);
   const double s = field[e];
   double sn, extra;
-  if (gauss) { sn = s + prop_width * (2.0 * u1 - 1.0); extra = -0.5 * (sn * sn - s * s); }
-  else { sn = -s; extra = 0.0; }
+  if (kind == FK_GAUSS) { sn = s + prop_width * (2.0 * u1 - 1.0); extra = -0.5 * (sn * sn - s * s); }
+  else if (kind == FK_ISING4) {
+    const int k = field4_index(f4, s);
+    const int j = min((int)(3.0 * u1), 2);
+    const int kn = (j < k) ? j : j + 1;
+    sn = field4_pick(f4.eta, kn);
+    extra = field4_pick(f4.lg, kn) - field4_pick(f4.lg, k);
+  } else { sn = -s; extra = 0.0; }
   out[4 * (size_t)e] = u0;
   out[4 * (size_t)e + 1] = exp(coupling * (sn - s)) - 1.0;
   out[4 * (size_t)e + 2] = exp(n_col * coupling * alpha * (sn - s) + extra);
@@ -395,10 +417,13 @@ __global__ __launch_bounds__(256) void k_measure_part(const double* G, const dou
 // Weight ratio of one proposed change s -> s_new at a site, from G(tau) (the
 // same formulas as the sweep's decisions); one thread.
 __global__ void k_ratio(const double* G, int N, int site, const double* field_row, double s_new, double coupling,
-                        double alpha, int n_col, int gauss, double* out) {
+                        double alpha, int n_col, int kind, Field4 f4, double* out) {
   if (threadIdx.x != 0) return;
   const double s = field_row[site];
-  const double extra = gauss ? -0.5 * (s_new * s_new - s * s) : 0.0;
+  const double extra = kind == FK_GAUSS    ? -0.5 * (s_new * s_new - s * s)
+                       : kind == FK_ISING4 ? field4_pick(f4.lg, field4_index(f4, s_new)) -
+                                                 field4_pick(f4.lg, field4_index(f4, s))
+                                           : 0.0;
   const double dl = exp(coupling * (s_new - s)) - 1.0;
   const double r = 1.0 + dl * (1.0 - G[(size_t)site * N + site]);
   out[0] = exp(n_col * coupling * alpha * (s_new - s) + extra) * ipow(r, n_col);
@@ -456,9 +481,11 @@ __global__ void k_finish_sweep(double* prec_hist, int n_hist, double* prec_tot, 
   counters[2] += 1ull;
 }
 
-// Random start of the field (s = +1 iff u < 1/2, or phi ~ N(0,1) by
-// Box-Muller on (1 - u0, u1), cosine branch); draws (INIT, 0, tau << 1, site).
-__global__ void k_random_field(double* field, int L, int N, const unsigned long long* counters, int gauss, size_t cs) {
+// Random start of the field (s = +1 iff u < 1/2; eta(l) of index floor(4 u)
+// for the four-valued field; or phi ~ N(0,1) by Box-Muller on (1 - u0, u1),
+// cosine branch); draws (INIT, 0, tau << 1, site).
+__global__ void k_random_field(double* field, int L, int N, const unsigned long long* counters, int kind, Field4 f4,
+                               size_t cs) {
   field += (size_t)blockIdx.y * cs;
   counters = reinterpret_cast<const unsigned long long*>(reinterpret_cast<const double*>(counters) +
                                                          (size_t)blockIdx.y * cs);
@@ -468,8 +495,10 @@ __global__ void k_random_field(double* field, int L, int N, const unsigned long 
   const int tau = e / N + 1, i = e % N;
   const Philox4 w = philox4x64_10(TAG_INIT, 0ull, (unsigned long long)tau << 1, (unsigned long long)i, seed, 0ull);
   const double u0 = unit_double(w.w[0]);
-  if (!gauss) {
+  if (kind == FK_ISING) {
     field[e] = (u0 < 0.5) ? 1.0 : -1.0;
+  } else if (kind == FK_ISING4) {
+    field[e] = field4_pick(f4.eta, min((int)(4.0 * u0), 3));
   } else {
     const double u1 = unit_double(w.w[1]);
     field[e] = sqrt(-2.0 * log(1.0 - u0)) * cos(2.0 * M_PI * u1);

@@ -19,7 +19,7 @@ def _log(msg):
 
 
 @pytest.mark.parametrize("kind,L1,L2,field", [("square", 4, 4, "ising"), ("honeycomb", 6, 6, "ising"),
-                                              ("square", 5, 5, "gauss")])
+                                              ("square", 5, 5, "gauss"), ("honeycomb", 6, 6, "ising4")])
 def test_random_field_matches_oracle(kind, L1, L2, field):
     _log(f"random field {kind} {L1}x{L2} {field}")
     om, ch, _ = pair(kind, L1, L2, 4.0, 2.0, 0.1, 10, seed=7, field=field)
@@ -27,7 +27,7 @@ def test_random_field_matches_oracle(kind, L1, L2, field):
     f, ctr = ch.get_state()
     fo = ohub.init_field(om)
     assert ctr == 0
-    if field == "ising":
+    if field in ("ising", "ising4"):
         assert np.array_equal(f, fo)
     else:
         assert maxabs(f, fo) < 1e-13
@@ -87,13 +87,22 @@ def test_sweep_parity_gauss_field():
     _trajectory("square", 4, 4, 4.0, 2.0, 5, "sym", 2, 2, field="gauss")
 
 
+def test_sweep_parity_four_valued_field():
+    """The four-valued field of Eq. (HS_squares) (three-way proposals, gamma in
+    the weight): 4x4 square for 20 sweeps and the ragged N = 72 honeycomb."""
+    _log("trajectory four-valued field square 4x4 20 sweeps")
+    _trajectory("square", 4, 4, 4.0, 2.0, 10, "sym", 4, 20, field="ising4")
+    _log("trajectory four-valued field honeycomb 6x6 2 sweeps")
+    _trajectory("honeycomb", 6, 6, 4.0, 4.0, 10, "asym", 8, 2, field="ising4")
+
+
 def test_sweep_parity_honeycomb12_one_sweep():
     """Honeycomb 12x12 (N = 288), U=4, beta=10, L=100: one sweep."""
     _log("trajectory honeycomb 12x12 1 sweep")
     _trajectory("honeycomb", 12, 12, 4.0, 10.0, 10, "asym", 0, 1)
 
 
-@pytest.mark.parametrize("field", ["ising", "gauss"])
+@pytest.mark.parametrize("field", ["ising", "gauss", "ising4"])
 def test_ratio_hook_equals_weight_ratio(field):
     """dqmc_ratio against W(C')/W(C) of two from-scratch weights (oracle)."""
     from oracle.stable import weight_ratio
@@ -104,7 +113,13 @@ def test_ratio_hook_equals_weight_ratio(field):
     rng = np.random.default_rng(2)
     for _ in range(5):
         tau, i = int(rng.integers(1, om.L + 1)), int(rng.integers(0, om.N))
-        s_new = -f0[tau - 1, i] if field == "ising" else float(f0[tau - 1, i] + rng.uniform(-1, 1))
+        if field == "ising":
+            s_new = -f0[tau - 1, i]
+        elif field == "ising4":
+            others = [v for v in ohub.ETA4 if v != f0[tau - 1, i]]
+            s_new = others[int(rng.integers(0, 3))]
+        else:
+            s_new = float(f0[tau - 1, i] + rng.uniform(-1, 1))
         got = ch.ratio(tau, i, s_new)
         want = weight_ratio(om, f0, tau, i, s_new)
         assert abs(got - want) < 1e-9 * max(1.0, abs(want)), (tau, i, got, want)
