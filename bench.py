@@ -25,7 +25,8 @@ Prints one JSON line with
              batched-vs-plain sweep rate at N = 64; gradient passes and
              Langevin steps of 64 Gaussian-field chains (10x10, beta = 4);
              the time-displaced pass of the 18x18 honeycomb chain (N = 648,
-             U = 5, beta = 20, L = 200) with its MFMA GEMM rate.
+             U = 5, beta = 20, L = 200) with its MFMA GEMM rate; the headline
+             chain with the paper's four-valued field.
 """
 import argparse
 import hashlib
@@ -175,6 +176,26 @@ def bench_time_displaced(torch, pa):
             "sweep_with_td_s": dts, "updates_per_s": st.proposals / dts}
 
 
+def bench_four_valued(torch, pa):
+    """The honeycomb 12x12 chain of the headline workload with the paper's
+    four-valued field (Eq. (HS_squares)) instead of the two-valued one: three
+    timed sweeps after one untimed."""
+    from inputs import WORKLOADS
+    w = WORKLOADS["honeycomb12_U4_b10"]
+    lat = w.lattice()
+    lam = pa.hubbard_coupling(w.U, w.dtau, "ising4")
+    ch = pa.Chain(pa.make_model(lat.n, w.beta, w.dtau, w.n_wrap, lam, U=w.U, field="ising4", trotter=w.trotter,
+                                seed=w.seed), lat.K)
+    ch.random_field().init()
+    ch.sweep(1, measure=True)
+    st0 = ch.sweep(0, measure=True)
+    dt, st = _sync_time(torch, lambda: ch.sweep(3, measure=True))
+    ch.close()
+    props, acc = st.proposals - st0.proposals, st.accepted - st0.accepted
+    return {"N": lat.n, "L": w.n_slices, "ms_per_sweep": 1e3 * dt / 3, "updates_per_s": props / dt,
+            "acceptance": acc / max(1, props), "prec_max": st.prec_max}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -182,7 +203,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--profile-extra", choices=["batched", "gradient", "time_displaced"],
+    ap.add_argument("--profile-extra", choices=["batched", "gradient", "time_displaced", "four_valued"],
                     help="run only this extra workload and print its figures (for rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -196,7 +217,8 @@ def main():
     from inputs import WORKLOADS
 
     if args.profile_extra:
-        fn = {"batched": bench_batched, "gradient": bench_gradient, "time_displaced": bench_time_displaced}
+        fn = {"batched": bench_batched, "gradient": bench_gradient, "time_displaced": bench_time_displaced,
+              "four_valued": bench_four_valued}
         print(json.dumps({args.profile_extra: fn[args.profile_extra](torch, pa)}))
         return
 
@@ -263,7 +285,8 @@ def main():
     ch.close()
     if not args.no_extras:
         out["config"]["extras"] = {"batched": bench_batched(torch, pa), "gradient": bench_gradient(torch, pa),
-                                   "time_displaced": bench_time_displaced(torch, pa)}
+                                   "time_displaced": bench_time_displaced(torch, pa),
+                                   "four_valued": bench_four_valued(torch, pa)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(lat, w, field0)
     print(json.dumps(out))
