@@ -9,7 +9,7 @@ import itertools
 
 import numpy as np
 
-from .measure import equal_time
+from .measure import eq_correlations, equal_time
 from .stable import green_scratch, log_weight
 from .timedisplaced import tdgf_measure
 
@@ -54,3 +54,16 @@ def enumerate_szsz(model, lat, kvec, taus):
     logw = np.array(logw)
     w = np.exp(logw - logw.max())
     return np.einsum("c,ctab->tab", w, np.array(obs)) / w.sum()
+
+
+def enumerate_eq_correlations(model, lat, tau=0):
+    """Exact weighted average of the lattice-resolved equal-time correlations
+    (measure.eq_correlations) at slice tau: [4, N_cells, norb, norb]."""
+    logw = []
+    obs = []
+    for f in all_fields(model):
+        logw.append(log_weight(model, f))
+        obs.append(eq_correlations(model, lat, green_scratch(model, f, tau)))
+    logw = np.array(logw)
+    w = np.exp(logw - logw.max())
+    return np.einsum("c,c...->...", w, np.array(obs)) / w.sum()
