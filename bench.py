@@ -26,7 +26,8 @@ Prints one JSON line with
              Langevin steps of 64 Gaussian-field chains (10x10, beta = 4);
              the time-displaced pass of the 18x18 honeycomb chain (N = 648,
              U = 5, beta = 20, L = 200) with its MFMA GEMM rate; the headline
-             chain with the paper's four-valued field.
+             chain with the paper's four-valued field; the headline chain
+             with the lattice-resolved equal-time correlations measured.
 """
 import argparse
 import hashlib
@@ -196,6 +197,31 @@ def bench_four_valued(torch, pa):
             "acceptance": acc / max(1, props), "prec_max": st.prec_max}
 
 
+def bench_correlations(torch, pa):
+    """The honeycomb 12x12 chain of the headline workload with the
+    lattice-resolved equal-time correlations (Green, SpinZ, SpinXY, Den by
+    displacement and orbital pair) measured on every slice of both passes:
+    three timed sweeps after one untimed, beside three without them."""
+    import numpy as np
+
+    from inputs import WORKLOADS
+    w = WORKLOADS["honeycomb12_U4_b10"]
+    lat = w.lattice()
+    ch = pa.Chain(pa.make_model(lat.n, w.beta, w.dtau, w.n_wrap, pa.hubbard_coupling(w.U, w.dtau, w.field_kind),
+                                U=w.U, field=w.field_kind, trotter=w.trotter, seed=w.seed), lat.K)
+    site = np.full((lat.n_cells, lat.norb), -1, dtype=np.int32)
+    site[lat.cell_of, lat.orb_of] = np.arange(lat.n)
+    ch.random_field().init()
+    ch.eq_setup(lat.L1, lat.L2, site, lat.sublattice_sign())
+    ch.sweep(1, measure=True, correlations=True)
+    dt_on, _ = _sync_time(torch, lambda: ch.sweep(3, measure=True, correlations=True))
+    dt_off, _ = _sync_time(torch, lambda: ch.sweep(3, measure=True))
+    _, cnt = ch.eq_read_bins()
+    ch.close()
+    return {"N": lat.n, "L": w.n_slices, "entries": 4 * lat.n_cells * lat.norb ** 2,
+            "ms_per_sweep": 1e3 * dt_on / 3, "ms_per_sweep_without": 1e3 * dt_off / 3, "measurements": cnt}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -203,12 +229,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--profile-extra", choices=["batched", "gradient", "time_displaced", "four_valued"],
+    ap.add_argument("--profile-extra", choices=["batched", "gradient", "time_displaced", "four_valued",
+                                                "correlations"],
                     help="run only this extra workload and print its figures (for rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: the sweep of one chain does not shard across GPUs "
-              "in this build (run with --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU only: the sweep of one chain runs on one GPU "
+              "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -218,7 +245,7 @@ def main():
 
     if args.profile_extra:
         fn = {"batched": bench_batched, "gradient": bench_gradient, "time_displaced": bench_time_displaced,
-              "four_valued": bench_four_valued}
+              "four_valued": bench_four_valued, "correlations": bench_correlations}
         print(json.dumps({args.profile_extra: fn[args.profile_extra](torch, pa)}))
         return
 
@@ -286,7 +313,8 @@ def main():
     if not args.no_extras:
         out["config"]["extras"] = {"batched": bench_batched(torch, pa), "gradient": bench_gradient(torch, pa),
                                    "time_displaced": bench_time_displaced(torch, pa),
-                                   "four_valued": bench_four_valued(torch, pa)}
+                                   "four_valued": bench_four_valued(torch, pa),
+                                   "correlations": bench_correlations(torch, pa)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(lat, w, field0)
     print(json.dumps(out))

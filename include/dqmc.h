@@ -128,7 +128,9 @@ dqmc_status dqmc_init(dqmc_ctx* ctx);
  * Algorithm 1).  measure: bit 0 accumulates the equal-time estimators on
  * every slice of both passes; bit 1 runs the time-displaced pass
  * (dqmc_td_measure, needs dqmc_td_setup) at the start of every sweep, as the
- * paper does for its time-displaced observables.  stats may be NULL.
+ * paper does for its time-displaced observables; bit 2 accumulates the
+ * lattice-resolved equal-time correlations (needs dqmc_eq_setup) on every
+ * slice of both passes.  Other bits: DQMC_E_ARG.  stats may be NULL.
  * DQMC_E_NUMERIC if the device flagged a numerical failure; the context then
  * needs dqmc_init. */
 dqmc_status dqmc_sweep(dqmc_ctx* ctx, int32_t n_sweeps, int32_t measure, dqmc_stats* stats);
@@ -201,6 +203,30 @@ dqmc_status dqmc_td_measure(dqmc_ctx* ctx, double* S_host, double* prec);
 /* Bin sums of S in the layout of dqmc_td_measure and the number of passes
  * summed (count, may be NULL).  Zeroed by dqmc_init and dqmc_reset_bins. */
 dqmc_status dqmc_td_read_bins(dqmc_ctx* ctx, double* sums_host, double* count);
+
+/* ---- lattice-resolved equal-time correlations (section "Observables":
+ * correlation functions summed over unit cells and stored by the displacement
+ * R between cells) ----
+ * Per measurement, from the measured G~ (G, or e^{-dtau K/2} G e^{+dtau K/2}
+ * for the symmetric split), both particle-hole species sharing G and s_i the
+ * sublattice sign of the down-spin map,
+ *   C_o[R][a][b] += 1/n_cells sum_I O(site(I, a), site(I + R, b)),
+ *   Green  = 1/2 (d_ij - G_ji + s_i s_j G_ij)
+ *   SpinZ  = 1/4 ((1 - 2 G_ii)(1 - 2 G_jj) + 2 (d_ij - G_ji) G_ij)
+ *   SpinXY = 1/4 s_i s_j ((d_ij - G_ji)^2 + G_ij^2)
+ *   Den    = 1 + 2 (d_ij - G_ji) G_ij,
+ * cells I = i1 + L1 i2 and R = r1 + L1 r2, I + R taken modulo (L1, L2).
+ *
+ * dqmc_eq_setup: an L1 x L2 lattice of norb orbitals per cell (1..4,
+ * L1 L2 norb = n, else DQMC_E_ARG); site[I * norb + a] the orbital index of
+ * orbital a of cell I (a permutation of 0..n-1, else DQMC_E_ARG); sign[n] the
+ * sublattice signs, each +1 or -1 (else DQMC_E_ARG).  Host arrays, copied.
+ * Zeroes these bins. */
+dqmc_status dqmc_eq_setup(dqmc_ctx* ctx, int32_t L1, int32_t L2, int32_t norb, const int32_t* site, const double* sign);
+/* Bin sums [o][R][a][b] (4 * n_cells * norb * norb host doubles, o = Green,
+ * SpinZ, SpinXY, Den) and the number of measurements summed (count, may be
+ * NULL).  Zeroed by dqmc_init, dqmc_reset_bins and dqmc_eq_setup. */
+dqmc_status dqmc_eq_read_bins(dqmc_ctx* ctx, double* sums_host, double* count);
 
 /* Per-launch timing of one kernel of the sweep, for roofline reports: while
  * enabled, launches of the selected kernel on the context's stream are

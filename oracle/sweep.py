@@ -59,6 +59,8 @@ class Chain:
         self.prec = []                    # max|G_wrapped - G_scratch| per stabilisation
         self.trace = None                 # optional per-event record
         self.min_tie = np.inf             # min |R - u| over all proposals
+        self.eq_lat = None                # lattice for the lattice-resolved correlations, if measured
+        self.eq_bins = None
 
     # -- setup (Algorithm 1: confin, then the wrapul fill) ----------------------
     def init(self):
@@ -122,6 +124,10 @@ class Chain:
         if measure:
             D, ekin, epot = equal_time(self.m, self.G)
             self.bins += np.array([D, ekin, epot, 1.0])
+            if self.eq_lat is not None:
+                from .measure import eq_correlations
+                c = eq_correlations(self.m, self.eq_lat, self.G)
+                self.eq_bins = c if self.eq_bins is None else self.eq_bins + c
 
     def _stabilise(self, G_s, G_cmp):
         self.prec.append(float(np.max(np.abs(G_cmp - G_s))))

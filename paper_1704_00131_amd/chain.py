@@ -76,9 +76,9 @@ class Chain:
         self._chk(self.lib.dqmc_init(self.ctx))
         return self
 
-    def sweep(self, n_sweeps=1, measure=True, time_displaced=False) -> Stats:
+    def sweep(self, n_sweeps=1, measure=True, time_displaced=False, correlations=False) -> Stats:
         st = Stats()
-        flags = (1 if measure else 0) | (2 if time_displaced else 0)
+        flags = (1 if measure else 0) | (2 if time_displaced else 0) | (4 if correlations else 0)
         self._chk(self.lib.dqmc_sweep(self.ctx, n_sweeps, flags, ctypes.byref(st)))
         return st
 
@@ -146,6 +146,27 @@ class Chain:
         cnt = ctypes.c_double()
         self._chk(self.lib.dqmc_td_read_bins(self.ctx, raw.ctypes.data, ctypes.byref(cnt)))
         return raw[..., 0] + 1j * raw[..., 1], cnt.value
+
+    def eq_setup(self, L1: int, L2: int, site, sign):
+        """Lattice of the lattice-resolved equal-time correlations: site [n_cells,
+        norb] the orbital index of each (cell, orbital), cells I = i1 + L1 i2;
+        sign [N] the sublattice signs (+1 / -1)."""
+        st = np.ascontiguousarray(site, dtype=np.int32)
+        sg = np.ascontiguousarray(sign, dtype=np.float64)
+        if st.ndim != 2 or sg.shape != (self.N,):
+            raise ValueError("site must be [n_cells, norb], sign [N]")
+        self.eq_shape = (st.shape[0], st.shape[1])
+        self._chk(self.lib.dqmc_eq_setup(self.ctx, int(L1), int(L2), st.shape[1], st.ctypes.data, sg.ctypes.data))
+        return self
+
+    def eq_read_bins(self):
+        """Bin sums [4, n_cells, norb, norb] (Green, SpinZ, SpinXY, Den) and the
+        number of measurements summed."""
+        nc, no = self.eq_shape
+        out = np.empty((4, nc, no, no))
+        cnt = ctypes.c_double()
+        self._chk(self.lib.dqmc_eq_read_bins(self.ctx, out.ctypes.data, ctypes.byref(cnt)))
+        return out, cnt.value
 
     def timing(self, kernel: str = "block_update", enable: bool = True, every: int = 1):
         """Bracket launches of one kernel with HIP events: every launch, or every

@@ -73,6 +73,11 @@ struct dqmc_ctx {
   double* kph = nullptr;
   int* korb = nullptr;
   int td_norb = 0, td_cells = 0;
+  // lattice-resolved equal-time correlations: the sublattice signs and the
+  // orbital of (cell, orbital) are shared, the bin sums per chain
+  double *eq_sign = nullptr, *eq_bins = nullptr;
+  int* eq_site = nullptr;
+  int eq_L1 = 0, eq_L2 = 0, eq_norb = 0;
   unsigned long long* counters = nullptr;   // proposals, accepted, sweep counter
   int* err_flag = nullptr;
   size_t work_doubles = 0;
@@ -118,6 +123,10 @@ dqmc_status fail(dqmc_ctx* c, dqmc_status s, const std::string& msg) {
       return fail(c, DQMC_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+constexpr int kEqMaxOrb = 4;   // orbitals per unit cell of the lattice-resolved correlations
+// Four correlators of N_cells * norb^2 entries each (at most 4 N kEqMaxOrb), then the count.
+inline size_t eq_bins_size(const dqmc_ctx* c) { return 4 * (size_t)c->N * kEqMaxOrb + 4; }
+
 // Shared part: the exponentials, K and the identity UDV (one copy for all
 // chains).  With base == nullptr only the size is computed and no pointer of
 // the context is touched.
@@ -132,6 +141,10 @@ size_t layout_shared(dqmc_ctx* c, double* base) {
   double* ko = nullptr;
   P(ko, N / 2 + 1);
   if (base) c->korb = reinterpret_cast<int*>(ko);
+  P(c->eq_sign, N);
+  double* es = nullptr;
+  P(es, N / 2 + 1);
+  if (base) c->eq_site = reinterpret_cast<int*>(es);
   if (base) { c->shared_lo = base; c->shared_hi = base + l.off; }
   return l.off;
 }
@@ -167,6 +180,7 @@ size_t layout_chain(dqmc_ctx* c, double* base) {
   P(c->tdbins, (size_t)(c->L + 1) * kTdStride + 4);
   P(c->tdpart, (size_t)((N + kTdRows - 1) / kTdRows) * kTdPart);
   P(c->a00, 2 * kTdMaxOrb);
+  P(c->eq_bins, eq_bins_size(c));
   double* ctr = nullptr;
   double* ef = nullptr;
   P(ctr, 4); P(ef, 1);
@@ -298,7 +312,7 @@ dqmc_status wrap_down(dqmc_ctx* c, int tau, double* dst) {
 
 // Sequential flips of slice tau, one fused launch per block of 32 sites; G
 // alternates between the two buffers, the field row moves to the other buffer.
-dqmc_status update_slice(dqmc_ctx* c, int tau, int dir) {
+dqmc_status update_slice(dqmc_ctx* c, int tau) {
   const int N = c->N;
   const double* fin = field_row(c, tau);
   c->row_alt[tau - 1] ^= 1;
@@ -597,6 +611,24 @@ dqmc_status measure(dqmc_ctx* c) {
   return DQMC_OK;
 }
 
+// Lattice-resolved equal-time correlations of the current configuration,
+// added to the bins, from G~ = e^{-dtau K/2} G e^{+dtau K/2} (symmetric split)
+// or G (asymmetric split).
+dqmc_status eq_measure(dqmc_ctx* c) {
+  const int N = c->N;
+  const double* Gt = c->Gcur;
+  if (c->m.trotter == DQMC_TROTTER_SYM) {
+    if (dqmc_status s = gemm(c, gemm_args(N, N, N, c->Eh, N, 0, c->Gcur, N, 0, c->T1, N))) return s;
+    if (dqmc_status s = gemm(c, gemm_args(N, N, N, c->T1, N, 0, c->Ehinv, N, 0, c->Gs, N))) return s;
+    Gt = c->Gs;
+  }
+  const int nb = c->eq_L1 * c->eq_L2 * c->eq_norb * c->eq_norb;
+  hipLaunchKernelGGL(k_eq_corr, gridc(c, grid1((size_t)nb + 1, 4)), dim3(256), 0, c->stream, Gt, N, c->eq_L1, c->eq_L2,
+                     c->eq_norb, c->eq_site, c->eq_sign, c->eq_bins, c->cs);
+  HIPCHK(hipGetLastError());
+  return DQMC_OK;
+}
+
 // The four-valued field's values eta(l) and log gamma(l), l = -2, -1, +1, +2
 // (Eq. (HS_squares)), computed on the host.
 Field4 field4_table() {
@@ -633,7 +665,8 @@ dqmc_status pass_draws(dqmc_ctx* c, int dir) {
 
 // One sweep (Algorithm 1): upward pass tau = 1..L, downward pass tau = L..1.
 // meas: bit 0 = equal-time estimators on every slice, bit 1 = the
-// time-displaced pass at the start of the sweep.
+// time-displaced pass at the start of the sweep, bit 2 = the lattice-resolved
+// equal-time correlations on every slice.
 dqmc_status td_pass(dqmc_ctx* c);
 dqmc_status sweep_once(dqmc_ctx* c, int meas) {
   const int L = c->L, nw = c->nw, nk = c->nk;
@@ -645,7 +678,7 @@ dqmc_status sweep_once(dqmc_ctx* c, int meas) {
   if (dqmc_status s = pass_draws(c, 0)) return s;
   for (int tau = 1; tau <= L; ++tau) {
     if (dqmc_status s = wrap_up(c, tau, c->G)) return s;
-    if (dqmc_status s = update_slice(c, tau, 0)) return s;
+    if (dqmc_status s = update_slice(c, tau)) return s;
     if (tau % nw == 0) {
       const int k = tau / nw;
       UDVp prev = (k == 1) ? c->uid : c->slot(k - 1);
@@ -657,12 +690,16 @@ dqmc_status sweep_once(dqmc_ctx* c, int meas) {
     }
     if (meas & 1)
       if (dqmc_status s = measure(c)) return s;
+    if (meas & 4)
+      if (dqmc_status s = eq_measure(c)) return s;
   }
   if (dqmc_status s = pass_draws(c, 1)) return s;
   for (int tau = L; tau >= 1; --tau) {
-    if (dqmc_status s = update_slice(c, tau, 1)) return s;
+    if (dqmc_status s = update_slice(c, tau)) return s;
     if (meas & 1)
       if (dqmc_status s = measure(c)) return s;
+    if (meas & 4)
+      if (dqmc_status s = eq_measure(c)) return s;
     if ((tau - 1) % nw == 0) {
       const int k = (tau - 1) / nw;
       // wrapped G(tau-1), compared against the recomputed one below
@@ -1086,6 +1123,7 @@ dqmc_status dqmc_init(dqmc_ctx* c) {
   // statistics, bins, flag
   if (dqmc_status s = fill_small(c, c->bins, 4, 0.0)) return s;
   if (dqmc_status s = fill_small(c, c->tdbins, (size_t)(c->L + 1) * kTdStride + 4, 0.0)) return s;
+  if (dqmc_status s = fill_small(c, c->eq_bins, eq_bins_size(c), 0.0)) return s;
   if (dqmc_status s = fill_small(c, c->prec_hist, 2 * (size_t)c->nk + 2, 0.0)) return s;
   if (dqmc_status s = fill_small(c, c->prec_tot, 4, 0.0)) return s;
   if (dqmc_status s = fill_small(c, reinterpret_cast<double*>(c->counters), 2, 0.0)) return s;
@@ -1100,8 +1138,9 @@ dqmc_status dqmc_init(dqmc_ctx* c) {
 dqmc_status dqmc_sweep(dqmc_ctx* c, int32_t n_sweeps, int32_t meas, dqmc_stats* st) {
   if (!c || n_sweeps < 0) return fail(c, DQMC_E_ARG, "bad arguments");
   if (!c->bound || !c->initialized || c->poisoned) return fail(c, DQMC_E_STATE, "context not initialised");
-  if (meas & ~3) return fail(c, DQMC_E_ARG, "unknown measurement flags");
+  if (meas & ~7) return fail(c, DQMC_E_ARG, "unknown measurement flags");
   if ((meas & 2) && c->td_norb < 1) return fail(c, DQMC_E_STATE, "time-displaced measurement not set up");
+  if ((meas & 4) && c->eq_norb < 1) return fail(c, DQMC_E_STATE, "lattice-resolved correlations not set up");
   const auto t0 = std::chrono::steady_clock::now();
   for (int s = 0; s < n_sweeps; ++s)
     if (dqmc_status r = sweep_once(c, meas)) return r;
@@ -1127,6 +1166,7 @@ dqmc_status dqmc_reset_bins(dqmc_ctx* c) {
   if (!c->bound) return fail(c, DQMC_E_STATE, "not bound");
   if (dqmc_status s = fill_small(c, c->bins, 4, 0.0)) return s;
   if (dqmc_status s = fill_small(c, c->tdbins, (size_t)(c->L + 1) * kTdStride + 4, 0.0)) return s;
+  if (dqmc_status s = fill_small(c, c->eq_bins, eq_bins_size(c), 0.0)) return s;
   HIPCHK(hipStreamSynchronize(c->stream));
   return DQMC_OK;
 }
@@ -1229,6 +1269,39 @@ dqmc_status dqmc_td_setup(dqmc_ctx* c, int32_t norb, const int32_t* orb_of, cons
   HIPCHK(hipStreamSynchronize(c->stream));
   c->td_norb = norb;
   c->td_cells = n_cells;
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_eq_setup(dqmc_ctx* c, int32_t L1, int32_t L2, int32_t norb, const int32_t* site, const double* sign) {
+  if (!c || !site || !sign || L1 < 1 || L2 < 1 || norb < 1 || norb > kEqMaxOrb)
+    return fail(c, DQMC_E_ARG, "bad arguments");
+  if (!c->bound) return fail(c, DQMC_E_STATE, "not bound");
+  if ((int64_t)L1 * L2 * norb != c->N) return fail(c, DQMC_E_ARG, "L1 * L2 * norb must equal the number of orbitals");
+  std::vector<char> seen(c->N, 0);
+  for (int i = 0; i < c->N; ++i) {
+    if (site[i] < 0 || site[i] >= c->N || seen[site[i]]) return fail(c, DQMC_E_ARG, "site map is not a permutation");
+    seen[site[i]] = 1;
+    if (sign[i] != 1.0 && sign[i] != -1.0) return fail(c, DQMC_E_ARG, "sublattice signs must be +1 or -1");
+  }
+  HIPCHK(hipMemcpyAsync(c->eq_sign, sign, sizeof(double) * c->N, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->eq_site, site, sizeof(int32_t) * c->N, hipMemcpyHostToDevice, c->stream));
+  if (dqmc_status s = fill_small(c, c->eq_bins, eq_bins_size(c), 0.0)) return s;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->eq_L1 = L1;
+  c->eq_L2 = L2;
+  c->eq_norb = norb;
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_eq_read_bins(dqmc_ctx* c, double* sums_host, double* count) {
+  if (!c || !sums_host) return DQMC_E_ARG;
+  if (!c->bound || c->eq_norb < 1) return fail(c, DQMC_E_STATE, "lattice-resolved correlations not set up");
+  const size_t nb = (size_t)c->eq_L1 * c->eq_L2 * c->eq_norb * c->eq_norb;
+  std::vector<double> raw(4 * nb + 1);
+  HIPCHK(hipMemcpyAsync(raw.data(), c->eq_bins, raw.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  std::copy(raw.begin(), raw.begin() + 4 * nb, sums_host);
+  if (count) *count = raw.back();
   return DQMC_OK;
 }
 
@@ -1419,7 +1492,8 @@ bool layout_ok(const dqmc_ctx* c, const double* lo, const double* hi) {
        in(c->tdS, (size_t)(c->L + 1) * kTdStride, true) &&
        in(c->tdbins, (size_t)(c->L + 1) * kTdStride + 4, true) &&
        in(c->tdpart, (size_t)((N + kTdRows - 1) / kTdRows) * kTdPart, true) && in(c->a00, 2 * kTdMaxOrb, true) &&
-       in(c->kph, 2 * N, false) && in(c->korb, N / 2 + 1, false) &&
+       in(c->kph, 2 * N, false) && in(c->korb, N / 2 + 1, false) && in(c->eq_sign, N, false) &&
+       in(c->eq_site, N / 2 + 1, false) && in(c->eq_bins, eq_bins_size(c), true) &&
        in(c->counters, 4, true) && in(c->err_flag, 1, true);
   return ok;
 }

@@ -414,6 +414,63 @@ __global__ __launch_bounds__(256) void k_measure_part(const double* G, const dou
   }
 }
 
+// Lattice-resolved equal-time correlations (section "Observables": equal-time
+// correlation functions summed over unit cells, stored by the displacement R
+// between them), accumulated per measurement from the measured G~ (Gt):
+//   bins[o][R][a][b] += 1/N_cells sum_I O(site(I, a), site(I + R, b)),
+// o = Green, SpinZ, SpinXY, Den, with both particle-hole species carrying the
+// same G (G_ij = <c_i c_j^+>) and s the sublattice signs of the down-spin map:
+//   Green  = 1/2 (d_ij - G_ji + s_i s_j G_ij)
+//   SpinZ  = 1/4 ((1 - 2 G_ii)(1 - 2 G_jj) + 2 (d_ij - G_ji) G_ij)
+//   SpinXY = 1/4 s_i s_j ((d_ij - G_ji)^2 + G_ij^2)      (half of S^x S^x + S^y S^y)
+//   Den    = 1 + 2 (d_ij - G_ji) G_ij.
+// One wavefront per (R, a, b): its lanes take the cells I = lane, lane + 64, ...
+// and a butterfly reduction sums them (four waves per workgroup, so N_cells
+// norb^2 / 4 workgroups); the wave of entry nb adds the count.
+// site[I * norb + a] is the orbital index of orbital a of cell I (a permutation
+// of 0..N-1, checked on the host); cells are I = i1 + L1 i2.
+__global__ __launch_bounds__(256) void k_eq_corr(const double* Gt, int N, int L1, int L2, int norb, const int* site,
+                                                 const double* sgn, double* bins, size_t cs) {
+  Gt += (size_t)blockIdx.y * cs;
+  bins += (size_t)blockIdx.y * cs;
+  const int nc = L1 * L2, nb = nc * norb * norb;
+  const int lane = threadIdx.x & 63;
+  const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (e > nb) return;
+  if (e == nb) {
+    if (lane == 0) bins[4 * (size_t)nb] += 1.0;
+    return;
+  }
+  const int R = e / (norb * norb), a = (e / norb) % norb, b = e % norb;
+  const int r1 = R % L1, r2 = R / L1;
+  double g = 0.0, z = 0.0, xy = 0.0, dn = 0.0;
+  for (int I = lane; I < nc; I += 64) {
+    const int i1 = I % L1, i2 = I / L1;
+    const int J = (i1 + r1) % L1 + L1 * ((i2 + r2) % L2);
+    const int i = site[I * norb + a], j = site[J * norb + b];
+    const double d = (i == j) ? 1.0 : 0.0;
+    const double gij = Gt[(size_t)i * N + j], gji = Gt[(size_t)j * N + i];
+    const double gii = Gt[(size_t)i * N + i], gjj = Gt[(size_t)j * N + j];
+    const double ss = sgn[i] * sgn[j];
+    g += 0.5 * (d - gji + ss * gij);
+    z += 0.25 * ((1.0 - 2.0 * gii) * (1.0 - 2.0 * gjj) + 2.0 * (d - gji) * gij);
+    xy += 0.25 * ss * ((d - gji) * (d - gji) + gij * gij);
+    dn += 1.0 + 2.0 * (d - gji) * gij;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    g += __shfl_xor(g, off, 64);
+    z += __shfl_xor(z, off, 64);
+    xy += __shfl_xor(xy, off, 64);
+    dn += __shfl_xor(dn, off, 64);
+  }
+  if (lane == 0) {
+    bins[e] += g / nc;
+    bins[(size_t)nb + e] += z / nc;
+    bins[2 * (size_t)nb + e] += xy / nc;
+    bins[3 * (size_t)nb + e] += dn / nc;
+  }
+}
+
 // Weight ratio of one proposed change s -> s_new at a site, from G(tau) (the
 // same formulas as the sweep's decisions); one thread.
 __global__ void k_ratio(const double* G, int N, int site, const double* field_row, double s_new, double coupling,

@@ -1,0 +1,74 @@
+"""Parity of the lattice-resolved equal-time correlations (Green, SpinZ,
+SpinXY, Den by displacement R and orbital pair) accumulated on the device
+during sweeps with the oracle's, on the same trajectory: 1e-9 relative to the
+number of measurements summed; bit-exact count."""
+import numpy as np
+import pytest
+
+from gpu_util import maxabs, pair
+from oracle import sweep as osweep
+from paper_1704_00131_amd._lib import DQMCError
+
+pytestmark = pytest.mark.gpu
+
+DQMC_E_ARG, DQMC_E_STATE = 1, 6
+
+
+def _site(lat):
+    site = -np.ones((lat.n_cells, lat.norb), dtype=np.int32)
+    site[lat.cell_of, lat.orb_of] = np.arange(lat.n)
+    return site
+
+
+@pytest.mark.parametrize("kind,L1,L2,beta,trotter,seed,sweeps", [
+    ("square", 4, 4, 2.0, "sym", 3, 3),
+    ("honeycomb", 6, 6, 2.0, "asym", 1, 1),     # N = 72: a ragged last block
+    ("honeycomb", 3, 3, 2.0, "sym", 2, 2),
+])
+def test_eq_correlation_bins_match_oracle(kind, L1, L2, beta, trotter, seed, sweeps):
+    print(f"correlations {kind} {L1}x{L2} {trotter} seed {seed}", flush=True)
+    om, ch, lat = pair(kind, L1, L2, 4.0, beta, 0.1, 10, trotter=trotter, seed=seed)
+    ch.random_field().init()
+    ch.eq_setup(L1, L2, _site(lat), lat.sublattice_sign())
+    f0, _ = ch.get_state()
+    oc = osweep.Chain(om, f0).init()
+    oc.eq_lat = lat
+    for s in range(sweeps):
+        ch.sweep(1, measure=True, correlations=True)
+        oc.sweep(measure=True)
+        assert oc.min_tie > 1e-9, "near-tie in the oracle's decisions; pick another seed"
+        f, _ = ch.get_state()
+        assert np.array_equal(f, oc.field), f"field differs after sweep {s}"
+    got, cnt = ch.eq_read_bins()
+    n_meas = 2 * om.L * sweeps
+    assert cnt == n_meas == oc.bins[3]
+    assert maxabs(got, oc.eq_bins) < 1e-9 * n_meas
+    assert np.all(np.isfinite(got))
+    # bins restart from zero
+    ch.reset_bins()
+    z, c0 = ch.eq_read_bins()
+    assert c0 == 0.0 and not np.any(z)
+
+
+def test_eq_setup_rejects_bad_maps():
+    om, ch, lat = pair("square", 4, 4, 4.0, 1.0, 0.1, 5, seed=0)
+    ch.random_field().init()
+    with pytest.raises(DQMCError) as e:
+        ch.sweep(1, correlations=True)
+    assert e.value.status == DQMC_E_STATE
+    site = _site(lat)
+    bad = site.copy()
+    bad[0, 0] = bad[1, 0]
+    with pytest.raises(DQMCError) as e:
+        ch.eq_setup(4, 4, bad, lat.sublattice_sign())
+    assert e.value.status == DQMC_E_ARG
+    with pytest.raises(DQMCError) as e:
+        ch.eq_setup(4, 4, site, 0.5 * lat.sublattice_sign())
+    assert e.value.status == DQMC_E_ARG
+    with pytest.raises(DQMCError) as e:
+        ch.eq_setup(2, 4, site, lat.sublattice_sign())
+    assert e.value.status == DQMC_E_ARG
+    ch.eq_setup(4, 4, site, lat.sublattice_sign())
+    ch.sweep(1, correlations=True)
+    _, cnt = ch.eq_read_bins()
+    assert cnt == 2 * om.L
