@@ -67,3 +67,18 @@ def enumerate_eq_correlations(model, lat, tau=0):
     logw = np.array(logw)
     w = np.exp(logw - logw.max())
     return np.einsum("c,c...->...", w, np.array(obs)) / w.sum()
+
+
+def enumerate_td_correlations(model, lat, taus):
+    """Exact weighted average of the time-displaced lattice-resolved
+    correlations (timedisplaced.td_correlations) at each tau in taus:
+    [len(taus), 4, N_cells, norb, norb]."""
+    from .timedisplaced import tdgf_correlations
+    logw = []
+    obs = []
+    for f in all_fields(model):
+        logw.append(log_weight(model, f))
+        obs.append(tdgf_correlations(model, lat, f, taus))
+    logw = np.array(logw)
+    w = np.exp(logw - logw.max())
+    return np.einsum("c,c...->...", w, np.array(obs)) / w.sum()

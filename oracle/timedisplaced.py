@@ -89,6 +89,60 @@ def szsz_k(model, lat, kvec, GT0, G0T, GTT, G00):
     return S / lat.n_cells
 
 
+def td_correlations(model, lat, GT0, G0T, GTT, G00):
+    """Time-displaced correlation functions on the Bravais lattice (section
+    "Observables": correlations summed over unit cells and stored by the
+    displacement R; section "Measuring time displaced observables" for the
+    time-displaced Green's functions), one configuration at one tau:
+
+        C_o[R, a, b] = 1/N_cells sum_I <O_i(tau) O_j(0)>,  i = site(I, a), j = site(I + R, b),
+
+    o = Green, SpinZ, SpinXY, Den.  Wick's theorem per sampling-frame colour,
+    both colours carrying the same Green's functions and the down spin the
+    particle-hole image c_{i,dn} = s_i c'^+_i (s the sublattice sign), with
+    <c^+_i(tau) c_j(0)> = -G0T_ji and <c_i(tau) c^+_j(0)> = GT0_ij:
+        Green  1/2 sum_s <c^+_{i s}(tau) c_{j s}(0)>  = 1/2 (-G0T_ji + s_i s_j GT0_ij)
+        SpinZ  <S^z_i(tau) S^z_j(0)>                  = 1/4 ((1 - 2 GTT_ii)(1 - 2 G00_jj) - 2 G0T_ji GT0_ij)
+        SpinXY 1/2 <S^x_i S^x_j + S^y_i S^y_j>(tau)   = 1/4 s_i s_j (G0T_ji^2 + GT0_ij^2)
+        Den    <n_i(tau) n_j(0)>                      = 1 - 2 G0T_ji GT0_ij.
+    At tau = 0 (GT0 = G, G0T = G - 1) these are the equal-time estimators.
+    With the symmetric split all four are rotated as the equal-time G.
+    Returns [4, N_cells, norb, norb]."""
+    GT0, G0T, GTT, G00 = (_rotate(model, M) for M in (GT0, G0T, GTT, G00))
+    L1, L2, norb = lat.L1, lat.L2, lat.norb
+    nc = L1 * L2
+    s = lat.sublattice_sign()
+    site = -np.ones((nc, norb), dtype=int)
+    for i in range(model.N):
+        site[lat.cell_of[i], lat.orb_of[i]] = i
+    out = np.zeros((4, nc, norb, norb))
+    for I in range(nc):
+        i1, i2 = I % L1, I // L1
+        for R in range(nc):
+            J = (i1 + R % L1) % L1 + L1 * ((i2 + R // L1) % L2)
+            for a in range(norb):
+                for b in range(norb):
+                    i, j = site[I, a], site[J, b]
+                    h, g = G0T[j, i], GT0[i, j]
+                    out[0, R, a, b] += 0.5 * (-h + s[i] * s[j] * g)
+                    out[1, R, a, b] += 0.25 * ((1.0 - 2.0 * GTT[i, i]) * (1.0 - 2.0 * G00[j, j]) - 2.0 * h * g)
+                    out[2, R, a, b] += 0.25 * s[i] * s[j] * (h * h + g * g)
+                    out[3, R, a, b] += 1.0 - 2.0 * h * g
+    return out / nc
+
+
+def tdgf_correlations(model, lat, field, taus=None):
+    """td_correlations for tau in taus (default 0..L) of one configuration,
+    every tau from scratch: [len(taus), 4, N_cells, norb, norb]."""
+    taus = range(model.L + 1) if taus is None else taus
+    _, _, G00 = tdgf_scratch(model, field, 0)
+    out = []
+    for tau in taus:
+        GT0, G0T, GTT = tdgf_scratch(model, field, tau)
+        out.append(td_correlations(model, lat, GT0, G0T, GTT, G00))
+    return np.array(out)
+
+
 def tdgf_measure(model, lat, kvec, field, taus=None):
     """S_ab(K, tau) for tau in taus (default 0..L) of one configuration, every
     tau evaluated from scratch."""

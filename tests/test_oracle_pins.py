@@ -512,3 +512,62 @@ def test_eq_correlations_enumeration_equals_fock(trotter):
     finally:
         lat.sublattice_sign = s_saved
     assert np.max(np.abs(bad[0] - want[0])) > 1e-3
+
+
+@pytest.mark.parametrize("trotter", ["sym", "asym"])
+def test_td_correlations_enumeration_equals_fock(trotter):
+    """Time-displaced lattice-resolved correlations (Green, SpinZ, SpinXY, Den
+    by displacement and orbital pair) of a 4-site honeycomb ring (2 cells x 2
+    orbitals) x 2 slices at tau = 0, 1, 2 slices: the exact weighted average of
+    the per-configuration estimators against Tr(S^(L-n) A_i S^n B_j) / Tr(S^L)
+    in Fock space, with A, B built from the original-frame fermions."""
+    from oracle import exact_small
+    from oracle import timedisplaced as otd
+    lat = honeycomb_lattice(1, 2)
+    U, dtau, L = 4.0, 0.25, 2
+    m = hubbard.hubbard_model(lat.K, U, L * dtau, dtau, 1, trotter=trotter)
+    taus = (0, 1, 2)
+    got = exact_small.enumerate_td_correlations(m, lat, taus)
+    F = Fock(lat.K, U)
+    S = F.trotter(dtau) if trotter == "sym" else F.trotter_asym(dtau)
+    c = F.c
+
+    def pairs(i, j):
+        sp_i, sp_j = c[2 * i].T @ c[2 * i + 1], c[2 * j].T @ c[2 * j + 1]
+        n_i, n_j = F.n[i][0] + F.n[i][1], F.n[j][0] + F.n[j][1]
+        return ([(0.5, c[2 * i + s].T, c[2 * j + s]) for s in (0, 1)],
+                [(1.0, F.sz(i), F.sz(j))],
+                [(0.25, sp_i, sp_j.T), (0.25, sp_i.T, sp_j)],
+                [(1.0, n_i, n_j)])
+
+    nc, norb = lat.n_cells, lat.norb
+    site = {(int(lat.cell_of[i]), int(lat.orb_of[i])): i for i in range(lat.n)}
+    want = np.zeros((len(taus), 4, nc, norb, norb))
+    for t, n in enumerate(taus):
+        for I in range(nc):
+            i1, i2 = I % lat.L1, I // lat.L1
+            for R in range(nc):
+                J = (i1 + R % lat.L1) % lat.L1 + lat.L1 * ((i2 + R // lat.L1) % lat.L2)
+                for a in range(norb):
+                    for b in range(norb):
+                        for o, terms in enumerate(pairs(site[I, a], site[J, b])):
+                            for w, A, B in terms:
+                                want[t, o, R, a, b] += w * F.expect_tau_with(S, A, B, L, n) / nc
+    assert np.max(np.abs(got - want)) < 1e-12, (trotter, np.max(np.abs(got - want), axis=(2, 3, 4)))
+    # SU(2) on average; tau = 0 is the equal-time estimator; the Fourier sum of
+    # SpinZ at K is the momentum-space estimator of the pass
+    assert np.max(np.abs(got[:, 1] - got[:, 2])) < 1e-12
+    assert np.max(np.abs(got[0] - exact_small.enumerate_eq_correlations(m, lat, tau=0))) < 1e-12
+    g1, g2 = lat.reciprocal()
+    kvec = 0.5 * g2
+    rpos = np.array([(R % lat.L1) * lat.a1 + (R // lat.L1) * lat.a2 for R in range(nc)])
+    sk = np.einsum("r,trab->tab", np.exp(1j * (rpos @ kvec)), got[:, 1])
+    assert np.max(np.abs(sk - exact_small.enumerate_szsz(m, lat, kvec, taus))) < 1e-12
+    # a planted mistake in the oracle (G0T transposed) fails it
+    saved = otd.tdgf_scratch
+    try:
+        otd.tdgf_scratch = lambda model, f, tau: (lambda r: (r[0], r[1].T, r[2]))(saved(model, f, tau))
+        bad = exact_small.enumerate_td_correlations(m, lat, taus)
+    finally:
+        otd.tdgf_scratch = saved
+    assert np.max(np.abs(bad[1:] - want[1:])) > 1e-3
