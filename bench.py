@@ -152,8 +152,9 @@ def bench_gradient(torch, pa):
 
 def bench_time_displaced(torch, pa):
     """Honeycomb 18x18 (N = 648), U = 5, beta = 20, L = 200, n_wrap = 10: one
-    time-displaced pass (S^z-S^z at K = (4 pi / 3, 0) for all tau) and one
-    sweep with it."""
+    time-displaced pass (S^z-S^z at K = (4 pi / 3, 0) for all tau), one sweep
+    with it, and one sweep with it and the lattice-resolved time-displaced
+    correlations (all displacements, all tau)."""
     import numpy as np
     from inputs import WORKLOADS
     w = WORKLOADS["honeycomb18_U5_b20"]
@@ -170,11 +171,16 @@ def bench_time_displaced(torch, pa):
     ms, launches, flops = ch.timing_read()
     ch.timing("gemm", False)
     dts, st = _sync_time(torch, lambda: ch.sweep(1, measure=True, time_displaced=True))
+    site = np.full((lat.n_cells, lat.norb), -1, dtype=np.int32)
+    site[lat.cell_of, lat.orb_of] = np.arange(lat.n)
+    ch.eq_setup(lat.L1, lat.L2, site, lat.sublattice_sign())
+    dtc, _ = _sync_time(torch, lambda: ch.sweep(1, measure=True, time_displaced=True, td_correlations=True))
     ch.close()
     tf = flops / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
     return {"N": lat.n, "L": w.n_slices, "td_pass_s": dt, "td_prec": list(prec),
             "gemm_tflops": tf, "gemm_frac_of_fp64_mfma_peak": tf / 78.6, "gemm_share_of_pass": ms * 1e-3 / dt,
-            "sweep_with_td_s": dts, "updates_per_s": st.proposals / dts}
+            "sweep_with_td_s": dts, "updates_per_s": st.proposals / dts,
+            "sweep_with_td_and_lattice_correlations_s": dtc}
 
 
 def bench_four_valued(torch, pa):

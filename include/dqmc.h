@@ -130,7 +130,9 @@ dqmc_status dqmc_init(dqmc_ctx* ctx);
  * (dqmc_td_measure, needs dqmc_td_setup) at the start of every sweep, as the
  * paper does for its time-displaced observables; bit 2 accumulates the
  * lattice-resolved equal-time correlations (needs dqmc_eq_setup) on every
- * slice of both passes.  Other bits: DQMC_E_ARG.  stats may be NULL.
+ * slice of both passes; bit 3 adds the lattice-resolved time-displaced
+ * correlations to the pass of bit 1 (needs bit 1, dqmc_eq_setup and a single
+ * chain, else DQMC_E_STATE).  Other bits: DQMC_E_ARG.  stats may be NULL.
  * DQMC_E_NUMERIC if the device flagged a numerical failure; the context then
  * needs dqmc_init. */
 dqmc_status dqmc_sweep(dqmc_ctx* ctx, int32_t n_sweeps, int32_t measure, dqmc_stats* stats);
@@ -227,6 +229,19 @@ dqmc_status dqmc_eq_setup(dqmc_ctx* ctx, int32_t L1, int32_t L2, int32_t norb, c
  * SpinZ, SpinXY, Den) and the number of measurements summed (count, may be
  * NULL).  Zeroed by dqmc_init, dqmc_reset_bins and dqmc_eq_setup. */
 dqmc_status dqmc_eq_read_bins(dqmc_ctx* ctx, double* sums_host, double* count);
+/* The same four correlators between tau and 0, from the time-displaced pass
+ * (section "Measuring time displaced observables"), per configuration
+ *   C_o[tau][R][a][b] += 1/n_cells sum_I <O_i(tau) O_j(0)>,  i = site(I, a), j = site(I + R, b),
+ * with h = G0T_ji, g = GT0_ij:
+ *   Green  = 1/2 (-h + s_i s_j g)
+ *   SpinZ  = 1/4 ((1 - 2 GTT_ii)(1 - 2 G00_jj) - 2 h g)
+ *   SpinXY = 1/4 s_i s_j (h^2 + g^2)
+ *   Den    = 1 - 2 h g
+ * (the equal-time ones at tau = 0).  Accumulated by sweeps with bits 1 and 3.
+ * Bin sums [tau][o][R][a][b] ((L+1) * 4 * n_cells * norb * norb host doubles)
+ * and the number of passes summed (count, may be NULL).  Zeroed by dqmc_init,
+ * dqmc_reset_bins and dqmc_eq_setup.  DQMC_E_STATE without dqmc_eq_setup. */
+dqmc_status dqmc_td_read_corr_bins(dqmc_ctx* ctx, double* sums_host, double* count);
 
 /* Per-launch timing of one kernel of the sweep, for roofline reports: while
  * enabled, launches of the selected kernel on the context's stream are

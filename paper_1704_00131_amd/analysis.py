@@ -13,7 +13,11 @@ gives one row per bin.  Everything here works on such host arrays, shape
 - autocorrelation(x, n) the normalised autocorrelation function of the bin
                         series for lags 0..n (N_auto);
 - covariance(x)         the covariance of the bin means of a vector
-                        observable, e.g. S(k, tau) over tau (N_Cov).
+                        observable, e.g. S(k, tau) over tau (N_Cov);
+- momentum_grid(lat)    the L1 x L2 momenta of the Bravais torus;
+- to_momentum(C, lat, k) a correlation stored by displacement R (the
+                        lattice-resolved bins) at momenta k:
+                        C(k) = sum_R exp(i k.R) C(R).
 """
 from typing import Callable, Sequence, Tuple
 
@@ -86,3 +90,29 @@ def error_vs_rebin(x, sizes: Sequence[int]) -> np.ndarray:
     effective bins are shorter than the autocorrelation time and levels off
     beyond it."""
     return np.array([jackknife(lambda a: a, rebin(x, s))[1] for s in sizes])
+
+
+def displacements(lat) -> np.ndarray:
+    """[N_cells, 2] positions R = r1 a1 + r2 a2 of the displacement index
+    r1 + L1 r2 used by the lattice-resolved bins."""
+    idx = np.arange(lat.L1 * lat.L2)
+    return np.outer(idx % lat.L1, lat.a1) + np.outer(idx // lat.L1, lat.a2)
+
+
+def momentum_grid(lat) -> np.ndarray:
+    """[N_cells, 2] momenta k = (m1/L1) g1 + (m2/L2) g2 of the torus, m1 + L1 m2
+    ordered like the displacements (g1, g2 the reciprocal vectors)."""
+    g1, g2 = lat.reciprocal()
+    idx = np.arange(lat.L1 * lat.L2)
+    return np.outer((idx % lat.L1) / lat.L1, g1) + np.outer((idx // lat.L1) / lat.L2, g2)
+
+
+def to_momentum(C, lat, kvecs) -> np.ndarray:
+    """C(k)[..., a, b] = sum_R exp(i k.R) C[..., R, a, b] for each k in kvecs
+    ([n_k, 2]): the Fourier transform of a correlation stored by displacement,
+    C(R) = 1/N_cells sum_I <O_{I,a} O_{I+R,b}>; its sign convention makes C(k)
+    at a torus momentum equal to 1/N_cells sum_{I,J} exp(-i k.(R_I - R_J))
+    <O_{I,a} O_{J,b}>.  Returns [..., n_k, norb, norb] complex."""
+    C = np.asarray(C, dtype=np.float64)
+    ph = np.exp(1j * (np.asarray(kvecs, dtype=np.float64).reshape(-1, 2) @ displacements(lat).T))   # [k, R]
+    return np.einsum("kr,...rab->...kab", ph, C)

@@ -76,9 +76,11 @@ class Chain:
         self._chk(self.lib.dqmc_init(self.ctx))
         return self
 
-    def sweep(self, n_sweeps=1, measure=True, time_displaced=False, correlations=False) -> Stats:
+    def sweep(self, n_sweeps=1, measure=True, time_displaced=False, correlations=False,
+              td_correlations=False) -> Stats:
         st = Stats()
-        flags = (1 if measure else 0) | (2 if time_displaced else 0) | (4 if correlations else 0)
+        flags = ((1 if measure else 0) | (2 if time_displaced else 0) | (4 if correlations else 0)
+                 | (8 if td_correlations else 0))
         self._chk(self.lib.dqmc_sweep(self.ctx, n_sweeps, flags, ctypes.byref(st)))
         return st
 
@@ -166,6 +168,15 @@ class Chain:
         out = np.empty((4, nc, no, no))
         cnt = ctypes.c_double()
         self._chk(self.lib.dqmc_eq_read_bins(self.ctx, out.ctypes.data, ctypes.byref(cnt)))
+        return out, cnt.value
+
+    def td_read_corr_bins(self):
+        """Bin sums [L+1, 4, n_cells, norb, norb] of the lattice-resolved
+        time-displaced correlations and the number of passes summed."""
+        nc, no = self.eq_shape
+        out = np.empty((self.L + 1, 4, nc, no, no))
+        cnt = ctypes.c_double()
+        self._chk(self.lib.dqmc_td_read_corr_bins(self.ctx, out.ctypes.data, ctypes.byref(cnt)))
         return out, cnt.value
 
     def timing(self, kernel: str = "block_update", enable: bool = True, every: int = 1):

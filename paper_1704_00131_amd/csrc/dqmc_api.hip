@@ -78,6 +78,11 @@ struct dqmc_ctx {
   double *eq_sign = nullptr, *eq_bins = nullptr;
   int* eq_site = nullptr;
   int eq_L1 = 0, eq_L2 = 0, eq_norb = 0;
+  // the same correlations between tau and 0 in the time-displaced pass (single
+  // chains only): [L+1] blocks of td_corr_stride doubles, then the count, and
+  // the diagonal of G00
+  double *td_corr = nullptr, *td_g00 = nullptr;
+  bool td_corr_now = false;
   unsigned long long* counters = nullptr;   // proposals, accepted, sweep counter
   int* err_flag = nullptr;
   size_t work_doubles = 0;
@@ -126,6 +131,10 @@ dqmc_status fail(dqmc_ctx* c, dqmc_status s, const std::string& msg) {
 constexpr int kEqMaxOrb = 4;   // orbitals per unit cell of the lattice-resolved correlations
 // Four correlators of N_cells * norb^2 entries each (at most 4 N kEqMaxOrb), then the count.
 inline size_t eq_bins_size(const dqmc_ctx* c) { return 4 * (size_t)c->N * kEqMaxOrb + 4; }
+inline size_t td_corr_stride(const dqmc_ctx* c) { return 4 * (size_t)c->N * kEqMaxOrb; }
+inline size_t td_corr_size(const dqmc_ctx* c) {
+  return c->nch == 1 ? (size_t)(c->L + 1) * td_corr_stride(c) + 4 : 0;
+}
 
 // Shared part: the exponentials, K and the identity UDV (one copy for all
 // chains).  With base == nullptr only the size is computed and no pointer of
@@ -181,6 +190,8 @@ size_t layout_chain(dqmc_ctx* c, double* base) {
   P(c->tdpart, (size_t)((N + kTdRows - 1) / kTdRows) * kTdPart);
   P(c->a00, 2 * kTdMaxOrb);
   P(c->eq_bins, eq_bins_size(c));
+  P(c->td_g00, N);
+  P(c->td_corr, td_corr_size(c));
   double* ctr = nullptr;
   double* ef = nullptr;
   P(ctr, 4); P(ef, 1);
@@ -623,8 +634,9 @@ dqmc_status eq_measure(dqmc_ctx* c) {
     Gt = c->Gs;
   }
   const int nb = c->eq_L1 * c->eq_L2 * c->eq_norb * c->eq_norb;
-  hipLaunchKernelGGL(k_eq_corr, gridc(c, grid1((size_t)nb + 1, 4)), dim3(256), 0, c->stream, Gt, N, c->eq_L1, c->eq_L2,
-                     c->eq_norb, c->eq_site, c->eq_sign, c->eq_bins, c->cs);
+  hipLaunchKernelGGL(k_corr<false>, gridc(c, grid1((size_t)nb + 1, 4)), dim3(256), 0, c->stream, Gt, nullptr, nullptr,
+                     nullptr, N, c->eq_L1, c->eq_L2, c->eq_norb, c->eq_site, c->eq_sign, c->eq_bins,
+                     c->eq_bins + 4 * (size_t)nb, c->cs);
   HIPCHK(hipGetLastError());
   return DQMC_OK;
 }
@@ -666,12 +678,17 @@ dqmc_status pass_draws(dqmc_ctx* c, int dir) {
 // One sweep (Algorithm 1): upward pass tau = 1..L, downward pass tau = L..1.
 // meas: bit 0 = equal-time estimators on every slice, bit 1 = the
 // time-displaced pass at the start of the sweep, bit 2 = the lattice-resolved
-// equal-time correlations on every slice.
+// equal-time correlations on every slice, bit 3 = the lattice-resolved
+// time-displaced correlations in that pass.
 dqmc_status td_pass(dqmc_ctx* c);
 dqmc_status sweep_once(dqmc_ctx* c, int meas) {
   const int L = c->L, nw = c->nw, nk = c->nk;
-  if (meas & 2)
-    if (dqmc_status s = td_pass(c)) return s;
+  if (meas & 2) {
+    c->td_corr_now = (meas & 8) != 0;
+    const dqmc_status s = td_pass(c);
+    c->td_corr_now = false;
+    if (s) return s;
+  }
   int hist = 0;
   c->row_alt.assign(L, 0);
   c->Gcur = c->G;
@@ -853,6 +870,18 @@ dqmc_status td_measure(dqmc_ctx* c, int tau, const double* gt0, const double* h,
     if (dqmc_status s = gemm(c, gemm_args(N, N, N, c->Eh, N, 0, gtt, N, 0, c->T1, N))) return s;
     if (dqmc_status s = gemm(c, gemm_args(N, N, N, c->T1, N, 0, c->Ehinv, N, 0, c->RHS, N))) return s;
     gt0 = c->Gs; h = c->X; gtt = c->RHS;
+  }
+  if (c->td_corr_now) {
+    if (tau == 0) {
+      hipLaunchKernelGGL(k_diag, gridc(c, grid1(N)), dim3(256), 0, c->stream, gtt, N, c->td_g00, c->cs);
+      HIPCHK(hipGetLastError());
+    }
+    const int nb = c->eq_L1 * c->eq_L2 * c->eq_norb * c->eq_norb;
+    hipLaunchKernelGGL(k_corr<true>, gridc(c, grid1((size_t)nb + 1, 4)), dim3(256), 0, c->stream, gt0, h, gtt,
+                       c->td_g00, N, c->eq_L1, c->eq_L2, c->eq_norb, c->eq_site, c->eq_sign,
+                       c->td_corr + (size_t)tau * td_corr_stride(c),
+                       tau == 0 ? c->td_corr + (size_t)(c->L + 1) * td_corr_stride(c) : nullptr, c->cs);
+    HIPCHK(hipGetLastError());
   }
   const int nblk = (N + kTdRows - 1) / kTdRows;
   hipLaunchKernelGGL(k_td_partial, gridc(c, (unsigned)nblk), dim3(256), 0, c->stream, gt0, h, gtt, c->kph, c->korb,
@@ -1124,6 +1153,8 @@ dqmc_status dqmc_init(dqmc_ctx* c) {
   if (dqmc_status s = fill_small(c, c->bins, 4, 0.0)) return s;
   if (dqmc_status s = fill_small(c, c->tdbins, (size_t)(c->L + 1) * kTdStride + 4, 0.0)) return s;
   if (dqmc_status s = fill_small(c, c->eq_bins, eq_bins_size(c), 0.0)) return s;
+  if (td_corr_size(c))
+    if (dqmc_status s = fill_small(c, c->td_corr, td_corr_size(c), 0.0)) return s;
   if (dqmc_status s = fill_small(c, c->prec_hist, 2 * (size_t)c->nk + 2, 0.0)) return s;
   if (dqmc_status s = fill_small(c, c->prec_tot, 4, 0.0)) return s;
   if (dqmc_status s = fill_small(c, reinterpret_cast<double*>(c->counters), 2, 0.0)) return s;
@@ -1138,7 +1169,9 @@ dqmc_status dqmc_init(dqmc_ctx* c) {
 dqmc_status dqmc_sweep(dqmc_ctx* c, int32_t n_sweeps, int32_t meas, dqmc_stats* st) {
   if (!c || n_sweeps < 0) return fail(c, DQMC_E_ARG, "bad arguments");
   if (!c->bound || !c->initialized || c->poisoned) return fail(c, DQMC_E_STATE, "context not initialised");
-  if (meas & ~7) return fail(c, DQMC_E_ARG, "unknown measurement flags");
+  if (meas & ~15) return fail(c, DQMC_E_ARG, "unknown measurement flags");
+  if ((meas & 8) && (!(meas & 2) || c->eq_norb < 1 || td_corr_size(c) == 0))
+    return fail(c, DQMC_E_STATE, "time-displaced correlations need bit 1 and dqmc_eq_setup");
   if ((meas & 2) && c->td_norb < 1) return fail(c, DQMC_E_STATE, "time-displaced measurement not set up");
   if ((meas & 4) && c->eq_norb < 1) return fail(c, DQMC_E_STATE, "lattice-resolved correlations not set up");
   const auto t0 = std::chrono::steady_clock::now();
@@ -1167,6 +1200,8 @@ dqmc_status dqmc_reset_bins(dqmc_ctx* c) {
   if (dqmc_status s = fill_small(c, c->bins, 4, 0.0)) return s;
   if (dqmc_status s = fill_small(c, c->tdbins, (size_t)(c->L + 1) * kTdStride + 4, 0.0)) return s;
   if (dqmc_status s = fill_small(c, c->eq_bins, eq_bins_size(c), 0.0)) return s;
+  if (td_corr_size(c))
+    if (dqmc_status s = fill_small(c, c->td_corr, td_corr_size(c), 0.0)) return s;
   HIPCHK(hipStreamSynchronize(c->stream));
   return DQMC_OK;
 }
@@ -1286,6 +1321,8 @@ dqmc_status dqmc_eq_setup(dqmc_ctx* c, int32_t L1, int32_t L2, int32_t norb, con
   HIPCHK(hipMemcpyAsync(c->eq_sign, sign, sizeof(double) * c->N, hipMemcpyHostToDevice, c->stream));
   HIPCHK(hipMemcpyAsync(c->eq_site, site, sizeof(int32_t) * c->N, hipMemcpyHostToDevice, c->stream));
   if (dqmc_status s = fill_small(c, c->eq_bins, eq_bins_size(c), 0.0)) return s;
+  if (td_corr_size(c))
+    if (dqmc_status s = fill_small(c, c->td_corr, td_corr_size(c), 0.0)) return s;
   HIPCHK(hipStreamSynchronize(c->stream));
   c->eq_L1 = L1;
   c->eq_L2 = L2;
@@ -1302,6 +1339,20 @@ dqmc_status dqmc_eq_read_bins(dqmc_ctx* c, double* sums_host, double* count) {
   HIPCHK(hipStreamSynchronize(c->stream));
   std::copy(raw.begin(), raw.begin() + 4 * nb, sums_host);
   if (count) *count = raw.back();
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_td_read_corr_bins(dqmc_ctx* c, double* sums_host, double* count) {
+  if (!c || !sums_host) return DQMC_E_ARG;
+  if (!c->bound || c->eq_norb < 1 || td_corr_size(c) == 0)
+    return fail(c, DQMC_E_STATE, "lattice-resolved correlations not set up");
+  const size_t nb = (size_t)c->eq_L1 * c->eq_L2 * c->eq_norb * c->eq_norb, st = td_corr_stride(c);
+  std::vector<double> raw(td_corr_size(c));
+  HIPCHK(hipMemcpyAsync(raw.data(), c->td_corr, raw.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (int t = 0; t <= c->L; ++t)
+    std::copy(raw.begin() + t * st, raw.begin() + t * st + 4 * nb, sums_host + (size_t)t * 4 * nb);
+  if (count) *count = raw[(size_t)(c->L + 1) * st];
   return DQMC_OK;
 }
 
@@ -1493,7 +1544,8 @@ bool layout_ok(const dqmc_ctx* c, const double* lo, const double* hi) {
        in(c->tdbins, (size_t)(c->L + 1) * kTdStride + 4, true) &&
        in(c->tdpart, (size_t)((N + kTdRows - 1) / kTdRows) * kTdPart, true) && in(c->a00, 2 * kTdMaxOrb, true) &&
        in(c->kph, 2 * N, false) && in(c->korb, N / 2 + 1, false) && in(c->eq_sign, N, false) &&
-       in(c->eq_site, N / 2 + 1, false) && in(c->eq_bins, eq_bins_size(c), true) &&
+       in(c->eq_site, N / 2 + 1, false) && in(c->eq_bins, eq_bins_size(c), true) && in(c->td_g00, N, true) &&
+       (td_corr_size(c) == 0 || in(c->td_corr, td_corr_size(c), true)) &&
        in(c->counters, 4, true) && in(c->err_flag, 1, true);
   return ok;
 }

@@ -85,3 +85,28 @@ def test_skip_and_rebin_shapes_and_errors():
         an.skip(x, 10)
     with pytest.raises(ValueError):
         an.autocorrelation(np.ones(5), 2)
+
+
+def test_momentum_transform_matches_the_site_double_sum():
+    """The Fourier transform of the displacement-resolved SpinZ correlation of
+    one configuration equals, at every torus momentum, the double sum over
+    sites with a phase per site (the time-displaced S(K, tau) estimator); the
+    inverse transform over the grid gives C(R) back."""
+    from inputs import honeycomb_lattice
+    from oracle import hubbard
+    from oracle import timedisplaced as otd
+    lat = honeycomb_lattice(3, 3)
+    m = hubbard.hubbard_model(lat.K, 4.0, 0.4, 0.1, 2, trotter="asym")
+    f = np.where(np.random.default_rng(1).random((m.L, m.N)) < 0.5, 1.0, -1.0)
+    GT0, G0T, GTT = otd.tdgf_scratch(m, f, 2)
+    _, _, G00 = otd.tdgf_scratch(m, f, 0)
+    C = otd.td_correlations(m, lat, GT0, G0T, GTT, G00)
+    ks = an.momentum_grid(lat)
+    Ck = an.to_momentum(C[1], lat, ks)
+    assert Ck.shape == (lat.n_cells, 2, 2)
+    for k in range(lat.n_cells):
+        assert np.max(np.abs(Ck[k] - otd.szsz_k(m, lat, ks[k], GT0, G0T, GTT, G00))) < 1e-12
+    back = np.einsum("kr,kab->rab", np.exp(-1j * (ks @ an.displacements(lat).T)), Ck) / lat.n_cells
+    assert np.max(np.abs(back - C[1])) < 1e-12
+    # every correlator at once: leading axes are kept
+    assert an.to_momentum(C, lat, ks[:3]).shape == (4, 3, 2, 2)

@@ -72,3 +72,64 @@ def test_eq_setup_rejects_bad_maps():
     ch.sweep(1, correlations=True)
     _, cnt = ch.eq_read_bins()
     assert cnt == 2 * om.L
+
+
+KVEC = np.array([4.0 * np.pi / 3.0, 0.0])
+
+
+@pytest.mark.parametrize("kind,L1,L2,beta,n_wrap,trotter", [
+    ("honeycomb", 3, 3, 2.0, 5, "sym"),
+    ("honeycomb", 5, 5, 1.6, 4, "asym"),
+    ("square", 10, 10, 1.0, 5, "asym"),     # 100 cells: more than one cell per lane
+    ("honeycomb", 6, 6, 1.0, 5, "asym"),    # K = (4 pi/3, 0) on the grid: ties to S(K, tau)
+])
+def test_td_correlation_bins_match_oracle(kind, L1, L2, beta, n_wrap, trotter):
+    """Sweeps with the time-displaced pass and its lattice-resolved
+    correlations: every tau of the start-of-sweep configuration against the
+    oracle's from-scratch GT0 / G0T / GTT, summed over two sweeps."""
+    from oracle import timedisplaced as otd
+    print(f"td correlations {kind} {L1}x{L2} beta={beta} n_wrap={n_wrap} {trotter}", flush=True)
+    om, ch, lat = pair(kind, L1, L2, 4.0, beta, 0.1, n_wrap, trotter=trotter, seed=4)
+    ph = np.exp(-1j * (lat.cell_pos[lat.cell_of] @ KVEC))
+    ch.td_setup(lat.orb_of, ph, lat.n_cells)
+    ch.eq_setup(L1, L2, _site(lat), lat.sublattice_sign())
+    ch.random_field()
+    f0, _ = ch.get_state()
+    ch.init()
+    oc = osweep.Chain(om, f0).init()
+    want = 0.0
+    for s in range(2):
+        want = want + otd.tdgf_correlations(om, lat, oc.field)
+        oc.sweep(measure=True)
+    ch.sweep(2, measure=True, time_displaced=True, td_correlations=True)
+    assert oc.min_tie > 1e-9, "near-tie in the oracle's decisions; pick another seed"
+    f, _ = ch.get_state()
+    assert np.array_equal(f, oc.field)
+    got, cnt = ch.td_read_corr_bins()
+    assert cnt == 2
+    assert got.shape == want.shape
+    assert maxabs(got, want) < 2e-9
+    # where K is a momentum of the L1 x L2 torus, the Fourier sum of SpinZ at K
+    # equals the pass's own S(K, tau) bins
+    if abs(np.exp(1j * L1 * (lat.a1 @ KVEC)) - 1) < 1e-12 and abs(np.exp(1j * L2 * (lat.a2 @ KVEC)) - 1) < 1e-12:
+        rpos = np.array([(R % L1) * lat.a1 + (R // L1) * lat.a2 for R in range(lat.n_cells)])
+        sk = np.einsum("r,trab->tab", np.exp(1j * (rpos @ KVEC)), got[:, 1])
+        S, c2 = ch.td_read_bins()
+        assert c2 == 2 and maxabs(sk, S) < 1e-9
+
+
+def test_td_correlations_need_setup():
+    om, ch, lat = pair("square", 4, 4, 4.0, 1.0, 0.1, 5, seed=0)
+    ch.random_field().init()
+    ph = np.ones(lat.n, dtype=complex)
+    ch.td_setup(lat.orb_of, ph, lat.n_cells)
+    with pytest.raises(DQMCError) as e:
+        ch.sweep(1, time_displaced=True, td_correlations=True)
+    assert e.value.status == DQMC_E_STATE
+    ch.eq_setup(4, 4, _site(lat), lat.sublattice_sign())
+    with pytest.raises(DQMCError) as e:
+        ch.sweep(1, td_correlations=True)     # without the pass
+    assert e.value.status == DQMC_E_STATE
+    ch.sweep(1, time_displaced=True, td_correlations=True)
+    _, cnt = ch.td_read_corr_bins()
+    assert cnt == 1
