@@ -19,6 +19,7 @@
 #include "update.h"
 #include "adjoint.h"
 #include "timedisplaced.h"
+#include "correlations.h"
 
 namespace {
 
