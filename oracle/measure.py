@@ -30,14 +30,15 @@ def equal_time(model, G: np.ndarray):
     return D, ekin, model.U * D
 
 
-def eq_correlations(model, lat, G: np.ndarray) -> np.ndarray:
+def eq_correlations(model, lat, G: np.ndarray, entries=None) -> np.ndarray:
     """Equal-time correlation functions on the Bravais lattice (section
     "Observables": correlations summed over unit cells and stored by the
     displacement R between them), per configuration, from the measured G~:
 
         C_o[R, a, b] = 1/N_cells sum_I O(site(I, a), site(I + R, b)),
 
-    o = Green, SpinZ, SpinXY, Den.  In the sampling frame both species carry
+    o = Green, SpinZ, SpinXY, Den (entries: an optional list of (R, a, b); then
+    only those are evaluated and [4, len(entries)] is returned).  In the sampling frame both species carry
     the same G (G_ij = <c_i c_j^+>), the down spin is the particle-hole image
     c_{i,dn} = s_i c'^+_i with s_i the sublattice sign, and Wick's theorem gives
         Green  1/2 <c^+_{i s} c_{j s}> summed over s = 1/2 (d_ij - G_ji + s_i s_j G_ij),
@@ -53,22 +54,24 @@ def eq_correlations(model, lat, G: np.ndarray) -> np.ndarray:
     site = -np.ones((nc, norb), dtype=int)
     for i in range(n):
         site[lat.cell_of[i], lat.orb_of[i]] = i
-    out = np.zeros((4, nc, norb, norb))
-    for I in range(nc):
-        i1, i2 = I % L1, I // L1
-        for R in range(nc):
-            r1, r2 = R % L1, R // L1
+    todo = [(R, a, b) for R in range(nc) for a in range(norb) for b in range(norb)] if entries is None else entries
+    vals = np.zeros((4, len(todo)))
+    for e, (R, a, b) in enumerate(todo):
+        r1, r2 = R % L1, R // L1
+        for I in range(nc):
+            i1, i2 = I % L1, I // L1
             J = (i1 + r1) % L1 + L1 * ((i2 + r2) % L2)
-            for a in range(norb):
-                for b in range(norb):
-                    i, j = site[I, a], site[J, b]
-                    d = 1.0 if i == j else 0.0
-                    gij, gji = Gt[i, j], Gt[j, i]
-                    out[0, R, a, b] += 0.5 * (d - gji + s[i] * s[j] * gij)
-                    out[1, R, a, b] += 0.25 * ((1.0 - 2.0 * Gt[i, i]) * (1.0 - 2.0 * Gt[j, j]) + 2.0 * (d - gji) * gij)
-                    out[2, R, a, b] += 0.25 * s[i] * s[j] * ((d - gji) ** 2 + gij ** 2)
-                    out[3, R, a, b] += 1.0 + 2.0 * (d - gji) * gij
-    return out / nc
+            i, j = site[I, a], site[J, b]
+            d = 1.0 if i == j else 0.0
+            gij, gji = Gt[i, j], Gt[j, i]
+            vals[0, e] += 0.5 * (d - gji + s[i] * s[j] * gij)
+            vals[1, e] += 0.25 * ((1.0 - 2.0 * Gt[i, i]) * (1.0 - 2.0 * Gt[j, j]) + 2.0 * (d - gji) * gij)
+            vals[2, e] += 0.25 * s[i] * s[j] * ((d - gji) ** 2 + gij ** 2)
+            vals[3, e] += 1.0 + 2.0 * (d - gji) * gij
+    vals /= nc
+    if entries is not None:
+        return vals
+    return vals.reshape(4, nc, norb, norb)
 
 
 def density(model, G: np.ndarray) -> float:

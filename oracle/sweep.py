@@ -60,6 +60,7 @@ class Chain:
         self.trace = None                 # optional per-event record
         self.min_tie = np.inf             # min |R - u| over all proposals
         self.eq_lat = None                # lattice for the lattice-resolved correlations, if measured
+        self.eq_entries = None            # optional list of (R, a, b) to evaluate
         self.eq_bins = None
 
     # -- setup (Algorithm 1: confin, then the wrapul fill) ----------------------
@@ -126,7 +127,7 @@ class Chain:
             self.bins += np.array([D, ekin, epot, 1.0])
             if self.eq_lat is not None:
                 from .measure import eq_correlations
-                c = eq_correlations(self.m, self.eq_lat, self.G)
+                c = eq_correlations(self.m, self.eq_lat, self.G, self.eq_entries)
                 self.eq_bins = c if self.eq_bins is None else self.eq_bins + c
 
     def _stabilise(self, G_s, G_cmp):

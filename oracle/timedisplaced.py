@@ -89,7 +89,7 @@ def szsz_k(model, lat, kvec, GT0, G0T, GTT, G00):
     return S / lat.n_cells
 
 
-def td_correlations(model, lat, GT0, G0T, GTT, G00):
+def td_correlations(model, lat, GT0, G0T, GTT, G00, entries=None):
     """Time-displaced correlation functions on the Bravais lattice (section
     "Observables": correlations summed over unit cells and stored by the
     displacement R; section "Measuring time displaced observables" for the
@@ -107,7 +107,8 @@ def td_correlations(model, lat, GT0, G0T, GTT, G00):
         Den    <n_i(tau) n_j(0)>                      = 1 - 2 G0T_ji GT0_ij.
     At tau = 0 (GT0 = G, G0T = G - 1) these are the equal-time estimators.
     With the symmetric split all four are rotated as the equal-time G.
-    Returns [4, N_cells, norb, norb]."""
+    Returns [4, N_cells, norb, norb], or [4, len(entries)] for an optional list
+    of (R, a, b) entries, the only ones then evaluated."""
     GT0, G0T, GTT, G00 = (_rotate(model, M) for M in (GT0, G0T, GTT, G00))
     L1, L2, norb = lat.L1, lat.L2, lat.norb
     nc = L1 * L2
@@ -115,31 +116,34 @@ def td_correlations(model, lat, GT0, G0T, GTT, G00):
     site = -np.ones((nc, norb), dtype=int)
     for i in range(model.N):
         site[lat.cell_of[i], lat.orb_of[i]] = i
-    out = np.zeros((4, nc, norb, norb))
-    for I in range(nc):
-        i1, i2 = I % L1, I // L1
-        for R in range(nc):
+    todo = [(R, a, b) for R in range(nc) for a in range(norb) for b in range(norb)] if entries is None else entries
+    vals = np.zeros((4, len(todo)))
+    for e, (R, a, b) in enumerate(todo):
+        for I in range(nc):
+            i1, i2 = I % L1, I // L1
             J = (i1 + R % L1) % L1 + L1 * ((i2 + R // L1) % L2)
-            for a in range(norb):
-                for b in range(norb):
-                    i, j = site[I, a], site[J, b]
-                    h, g = G0T[j, i], GT0[i, j]
-                    out[0, R, a, b] += 0.5 * (-h + s[i] * s[j] * g)
-                    out[1, R, a, b] += 0.25 * ((1.0 - 2.0 * GTT[i, i]) * (1.0 - 2.0 * G00[j, j]) - 2.0 * h * g)
-                    out[2, R, a, b] += 0.25 * s[i] * s[j] * (h * h + g * g)
-                    out[3, R, a, b] += 1.0 - 2.0 * h * g
-    return out / nc
+            i, j = site[I, a], site[J, b]
+            h, g = G0T[j, i], GT0[i, j]
+            vals[0, e] += 0.5 * (-h + s[i] * s[j] * g)
+            vals[1, e] += 0.25 * ((1.0 - 2.0 * GTT[i, i]) * (1.0 - 2.0 * G00[j, j]) - 2.0 * h * g)
+            vals[2, e] += 0.25 * s[i] * s[j] * (h * h + g * g)
+            vals[3, e] += 1.0 - 2.0 * h * g
+    vals /= nc
+    if entries is not None:
+        return vals
+    return vals.reshape(4, nc, norb, norb)
 
 
-def tdgf_correlations(model, lat, field, taus=None):
+def tdgf_correlations(model, lat, field, taus=None, entries=None):
     """td_correlations for tau in taus (default 0..L) of one configuration,
-    every tau from scratch: [len(taus), 4, N_cells, norb, norb]."""
+    every tau from scratch: [len(taus), 4, N_cells, norb, norb] (or
+    [len(taus), 4, len(entries)])."""
     taus = range(model.L + 1) if taus is None else taus
     _, _, G00 = tdgf_scratch(model, field, 0)
     out = []
     for tau in taus:
         GT0, G0T, GTT = tdgf_scratch(model, field, tau)
-        out.append(td_correlations(model, lat, GT0, G0T, GTT, G00))
+        out.append(td_correlations(model, lat, GT0, G0T, GTT, G00, entries))
     return np.array(out)
 
 

@@ -133,3 +133,51 @@ def test_td_correlations_need_setup():
     ch.sweep(1, time_displaced=True, td_correlations=True)
     _, cnt = ch.td_read_corr_bins()
     assert cnt == 1
+
+
+def test_eq_correlations_honeycomb12_sampled_entries():
+    """The headline chain (honeycomb 12x12, N = 288, U = 4, beta = 10, L = 100):
+    one sweep measuring the correlations on all 200 slices; sampled entries
+    against the oracle's, accumulated along its own trajectory."""
+    print("correlations honeycomb 12x12 one sweep", flush=True)
+    entries = [(0, 0, 0), (0, 0, 1), (0, 1, 1), (1, 0, 1), (12, 1, 0), (13, 1, 0), (71, 0, 0), (143, 1, 1)]
+    om, ch, lat = pair("honeycomb", 12, 12, 4.0, 10.0, 0.1, 10, trotter="asym", seed=0)
+    ch.random_field().init()
+    ch.eq_setup(12, 12, _site(lat), lat.sublattice_sign())
+    f0, _ = ch.get_state()
+    oc = osweep.Chain(om, f0).init()
+    oc.eq_lat, oc.eq_entries = lat, entries
+    ch.sweep(1, measure=True, correlations=True)
+    oc.sweep(measure=True)
+    assert oc.min_tie > 1e-9, "near-tie in the oracle's decisions; pick another seed"
+    f, _ = ch.get_state()
+    assert np.array_equal(f, oc.field)
+    got, cnt = ch.eq_read_bins()
+    assert cnt == 200
+    for e, (R, a, b) in enumerate(entries):
+        assert maxabs(got[:, R, a, b], oc.eq_bins[:, e]) < 1e-9 * cnt, (R, a, b)
+
+
+def test_td_correlations_honeycomb18_sampled():
+    """The 18x18 honeycomb time-displaced workload (N = 648, U = 5, beta = 20,
+    L = 200, n_wrap = 10): one sweep with the pass and its lattice-resolved
+    correlations; sampled tau and entries against the oracle from scratch."""
+    from oracle import timedisplaced as otd
+    print("td correlations honeycomb 18x18", flush=True)
+    entries = [(0, 0, 0), (0, 0, 1), (1, 1, 0), (19, 0, 1), (161, 1, 1), (323, 0, 0)]
+    om, ch, lat = pair("honeycomb", 18, 18, 5.0, 20.0, 0.1, 10, trotter="asym", seed=0)
+    ph = np.exp(-1j * (lat.cell_pos[lat.cell_of] @ KVEC))
+    ch.td_setup(lat.orb_of, ph, lat.n_cells)
+    ch.eq_setup(18, 18, _site(lat), lat.sublattice_sign())
+    ch.random_field()
+    f0, _ = ch.get_state()
+    ch.init()
+    ch.sweep(1, measure=False, time_displaced=True, td_correlations=True)
+    got, cnt = ch.td_read_corr_bins()
+    assert cnt == 1
+    _, _, G00 = otd.tdgf_scratch(om, f0, 0)
+    for tau in (0, 7, 100, 200):
+        GT0, G0T, GTT = otd.tdgf_scratch(om, f0, tau)
+        want = otd.td_correlations(om, lat, GT0, G0T, GTT, G00, entries)
+        for e, (R, a, b) in enumerate(entries):
+            assert maxabs(got[tau, :, R, a, b], want[:, e]) < 1e-9, (tau, R, a, b)

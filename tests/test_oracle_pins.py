@@ -571,3 +571,25 @@ def test_td_correlations_enumeration_equals_fock(trotter):
     finally:
         otd.tdgf_scratch = saved
     assert np.max(np.abs(bad[1:] - want[1:])) > 1e-3
+
+
+def test_correlation_entry_subsets_equal_the_full_evaluation():
+    """The oracle's optional entry lists evaluate exactly the listed entries
+    of the full (Fock-pinned) evaluation, equal-time and time-displaced."""
+    from oracle import measure
+    from oracle import timedisplaced as otd
+    lat = honeycomb_lattice(3, 2)
+    m = hubbard.hubbard_model(lat.K, 4.0, 0.4, 0.1, 2, trotter="sym")
+    f = np.where(np.random.default_rng(5).random((m.L, m.N)) < 0.5, 1.0, -1.0)
+    entries = [(0, 0, 0), (0, 1, 0), (4, 0, 1), (5, 1, 1), (2, 1, 0)]
+    from oracle.stable import green_scratch
+    G = green_scratch(m, f, 2)
+    full = measure.eq_correlations(m, lat, G)
+    sub = measure.eq_correlations(m, lat, G, entries)
+    assert sub.shape == (4, len(entries))
+    for e, (R, a, b) in enumerate(entries):
+        assert np.array_equal(sub[:, e], full[:, R, a, b])
+    full_t = otd.tdgf_correlations(m, lat, f, taus=(1, 3))
+    sub_t = otd.tdgf_correlations(m, lat, f, taus=(1, 3), entries=entries)
+    for e, (R, a, b) in enumerate(entries):
+        assert np.array_equal(sub_t[:, :, e], full_t[:, :, R, a, b])
