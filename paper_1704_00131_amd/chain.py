@@ -38,6 +38,7 @@ class Chain:
         self.model = model
         self.N = model.n
         self.L = model.n_slices
+        self.eq_shape = (0, 0)    # (n_cells, norb) once eq_setup has run; the library refuses reads before
         sizes = Sizes()
         check(lib.dqmc_query_sizes(ctypes.byref(model), ctypes.byref(sizes)))
         self.sizes = sizes

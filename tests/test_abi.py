@@ -113,3 +113,26 @@ def test_batch_groups_and_size(lib):
     assert lib.dqmc_batch_init(b) == 6          # not bound yet
     assert lib.dqmc_batch_check_layout(b) == 0  # every chain's buffers inside the buffer
     lib.dqmc_batch_destroy(b)
+
+
+def test_correlation_entry_points_check_arguments_and_order(lib):
+    """Host-side checks of the lattice-resolved correlation calls: a null
+    context or bad sizes are DQMC_E_ARG; a context not yet bound is
+    DQMC_E_STATE (no device work)."""
+    m = _model(n=4, beta=1.0, dtau=0.1, n_wrap=5)
+    K = np.zeros((4, 4))
+    K[0, 1] = K[1, 0] = -1.0
+    ctx = ctypes.c_void_p()
+    assert lib.dqmc_create(ctypes.byref(m), K.ctypes.data, None, ctypes.byref(ctx)) == 0
+    site = np.arange(4, dtype=np.int32)
+    sign = np.array([1.0, -1.0, 1.0, -1.0])
+    out = np.zeros(64)
+    cnt = ctypes.c_double()
+    assert lib.dqmc_eq_setup(None, 2, 2, 1, site.ctypes.data, sign.ctypes.data) == 1
+    assert lib.dqmc_eq_setup(ctx, 2, 2, 5, site.ctypes.data, sign.ctypes.data) == 1    # norb above 4
+    assert lib.dqmc_eq_setup(ctx, 2, 2, 1, None, sign.ctypes.data) == 1
+    assert lib.dqmc_eq_setup(ctx, 2, 2, 1, site.ctypes.data, sign.ctypes.data) == 6    # not bound
+    assert lib.dqmc_eq_read_bins(ctx, out.ctypes.data, ctypes.byref(cnt)) == 6
+    assert lib.dqmc_td_read_corr_bins(ctx, out.ctypes.data, ctypes.byref(cnt)) == 6
+    assert lib.dqmc_eq_read_bins(None, out.ctypes.data, ctypes.byref(cnt)) == 1
+    lib.dqmc_destroy(ctx)

@@ -181,3 +181,12 @@ def test_td_correlations_honeycomb18_sampled():
         want = otd.td_correlations(om, lat, GT0, G0T, GTT, G00, entries)
         for e, (R, a, b) in enumerate(entries):
             assert maxabs(got[tau, :, R, a, b], want[:, e]) < 1e-9, (tau, R, a, b)
+
+
+def test_reading_correlation_bins_before_setup_is_refused():
+    om, ch, lat = pair("square", 4, 4, 4.0, 1.0, 0.1, 5, seed=0)
+    ch.random_field().init()
+    for read in (ch.eq_read_bins, ch.td_read_corr_bins):
+        with pytest.raises(DQMCError) as e:
+            read()
+        assert e.value.status == DQMC_E_STATE
