@@ -125,6 +125,27 @@ class Model:
         return float(out)
 
 
+def mz_frame_hopping(T, h, sign) -> np.ndarray:
+    """Hopping of the sampling frame for the M_z form of the Hubbard model
+    (section "The M_z-Hubbard model on a square lattice": two flavours with
+    V = +1 and -1 on the site, alpha = 0, flavour hopping T_up, T_dn) with a
+    Zeeman field h: T_up = T - h, T_dn = T + h.  The field coupled to
+    n_up - n_dn becomes, under c_{i,dn} = s_i c'^+_i, the field coupled to
+    n_1 + n_2 - 1 of the density frame, and the flavours' hopping become
+    K_1 = T_up and K_2 = -S T_dn^T S (S = diag(s)).  When these agree (T
+    symmetric, T_ij = 0 unless s_i s_j = -1, no chemical potential) one
+    Green's function serves both and K = T - h 1; otherwise the two flavours
+    need two Green's functions, outside this frame (ValueError)."""
+    T = np.asarray(T, dtype=np.float64)
+    S = np.diag(np.asarray(sign, dtype=np.float64))
+    n = T.shape[0]
+    K1 = T - h * np.eye(n)
+    K2 = -S @ (T + h * np.eye(n)).T @ S
+    if not np.array_equal(K1, K2):
+        raise ValueError("the two flavours' hopping differ in the density frame")
+    return K1
+
+
 def hubbard_model(K, U, beta, dtau, n_wrap, field_kind="ising", trotter="sym", seed=0) -> Model:
     lam = {"ising": ising_coupling, "gauss": gauss_coupling, "ising4": ising4_coupling}[field_kind](U, dtau)
     return Model(K=K, beta=beta, dtau=dtau, n_wrap=n_wrap, coupling=lam, U=U,

@@ -1,7 +1,8 @@
 """Fock-space evaluation of Trotterised Hubbard expectation values (a pin).
 
 Independent of the oracle: the repulsive Hubbard Hamiltonian
-H = sum_sigma c^+ K c + (U/2) sum_i (n_i - 1)^2 is built as a 4^N-dimensional
+H = sum_sigma c^+ K c - h sum_i (n_i,up - n_i,dn) + (U/2) sum_i (n_i - 1)^2
+(h an optional Zeeman field, part of the one-body H_T) is built as a 4^N-dimensional
 matrix from Jordan-Wigner fermions, and the symmetric Trotter product
 S = exp(-dtau H_T/2) exp(-dtau H_U) exp(-dtau H_T/2) of the section
 "The partition function" gives
@@ -22,7 +23,7 @@ def _expmh(H, x):
 
 
 class Fock:
-    def __init__(self, K, U):
+    def __init__(self, K, U, h=0.0):
         K = np.asarray(K, dtype=float)
         self.N = N = K.shape[0]
         nm = 2 * N
@@ -48,6 +49,8 @@ class Fock:
                     if K[i, j] != 0.0:
                         HT += K[i, j] * self.c[mode(i, s)].T @ self.c[mode(j, s)]
         self.n = [[self.c[mode(i, s)].T @ self.c[mode(i, s)] for s in range(2)] for i in range(N)]
+        for i in range(N):
+            HT -= h * (self.n[i][0] - self.n[i][1])
         HU = np.zeros((dim, dim))
         for i in range(N):
             ni = self.n[i][0] + self.n[i][1] - np.eye(dim)

@@ -160,6 +160,43 @@ def test_two_site_enumeration_equals_fock_trotter(trotter):
     assert np.max(np.abs(res[:, 1] - E)) < 1e-13
 
 
+@pytest.mark.parametrize("trotter", ["sym", "asym"])
+def test_mz_zeeman_field_enumeration_equals_fock(trotter):
+    """The M_z form with a Zeeman field h (flavour hopping T -+ h): the oracle
+    in the density frame with K = T - h (one Green's function for both
+    flavours) against the Fock-space Trotter product of the original-frame
+    Hamiltonian with the field.  Double occupancy, and the frame's kinetic
+    energy per site plus h (the constant of the particle-hole map) equal to
+    <H_T>/N; the field polarises (<n_up - n_dn> = 1 - 2 G_ii per site, here
+    compared with Fock space too)."""
+    from oracle.measure import measured_green
+    from oracle.stable import green_scratch, log_weight
+    K = np.array([[0.0, -1.0], [-1.0, 0.0]])
+    U, dtau, L, h = 4.0, 0.25, 4, 0.7
+    sign = np.array([1.0, -1.0])
+    Kf = hubbard.mz_frame_hopping(K, h, sign)
+    m = hubbard.hubbard_model(Kf, U, L * dtau, dtau, 2, trotter=trotter)
+    res = exact_small.enumerate_observables(m, taus=(0, 1, 2, 3))
+    F = Fock(K, U, h)
+    S = F.trotter(dtau) if trotter == "sym" else F.trotter_asym(dtau)
+    D = F.expect_with(S, F.double_occ(), L)
+    E = F.expect_with(S, F.kinetic(), L)
+    assert np.max(np.abs(res[:, 0] - D)) < 1e-13
+    assert np.max(np.abs(res[:, 1] + h - E)) < 1e-13
+    # magnetisation per site
+    mz_fock = F.expect_with(S, sum(F.n[i][0] - F.n[i][1] for i in range(2)) / 2, L)
+    logw, mz = [], []
+    for f in exact_small.all_fields(m):
+        logw.append(log_weight(m, f))
+        mz.append(np.mean(1.0 - 2.0 * np.diag(measured_green(m, green_scratch(m, f, 1)))))
+    w = np.exp(np.array(logw) - max(logw))
+    assert abs(np.dot(w, mz) / w.sum() - mz_fock) < 1e-13
+    assert mz_fock > 0.05
+    # a chemical potential makes the flavours differ in this frame: refused
+    with pytest.raises(ValueError):
+        hubbard.mz_frame_hopping(K - 0.3 * np.eye(2), h, sign)
+
+
 def test_two_site_enumeration_detects_wrong_alpha():
     """Planted mistake on the CPU: flipping the sign of alpha moves D away
     from the Fock-space value, so the pin above is sensitive to it."""
@@ -466,19 +503,21 @@ def test_szsz_enumeration_equals_fock(trotter):
         assert np.max(np.abs(got[t] - want)) < 1e-12, (trotter, n, got[t], want)
 
 
-@pytest.mark.parametrize("trotter", ["sym", "asym"])
-def test_eq_correlations_enumeration_equals_fock(trotter):
+@pytest.mark.parametrize("trotter,h", [("sym", 0.0), ("asym", 0.0), ("sym", 0.6), ("asym", 0.6)])
+def test_eq_correlations_enumeration_equals_fock(trotter, h):
     """Lattice-resolved equal-time correlations (Green, SpinZ, SpinXY, Den by
     displacement and orbital pair) of a 4-site honeycomb ring (2 cells x 2
     orbitals) x 2 slices: the exact weighted average of the per-configuration
     estimators against Tr(S^L O_ij) / Tr(S^L) in Fock space, with O_ij built
-    from the original-frame fermions (no particle-hole map)."""
+    from the original-frame fermions (no particle-hole map); h > 0 adds the
+    M_z form's Zeeman field (frame hopping K = T - h)."""
     from oracle import exact_small, measure
     lat = honeycomb_lattice(1, 2)
     U, dtau, L = 4.0, 0.25, 2
-    m = hubbard.hubbard_model(lat.K, U, L * dtau, dtau, 1, trotter=trotter)
+    K = hubbard.mz_frame_hopping(lat.K, h, lat.sublattice_sign())
+    m = hubbard.hubbard_model(K, U, L * dtau, dtau, 1, trotter=trotter)
     got = exact_small.enumerate_eq_correlations(m, lat, tau=0)
-    F = Fock(lat.K, U)
+    F = Fock(lat.K, U, h)
     S = F.trotter(dtau) if trotter == "sym" else F.trotter_asym(dtau)
     c = F.c
 
@@ -502,8 +541,12 @@ def test_eq_correlations_enumeration_equals_fock(trotter):
                     for o, O in enumerate(ops(site[I, a], site[J, b])):
                         want[o, R, a, b] += F.expect_with(S, O, L) / nc
     assert np.max(np.abs(got - want)) < 1e-12, (trotter, np.max(np.abs(got - want), axis=(1, 2, 3)))
-    # SU(2): the z and xy spin correlations agree on average (not per configuration)
-    assert np.max(np.abs(got[1] - got[2])) < 1e-12
+    # SU(2): the z and xy spin correlations agree on average (not per
+    # configuration); the Zeeman field breaks it
+    if h == 0.0:
+        assert np.max(np.abs(got[1] - got[2])) < 1e-12
+    else:
+        assert np.max(np.abs(got[1] - got[2])) > 1e-3
     # a planted mistake (no sublattice sign in the down-spin Green term) fails
     s_saved = lat.sublattice_sign
     try:
@@ -514,21 +557,23 @@ def test_eq_correlations_enumeration_equals_fock(trotter):
     assert np.max(np.abs(bad[0] - want[0])) > 1e-3
 
 
-@pytest.mark.parametrize("trotter", ["sym", "asym"])
-def test_td_correlations_enumeration_equals_fock(trotter):
+@pytest.mark.parametrize("trotter,h", [("sym", 0.0), ("asym", 0.0), ("asym", 0.6)])
+def test_td_correlations_enumeration_equals_fock(trotter, h):
     """Time-displaced lattice-resolved correlations (Green, SpinZ, SpinXY, Den
     by displacement and orbital pair) of a 4-site honeycomb ring (2 cells x 2
     orbitals) x 2 slices at tau = 0, 1, 2 slices: the exact weighted average of
     the per-configuration estimators against Tr(S^(L-n) A_i S^n B_j) / Tr(S^L)
-    in Fock space, with A, B built from the original-frame fermions."""
+    in Fock space, with A, B built from the original-frame fermions; h > 0 adds
+    the M_z form's Zeeman field (frame hopping K = T - h)."""
     from oracle import exact_small
     from oracle import timedisplaced as otd
     lat = honeycomb_lattice(1, 2)
     U, dtau, L = 4.0, 0.25, 2
-    m = hubbard.hubbard_model(lat.K, U, L * dtau, dtau, 1, trotter=trotter)
+    K = hubbard.mz_frame_hopping(lat.K, h, lat.sublattice_sign())
+    m = hubbard.hubbard_model(K, U, L * dtau, dtau, 1, trotter=trotter)
     taus = (0, 1, 2)
     got = exact_small.enumerate_td_correlations(m, lat, taus)
-    F = Fock(lat.K, U)
+    F = Fock(lat.K, U, h)
     S = F.trotter(dtau) if trotter == "sym" else F.trotter_asym(dtau)
     c = F.c
 
@@ -554,9 +599,10 @@ def test_td_correlations_enumeration_equals_fock(trotter):
                             for w, A, B in terms:
                                 want[t, o, R, a, b] += w * F.expect_tau_with(S, A, B, L, n) / nc
     assert np.max(np.abs(got - want)) < 1e-12, (trotter, np.max(np.abs(got - want), axis=(2, 3, 4)))
-    # SU(2) on average; tau = 0 is the equal-time estimator; the Fourier sum of
-    # SpinZ at K is the momentum-space estimator of the pass
-    assert np.max(np.abs(got[:, 1] - got[:, 2])) < 1e-12
+    # SU(2) on average (without the Zeeman field); tau = 0 is the equal-time
+    # estimator; the Fourier sum of SpinZ at K is the momentum-space estimator
+    if h == 0.0:
+        assert np.max(np.abs(got[:, 1] - got[:, 2])) < 1e-12
     assert np.max(np.abs(got[0] - exact_small.enumerate_eq_correlations(m, lat, tau=0))) < 1e-12
     g1, g2 = lat.reciprocal()
     kvec = 0.5 * g2
