@@ -27,7 +27,8 @@ Prints one JSON line with
              the time-displaced pass of the 18x18 honeycomb chain (N = 648,
              U = 5, beta = 20, L = 200) with its MFMA GEMM rate; the headline
              chain with the paper's four-valued field; the headline chain
-             with the lattice-resolved equal-time correlations measured.
+             with the lattice-resolved equal-time correlations measured; the
+             headline chain in the M_z form with a Zeeman field.
 """
 import argparse
 import hashlib
@@ -203,6 +204,28 @@ def bench_four_valued(torch, pa):
             "acceptance": acc / max(1, props), "prec_max": st.prec_max}
 
 
+def bench_zeeman(torch, pa):
+    """The honeycomb 12x12 chain of the headline workload in the M_z form with
+    a Zeeman field h = 0.5 (frame hopping T - h): three timed sweeps after one
+    untimed."""
+    from inputs import WORKLOADS
+    w = WORKLOADS["honeycomb12_U4_b10"]
+    lat = w.lattice()
+    K = pa.mz_frame_hopping(lat.K, 0.5, lat.sublattice_sign())
+    ch = pa.Chain(pa.make_model(lat.n, w.beta, w.dtau, w.n_wrap, pa.hubbard_coupling(w.U, w.dtau), U=w.U,
+                                trotter=w.trotter, seed=w.seed), K)
+    ch.random_field().init()
+    ch.sweep(1, measure=True)
+    st0 = ch.sweep(0, measure=True)
+    dt, st = _sync_time(torch, lambda: ch.sweep(3, measure=True))
+    bins = ch.read_bins()
+    ch.close()
+    props = st.proposals - st0.proposals
+    return {"N": lat.n, "L": w.n_slices, "h": 0.5, "ms_per_sweep": 1e3 * dt / 3, "updates_per_s": props / dt,
+            "acceptance": (st.accepted - st0.accepted) / max(1, props), "prec_max": st.prec_max,
+            "double_occupancy": bins[0] / bins[3]}
+
+
 def bench_correlations(torch, pa):
     """The honeycomb 12x12 chain of the headline workload with the
     lattice-resolved equal-time correlations (Green, SpinZ, SpinXY, Den by
@@ -236,7 +259,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--profile-extra", choices=["batched", "gradient", "time_displaced", "four_valued",
-                                                "correlations"],
+                                                "correlations", "zeeman"],
                     help="run only this extra workload and print its figures (for rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -251,7 +274,7 @@ def main():
 
     if args.profile_extra:
         fn = {"batched": bench_batched, "gradient": bench_gradient, "time_displaced": bench_time_displaced,
-              "four_valued": bench_four_valued, "correlations": bench_correlations}
+              "four_valued": bench_four_valued, "correlations": bench_correlations, "zeeman": bench_zeeman}
         print(json.dumps({args.profile_extra: fn[args.profile_extra](torch, pa)}))
         return
 
@@ -320,7 +343,8 @@ def main():
         out["config"]["extras"] = {"batched": bench_batched(torch, pa), "gradient": bench_gradient(torch, pa),
                                    "time_displaced": bench_time_displaced(torch, pa),
                                    "four_valued": bench_four_valued(torch, pa),
-                                   "correlations": bench_correlations(torch, pa)}
+                                   "correlations": bench_correlations(torch, pa),
+                                   "zeeman": bench_zeeman(torch, pa)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(lat, w, field0)
     print(json.dumps(out))

@@ -317,6 +317,19 @@ void dqmc_batch_destroy(dqmc_batch* b);
  * identity of Eq. (HS_squares), sqrt(dtau U / 2) (DQMC_FIELD_ISING4). */
 dqmc_status dqmc_hubbard_coupling(double U, double dtau, dqmc_field_kind kind, double* coupling);
 
+/* Hopping matrix of the density frame for the M_z form of the Hubbard model
+ * (section "The M_z-Hubbard model on a square lattice": two flavours coupled
+ * to n_up - n_dn) with a Zeeman field h, i.e. flavour hopping T_up = T - h and
+ * T_dn = T + h.  Under c_{i,dn} = s_i c'^+_i the flavours' matrices become
+ * K_1 = T - h 1 and K_2 = -S (T + h 1)^T S, S = diag(sign); when they are equal
+ * (T symmetric with zero diagonal, bonds only between opposite signs) the
+ * frame's single Green's function serves both and K_out = T - h 1.  T (n*n,
+ * row-major), sign (n, each +1 or -1) and K_out (n*n) are host arrays owned by
+ * the caller.  DQMC_E_ARG for bad arguments, DQMC_E_UNSUPPORTED when the two
+ * flavours differ (a chemical potential, a non-bipartite bond, flavour-
+ * dependent hopping beyond the field): those need two Green's functions. */
+dqmc_status dqmc_mz_frame_hopping(int32_t n, const double* T, double h, const double* sign, double* K_out);
+
 #ifdef __cplusplus
 }
 #endif

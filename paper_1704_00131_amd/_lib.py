@@ -95,6 +95,8 @@ SIGNATURES = {
     "dqmc_batch_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "dqmc_batch_destroy": (None, [ctypes.c_void_p]),
     "dqmc_destroy": (None, [ctypes.c_void_p]),
+    "dqmc_mz_frame_hopping": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
+                                             ctypes.c_void_p]),
     "dqmc_hubbard_coupling": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                              ctypes.POINTER(ctypes.c_double)]),
 }

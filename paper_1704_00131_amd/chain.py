@@ -15,6 +15,21 @@ def hubbard_coupling(U: float, dtau: float, field: str = "ising") -> float:
     return out.value
 
 
+def mz_frame_hopping(T, h: float, sign) -> np.ndarray:
+    """Density-frame hopping K = T - h for the M_z form of the Hubbard model
+    with a Zeeman field h (flavour hopping T -+ h); the library refuses
+    (DQMC_E_UNSUPPORTED) when the two flavours would need two Green's
+    functions."""
+    Tc = np.ascontiguousarray(T, dtype=np.float64)
+    sg = np.ascontiguousarray(sign, dtype=np.float64)
+    n = Tc.shape[0]
+    if Tc.shape != (n, n) or sg.shape != (n,):
+        raise ValueError("T must be n x n and sign of length n")
+    out = np.empty((n, n))
+    check(_lib.load().dqmc_mz_frame_hopping(n, Tc.ctypes.data, float(h), sg.ctypes.data, out.ctypes.data))
+    return out
+
+
 def make_model(n, beta, dtau, n_wrap, coupling, U=0.0, field="ising", trotter="sym", seed=0,
                alpha=-0.5, n_col=2, prec_threshold=0.0, prop_width=1.0) -> Model:
     L = int(round(beta / dtau))

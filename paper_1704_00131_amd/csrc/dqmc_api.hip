@@ -1429,6 +1429,21 @@ const char* dqmc_last_error(const dqmc_ctx* c) { return c ? c->err.c_str() : "nu
 
 void dqmc_destroy(dqmc_ctx* c) { delete c; }
 
+dqmc_status dqmc_mz_frame_hopping(int32_t n, const double* T, double h, const double* sign, double* K_out) {
+  if (n < 1 || !T || !sign || !K_out || !std::isfinite(h)) return DQMC_E_ARG;
+  for (int i = 0; i < n; ++i)
+    if (sign[i] != 1.0 && sign[i] != -1.0) return DQMC_E_ARG;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      const double up = T[(size_t)i * n + j] - (i == j ? h : 0.0);                // K_1
+      const double dn = -sign[i] * (T[(size_t)j * n + i] + (i == j ? h : 0.0)) * sign[j];   // K_2
+      if (!std::isfinite(up) || up != dn) return DQMC_E_UNSUPPORTED;
+    }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) K_out[(size_t)i * n + j] = T[(size_t)i * n + j] - (i == j ? h : 0.0);
+  return DQMC_OK;
+}
+
 dqmc_status dqmc_hubbard_coupling(double U, double dtau, dqmc_field_kind kind, double* coupling) {
   if (!coupling || !(dtau > 0.0) || !std::isfinite(U)) return DQMC_E_ARG;
   if (kind == DQMC_FIELD_ISING) {

@@ -136,3 +136,24 @@ def test_correlation_entry_points_check_arguments_and_order(lib):
     assert lib.dqmc_td_read_corr_bins(ctx, out.ctypes.data, ctypes.byref(cnt)) == 6
     assert lib.dqmc_eq_read_bins(None, out.ctypes.data, ctypes.byref(cnt)) == 1
     lib.dqmc_destroy(ctx)
+
+
+def test_mz_frame_hopping_matches_oracle_and_refuses_two_flavours(lib):
+    """Host-only: the library's density-frame hopping for the M_z form with a
+    Zeeman field equals the oracle's (bit for bit) on square and honeycomb
+    lattices, and both refuse a chemical potential (two Green's functions)."""
+    import paper_1704_00131_amd as pa
+    from inputs import honeycomb_lattice, square_lattice
+    from oracle import hubbard
+    from paper_1704_00131_amd._lib import DQMCError
+    for lat in (square_lattice(4, 4), honeycomb_lattice(3, 3)):
+        for h in (0.0, 0.45):
+            got = pa.mz_frame_hopping(lat.K, h, lat.sublattice_sign())
+            assert np.array_equal(got, hubbard.mz_frame_hopping(lat.K, h, lat.sublattice_sign()))
+    lat = square_lattice(4, 4)
+    with pytest.raises(DQMCError) as e:
+        pa.mz_frame_hopping(lat.K - 0.2 * np.eye(lat.n), 0.45, lat.sublattice_sign())
+    assert e.value.status == 2
+    with pytest.raises(DQMCError) as e:
+        pa.mz_frame_hopping(lat.K, 0.45, 0.5 * lat.sublattice_sign())
+    assert e.value.status == 1
