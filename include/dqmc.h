@@ -229,6 +229,12 @@ dqmc_status dqmc_eq_setup(dqmc_ctx* ctx, int32_t L1, int32_t L2, int32_t norb, c
  * SpinZ, SpinXY, Den) and the number of measurements summed (count, may be
  * NULL).  Zeroed by dqmc_init, dqmc_reset_bins and dqmc_eq_setup. */
 dqmc_status dqmc_eq_read_bins(dqmc_ctx* ctx, double* sums_host, double* count);
+/* Bin sums of the one-point function <S^z> per orbital of the cell, summed
+ * with the correlations of bit 2: 1/n_cells sum_I 1/2 (1 - 2 G~_ii) for
+ * i = site(I, a) (n_up = n_1, n_dn = 1 - n_2 in the frame), norb host doubles,
+ * and the number of measurements (count, may be NULL).  Zeroed with the
+ * correlation bins. */
+dqmc_status dqmc_eq_read_spin_z(dqmc_ctx* ctx, double* sz_host, double* count);
 /* The same four correlators between tau and 0, from the time-displaced pass
  * (section "Measuring time displaced observables"), per configuration
  *   C_o[tau][R][a][b] += 1/n_cells sum_I <O_i(tau) O_j(0)>,  i = site(I, a), j = site(I + R, b),

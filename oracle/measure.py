@@ -88,3 +88,16 @@ def jackknife(values: np.ndarray):
     mean = loo.mean()
     err = np.sqrt((n - 1) / n * np.sum((loo - mean) ** 2))
     return float(mean), float(err)
+
+
+def eq_spin_z(model, lat, G: np.ndarray) -> np.ndarray:
+    """<S^z> per orbital of the unit cell, one configuration (the one-point
+    function of the section "Observables", averaged over cells): with the
+    down spin the particle-hole image of the second colour, n_up = n_1 and
+    n_dn = 1 - n_2, so <S^z_i> = 1/2 (<n_1> - 1 + <n_2>) = 1/2 (1 - 2 G~_ii)
+    (both colours carry G).  Returns [norb]: 1/N_cells sum_I <S^z_{site(I,a)}>."""
+    Gt = measured_green(model, G)
+    out = np.zeros(lat.norb)
+    for i in range(model.N):
+        out[lat.orb_of[i]] += 0.5 * (1.0 - 2.0 * Gt[i, i])
+    return out / (lat.L1 * lat.L2)

@@ -62,6 +62,7 @@ class Chain:
         self.eq_lat = None                # lattice for the lattice-resolved correlations, if measured
         self.eq_entries = None            # optional list of (R, a, b) to evaluate
         self.eq_bins = None
+        self.eq_sz = None
 
     # -- setup (Algorithm 1: confin, then the wrapul fill) ----------------------
     def init(self):
@@ -129,6 +130,9 @@ class Chain:
                 from .measure import eq_correlations
                 c = eq_correlations(self.m, self.eq_lat, self.G, self.eq_entries)
                 self.eq_bins = c if self.eq_bins is None else self.eq_bins + c
+                from .measure import eq_spin_z
+                mz = eq_spin_z(self.m, self.eq_lat, self.G)
+                self.eq_sz = mz if self.eq_sz is None else self.eq_sz + mz
 
     def _stabilise(self, G_s, G_cmp):
         self.prec.append(float(np.max(np.abs(G_cmp - G_s))))

@@ -186,6 +186,14 @@ class Chain:
         self._chk(self.lib.dqmc_eq_read_bins(self.ctx, out.ctypes.data, ctypes.byref(cnt)))
         return out, cnt.value
 
+    def eq_read_spin_z(self):
+        """Bin sums of <S^z> per orbital of the cell [norb] and the number of
+        measurements summed."""
+        out = np.empty(max(1, self.eq_shape[1]))
+        cnt = ctypes.c_double()
+        self._chk(self.lib.dqmc_eq_read_spin_z(self.ctx, out.ctypes.data, ctypes.byref(cnt)))
+        return out[: self.eq_shape[1]], cnt.value
+
     def td_read_corr_bins(self):
         """Bin sums [L+1, 4, n_cells, norb, norb] of the lattice-resolved
         time-displaced correlations and the number of passes summed."""

@@ -21,7 +21,8 @@
 // One wavefront per (R, a, b): its lanes take the cells I = lane, lane + 64, ...
 // and a butterfly reduction sums them (four waves per workgroup, so N_cells
 // norb^2 / 4 workgroups); the wave past the last entry adds 1 to *count when
-// count is non-null.  site[I * norb + a] is the orbital index of orbital a of
+// count is non-null and, for equal time, the per-orbital <S^z> to
+// bins[4 nb + 1 + a].  site[I * norb + a] is the orbital index of orbital a of
 // cell I (a permutation of 0..N-1, checked on the host); cells are I = i1 + L1 i2.
 template <bool TD>
 __global__ __launch_bounds__(256) void k_corr(const double* A, const double* H, const double* GTT, const double* g00,
@@ -39,6 +40,19 @@ __global__ __launch_bounds__(256) void k_corr(const double* A, const double* H, 
   const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (e > nb) return;
   if (e == nb) {
+    if (!TD) {
+      // one-point function: bins[4 nb + 1 + a] += 1/N_cells sum_I <S^z_{site(I, a)}>,
+      // <S^z_i> = 1/2 (1 - 2 G~_ii) (n_up = n_1, n_dn = 1 - n_2)
+      for (int oa = 0; oa < norb; ++oa) {
+        double m = 0.0;
+        for (int I = lane; I < nc; I += 64) {
+          const int i = site[I * norb + oa];
+          m += 0.5 * (1.0 - 2.0 * A[(size_t)i * N + i]);
+        }
+        for (int off = 32; off > 0; off >>= 1) m += __shfl_xor(m, off, 64);
+        if (lane == 0) bins[4 * (size_t)nb + 1 + oa] += m / nc;
+      }
+    }
     if (lane == 0 && count) *count += 1.0;
     return;
   }

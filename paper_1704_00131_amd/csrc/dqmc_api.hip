@@ -130,8 +130,9 @@ dqmc_status fail(dqmc_ctx* c, dqmc_status s, const std::string& msg) {
   } while (0)
 
 constexpr int kEqMaxOrb = 4;   // orbitals per unit cell of the lattice-resolved correlations
-// Four correlators of N_cells * norb^2 entries each (at most 4 N kEqMaxOrb), then the count.
-inline size_t eq_bins_size(const dqmc_ctx* c) { return 4 * (size_t)c->N * kEqMaxOrb + 4; }
+// Four correlators of N_cells * norb^2 entries each (at most 4 N kEqMaxOrb), then the
+// count, then <S^z> per orbital.
+inline size_t eq_bins_size(const dqmc_ctx* c) { return 4 * (size_t)c->N * kEqMaxOrb + 8; }
 inline size_t td_corr_stride(const dqmc_ctx* c) { return 4 * (size_t)c->N * kEqMaxOrb; }
 inline size_t td_corr_size(const dqmc_ctx* c) {
   return c->nch == 1 ? (size_t)(c->L + 1) * td_corr_stride(c) + 4 : 0;
@@ -1340,6 +1341,19 @@ dqmc_status dqmc_eq_read_bins(dqmc_ctx* c, double* sums_host, double* count) {
   HIPCHK(hipStreamSynchronize(c->stream));
   std::copy(raw.begin(), raw.begin() + 4 * nb, sums_host);
   if (count) *count = raw.back();
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_eq_read_spin_z(dqmc_ctx* c, double* sz_host, double* count) {
+  if (!c || !sz_host) return DQMC_E_ARG;
+  if (!c->bound || c->eq_norb < 1) return fail(c, DQMC_E_STATE, "lattice-resolved correlations not set up");
+  const size_t nb = (size_t)c->eq_L1 * c->eq_L2 * c->eq_norb * c->eq_norb;
+  double raw[1 + kEqMaxOrb];
+  HIPCHK(hipMemcpyAsync(raw, c->eq_bins + 4 * nb, (1 + c->eq_norb) * sizeof(double), hipMemcpyDeviceToHost,
+                        c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (int a = 0; a < c->eq_norb; ++a) sz_host[a] = raw[1 + a];
+  if (count) *count = raw[0];
   return DQMC_OK;
 }
 

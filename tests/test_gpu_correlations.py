@@ -43,6 +43,8 @@ def test_eq_correlation_bins_match_oracle(kind, L1, L2, beta, trotter, seed, swe
     n_meas = 2 * om.L * sweeps
     assert cnt == n_meas == oc.bins[3]
     assert maxabs(got, oc.eq_bins) < 1e-9 * n_meas
+    sz, c2 = ch.eq_read_spin_z()
+    assert c2 == cnt and sz.shape == (lat.norb,) and maxabs(sz, oc.eq_sz) < 1e-9 * n_meas
     assert np.all(np.isfinite(got))
     # bins restart from zero
     ch.reset_bins()
@@ -156,6 +158,8 @@ def test_eq_correlations_honeycomb12_sampled_entries():
     assert cnt == 200
     for e, (R, a, b) in enumerate(entries):
         assert maxabs(got[:, R, a, b], oc.eq_bins[:, e]) < 1e-9 * cnt, (R, a, b)
+    sz, _ = ch.eq_read_spin_z()
+    assert maxabs(sz, oc.eq_sz) < 1e-9 * cnt
 
 
 def test_td_correlations_honeycomb18_sampled():
@@ -186,7 +190,7 @@ def test_td_correlations_honeycomb18_sampled():
 def test_reading_correlation_bins_before_setup_is_refused():
     om, ch, lat = pair("square", 4, 4, 4.0, 1.0, 0.1, 5, seed=0)
     ch.random_field().init()
-    for read in (ch.eq_read_bins, ch.td_read_corr_bins):
+    for read in (ch.eq_read_bins, ch.eq_read_spin_z, ch.td_read_corr_bins):
         with pytest.raises(DQMCError) as e:
             read()
         assert e.value.status == DQMC_E_STATE

@@ -46,6 +46,9 @@ def test_zeeman_chain_matches_oracle(kind, L1, L2, h, trotter, seed, sweeps):
     got, cnt = ch.eq_read_bins()
     assert cnt == oc.bins[3]
     assert maxabs(got, oc.eq_bins) < 1e-9 * cnt
+    sz, c2 = ch.eq_read_spin_z()
+    assert c2 == cnt and maxabs(sz, oc.eq_sz) < 1e-9 * cnt
+    assert np.min(sz / cnt) > 1e-3                 # the field polarises every orbital
     # the field breaks the spin symmetry: SpinZ and SpinXY differ away from
     # R = 0 (on a site they agree for every configuration)
     assert np.max(np.abs(got[1] - got[2])) / cnt > 1e-3

@@ -512,6 +512,7 @@ def test_eq_correlations_enumeration_equals_fock(trotter, h):
     from the original-frame fermions (no particle-hole map); h > 0 adds the
     M_z form's Zeeman field (frame hopping K = T - h)."""
     from oracle import exact_small, measure
+    from oracle.stable import green_scratch, log_weight
     lat = honeycomb_lattice(1, 2)
     U, dtau, L = 4.0, 0.25, 2
     K = hubbard.mz_frame_hopping(lat.K, h, lat.sublattice_sign())
@@ -541,6 +542,18 @@ def test_eq_correlations_enumeration_equals_fock(trotter, h):
                     for o, O in enumerate(ops(site[I, a], site[J, b])):
                         want[o, R, a, b] += F.expect_with(S, O, L) / nc
     assert np.max(np.abs(got - want)) < 1e-12, (trotter, np.max(np.abs(got - want), axis=(1, 2, 3)))
+    # <S^z> per orbital, averaged over cells
+    logw, sz = [], []
+    for f in exact_small.all_fields(m):
+        logw.append(log_weight(m, f))
+        sz.append(measure.eq_spin_z(m, lat, green_scratch(m, f, 0)))
+    w = np.exp(np.array(logw) - max(logw))
+    sz_want = np.zeros(norb)
+    for I in range(nc):
+        for a in range(norb):
+            sz_want[a] += F.expect_with(S, F.sz(site[I, a]), L) / nc
+    assert np.max(np.abs(w @ np.array(sz) / w.sum() - sz_want)) < 1e-12
+    assert (np.min(sz_want) > 1e-3) == (h > 0.0)
     # SU(2): the z and xy spin correlations agree on average (not per
     # configuration); the Zeeman field breaks it
     if h == 0.0:
