@@ -20,14 +20,16 @@ def _site(lat):
     return site
 
 
-@pytest.mark.parametrize("kind,L1,L2,beta,trotter,seed,sweeps", [
-    ("square", 4, 4, 2.0, "sym", 3, 3),
-    ("honeycomb", 6, 6, 2.0, "asym", 1, 1),     # N = 72: a ragged last block
-    ("honeycomb", 3, 3, 2.0, "sym", 2, 2),
+@pytest.mark.parametrize("kind,L1,L2,beta,trotter,seed,sweeps,field", [
+    ("square", 4, 4, 2.0, "sym", 3, 3, "ising"),
+    ("honeycomb", 6, 6, 2.0, "asym", 1, 1, "ising"),     # N = 72: a ragged last block
+    ("honeycomb", 3, 3, 2.0, "sym", 2, 2, "ising"),
+    ("square", 4, 4, 2.0, "sym", 6, 2, "gauss"),
+    ("honeycomb", 3, 3, 2.0, "asym", 7, 2, "ising4"),
 ])
-def test_eq_correlation_bins_match_oracle(kind, L1, L2, beta, trotter, seed, sweeps):
-    print(f"correlations {kind} {L1}x{L2} {trotter} seed {seed}", flush=True)
-    om, ch, lat = pair(kind, L1, L2, 4.0, beta, 0.1, 10, trotter=trotter, seed=seed)
+def test_eq_correlation_bins_match_oracle(kind, L1, L2, beta, trotter, seed, sweeps, field):
+    print(f"correlations {kind} {L1}x{L2} {trotter} seed {seed} field {field}", flush=True)
+    om, ch, lat = pair(kind, L1, L2, 4.0, beta, 0.1, 10, trotter=trotter, seed=seed, field=field)
     ch.random_field().init()
     ch.eq_setup(L1, L2, _site(lat), lat.sublattice_sign())
     f0, _ = ch.get_state()
@@ -79,19 +81,21 @@ def test_eq_setup_rejects_bad_maps():
 KVEC = np.array([4.0 * np.pi / 3.0, 0.0])
 
 
-@pytest.mark.parametrize("kind,L1,L2,beta,n_wrap,trotter", [
-    ("honeycomb", 3, 3, 2.0, 5, "sym"),
-    ("honeycomb", 5, 5, 1.6, 4, "asym"),
-    ("square", 10, 10, 1.0, 5, "asym"),     # 100 cells: more than one cell per lane
-    ("honeycomb", 6, 6, 1.0, 5, "asym"),    # K = (4 pi/3, 0) on the grid: ties to S(K, tau)
+@pytest.mark.parametrize("kind,L1,L2,beta,n_wrap,trotter,field", [
+    ("honeycomb", 3, 3, 2.0, 5, "sym", "ising"),
+    ("honeycomb", 5, 5, 1.6, 4, "asym", "ising"),
+    ("square", 10, 10, 1.0, 5, "asym", "ising"),     # 100 cells: more than one cell per lane
+    ("honeycomb", 6, 6, 1.0, 5, "asym", "ising"),    # K = (4 pi/3, 0) on the grid: ties to S(K, tau)
+    ("honeycomb", 3, 3, 1.0, 5, "sym", "gauss"),
+    ("honeycomb", 3, 3, 1.0, 5, "asym", "ising4"),
 ])
-def test_td_correlation_bins_match_oracle(kind, L1, L2, beta, n_wrap, trotter):
+def test_td_correlation_bins_match_oracle(kind, L1, L2, beta, n_wrap, trotter, field):
     """Sweeps with the time-displaced pass and its lattice-resolved
     correlations: every tau of the start-of-sweep configuration against the
     oracle's from-scratch GT0 / G0T / GTT, summed over two sweeps."""
     from oracle import timedisplaced as otd
-    print(f"td correlations {kind} {L1}x{L2} beta={beta} n_wrap={n_wrap} {trotter}", flush=True)
-    om, ch, lat = pair(kind, L1, L2, 4.0, beta, 0.1, n_wrap, trotter=trotter, seed=4)
+    print(f"td correlations {kind} {L1}x{L2} beta={beta} n_wrap={n_wrap} {trotter} field {field}", flush=True)
+    om, ch, lat = pair(kind, L1, L2, 4.0, beta, 0.1, n_wrap, trotter=trotter, seed=4, field=field)
     ph = np.exp(-1j * (lat.cell_pos[lat.cell_of] @ KVEC))
     ch.td_setup(lat.orb_of, ph, lat.n_cells)
     ch.eq_setup(L1, L2, _site(lat), lat.sublattice_sign())
