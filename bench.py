@@ -107,7 +107,10 @@ def _square_batch(pa, layout, beta, field="ising", U=4.0, dtau=0.1, n_wrap=10):
 def bench_batched(torch, pa):
     """512 chains (256 x 8x8, 128 x 6x6, 128 x 10x10; U = 4, beta = 8, L = 80):
     autotuned, one sweep per captured graph.  Batched vs plain at N = 64:
-    256 chains of 8x8 in one batch against one 8x8 chain per launch sequence."""
+    256 chains of 8x8 in one batch against one 8x8 chain per launch sequence;
+    the 256-chain batch also with the lattice-resolved correlations."""
+    import numpy as np
+
     from inputs import batched_chain_layout, square_lattice
     out = {}
     lam = pa.hubbard_coupling(4.0, 0.1)
@@ -130,6 +133,14 @@ def bench_batched(torch, pa):
         out[name] = {"chains": len(lay), "sweeps_per_s": 2 / dt, "chain_sweeps_per_s": 2 * len(lay) / dt,
                      "updates_per_s": (st.proposals - st0.proposals) / dt,
                      "gemm_tiles": sorted({b.tuning(i) for i in range(len(lay))})}
+        if name == "n64x256":
+            # the same batch measuring the lattice-resolved correlations on every slice
+            site = np.arange(64, dtype=np.int32).reshape(64, 1)
+            b.eq_setup(0, 8, 8, site, lat.sublattice_sign())
+            b.capture(1, measure=True, correlations=True)
+            b.sweep(1, correlations=True)
+            dtc, _ = _sync_time(torch, lambda: b.sweep(2, correlations=True))
+            out[name]["sweeps_per_s_with_correlations"] = 2 / dtc
         b.close()
     out["plain_n64_sweeps_per_s"] = plain
     out["batched_vs_plain_n64"] = out["n64x256"]["chain_sweeps_per_s"] / plain

@@ -298,13 +298,30 @@ dqmc_status dqmc_batch_autotune(dqmc_batch* b, int32_t trials);
 /* The GEMM tile chosen for a chain's group (0 = size-based default). */
 dqmc_status dqmc_batch_tuning(const dqmc_batch* b, int32_t chain, int32_t* gemm_tile);
 /* Record `sweeps_per_graph` sweeps of the whole batch into a hipGraph; later
- * dqmc_batch_sweep calls with the same measure flag replay it. */
+ * dqmc_batch_sweep calls with the same measure flags replay it.  measure:
+ * bit 0 the equal-time estimators, bit 2 the lattice-resolved equal-time
+ * correlations of the groups set up with dqmc_batch_eq_setup (others skip
+ * them); other bits DQMC_E_ARG. */
 dqmc_status dqmc_batch_capture(dqmc_batch* b, int32_t sweeps_per_graph, int32_t measure);
-/* n_sweeps sweeps of every chain; stats summed over chains. */
+/* n_sweeps sweeps of every chain (measure as for dqmc_batch_capture); stats
+ * summed over chains. */
 dqmc_status dqmc_batch_sweep(dqmc_batch* b, int32_t n_sweeps, int32_t measure, dqmc_stats* total);
 /* G (n*n host doubles), bin sums (4 host doubles) and statistics of one chain. */
 dqmc_status dqmc_batch_read_chain(dqmc_batch* b, int32_t chain, double* G_host, double* bins_host,
                                   dqmc_stats* stats);
+/* Lattice-resolved equal-time correlations (as dqmc_eq_setup) for every chain
+ * of `chain`'s group (chains with the same model but the seed share the
+ * lattice); zeroes their correlation bins and drops a captured graph.  Each
+ * chain keeps its own bins. */
+dqmc_status dqmc_batch_eq_setup(dqmc_batch* b, int32_t chain, int32_t L1, int32_t L2, int32_t norb,
+                                const int32_t* site, const double* sign);
+/* One chain's correlation bins: shape[2] (may be NULL) receives n_cells and
+ * norb; sums_host (may be NULL) the 4 * n_cells * norb * norb sums of
+ * dqmc_eq_read_bins; sz_host (may be NULL) the norb sums of
+ * dqmc_eq_read_spin_z; count (may be NULL) the measurements summed.
+ * DQMC_E_STATE if the chain's group is not set up. */
+dqmc_status dqmc_batch_eq_read(dqmc_batch* b, int32_t chain, int32_t* shape, double* sums_host, double* sz_host,
+                               double* count);
 /* Gradient pass (as dqmc_grad_logdet) of every chain, kept on the device. */
 dqmc_status dqmc_batch_grad_logdet(dqmc_batch* b);
 /* The last gradient of one chain: L*n host doubles [L][n]; prec may be NULL. */

@@ -65,13 +65,37 @@ class Batch:
         self._chk(self.lib.dqmc_batch_tuning(self.b, chain, ctypes.byref(v)))
         return v.value
 
-    def capture(self, sweeps_per_graph=1, measure=True):
-        self._chk(self.lib.dqmc_batch_capture(self.b, sweeps_per_graph, 1 if measure else 0))
+    def capture(self, sweeps_per_graph=1, measure=True, correlations=False):
+        flags = (1 if measure else 0) | (4 if correlations else 0)
+        self._chk(self.lib.dqmc_batch_capture(self.b, sweeps_per_graph, flags))
 
-    def sweep(self, n_sweeps=1, measure=True) -> Stats:
+    def sweep(self, n_sweeps=1, measure=True, correlations=False) -> Stats:
         st = Stats()
-        self._chk(self.lib.dqmc_batch_sweep(self.b, n_sweeps, 1 if measure else 0, ctypes.byref(st)))
+        flags = (1 if measure else 0) | (4 if correlations else 0)
+        self._chk(self.lib.dqmc_batch_sweep(self.b, n_sweeps, flags, ctypes.byref(st)))
         return st
+
+    def eq_setup(self, chain, L1, L2, site, sign):
+        """Lattice-resolved equal-time correlations for every chain of
+        `chain`'s group: site [n_cells, norb], sign [N] (as Chain.eq_setup)."""
+        st = np.ascontiguousarray(site, dtype=np.int32)
+        sg = np.ascontiguousarray(sign, dtype=np.float64)
+        if st.ndim != 2 or sg.shape != (self.models[chain].n,):
+            raise ValueError("site must be [n_cells, norb], sign [N]")
+        self._chk(self.lib.dqmc_batch_eq_setup(self.b, chain, int(L1), int(L2), st.shape[1], st.ctypes.data,
+                                               sg.ctypes.data))
+        return self
+
+    def eq_read(self, chain):
+        """(sums [4, n_cells, norb, norb], <S^z> sums [norb], count) of one chain."""
+        shape = (ctypes.c_int32 * 2)()
+        self._chk(self.lib.dqmc_batch_eq_read(self.b, chain, ctypes.cast(shape, ctypes.c_void_p), None, None, None))
+        nc, no = shape[0], shape[1]
+        sums = np.empty((4, nc, no, no))
+        sz = np.empty(no)
+        cnt = ctypes.c_double()
+        self._chk(self.lib.dqmc_batch_eq_read(self.b, chain, None, sums.ctypes.data, sz.ctypes.data, ctypes.byref(cnt)))
+        return sums, sz, cnt.value
 
     def read_chain(self, chain):
         m = self.models[chain]

@@ -1704,13 +1704,21 @@ dqmc_status dqmc_batch_init(dqmc_batch* b) {
   return DQMC_OK;
 }
 
+// Sweep flags of one group for a batch call's measure flags: bit 0 the
+// equal-time estimators, bit 2 the lattice-resolved correlations where the
+// group has been set up for them.
+int group_flags(const dqmc_ctx* c, int measure) {
+  return (measure & 1) | (((measure & 4) && c->eq_norb > 0) ? 4 : 0);
+}
+
 dqmc_status dqmc_batch_sweep(dqmc_batch* b, int32_t n_sweeps, int32_t measure, dqmc_stats* st) {
   if (!b || n_sweeps < 0) return bfail(b, DQMC_E_ARG, "bad arguments");
+  if (measure & ~5) return bfail(b, DQMC_E_ARG, "unknown measurement flags");
   for (dqmc_ctx* c : b->groups)
     if (!c->bound || !c->initialized || c->poisoned) return bfail(b, DQMC_E_STATE, "batch not initialised");
   const auto t0 = std::chrono::steady_clock::now();
   int left = n_sweeps;
-  if (b->gexec && b->graph_measure == (measure ? 1 : 0)) {
+  if (b->gexec && b->graph_measure == measure) {
     while (left >= b->graph_sweeps) {
       BHIPCHK_(hipGraphLaunch(b->gexec, b->stream));
       left -= b->graph_sweeps;
@@ -1718,7 +1726,7 @@ dqmc_status dqmc_batch_sweep(dqmc_batch* b, int32_t n_sweeps, int32_t measure, d
   }
   for (int s = 0; s < left; ++s)
     for (dqmc_ctx* c : b->groups)
-      if (dqmc_status r = sweep_once(c, measure ? 1 : 0)) return bfail(b, r, c->err);
+      if (dqmc_status r = sweep_once(c, group_flags(c, measure))) return bfail(b, r, c->err);
   if (dqmc_status r = batch_flags(b)) return r;
   const auto t1 = std::chrono::steady_clock::now();
   if (st) {
@@ -1742,6 +1750,7 @@ dqmc_status dqmc_batch_sweep(dqmc_batch* b, int32_t n_sweeps, int32_t measure, d
 
 dqmc_status dqmc_batch_capture(dqmc_batch* b, int32_t sweeps_per_graph, int32_t measure) {
   if (!b || sweeps_per_graph < 1) return bfail(b, DQMC_E_ARG, "bad arguments");
+  if (measure & ~5) return bfail(b, DQMC_E_ARG, "unknown measurement flags");
   if (!b->bound) return bfail(b, DQMC_E_STATE, "not bound");
   if (!b->stream) return bfail(b, DQMC_E_ARG, "graph capture needs a stream other than the null stream");
   for (dqmc_ctx* c : b->groups)
@@ -1752,13 +1761,13 @@ dqmc_status dqmc_batch_capture(dqmc_batch* b, int32_t sweeps_per_graph, int32_t 
   dqmc_status st = DQMC_OK;
   for (int s = 0; s < sweeps_per_graph && st == DQMC_OK; ++s)
     for (dqmc_ctx* c : b->groups)
-      if ((st = sweep_once(c, measure ? 1 : 0)) != DQMC_OK) break;
+      if ((st = sweep_once(c, group_flags(c, measure))) != DQMC_OK) break;
   hipError_t ce = hipStreamEndCapture(b->stream, &b->graph);
   if (st != DQMC_OK) return bfail(b, st, "capture failed");
   BHIPCHK_(ce);
   BHIPCHK_(hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
   b->graph_sweeps = sweeps_per_graph;
-  b->graph_measure = measure ? 1 : 0;
+  b->graph_measure = measure;
   return DQMC_OK;
 }
 
@@ -1817,6 +1826,37 @@ dqmc_status dqmc_batch_read_chain(dqmc_batch* b, int32_t chain, double* G_host, 
   BHIPCHK_(hipStreamSynchronize(b->stream));
   if (st)
     if (dqmc_status r = chain_stats(c, i, st)) return bfail(b, r, c->err);
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_batch_eq_setup(dqmc_batch* b, int32_t chain, int32_t L1, int32_t L2, int32_t norb,
+                                const int32_t* site, const double* sign) {
+  if (!b || chain < 0 || chain >= (int)b->group_of.size()) return bfail(b, DQMC_E_ARG, "bad arguments");
+  if (!b->bound) return bfail(b, DQMC_E_STATE, "not bound");
+  dqmc_ctx* c = b->groups[b->group_of[chain]];
+  if (dqmc_status s = dqmc_eq_setup(c, L1, L2, norb, site, sign)) return bfail(b, s, c->err);
+  // a captured graph was recorded without (or with other) correlations
+  if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
+  if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_batch_eq_read(dqmc_batch* b, int32_t chain, int32_t* shape, double* sums_host, double* sz_host,
+                               double* count) {
+  if (!b || chain < 0 || chain >= (int)b->group_of.size()) return bfail(b, DQMC_E_ARG, "bad arguments");
+  if (!b->bound) return bfail(b, DQMC_E_STATE, "not bound");
+  dqmc_ctx* c = b->groups[b->group_of[chain]];
+  if (c->eq_norb < 1) return bfail(b, DQMC_E_STATE, "lattice-resolved correlations not set up for this chain's group");
+  const size_t nb = (size_t)c->eq_L1 * c->eq_L2 * c->eq_norb * c->eq_norb;
+  if (shape) { shape[0] = c->eq_L1 * c->eq_L2; shape[1] = c->eq_norb; }
+  if (!sums_host && !sz_host && !count) return DQMC_OK;
+  std::vector<double> raw(4 * nb + 1 + c->eq_norb);
+  BHIPCHK_(hipMemcpyAsync(raw.data(), c->eq_bins + (size_t)b->index_of[chain] * c->cs, raw.size() * sizeof(double),
+                          hipMemcpyDeviceToHost, b->stream));
+  BHIPCHK_(hipStreamSynchronize(b->stream));
+  if (sums_host) std::copy(raw.begin(), raw.begin() + 4 * nb, sums_host);
+  if (count) *count = raw[4 * nb];
+  if (sz_host) std::copy(raw.begin() + 4 * nb + 1, raw.end(), sz_host);
   return DQMC_OK;
 }
 

@@ -115,3 +115,48 @@ def test_batch_autotune_keeps_trajectory():
         G, _, _ = b.read_chain(i)
         assert np.array_equal(f, oc.field)
         assert maxabs(G, oc.G) < 1e-9
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_lattice_correlations(graph):
+    """Lattice-resolved equal-time correlations in a batch: two groups (4x4
+    square chains and 3x3 honeycomb chains), each set up through one of its
+    chains; every chain's bins and <S^z> against its own oracle chain, with
+    plain sweeps or a replayed graph.  A group without the set-up is refused
+    on read and sweeps on without correlations."""
+    from paper_1704_00131_amd._lib import DQMCError
+    _log(f"batch correlations graph={graph}")
+    specs = [("square", 4, 4, 0), ("honeycomb", 3, 3, 1), ("square", 4, 4, 2), ("honeycomb", 3, 3, 3),
+             ("square", 6, 6, 4)]
+    b, oms = _batch(specs, 1.0, 5)
+    b.random_fields().init()
+    lats = [lattice(k, L1, L2) for (k, L1, L2, _) in specs]
+    for ch in (0, 1):
+        lat = lats[ch]
+        site = np.full((lat.n_cells, lat.norb), -1, dtype=np.int32)
+        site[lat.cell_of, lat.orb_of] = np.arange(lat.n)
+        b.eq_setup(ch, lat.L1, lat.L2, site, lat.sublattice_sign())
+    ocs = []
+    for i, om in enumerate(oms):
+        f0, _ = b.get_state(i)
+        oc = osweep.Chain(om, f0).init()
+        if i < 4:
+            oc.eq_lat = lats[i]
+        ocs.append(oc)
+    if graph:
+        b.capture(1, measure=True, correlations=True)
+    b.sweep(2, measure=True, correlations=True)
+    for oc in ocs:
+        oc.sweep(measure=True)
+        oc.sweep(measure=True)
+    for i, oc in enumerate(ocs):
+        f, _ = b.get_state(i)
+        assert oc.min_tie > 1e-9
+        assert np.array_equal(f, oc.field), f"chain {i}"
+        if i < 4:
+            sums, sz, cnt = b.eq_read(i)
+            assert cnt == oc.bins[3] == 4 * oms[i].L
+            assert maxabs(sums, oc.eq_bins) < 1e-9 * cnt, f"chain {i}"
+            assert maxabs(sz, oc.eq_sz) < 1e-9 * cnt, f"chain {i}"
+        else:
+            with pytest.raises(DQMCError):
+                b.eq_read(i)
