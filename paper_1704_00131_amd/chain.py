@@ -173,8 +173,9 @@ class Chain:
         sg = np.ascontiguousarray(sign, dtype=np.float64)
         if st.ndim != 2 or sg.shape != (self.N,):
             raise ValueError("site must be [n_cells, norb], sign [N]")
-        self.eq_shape = (st.shape[0], st.shape[1])
         self._chk(self.lib.dqmc_eq_setup(self.ctx, int(L1), int(L2), st.shape[1], st.ctypes.data, sg.ctypes.data))
+        # recorded only once the library holds this lattice (the read buffers are sized from it)
+        self.eq_shape = (st.shape[0], st.shape[1])
         return self
 
     def eq_read_bins(self):

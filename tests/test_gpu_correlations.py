@@ -76,6 +76,13 @@ def test_eq_setup_rejects_bad_maps():
     ch.sweep(1, correlations=True)
     _, cnt = ch.eq_read_bins()
     assert cnt == 2 * om.L
+    # a failed re-set-up leaves the working one (and the binding's shape) in place
+    bad4 = site.reshape(4, 4).copy()
+    bad4[0, 0] = bad4[0, 1]                     # 4 orbitals per cell, not a permutation
+    with pytest.raises(DQMCError):
+        ch.eq_setup(2, 2, bad4, lat.sublattice_sign())
+    got, cnt = ch.eq_read_bins()
+    assert got.shape == (4, 16, 1, 1) and cnt == 2 * om.L
 
 
 KVEC = np.array([4.0 * np.pi / 3.0, 0.0])
