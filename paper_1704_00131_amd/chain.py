@@ -54,6 +54,7 @@ class Chain:
         self.N = model.n
         self.L = model.n_slices
         self.eq_shape = (0, 0)    # (n_cells, norb) once eq_setup has run; the library refuses reads before
+        self.td_norb = 0          # orbitals per cell once td_setup has run; likewise
         sizes = Sizes()
         check(lib.dqmc_query_sizes(ctypes.byref(model), ctypes.byref(sizes)))
         self.sizes = sizes
@@ -147,8 +148,9 @@ class Chain:
         orb_of [N] ints, phase [N] complex exp(-i K.R_cell(x))."""
         orb = np.ascontiguousarray(orb_of, dtype=np.int32)
         ph = np.ascontiguousarray(np.stack([np.real(phase), np.imag(phase)], axis=1), dtype=np.float64)
-        self.td_norb = int(orb.max()) + 1
-        self._chk(self.lib.dqmc_td_setup(self.ctx, self.td_norb, orb.ctypes.data, ph.ctypes.data, n_cells))
+        norb = int(orb.max()) + 1
+        self._chk(self.lib.dqmc_td_setup(self.ctx, norb, orb.ctypes.data, ph.ctypes.data, n_cells))
+        self.td_norb = norb        # only once the library holds it (the read buffers are sized from it)
         return self
 
     def td_measure(self):

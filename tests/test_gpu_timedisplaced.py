@@ -79,3 +79,16 @@ def test_td_honeycomb18_sampled_tau():
         GT0, G0T, GTT = otd.tdgf_scratch(om, f0, tau)
         want = otd.szsz_k(om, lat, KVEC, GT0, G0T, GTT, G00)
         assert maxabs(S[tau], want) < 1e-9, tau
+
+
+def test_td_refused_setup_keeps_the_working_one():
+    """A refused re-set-up (non-finite phases, one orbital) leaves the working
+    two-orbital set-up, and the binding keeps sizing reads for it."""
+    from paper_1704_00131_amd._lib import DQMCError
+    om, ch, lat, f0 = _setup("honeycomb", 3, 3, 4.0, 1.0, 5, "asym", seed=3)
+    ch.sweep(1, measure=False, time_displaced=True)
+    bad = np.full(lat.n, np.nan, dtype=complex)
+    with pytest.raises(DQMCError):
+        ch.td_setup(np.zeros(lat.n, dtype=np.int32), bad, lat.n_cells)
+    sums, count = ch.td_read_bins()
+    assert sums.shape == (om.L + 1, 2, 2) and count == 1
