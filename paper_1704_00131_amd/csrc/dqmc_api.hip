@@ -626,12 +626,14 @@ dqmc_status measure(dqmc_ctx* c) {
 
 // Lattice-resolved equal-time correlations of the current configuration,
 // added to the bins, from G~ = e^{-dtau K/2} G e^{+dtau K/2} (symmetric split)
-// or G (asymmetric split).
-dqmc_status eq_measure(dqmc_ctx* c) {
+// or G (asymmetric split).  t1_ready: T1 already holds e^{-dtau K/2} G of this
+// configuration (the equal-time estimators ran just before).
+dqmc_status eq_measure(dqmc_ctx* c, bool t1_ready) {
   const int N = c->N;
   const double* Gt = c->Gcur;
   if (c->m.trotter == DQMC_TROTTER_SYM) {
-    if (dqmc_status s = gemm(c, gemm_args(N, N, N, c->Eh, N, 0, c->Gcur, N, 0, c->T1, N))) return s;
+    if (!t1_ready)
+      if (dqmc_status s = gemm(c, gemm_args(N, N, N, c->Eh, N, 0, c->Gcur, N, 0, c->T1, N))) return s;
     if (dqmc_status s = gemm(c, gemm_args(N, N, N, c->T1, N, 0, c->Ehinv, N, 0, c->Gs, N))) return s;
     Gt = c->Gs;
   }
@@ -710,7 +712,7 @@ dqmc_status sweep_once(dqmc_ctx* c, int meas) {
     if (meas & 1)
       if (dqmc_status s = measure(c)) return s;
     if (meas & 4)
-      if (dqmc_status s = eq_measure(c)) return s;
+      if (dqmc_status s = eq_measure(c, (meas & 1) != 0)) return s;
   }
   if (dqmc_status s = pass_draws(c, 1)) return s;
   for (int tau = L; tau >= 1; --tau) {
@@ -718,7 +720,7 @@ dqmc_status sweep_once(dqmc_ctx* c, int meas) {
     if (meas & 1)
       if (dqmc_status s = measure(c)) return s;
     if (meas & 4)
-      if (dqmc_status s = eq_measure(c)) return s;
+      if (dqmc_status s = eq_measure(c, (meas & 1) != 0)) return s;
     if ((tau - 1) % nw == 0) {
       const int k = (tau - 1) / nw;
       // wrapped G(tau-1), compared against the recomputed one below

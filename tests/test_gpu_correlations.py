@@ -205,3 +205,23 @@ def test_reading_correlation_bins_before_setup_is_refused():
         with pytest.raises(DQMCError) as e:
             read()
         assert e.value.status == DQMC_E_STATE
+
+
+def test_eq_correlations_without_the_estimators_sym():
+    """Symmetric split, correlations measured without the equal-time
+    estimators (the rotation then forms e^{-dtau K/2} G itself)."""
+    print("correlations without estimators, square 4x4 sym", flush=True)
+    om, ch, lat = pair("square", 4, 4, 4.0, 2.0, 0.1, 10, trotter="sym", seed=9)
+    ch.random_field().init()
+    ch.eq_setup(4, 4, _site(lat), lat.sublattice_sign())
+    f0, _ = ch.get_state()
+    oc = osweep.Chain(om, f0).init()
+    oc.eq_lat = lat
+    ch.sweep(2, measure=False, correlations=True)
+    oc.sweep(measure=True)
+    oc.sweep(measure=True)
+    assert oc.min_tie > 1e-9
+    got, cnt = ch.eq_read_bins()
+    assert cnt == oc.bins[3]
+    assert maxabs(got, oc.eq_bins) < 1e-9 * cnt
+    assert not np.any(ch.read_bins())          # the estimators were not measured
