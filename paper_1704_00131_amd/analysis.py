@@ -14,6 +14,10 @@ gives one row per bin.  Everything here works on such host arrays, shape
                         series for lags 0..n (N_auto);
 - covariance(x)         the covariance of the bin means of a vector
                         observable, e.g. S(k, tau) over tau (N_Cov);
+- spin_total(C)         the rotation-averaged spin correlation
+                        (S^x S^x + S^y S^y + S^z S^z)/3 from the SpinZ and
+                        SpinXY bins (the improved estimator of the error
+                        analysis section);
 - momentum_grid(lat)    the L1 x L2 momenta of the Bravais torus;
 - to_momentum(C, lat, k) a correlation stored by displacement R (the
                         lattice-resolved bins) at momenta k:
@@ -116,3 +120,14 @@ def to_momentum(C, lat, kvecs) -> np.ndarray:
     C = np.asarray(C, dtype=np.float64)
     ph = np.exp(1j * (np.asarray(kvecs, dtype=np.float64).reshape(-1, 2) @ displacements(lat).T))   # [k, R]
     return np.einsum("kr,...rab->...kab", ph, C)
+
+
+def spin_total(C) -> np.ndarray:
+    """(<S^x S^x> + <S^y S^y> + <S^z S^z>)/3 from correlation bins ordered
+    Green, SpinZ, SpinXY, Den on the first axis ([4, ...]; for time-displaced
+    bins [L+1, 4, ...] pass them with that axis first, e.g. np.moveaxis(C, 1,
+    0)).  SpinXY holds half of S^x S^x + S^y S^y, so the sum is
+    (SpinZ + 2 SpinXY)/3.  Its average equals SpinZ's where the spin symmetry
+    holds, and it fluctuates less between configurations."""
+    C = np.asarray(C, dtype=np.float64)
+    return (C[1] + 2.0 * C[2]) / 3.0

@@ -110,3 +110,33 @@ def test_momentum_transform_matches_the_site_double_sum():
     assert np.max(np.abs(back - C[1])) < 1e-12
     # every correlator at once: leading axes are kept
     assert an.to_momentum(C, lat, ks[:3]).shape == (4, 3, 2, 2)
+
+
+def test_spin_total_equals_fock_s_dot_s():
+    """(SpinZ + 2 SpinXY)/3 of the exactly enumerated correlation bins equals
+    the Fock-space <S_i . S_j>/3 with the Zeeman field on (where SpinZ and
+    SpinXY differ, so a wrong weight fails)."""
+    from fock import Fock
+    from inputs import honeycomb_lattice
+    from oracle import exact_small, hubbard
+    lat = honeycomb_lattice(1, 2)
+    U, dtau, L, h = 4.0, 0.25, 2, 0.6
+    m = hubbard.hubbard_model(hubbard.mz_frame_hopping(lat.K, h, lat.sublattice_sign()), U, L * dtau, dtau, 1,
+                              trotter="asym")
+    C = exact_small.enumerate_eq_correlations(m, lat, tau=0)
+    F = Fock(lat.K, U, h)
+    S = F.trotter_asym(dtau)
+    c = F.c
+    site = {(int(lat.cell_of[i]), int(lat.orb_of[i])): i for i in range(lat.n)}
+    want = np.zeros((lat.n_cells, 2, 2))
+    for I in range(lat.n_cells):
+        for R in range(lat.n_cells):
+            J = (I % lat.L1 + R % lat.L1) % lat.L1 + lat.L1 * ((I // lat.L1 + R // lat.L1) % lat.L2)
+            for a in range(2):
+                for b in range(2):
+                    i, j = site[I, a], site[J, b]
+                    sp_i, sp_j = c[2 * i].T @ c[2 * i + 1], c[2 * j].T @ c[2 * j + 1]
+                    sdots = F.sz(i) @ F.sz(j) + 0.5 * (sp_i @ sp_j.T + sp_i.T @ sp_j)
+                    want[R, a, b] += F.expect_with(S, sdots, L) / 3.0 / lat.n_cells
+    assert np.max(np.abs(an.spin_total(C) - want)) < 1e-12
+    assert np.max(np.abs(C[1] - want)) > 1e-3
