@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 from gpu_util import maxabs, pair
+from oracle import hubbard as ohub
 from oracle import sweep as osweep
 from paper_1704_00131_amd._lib import DQMCError
 
@@ -225,3 +226,61 @@ def test_eq_correlations_without_the_estimators_sym():
     assert cnt == oc.bins[3]
     assert maxabs(got, oc.eq_bins) < 1e-9 * cnt
     assert not np.any(ch.read_bins())          # the estimators were not measured
+
+
+def _square_as_supercells(L):
+    """The L x L square lattice viewed as an (L/2) x (L/2) lattice of 2 x 2
+    cells with four orbitals (o = dx + 2 dy): the largest orbital count of the
+    correlation bins.  The checkerboard signs of the square lattice stay."""
+    from inputs import square_lattice
+    from inputs.lattices import Lattice
+    sq = square_lattice(L, L)
+    x, y = np.arange(L * L) % L, np.arange(L * L) // L
+    cell_of = (x // 2) + (L // 2) * (y // 2)
+    orb_of = (x % 2) + 2 * (y % 2)
+    h = L // 2
+    cell_pos = np.array([[2.0 * (c % h), 2.0 * (c // h)] for c in range(h * h)])
+    lat = Lattice("square-2x2-cells", h, h, 4, np.array([2.0, 0.0]), np.array([0.0, 2.0]), sq.K, cell_of, orb_of,
+                  cell_pos)
+    signs = sq.sublattice_sign()
+    lat.sublattice_sign = lambda: signs
+    return lat
+
+
+@pytest.mark.parametrize("trotter", ["sym", "asym"])
+def test_correlations_with_four_orbitals_per_cell(trotter):
+    """norb = 4 (the maximum; the time-displaced bins then fill their stride
+    exactly): equal-time bins over two sweeps and the time-displaced bins of
+    the two passes against the oracle, on the 4x4 square lattice as 2 x 2
+    cells of four orbitals."""
+    from oracle import timedisplaced as otd
+    import paper_1704_00131_amd as pa
+    print(f"correlations with four orbitals per cell, {trotter}", flush=True)
+    lat = _square_as_supercells(4)
+    U, beta, dtau, n_wrap = 4.0, 1.0, 0.1, 5
+    om = ohub.hubbard_model(lat.K, U, beta, dtau, n_wrap, trotter=trotter, seed=11)
+    ch = pa.Chain(pa.make_model(lat.n, beta, dtau, n_wrap, pa.hubbard_coupling(U, dtau), U=U, trotter=trotter,
+                                seed=11), lat.K)
+    ch.td_setup(lat.orb_of, np.ones(lat.n, dtype=complex), lat.n_cells)
+    ch.eq_setup(lat.L1, lat.L2, _site(lat), lat.sublattice_sign())
+    ch.random_field()
+    f0, _ = ch.get_state()
+    ch.init()
+    oc = osweep.Chain(om, f0).init()
+    oc.eq_lat = lat
+    want_td = 0.0
+    for _ in range(2):
+        want_td = want_td + otd.tdgf_correlations(om, lat, oc.field)
+        oc.sweep(measure=True)
+    ch.sweep(2, measure=True, time_displaced=True, correlations=True, td_correlations=True)
+    assert oc.min_tie > 1e-9
+    f, _ = ch.get_state()
+    assert np.array_equal(f, oc.field)
+    got, cnt = ch.eq_read_bins()
+    assert got.shape == (4, 4, 4, 4) and cnt == oc.bins[3]
+    assert maxabs(got, oc.eq_bins) < 1e-9 * cnt
+    sz, _ = ch.eq_read_spin_z()
+    assert maxabs(sz, oc.eq_sz) < 1e-9 * cnt
+    got_td, c2 = ch.td_read_corr_bins()
+    assert c2 == 2 and got_td.shape == want_td.shape
+    assert maxabs(got_td, want_td) < 2e-9
