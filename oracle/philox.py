@@ -4,7 +4,7 @@ Written from the published definition of Salmon, Moraes, Dror and Shaw,
 "Parallel random numbers: as easy as 1, 2, 3" (SC'11): ten rounds of two
 64x64->128-bit multiplications with the multipliers M0, M1, the key bumped by
 the Weyl constants W0, W1 between rounds.  The paper itself only has a seeds
-file (section "Input files"); the addressing below is this build's reading:
+file (section "Input files"); the addressing below is a reading of our own:
 
     key     = (chain seed, 0)
     counter = (stream tag, sweep, (tau << 1) | direction, site)
