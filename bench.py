@@ -108,7 +108,8 @@ def bench_batched(torch, pa):
     """512 chains (256 x 8x8, 128 x 6x6, 128 x 10x10; U = 4, beta = 8, L = 80):
     autotuned, one sweep per captured graph.  Batched vs plain at N = 64:
     256 chains of 8x8 in one batch against one 8x8 chain per launch sequence;
-    the 256-chain batch also with the lattice-resolved correlations."""
+    the 256-chain batch also with the lattice-resolved correlations and with
+    the time-displaced pass."""
     import numpy as np
 
     from inputs import batched_chain_layout, square_lattice
@@ -141,6 +142,13 @@ def bench_batched(torch, pa):
             b.sweep(1, correlations=True)
             dtc, _ = _sync_time(torch, lambda: b.sweep(2, correlations=True))
             out[name]["sweeps_per_s_with_correlations"] = 2 / dtc
+            # and with the time-displaced pass (S^z-S^z at K = (pi, pi)) at the start of each sweep
+            ph = np.exp(-1j * (lat.cell_pos[lat.cell_of] @ np.array([np.pi, np.pi])))
+            b.td_setup(0, lat.orb_of, ph, lat.n_cells)
+            b.capture(1, measure=True, time_displaced=True)
+            b.sweep(1, time_displaced=True)
+            dtt, _ = _sync_time(torch, lambda: b.sweep(2, time_displaced=True))
+            out[name]["sweeps_per_s_with_time_displaced"] = 2 / dtt
         b.close()
     out["plain_n64_sweeps_per_s"] = plain
     out["batched_vs_plain_n64"] = out["n64x256"]["chain_sweeps_per_s"] / plain

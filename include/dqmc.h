@@ -299,9 +299,11 @@ dqmc_status dqmc_batch_autotune(dqmc_batch* b, int32_t trials);
 dqmc_status dqmc_batch_tuning(const dqmc_batch* b, int32_t chain, int32_t* gemm_tile);
 /* Record `sweeps_per_graph` sweeps of the whole batch into a hipGraph; later
  * dqmc_batch_sweep calls with the same measure flags replay it.  measure:
- * bit 0 the equal-time estimators, bit 2 the lattice-resolved equal-time
- * correlations of the groups set up with dqmc_batch_eq_setup (others skip
- * them); other bits DQMC_E_ARG. */
+ * bit 0 the equal-time estimators, bit 1 the time-displaced pass at the start
+ * of each sweep for the groups set up with dqmc_batch_td_setup, bit 2 the
+ * lattice-resolved equal-time correlations of the groups set up with
+ * dqmc_batch_eq_setup (groups without a set-up skip that part); other bits
+ * DQMC_E_ARG. */
 dqmc_status dqmc_batch_capture(dqmc_batch* b, int32_t sweeps_per_graph, int32_t measure);
 /* n_sweeps sweeps of every chain (measure as for dqmc_batch_capture); stats
  * summed over chains. */
@@ -309,6 +311,15 @@ dqmc_status dqmc_batch_sweep(dqmc_batch* b, int32_t n_sweeps, int32_t measure, d
 /* G (n*n host doubles), bin sums (4 host doubles) and statistics of one chain. */
 dqmc_status dqmc_batch_read_chain(dqmc_batch* b, int32_t chain, double* G_host, double* bins_host,
                                   dqmc_stats* stats);
+/* Time-displaced measurement (as dqmc_td_setup) for every chain of `chain`'s
+ * group; zeroes their time-displaced bins and drops a captured graph. */
+dqmc_status dqmc_batch_td_setup(dqmc_batch* b, int32_t chain, int32_t norb, const int32_t* orb_of,
+                                const double* phase, int32_t n_cells);
+/* One chain's time-displaced bins: norb (may be NULL) receives the group's
+ * orbitals per cell; sums_host (may be NULL) the sums in the layout of
+ * dqmc_td_read_bins ((L+1)*norb*norb*2 host doubles); count (may be NULL) the
+ * passes summed.  DQMC_E_STATE if the chain's group is not set up. */
+dqmc_status dqmc_batch_td_read_bins(dqmc_batch* b, int32_t chain, int32_t* norb, double* sums_host, double* count);
 /* Lattice-resolved equal-time correlations (as dqmc_eq_setup) for every chain
  * of `chain`'s group (chains with the same model but the seed share the
  * lattice); zeroes their correlation bins and drops a captured graph.  Each

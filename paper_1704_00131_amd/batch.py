@@ -65,15 +65,34 @@ class Batch:
         self._chk(self.lib.dqmc_batch_tuning(self.b, chain, ctypes.byref(v)))
         return v.value
 
-    def capture(self, sweeps_per_graph=1, measure=True, correlations=False):
-        flags = (1 if measure else 0) | (4 if correlations else 0)
+    def capture(self, sweeps_per_graph=1, measure=True, correlations=False, time_displaced=False):
+        flags = (1 if measure else 0) | (2 if time_displaced else 0) | (4 if correlations else 0)
         self._chk(self.lib.dqmc_batch_capture(self.b, sweeps_per_graph, flags))
 
-    def sweep(self, n_sweeps=1, measure=True, correlations=False) -> Stats:
+    def sweep(self, n_sweeps=1, measure=True, correlations=False, time_displaced=False) -> Stats:
         st = Stats()
-        flags = (1 if measure else 0) | (4 if correlations else 0)
+        flags = (1 if measure else 0) | (2 if time_displaced else 0) | (4 if correlations else 0)
         self._chk(self.lib.dqmc_batch_sweep(self.b, n_sweeps, flags, ctypes.byref(st)))
         return st
+
+    def td_setup(self, chain, orb_of, phase, n_cells):
+        """Time-displaced S^z-S^z measurement for every chain of `chain`'s
+        group (as Chain.td_setup)."""
+        orb = np.ascontiguousarray(orb_of, dtype=np.int32)
+        ph = np.ascontiguousarray(np.stack([np.real(phase), np.imag(phase)], axis=1), dtype=np.float64)
+        norb = int(orb.max()) + 1
+        self._chk(self.lib.dqmc_batch_td_setup(self.b, chain, norb, orb.ctypes.data, ph.ctypes.data, n_cells))
+        return self
+
+    def td_read_bins(self, chain):
+        """(S sums [L+1, norb, norb] complex, passes summed) of one chain; the
+        chain's group must be set up (through any of its chains)."""
+        no = ctypes.c_int32()
+        self._chk(self.lib.dqmc_batch_td_read_bins(self.b, chain, ctypes.byref(no), None, None))
+        raw = np.empty((self.models[chain].n_slices + 1, no.value, no.value, 2))
+        cnt = ctypes.c_double()
+        self._chk(self.lib.dqmc_batch_td_read_bins(self.b, chain, None, raw.ctypes.data, ctypes.byref(cnt)))
+        return raw[..., 0] + 1j * raw[..., 1], cnt.value
 
     def eq_setup(self, chain, L1, L2, site, sign):
         """Lattice-resolved equal-time correlations for every chain of

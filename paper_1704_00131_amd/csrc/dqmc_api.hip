@@ -1707,15 +1707,15 @@ dqmc_status dqmc_batch_init(dqmc_batch* b) {
 }
 
 // Sweep flags of one group for a batch call's measure flags: bit 0 the
-// equal-time estimators, bit 2 the lattice-resolved correlations where the
-// group has been set up for them.
+// equal-time estimators, bit 1 the time-displaced pass and bit 2 the
+// lattice-resolved correlations, each where the group has been set up for it.
 int group_flags(const dqmc_ctx* c, int measure) {
-  return (measure & 1) | (((measure & 4) && c->eq_norb > 0) ? 4 : 0);
+  return (measure & 1) | (((measure & 2) && c->td_norb > 0) ? 2 : 0) | (((measure & 4) && c->eq_norb > 0) ? 4 : 0);
 }
 
 dqmc_status dqmc_batch_sweep(dqmc_batch* b, int32_t n_sweeps, int32_t measure, dqmc_stats* st) {
   if (!b || n_sweeps < 0) return bfail(b, DQMC_E_ARG, "bad arguments");
-  if (measure & ~5) return bfail(b, DQMC_E_ARG, "unknown measurement flags");
+  if (measure & ~7) return bfail(b, DQMC_E_ARG, "unknown measurement flags");
   for (dqmc_ctx* c : b->groups)
     if (!c->bound || !c->initialized || c->poisoned) return bfail(b, DQMC_E_STATE, "batch not initialised");
   const auto t0 = std::chrono::steady_clock::now();
@@ -1752,7 +1752,7 @@ dqmc_status dqmc_batch_sweep(dqmc_batch* b, int32_t n_sweeps, int32_t measure, d
 
 dqmc_status dqmc_batch_capture(dqmc_batch* b, int32_t sweeps_per_graph, int32_t measure) {
   if (!b || sweeps_per_graph < 1) return bfail(b, DQMC_E_ARG, "bad arguments");
-  if (measure & ~5) return bfail(b, DQMC_E_ARG, "unknown measurement flags");
+  if (measure & ~7) return bfail(b, DQMC_E_ARG, "unknown measurement flags");
   if (!b->bound) return bfail(b, DQMC_E_STATE, "not bound");
   if (!b->stream) return bfail(b, DQMC_E_ARG, "graph capture needs a stream other than the null stream");
   for (dqmc_ctx* c : b->groups)
@@ -1840,6 +1840,33 @@ dqmc_status dqmc_batch_eq_setup(dqmc_batch* b, int32_t chain, int32_t L1, int32_
   // a captured graph was recorded without (or with other) correlations
   if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
   if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_batch_td_setup(dqmc_batch* b, int32_t chain, int32_t norb, const int32_t* orb_of,
+                                const double* phase, int32_t n_cells) {
+  if (!b || chain < 0 || chain >= (int)b->group_of.size()) return bfail(b, DQMC_E_ARG, "bad arguments");
+  if (!b->bound) return bfail(b, DQMC_E_STATE, "not bound");
+  dqmc_ctx* c = b->groups[b->group_of[chain]];
+  if (dqmc_status s = dqmc_td_setup(c, norb, orb_of, phase, n_cells)) return bfail(b, s, c->err);
+  if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
+  if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_batch_td_read_bins(dqmc_batch* b, int32_t chain, int32_t* norb, double* sums_host, double* count) {
+  if (!b || chain < 0 || chain >= (int)b->group_of.size()) return bfail(b, DQMC_E_ARG, "bad arguments");
+  if (!b->bound) return bfail(b, DQMC_E_STATE, "not bound");
+  dqmc_ctx* c = b->groups[b->group_of[chain]];
+  if (c->td_norb < 1) return bfail(b, DQMC_E_STATE, "time-displaced measurement not set up for this chain's group");
+  if (norb) *norb = c->td_norb;
+  if (!sums_host && !count) return DQMC_OK;
+  std::vector<double> raw((size_t)(c->L + 1) * kTdStride + 1);
+  BHIPCHK_(hipMemcpyAsync(raw.data(), c->tdbins + (size_t)b->index_of[chain] * c->cs, raw.size() * sizeof(double),
+                          hipMemcpyDeviceToHost, b->stream));
+  BHIPCHK_(hipStreamSynchronize(b->stream));
+  if (sums_host) td_compact(c, raw.data(), sums_host);
+  if (count) *count = raw.back();
   return DQMC_OK;
 }
 

@@ -160,3 +160,48 @@ def test_batch_lattice_correlations(graph):
         else:
             with pytest.raises(DQMCError):
                 b.eq_read(i)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_time_displaced_pass(graph):
+    """The time-displaced pass in a batch: two set-up groups (3x3 honeycomb
+    chains, asymmetric split, and 4x4 square chains) and one without; every
+    set-up chain's S(K, tau) bins over two sweeps against the oracle's
+    from-scratch S of its start-of-sweep fields, with plain or replayed sweeps,
+    and the trajectories unchanged."""
+    from oracle import timedisplaced as otd
+    from paper_1704_00131_amd._lib import DQMCError
+    _log(f"batch time-displaced graph={graph}")
+    kvec = np.array([4.0 * np.pi / 3.0, 0.0])
+    specs = [("honeycomb", 3, 3, 0), ("square", 4, 4, 1), ("honeycomb", 3, 3, 2), ("square", 4, 4, 3),
+             ("square", 6, 6, 4)]
+    b, oms = _batch(specs, 1.0, 5, trotter="asym")
+    b.random_fields().init()
+    lats = [lattice(k, L1, L2) for (k, L1, L2, _) in specs]
+    for ch in (0, 1):
+        lat = lats[ch]
+        b.td_setup(ch, lat.orb_of, np.exp(-1j * (lat.cell_pos[lat.cell_of] @ kvec)), lat.n_cells)
+    ocs = []
+    for i, om in enumerate(oms):
+        f0, _ = b.get_state(i)
+        ocs.append(osweep.Chain(om, f0).init())
+    want = [0.0] * len(specs)
+    for _ in range(2):
+        for i, oc in enumerate(ocs):
+            if i < 4:
+                want[i] = want[i] + otd.tdgf_measure(oms[i], lats[i], kvec, oc.field)
+            oc.sweep(measure=True)
+    if graph:
+        b.capture(1, measure=True, time_displaced=True)
+    b.sweep(2, measure=True, time_displaced=True)
+    for i, oc in enumerate(ocs):
+        f, _ = b.get_state(i)
+        assert oc.min_tie > 1e-9
+        assert np.array_equal(f, oc.field), f"chain {i}"
+        if i < 4:
+            S, cnt = b.td_read_bins(i)
+            assert cnt == 2 and S.shape == want[i].shape
+            assert maxabs(S, want[i]) < 2e-9, f"chain {i}"
+        else:
+            with pytest.raises(DQMCError):
+                b.td_read_bins(i)
