@@ -113,15 +113,24 @@ class Model:
     def B_inv(self, field: np.ndarray, tau: int) -> np.ndarray:
         return self.expK_inv * (1.0 / self.vdiag(field[tau - 1]))[None, :]
 
+    def vertex_log_factor(self, s) -> np.ndarray:
+        """log of the factor one vertex's field value carries in the weight
+        besides exp(N_col coupling alpha s): the Gaussian measure -phi^2/2 of
+        the continuous field, log gamma(l) of the four-valued field of
+        Eq. (HS_squares), zero for the two-valued field (elementwise)."""
+        s = np.asarray(s, dtype=np.float64)
+        if self.field_kind == "gauss":
+            return -0.5 * s * s
+        if self.field_kind == "ising4":
+            return np.log(np.array(GAMMA4))[ising4_index(s)]
+        return np.zeros_like(s)
+
     def prefactor_log(self, field: np.ndarray) -> float:
         """log of the field-dependent prefactor of Eq. (partition_2):
-        N_col * coupling * alpha * sum(field)  (plus -phi^2/2 for a Gaussian field)."""
+        N_col * coupling * alpha * sum(field) plus the vertex factors above."""
         f = np.asarray(field, dtype=np.float64)
         out = self.n_col * self.coupling * self.alpha * f.sum()
-        if self.field_kind == "gauss":
-            out -= 0.5 * np.sum(f * f)
-        if self.field_kind == "ising4":
-            out += float(np.sum(np.log(np.array(GAMMA4))[ising4_index(f)]))
+        out += float(np.sum(self.vertex_log_factor(f)))
         return float(out)
 
 

@@ -82,18 +82,18 @@ class Chain:
         s = self.field[tau - 1, i]
         if m.field_kind == "ising":
             s_new = -s
-            extra = 0.0
         elif m.field_kind == "ising4":
             # one of the three other values of the four-valued field, equally likely
-            from .hubbard import ETA4, GAMMA4, ising4_index
+            from .hubbard import ETA4, ising4_index
             k = int(ising4_index(s))
             j = min(int(3.0 * u1), 2)
             kn = j if j < k else j + 1
             s_new = ETA4[kn]
-            extra = float(np.log(GAMMA4[kn])) - float(np.log(GAMMA4[k]))
         else:
             s_new = s + m.prop_width * (2.0 * u1 - 1.0)
-            extra = -0.5 * (s_new * s_new - s * s)
+        # the change of the vertex's own factor in the weight (zero, the
+        # Gaussian measure, or gamma(l') / gamma(l))
+        extra = float(m.vertex_log_factor(s_new)) - float(m.vertex_log_factor(s))
         delta = np.exp(m.coupling * (s_new - s)) - 1.0
         r = 1.0 + delta * (1.0 - self.G[i, i])
         R = np.exp(m.n_col * m.coupling * m.alpha * (s_new - s) + extra) * r ** m.n_col
