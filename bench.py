@@ -163,8 +163,8 @@ def bench_gradient(torch, pa):
     b.random_fields().init()
     b.grad_logdet()
     dtg, _ = _sync_time(torch, lambda: [b.grad_logdet() for _ in range(3)])
-    dtl, _ = _sync_time(torch, lambda: b.langevin(1e-3, 3, first_step=0))
-    dtm, _ = _sync_time(torch, lambda: (b.sweep(1, measure=False), b.langevin(1e-3, 10, first_step=3)))
+    dtl, _ = _sync_time(torch, lambda: b.langevin(1e-3, 3))
+    dtm, _ = _sync_time(torch, lambda: (b.sweep(1, measure=False), b.langevin(1e-3, 10)))
     b.close()
     return {"chains": 64, "gradients_per_s": 3 * 64 / dtg, "gradient_entries_per_s": 3 * 64 * 40 * 100 / dtg,
             "langevin_steps_per_s": 3 * 64 / dtl, "mc_steps_per_s": 64 / dtm}

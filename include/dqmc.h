@@ -173,13 +173,20 @@ dqmc_status dqmc_logdet(dqmc_ctx* ctx, double* logdet);
  * G, field and stored forms are unchanged. */
 dqmc_status dqmc_grad_logdet(dqmc_ctx* ctx, double* grad_dev, double* prec);
 
-/* n_steps unadjusted Langevin steps of a Gaussian field, step k using
- * Philox counter (tag 3, first_step + k, tau << 1, site):
+/* n_steps unadjusted Langevin steps of a Gaussian field:
  *   phi <- phi + eps (-phi + n_col coupling alpha + n_col grad) + sqrt(2 eps) xi,
- * xi standard normal (Box-Muller, cosine branch), grad as in dqmc_grad_logdet.
- * After each step the stored forms and G(0) are rebuilt from the new field.
- * DQMC_E_UNSUPPORTED for an Ising field; eps must be positive and finite. */
-dqmc_status dqmc_langevin(dqmc_ctx* ctx, double eps, int32_t n_steps, uint64_t first_step);
+ * xi standard normal (Box-Muller, cosine branch) from Philox counter
+ * (tag 3, step, tau << 1, site), grad as in dqmc_grad_logdet.  step is the
+ * chain's Langevin step counter, kept on the device: it starts at 0
+ * (dqmc_random_field, dqmc_bind) and advances by one per step, so successive
+ * calls never reuse noise.  After each step the stored forms and G(0) are
+ * rebuilt from the new field.  DQMC_E_UNSUPPORTED for an Ising field; eps
+ * must be positive and finite. */
+dqmc_status dqmc_langevin(dqmc_ctx* ctx, double eps, int32_t n_steps);
+/* The Langevin step counter, read and set (part of the chain's state beside
+ * the field and the sweep counter, for resuming a run). */
+dqmc_status dqmc_get_langevin_step(dqmc_ctx* ctx, uint64_t* step);
+dqmc_status dqmc_set_langevin_step(dqmc_ctx* ctx, uint64_t step);
 
 /* ---- time-displaced Green's functions (section "Measuring time displaced
  * observables"; Eq. (s_corr)) ----
@@ -337,8 +344,11 @@ dqmc_status dqmc_batch_eq_read(dqmc_batch* b, int32_t chain, int32_t* shape, dou
 dqmc_status dqmc_batch_grad_logdet(dqmc_batch* b);
 /* The last gradient of one chain: L*n host doubles [L][n]; prec may be NULL. */
 dqmc_status dqmc_batch_read_grad(dqmc_batch* b, int32_t chain, double* grad_host, double* prec);
-/* n_steps Langevin steps (as dqmc_langevin) of every chain; Gaussian fields only. */
-dqmc_status dqmc_batch_langevin(dqmc_batch* b, double eps, int32_t n_steps, uint64_t first_step);
+/* n_steps Langevin steps (as dqmc_langevin) of every chain, each with its own
+ * step counter; Gaussian fields only. */
+dqmc_status dqmc_batch_langevin(dqmc_batch* b, double eps, int32_t n_steps);
+dqmc_status dqmc_batch_get_langevin_step(dqmc_batch* b, int32_t chain, uint64_t* step);
+dqmc_status dqmc_batch_set_langevin_step(dqmc_batch* b, int32_t chain, uint64_t step);
 int32_t dqmc_batch_groups(const dqmc_batch* b);
 /* Host-only self-check of the batch buffer layout (no device access). */
 dqmc_status dqmc_batch_check_layout(dqmc_batch* b);

@@ -24,12 +24,14 @@ from . import philox
 from .stable import green_scratch, logdet_scratch
 
 
-def grad_logdet(model, field):
-    """[L, N]: d log det(1 + B(beta,0)) / d phi, from scratch G(tau) for every tau."""
-    g = np.empty((model.L, model.N))
-    for tau in range(1, model.L + 1):
+def grad_logdet(model, field, taus=None):
+    """[L, N]: d log det(1 + B(beta,0)) / d phi, from scratch G(tau) for every
+    tau (or [len(taus), N] for the listed slices only)."""
+    taus = range(1, model.L + 1) if taus is None else taus
+    g = np.empty((len(taus), model.N))
+    for k, tau in enumerate(taus):
         G = green_scratch(model, field, tau)
-        g[tau - 1] = model.coupling * (1.0 - np.diag(G))
+        g[k] = model.coupling * (1.0 - np.diag(G))
     return g
 
 

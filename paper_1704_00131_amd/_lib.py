@@ -58,7 +58,9 @@ SIGNATURES = {
                                   ctypes.POINTER(ctypes.c_double)]),
     "dqmc_logdet": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
     "dqmc_grad_logdet": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
-    "dqmc_langevin": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int32, ctypes.c_uint64]),
+    "dqmc_langevin": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int32]),
+    "dqmc_get_langevin_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
+    "dqmc_set_langevin_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
     "dqmc_td_setup": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_int32]),
     "dqmc_td_measure": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
@@ -98,7 +100,9 @@ SIGNATURES = {
     "dqmc_batch_grad_logdet": (ctypes.c_int, [ctypes.c_void_p]),
     "dqmc_batch_read_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                             ctypes.POINTER(ctypes.c_double)]),
-    "dqmc_batch_langevin": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int32, ctypes.c_uint64]),
+    "dqmc_batch_langevin": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int32]),
+    "dqmc_batch_get_langevin_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)]),
+    "dqmc_batch_set_langevin_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64]),
     "dqmc_batch_groups": (ctypes.c_int32, [ctypes.c_void_p]),
     "dqmc_batch_check_layout": (ctypes.c_int, [ctypes.c_void_p]),
     "dqmc_batch_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),

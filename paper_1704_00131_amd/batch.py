@@ -79,6 +79,9 @@ class Batch:
         """Time-displaced S^z-S^z measurement for every chain of `chain`'s
         group (as Chain.td_setup)."""
         orb = np.ascontiguousarray(orb_of, dtype=np.int32)
+        n = self.models[chain].n
+        if orb.shape != (n,) or np.shape(phase) != (n,):
+            raise ValueError("orb_of and phase must both have the chain's length N")
         ph = np.ascontiguousarray(np.stack([np.real(phase), np.imag(phase)], axis=1), dtype=np.float64)
         norb = int(orb.max()) + 1
         self._chk(self.lib.dqmc_batch_td_setup(self.b, chain, norb, orb.ctypes.data, ph.ctypes.data, n_cells))
@@ -99,8 +102,8 @@ class Batch:
         `chain`'s group: site [n_cells, norb], sign [N] (as Chain.eq_setup)."""
         st = np.ascontiguousarray(site, dtype=np.int32)
         sg = np.ascontiguousarray(sign, dtype=np.float64)
-        if st.ndim != 2 or sg.shape != (self.models[chain].n,):
-            raise ValueError("site must be [n_cells, norb], sign [N]")
+        if st.ndim != 2 or st.shape[0] != int(L1) * int(L2) or sg.shape != (self.models[chain].n,):
+            raise ValueError("site must be [L1 * L2, norb], sign [N]")
         self._chk(self.lib.dqmc_batch_eq_setup(self.b, chain, int(L1), int(L2), st.shape[1], st.ctypes.data,
                                                sg.ctypes.data))
         return self
@@ -136,8 +139,19 @@ class Batch:
         self._chk(self.lib.dqmc_batch_read_grad(self.b, chain, g.ctypes.data, ctypes.byref(prec)))
         return g, prec.value
 
-    def langevin(self, eps, n_steps=1, first_step=0):
-        self._chk(self.lib.dqmc_batch_langevin(self.b, eps, n_steps, first_step))
+    def langevin(self, eps, n_steps=1):
+        """n_steps Langevin steps of every chain, each keyed by the chain's own
+        step counter on the device."""
+        self._chk(self.lib.dqmc_batch_langevin(self.b, eps, n_steps))
+        return self
+
+    def langevin_step(self, chain) -> int:
+        v = ctypes.c_uint64()
+        self._chk(self.lib.dqmc_batch_get_langevin_step(self.b, chain, ctypes.byref(v)))
+        return v.value
+
+    def set_langevin_step(self, chain, step):
+        self._chk(self.lib.dqmc_batch_set_langevin_step(self.b, chain, int(step)))
         return self
 
     def close(self):

@@ -139,14 +139,28 @@ class Chain:
         self._chk(self.lib.dqmc_grad_logdet(self.ctx, ctypes.c_void_p(out.data_ptr()), ctypes.byref(prec)))
         return out, prec.value
 
-    def langevin(self, eps: float, n_steps: int = 1, first_step: int = 0):
-        self._chk(self.lib.dqmc_langevin(self.ctx, eps, n_steps, first_step))
+    def langevin(self, eps: float, n_steps: int = 1):
+        """n_steps Langevin steps; the noise of each is keyed by the chain's
+        step counter on the device, which advances by one per step."""
+        self._chk(self.lib.dqmc_langevin(self.ctx, eps, n_steps))
+        return self
+
+    @property
+    def langevin_step(self) -> int:
+        v = ctypes.c_uint64()
+        self._chk(self.lib.dqmc_get_langevin_step(self.ctx, ctypes.byref(v)))
+        return v.value
+
+    def set_langevin_step(self, step: int):
+        self._chk(self.lib.dqmc_set_langevin_step(self.ctx, int(step)))
         return self
 
     def td_setup(self, orb_of, phase, n_cells: int):
         """Momentum and orbitals of the time-displaced S^z-S^z measurement:
         orb_of [N] ints, phase [N] complex exp(-i K.R_cell(x))."""
         orb = np.ascontiguousarray(orb_of, dtype=np.int32)
+        if orb.shape != (self.N,) or np.shape(phase) != (self.N,):
+            raise ValueError("orb_of and phase must both have length N")
         ph = np.ascontiguousarray(np.stack([np.real(phase), np.imag(phase)], axis=1), dtype=np.float64)
         norb = int(orb.max()) + 1
         self._chk(self.lib.dqmc_td_setup(self.ctx, norb, orb.ctypes.data, ph.ctypes.data, n_cells))
@@ -173,8 +187,8 @@ class Chain:
         sign [N] the sublattice signs (+1 / -1)."""
         st = np.ascontiguousarray(site, dtype=np.int32)
         sg = np.ascontiguousarray(sign, dtype=np.float64)
-        if st.ndim != 2 or sg.shape != (self.N,):
-            raise ValueError("site must be [n_cells, norb], sign [N]")
+        if st.ndim != 2 or st.shape[0] != int(L1) * int(L2) or sg.shape != (self.N,):
+            raise ValueError("site must be [L1 * L2, norb], sign [N]")
         self._chk(self.lib.dqmc_eq_setup(self.ctx, int(L1), int(L2), st.shape[1], st.ctypes.data, sg.ctypes.data))
         # recorded only once the library holds this lattice (the read buffers are sized from it)
         self.eq_shape = (st.shape[0], st.shape[1])

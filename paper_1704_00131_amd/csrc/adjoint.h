@@ -25,11 +25,12 @@ __global__ __launch_bounds__(256) void k_grad_diag(const double* G, int N, doubl
 //   d log W = -phi + n_col c alpha + n_col grad,
 //   phi <- phi + eps d log W + sqrt(2 eps) xi,
 // xi by Box-Muller (cosine branch) from Philox counter
-// (TAG_LANGEVIN, step, tau << 1, site) under the chain's key.
+// (TAG_LANGEVIN, step, tau << 1, site) under the chain's key, where step is
+// the chain's Langevin step counter (counters[4]); k_next_langevin_step
+// advances it once every workgroup of this launch has read it.
 __global__ __launch_bounds__(256) void k_langevin(double* field, const double* grad, int L, int N, double eps,
                                                   double coupling, double alpha, double n_col,
-                                                  unsigned long long step, const unsigned long long* counters,
-                                                  size_t cs) {
+                                                  const unsigned long long* counters, size_t cs) {
   const size_t co = (size_t)blockIdx.y * cs;
   field += co;
   grad += co;
@@ -37,11 +38,19 @@ __global__ __launch_bounds__(256) void k_langevin(double* field, const double* g
   const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= L * N) return;
   const int tau = e / N + 1, i = e % N;
-  const Philox4 w = philox4x64_10(TAG_LANGEVIN, step, (unsigned long long)tau << 1, (unsigned long long)i,
+  const Philox4 w = philox4x64_10(TAG_LANGEVIN, counters[4], (unsigned long long)tau << 1, (unsigned long long)i,
                                   counters[3], 0ull);
   const double u0 = unit_double(w.w[0]), u1 = unit_double(w.w[1]);
   const double xi = sqrt(-2.0 * log1p(-u0)) * cos(2.0 * M_PI * u1);
   const double phi = field[e];
   const double dlw = -phi + n_col * coupling * alpha + n_col * grad[e];
   field[e] = phi + eps * dlw + sqrt(2.0 * eps) * xi;
+}
+
+// counters[4] += 1 for every chain (one thread per chain, grid (1, chains)),
+// after the step that used it.
+__global__ void k_next_langevin_step(unsigned long long* counters, size_t cs) {
+  if (threadIdx.x != 0) return;
+  counters = reinterpret_cast<unsigned long long*>(reinterpret_cast<double*>(counters) + (size_t)blockIdx.y * cs);
+  counters[4] += 1ull;
 }

@@ -84,7 +84,7 @@ struct dqmc_ctx {
   // the diagonal of G00
   double *td_corr = nullptr, *td_g00 = nullptr;
   bool td_corr_now = false;
-  unsigned long long* counters = nullptr;   // proposals, accepted, sweep counter
+  unsigned long long* counters = nullptr;   // proposals, accepted, sweep counter, key, Langevin step
   int* err_flag = nullptr;
   size_t work_doubles = 0;
   // batching: nch chains with identical models except the seed; every
@@ -130,6 +130,9 @@ dqmc_status fail(dqmc_ctx* c, dqmc_status s, const std::string& msg) {
   } while (0)
 
 constexpr int kEqMaxOrb = 4;   // orbitals per unit cell of the lattice-resolved correlations
+// per-chain counters: [0] proposals, [1] accepted, [2] sweep counter, [3] Philox
+// key, [4] Langevin step counter (the rest reserved)
+constexpr int kCounters = 8;
 // Four correlators of N_cells * norb^2 entries each (at most 4 N kEqMaxOrb), then the
 // count, then <S^z> per orbital.
 inline size_t eq_bins_size(const dqmc_ctx* c) { return 4 * (size_t)c->N * kEqMaxOrb + 8; }
@@ -196,7 +199,7 @@ size_t layout_chain(dqmc_ctx* c, double* base) {
   P(c->td_corr, td_corr_size(c));
   double* ctr = nullptr;
   double* ef = nullptr;
-  P(ctr, 4); P(ef, 1);
+  P(ctr, kCounters); P(ef, 1);
   if (base) {
     c->piv = reinterpret_cast<int*>(pv);
     c->moves = reinterpret_cast<int*>(mv);
@@ -811,11 +814,13 @@ dqmc_status grad_pass(dqmc_ctx* c) {
 
 // One Langevin step of every chain: gradient pass, field update, then the
 // left storage and G(0) of the new field.
-dqmc_status langevin_once(dqmc_ctx* c, double eps, uint64_t step) {
+dqmc_status langevin_once(dqmc_ctx* c, double eps) {
   if (dqmc_status s = grad_pass(c)) return s;
   const size_t n = (size_t)c->L * c->N;
   hipLaunchKernelGGL(k_langevin, gridc(c, grid1(n)), dim3(256), 0, c->stream, c->field, c->grad, c->L, c->N, eps,
-                     c->m.coupling, c->m.alpha, (double)c->m.n_col, (unsigned long long)step, c->counters, c->cs);
+                     c->m.coupling, c->m.alpha, (double)c->m.n_col, c->counters, c->cs);
+  HIPCHK(hipGetLastError());
+  hipLaunchKernelGGL(k_next_langevin_step, dim3(1, c->nch), dim3(64), 0, c->stream, c->counters, c->cs);
   HIPCHK(hipGetLastError());
   return reanchor(c);
 }
@@ -1073,7 +1078,7 @@ dqmc_status setup_device(dqmc_ctx* c) {
   hipLaunchKernelGGL(k_set_identity, dim3(grid1((size_t)N * N)), dim3(256), 0, c->stream, c->uid.Q, N, N, (size_t)0);
   hipLaunchKernelGGL(k_set_identity, dim3(grid1((size_t)N * N)), dim3(256), 0, c->stream, c->uid.T, N, N, (size_t)0);
   if (dqmc_status s = fill_small(c, c->uid.D, N, 1.0)) return s;
-  if (dqmc_status s = fill_small(c, reinterpret_cast<double*>(c->counters), 4, 0.0)) return s;
+  if (dqmc_status s = fill_small(c, reinterpret_cast<double*>(c->counters), kCounters, 0.0)) return s;
   if (dqmc_status s = fill_small(c, reinterpret_cast<double*>(c->err_flag), 1, 0.0)) return s;
   // measurement partials and their completion counter
   if (dqmc_status s = fill_small(c, c->mpart, 4 * (size_t)((N + kMeasRows - 1) / kMeasRows) + 4, 0.0)) return s;
@@ -1145,6 +1150,7 @@ dqmc_status dqmc_random_field(dqmc_ctx* c) {
                      c->counters, (int)c->m.field, field4_table(), c->cs);
   HIPCHK(hipGetLastError());
   if (dqmc_status s = fill_small(c, reinterpret_cast<double*>(c->counters + 2), 1, 0.0)) return s;
+  if (dqmc_status s = fill_small(c, reinterpret_cast<double*>(c->counters + 4), 1, 0.0)) return s;
   HIPCHK(hipStreamSynchronize(c->stream));
   c->initialized = false;
   return DQMC_OK;
@@ -1285,13 +1291,32 @@ dqmc_status dqmc_grad_logdet(dqmc_ctx* c, double* grad_dev, double* prec) {
   return read_flag(c);
 }
 
-dqmc_status dqmc_langevin(dqmc_ctx* c, double eps, int32_t n_steps, uint64_t first_step) {
+dqmc_status dqmc_langevin(dqmc_ctx* c, double eps, int32_t n_steps) {
   if (!c || n_steps < 0 || !(eps > 0.0) || !std::isfinite(eps)) return fail(c, DQMC_E_ARG, "bad arguments");
   if (c->m.field != DQMC_FIELD_GAUSS) return fail(c, DQMC_E_UNSUPPORTED, "Langevin steps need a Gaussian field");
   if (!c->bound || !c->initialized || c->poisoned) return fail(c, DQMC_E_STATE, "context not initialised");
   for (int k = 0; k < n_steps; ++k)
-    if (dqmc_status s = langevin_once(c, eps, first_step + (uint64_t)k)) return s;
+    if (dqmc_status s = langevin_once(c, eps)) return s;
   return read_flag(c);
+}
+
+dqmc_status dqmc_get_langevin_step(dqmc_ctx* c, uint64_t* step) {
+  if (!c || !step) return fail(c, DQMC_E_ARG, "null argument");
+  if (!c->bound) return fail(c, DQMC_E_STATE, "not bound");
+  unsigned long long v = 0;
+  HIPCHK(hipMemcpyAsync(&v, c->counters + 4, sizeof(v), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  *step = v;
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_set_langevin_step(dqmc_ctx* c, uint64_t step) {
+  if (!c) return DQMC_E_ARG;
+  if (!c->bound) return fail(c, DQMC_E_STATE, "not bound");
+  unsigned long long v = step;
+  HIPCHK(hipMemcpyAsync(c->counters + 4, &v, sizeof(v), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return DQMC_OK;
 }
 
 dqmc_status dqmc_td_setup(dqmc_ctx* c, int32_t norb, const int32_t* orb_of, const double* phase, int32_t n_cells) {
@@ -1578,7 +1603,7 @@ bool layout_ok(const dqmc_ctx* c, const double* lo, const double* hi) {
        in(c->kph, 2 * N, false) && in(c->korb, N / 2 + 1, false) && in(c->eq_sign, N, false) &&
        in(c->eq_site, N / 2 + 1, false) && in(c->eq_bins, eq_bins_size(c), true) && in(c->td_g00, N, true) &&
        (td_corr_size(c) == 0 || in(c->td_corr, td_corr_size(c), true)) &&
-       in(c->counters, 4, true) && in(c->err_flag, 1, true);
+       in(c->counters, kCounters, true) && in(c->err_flag, 1, true);
   return ok;
 }
 
@@ -1910,7 +1935,7 @@ dqmc_status dqmc_batch_read_grad(dqmc_batch* b, int32_t chain, double* grad_host
   return DQMC_OK;
 }
 
-dqmc_status dqmc_batch_langevin(dqmc_batch* b, double eps, int32_t n_steps, uint64_t first_step) {
+dqmc_status dqmc_batch_langevin(dqmc_batch* b, double eps, int32_t n_steps) {
   if (!b || n_steps < 0 || !(eps > 0.0) || !std::isfinite(eps)) return bfail(b, DQMC_E_ARG, "bad arguments");
   for (dqmc_ctx* c : b->groups) {
     if (!c->bound || !c->initialized || c->poisoned) return bfail(b, DQMC_E_STATE, "batch not initialised");
@@ -1918,8 +1943,31 @@ dqmc_status dqmc_batch_langevin(dqmc_batch* b, double eps, int32_t n_steps, uint
   }
   for (int k = 0; k < n_steps; ++k)
     for (dqmc_ctx* c : b->groups)
-      if (dqmc_status s = langevin_once(c, eps, first_step + (uint64_t)k)) return bfail(b, s, c->err);
+      if (dqmc_status s = langevin_once(c, eps)) return bfail(b, s, c->err);
   return batch_flags(b);
+}
+
+dqmc_status dqmc_batch_get_langevin_step(dqmc_batch* b, int32_t chain, uint64_t* step) {
+  if (!b || !step || chain < 0 || chain >= (int)b->group_of.size()) return bfail(b, DQMC_E_ARG, "bad arguments");
+  if (!b->bound) return bfail(b, DQMC_E_STATE, "not bound");
+  dqmc_ctx* c = b->groups[b->group_of[chain]];
+  unsigned long long v = 0;
+  BHIPCHK_(hipMemcpyAsync(&v, reinterpret_cast<double*>(c->counters + 4) + (size_t)b->index_of[chain] * c->cs,
+                          sizeof(v), hipMemcpyDeviceToHost, b->stream));
+  BHIPCHK_(hipStreamSynchronize(b->stream));
+  *step = v;
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_batch_set_langevin_step(dqmc_batch* b, int32_t chain, uint64_t step) {
+  if (!b || chain < 0 || chain >= (int)b->group_of.size()) return bfail(b, DQMC_E_ARG, "bad arguments");
+  if (!b->bound) return bfail(b, DQMC_E_STATE, "not bound");
+  dqmc_ctx* c = b->groups[b->group_of[chain]];
+  unsigned long long v = step;
+  BHIPCHK_(hipMemcpyAsync(reinterpret_cast<double*>(c->counters + 4) + (size_t)b->index_of[chain] * c->cs, &v,
+                          sizeof(v), hipMemcpyHostToDevice, b->stream));
+  BHIPCHK_(hipStreamSynchronize(b->stream));
+  return DQMC_OK;
 }
 
 int32_t dqmc_batch_groups(const dqmc_batch* b) { return b ? (int32_t)b->groups.size() : 0; }

@@ -162,20 +162,20 @@ def test_batch_lattice_correlations(graph):
                 b.eq_read(i)
 
 
-@pytest.mark.parametrize("graph", [False, True])
-def test_batch_time_displaced_pass(graph):
+@pytest.mark.parametrize("graph,trotter", [(False, "asym"), (True, "asym"), (False, "sym"), (True, "sym")])
+def test_batch_time_displaced_pass(graph, trotter):
     """The time-displaced pass in a batch: two set-up groups (3x3 honeycomb
-    chains, asymmetric split, and 4x4 square chains) and one without; every
+    chains and 4x4 square chains) and one without, both Trotter splits; every
     set-up chain's S(K, tau) bins over two sweeps against the oracle's
     from-scratch S of its start-of-sweep fields, with plain or replayed sweeps,
     and the trajectories unchanged."""
     from oracle import timedisplaced as otd
     from paper_1704_00131_amd._lib import DQMCError
-    _log(f"batch time-displaced graph={graph}")
+    _log(f"batch time-displaced graph={graph} trotter={trotter}")
     kvec = np.array([4.0 * np.pi / 3.0, 0.0])
     specs = [("honeycomb", 3, 3, 0), ("square", 4, 4, 1), ("honeycomb", 3, 3, 2), ("square", 4, 4, 3),
              ("square", 6, 6, 4)]
-    b, oms = _batch(specs, 1.0, 5, trotter="asym")
+    b, oms = _batch(specs, 1.0, 5, trotter=trotter)
     b.random_fields().init()
     lats = [lattice(k, L1, L2) for (k, L1, L2, _) in specs]
     for ch in (0, 1):

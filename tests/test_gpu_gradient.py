@@ -92,17 +92,31 @@ def test_langevin_steps_match_oracle():
     om, ch, f0 = _gauss_pair("square", 4, 4, 2.0, 5, seed=7)
     eps = 1e-3
     f = f0.copy()
-    ch.langevin(eps, 1, first_step=0)
+    assert ch.langevin_step == 0
+    ch.langevin(eps, 1)
     f = ograd.langevin_step(om, f, eps, 0)
     got, _ = ch.get_state()
     assert maxabs(got, f) < 1e-9
-    ch.langevin(eps, 2, first_step=1)
+    # the next call continues the step counter (no noise reused)
+    ch.langevin(eps, 2)
     f = ograd.langevin_step(om, f, eps, 1)
     f = ograd.langevin_step(om, f, eps, 2)
     got, _ = ch.get_state()
     assert maxabs(got, f) < 1e-9
+    assert ch.langevin_step == 3
     # G(0) rebuilt from the new field
     assert maxabs(ch.G.cpu().numpy(), osweep.Chain(om, got).init().G) < 1e-10
+    # resuming elsewhere: the field, the sweep counter and the step counter
+    import paper_1704_00131_amd as pa
+    ch2 = pa.Chain(ch.model, om.K, device="cuda")
+    ch2.set_state(got, 0).set_langevin_step(3).init()
+    ch.langevin(eps, 1)
+    ch2.langevin(eps, 1)
+    a, _ = ch.get_state()
+    b, _ = ch2.get_state()
+    assert np.array_equal(a, b)
+    assert ch2.langevin_step == 4
+    ch2.close()
 
 
 def test_langevin_rejects_ising():
@@ -133,12 +147,14 @@ def test_batch_grad_and_langevin():
     for i, om in enumerate(oms):
         g, prec = b.read_grad(i)
         assert maxabs(g, ograd.grad_logdet(om, fields[i])) < 1e-9, f"chain {i}"
-    b.langevin(1e-3, 2, first_step=0)
+    b.langevin(1e-3, 1)
+    b.langevin(1e-3, 1)
     for i, om in enumerate(oms):
         f = ograd.langevin_step(om, fields[i], 1e-3, 0)
         fields[i] = ograd.langevin_step(om, f, 1e-3, 1)
         got, _ = b.get_state(i)
         assert maxabs(got, fields[i]) < 1e-9, f"chain {i}"
+        assert b.langevin_step(i) == 2
     # a local sweep from the Langevin fields follows the oracle's decisions
     before = [b.get_state(i)[0] for i in range(len(specs))]
     b.sweep(1, measure=False)
