@@ -2,33 +2,46 @@
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-extras]
 
-A step is one full sweep (upward and downward pass over all L slices with
-wraps, sequential single-flip updates, QR/UDV stabilisation every n_wrap
-slices and equal-time measurements on every slice) of the honeycomb 12x12
-Hubbard chain (N = 288, U = 4, beta = 10, dtau = 0.1, L = 100, n_wrap = 10,
-Ising field, seed 0).  The field and G live in HBM before the timed region.
+A step is one full sweep of the honeycomb 18x18 Hubbard chain (N = 648,
+U = 5, beta = 20, dtau = 0.1, L = 200, n_wrap = 10, two-valued field, seed 0),
+the largest single-GPU workload: the time-displaced pass at the start of the
+sweep (GT0, G0T, GTT for every tau, S^z-S^z at K = (4 pi/3, 0)), then the
+upward and downward passes over all L slices with wraps, sequential
+single-flip updates, QR/UDV stabilisation every n_wrap slices and the
+equal-time estimators on every slice.  The field, G and the stored forms live
+in HBM before the timed region.
 
 Prints one JSON line with
   value      HS-field proposals per second over the timed sweeps,
-  roofline   the fused block-update kernel (the sweep's dominant kernel) against
-             the 8 TB/s HBM peak: algorithmic bytes per launch = accepted flips
-             x (16 N^2 + 16 N) / launches, over the average launch duration
-             from HIP events on the chain's stream around a rotating sample of
-             one launch in ten inside the timed region (bracketing every launch
-             slows the timed sweep by about 15%),
-             traffic = HBM bytes per launch from the committed rocprofv3
-             FETCH_SIZE / WRITE_SIZE summary (null if the kernel source changed
-             since those counters were taken),
-  cpu_baseline  the CPU oracle on one sweep of the same chain,
-  config.extras the other workloads of the path, each timed the same way:
-             the 512-chain mixed-size batch (captured sweeps) and the
-             batched-vs-plain sweep rate at N = 64; gradient passes and
-             Langevin steps of 64 Gaussian-field chains (10x10, beta = 4);
-             the time-displaced pass of the 18x18 honeycomb chain (N = 648,
-             U = 5, beta = 20, L = 200) with its MFMA GEMM rate; the headline
-             chain with the paper's four-valued field; the headline chain
-             with the lattice-resolved equal-time correlations measured; the
-             headline chain in the M_z form with a Zeeman field.
+  roofline   the fused block-update kernel, the sweep's largest single kernel,
+             against the 8 TB/s HBM peak: achieved = algorithmic bytes per
+             launch (accepted flips x (16 N^2 + 16 N) / launches, the paper's
+             rank-1 form) over the average launch duration from HIP events on
+             the chain's stream around a rotating sample of one launch in ten
+             inside the timed region.  The blocked kernel moves far fewer
+             bytes than that form, so the algorithmic figure can exceed the
+             peak; measured_gbs / measured_frac are the counter-measured HBM
+             bytes per launch (traffic, from the committed rocprofv3
+             FETCH_SIZE / WRITE_SIZE summary, null if the kernel source
+             changed since) over the same launch time,
+  rooflines  the MFMA side: the GEMM kernel (FLOPs of every product of one
+             sweep over their event-timed duration), the stabilisation steps
+             (the method's 2 n_wrap N^3 + 14 N^3 FLOPs per step over the
+             event-timed steps) and the time-displaced pass (8 L N^3 FLOPs
+             over its wall time), each against the 78.6 TFLOP/s FP64 peak,
+  cpu_baseline  the oracle on the host cores (run first, before the GPU is
+             touched): a bounded sample of the same chain with all cores and
+             with one, one full sweep of the honeycomb 12x12 chain with all
+             cores and with one, and one chain per process per core for the
+             batched 8x8 chains and the Gaussian 10x10 gradients,
+  config.extras the other workloads of the path, each timed with
+             HIP-synchronised wall clocks: the honeycomb 12x12 chain (N = 288,
+             its block-update roofline), the 512-chain mixed-size batch
+             (captured sweeps) and the batched-vs-plain sweep rate at N = 64;
+             gradient passes and Langevin steps of 64 Gaussian-field chains
+             (10x10, beta = 4); the time-displaced pass alone; the 12x12 chain
+             with the paper's four-valued field, with the lattice-resolved
+             equal-time correlations, and in the M_z form with a Zeeman field.
 """
 import argparse
 import hashlib
@@ -42,10 +55,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "HS-field updates/s & sweeps/s at |G−G_oracle|≤1e-9; batched vs plain, 1 GPU"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
 KERNEL_SRC = os.path.join(ROOT, "paper_1704_00131_amd", "csrc", "update.h")
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "block_update_pmc_honeycomb12.json")
-TIMING_EVERY = 10   # event sample period, coprime with the 9 block launches per slice at N = 288
-
+PMC_SUMMARY = {288: os.path.join(ROOT, "profiles", "block_update_pmc_honeycomb12.json"),
+               648: os.path.join(ROOT, "profiles", "block_update_pmc_honeycomb18.json")}
+# event sample period, coprime with the block launches per slice (21 at N = 648, 9 at N = 288)
+TIMING_EVERY = 10
+KPOINT = (4.0 * 3.141592653589793 / 3.0, 0.0)
 
 
 def kernel_source_hash() -> str:
@@ -53,36 +69,141 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def traffic_per_launch():
-    """HBM bytes per block-update launch from the committed counter summary,
-    scaled by the copy-kernel calibration, or None if stale/missing."""
+def traffic_per_launch(n):
+    """HBM bytes per block-update launch at size n from the committed counter
+    summary, scaled by the copy-kernel calibration, or None if stale/missing."""
     try:
-        with open(PMC_SUMMARY) as f:
+        with open(PMC_SUMMARY[n]) as f:
             d = json.load(f)
-    except (OSError, ValueError):
+    except (KeyError, OSError, ValueError):
         return None
     if d.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
     return float(d["hbm_bytes_per_launch"])
 
 
-def cpu_baseline(lat, w, field):
-    """The oracle, as it stands, on one sweep of the same chain."""
-    from oracle import hubbard, sweep
+def block_update_roofline(n, accepted, launches, k_ms, k_launches):
+    """Roofline entry of the block update: algorithmic bytes (rank-1 form) and
+    counter-measured bytes per launch over the event-timed launch duration."""
+    bytes_per_launch = accepted * (16.0 * n * n + 16.0 * n) / max(1, launches)
+    avg_s = k_ms * 1e-3 / max(1, k_launches)
+    achieved = bytes_per_launch / avg_s / 1e9 if k_ms > 0 else 0.0
+    traffic = traffic_per_launch(n)
+    measured = traffic / avg_s / 1e9 if (traffic and k_ms > 0) else None
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": "k_block_update", "launches": launches, "timed_launches": k_launches,
+            "avg_launch_us": 1e6 * avg_s, "algorithmic_bytes_per_launch": bytes_per_launch,
+            "algorithmic_exceeds_peak": achieved > HBM_PEAK_GBS,
+            "measured_gbs": measured, "measured_frac": (measured / HBM_PEAK_GBS) if measured else None}
+
+
+# ------------------------------------------------------------ CPU baseline --
+def _threads_info():
     try:
         import threadpoolctl
         info = threadpoolctl.threadpool_info()
-        cores = max([i.get("num_threads", 1) for i in info] or [1])
+        return max([i.get("num_threads", 1) for i in info] or [1]), \
+            ",".join(sorted({i.get("internal_api", "?") for i in info}))
     except Exception:
-        cores = 1
+        return 1, "unknown"
+
+
+def _one_core():
+    import threadpoolctl
+    return threadpoolctl.threadpool_limits(1)
+
+
+def _oracle_chain(w, lat):
+    from oracle import hubbard, sweep
     om = hubbard.hubbard_model(lat.K, w.U, w.beta, w.dtau, w.n_wrap, trotter=w.trotter, seed=w.seed)
-    ch = sweep.Chain(om, field).init()
+    return om, sweep.Chain(om, hubbard.init_field(om)).init()
+
+
+def _oracle_sample(w, lat, max_slices):
+    """Proposals per second of the oracle's upward pass over the first
+    max_slices slices of the chain (a bounded sample of one sweep)."""
+    _, ch = _oracle_chain(w, lat)
+    t0 = time.perf_counter()
+    ch.sweep(measure=True, max_slices=max_slices)
+    dt = time.perf_counter() - t0
+    return ch.proposals / dt, ch.proposals, dt
+
+
+def _per_core_batch_chain(seed):
+    import threadpoolctl
+    from inputs import square_lattice
+    from oracle import hubbard, sweep
+    with threadpoolctl.threadpool_limits(1):
+        lat = square_lattice(8, 8)
+        m = hubbard.hubbard_model(lat.K, 4.0, 8.0, 0.1, 10, seed=seed)
+        ch = sweep.Chain(m, hubbard.init_field(m)).init()
+        ch.sweep(measure=True)
+    return ch.proposals
+
+
+def _per_core_gradient(seed):
+    import threadpoolctl
+    from inputs import square_lattice
+    from oracle import gradient, hubbard
+    with threadpoolctl.threadpool_limits(1):
+        lat = square_lattice(10, 10)
+        m = hubbard.hubbard_model(lat.K, 4.0, 4.0, 0.1, 10, field_kind="gauss", seed=seed)
+        gradient.grad_logdet(m, hubbard.init_field(m))
+    return 1
+
+
+def _pool_rate(fn, n_proc):
+    """Aggregate rate of n_proc independent oracle chains, one per process
+    (the paper's one walker per core), with BLAS limited to one thread."""
+    import multiprocessing as mp
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(n_proc) as pool:
+        pool.map(fn, [10_000 + i for i in range(n_proc)])      # start-up and imports, untimed
+        t0 = time.perf_counter()
+        res = pool.map(fn, list(range(n_proc)))
+        dt = time.perf_counter() - t0
+    return res, dt
+
+
+def cpu_baseline():
+    """The oracle, as it stands, on the host cores (a baseline, not a target)."""
+    from inputs import WORKLOADS
+    cores, blas = _threads_info()
+    # one process per core of the host's share (at most 16 on the GPU boxes)
+    n_proc = max(1, min(len(os.sched_getaffinity(0)), 16))
+    w18 = WORKLOADS["honeycomb18_U5_b20"]
+    lat18 = w18.lattice()
+    rate, props, dt = _oracle_sample(w18, lat18, 10)
+    with _one_core():
+        rate1, props1, dt1 = _oracle_sample(w18, lat18, 5)
+    w12 = WORKLOADS["honeycomb12_U4_b10"]
+    lat12 = w12.lattice()
+    _, ch = _oracle_chain(w12, lat12)
     t0 = time.perf_counter()
     ch.sweep(measure=True)
-    dt = time.perf_counter() - t0
-    return {"value": ch.proposals / dt, "unit": "HS-field updates/s", "cores": int(cores), "kind": "oracle",
-            "sample": "one oracle sweep (%d proposals, %d accepted) of the same honeycomb 12x12 chain from its "
-                      "initial field, NumPy/SciPy FP64, %.1f s" % (ch.proposals, ch.accepted, dt)}
+    dt12 = time.perf_counter() - t0
+    with _one_core():
+        rate12_1, _, dt12_1 = _oracle_sample(w12, lat12, 20)
+    res, dtb = _pool_rate(_per_core_batch_chain, n_proc)
+    _, dtg = _pool_rate(_per_core_gradient, n_proc)
+    return {"value": rate, "unit": "HS-field updates/s", "cores": int(cores), "kind": "oracle",
+            "sample": "the oracle's upward pass over the first 10 of the 200 slices (%d proposals, one "
+                      "stabilisation, equal-time estimators) of the same honeycomb 18x18 chain from its initial "
+                      "field, NumPy/SciPy FP64 on %d BLAS threads (%s), %.1f s; baseline, not target"
+                      % (props, cores, blas, dt),
+            "one_core": {"value": rate1, "sample": "first 5 slices (%d proposals), BLAS on 1 thread, %.1f s"
+                                                   % (props1, dt1)},
+            "honeycomb12": {"updates_per_s": ch.proposals / dt12, "sweep_s": dt12, "cores": int(cores),
+                            "one_core_updates_per_s": rate12_1,
+                            "one_core_sample": "first 20 of 100 slices, %.1f s" % dt12_1},
+            "batched_8x8_per_core": {"processes": n_proc, "chain_sweeps_per_s": n_proc / dtb,
+                                     "updates_per_s": sum(res) / dtb,
+                                     "sample": "one sweep of one 8x8 chain (L = 80) per process, BLAS on 1 "
+                                               "thread each, %.1f s" % dtb},
+            "gradient_10x10_per_core": {"processes": n_proc, "gradients_per_s": n_proc / dtg,
+                                        "sample": "one gradient (L = 40 from-scratch G(tau)) of one Gaussian 10x10 "
+                                                  "chain per process, BLAS on 1 thread each, %.1f s" % dtg}}
 
 
 def _sync_time(torch, fn):
@@ -172,35 +293,69 @@ def bench_gradient(torch, pa):
 
 def bench_time_displaced(torch, pa):
     """Honeycomb 18x18 (N = 648), U = 5, beta = 20, L = 200, n_wrap = 10: one
-    time-displaced pass (S^z-S^z at K = (4 pi / 3, 0) for all tau), one sweep
-    with it, and one sweep with it and the lattice-resolved time-displaced
-    correlations (all displacements, all tau)."""
+    time-displaced pass alone (S^z-S^z at K = (4 pi / 3, 0) for all tau), with
+    its GEMM rate, and one sweep with it and the lattice-resolved
+    time-displaced correlations (all displacements, all tau)."""
     import numpy as np
-    from inputs import WORKLOADS
-    w = WORKLOADS["honeycomb18_U5_b20"]
-    lat = w.lattice()
-    lam = pa.hubbard_coupling(w.U, w.dtau)
-    ch = pa.Chain(pa.make_model(lat.n, w.beta, w.dtau, w.n_wrap, lam, U=w.U, trotter=w.trotter, seed=w.seed), lat.K)
-    ph = np.exp(-1j * (lat.cell_pos[lat.cell_of] @ np.array([4.0 * np.pi / 3.0, 0.0])))
-    ch.td_setup(lat.orb_of, ph, lat.n_cells)
-    ch.random_field().init()
+    ch, lat = _honeycomb18_chain(pa)
     ch.td_measure()
     dt, (S, prec) = _sync_time(torch, ch.td_measure)
     ch.timing("gemm", True)
     ch.td_measure()
     ms, launches, flops = ch.timing_read()
     ch.timing("gemm", False)
-    dts, st = _sync_time(torch, lambda: ch.sweep(1, measure=True, time_displaced=True))
     site = np.full((lat.n_cells, lat.norb), -1, dtype=np.int32)
     site[lat.cell_of, lat.orb_of] = np.arange(lat.n)
     ch.eq_setup(lat.L1, lat.L2, site, lat.sublattice_sign())
     dtc, _ = _sync_time(torch, lambda: ch.sweep(1, measure=True, time_displaced=True, td_correlations=True))
     ch.close()
     tf = flops / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
-    return {"N": lat.n, "L": w.n_slices, "td_pass_s": dt, "td_prec": list(prec),
-            "gemm_tflops": tf, "gemm_frac_of_fp64_mfma_peak": tf / 78.6, "gemm_share_of_pass": ms * 1e-3 / dt,
-            "sweep_with_td_s": dts, "updates_per_s": st.proposals / dts,
+    return {"N": lat.n, "L": 200, "td_pass_s": dt, "td_prec": list(prec),
+            "gemm_tflops": tf, "gemm_frac_of_fp64_mfma_peak": tf / FP64_PEAK_TFLOPS,
+            "gemm_share_of_pass": ms * 1e-3 / dt,
             "sweep_with_td_and_lattice_correlations_s": dtc}
+
+
+def _honeycomb18_chain(pa):
+    import numpy as np
+    from inputs import WORKLOADS
+    w = WORKLOADS["honeycomb18_U5_b20"]
+    lat = w.lattice()
+    lam = pa.hubbard_coupling(w.U, w.dtau)
+    ch = pa.Chain(pa.make_model(lat.n, w.beta, w.dtau, w.n_wrap, lam, U=w.U, trotter=w.trotter, seed=w.seed),
+                  lat.K, device="cuda:0")
+    ph = np.exp(-1j * (lat.cell_pos[lat.cell_of] @ np.array(KPOINT)))
+    ch.td_setup(lat.orb_of, ph, lat.n_cells)
+    ch.random_field().init()
+    return ch, lat
+
+
+def bench_honeycomb12(torch, pa, steps=5):
+    """The honeycomb 12x12 chain (N = 288, U = 4, beta = 10, L = 100): sweeps
+    with the equal-time estimators, its block-update roofline and GEMM rate."""
+    from inputs import WORKLOADS
+    w = WORKLOADS["honeycomb12_U4_b10"]
+    lat = w.lattice()
+    n = lat.n
+    lam = pa.hubbard_coupling(w.U, w.dtau)
+    ch = pa.Chain(pa.make_model(n, w.beta, w.dtau, w.n_wrap, lam, U=w.U, trotter=w.trotter, seed=w.seed), lat.K)
+    ch.random_field().init()
+    ch.sweep(2, measure=True)
+    st0 = ch.sweep(0, measure=True)
+    ch.timing("block_update", True, every=TIMING_EVERY)
+    dt, st = _sync_time(torch, lambda: ch.sweep(steps, measure=True))
+    k_ms, k_launches, _ = ch.timing_read()
+    ch.timing("gemm", True)
+    ch.sweep(1, measure=True)
+    g_ms, _, g_flops = ch.timing_read()
+    ch.timing("gemm", False)
+    ch.close()
+    props, acc = st.proposals - st0.proposals, st.accepted - st0.accepted
+    launches = steps * 2 * w.n_slices * ((n + 31) // 32)
+    return {"N": n, "L": w.n_slices, "ms_per_sweep": 1e3 * dt / steps, "updates_per_s": props / dt,
+            "acceptance": acc / max(1, props), "prec_mean": st.prec_mean, "prec_max": st.prec_max,
+            "gemm_tflops": g_flops / (g_ms * 1e-3) / 1e12 if g_ms > 0 else 0.0,
+            "roofline_block_update": block_update_roofline(n, acc, launches, k_ms, k_launches)}
 
 
 def bench_four_valued(torch, pa):
@@ -273,12 +428,12 @@ def bench_correlations(torch, pa):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--profile-extra", choices=["batched", "gradient", "time_displaced", "four_valued",
-                                                "correlations", "zeeman"],
+    ap.add_argument("--profile-extra", choices=["honeycomb12", "batched", "gradient", "time_displaced",
+                                                "four_valued", "correlations", "zeeman"],
                     help="run only this extra workload and print its figures (for rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -286,54 +441,64 @@ def main():
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
+    # the CPU baseline first: its worker processes start before this process touches the GPU
+    cpu = None if (args.no_cpu_baseline or args.profile_extra) else cpu_baseline()
+
     import torch
 
     import paper_1704_00131_amd as pa
-    from inputs import WORKLOADS
 
     if args.profile_extra:
-        fn = {"batched": bench_batched, "gradient": bench_gradient, "time_displaced": bench_time_displaced,
-              "four_valued": bench_four_valued, "correlations": bench_correlations, "zeeman": bench_zeeman}
+        fn = {"honeycomb12": bench_honeycomb12, "batched": bench_batched, "gradient": bench_gradient,
+              "time_displaced": bench_time_displaced, "four_valued": bench_four_valued,
+              "correlations": bench_correlations, "zeeman": bench_zeeman}
         print(json.dumps({args.profile_extra: fn[args.profile_extra](torch, pa)}))
         return
 
-    w = WORKLOADS["honeycomb12_U4_b10"]
-    lat = w.lattice()
-    N = lat.n
-    lam = pa.hubbard_coupling(w.U, w.dtau)
-    model = pa.make_model(N, w.beta, w.dtau, w.n_wrap, lam, U=w.U, trotter=w.trotter, seed=w.seed)
-    ch = pa.Chain(model, lat.K, device="cuda:0")
-    ch.random_field()
-    field0, _ = ch.get_state()
-    ch.init()
+    ch, lat = _honeycomb18_chain(pa)
+    N, L = lat.n, 200
+    flags = dict(measure=True, time_displaced=True)
     for _ in range(args.warmup):
-        ch.sweep(1, measure=True)
-    st0 = ch.sweep(0, measure=True)
+        ch.sweep(1, **flags)
+    st0 = ch.sweep(0, **flags)
     ch.timing("block_update", True, every=TIMING_EVERY)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    st = ch.sweep(args.steps, measure=True)
+    st = ch.sweep(args.steps, **flags)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     k_ms, k_launches, _ = ch.timing_read()
+    # MFMA side, on one more sweep each: every GEMM launch, then every stabilisation step
     ch.timing("gemm", True)
-    ch.sweep(1, measure=True)
+    ch.sweep(1, **flags)
     g_ms, g_launches, g_flops = ch.timing_read()
-    ch.timing("gemm", False)
+    ch.timing("stabilise", True)
+    ch.sweep(1, **flags)
+    s_ms, s_steps, _ = ch.timing_read()
+    ch.timing("stabilise", False)
+    td_s, _ = _sync_time(torch, ch.td_measure)
+    ch.close()
     dt = t1 - t0
     proposals = st.proposals - st0.proposals
     accepted = st.accepted - st0.accepted
-
-    # every launch of the timed sweeps: two passes of L slices, one launch per 32 sites
-    all_launches = args.steps * 2 * w.n_slices * ((N + 31) // 32)
-    bytes_per_launch = accepted * (16.0 * N * N + 16.0 * N) / max(1, all_launches)
-    avg_s = k_ms * 1e-3 / max(1, k_launches)
-    achieved = bytes_per_launch / avg_s / 1e9 if k_ms > 0 else 0.0
-    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_per_launch(),
-                "kernel": "k_block_update", "launches": all_launches, "timed_launches": k_launches,
-                "avg_launch_us": 1e6 * avg_s,
-                "algorithmic_bytes_per_launch": bytes_per_launch}
+    # every block-update launch of the timed sweeps: two passes of L slices, one launch per 32 sites
+    all_launches = args.steps * 2 * L * ((N + 31) // 32)
+    roofline = block_update_roofline(N, accepted, all_launches, k_ms, k_launches)
+    g_tf = g_flops / (g_ms * 1e-3) / 1e12 if g_ms > 0 else 0.0
+    stab_flops = (2 * 10 + 14) * float(N) ** 3           # per step, n_wrap = 10
+    s_tf = stab_flops * s_steps / (s_ms * 1e-3) / 1e12 if s_ms > 0 else 0.0
+    td_tf = 8.0 * L * float(N) ** 3 / td_s / 1e12
+    rooflines = [
+        {"kernel": "k_gemm (every product of one sweep)", "bound": "mfma", "achieved": g_tf,
+         "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": g_tf / FP64_PEAK_TFLOPS, "launches": g_launches,
+         "share_of_sweep": g_ms * 1e-3 / (dt / args.steps)},
+        {"kernel": "stabilisation step (chunk products, QR, merge, LU solve)", "bound": "mfma", "achieved": s_tf,
+         "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": s_tf / FP64_PEAK_TFLOPS, "steps": s_steps,
+         "ms_per_step": s_ms / max(1, s_steps), "flops_per_step": stab_flops,
+         "share_of_sweep": s_ms * 1e-3 / (dt / args.steps)},
+        {"kernel": "time-displaced pass", "bound": "mfma", "achieved": td_tf, "peak": FP64_PEAK_TFLOPS,
+         "unit": "TFLOP/s", "frac": td_tf / FP64_PEAK_TFLOPS, "pass_s": td_s, "flops": 8.0 * L * float(N) ** 3},
+    ]
     out = {
         "metric": METRIC,
         "value": proposals / dt,
@@ -347,25 +512,25 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "honeycomb 12x12 Hubbard, N=288, U=4, beta=10, dtau=0.1, L=100, n_wrap=10, "
-                               "Ising field, seed 0, one chain, measurements on every slice",
+        "config": {"workload": "honeycomb 18x18 Hubbard, N=648, U=5, beta=20, dtau=0.1, L=200, n_wrap=10, "
+                               "Ising field, seed 0, one chain; per sweep the time-displaced pass (S^z-S^z at "
+                               "K=(4pi/3,0), all tau) and the equal-time estimators on every slice",
                    "sweeps_per_s": args.steps / dt,
                    "accepted_updates_per_s": accepted / dt,
                    "acceptance": accepted / max(1, proposals),
-                   "prec_mean": st.prec_mean, "prec_max": st.prec_max,
-                   "gemm_tflops": g_flops / (g_ms * 1e-3) / 1e12 if g_ms > 0 else 0.0,
-                   "gemm_share_of_sweep": g_ms * 1e-3 / (dt / args.steps)},
+                   "prec_mean": st.prec_mean, "prec_max": st.prec_max},
         "roofline": roofline,
+        "rooflines": rooflines,
     }
-    ch.close()
     if not args.no_extras:
-        out["config"]["extras"] = {"batched": bench_batched(torch, pa), "gradient": bench_gradient(torch, pa),
+        out["config"]["extras"] = {"honeycomb12": bench_honeycomb12(torch, pa),
+                                   "batched": bench_batched(torch, pa), "gradient": bench_gradient(torch, pa),
                                    "time_displaced": bench_time_displaced(torch, pa),
                                    "four_valued": bench_four_valued(torch, pa),
                                    "correlations": bench_correlations(torch, pa),
                                    "zeeman": bench_zeeman(torch, pa)}
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(lat, w, field0)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out))
 
 

@@ -265,8 +265,11 @@ dqmc_status dqmc_td_read_corr_bins(dqmc_ctx* ctx, double* sums_host, double* cou
  * dqmc_timing_read synchronises the stream, returns the summed event time (ms)
  * and the number of bracketed launches since the last read (and, for the GEMM,
  * their FLOPs), and clears them.  kernel: DQMC_KERNEL_BLOCK_UPDATE (the fused
- * block update) or DQMC_KERNEL_GEMM (the MFMA product). */
-typedef enum { DQMC_KERNEL_BLOCK_UPDATE = 0, DQMC_KERNEL_GEMM = 1 } dqmc_kernel;
+ * block update), DQMC_KERNEL_GEMM (the MFMA product) or DQMC_KERNEL_STABILISE
+ * (a whole stabilisation step of a sweep: the chunk products, the QR, the
+ * merge with its LU solve and the precision check, section "Stabilization";
+ * the events bracket the step's launch sequence). */
+typedef enum { DQMC_KERNEL_BLOCK_UPDATE = 0, DQMC_KERNEL_GEMM = 1, DQMC_KERNEL_STABILISE = 2 } dqmc_kernel;
 dqmc_status dqmc_timing_enable(dqmc_ctx* ctx, dqmc_kernel kernel, int32_t enable);
 dqmc_status dqmc_timing_read(dqmc_ctx* ctx, double* total_ms, uint64_t* launches, double* flops);
 

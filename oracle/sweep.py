@@ -141,7 +141,10 @@ class Chain:
         self.G = G_s
 
     # -- one sweep -----------------------------------------------------------
-    def sweep(self, measure: bool = True):
+    def sweep(self, measure: bool = True, max_slices=None):
+        """One sweep.  max_slices (a bounded sample, for timing only): stop
+        after that many slices of the upward pass, leaving the sweep
+        unfinished and the sweep counter where it was."""
         m = self.m
         nw = m.n_wrap
         nk = m.n_stab
@@ -150,6 +153,8 @@ class Chain:
         # upward pass
         right = None
         for tau in range(1, m.L + 1):
+            if max_slices is not None and tau > max_slices:
+                return self
             self.G = m.B(self.field, tau) @ self.G @ m.B_inv(self.field, tau)
             self._update_slice(tau, philox.DIR_UP)
             if tau % nw == 0:

@@ -11,7 +11,7 @@ STATUS_NAMES = {0: "DQMC_OK", 1: "DQMC_E_ARG", 2: "DQMC_E_UNSUPPORTED", 3: "DQMC
 FIELD_ISING, FIELD_GAUSS, FIELD_ISING4 = 0, 1, 2
 FIELD_KINDS = {"ising": FIELD_ISING, "gauss": FIELD_GAUSS, "ising4": FIELD_ISING4}
 TROTTER_ASYM, TROTTER_SYM = 0, 1
-KERNEL_BLOCK_UPDATE, KERNEL_GEMM = 0, 1
+KERNEL_BLOCK_UPDATE, KERNEL_GEMM, KERNEL_STABILISE = 0, 1, 2
 
 
 class Model(ctypes.Structure):

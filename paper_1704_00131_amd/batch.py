@@ -102,8 +102,9 @@ class Batch:
         `chain`'s group: site [n_cells, norb], sign [N] (as Chain.eq_setup)."""
         st = np.ascontiguousarray(site, dtype=np.int32)
         sg = np.ascontiguousarray(sign, dtype=np.float64)
-        if st.ndim != 2 or st.shape[0] != int(L1) * int(L2) or sg.shape != (self.models[chain].n,):
-            raise ValueError("site must be [L1 * L2, norb], sign [N]")
+        # the library reads N entries of each (it checks L1 * L2 * norb = N itself)
+        if st.ndim != 2 or st.size != self.models[chain].n or sg.shape != (self.models[chain].n,):
+            raise ValueError("site must be [n_cells, norb] with N entries, sign [N]")
         self._chk(self.lib.dqmc_batch_eq_setup(self.b, chain, int(L1), int(L2), st.shape[1], st.ctypes.data,
                                                sg.ctypes.data))
         return self

@@ -187,8 +187,9 @@ class Chain:
         sign [N] the sublattice signs (+1 / -1)."""
         st = np.ascontiguousarray(site, dtype=np.int32)
         sg = np.ascontiguousarray(sign, dtype=np.float64)
-        if st.ndim != 2 or st.shape[0] != int(L1) * int(L2) or sg.shape != (self.N,):
-            raise ValueError("site must be [L1 * L2, norb], sign [N]")
+        # the library reads N entries of each (it checks L1 * L2 * norb = N itself)
+        if st.ndim != 2 or st.size != self.N or sg.shape != (self.N,):
+            raise ValueError("site must be [n_cells, norb] with N entries, sign [N]")
         self._chk(self.lib.dqmc_eq_setup(self.ctx, int(L1), int(L2), st.shape[1], st.ctypes.data, sg.ctypes.data))
         # recorded only once the library holds this lattice (the read buffers are sized from it)
         self.eq_shape = (st.shape[0], st.shape[1])
@@ -223,7 +224,8 @@ class Chain:
     def timing(self, kernel: str = "block_update", enable: bool = True, every: int = 1):
         """Bracket launches of one kernel with HIP events: every launch, or every
         `every`-th one (a rotating sample) when every > 1."""
-        k = _lib.KERNEL_BLOCK_UPDATE if kernel == "block_update" else _lib.KERNEL_GEMM
+        k = {"block_update": _lib.KERNEL_BLOCK_UPDATE, "gemm": _lib.KERNEL_GEMM,
+             "stabilise": _lib.KERNEL_STABILISE}[kernel]
         self._chk(self.lib.dqmc_timing_enable(self.ctx, k, max(1, int(every)) if enable else 0))
 
     def timing_read(self):

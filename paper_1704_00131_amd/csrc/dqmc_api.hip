@@ -705,12 +705,14 @@ dqmc_status sweep_once(dqmc_ctx* c, int meas) {
     if (dqmc_status s = update_slice(c, tau)) return s;
     if (tau % nw == 0) {
       const int k = tau / nw;
+      if (dqmc_status s = timing_begin(c, DQMC_KERNEL_STABILISE)) return s;
       UDVp prev = (k == 1) ? c->uid : c->slot(k - 1);
       if (dqmc_status s = right_step(c, prev, tau - nw, tau, c->cur)) return s;
       UDVp left = (k == nk) ? c->uid : c->slot(k);
       if (dqmc_status s = merge(c, c->cur, left, c->Gs, nullptr)) return s;
       if (dqmc_status s = copy_udv(c, c->slot(k), c->cur)) return s;
       if (dqmc_status s = stabilise(c, hist++)) return s;
+      if (dqmc_status s = timing_end(c, DQMC_KERNEL_STABILISE)) return s;
     }
     if (meas & 1)
       if (dqmc_status s = measure(c)) return s;
@@ -728,12 +730,14 @@ dqmc_status sweep_once(dqmc_ctx* c, int meas) {
       const int k = (tau - 1) / nw;
       // wrapped G(tau-1), compared against the recomputed one below
       if (dqmc_status s = wrap_down(c, tau, c->G)) return s;
+      if (dqmc_status s = timing_begin(c, DQMC_KERNEL_STABILISE)) return s;
       UDVp prev = (k + 1 == nk) ? c->uid : c->slot(k + 1);
       if (dqmc_status s = left_step(c, prev, tau - 1, tau - 1 + nw, c->cur)) return s;
       UDVp right = (k == 0) ? c->uid : c->slot(k);
       if (dqmc_status s = merge(c, right, c->cur, c->Gs, nullptr)) return s;
       if (dqmc_status s = copy_udv(c, c->slot(k), c->cur)) return s;
       if (dqmc_status s = stabilise(c, hist++)) return s;
+      if (dqmc_status s = timing_end(c, DQMC_KERNEL_STABILISE)) return s;
     } else {
       if (dqmc_status s = wrap_down(c, tau, c->G)) return s;
     }
@@ -1438,7 +1442,9 @@ dqmc_status dqmc_td_read_bins(dqmc_ctx* c, double* sums_host, double* count) {
 }
 
 dqmc_status dqmc_timing_enable(dqmc_ctx* c, dqmc_kernel kernel, int32_t enable) {
-  if (!c || enable < 0 || (kernel != DQMC_KERNEL_BLOCK_UPDATE && kernel != DQMC_KERNEL_GEMM)) return DQMC_E_ARG;
+  if (!c || enable < 0 ||
+      (kernel != DQMC_KERNEL_BLOCK_UPDATE && kernel != DQMC_KERNEL_GEMM && kernel != DQMC_KERNEL_STABILISE))
+    return DQMC_E_ARG;
   c->timing = enable != 0;
   c->timing_open = false;
   c->timing_kernel = kernel;
