@@ -147,6 +147,22 @@ dqmc_status dqmc_reset_bins(dqmc_ctx* ctx);
  * same stabilised products as the sweep.  Does not change the chain. */
 dqmc_status dqmc_green_scratch(dqmc_ctx* ctx, int32_t tau, double* G_dev);
 
+/* The same recomputation for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): every device buffer it needs besides its input and its output
+ * lives in one static device array of at most 32 MiB that each GPU holds for
+ * the life of the process; nothing is allocated or freed.  ctx: a created
+ * context (bound or not; its model and hopping matrix are used, its own
+ * buffers are not touched).  field_dev: device field of the chain, n_slices*n
+ * doubles (read only).  G_dev: device output, n*n doubles.  The work is
+ * enqueued on hip_stream, which is synchronised before return.
+ * DQMC_E_UNSUPPORTED if the model's scratch exceeds 32 MiB (the 12x12
+ * honeycomb chain, N = 288 and L = 100, needs 28.5 MB).  Every call on one GPU
+ * uses that GPU's single array, so calls that overlap in time on the same GPU
+ * (any contexts, any streams) race and must be serialised by the caller. */
+dqmc_status dqmc_green_scratch_noalloc(dqmc_ctx* ctx, const double* field_dev, int32_t tau, double* G_dev,
+                                       void* hip_stream);
+
 /* Test hook: the weight ratio R of changing the field of `site` on slice tau
  * (1..L) to s_new, with everything else fixed (section "Updating schemes";
  * Eq. (Green_eq) and the matrix determinant lemma): with Delta =

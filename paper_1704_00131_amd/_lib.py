@@ -54,6 +54,8 @@ SIGNATURES = {
     "dqmc_read_bins": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "dqmc_reset_bins": (ctypes.c_int, [ctypes.c_void_p]),
     "dqmc_green_scratch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "dqmc_green_scratch_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                                  ctypes.c_void_p]),
     "dqmc_ratio": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                   ctypes.POINTER(ctypes.c_double)]),
     "dqmc_logdet": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),

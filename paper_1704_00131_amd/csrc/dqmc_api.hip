@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1220,9 +1221,14 @@ dqmc_status dqmc_reset_bins(dqmc_ctx* c) {
   return DQMC_OK;
 }
 
-dqmc_status dqmc_green_scratch(dqmc_ctx* c, int32_t tau, double* G_dev) {
-  if (!c || !G_dev || tau < 0 || tau > c->L) return fail(c, DQMC_E_ARG, "bad arguments");
-  if (!c->bound) return fail(c, DQMC_E_STATE, "not bound");
+}  // extern "C"
+
+namespace {
+
+// G(tau) from scratch for the field the context points at, into G_dev: the
+// right chain 0 -> tau and the left chain beta -> tau in chunks aligned to
+// n_wrap, then the merge (enqueued only).
+dqmc_status green_scratch_into(dqmc_ctx* c, int tau, double* G_dev) {
   // right chain 0 -> tau in chunks aligned to n_wrap, ping-pong hA/hB
   UDVp right = c->uid;
   UDVp bufs[2] = {c->hA, c->hB};
@@ -1246,7 +1252,17 @@ dqmc_status dqmc_green_scratch(dqmc_ctx* c, int32_t tau, double* G_dev) {
     left = lb[q];
     q ^= 1;
   }
-  if (dqmc_status s = merge(c, right, left, G_dev, nullptr)) return s;
+  return merge(c, right, left, G_dev, nullptr);
+}
+
+}  // namespace
+
+extern "C" {
+
+dqmc_status dqmc_green_scratch(dqmc_ctx* c, int32_t tau, double* G_dev) {
+  if (!c || !G_dev || tau < 0 || tau > c->L) return fail(c, DQMC_E_ARG, "bad arguments");
+  if (!c->bound) return fail(c, DQMC_E_STATE, "not bound");
+  if (dqmc_status s = green_scratch_into(c, tau, G_dev)) return s;
   HIPCHK(hipStreamSynchronize(c->stream));
   return read_flag(c);
 }
@@ -1998,5 +2014,91 @@ dqmc_status dqmc_batch_check_layout(dqmc_batch* b) {
 const char* dqmc_batch_last_error(const dqmc_batch* b) { return b ? b->err.c_str() : "null batch"; }
 
 void dqmc_batch_destroy(dqmc_batch* b) { delete b; }
+
+}  // extern "C"
+
+// ============================================== allocation-free variant ==
+// dqmc_green_scratch_noalloc computes what dqmc_green_scratch computes, with
+// every device buffer it needs besides its input (the field) and its output
+// (G) in one static device array, so it runs without any device allocation
+// by the caller or the library.  Each GPU holds its own copy of the array
+// for the life of the process; host code reaches it only through the
+// address hipGetSymbolAddress returns on that device.
+namespace {
+
+constexpr size_t kNoallocScratchDoubles = (size_t)4 << 20;   // 32 MiB
+static __device__ __align__(256) double scratch[kNoallocScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+dqmc_status scratch_address(dqmc_ctx* c, double** out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(c, DQMC_E_DEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(c, DQMC_E_DEVICE, "no device address for the static scratch array");
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return DQMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dqmc_status dqmc_green_scratch_noalloc(dqmc_ctx* c, const double* field_dev, int32_t tau, double* G_dev,
+                                       void* hip_stream) {
+  if (!c || !field_dev || !G_dev || tau < 0 || tau > c->L) return fail(c, DQMC_E_ARG, "bad arguments");
+  // a host-side context of its own: model and hopping from c, every device
+  // pointer inside the static array (c's own binding, if any, is untouched)
+  dqmc_ctx t;
+  t.m = c->m;
+  t.N = c->N; t.L = c->L; t.nw = c->nw; t.nk = c->nk; t.nb = c->nb;
+  t.K = c->K;
+  t.trK = c->trK; t.normK1 = c->normK1;
+  const size_t need = layout_work(&t, false);
+  if (need > kNoallocScratchDoubles)
+    return fail(c, DQMC_E_UNSUPPORTED,
+                "dqmc_green_scratch_noalloc: this model needs " + std::to_string(need * 8 >> 20) +
+                    " MiB of scratch, above the static maximum of " +
+                    std::to_string(kNoallocScratchDoubles * 8 >> 20) + " MiB");
+  double* base = nullptr;
+  if (dqmc_status s = scratch_address(c, &base)) return s;
+  t.stream = static_cast<hipStream_t>(hip_stream);
+  t.work = base;
+  t.field = const_cast<double*>(field_dev);   // read only on this path
+  layout_work(&t, true);
+  auto run = [&]() -> dqmc_status {
+    if (dqmc_status s = set_lds_limits(&t)) return s;
+    // the array keeps the last call's contents: everything read below is
+    // written first, and the error flag is cleared here
+    if (dqmc_status s = fill_small(&t, reinterpret_cast<double*>(t.err_flag), 1, 0.0)) return s;
+    HIPCHK(hipMemcpyAsync(t.Kd, t.K.data(), sizeof(double) * t.N * t.N, hipMemcpyHostToDevice, t.stream));
+    if (dqmc_status s = expm(&t, -t.m.dtau, t.E)) return s;
+    hipLaunchKernelGGL(k_set_identity, dim3(grid1((size_t)t.N * t.N)), dim3(256), 0, t.stream, t.uid.Q, t.N, t.N,
+                       (size_t)0);
+    hipLaunchKernelGGL(k_set_identity, dim3(grid1((size_t)t.N * t.N)), dim3(256), 0, t.stream, t.uid.T, t.N, t.N,
+                       (size_t)0);
+    HIPCHK(hipGetLastError());
+    if (dqmc_status s = fill_small(&t, t.uid.D, t.N, 1.0)) return s;
+    if (dqmc_status s = green_scratch_into(&t, tau, G_dev)) return s;
+    int flag = 0;
+    HIPCHK(hipMemcpyAsync(&flag, t.err_flag, sizeof(int), hipMemcpyDeviceToHost, t.stream));
+    HIPCHK(hipStreamSynchronize(t.stream));
+    if (flag) return fail(&t, DQMC_E_NUMERIC, "numerical failure in the recomputation (flags " +
+                                                  std::to_string(flag) + ")");
+    return DQMC_OK;
+  };
+  const dqmc_status s = run();
+  if (s != DQMC_OK && !t.err.empty()) c->err = t.err;
+  return s;
+}
 
 }  // extern "C"
