@@ -63,6 +63,7 @@ struct dqmc_ctx {
   int *piv = nullptr, *moves = nullptr;
   double* XA = nullptr;    // [X | right-hand sides] of the blocked LU solve, n x 3n
   double* Mgj = nullptr;   // multipliers of one panel, n x 32
+  double* Uinv = nullptr;  // inverses of the diagonal blocks of U, 32 x 32 each, for the back substitution
   double *bins = nullptr, *prec_hist = nullptr, *prec_tot = nullptr, *logdet = nullptr;
   double *grad = nullptr, *gprec = nullptr;   // gradient rows [L][N] and the gradient pass's precision
   double* mpart = nullptr;                     // partial sums of the equal-time estimators
@@ -138,6 +139,9 @@ constexpr int kCounters = 8;
 // count, then <S^z> per orbital.
 inline size_t eq_bins_size(const dqmc_ctx* c) { return 4 * (size_t)c->N * kEqMaxOrb + 8; }
 inline size_t td_corr_stride(const dqmc_ctx* c) { return 4 * (size_t)c->N * kEqMaxOrb; }
+// inverted diagonal blocks of the LU solve: one 32 x 32 matrix per block of
+// the narrowest panel width (8), so the size does not depend on the width chosen
+inline size_t uinv_size(const dqmc_ctx* c) { return ((size_t)c->N + 7) / 8 * 1024; }
 inline size_t td_corr_size(const dqmc_ctx* c) {
   return c->nch == 1 ? (size_t)(c->L + 1) * td_corr_stride(c) + 4 : 0;
 }
@@ -177,6 +181,7 @@ size_t layout_chain(dqmc_ctx* c, double* base) {
   P(c->G2, NN);
   P(c->XA, 3 * NN);
   P(c->Mgj, 32 * N);
+  P(c->Uinv, uinv_size(c));
   P(c->field_alt, (size_t)c->L * N);
   P(c->norms, N);
   double* pv = nullptr;
@@ -541,17 +546,13 @@ dqmc_status lu_solve(dqmc_ctx* c, double* XA, int nrhs, int ld, double* logdet) 
                                             XA + (size_t)(j0 + nbw) * ld + j0 + nbw, ld, -1.0, 1.0)))
         return s;
   }
-  // back substitution, one diagonal block at a time from the last
-  const int last = ((N - 1) / nb) * nb;
-  for (int j0 = last; j0 >= 0; j0 -= nb) {
-    const int nbw = std::min(nb, N - j0);
-    hipLaunchKernelGGL(k_lu_diag, gridc(c, grid1(nrhs)), dim3(256), 0, c->stream, XA, N, ld, j0, nb, nrhs, c->cs);
-    HIPCHK(hipGetLastError());
-    if (j0 > 0)
-      if (dqmc_status s = gemm(c, gemm_args(j0, nrhs, nbw, XA + j0, ld, 0, XA + (size_t)j0 * ld + N, ld, 0, XA + N, ld,
-                                            -1.0, 1.0)))
-        return s;
-  }
+  // back substitution: the diagonal blocks' inverses, then every 16-column
+  // slab of the right-hand sides through the whole block recursion at once
+  const int nblk = (N + nb - 1) / nb;
+  hipLaunchKernelGGL(k_lu_diag_inv, gridc(c, (unsigned)nblk), dim3(256), 0, c->stream, XA, N, ld, nb, c->Uinv, c->cs);
+  hipLaunchKernelGGL(k_lu_back, gridc(c, (unsigned)((nrhs + kBackCols - 1) / kBackCols)), dim3(256), 0, c->stream, XA,
+                     N, ld, nb, nrhs, c->Uinv, c->cs);
+  HIPCHK(hipGetLastError());
   if (logdet) {
     hipLaunchKernelGGL(k_logabs_diag, gridc(c, 1), dim3(256), 0, c->stream, XA, N, ld, logdet, c->cs);
     HIPCHK(hipGetLastError());
@@ -1611,7 +1612,7 @@ bool layout_ok(const dqmc_ctx* c, const double* lo, const double* hi) {
        in(c->slots, (size_t)(c->nk + 1) * (2 * NN + N), true);
   for (int i = 0; i < 6; ++i) ok = ok && in(c->S[i], NN, true);
   for (const double* p : {c->Vall, c->VTall, c->Zq, c->Rt, c->X, c->RHS, c->Gs, c->T1, c->G2}) ok = ok && in(p, NN, true);
-  ok = ok && in(c->XA, 3 * NN, true) && in(c->Mgj, 32 * N, true);
+  ok = ok && in(c->XA, 3 * NN, true) && in(c->Mgj, 32 * N, true) && in(c->Uinv, uinv_size(c), true);
   for (const UDVp* u : {&c->cur, &c->hA, &c->hB}) ok = ok && in(u->Q, NN, true) && in(u->D, N, true) && in(u->T, NN, true);
   ok = ok && in(c->field_alt, (size_t)c->L * N, true) && in(c->norms, N, true) && in(c->piv, N / 2 + 1, true) &&
        in(c->moves, (kLuMoves + 1) / 2, true) && in(c->bins, 4, true) && in(c->prec_hist, 2 * (size_t)c->nk + 2, true) &&

@@ -749,6 +749,111 @@ __global__ __launch_bounds__(256) void k_lu_diag(double* XA, int n, int ld, int 
     if (r < nrow) B[(size_t)r * ld + col] = z[r];
 }
 
+// Back substitution of all right-hand sides in two launches, instead of one
+// diagonal solve and one product per block row:
+//   k_lu_diag_inv  inverts every diagonal block U_bb of U (grid (blocks,
+//                  chains), one workgroup each, the 32 columns of the inverse
+//                  by the backward solve of k_lu_diag on unit vectors); block
+//                  b is stored as a 32 x 32 row-major matrix at Uinv + 1024 b,
+//                  the identity beyond a ragged last block;
+//   k_lu_back      gives every workgroup 16 right-hand-side columns and runs
+//                  the whole backward block recursion on them, bottom block
+//                  first: Y_b = U_bb^-1 R_b (one 32 x 32 x 16 MFMA product,
+//                  written in place of R_b), then R[rows above] -= U[rows
+//                  above, b] Y_b (16-row MFMA tiles over the four waves).  The
+//                  column slabs are independent, so no workgroup waits for
+//                  another.
+constexpr int kBackCols = 16;
+
+__global__ __launch_bounds__(256) void k_lu_diag_inv(const double* XA, int n, int ld, int nb, double* Uinv,
+                                                     size_t cs) {
+  __shared__ __attribute__((aligned(16))) double tt[32][34];   // tt[k][r] = U[r][k]
+  __shared__ double dinv[32];
+  XA += (size_t)blockIdx.y * cs;
+  Uinv += (size_t)blockIdx.y * cs;
+  const int r0 = blockIdx.x * nb, nrow = min(nb, n - r0);
+  const double* U = XA + (size_t)r0 * ld + r0;
+  for (int e = threadIdx.x; e < 32 * 32; e += 256) {
+    const int r = e >> 5, k = e & 31;
+    tt[k][r] = (r < nrow && k < nrow && k >= r) ? U[(size_t)r * ld + k] : (r == k ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  if (threadIdx.x < 32) dinv[threadIdx.x] = 1.0 / tt[threadIdx.x][threadIdx.x];
+  __syncthreads();
+  if (threadIdx.x >= 32) return;
+  const int col = threadIdx.x;
+  double z[32];
+#pragma unroll
+  for (int r = 0; r < 32; ++r) z[r] = (r == col) ? 1.0 : 0.0;
+  tri_solve_back<false>(z, tt, dinv);
+  double* out = Uinv + (size_t)blockIdx.x * 1024;
+#pragma unroll
+  for (int r = 0; r < 32; ++r) out[r * 32 + col] = z[r];
+}
+
+__global__ __launch_bounds__(256) void k_lu_back(double* XA, int n, int ld, int nb, int nrhs, const double* Uinv,
+                                                 size_t cs) {
+  __shared__ double Rb[32][kBackCols + 1];   // R_b of this slab
+  __shared__ double Yb[32][kBackCols + 1];   // Y_b = U_bb^-1 R_b
+  XA += (size_t)blockIdx.y * cs;
+  Uinv += (size_t)blockIdx.y * cs;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int m16 = lane & 15, kk = lane >> 4;
+  const int c0 = blockIdx.x * kBackCols;             // first right-hand side of the slab
+  const int col = c0 + m16, colc = min(col, nrhs - 1);
+  const bool cin = col < nrhs;
+  double* R = XA + n;                                  // right-hand sides: R[r][j] at R[r * ld + j]
+  const int nblk = (n + nb - 1) / nb;
+  for (int b = nblk - 1; b >= 0; --b) {
+    const int j0 = b * nb, nbw = min(nb, n - j0);
+    for (int e = tid; e < 32 * kBackCols; e += 256) {
+      const int r = e / kBackCols, q = e % kBackCols;
+      const double v = R[(size_t)(j0 + min(r, nbw - 1)) * ld + min(c0 + q, nrhs - 1)];
+      Rb[r][q] = (r < nbw && c0 + q < nrhs) ? v : 0.0;
+    }
+    __syncthreads();
+    if (w < 2) {
+      // rows w*16 .. w*16+15 of Y_b (K = 32; Uinv is the identity past nbw)
+      const double* Ui = Uinv + (size_t)b * 1024;
+      v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int k0 = 0; k0 < 32; k0 += 4)
+        acc = mfma_f64_16x16x4(Ui[(w * 16 + m16) * 32 + k0 + kk], Rb[k0 + kk][m16], acc);
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int row = w * 16 + kk + 4 * rr;
+        Yb[row][m16] = acc[rr];
+        if (row < nbw && cin) R[(size_t)(j0 + row) * ld + col] = acc[rr];
+      }
+    }
+    __syncthreads();
+    // R[0:j0, slab] -= U[0:j0, j0:j0+nbw] Y_b in 16-row tiles; with 8-column
+    // panels the last tile may reach past j0, and those rows are left alone
+    for (int t = w; t * 16 < j0; t += 4) {
+      v4d acc;
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) acc[rr] = R[(size_t)min(t * 16 + kk + 4 * rr, n - 1) * ld + colc];
+      const int ra = t * 16 + m16;
+      const double* Urow = XA + (size_t)min(ra, n - 1) * ld + j0;
+#pragma unroll
+      for (int k0 = 0; k0 < 32; k0 += 4) {
+        if (k0 >= nbw) break;   // uniform
+        const int k = k0 + kk;
+        const double a = (k < nbw && ra < j0) ? -Urow[min(k, nbw - 1)] : 0.0;
+        acc = mfma_f64_16x16x4(a, Yb[k][m16], acc);
+      }
+      if (cin) {
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const int row = t * 16 + kk + 4 * rr;
+          if (row < j0) R[(size_t)row * ld + col] = acc[rr];
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // out += sum_i log|U_ii| (one workgroup)
 __global__ __launch_bounds__(256) void k_logabs_diag(const double* U, int n, int ld, double* out, size_t cs) {
   __shared__ double red[8];
