@@ -362,10 +362,21 @@ dqmc_status update_slice(dqmc_ctx* c, int tau) {
 }
 
 // ---------------------------------------------------- UDV stabilisation --
+// One QR step (k_qr_panel): the panel at j0 and, when there is a previous
+// panel (its factors at V - nb N, VT - nb N), that panel's block applied to
+// this panel's columns in the same workgroup and to the ntr columns right of
+// this panel by ntr / 16 more workgroups.
 template <int NBW, int MAXR>
 void qr_panel_launch(dqmc_ctx* c, double* Ap, int j0, int nbw, double* V, double* VT) {
-  hipLaunchKernelGGL((k_qr_panel<NBW, MAXR>), gridc(c, 1), dim3(256), sizeof(double) * qr_panel_lds<NBW>(64 * MAXR),
-                     c->stream, Ap, c->N, j0, nbw, V, VT, c->cs);
+  const int N = c->N;
+  const bool prev = j0 > 0;
+  const double* Vp = prev ? V - (size_t)NBW * N : nullptr;
+  const double* VTp = prev ? VT - (size_t)NBW * N : nullptr;
+  const int ntr = prev ? N - j0 - nbw : 0;
+  double* At = prev ? Ap + (size_t)(j0 - NBW) * N + j0 + nbw : nullptr;
+  const unsigned gx = 1 + (unsigned)((ntr + 15) / 16);
+  hipLaunchKernelGGL((k_qr_panel<NBW, MAXR>), gridc(c, gx), dim3(256), sizeof(double) * qr_panel_lds<NBW>(64 * MAXR),
+                     c->stream, Ap, N, j0, nbw, V, VT, Vp, VTp, At, ntr, c->cs);
 }
 
 // rows per lane = ceil(h / 64), rounded up to the instantiated counts; the
@@ -410,13 +421,17 @@ dqmc_status launch_lu_panel(dqmc_ctx* c, double* XA, int ld, int j0, int nbw) {
   return DQMC_OK;
 }
 
+// each QR panel instance's dynamic LDS limit: exactly what its launch asks for
+// (the static apply_wy_slab scratch comes on top, within the 160 KB of a CU)
 template <int NBW, int R1, int R2, int R3>
 hipError_t lds_limit_qr() {
   const void* fns[] = {reinterpret_cast<const void*>(k_qr_panel<NBW, R1>),
                        reinterpret_cast<const void*>(k_qr_panel<NBW, R2>),
                        reinterpret_cast<const void*>(k_qr_panel<NBW, R3>)};
-  for (const void* f : fns) {
-    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 156 * 1024);
+  const int rows[] = {R1, R2, R3};
+  for (int i = 0; i < 3; ++i) {
+    hipError_t e = hipFuncSetAttribute(fns[i], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)(sizeof(double) * qr_panel_lds<NBW>(64 * rows[i])));
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -460,18 +475,13 @@ dqmc_status qr_udv(dqmc_ctx* c, double* M, const double* T_in, UDVp out) {
   hipLaunchKernelGGL(k_permute_cols, gridc(c, grid1((size_t)N * N)), dim3(256), 0, c->stream, Ap, M, c->piv, N,
                      c->cs);
   HIPCHK(hipGetLastError());
+  // one launch per panel: each applies the previous panel's reflectors (to
+  // its own columns and, in other workgroups, to the rest) and factorises
   for (int j0 = 0; j0 < N; j0 += nb) {
-    const int nbw = std::min(nb, N - j0), h = N - j0;
+    const int nbw = std::min(nb, N - j0);
     double* V = c->Vall + (size_t)j0 * N;
     double* VT = c->VTall + (size_t)j0 * N;
     if (dqmc_status s = launch_qr_panel(c, Ap, j0, nbw, V, VT)) return s;
-    const int ntr = N - j0 - nbw;
-    if (ntr > 0) {
-      double* At = Ap + (size_t)j0 * N + j0 + nbw;
-      hipLaunchKernelGGL(k_apply_wy, gridc(c, (unsigned)((ntr + 15) / 16)), dim3(256), 0, c->stream, V, VT, nbw, At,
-                         N, h, ntr, nbw, c->cs, c->cs);
-      HIPCHK(hipGetLastError());
-    }
   }
   // explicit Q by backward accumulation of the block reflectors
   hipLaunchKernelGGL(k_set_identity, gridc(c, grid1((size_t)N * N)), dim3(256), 0, c->stream, out.Q, N, N, c->cs);

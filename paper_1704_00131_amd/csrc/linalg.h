@@ -122,6 +122,113 @@ __global__ void k_permute_cols(double* dst, const double* src, const int* piv, i
   dst[e] = src[(size_t)i * n + piv[j]];
 }
 
+// Block reflector applied to one 16-column slab: C <- C - P (S^T C) for the
+// columns 16 bx .. 16 bx + 15 of an h x ncol block C (ld ldc) and the h x nbw
+// factors P, S (ld ldps, nbw <= 32): with (P, S) = (V, VT) it is Q^T C for the
+// trailing matrix of a QR panel, with (VT, V) it is Q C for the accumulation
+// of Q.  The four waves split the rows for Z = S^T C (two 16 x 16 MFMA tiles
+// each, summed through LDS), then split the 16-row tiles of C for C - P Z
+// (the accumulator starts from C and P enters negated).  Operands are read
+// from clamped addresses and masked, so the loads issue back to back.  C may
+// live in global memory or in LDS (generic addressing).  Every wave of the
+// workgroup calls it; zp and Zs are the workgroup's LDS scratch.
+__device__ __forceinline__ void apply_wy_slab(const double* P, const double* S, int ldps, double* C, int ldc, int h,
+                                              int ncol, int nbw, int bx, double (*zp)[2][4][64],
+                                              double (*Zs)[17]) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int m16 = lane & 15, kk = lane >> 4;
+  const int c0 = bx * 16, col = c0 + m16, colc = min(col, ncol - 1);
+  const bool cin = col < ncol;
+  // Z = S^T C over this wave's quarter of the rows, k-steps of 4
+  const int kq = ((h + 15) / 16) * 4;
+  const int kb = w * kq, ke = min(h, kb + kq);
+  v4d z[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+  constexpr int U = 6;   // k-steps whose loads are issued together
+  for (int kc = kb; kc < ke; kc += 4 * U) {
+    double a[U][2], b[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int rc = min(kc + 4 * u + kk, h - 1);
+#pragma unroll
+      for (int t = 0; t < 2; ++t) a[u][t] = S[(size_t)rc * ldps + min(t * 16 + m16, nbw - 1)];
+      b[u] = C[(size_t)rc * ldc + colc];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool rin = kc + 4 * u + kk < ke;
+#pragma unroll
+      for (int t = 0; t < 2; ++t) a[u][t] = (rin && t * 16 + m16 < nbw) ? a[u][t] : 0.0;
+      b[u] = (rin && cin) ? b[u] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) z[t] = mfma_f64_16x16x4(a[u][t], b[u], z[t]);
+  }
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) zp[w][t][rr][lane] = z[t][rr];
+  __syncthreads();
+  if (w == 0) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const double v = (zp[0][t][rr][lane] + zp[1][t][rr][lane]) + (zp[2][t][rr][lane] + zp[3][t][rr][lane]);
+        Zs[t * 16 + kk + 4 * rr][m16] = v;   // D layout: row kk + 4 rr, column m16 of tile t
+      }
+  }
+  __syncthreads();
+  // C tile - P Z, 16-row tiles over the waves; K = nbw in steps of 4 (Z rows past nbw are zero)
+  double zb[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) zb[k] = (4 * k + kk < nbw) ? Zs[4 * k + kk][m16] : 0.0;
+  const int nrt = (h + 15) / 16;
+  for (int tr0 = w; tr0 < nrt; tr0 += 8) {   // two row tiles per round, their loads together
+    v4d acc[2];
+    double pa[2][8];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int r0 = (tr0 + 4 * q) * 16, pr = min(r0 + m16, h - 1);
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) acc[q][rr] = C[(size_t)min(r0 + kk + 4 * rr, h - 1) * ldc + colc];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) pa[q][k] = P[(size_t)pr * ldps + min(4 * k + kk, nbw - 1)];
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int k = 0; k < 8; ++k) pa[q][k] = (4 * k + kk < nbw) ? -pa[q][k] : 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) acc[q] = mfma_f64_16x16x4(pa[q][k], zb[k], acc[q]);
+    if (cin) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        if (tr0 + 4 * q >= nrt) break;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const int r = (tr0 + 4 * q) * 16 + kk + 4 * rr;
+          if (r < h) C[(size_t)r * ldc + col] = acc[q][rr];
+        }
+      }
+    }
+  }
+}
+
+// One launch of apply_wy_slab per 16 columns of C (grid (slabs, chains)).
+__global__ __launch_bounds__(256) void k_apply_wy(const double* P, const double* S, int ldps, double* C, int ldc,
+                                                  int h, int ncol, int nbw, size_t cs_ps, size_t cs_c) {
+  __shared__ double zp[4][2][4][64];   // per-wave partial Z tiles in the MFMA D layout
+  __shared__ double Zs[32][17];        // Z: nbw x 16
+  P += (size_t)blockIdx.y * cs_ps;
+  S += (size_t)blockIdx.y * cs_ps;
+  C += (size_t)blockIdx.y * cs_c;
+  apply_wy_slab(P, S, ldps, C, ldc, h, ncol, nbw, blockIdx.x, zp, Zs);
+}
+
 // ---------------------------------------------------------- QR panel ----
 // Householder QR of one panel (columns j0..j0+nbw-1, rows j0..n-1 of A, ld n)
 // by one workgroup, with the compact-WY output V (h x nbw, ld nbw, unit lower
@@ -147,24 +254,43 @@ __global__ void k_permute_cols(double* dst, const double* src, const int* piv, i
 // in Y.  After the loop: the T recurrence
 // T[t][i] = -tau_i sum_{k<i} T[t][k] Y[k][i] row by row (each lane one row,
 // the two halves of the wave splitting k), and VT = V T by MFMA.
+// Dynamic LDS of k_qr_panel: NBW rows above the panel (the previous panel's
+// rows), the panel's rows, Y, T, tau and the diagonal of R.
 template <int NBW>
 __host__ __device__ inline size_t qr_panel_lds(int rows) {
-  return (size_t)rows * (NBW + 1) + 2 * (size_t)NBW * (NBW + 1) + 2 * NBW;
+  return (size_t)(rows + NBW) * (NBW + 1) + 2 * (size_t)NBW * (NBW + 1) + 2 * NBW;
 }
 
+// One step of the blocked QR in one launch.  Workgroup 0 factorises the panel
+// j0 .. j0 + nbw - 1; when the previous panel's reflector block (Vp, VTp,
+// rows j0 - NBW .. n-1, ld NBW) is given, it first applies that block to its
+// own columns in LDS (rows j0 - NBW onward) and writes the previous panel's
+// rows of them (entries of R) back.  The other workgroups apply the same
+// previous block to the columns right of this panel (At: rows j0 - NBW ..,
+// columns j0 + nbw .., ntr of them, 16 per workgroup), which this panel does
+// not touch, so the two roles never wait for each other.
 template <int NBW, int MAXR>
 __global__ __launch_bounds__(256) void k_qr_panel(double* A, int n, int j0, int nbw, double* Vout,
-                                                  double* VTout, size_t cs) {
+                                                  double* VTout, const double* Vp, const double* VTp, double* At,
+                                                  int ntr, size_t cs) {
   extern __shared__ double smem[];
+  __shared__ double zp[4][2][4][64];   // apply_wy_slab scratch (either role)
+  __shared__ double Zs[32][17];
   constexpr int CPW = NBW / 4, PV = NBW + 1, PY = NBW + 1, NE = MAXR * NBW / 4, HR = 64 * MAXR;
   static_assert(NBW <= 32, "rows at or above the diagonal must sit in the first row group");
   {
     const size_t co = (size_t)blockIdx.y * cs;
     A += co; Vout += co; VTout += co;
+    if (Vp) { Vp += co; VTp += co; At += co; }
   }
   const int h = n - j0, tid = threadIdx.x, lane = tid & 63;
+  if (blockIdx.x > 0) {   // trailing columns: the previous panel's block reflector
+    apply_wy_slab(Vp, VTp, NBW, At, n, h + NBW, ntr, NBW, blockIdx.x - 1, zp, Zs);
+    return;
+  }
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  double* vsh = smem;                       // HR x PV: the panel, then V
+  double* top = smem;                       // NBW x PV: rows j0 - NBW .. j0 - 1 of the panel's columns
+  double* vsh = top + NBW * PV;             // HR x PV: the panel, then V
   double* Ym = vsh + HR * PV;               // NBW x PY: strictly upper V^T V
   double* Tm = Ym + NBW * PY;               // NBW x PY: T
   double* tau = Tm + NBW * PY;              // NBW
@@ -180,6 +306,21 @@ __global__ __launch_bounds__(256) void k_qr_panel(double* A, int n, int j0, int 
     for (int u = 0; u < NE; ++u) {
       const int e = tid + 256 * u, r = e / NBW, q = e % NBW;
       vsh[r * PV + q] = t[u];
+    }
+  }
+  if (Vp) {
+    // the previous panel's rows of these columns, then that panel's block
+    // reflector on [top; vsh] (h + NBW rows) in LDS, NBW / 16 slabs
+    for (int e = tid; e < NBW * NBW; e += 256) {
+      const int r = e / NBW, q = e % NBW;
+      top[r * PV + q] = (q < nbw) ? A[(size_t)(j0 - NBW + r) * n + j0 + q] : 0.0;
+    }
+    __syncthreads();
+    for (int bx = 0; bx * 16 < NBW; ++bx) apply_wy_slab(Vp, VTp, NBW, top, PV, h + NBW, nbw, NBW, bx, zp, Zs);
+    __syncthreads();
+    for (int e = tid; e < NBW * NBW; e += 256) {
+      const int r = e / NBW, q = e % NBW;
+      if (q < nbw) A[(size_t)(j0 - NBW + r) * n + j0 + q] = top[r * PV + q];
     }
   }
   for (int e = tid; e < NBW * PY; e += 256) Ym[e] = 0.0;
@@ -327,104 +468,6 @@ __global__ __launch_bounds__(256) void k_qr_panel(double* A, int n, int j0, int 
       for (int rr = 0; rr < 4; ++rr) {
         const int orow = tr * 16 + kk + 4 * rr;
         if (orow < h && col < nbw) VTout[(size_t)orow * nbw + col] = acc[tc][rr];
-      }
-    }
-  }
-}
-
-// Block reflector applied in one launch: C <- C - P (S^T C) for an h x ncol
-// block C (ld ldc) and the h x nbw factors P, S (ld ldps, nbw <= 32): with
-// (P, S) = (V, VT) it is Q^T C for the trailing matrix of a QR panel, with
-// (VT, V) it is Q C for the accumulation of Q.  One workgroup per 16 columns
-// of C: the four waves split the rows for Z = S^T C (two 16 x 16 MFMA tiles
-// each, summed through LDS), then split the 16-row tiles of C for
-// C - P Z (the accumulator starts from C and P enters negated).  Operands are
-// read from clamped addresses and masked, so the loads issue back to back.
-__global__ __launch_bounds__(256) void k_apply_wy(const double* P, const double* S, int ldps, double* C, int ldc,
-                                                  int h, int ncol, int nbw, size_t cs_ps, size_t cs_c) {
-  __shared__ double zp[4][2][4][64];   // per-wave partial Z tiles in the MFMA D layout
-  __shared__ double Zs[32][17];        // Z: nbw x 16
-  P += (size_t)blockIdx.y * cs_ps;
-  S += (size_t)blockIdx.y * cs_ps;
-  C += (size_t)blockIdx.y * cs_c;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int m16 = lane & 15, kk = lane >> 4;
-  const int c0 = blockIdx.x * 16, col = c0 + m16, colc = min(col, ncol - 1);
-  const bool cin = col < ncol;
-  // Z = S^T C over this wave's quarter of the rows, k-steps of 4
-  const int kq = ((h + 15) / 16) * 4;
-  const int kb = w * kq, ke = min(h, kb + kq);
-  v4d z[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
-  constexpr int U = 6;   // k-steps whose loads are issued together
-  for (int kc = kb; kc < ke; kc += 4 * U) {
-    double a[U][2], b[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int rc = min(kc + 4 * u + kk, h - 1);
-#pragma unroll
-      for (int t = 0; t < 2; ++t) a[u][t] = S[(size_t)rc * ldps + min(t * 16 + m16, nbw - 1)];
-      b[u] = C[(size_t)rc * ldc + colc];
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const bool rin = kc + 4 * u + kk < ke;
-#pragma unroll
-      for (int t = 0; t < 2; ++t) a[u][t] = (rin && t * 16 + m16 < nbw) ? a[u][t] : 0.0;
-      b[u] = (rin && cin) ? b[u] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int t = 0; t < 2; ++t) z[t] = mfma_f64_16x16x4(a[u][t], b[u], z[t]);
-  }
-#pragma unroll
-  for (int t = 0; t < 2; ++t)
-#pragma unroll
-    for (int rr = 0; rr < 4; ++rr) zp[w][t][rr][lane] = z[t][rr];
-  __syncthreads();
-  if (w == 0) {
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-      for (int rr = 0; rr < 4; ++rr) {
-        const double v = (zp[0][t][rr][lane] + zp[1][t][rr][lane]) + (zp[2][t][rr][lane] + zp[3][t][rr][lane]);
-        Zs[t * 16 + kk + 4 * rr][m16] = v;   // D layout: row kk + 4 rr, column m16 of tile t
-      }
-  }
-  __syncthreads();
-  // C tile - P Z, 16-row tiles over the waves; K = nbw in steps of 4 (Z rows past nbw are zero)
-  double zb[8];
-#pragma unroll
-  for (int k = 0; k < 8; ++k) zb[k] = (4 * k + kk < nbw) ? Zs[4 * k + kk][m16] : 0.0;
-  const int nrt = (h + 15) / 16;
-  for (int tr0 = w; tr0 < nrt; tr0 += 8) {   // two row tiles per round, their loads together
-    v4d acc[2];
-    double pa[2][8];
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int r0 = (tr0 + 4 * q) * 16, pr = min(r0 + m16, h - 1);
-#pragma unroll
-      for (int rr = 0; rr < 4; ++rr) acc[q][rr] = C[(size_t)min(r0 + kk + 4 * rr, h - 1) * ldc + colc];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) pa[q][k] = P[(size_t)pr * ldps + min(4 * k + kk, nbw - 1)];
-    }
-#pragma unroll
-    for (int q = 0; q < 2; ++q)
-#pragma unroll
-      for (int k = 0; k < 8; ++k) pa[q][k] = (4 * k + kk < nbw) ? -pa[q][k] : 0.0;
-#pragma unroll
-    for (int k = 0; k < 8; ++k)
-#pragma unroll
-      for (int q = 0; q < 2; ++q) acc[q] = mfma_f64_16x16x4(pa[q][k], zb[k], acc[q]);
-    if (cin) {
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        if (tr0 + 4 * q >= nrt) break;
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-          const int r = (tr0 + 4 * q) * 16 + kk + 4 * rr;
-          if (r < h) C[(size_t)r * ldc + col] = acc[q][rr];
-        }
       }
     }
   }
