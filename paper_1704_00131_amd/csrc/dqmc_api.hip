@@ -142,6 +142,8 @@ inline size_t td_corr_stride(const dqmc_ctx* c) { return 4 * (size_t)c->N * kEqM
 // inverted diagonal blocks of the LU solve: one 32 x 32 matrix per block of
 // the narrowest panel width (8), so the size does not depend on the width chosen
 inline size_t uinv_size(const dqmc_ctx* c) { return ((size_t)c->N + 7) / 8 * 1024; }
+// partial records of the time-displaced estimator, then its completion counter
+inline size_t td_part_size(const dqmc_ctx* c) { return ((size_t)c->N + kTdRows - 1) / kTdRows * kTdPart + 4; }
 inline size_t td_corr_size(const dqmc_ctx* c) {
   return c->nch == 1 ? (size_t)(c->L + 1) * td_corr_stride(c) + 4 : 0;
 }
@@ -198,7 +200,7 @@ size_t layout_chain(dqmc_ctx* c, double* base) {
   for (int i = 0; i < 4; ++i) P(c->TD[i], NN);
   P(c->tdS, (size_t)(c->L + 1) * kTdStride);
   P(c->tdbins, (size_t)(c->L + 1) * kTdStride + 4);
-  P(c->tdpart, (size_t)((N + kTdRows - 1) / kTdRows) * kTdPart);
+  P(c->tdpart, td_part_size(c));
   P(c->a00, 2 * kTdMaxOrb);
   P(c->eq_bins, eq_bins_size(c));
   P(c->td_g00, N);
@@ -268,6 +270,34 @@ dqmc_status gemm(dqmc_ctx* c, GemmArgs g) {
   if (dqmc_status s = timing_begin(c, DQMC_KERNEL_GEMM)) return s;
   HIPCHK(launch_gemm(g, c->stream));
   if (c->timing_open && c->timing_kernel == DQMC_KERNEL_GEMM) c->timed_flops += 2.0 * g.M * (double)g.N * g.K * c->nch;
+  return timing_end(c, DQMC_KERNEL_GEMM);
+}
+
+// Up to three independent products of the same shape in one launch.
+dqmc_status gemm_group(dqmc_ctx* c, GemmArgs* gs, int count) {
+  GemmGroup gg;
+  double flops = 0.0;
+  for (int i = 0; i < count; ++i) {
+    GemmArgs g = gs[i];
+    g.nch = c->nch;
+    g.tile = c->gemm_tile;
+    g.cstride = c->cs;
+    g.pc = 0;
+    if (c->cs) {
+      if (!is_shared(c, g.A)) g.pc |= PC_A;
+      if (!is_shared(c, g.B)) g.pc |= PC_B;
+      if (!is_shared(c, g.C)) g.pc |= PC_C;
+      if (g.rs && !is_shared(c, g.rs)) g.pc |= PC_RS;
+      if (g.cs && !is_shared(c, g.cs)) g.pc |= PC_CS;
+      if (g.ks && !is_shared(c, g.ks)) g.pc |= PC_KS;
+    }
+    if (g.M != gs[0].M || g.N != gs[0].N) return fail(c, DQMC_E_ARG, "grouped products of different shapes");
+    gg.g[i] = g;
+    flops += 2.0 * g.M * (double)g.N * g.K * c->nch;
+  }
+  if (dqmc_status s = timing_begin(c, DQMC_KERNEL_GEMM)) return s;
+  HIPCHK(launch_gemm_group(gg, count, c->stream));
+  if (c->timing_open && c->timing_kernel == DQMC_KERNEL_GEMM) c->timed_flops += flops;
   return timing_end(c, DQMC_KERNEL_GEMM);
 }
 
@@ -888,12 +918,16 @@ dqmc_status td_anchor(dqmc_ctx* c, UDVp R, UDVp Lf, double* gt0, double* h) {
 dqmc_status td_measure(dqmc_ctx* c, int tau, const double* gt0, const double* h, const double* gtt) {
   const int N = c->N;
   if (c->m.trotter == DQMC_TROTTER_SYM) {
-    if (dqmc_status s = gemm(c, gemm_args(N, N, N, c->Eh, N, 0, gt0, N, 0, c->T1, N))) return s;
-    if (dqmc_status s = gemm(c, gemm_args(N, N, N, c->T1, N, 0, c->Ehinv, N, 0, c->Gs, N))) return s;
-    if (dqmc_status s = gemm(c, gemm_args(N, N, N, c->Ehinv, N, 0, h, N, 0, c->T1, N))) return s;
-    if (dqmc_status s = gemm(c, gemm_args(N, N, N, c->T1, N, 0, c->Eh, N, 0, c->X, N))) return s;
-    if (dqmc_status s = gemm(c, gemm_args(N, N, N, c->Eh, N, 0, gtt, N, 0, c->T1, N))) return s;
-    if (dqmc_status s = gemm(c, gemm_args(N, N, N, c->T1, N, 0, c->Ehinv, N, 0, c->RHS, N))) return s;
+    // e^{-dtau K/2} (.) e^{+dtau K/2} of GT0 and GTT, e^{+dtau K/2} H e^{-dtau K/2}:
+    // the three left products in one launch, then the three right products
+    GemmArgs gl[3] = {gemm_args(N, N, N, c->Eh, N, 0, gt0, N, 0, c->T1, N),
+                      gemm_args(N, N, N, c->Ehinv, N, 0, h, N, 0, c->Zq, N),
+                      gemm_args(N, N, N, c->Eh, N, 0, gtt, N, 0, c->Rt, N)};
+    if (dqmc_status s = gemm_group(c, gl, 3)) return s;
+    GemmArgs gr[3] = {gemm_args(N, N, N, c->T1, N, 0, c->Ehinv, N, 0, c->Gs, N),
+                      gemm_args(N, N, N, c->Zq, N, 0, c->Eh, N, 0, c->X, N),
+                      gemm_args(N, N, N, c->Rt, N, 0, c->Ehinv, N, 0, c->RHS, N)};
+    if (dqmc_status s = gemm_group(c, gr, 3)) return s;
     gt0 = c->Gs; h = c->X; gtt = c->RHS;
   }
   if (c->td_corr_now) {
@@ -909,13 +943,10 @@ dqmc_status td_measure(dqmc_ctx* c, int tau, const double* gt0, const double* h,
     HIPCHK(hipGetLastError());
   }
   const int nblk = (N + kTdRows - 1) / kTdRows;
-  hipLaunchKernelGGL(k_td_partial, gridc(c, (unsigned)nblk), dim3(256), 0, c->stream, gt0, h, gtt, c->kph, c->korb,
-                     N, c->tdpart, c->cs);
-  HIPCHK(hipGetLastError());
   const size_t off = (size_t)tau * kTdStride;
-  hipLaunchKernelGGL(k_td_finish, gridc(c, 1), dim3(64), 0, c->stream, c->tdpart, nblk, 1.0 / c->td_cells, c->a00,
-                     c->tdS + off, c->tdbins + off, c->tdbins + (size_t)(c->L + 1) * kTdStride, tau == 0 ? 1 : 0,
-                     c->cs);
+  hipLaunchKernelGGL(k_td_measure, gridc(c, (unsigned)nblk), dim3(256), 0, c->stream, gt0, h, gtt, c->kph, c->korb, N,
+                     c->tdpart, 1.0 / c->td_cells, c->a00, c->tdS + off, c->tdbins + off,
+                     c->tdbins + (size_t)(c->L + 1) * kTdStride, tau == 0 ? 1 : 0, c->cs);
   HIPCHK(hipGetLastError());
   return DQMC_OK;
 }
@@ -943,14 +974,20 @@ dqmc_status td_pass(dqmc_ctx* c) {
   UDVp bufs[2] = {c->hA, c->hB};
   int b = 0;
   for (int tau = 1; tau <= L; ++tau) {
-    if (dqmc_status s = wrap_up(c, tau, c->G2)) return s;
-    GemmArgs ga = gemm_args(N, N, N, c->E, N, 0, gt0, N, 0, gt0_alt, N);
-    ga.rs = field_row(c, tau); ga.rs_mode = SC_EXP; ga.rs_coef = c->m.coupling;
-    if (dqmc_status s = gemm(c, ga)) return s;
+    // three independent left products in one launch: E GTT (first half of
+    // the wrap), B_tau GT0 and B_tau^-T H; then the wrap's second half
+    GemmArgs g3[3];
+    g3[0] = gemm_args(N, N, N, c->E, N, 0, c->G2, N, 0, c->T1, N);
+    g3[1] = gemm_args(N, N, N, c->E, N, 0, gt0, N, 0, gt0_alt, N);
+    g3[1].rs = field_row(c, tau); g3[1].rs_mode = SC_EXP; g3[1].rs_coef = c->m.coupling;
+    g3[2] = gemm_args(N, N, N, c->Einv, N, 0, h, N, 0, h_alt, N);
+    g3[2].rs = field_row(c, tau); g3[2].rs_mode = SC_EXP; g3[2].rs_coef = -c->m.coupling;
+    if (dqmc_status s = gemm_group(c, g3, 3)) return s;
+    GemmArgs gw = gemm_args(N, N, N, c->T1, N, 0, c->Einv, N, 0, c->G2, N);
+    gw.rs = field_row(c, tau); gw.rs_mode = SC_EXP; gw.rs_coef = c->m.coupling;
+    gw.cs = field_row(c, tau); gw.cs_mode = SC_EXP; gw.cs_coef = -c->m.coupling;
+    if (dqmc_status s = gemm(c, gw)) return s;
     std::swap(gt0, gt0_alt);
-    GemmArgs gh = gemm_args(N, N, N, c->Einv, N, 0, h, N, 0, h_alt, N);
-    gh.rs = field_row(c, tau); gh.rs_mode = SC_EXP; gh.rs_coef = -c->m.coupling;
-    if (dqmc_status s = gemm(c, gh)) return s;
     std::swap(h, h_alt);
     if (tau % nw == 0) {
       const int k = tau / nw;
@@ -1096,8 +1133,9 @@ dqmc_status setup_device(dqmc_ctx* c) {
   if (dqmc_status s = fill_small(c, c->uid.D, N, 1.0)) return s;
   if (dqmc_status s = fill_small(c, reinterpret_cast<double*>(c->counters), kCounters, 0.0)) return s;
   if (dqmc_status s = fill_small(c, reinterpret_cast<double*>(c->err_flag), 1, 0.0)) return s;
-  // measurement partials and their completion counter
+  // measurement partials and their completion counters
   if (dqmc_status s = fill_small(c, c->mpart, 4 * (size_t)((N + kMeasRows - 1) / kMeasRows) + 4, 0.0)) return s;
+  if (dqmc_status s = fill_small(c, c->tdpart, td_part_size(c), 0.0)) return s;
   if (c->seeds.empty()) c->seeds.assign(c->nch, c->m.seed);
   // chain keys: host -> staging buffer -> counters[3] of every chain
   HIPCHK(hipMemcpyAsync(c->gbuf, c->seeds.data(), sizeof(uint64_t) * c->nch, hipMemcpyHostToDevice, c->stream));
@@ -1632,7 +1670,7 @@ bool layout_ok(const dqmc_ctx* c, const double* lo, const double* hi) {
        in(c->TD[0], NN, true) && in(c->TD[1], NN, true) && in(c->TD[2], NN, true) && in(c->TD[3], NN, true) &&
        in(c->tdS, (size_t)(c->L + 1) * kTdStride, true) &&
        in(c->tdbins, (size_t)(c->L + 1) * kTdStride + 4, true) &&
-       in(c->tdpart, (size_t)((N + kTdRows - 1) / kTdRows) * kTdPart, true) && in(c->a00, 2 * kTdMaxOrb, true) &&
+       in(c->tdpart, td_part_size(c), true) && in(c->a00, 2 * kTdMaxOrb, true) &&
        in(c->kph, 2 * N, false) && in(c->korb, N / 2 + 1, false) && in(c->eq_sign, N, false) &&
        in(c->eq_site, N / 2 + 1, false) && in(c->eq_bins, eq_bins_size(c), true) && in(c->td_g00, N, true) &&
        (td_corr_size(c) == 0 || in(c->td_corr, td_corr_size(c), true)) &&

@@ -35,7 +35,7 @@ struct GemmArgs {
 enum { PC_A = 1, PC_B = 2, PC_C = 4, PC_RS = 8, PC_CS = 16, PC_KS = 32 };
 
 template <int TILE, int UNR, int WV>
-__global__ __launch_bounds__(64 * WV) void k_gemm(GemmArgs g) {
+__device__ __forceinline__ void gemm_tile(GemmArgs g) {
   constexpr int NB = TILE / 16;
   if (g.cstride) {
     const size_t co = (size_t)blockIdx.y * g.cstride;
@@ -131,6 +131,20 @@ __global__ __launch_bounds__(64 * WV) void k_gemm(GemmArgs g) {
         *cp = v;
       }
     }
+}
+
+template <int TILE, int UNR, int WV>
+__global__ __launch_bounds__(64 * WV) void k_gemm(GemmArgs g) {
+  gemm_tile<TILE, UNR, WV>(g);
+}
+
+// Up to three independent products of the same M x N shape in one launch
+// (blockIdx.z picks the product), so small products fill more of the chip.
+struct GemmGroup { GemmArgs g[3]; };
+
+template <int TILE, int UNR, int WV>
+__global__ __launch_bounds__(64 * WV) void k_gemm_group(GemmGroup gg) {
+  gemm_tile<TILE, UNR, WV>(gg.g[blockIdx.z]);
 }
 
 // Large products: a 64 x 64 tile per workgroup, K in steps of 32 staged
@@ -231,7 +245,7 @@ __device__ __forceinline__ void gemm64_store(double* As, double* Bs, const doubl
 }
 
 template <int TA, int TB>
-__global__ __launch_bounds__(256) void k_gemm64(GemmArgs g, int ntiles) {
+__device__ __forceinline__ void gemm64_tile(GemmArgs g, int ntiles) {
   // physical workgroup -> logical tile: each XCD (physical id mod 8) gets a
   // contiguous range of tiles
   const int per = (ntiles + kGXcd - 1) / kGXcd;
@@ -310,6 +324,17 @@ __global__ __launch_bounds__(256) void k_gemm64(GemmArgs g, int ntiles) {
   }
 }
 
+template <int TA, int TB>
+__global__ __launch_bounds__(256) void k_gemm64(GemmArgs g, int ntiles) {
+  gemm64_tile<TA, TB>(g, ntiles);
+}
+
+// Grouped products (blockIdx.z picks one) on the LDS-staged 64 x 64 tiles.
+template <int TA, int TB>
+__global__ __launch_bounds__(256) void k_gemm64_group(GemmGroup gg, int ntiles) {
+  gemm64_tile<TA, TB>(gg.g[blockIdx.z], ntiles);
+}
+
 __host__ __device__ inline GemmArgs gemm_args(int M, int N, int K, const double* A, int lda, int transA,
                                             const double* B, int ldb, int transB, double* C, int ldc,
                                             double alpha = 1.0, double beta = 0.0) {
@@ -329,12 +354,42 @@ __host__ __device__ inline GemmArgs gemm_args(int M, int N, int K, const double*
 // Raise the dynamic LDS limit of the four k_gemm64 instances (once per device).
 static inline hipError_t gemm64_set_lds() {
   const void* fns[] = {reinterpret_cast<const void*>(k_gemm64<0, 0>), reinterpret_cast<const void*>(k_gemm64<0, 1>),
-                       reinterpret_cast<const void*>(k_gemm64<1, 0>), reinterpret_cast<const void*>(k_gemm64<1, 1>)};
+                       reinterpret_cast<const void*>(k_gemm64<1, 0>), reinterpret_cast<const void*>(k_gemm64<1, 1>),
+                       reinterpret_cast<const void*>(k_gemm64_group<0, 0>)};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)gemm64_lds());
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+// A group of products (same M, N and chain count; count <= 3) with the direct
+// kernel; tiles as launch_gemm picks them for the whole group.
+static inline hipError_t launch_gemm_group(const GemmGroup& gg, int count, hipStream_t s) {
+  const GemmArgs& g = gg.g[0];
+  if (g.M <= 0 || g.N <= 0 || count < 1 || count > 3) return hipSuccess;
+  const int nch = g.nch > 0 ? g.nch : 1;
+  // enough 64 x 64 tiles over the group to cover the chip: the LDS-staged kernel
+  bool plain = true;
+  for (int i = 0; i < count; ++i) plain = plain && !gg.g[i].transA && !gg.g[i].transB;
+  const int t64 = ((g.M + 63) / 64) * ((g.N + 63) / 64);
+  if (plain && g.tile != 16 && g.tile != 32 && (long long)t64 * nch * count >= 240) {
+    const unsigned blocks = (unsigned)(((t64 + kGXcd - 1) / kGXcd) * kGXcd);
+    hipLaunchKernelGGL((k_gemm64_group<0, 0>), dim3(blocks, nch, count), dim3(256), gemm64_lds(), s, gg, t64);
+    return hipGetLastError();
+  }
+  const int t32 = ((g.M + 31) / 32) * ((g.N + 31) / 32);
+  const bool use32 = g.tile == 32 || (g.tile != 16 && (long long)t32 * nch * count >= 192);
+  const bool deep = nch == 1 && g.K >= 128;
+  if (use32) {
+    if (deep) hipLaunchKernelGGL((k_gemm_group<32, 2, 8>), dim3(t32, nch, count), dim3(512), 0, s, gg);
+    else hipLaunchKernelGGL((k_gemm_group<32, 1, 4>), dim3(t32, nch, count), dim3(256), 0, s, gg);
+  } else {
+    const int t16 = ((g.M + 15) / 16) * ((g.N + 15) / 16);
+    if (deep) hipLaunchKernelGGL((k_gemm_group<16, 1, 8>), dim3(t16, nch, count), dim3(512), 0, s, gg);
+    else hipLaunchKernelGGL((k_gemm_group<16, 1, 4>), dim3(t16, nch, count), dim3(256), 0, s, gg);
+  }
+  return hipGetLastError();
 }
 
 // Tile choice: g.tile = 16, 32 or 64 forces it (64: the LDS-staged kernel, an

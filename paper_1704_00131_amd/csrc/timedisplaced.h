@@ -18,7 +18,7 @@
 #include "device_common.h"
 
 constexpr int kTdMaxOrb = 4;          // orbitals per unit cell
-constexpr int kTdRows = 8;            // rows of the product per workgroup
+constexpr int kTdRows = 4;            // rows of the product per workgroup
 constexpr int kTdPart = 2 * kTdMaxOrb * kTdMaxOrb + 2 * kTdMaxOrb;   // doubles per partial record
 constexpr int kTdStride = 2 * kTdMaxOrb * kTdMaxOrb;                 // doubles per tau of S
 
@@ -70,18 +70,30 @@ __global__ __launch_bounds__(256) void k_td_rhs(double* R2, int ld_r, const doub
   }
 }
 
-// Partial sums of C_ab and A_a over kTdRows rows per workgroup; grid
-// (ceil(n / kTdRows), chains), 256 threads.  phase: [n][2] (re, im) of
-// exp(-i K.R_x); orb: [n] orbital of each site (< norb <= kTdMaxOrb).
-__global__ __launch_bounds__(256) void k_td_partial(const double* GT0, const double* H, const double* GTT,
+// S_ab(K, tau) in one launch: every workgroup sums C_ab and A_a over
+// kTdRows rows and stores its partial record; the workgroup that finishes
+// last (a device-scope counter after the records, taken behind a release
+// fence and reset by that workgroup) adds the records in a fixed order and
+// forms S_ab(K, tau): out[0 .. kTdStride) (entry (a * kTdMaxOrb + b) * 2 +
+// {re, im}), also added to bins.  At tau = 0 it first stores A_a(0) in a00
+// (and counts one pass in *count).  Grid (ceil(n / kTdRows), chains), 256
+// threads.  phase: [n][2] (re, im) of exp(-i K.R_x); orb: [n] orbital of each
+// site (< norb <= kTdMaxOrb); part: the records, then the counter.
+__global__ __launch_bounds__(256) void k_td_measure(const double* GT0, const double* H, const double* GTT,
                                                     const double* phase, const int* orb, int n, double* part,
-                                                    size_t cs) {
+                                                    double inv_cells, double* a00, double* out, double* bins,
+                                                    double* count, int first, size_t cs) {
+  constexpr int kGroups = 256 / kTdPart;   // threads per record entry in the final sum
   __shared__ double red[4][kTdPart];
+  __shared__ double gsum[kGroups][kTdPart];
+  __shared__ double tot[kTdPart];
+  __shared__ int last_s;
   {
     const size_t co = (size_t)blockIdx.y * cs;
-    GT0 += co; H += co; GTT += co; part += co;
+    GT0 += co; H += co; GTT += co; part += co; a00 += co; out += co; bins += co; count += co;
   }
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int nblk = gridDim.x;
   double acc[kTdPart];
 #pragma unroll
   for (int k = 0; k < kTdPart; ++k) acc[k] = 0.0;
@@ -134,25 +146,36 @@ __global__ __launch_bounds__(256) void k_td_partial(const double* GT0, const dou
     if (lane == 0) red[w][k] = v;
   }
   __syncthreads();
-  if (tid < kTdPart) part[(size_t)blockIdx.x * kTdPart + tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
-}
-
-// Sums the partial records in a fixed order and forms S_ab(K, tau): writes
-// out[0 .. kTdStride) (entry (a * kTdMaxOrb + b) * 2 + {re, im}) and adds it to
-// bins.  At tau = 0 it first stores A_a(0) in a00 (and counts one pass in
-// *count).  One workgroup of 64 threads per chain.
-__global__ __launch_bounds__(64) void k_td_finish(const double* part, int nblk, double inv_cells, double* a00,
-                                                  double* out, double* bins, double* count, int first, size_t cs) {
-  __shared__ double tot[kTdPart];
-  {
-    const size_t co = (size_t)blockIdx.y * cs;
-    part += co; a00 += co; out += co; bins += co; count += co;
+  unsigned int* counter = reinterpret_cast<unsigned int*>(part + (size_t)nblk * kTdPart);
+  if (tid < kTdPart) part[(size_t)blockIdx.x * kTdPart + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) last_s = (atomicAdd(counter, 1u) == (unsigned)nblk - 1u);
+  __syncthreads();
+  if (!last_s) return;
+  __threadfence();
+  // the records in a fixed order: group g adds records g, g + kGroups, ...,
+  // four loads in flight (four partial sums, combined in a fixed order)
+  if (tid < kGroups * kTdPart) {
+    const int k = tid % kTdPart, g = tid / kTdPart;
+    double s4[4] = {0.0, 0.0, 0.0, 0.0};
+    int b = g;
+    for (; b + 3 * kGroups < nblk; b += 4 * kGroups) {
+      double v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] = __builtin_nontemporal_load(part + (size_t)(b + q * kGroups) * kTdPart + k);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) s4[q] += v[q];
+    }
+    for (; b < nblk; b += kGroups) s4[0] += __builtin_nontemporal_load(part + (size_t)b * kTdPart + k);
+    gsum[g][k] = (s4[0] + s4[1]) + (s4[2] + s4[3]);
   }
-  const int tid = threadIdx.x;
+  __syncthreads();
   if (tid < kTdPart) {
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * kTdPart + tid];
-    tot[tid] = s;
+    double sg = 0.0;
+#pragma unroll
+    for (int g = 0; g < kGroups; ++g) sg += gsum[g][tid];
+    tot[tid] = sg;
   }
   __syncthreads();
   const double* A = tot + 2 * kTdMaxOrb * kTdMaxOrb;
@@ -171,4 +194,5 @@ __global__ __launch_bounds__(64) void k_td_finish(const double* part, int nblk, 
     bins[2 * tid] += sr;
     bins[2 * tid + 1] += si;
   }
+  if (tid == 0) *counter = 0u;   // ready for the next tau (kernel boundaries order it)
 }
