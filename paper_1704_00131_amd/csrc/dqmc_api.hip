@@ -62,7 +62,7 @@ struct dqmc_ctx {
   double *norms = nullptr;
   int *piv = nullptr, *moves = nullptr;
   double* XA = nullptr;    // [X | right-hand sides] of the blocked LU solve, n x 3n
-  double* Mgj = nullptr;   // multipliers of one panel, n x 32
+  double* Mgj = nullptr;   // multipliers of two consecutive panels, 2 x (n x 32)
   double* Uinv = nullptr;  // inverses of the diagonal blocks of U, 32 x 32 each, for the back substitution
   double *bins = nullptr, *prec_hist = nullptr, *prec_tot = nullptr, *logdet = nullptr;
   double *grad = nullptr, *gprec = nullptr;   // gradient rows [L][N] and the gradient pass's precision
@@ -182,13 +182,13 @@ size_t layout_chain(dqmc_ctx* c, double* base) {
   for (UDVp* u : us) { P(u->Q, NN); P(u->D, N); P(u->T, NN); }
   P(c->G2, NN);
   P(c->XA, 3 * NN);
-  P(c->Mgj, 32 * N);
+  P(c->Mgj, 64 * N);
   P(c->Uinv, uinv_size(c));
   P(c->field_alt, (size_t)c->L * N);
   P(c->norms, N);
   double* pv = nullptr;
   double* mv = nullptr;
-  P(pv, N); P(mv, (kLuMoves + 1) / 2);
+  P(pv, N); P(mv, kLuMoves + 1);   // the move lists of two consecutive panels
   P(c->bins, 4);
   P(c->prec_hist, 2 * (size_t)c->nk + 2);
   P(c->prec_tot, 4);
@@ -427,26 +427,42 @@ dqmc_status launch_qr_panel(dqmc_ctx* c, double* Ap, int j0, int nbw, double* V,
   return DQMC_OK;
 }
 
+// One step s of the blocked LU solve (k_lu_step): panel s at j0 (width nbw,
+// when has_panel) and the previous panel's step on its columns and, in other
+// workgroups, on the columns from tstart to ncols - 1.  Multipliers and move
+// lists alternate between two buffers by step parity.
+struct LuStep {
+  int j0, nbw, has_panel, j0p, nbp, tstart, ncols, s;
+};
+
 template <int NBW, int MR>
-void lu_panel(dqmc_ctx* c, double* XA, int ld, int j0, int nbw) {
-  const size_t lds = sizeof(double) * (size_t)(c->N - j0) * (NBW + 1);   // the staged panel
-  hipLaunchKernelGGL((k_lu_panel<NBW, MR>), gridc(c, 1), dim3(256), lds, c->stream, XA, c->N, ld, j0, nbw, c->Mgj,
-                     32, c->moves, c->err_flag, c->cs);
+void lu_step_launch(dqmc_ctx* c, double* XA, int ld, const LuStep& q) {
+  const int N = c->N;
+  double* M = c->Mgj + (size_t)(q.s & 1) * 32 * N;
+  int* moves = c->moves + (size_t)(q.s & 1) * kLuMoves;
+  const bool prev = q.s > 0;
+  const double* Mp = prev ? c->Mgj + (size_t)((q.s - 1) & 1) * 32 * N : nullptr;
+  const int* movesp = prev ? c->moves + (size_t)((q.s - 1) & 1) * kLuMoves : nullptr;
+  const int nT = prev ? (q.ncols - q.tstart + 15) / 16 : 0;
+  const size_t lds = q.has_panel ? sizeof(double) * (size_t)(N - q.j0) * (NBW + 1) : 0;   // the staged panel
+  const unsigned gx = (unsigned)((q.has_panel ? 1 : 0) + nT);
+  hipLaunchKernelGGL((k_lu_step<NBW, MR>), gridc(c, gx), dim3(256), lds, c->stream, XA, N, ld, q.j0, q.nbw, M, moves,
+                     q.has_panel, q.j0p, q.nbp, Mp, movesp, q.tstart, q.ncols, c->err_flag, c->cs);
 }
 
-// Panel step of the blocked LU solve: rows per thread = ceil(h / 256).
-dqmc_status launch_lu_panel(dqmc_ctx* c, double* XA, int ld, int j0, int nbw) {
-  const int rows = (c->N - j0 + 255) / 256;
-  if (c->nb == 32 && rows <= 1) lu_panel<32, 1>(c, XA, ld, j0, nbw);
-  else if (c->nb == 32 && rows <= 2) lu_panel<32, 2>(c, XA, ld, j0, nbw);
-  else if (c->nb == 16 && rows <= 1) lu_panel<16, 1>(c, XA, ld, j0, nbw);
-  else if (c->nb == 16 && rows <= 2) lu_panel<16, 2>(c, XA, ld, j0, nbw);
-  else if (c->nb == 16 && rows <= 3) lu_panel<16, 3>(c, XA, ld, j0, nbw);
-  else if (c->nb == 8 && rows <= 1) lu_panel<8, 1>(c, XA, ld, j0, nbw);
-  else if (c->nb == 8 && rows <= 2) lu_panel<8, 2>(c, XA, ld, j0, nbw);
-  else if (c->nb == 8 && rows <= 3) lu_panel<8, 3>(c, XA, ld, j0, nbw);
-  else if (c->nb == 8 && rows <= 4) lu_panel<8, 4>(c, XA, ld, j0, nbw);
-  else return fail(c, DQMC_E_UNSUPPORTED, "no LU panel kernel for this size");
+// rows per thread = ceil(h / 256) of the panel
+dqmc_status launch_lu_step(dqmc_ctx* c, double* XA, int ld, const LuStep& q) {
+  const int rows = q.has_panel ? (c->N - q.j0 + 255) / 256 : 1;
+  if (c->nb == 32 && rows <= 1) lu_step_launch<32, 1>(c, XA, ld, q);
+  else if (c->nb == 32 && rows <= 2) lu_step_launch<32, 2>(c, XA, ld, q);
+  else if (c->nb == 16 && rows <= 1) lu_step_launch<16, 1>(c, XA, ld, q);
+  else if (c->nb == 16 && rows <= 2) lu_step_launch<16, 2>(c, XA, ld, q);
+  else if (c->nb == 16 && rows <= 3) lu_step_launch<16, 3>(c, XA, ld, q);
+  else if (c->nb == 8 && rows <= 1) lu_step_launch<8, 1>(c, XA, ld, q);
+  else if (c->nb == 8 && rows <= 2) lu_step_launch<8, 2>(c, XA, ld, q);
+  else if (c->nb == 8 && rows <= 3) lu_step_launch<8, 3>(c, XA, ld, q);
+  else if (c->nb == 8 && rows <= 4) lu_step_launch<8, 4>(c, XA, ld, q);
+  else return fail(c, DQMC_E_UNSUPPORTED, "no LU step kernel for this size");
   HIPCHK(hipGetLastError());
   return DQMC_OK;
 }
@@ -470,9 +486,9 @@ hipError_t lds_limit_qr() {
 template <int NBW, int MR>
 hipError_t lds_limit_lu() {
   // the staged panel: at most 384 x 33, 768 x 17 or 1024 x 9 doubles (about
-  // 104 KB), beside a few KB of static LDS
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(k_lu_panel<NBW, MR>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, 120 * 1024);
+  // 104 KB), beside about 24 KB of static LDS
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(k_lu_step<NBW, MR>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, 108 * 1024);
 }
 
 dqmc_status set_lds_limits(dqmc_ctx* c) {
@@ -573,18 +589,21 @@ dqmc_status left_step(dqmc_ctx* c, UDVp in, int lo, int hi, UDVp out) {
 // given, adds log|det X|.
 dqmc_status lu_solve(dqmc_ctx* c, double* XA, int nrhs, int ld, double* logdet) {
   const int N = c->N, nb = c->nb, ncols = N + nrhs;
-  for (int j0 = 0; j0 < N; j0 += nb) {
-    const int nbw = std::min(nb, N - j0), rest = ncols - j0 - nbw;
-    if (dqmc_status s = launch_lu_panel(c, XA, ld, j0, nbw)) return s;
-    hipLaunchKernelGGL(k_lu_rowblock, gridc(c, grid1(rest)), dim3(256), 0, c->stream, XA, ld, j0, nbw, ncols,
-                       c->moves, c->cs);
-    HIPCHK(hipGetLastError());
-    const int below = N - j0 - nbw;
-    if (below > 0)
-      if (dqmc_status s = gemm(c, gemm_args(below, rest, nbw, c->Mgj + (size_t)(j0 + nbw) * 32, 32, 0,
-                                            XA + (size_t)j0 * ld + j0 + nbw, ld, 0,
-                                            XA + (size_t)(j0 + nbw) * ld + j0 + nbw, ld, -1.0, 1.0)))
-        return s;
+  // one launch per panel (its factorisation, with the previous panel's step
+  // on all later columns beside it), then one for the last panel's step on
+  // the right-hand sides
+  const int np = (N + nb - 1) / nb;
+  for (int s = 0; s <= np; ++s) {
+    LuStep q;
+    q.s = s;
+    q.has_panel = s < np ? 1 : 0;
+    q.j0 = s * nb;
+    q.nbw = q.has_panel ? std::min(nb, N - q.j0) : 0;
+    q.j0p = (s - 1) * nb;
+    q.nbp = s > 0 ? std::min(nb, N - q.j0p) : 0;
+    q.tstart = q.has_panel ? q.j0 + q.nbw : N;
+    q.ncols = ncols;
+    if (dqmc_status st = launch_lu_step(c, XA, ld, q)) return st;
   }
   // back substitution: the diagonal blocks' inverses, then every 16-column
   // slab of the right-hand sides through the whole block recursion at once
@@ -1660,10 +1679,10 @@ bool layout_ok(const dqmc_ctx* c, const double* lo, const double* hi) {
        in(c->slots, (size_t)(c->nk + 1) * (2 * NN + N), true);
   for (int i = 0; i < 6; ++i) ok = ok && in(c->S[i], NN, true);
   for (const double* p : {c->Vall, c->VTall, c->Zq, c->Rt, c->X, c->RHS, c->Gs, c->T1, c->G2}) ok = ok && in(p, NN, true);
-  ok = ok && in(c->XA, 3 * NN, true) && in(c->Mgj, 32 * N, true) && in(c->Uinv, uinv_size(c), true);
+  ok = ok && in(c->XA, 3 * NN, true) && in(c->Mgj, 64 * N, true) && in(c->Uinv, uinv_size(c), true);
   for (const UDVp* u : {&c->cur, &c->hA, &c->hB}) ok = ok && in(u->Q, NN, true) && in(u->D, N, true) && in(u->T, NN, true);
   ok = ok && in(c->field_alt, (size_t)c->L * N, true) && in(c->norms, N, true) && in(c->piv, N / 2 + 1, true) &&
-       in(c->moves, (kLuMoves + 1) / 2, true) && in(c->bins, 4, true) && in(c->prec_hist, 2 * (size_t)c->nk + 2, true) &&
+       in(c->moves, kLuMoves + 1, true) && in(c->bins, 4, true) && in(c->prec_hist, 2 * (size_t)c->nk + 2, true) &&
        in(c->prec_tot, 4, true) && in(c->logdet, 4, true) && in(c->grad, (size_t)c->L * N, true) && in(c->gprec, 4, true) &&
        in(c->mpart, 4 * (size_t)((N + kMeasRows - 1) / kMeasRows) + 4, true) &&
        in(c->draws, 4 * (size_t)c->L * N, true) &&

@@ -498,17 +498,19 @@ __global__ void k_build_rt(const double* R, const int* piv, int n, double* Rt, d
 // by LU with partial pivoting with the forward substitution carried along as
 // extra columns.  For each panel of nb columns j0..j0+nbw-1 (pivot: the
 // largest |a| among rows j0..n-1, ties to the lowest position):
-//   k_lu_panel     factors the panel into L11 U11 (diagonal block of XA) and
-//                  the multipliers L21 (rows below, into M) and lists the
-//                  composed row interchanges;
-//   k_lu_rowblock  applies the interchanges to the columns right of the panel
-//                  (the rest of X and all of R) and replaces the panel rows
-//                  there by U12 = L11^-1 (P XA)[panel rows, right];
-//   one product    XA[below, right] -= M U12 (the FP64 MFMA GEMM).
-// Then R holds L^-1 P R, and the back substitution runs block by block from
-// the last: k_lu_diag solves U_jj Y_j = R_j, and a product removes Y_j from
-// the rows above.  sum log|U_ii| is log|det X|.  Columns left of a panel are
-// never read again and are not updated.
+//   the panel factorisation (lu_panel_factor) gives L11 U11 (diagonal block
+//                  of XA), the multipliers L21 (rows below, into M) and the
+//                  list of the composed row interchanges;
+//   the panel's step on every later column (lu_prev_slab) applies the
+//                  interchanges, replaces the panel rows by
+//                  U12 = L11^-1 (P XA)[panel rows] and takes L21 U12 from the
+//                  rows below.
+// k_lu_step runs a panel's factorisation together with the previous panel's
+// step (on the panel's own columns first, in the same workgroup, and on the
+// other later columns in the launch's other workgroups), so each panel costs
+// one launch.  Then R holds L^-1 P R, and the back substitution (below) runs
+// block by block from the last.  sum log|U_ii| is log|det X|.  Columns left
+// of a panel are never read again and are not updated.
 constexpr int kLuMoves = 1 + 2 * 64;   // ints of the move list (count + pairs)
 
 // z <- U^-1 z for a 32 x 32 upper triangular U given by columns in LDS
@@ -556,7 +558,7 @@ __device__ __forceinline__ void tri_solve_back(double (&z)[32], const double (*t
 //     that wave's row as the pivot row, swaps the positions, and eliminates
 //     the rows that end below the pivot.
 // The move list (moves[0] = count K <= 2 nbw, then K pairs (destination,
-// source), absolute rows, in any order) is written for k_lu_rowblock.
+// source), absolute rows, in any order) is written for the next step.
 template <int NBW, int MR>
 struct LuShared {
   double key[2][4];
@@ -631,36 +633,14 @@ __device__ __forceinline__ void lu_columns(std::integer_sequence<int, C...>, dou
   (lu_column<NBW, MR, C>(a, pos, h, ncol, sh, err), ...);
 }
 
+// The factorisation of a staged panel (rows j0 .. n-1 of its columns in
+// stage, row stride NBW + 1), as described above; every thread calls it.
 template <int NBW, int MR>
-__global__ __launch_bounds__(256) void k_lu_panel(double* XA, int n, int ld, int j0, int nbw, double* M, int ldm,
-                                                  int* moves, int* err, size_t cs) {
-  __shared__ LuShared<NBW, MR> sh;
-  __shared__ int cnt_s;
-  extern __shared__ double stage[];   // h rows of NBW + 1: the panel in, then the factors out
-  {
-    const size_t co = (size_t)blockIdx.y * cs;
-    XA += co; M += co;
-    moves = reinterpret_cast<int*>(reinterpret_cast<double*>(moves) + co);
-    err = reinterpret_cast<int*>(reinterpret_cast<double*>(err) + co);
-  }
+__device__ __forceinline__ void lu_panel_factor(double* XA, int n, int ld, int j0, int nbw, double* M, int ldm,
+                                                int* moves, int* err, LuShared<NBW, MR>& sh, int& cnt_s,
+                                                double* stage) {
   const int h = n - j0, tid = threadIdx.x;
-  constexpr int PS = NBW + 1, NL = MR * NBW;   // stage row stride; loads per thread
-  // the panel through LDS: coalesced loads (consecutive threads along a row),
-  // all issued before the stores, zeros outside the panel
-  {
-    double t[NL];
-#pragma unroll
-    for (int u = 0; u < NL; ++u) {
-      const int e = 256 * u + tid, r = e / NBW, q = e % NBW;
-      t[u] = XA[(size_t)(j0 + min(r, h - 1)) * ld + j0 + min(q, nbw - 1)];
-    }
-#pragma unroll
-    for (int u = 0; u < NL; ++u) {
-      const int e = 256 * u + tid, r = e / NBW, q = e % NBW;
-      if (r < h) stage[r * PS + q] = (q < nbw) ? t[u] : 0.0;
-    }
-  }
-  __syncthreads();
+  constexpr int PS = NBW + 1, NL = MR * NBW;
   double a[MR][NBW];
   int pos[MR];
 #pragma unroll
@@ -703,100 +683,172 @@ __global__ __launch_bounds__(256) void k_lu_panel(double* XA, int n, int ld, int
   if (tid == 0) moves[0] = cnt_s;
 }
 
-// Interchanges and U12 for the columns j0+nbw .. ncols-1 of XA, one thread per
-// column: the sources of the panel rows are loaded together, the rows moved
-// out of the panel are copied, and the panel rows are solved with L11 (unit
-// lower, kept in LDS by columns) right-looking and stored.
-__global__ __launch_bounds__(256) void k_lu_rowblock(double* XA, int ld, int j0, int nbw, int ncols,
-                                                     const int* moves, size_t cs) {
-  __shared__ __attribute__((aligned(16))) double lr[32][34];   // lr[k][r] = L11[31 - r][31 - k]
-  __shared__ int srcrow[32], od[32], os[32], nout_s;
-  {
-    const size_t co = (size_t)blockIdx.y * cs;
-    XA += co;
-    moves = reinterpret_cast<const int*>(reinterpret_cast<const double*>(moves) + co);
-  }
-  const int tid = threadIdx.x;
+
+// ---- one launch per LU step ----
+// The previous panel's work on a 16-column slab of columns c0 .. c0+15 (only
+// those < ncols): its row interchanges, U12 = L11^-1 (P XA)[its rows, slab]
+// written to its rows, and the rows below it (from jb = j0p + nbp on) minus
+// L21 U12, with the multipliers L21 at Mp (absolute rows, ld 32) and the
+// interchanges as lu_panel_factor lists them (movesp).  The updated rows below go
+// back to XA, or, for the panel of this launch, to its LDS stage (row r at
+// stage + (r - jb) PS, column c - c0 + scol; zero past ncols).  Every thread
+// of the workgroup calls it.
+struct LuPrevShared {
+  __attribute__((aligned(16))) double lr[32][34];   // lr[k][r] = L11[31 - r][31 - k]
+  double u12[32][17];                                // U12 of the slab
+  double mv[32][17];                                 // new values of the rows moved out of the panel
+  int srcrow[32], od[32], os[32], nout;
+};
+
+template <bool TO_STAGE>
+__device__ __forceinline__ void lu_prev_slab(double* XA, int n, int ld, int j0p, int nbp, int c0, int ncols,
+                                             const double* Mp, const int* movesp, LuPrevShared& sh, short* odmap,
+                                             double* stage, int PS, int scol, int scols) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int m16 = lane & 15, kk = lane >> 4;
+  const int jb = j0p + nbp, hb = n - jb;   // rows below the previous panel
   for (int e = tid; e < 32 * 32; e += 256) {
     const int r = e >> 5, k = e & 31;
-    lr[31 - k][31 - r] = (k < r && r < nbw) ? XA[(size_t)(j0 + r) * ld + j0 + k] : (r == k ? 1.0 : 0.0);
+    sh.lr[31 - k][31 - r] = (k < r && r < nbp) ? XA[(size_t)(j0p + r) * ld + j0p + k] : (r == k ? 1.0 : 0.0);
   }
+  for (int e = tid; e < hb; e += 256) odmap[e] = -1;
   if (tid < 64) {
-    const int K = min(moves[0], 64);
+    const int K = min(movesp[0], 64);
     int dest = -1, src = -1;
-    if (tid < K) { dest = moves[1 + 2 * tid]; src = moves[2 + 2 * tid]; }
-    if (tid < 32) srcrow[tid] = j0 + min(tid, nbw - 1);   // rows past nbw: any valid row
+    if (tid < K) { dest = movesp[1 + 2 * tid]; src = movesp[2 + 2 * tid]; }
+    if (tid < 32) sh.srcrow[tid] = j0p + min(tid, nbp - 1);   // rows past nbp: any valid row
     __builtin_amdgcn_wave_barrier();   // the defaults land before the moves overwrite them
-    const bool inpanel = tid < K && dest < j0 + nbw;
-    if (inpanel) srcrow[dest - j0] = src;
+    const bool inpanel = tid < K && dest < jb;
+    if (inpanel) sh.srcrow[dest - j0p] = src;
     const bool outside = tid < K && !inpanel;
     const unsigned long long m = __ballot(outside);
     const int at = __popcll(m & ((1ull << tid) - 1ull));
-    if (outside && at < 32) { od[at] = dest; os[at] = src; }
-    if (tid == 0) nout_s = min(__popcll(m), 32);
+    if (outside && at < 32) { sh.od[at] = dest; sh.os[at] = src; }
+    if (tid == 0) sh.nout = min(__popcll(m), 32);
   }
   __syncthreads();
-  const int col = j0 + nbw + blockIdx.x * 256 + tid;
-  if (col >= ncols) return;
-  const int nout = nout_s;
-  double x[32];   // the panel rows in reversed order: x[31 - k] is row j0 + k
+  if (tid < sh.nout) odmap[sh.od[tid] - jb] = (short)tid;
+  if (tid < 16) {
+    // the slab's panel rows (reversed: x[31 - k] is row j0p + k), solved with L11
+    const int col = c0 + tid, colc = min(col, ncols - 1);
+    double x[32];
 #pragma unroll
-  for (int k = 0; k < 32; ++k) x[31 - k] = XA[(size_t)srcrow[k] * ld + col];
+    for (int k = 0; k < 32; ++k) x[31 - k] = XA[(size_t)sh.srcrow[k] * ld + colc];
 #pragma unroll
-  for (int k = 0; k < 32; ++k) x[31 - k] = (k < nbw) ? x[31 - k] : 0.0;
-  // rows moved out of the panel, eight at a time: with pivot rows at or below
-  // their step, a row leaving the panel carries an original panel row, and
-  // panel rows are stored only at the end, so no source is overwritten first
-  for (int k0 = 0; k0 < nout; k0 += 8) {
-    double ov[8];
+    for (int k = 0; k < 32; ++k) x[31 - k] = (k < nbp) ? x[31 - k] : 0.0;
+    for (int i = 0; i < sh.nout; ++i) sh.mv[i][tid] = XA[(size_t)sh.os[i] * ld + colc];
+    tri_solve_back<true>(x, sh.lr, nullptr);
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
-      if (k0 + k < nout) ov[k] = XA[(size_t)os[k0 + k] * ld + col];
-#pragma unroll
-    for (int k = 0; k < 8; ++k)
-      if (k0 + k < nout) XA[(size_t)od[k0 + k] * ld + col] = ov[k];
+    for (int k = 0; k < 32; ++k) sh.u12[31 - k][tid] = x[k];
   }
-  tri_solve_back<true>(x, lr, nullptr);
+  __syncthreads();
+  // rows below: A22 - L21 U12, 16-row tiles over the waves, K = nbp
+  const int col = c0 + m16, colc = min(col, ncols - 1);
+  const bool cin = col < ncols;
+  double ub[8];
 #pragma unroll
-  for (int k = 0; k < 32; ++k)   // (this store order keeps the register count under the limit)
-    if (31 - k < nbw) XA[(size_t)(j0 + 31 - k) * ld + col] = x[k];
+  for (int q = 0; q < 8; ++q) ub[q] = (4 * q + kk < nbp) ? sh.u12[4 * q + kk][m16] : 0.0;
+  const int nrt = (hb + 15) / 16;
+  for (int t = w; t < nrt; t += 4) {
+    const int r0 = jb + 16 * t;
+    v4d acc;
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const int row = r0 + kk + 4 * rr, rowc = min(row, n - 1);
+      const int mi = odmap[rowc - jb];
+      const double g = XA[(size_t)rowc * ld + colc];
+      acc[rr] = (mi >= 0) ? sh.mv[mi][m16] : g;
+    }
+    const double* Mrow = Mp + (size_t)min(r0 + m16, n - 1) * 32;
+    double av[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) av[q] = Mrow[4 * q + kk];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (4 * q >= nbp) break;   // uniform
+      acc = mfma_f64_16x16x4((4 * q + kk < nbp) ? -av[q] : 0.0, ub[q], acc);
+    }
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const int row = r0 + kk + 4 * rr;
+      if (row >= n) continue;
+      if (TO_STAGE) {
+        if (scol + m16 < scols) stage[(row - jb) * PS + scol + m16] = cin ? acc[rr] : 0.0;
+      }
+      else if (cin) XA[(size_t)row * ld + col] = acc[rr];
+    }
+  }
+  // U12 over the previous panel's rows
+  for (int e = tid; e < 32 * 16; e += 256) {
+    const int k = e >> 4, q = e & 15;
+    if (k < nbp && c0 + q < ncols) XA[(size_t)(j0p + k) * ld + c0 + q] = sh.u12[k][q];
+  }
+  __syncthreads();
 }
 
-// U_jj Y_j = R_j for the diagonal block starting at row r0: grid (columns /
-// 256, chains); the right-hand sides start at column n of XA.  Right-looking
-// with the reciprocal diagonal; the block is kept in LDS by columns.
-__global__ __launch_bounds__(256) void k_lu_diag(double* XA, int n, int ld, int r0, int nb, int nrhs, size_t cs) {
-  __shared__ __attribute__((aligned(16))) double tt[32][34];   // tt[k][r] = U[r][k]
-  __shared__ double dinv[32];
-  XA += (size_t)blockIdx.y * cs;
-  const int nrow = min(nb, n - r0);
-  const double* U = XA + (size_t)r0 * ld + r0;
-  double* B = XA + (size_t)r0 * ld + n;
-  for (int e = threadIdx.x; e < 32 * 32; e += 256) {
-    const int r = e >> 5, k = e & 31;
-    tt[k][r] = (r < nrow && k < nrow && k >= r) ? U[(size_t)r * ld + k] : (r == k ? 1.0 : 0.0);
+// One step of the blocked LU solve in one launch.  With has_panel, workgroup
+// 0 factorises the panel j0 .. j0 + nbw - 1 (lu_panel_factor); when
+// a previous panel exists (j0p, width nbp, its multipliers Mp and moves
+// movesp), that workgroup first applies the previous panel's step to its own
+// columns (lu_prev_slab into the stage), and the launch's other workgroups
+// apply it to the columns from tstart to ncols - 1, 16 per workgroup.  The
+// panel writes its multipliers to M and its moves to moves (the other buffer
+// of the pair the next launch reads).  Without has_panel (after the last
+// panel) every workgroup is a trailing one.
+template <int NBW, int MR>
+__global__ __launch_bounds__(256) void k_lu_step(double* XA, int n, int ld, int j0, int nbw, double* M, int* moves,
+                                                 int has_panel, int j0p, int nbp, const double* Mp,
+                                                 const int* movesp, int tstart, int ncols, int* err, size_t cs) {
+  __shared__ LuShared<NBW, MR> sh;
+  __shared__ LuPrevShared ps;
+  __shared__ short odmap[1024];
+  __shared__ int cnt_s;
+  extern __shared__ double stage[];   // h rows of NBW + 1: the panel in, then the factors out
+  {
+    const size_t co = (size_t)blockIdx.y * cs;
+    XA += co; M += co;
+    moves = reinterpret_cast<int*>(reinterpret_cast<double*>(moves) + co);
+    err = reinterpret_cast<int*>(reinterpret_cast<double*>(err) + co);
+    if (Mp) {
+      Mp += co;
+      movesp = reinterpret_cast<const int*>(reinterpret_cast<const double*>(movesp) + co);
+    }
   }
-  __syncthreads();
-  if (threadIdx.x < 32) dinv[threadIdx.x] = 1.0 / tt[threadIdx.x][threadIdx.x];
-  __syncthreads();
-  const int col = blockIdx.x * 256 + threadIdx.x;
-  if (col >= nrhs) return;
-  double z[32];
+  const int tslab = (int)blockIdx.x - (has_panel ? 1 : 0);
+  if (tslab >= 0) {   // trailing columns: the previous panel's step
+    lu_prev_slab<false>(XA, n, ld, j0p, nbp, tstart + 16 * tslab, ncols, Mp, movesp, ps, odmap, nullptr, 0, 0, 0);
+    return;
+  }
+  const int h = n - j0, tid = threadIdx.x;
+  constexpr int PS = NBW + 1, NL = MR * NBW;   // stage row stride; loads per thread
+  if (Mp) {
+    // the previous panel's step on this panel's columns, straight into the stage
+    for (int c0 = 0; c0 < NBW; c0 += 16)
+      lu_prev_slab<true>(XA, n, ld, j0p, nbp, j0 + c0, j0 + nbw, Mp, movesp, ps, odmap, stage, PS, c0, NBW);
+  } else {
+    // the panel through LDS: coalesced loads (consecutive threads along a row),
+    // all issued before the stores, zeros outside the panel
+    double t[NL];
 #pragma unroll
-  for (int r = 0; r < 32; ++r) z[r] = B[(size_t)min(r, nrow - 1) * ld + col];
+    for (int u = 0; u < NL; ++u) {
+      const int e = 256 * u + tid, r = e / NBW, q = e % NBW;
+      t[u] = XA[(size_t)(j0 + min(r, h - 1)) * ld + j0 + min(q, nbw - 1)];
+    }
 #pragma unroll
-  for (int r = 0; r < 32; ++r) z[r] = (r < nrow) ? z[r] : 0.0;
-  tri_solve_back<false>(z, tt, dinv);
-#pragma unroll
-  for (int r = 0; r < 32; ++r)
-    if (r < nrow) B[(size_t)r * ld + col] = z[r];
+    for (int u = 0; u < NL; ++u) {
+      const int e = 256 * u + tid, r = e / NBW, q = e % NBW;
+      if (r < h) stage[r * PS + q] = (q < nbw) ? t[u] : 0.0;
+    }
+    __syncthreads();
+  }
+  lu_panel_factor<NBW, MR>(XA, n, ld, j0, nbw, M, 32, moves, err, sh, cnt_s, stage);
 }
 
 // Back substitution of all right-hand sides in two launches, instead of one
 // diagonal solve and one product per block row:
 //   k_lu_diag_inv  inverts every diagonal block U_bb of U (grid (blocks,
 //                  chains), one workgroup each, the 32 columns of the inverse
-//                  by the backward solve of k_lu_diag on unit vectors); block
+//                  by the backward triangular solve on unit vectors); block
 //                  b is stored as a 32 x 32 row-major matrix at Uinv + 1024 b,
 //                  the identity beyond a ragged last block;
 //   k_lu_back      gives every workgroup 16 right-hand-side columns and runs
