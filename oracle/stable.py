@@ -90,16 +90,20 @@ def _split(D):
 
 def merge(right: Optional[UDV], left: Optional[UDV], n: int):
     """G(tau) and log|det(1 + B'(tau,0) B'(beta,tau))| from a right and a left
-    UDV form (None = identity)."""
+    UDV form (None = identity).  The Q factors are orthogonal (real) or
+    unitary (complex), so Q_R^-1 = Q_R^H and (Q_L^T)^-1 = conj(Q_L); for real
+    factors the conjugations change nothing."""
     right = right or identity_udv(n)
     left = left or identity_udv(n)
     DRb, DRs = _split(right.D)
     DLb, DLs = _split(left.D)
-    X = (right.Q.T @ left.Q) / DRb[:, None] / DLb[None, :] \
+    QRh = right.Q.conj().T
+    QLc = left.Q.conj()
+    X = (QRh @ QLc) / DRb[:, None] / DLb[None, :] \
         + (DRs[:, None] * (right.T @ left.T.T)) * DLs[None, :]
-    rhs = right.Q.T / DRb[:, None]
+    rhs = QRh / DRb[:, None]
     Y = np.linalg.solve(X, rhs)
-    G = (left.Q / DLb[None, :]) @ Y
+    G = (QLc / DLb[None, :]) @ Y
     sign, logabs = np.linalg.slogdet(X)
     logdet = float(np.sum(np.log(DRb)) + np.sum(np.log(DLb)) + logabs)
     return G, logdet
