@@ -44,7 +44,12 @@ typedef enum {
   DQMC_E_STATE = 6         /* call out of order (not bound / not initialised / poisoned)     */
 } dqmc_status;
 
-typedef enum { DQMC_FIELD_ISING = 0, DQMC_FIELD_GAUSS = 1, DQMC_FIELD_ISING4 = 2 } dqmc_field_kind;
+typedef enum {
+  DQMC_FIELD_ISING = 0,
+  DQMC_FIELD_GAUSS = 1,
+  DQMC_FIELD_ISING4 = 2,
+  DQMC_FIELD_ISING4_IMAG = 3
+} dqmc_field_kind;
 typedef enum { DQMC_TROTTER_ASYM = 0, DQMC_TROTTER_SYM = 1 } dqmc_trotter;
 
 /*
@@ -62,6 +67,20 @@ typedef enum { DQMC_TROTTER_ASYM = 0, DQMC_TROTTER_SYM = 1 } dqmc_trotter;
  * identity (Eq. (HS_squares)), and the weight gains prod gamma(l); a flip
  * proposes one of the three other values with probability 1/3 each;
  * DQMC_FIELD_GAUSS stores a real phi (continuous field, Gaussian weight).
+ *
+ * DQMC_FIELD_ISING4_IMAG is the complex formulation of the section "The
+ * SU(2)-Hubbard model on a square lattice": the four-valued field at
+ * lambda = -U/2 with the imaginary coupling i c (coupling holds c =
+ * sqrt(dtau U / 2)), in the original frame, exp(V_tau) = diag(exp(i c eta)),
+ * alpha = -1/2, n_col = 2, G complex.  The weight is complex; the chain
+ * samples its modulus (a flip is accepted iff u < |R|) and carries the phase
+ * W / |W| of Eq. (phase) (dqmc_read_phase).  Every complex n x n matrix is
+ * held as its real 2n x 2n image [[Re X, -Im X], [Im X, Re X]]: G is that
+ * image (4 n^2 doubles), the field stays n_slices*n doubles.  n <= 64, single
+ * chains; the sweep with measure bit 0 and dqmc_green_scratch are built, every
+ * other entry point returns DQMC_E_UNSUPPORTED.  The equal-time estimators
+ * are the real parts of D = (1/n) sum_i (1 - G~_ii)^2,
+ * E_kin = (n_col / n)(Tr T - Tr(T G)) and E_pot = U D.
  */
 typedef struct {
   int32_t n;               /* N_dim, number of orbitals, 1 <= n <= 1024                       */
@@ -91,7 +110,8 @@ typedef struct {
 
 typedef struct dqmc_ctx dqmc_ctx;
 
-/* Byte sizes of the device buffers for a model.  G: n*n doubles; field:
+/* Byte sizes of the device buffers for a model.  G: n*n doubles (the 2n x 2n
+ * image, 4 n^2 doubles, for DQMC_FIELD_ISING4_IMAG); field:
  * n_slices*n doubles; slots: the UDV storage of Algorithm 1,
  * (n_slices/n_wrap + 1) * (2 n^2 + n) doubles; work: scratch.  DQMC_E_ARG on
  * an inconsistent model. */
@@ -140,6 +160,13 @@ dqmc_status dqmc_sweep(dqmc_ctx* ctx, int32_t n_sweeps, int32_t measure, dqmc_st
 /* Bin sums: sums_host[0..3] = sum of D, sum of E_kin, sum of E_pot (per site)
  * and the number of measurements.  dqmc_reset_bins zeroes them. */
 dqmc_status dqmc_read_bins(dqmc_ctx* ctx, double* sums_host);
+/* The configuration's phase W / |W| (Eq. (phase)) carried along by the
+ * sweeps of a complex field: out3_host[0..1] = its real and imaginary parts,
+ * out3_host[2] = the largest |phase - 1| since dqmc_init (the "precision" of
+ * the phase: the weight of a half-filled bipartite lattice is real and
+ * positive, so the phase stays 1 up to rounding).  Reset to 1 by dqmc_init.
+ * DQMC_E_UNSUPPORTED for a real field. */
+dqmc_status dqmc_read_phase(dqmc_ctx* ctx, double* out3_host);
 dqmc_status dqmc_reset_bins(dqmc_ctx* ctx);
 
 /* Test hook: G(tau) = (1 + B(tau,0) B(beta,tau))^-1 recomputed from scratch
@@ -377,7 +404,8 @@ void dqmc_batch_destroy(dqmc_batch* b);
 /* Coupling of the exact two-valued Hubbard-Stratonovich identity,
  * cosh(lambda) = exp(dtau U / 2) (DQMC_FIELD_ISING), of the Gaussian
  * identity, c = sqrt(dtau U) (DQMC_FIELD_GAUSS), or of the four-valued
- * identity of Eq. (HS_squares), sqrt(dtau U / 2) (DQMC_FIELD_ISING4). */
+ * identity of Eq. (HS_squares), sqrt(dtau U / 2) (DQMC_FIELD_ISING4, and c of the
+ * imaginary coupling i c for DQMC_FIELD_ISING4_IMAG). */
 dqmc_status dqmc_hubbard_coupling(double U, double dtau, dqmc_field_kind kind, double* coupling);
 
 /* Hopping matrix of the density frame for the M_z form of the Hubbard model

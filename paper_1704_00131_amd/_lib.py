@@ -8,8 +8,9 @@ LIB_PATH = os.path.join(HERE, "libdqmc_gfx950.so")
 DQMC_OK = 0
 STATUS_NAMES = {0: "DQMC_OK", 1: "DQMC_E_ARG", 2: "DQMC_E_UNSUPPORTED", 3: "DQMC_E_DEVICE",
                 4: "DQMC_E_NUMERIC", 5: "DQMC_E_NOMEM", 6: "DQMC_E_STATE"}
-FIELD_ISING, FIELD_GAUSS, FIELD_ISING4 = 0, 1, 2
-FIELD_KINDS = {"ising": FIELD_ISING, "gauss": FIELD_GAUSS, "ising4": FIELD_ISING4}
+FIELD_ISING, FIELD_GAUSS, FIELD_ISING4, FIELD_ISING4_IMAG = 0, 1, 2, 3
+FIELD_KINDS = {"ising": FIELD_ISING, "gauss": FIELD_GAUSS, "ising4": FIELD_ISING4,
+               "ising4_imag": FIELD_ISING4_IMAG}
 TROTTER_ASYM, TROTTER_SYM = 0, 1
 KERNEL_BLOCK_UPDATE, KERNEL_GEMM, KERNEL_STABILISE = 0, 1, 2
 
@@ -52,6 +53,7 @@ SIGNATURES = {
     "dqmc_init": (ctypes.c_int, [ctypes.c_void_p]),
     "dqmc_sweep": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Stats)]),
     "dqmc_read_bins": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "dqmc_read_phase": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "dqmc_reset_bins": (ctypes.c_int, [ctypes.c_void_p]),
     "dqmc_green_scratch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "dqmc_green_scratch_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,

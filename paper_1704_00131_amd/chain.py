@@ -52,6 +52,9 @@ class Chain:
         self.lib = lib
         self.model = model
         self.N = model.n
+        # a complex field's matrices are held as their real 2n x 2n images
+        self.complex = model.field == _lib.FIELD_ISING4_IMAG
+        self.Nd = 2 * self.N if self.complex else self.N
         self.L = model.n_slices
         self.eq_shape = (0, 0)    # (n_cells, norb) once eq_setup has run; the library refuses reads before
         self.td_norb = 0          # orbitals per cell once td_setup has run; likewise
@@ -63,7 +66,7 @@ class Chain:
         check(lib.dqmc_create(ctypes.byref(model), Kc.ctypes.data, None, ctypes.byref(ctx)))
         self.ctx = ctx
         self.device = torch.device(device)
-        self.G = _dev_buffer(sizes.G, self.device).view(-1)[: self.N * self.N].view(self.N, self.N)
+        self.G = _dev_buffer(sizes.G, self.device).view(-1)[: self.Nd * self.Nd].view(self.Nd, self.Nd)
         self.field = _dev_buffer(sizes.field, self.device)
         self.slots = _dev_buffer(sizes.slots, self.device)
         self.work = _dev_buffer(sizes.work, self.device)
@@ -109,8 +112,22 @@ class Chain:
     def reset_bins(self):
         self._chk(self.lib.dqmc_reset_bins(self.ctx))
 
+    def read_phase(self):
+        """(phase of the configuration as a complex number, largest |phase - 1|
+        so far) of a complex field."""
+        out = np.zeros(3)
+        self._chk(self.lib.dqmc_read_phase(self.ctx, out.ctypes.data))
+        return complex(out[0], out[1]), float(out[2])
+
+    def green_complex(self, image=None) -> torch.Tensor:
+        """The complex n x n matrix whose real 2n x 2n image is `image` (default:
+        the chain's G): Re from the upper-left block, Im from the lower-left."""
+        X = self.G if image is None else image
+        n = self.N
+        return torch.complex(X[:n, :n], X[n:, :n])
+
     def green_scratch(self, tau: int) -> torch.Tensor:
-        out = torch.empty(self.N, self.N, dtype=torch.float64, device=self.device)
+        out = torch.empty(self.Nd, self.Nd, dtype=torch.float64, device=self.device)
         self._chk(self.lib.dqmc_green_scratch(self.ctx, tau, ctypes.c_void_p(out.data_ptr())))
         return out
 

@@ -21,6 +21,7 @@
 #include "adjoint.h"
 #include "timedisplaced.h"
 #include "correlations.h"
+#include "complex.h"
 
 namespace {
 
@@ -42,6 +43,11 @@ struct Layout {
 struct dqmc_ctx {
   dqmc_model m{};
   int N = 0, L = 0, nw = 0, nk = 0, nb = 32;
+  // field sites per slice; the complex field (cplx) runs on the real 2 Nf x 2 Nf
+  // images of its complex matrices, so there N = 2 Nf
+  int Nf = 0, cplx = 0;
+  double trK_field = 0.0;     // trace of the n x n hopping matrix (complex estimators)
+  double* phase = nullptr;    // complex field: [re, im, max |phase - 1|] per chain
   std::vector<double> K;
   double trK = 0.0, normK1 = 0.0;
   hipStream_t stream = nullptr;
@@ -193,6 +199,7 @@ size_t layout_chain(dqmc_ctx* c, double* base) {
   P(c->prec_hist, 2 * (size_t)c->nk + 2);
   P(c->prec_tot, 4);
   P(c->logdet, 4);
+  P(c->phase, 4);
   P(c->grad, (size_t)c->L * N);
   P(c->gprec, 4);
   P(c->mpart, 4 * (size_t)((N + kMeasRows - 1) / kMeasRows) + 4);   // partials, then the counter
@@ -334,7 +341,7 @@ dqmc_status expm(dqmc_ctx* c, double x, double* out) {
 // (so no launch reads and writes the same sites).
 inline double* field_row(dqmc_ctx* c, int tau) {
   double* base = (!c->row_alt.empty() && c->row_alt[tau - 1]) ? c->field_alt : c->field;
-  return base + (size_t)(tau - 1) * c->N;
+  return base + (size_t)(tau - 1) * c->Nf;
 }
 
 // G(tau) = B_tau G(tau-1) B_tau^-1 = diag(v) E G Einv diag(1/v), v = exp(coupling s_tau),
@@ -505,6 +512,9 @@ dqmc_status set_lds_limits(dqmc_ctx* c) {
   HIPCHK((lds_limit_qr<16, 4, 8, 12>()));
   HIPCHK((lds_limit_qr<8, 4, 8, 16>()));
   HIPCHK(gemm64_set_lds());
+  if (c->cplx)
+    HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(k_cupdate_slice),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)cupdate_lds(kCMaxN)));
   return DQMC_OK;
 }
 
@@ -549,6 +559,16 @@ dqmc_status qr_udv(dqmc_ctx* c, double* M, const double* T_in, UDVp out) {
 }
 
 // Right step: UDV of B(hi,0) from that of B(lo,0): M = (B_hi ... B_lo+1 Q) D.
+// Rotations of a complex field's images (k_crot): rows by diag(exp(i c_row eta)),
+// columns by diag(exp(-i c_col eta)); a zero coefficient skips that side.
+dqmc_status crot(dqmc_ctx* c, double* dst, const double* src, int tau, double coef_row, double coef_col) {
+  const int n = c->Nf;
+  hipLaunchKernelGGL(k_crot, gridc(c, grid1((size_t)n * n)), dim3(256), 0, c->stream, dst, src, n, c->N,
+                     field_row(c, tau), coef_row, coef_col, coef_row != 0.0 ? 1 : 0, coef_col != 0.0 ? 1 : 0, c->cs);
+  HIPCHK(hipGetLastError());
+  return DQMC_OK;
+}
+
 dqmc_status right_step(dqmc_ctx* c, UDVp in, int lo, int hi, UDVp out) {
   const int N = c->N;
   const double* src = in.Q;
@@ -556,9 +576,12 @@ dqmc_status right_step(dqmc_ctx* c, UDVp in, int lo, int hi, UDVp out) {
   int b = 0;
   for (int tau = lo + 1; tau <= hi; ++tau) {
     GemmArgs g = gemm_args(N, N, N, c->E, N, 0, src, N, 0, bufs[b], N);
-    g.rs = field_row(c, tau); g.rs_mode = SC_EXP; g.rs_coef = c->m.coupling;
+    if (!c->cplx) { g.rs = field_row(c, tau); g.rs_mode = SC_EXP; g.rs_coef = c->m.coupling; }
     if (tau == hi) { g.cs = in.D; g.cs_mode = SC_VAL; }
     if (dqmc_status s = gemm(c, g)) return s;
+    // complex field: B_tau = diag(exp(i c eta)) E on the image, a row rotation
+    if (c->cplx)
+      if (dqmc_status s = crot(c, bufs[b], bufs[b], tau, c->m.coupling, 0.0)) return s;
     src = bufs[b];
     b ^= 1;
   }
@@ -573,8 +596,14 @@ dqmc_status left_step(dqmc_ctx* c, UDVp in, int lo, int hi, UDVp out) {
   double* bufs[2] = {c->S[2], c->S[3]};
   int b = 0;
   for (int tau = hi; tau > lo; --tau) {
+    // complex field: the image of B_tau transposed is E times the rotation by
+    // diag(exp(-i c eta)) of the rows, applied first (into S[5])
+    if (c->cplx) {
+      if (dqmc_status s = crot(c, c->S[5], src, tau, -c->m.coupling, 0.0)) return s;
+      src = c->S[5];
+    }
     GemmArgs g = gemm_args(N, N, N, c->E, N, 0, src, N, 0, bufs[b], N);
-    g.ks = field_row(c, tau); g.ks_mode = SC_EXP; g.ks_coef = c->m.coupling;
+    if (!c->cplx) { g.ks = field_row(c, tau); g.ks_mode = SC_EXP; g.ks_coef = c->m.coupling; }
     if (tau == lo + 1) { g.cs = in.D; g.cs_mode = SC_VAL; }
     if (dqmc_status s = gemm(c, g)) return s;
     src = bufs[b];
@@ -724,7 +753,7 @@ Field4 field4_table() {
 bool field_value_ok(dqmc_field_kind kind, double v) {
   if (!std::isfinite(v)) return false;
   if (kind == DQMC_FIELD_ISING) return v == 1.0 || v == -1.0;
-  if (kind == DQMC_FIELD_ISING4) {
+  if (kind == DQMC_FIELD_ISING4 || kind == DQMC_FIELD_ISING4_IMAG) {
     const Field4 t = field4_table();
     return v == t.eta[0] || v == t.eta[1] || v == t.eta[2] || v == t.eta[3];
   }
@@ -810,6 +839,94 @@ dqmc_status sweep_once(dqmc_ctx* c, int meas) {
   return DQMC_OK;
 }
 
+// ------------------------------------------------- complex-field sweep --
+// The sweep of Algorithm 1 for the imaginary-coupling four-valued field, on
+// the real 2n x 2n images: wraps as two products and the rotations, the flips
+// with the complex G in LDS (k_cupdate_slice), the stabilisation of the real
+// sweep at dimension 2n, the original-frame estimators (k_cmeasure).
+dqmc_status cwrap_up(dqmc_ctx* c, int tau) {
+  const int N = c->N;
+  if (dqmc_status s = gemm(c, gemm_args(N, N, N, c->E, N, 0, c->G, N, 0, c->T1, N))) return s;
+  if (dqmc_status s = gemm(c, gemm_args(N, N, N, c->T1, N, 0, c->Einv, N, 0, c->Gs, N))) return s;
+  return crot(c, c->G, c->Gs, tau, c->m.coupling, c->m.coupling);
+}
+
+dqmc_status cwrap_down(dqmc_ctx* c, int tau) {
+  const int N = c->N;
+  if (dqmc_status s = crot(c, c->T1, c->G, tau, -c->m.coupling, -c->m.coupling)) return s;
+  if (dqmc_status s = gemm(c, gemm_args(N, N, N, c->T1, N, 0, c->E, N, 0, c->Gs, N))) return s;
+  return gemm(c, gemm_args(N, N, N, c->Einv, N, 0, c->Gs, N, 0, c->G, N));
+}
+
+dqmc_status cupdate(dqmc_ctx* c, int tau, int dir) {
+  hipLaunchKernelGGL(k_cupdate_slice, gridc(c, 1), dim3(256), cupdate_lds(c->Nf), c->stream, c->G, c->Nf,
+                     field_row(c, tau), tau, (unsigned long long)dir, c->m.coupling, c->m.alpha, c->m.n_col,
+                     field4_table(), c->counters, c->phase, c->cs);
+  HIPCHK(hipGetLastError());
+  return DQMC_OK;
+}
+
+dqmc_status cmeasure(dqmc_ctx* c) {
+  const int N = c->N;
+  const bool sym = c->m.trotter == DQMC_TROTTER_SYM;
+  if (sym)
+    if (dqmc_status s = gemm(c, gemm_args(N, N, N, c->Eh, N, 0, c->G, N, 0, c->T1, N))) return s;
+  hipLaunchKernelGGL(k_cmeasure, gridc(c, 1), dim3(256), 0, c->stream, c->G, sym ? c->T1 : nullptr, c->Ehinv,
+                     c->Kd, c->Nf, sym ? 1 : 0, c->trK_field, (double)c->m.n_col, c->m.u_int, c->bins,
+                     c->err_flag, c->cs);
+  HIPCHK(hipGetLastError());
+  return DQMC_OK;
+}
+
+dqmc_status stabilise(dqmc_ctx* c, int hist_index);
+dqmc_status copy_udv(dqmc_ctx* c, UDVp dst, UDVp src);
+dqmc_status csweep_once(dqmc_ctx* c, int meas) {
+  const int L = c->L, nw = c->nw, nk = c->nk;
+  int hist = 0;
+  c->row_alt.clear();
+  c->Gcur = c->G;
+  for (int tau = 1; tau <= L; ++tau) {
+    if (dqmc_status s = cwrap_up(c, tau)) return s;
+    if (dqmc_status s = cupdate(c, tau, 0)) return s;
+    if (tau % nw == 0) {
+      const int k = tau / nw;
+      if (dqmc_status s = timing_begin(c, DQMC_KERNEL_STABILISE)) return s;
+      UDVp prev = (k == 1) ? c->uid : c->slot(k - 1);
+      if (dqmc_status s = right_step(c, prev, tau - nw, tau, c->cur)) return s;
+      UDVp left = (k == nk) ? c->uid : c->slot(k);
+      if (dqmc_status s = merge(c, c->cur, left, c->Gs, nullptr)) return s;
+      if (dqmc_status s = copy_udv(c, c->slot(k), c->cur)) return s;
+      if (dqmc_status s = stabilise(c, hist++)) return s;
+      if (dqmc_status s = timing_end(c, DQMC_KERNEL_STABILISE)) return s;
+    }
+    if (meas & 1)
+      if (dqmc_status s = cmeasure(c)) return s;
+  }
+  for (int tau = L; tau >= 1; --tau) {
+    if (dqmc_status s = cupdate(c, tau, 1)) return s;
+    if (meas & 1)
+      if (dqmc_status s = cmeasure(c)) return s;
+    if ((tau - 1) % nw == 0) {
+      const int k = (tau - 1) / nw;
+      if (dqmc_status s = cwrap_down(c, tau)) return s;
+      if (dqmc_status s = timing_begin(c, DQMC_KERNEL_STABILISE)) return s;
+      UDVp prev = (k + 1 == nk) ? c->uid : c->slot(k + 1);
+      if (dqmc_status s = left_step(c, prev, tau - 1, tau - 1 + nw, c->cur)) return s;
+      UDVp right = (k == 0) ? c->uid : c->slot(k);
+      if (dqmc_status s = merge(c, right, c->cur, c->Gs, nullptr)) return s;
+      if (dqmc_status s = copy_udv(c, c->slot(k), c->cur)) return s;
+      if (dqmc_status s = stabilise(c, hist++)) return s;
+      if (dqmc_status s = timing_end(c, DQMC_KERNEL_STABILISE)) return s;
+    } else {
+      if (dqmc_status s = cwrap_down(c, tau)) return s;
+    }
+  }
+  hipLaunchKernelGGL(k_finish_sweep, gridc(c, 1), dim3(64), 0, c->stream, c->prec_hist, hist, c->prec_tot,
+                     c->m.prec_threshold, c->counters, c->err_flag, c->cs);
+  HIPCHK(hipGetLastError());
+  return DQMC_OK;
+}
+
 dqmc_status fill_small(dqmc_ctx* c, double* p, size_t n, double v) {
   hipLaunchKernelGGL(k_fill, gridc(c, grid1(n)), dim3(256), 0, c->stream, p, n, v, is_shared(c, p) ? (size_t)0 : c->cs);
   HIPCHK(hipGetLastError());
@@ -823,7 +940,9 @@ dqmc_status check_model(const dqmc_model* m) {
   if (!(m->beta > 0.0) || !(m->dtau > 0.0)) return DQMC_E_ARG;
   if (std::fabs(m->beta - m->n_slices * m->dtau) > 1e-12 * m->beta) return DQMC_E_ARG;
   if (m->n_col < 1 || m->n_col > 2) return DQMC_E_ARG;
-  if (m->field != DQMC_FIELD_ISING && m->field != DQMC_FIELD_GAUSS && m->field != DQMC_FIELD_ISING4) return DQMC_E_ARG;
+  if (m->field != DQMC_FIELD_ISING && m->field != DQMC_FIELD_GAUSS && m->field != DQMC_FIELD_ISING4 &&
+      m->field != DQMC_FIELD_ISING4_IMAG)
+    return DQMC_E_ARG;
   if (m->trotter != DQMC_TROTTER_ASYM && m->trotter != DQMC_TROTTER_SYM) return DQMC_E_ARG;
   if (!std::isfinite(m->coupling) || !std::isfinite(m->alpha)) return DQMC_E_ARG;
   return DQMC_OK;
@@ -1090,11 +1209,14 @@ extern "C" {
 
 dqmc_status dqmc_query_sizes(const dqmc_model* m, dqmc_sizes* out) {
   if (!out || check_model(m) != DQMC_OK) return DQMC_E_ARG;
+  const bool cplx = m->field == DQMC_FIELD_ISING4_IMAG;
+  if (cplx && m->n > kCMaxN) return DQMC_E_UNSUPPORTED;
   dqmc_ctx tmp;
-  tmp.N = m->n; tmp.L = m->n_slices; tmp.nw = m->n_wrap; tmp.nk = m->n_slices / m->n_wrap;
-  const size_t N = m->n;
+  tmp.N = cplx ? 2 * m->n : m->n; tmp.Nf = m->n; tmp.cplx = cplx ? 1 : 0;
+  tmp.L = m->n_slices; tmp.nw = m->n_wrap; tmp.nk = m->n_slices / m->n_wrap;
+  const size_t N = tmp.N;
   out->G = N * N * sizeof(double);
-  out->field = (size_t)m->n_slices * N * sizeof(double);
+  out->field = (size_t)m->n_slices * m->n * sizeof(double);
   out->slots = (size_t)(tmp.nk + 1) * (2 * N * N + N) * sizeof(double);
   out->work = layout_work(&tmp, false) * sizeof(double);
   return DQMC_OK;
@@ -1113,14 +1235,24 @@ dqmc_status dqmc_create(const dqmc_model* m, const double* K, const int32_t* ver
       const double a = K[(size_t)i * N + j], b = K[(size_t)j * N + i];
       if (!std::isfinite(a) || a != b) return DQMC_E_ARG;
     }
+  const bool cplx = m->field == DQMC_FIELD_ISING4_IMAG;
+  if (cplx && N > kCMaxN) return DQMC_E_UNSUPPORTED;
   dqmc_ctx* c = new (std::nothrow) dqmc_ctx();
   if (!c) return DQMC_E_NOMEM;
   c->m = *m;
-  c->N = N; c->L = m->n_slices; c->nw = m->n_wrap; c->nk = m->n_slices / m->n_wrap;
+  // a complex field runs on the 2n x 2n images: K becomes diag(K, K)
+  const int Nd = cplx ? 2 * N : N;
+  c->N = Nd; c->Nf = N; c->cplx = cplx ? 1 : 0;
+  c->L = m->n_slices; c->nw = m->n_wrap; c->nk = m->n_slices / m->n_wrap;
   // panel width: the register panels hold up to 48 rows per thread in
   // 256/nb row groups
-  c->nb = (N <= 8 * 48) ? 32 : (N <= 16 * 48 ? 16 : 8);
-  c->K.assign(K, K + (size_t)N * N);
+  c->nb = (Nd <= 8 * 48) ? 32 : (Nd <= 16 * 48 ? 16 : 8);
+  c->K.assign((size_t)Nd * Nd, 0.0);
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      c->K[(size_t)i * Nd + j] = K[(size_t)i * N + j];
+      if (cplx) c->K[(size_t)(i + N) * Nd + j + N] = K[(size_t)i * N + j];
+    }
   double tr = 0.0, n1 = 0.0;
   for (int j = 0; j < N; ++j) {
     double col = 0.0;
@@ -1128,7 +1260,7 @@ dqmc_status dqmc_create(const dqmc_model* m, const double* K, const int32_t* ver
     n1 = std::max(n1, col);
     tr += K[(size_t)j * N + j];
   }
-  c->trK = tr; c->normK1 = n1;
+  c->trK = cplx ? 2.0 * tr : tr; c->trK_field = tr; c->normK1 = n1;
   *out = c;
   return DQMC_OK;
 }
@@ -1187,7 +1319,7 @@ dqmc_status dqmc_bind(dqmc_ctx* c, const dqmc_buffers* b, void* stream) {
 dqmc_status dqmc_set_state(dqmc_ctx* c, const double* field_host, uint64_t sweep_counter) {
   if (!c || !field_host) return fail(c, DQMC_E_ARG, "null argument");
   if (!c->bound) return fail(c, DQMC_E_STATE, "not bound");
-  const size_t n = (size_t)c->L * c->N;
+  const size_t n = (size_t)c->L * c->Nf;
   for (size_t e = 0; e < n; ++e) {
     const double v = field_host[e];
     if (!field_value_ok(c->m.field, v))
@@ -1206,7 +1338,7 @@ dqmc_status dqmc_get_state(dqmc_ctx* c, double* field_host, uint64_t* sweep_coun
   if (!c) return DQMC_E_ARG;
   if (!c->bound) return fail(c, DQMC_E_STATE, "not bound");
   if (field_host)
-    HIPCHK(hipMemcpyAsync(field_host, c->field, (size_t)c->L * c->N * sizeof(double), hipMemcpyDeviceToHost,
+    HIPCHK(hipMemcpyAsync(field_host, c->field, (size_t)c->L * c->Nf * sizeof(double), hipMemcpyDeviceToHost,
                           c->stream));
   unsigned long long ctr = 0;
   HIPCHK(hipMemcpyAsync(&ctr, c->counters + 2, sizeof(ctr), hipMemcpyDeviceToHost, c->stream));
@@ -1218,9 +1350,10 @@ dqmc_status dqmc_get_state(dqmc_ctx* c, double* field_host, uint64_t* sweep_coun
 dqmc_status dqmc_random_field(dqmc_ctx* c) {
   if (!c) return DQMC_E_ARG;
   if (!c->bound) return fail(c, DQMC_E_STATE, "not bound");
-  const size_t n = (size_t)c->L * c->N;
-  hipLaunchKernelGGL(k_random_field, gridc(c, grid1(n)), dim3(256), 0, c->stream, c->field, c->L, c->N,
-                     c->counters, (int)c->m.field, field4_table(), c->cs);
+  const size_t n = (size_t)c->L * c->Nf;
+  const int kind = c->cplx ? (int)DQMC_FIELD_ISING4 : (int)c->m.field;   // the same four values
+  hipLaunchKernelGGL(k_random_field, gridc(c, grid1(n)), dim3(256), 0, c->stream, c->field, c->L, c->Nf,
+                     c->counters, kind, field4_table(), c->cs);
   HIPCHK(hipGetLastError());
   if (dqmc_status s = fill_small(c, reinterpret_cast<double*>(c->counters + 2), 1, 0.0)) return s;
   if (dqmc_status s = fill_small(c, reinterpret_cast<double*>(c->counters + 4), 1, 0.0)) return s;
@@ -1242,6 +1375,8 @@ dqmc_status dqmc_init(dqmc_ctx* c) {
   if (dqmc_status s = fill_small(c, c->prec_tot, 4, 0.0)) return s;
   if (dqmc_status s = fill_small(c, reinterpret_cast<double*>(c->counters), 2, 0.0)) return s;
   if (dqmc_status s = fill_small(c, reinterpret_cast<double*>(c->err_flag), 1, 0.0)) return s;
+  if (dqmc_status s = fill_small(c, c->phase, 1, 1.0)) return s;
+  if (dqmc_status s = fill_small(c, c->phase + 1, 3, 0.0)) return s;
   if (dqmc_status s = reanchor(c)) return s;
   if (dqmc_status s = read_flag(c)) return s;
   c->poisoned = false;
@@ -1253,13 +1388,14 @@ dqmc_status dqmc_sweep(dqmc_ctx* c, int32_t n_sweeps, int32_t meas, dqmc_stats* 
   if (!c || n_sweeps < 0) return fail(c, DQMC_E_ARG, "bad arguments");
   if (!c->bound || !c->initialized || c->poisoned) return fail(c, DQMC_E_STATE, "context not initialised");
   if (meas & ~15) return fail(c, DQMC_E_ARG, "unknown measurement flags");
+  if (c->cplx && (meas & ~1)) return fail(c, DQMC_E_UNSUPPORTED, "a complex field measures the estimators of bit 0 only");
   if ((meas & 8) && (!(meas & 2) || c->eq_norb < 1 || td_corr_size(c) == 0))
     return fail(c, DQMC_E_STATE, "time-displaced correlations need bit 1 and dqmc_eq_setup");
   if ((meas & 2) && c->td_norb < 1) return fail(c, DQMC_E_STATE, "time-displaced measurement not set up");
   if ((meas & 4) && c->eq_norb < 1) return fail(c, DQMC_E_STATE, "lattice-resolved correlations not set up");
   const auto t0 = std::chrono::steady_clock::now();
   for (int s = 0; s < n_sweeps; ++s)
-    if (dqmc_status r = sweep_once(c, meas)) return r;
+    if (dqmc_status r = c->cplx ? csweep_once(c, meas) : sweep_once(c, meas)) return r;
   if (dqmc_status r = read_flag(c)) return r;
   const auto t1 = std::chrono::steady_clock::now();
   if (st) {
@@ -1285,6 +1421,15 @@ dqmc_status dqmc_reset_bins(dqmc_ctx* c) {
   if (dqmc_status s = fill_small(c, c->eq_bins, eq_bins_size(c), 0.0)) return s;
   if (td_corr_size(c))
     if (dqmc_status s = fill_small(c, c->td_corr, td_corr_size(c), 0.0)) return s;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_read_phase(dqmc_ctx* c, double* out3) {
+  if (!c || !out3) return DQMC_E_ARG;
+  if (!c->cplx) return fail(c, DQMC_E_UNSUPPORTED, "only a complex field carries a phase");
+  if (!c->bound) return fail(c, DQMC_E_STATE, "not bound");
+  HIPCHK(hipMemcpyAsync(out3, c->phase, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   return DQMC_OK;
 }
@@ -1341,6 +1486,7 @@ dqmc_status dqmc_ratio(dqmc_ctx* c, int32_t tau, int32_t site, double s_new, dou
   if (c->nch != 1) return fail(c, DQMC_E_UNSUPPORTED, "single chains only");
   if (tau > c->L || site >= c->N) return fail(c, DQMC_E_ARG, "tau or site out of range");
   if (!field_value_ok(c->m.field, s_new)) return fail(c, DQMC_E_ARG, "not a value of the field");
+  if (c->cplx) return fail(c, DQMC_E_UNSUPPORTED, "not built for a complex field");
   if (dqmc_status s = dqmc_green_scratch(c, tau, c->Gs)) return s;
   hipLaunchKernelGGL(k_ratio, dim3(1), dim3(64), 0, c->stream, c->Gs, c->N, site,
                      c->field + (size_t)(tau - 1) * c->N, s_new, c->m.coupling, c->m.alpha, c->m.n_col,
@@ -1354,6 +1500,7 @@ dqmc_status dqmc_ratio(dqmc_ctx* c, int32_t tau, int32_t site, double s_new, dou
 dqmc_status dqmc_logdet(dqmc_ctx* c, double* logdet) {
   if (!c || !logdet) return DQMC_E_ARG;
   if (!c->bound) return fail(c, DQMC_E_STATE, "not bound");
+  if (c->cplx) return fail(c, DQMC_E_UNSUPPORTED, "not built for a complex field");
   UDVp left = c->uid;
   UDVp lb[2] = {c->hA, c->hB};
   int q = 0;
@@ -1370,6 +1517,7 @@ dqmc_status dqmc_logdet(dqmc_ctx* c, double* logdet) {
 
 dqmc_status dqmc_grad_logdet(dqmc_ctx* c, double* grad_dev, double* prec) {
   if (!c || !grad_dev) return fail(c, DQMC_E_ARG, "null argument");
+  if (c->cplx) return fail(c, DQMC_E_UNSUPPORTED, "not built for a complex field");
   if (!c->bound || !c->initialized || c->poisoned) return fail(c, DQMC_E_STATE, "context not initialised");
   if (dqmc_status s = grad_pass(c)) return s;
   HIPCHK(hipMemcpyAsync(grad_dev, c->grad, (size_t)c->L * c->N * sizeof(double), hipMemcpyDeviceToDevice,
@@ -1410,6 +1558,7 @@ dqmc_status dqmc_set_langevin_step(dqmc_ctx* c, uint64_t step) {
 dqmc_status dqmc_td_setup(dqmc_ctx* c, int32_t norb, const int32_t* orb_of, const double* phase, int32_t n_cells) {
   if (!c || !orb_of || !phase || norb < 1 || norb > kTdMaxOrb || n_cells < 1)
     return fail(c, DQMC_E_ARG, "bad arguments");
+  if (c->cplx) return fail(c, DQMC_E_UNSUPPORTED, "not built for a complex field");
   if (!c->bound) return fail(c, DQMC_E_STATE, "not bound");
   for (int i = 0; i < c->N; ++i) {
     if (orb_of[i] < 0 || orb_of[i] >= norb) return fail(c, DQMC_E_ARG, "orbital index out of range");
@@ -1427,6 +1576,7 @@ dqmc_status dqmc_td_setup(dqmc_ctx* c, int32_t norb, const int32_t* orb_of, cons
 dqmc_status dqmc_eq_setup(dqmc_ctx* c, int32_t L1, int32_t L2, int32_t norb, const int32_t* site, const double* sign) {
   if (!c || !site || !sign || L1 < 1 || L2 < 1 || norb < 1 || norb > kEqMaxOrb)
     return fail(c, DQMC_E_ARG, "bad arguments");
+  if (c->cplx) return fail(c, DQMC_E_UNSUPPORTED, "not built for a complex field");
   if (!c->bound) return fail(c, DQMC_E_STATE, "not bound");
   if ((int64_t)L1 * L2 * norb != c->N) return fail(c, DQMC_E_ARG, "L1 * L2 * norb must equal the number of orbitals");
   std::vector<char> seen(c->N, 0);
@@ -1583,7 +1733,8 @@ dqmc_status dqmc_hubbard_coupling(double U, double dtau, dqmc_field_kind kind, d
   } else if (kind == DQMC_FIELD_GAUSS) {
     if (U < 0.0) return DQMC_E_ARG;
     *coupling = std::sqrt(dtau * U);
-  } else if (kind == DQMC_FIELD_ISING4) {
+  } else if (kind == DQMC_FIELD_ISING4 || kind == DQMC_FIELD_ISING4_IMAG) {
+    // the real coupling of the attractive frame, or c of the imaginary one i c
     if (U < 0.0) return DQMC_E_ARG;
     *coupling = std::sqrt(dtau * U / 2.0);
   } else {
@@ -1711,6 +1862,8 @@ dqmc_status dqmc_batch_create(int32_t n_chains, const dqmc_model* models, const 
   if (!out) return DQMC_E_ARG;
   *out = nullptr;
   if (n_chains < 1 || !models || !K) return DQMC_E_ARG;
+  for (int i = 0; i < n_chains; ++i)
+    if (models[i].field == DQMC_FIELD_ISING4_IMAG) return DQMC_E_UNSUPPORTED;   // single chains only
   dqmc_batch* b = new (std::nothrow) dqmc_batch();
   if (!b) return DQMC_E_NOMEM;
   std::vector<int> first_of;   // chain index that defines each group
@@ -2129,6 +2282,7 @@ dqmc_status dqmc_green_scratch_noalloc(dqmc_ctx* c, const double* field_dev, int
   dqmc_ctx t;
   t.m = c->m;
   t.N = c->N; t.L = c->L; t.nw = c->nw; t.nk = c->nk; t.nb = c->nb;
+  t.Nf = c->Nf; t.cplx = c->cplx; t.trK_field = c->trK_field;
   t.K = c->K;
   t.trK = c->trK; t.normK1 = c->normK1;
   const size_t need = layout_work(&t, false);

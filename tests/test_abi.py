@@ -157,3 +157,30 @@ def test_mz_frame_hopping_matches_oracle_and_refuses_two_flavours(lib):
     with pytest.raises(DQMCError) as e:
         pa.mz_frame_hopping(lat.K, 0.45, 0.5 * lat.sublattice_sign())
     assert e.value.status == 1
+
+
+def test_complex_field_sizes_and_refusals(lib):
+    """Host-only: a complex field holds its G as the 2n x 2n real image and
+    the field as n_slices * n values; more than 64 sites, batches and the
+    phase read of a real field are refused before any device work."""
+    from paper_1704_00131_amd._lib import Sizes
+    m = _model(field="ising4_imag")
+    s = Sizes()
+    assert lib.dqmc_query_sizes(ctypes.byref(m), ctypes.byref(s)) == 0
+    assert s.G == 32 * 32 * 8 and s.field == 20 * 16 * 8
+    assert s.slots == 3 * (2 * 32 * 32 + 32) * 8
+    big = _model(n=65, field="ising4_imag")
+    assert lib.dqmc_query_sizes(ctypes.byref(big), ctypes.byref(Sizes())) == 2
+    K = np.zeros((65, 65))
+    ctx = ctypes.c_void_p()
+    assert lib.dqmc_create(ctypes.byref(big), K.ctypes.data, None, ctypes.byref(ctx)) == 2
+    K16 = np.zeros((16, 16))
+    models = (type(m) * 1)(m)
+    ptrs = (ctypes.c_void_p * 1)(K16.ctypes.data)
+    b = ctypes.c_void_p()
+    assert lib.dqmc_batch_create(1, models, ptrs, ctypes.byref(b)) == 2
+    real = _model()
+    assert lib.dqmc_create(ctypes.byref(real), K16.ctypes.data, None, ctypes.byref(ctx)) == 0
+    out = np.zeros(3)
+    assert lib.dqmc_read_phase(ctx, out.ctypes.data) == 2
+    lib.dqmc_destroy(ctx)

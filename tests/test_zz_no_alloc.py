@@ -65,3 +65,22 @@ def test_noalloc_refuses_models_beyond_the_static_maximum():
                                              ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)), ctx)
     assert e.value.status == 2 and "MiB" in str(e.value)
     lib.dqmc_destroy(ctx)
+
+
+def test_noalloc_green_complex_field():
+    """A complex field (the 2n x 2n images and the rotations of its slices)
+    through the allocation-free path equals the ordinary recomputation."""
+    import paper_1704_00131_amd as pa
+    from gpu_util import lattice
+    lib = pa.load()
+    lat = lattice("square", 6, 4)
+    c = pa.hubbard_coupling(4.0, 0.1, "ising4_imag")
+    m = pa.make_model(lat.n, 1.5, 0.1, 5, c, U=4.0, field="ising4_imag", trotter="asym", seed=5)
+    ch = pa.Chain(m, lat.K)
+    ch.random_field()
+    print("noalloc green complex 6x4", flush=True)
+    for tau in (0, 4, 15):
+        want = ch.green_scratch(tau)
+        got = _noalloc(lib, ch.ctx, ch.field.data_ptr(), tau, ch.Nd, ch.stream.cuda_stream)
+        assert maxabs(got.cpu().numpy(), want.cpu().numpy()) < 1e-9, tau
+    ch.close()
