@@ -41,7 +41,8 @@ Prints one JSON line with
              gradient passes and Langevin steps of 64 Gaussian-field chains
              (10x10, beta = 4); the time-displaced pass alone; the 12x12 chain
              with the paper's four-valued field, with the lattice-resolved
-             equal-time correlations, and in the M_z form with a Zeeman field.
+             equal-time correlations, and in the M_z form with a Zeeman field;
+             the complex (imaginary-coupling) formulation on the 8x8 square.
 """
 import argparse
 import hashlib
@@ -400,6 +401,30 @@ def bench_zeeman(torch, pa):
             "double_occupancy": bins[0] / bins[3]}
 
 
+def bench_complex(torch, pa):
+    """The paper-literal complex formulation of the SU(2) Hubbard model
+    (imaginary coupling of the four-valued field, complex G held as its real
+    image) on the largest lattice it runs, the 8x8 square (n = 64, images of
+    128), U = 4, beta = 4, L = 40: three timed sweeps after one untimed, with
+    the phase carried along."""
+    from inputs import square_lattice
+    lat = square_lattice(8, 8)
+    beta, dtau, U = 4.0, 0.1, 4.0
+    m = pa.make_model(lat.n, beta, dtau, 10, pa.hubbard_coupling(U, dtau, "ising4_imag"), U=U,
+                      field="ising4_imag", trotter="sym", seed=0)
+    ch = pa.Chain(m, lat.K)
+    ch.random_field().init()
+    ch.sweep(1, measure=True)
+    st0 = ch.sweep(0, measure=True)
+    dt, st = _sync_time(torch, lambda: ch.sweep(3, measure=True))
+    phase, dev = ch.read_phase()
+    ch.close()
+    props = st.proposals - st0.proposals
+    return {"n": lat.n, "L": m.n_slices, "ms_per_sweep": 1e3 * dt / 3, "updates_per_s": props / dt,
+            "acceptance": (st.accepted - st0.accepted) / max(1, props), "prec_max": st.prec_max,
+            "precision_phase": dev}
+
+
 def bench_correlations(torch, pa):
     """The honeycomb 12x12 chain of the headline workload with the
     lattice-resolved equal-time correlations (Green, SpinZ, SpinXY, Den by
@@ -433,7 +458,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--profile-extra", choices=["honeycomb12", "batched", "gradient", "time_displaced",
-                                                "four_valued", "correlations", "zeeman"],
+                                                "four_valued", "correlations", "zeeman", "complex"],
                     help="run only this extra workload and print its figures (for rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -451,7 +476,7 @@ def main():
     if args.profile_extra:
         fn = {"honeycomb12": bench_honeycomb12, "batched": bench_batched, "gradient": bench_gradient,
               "time_displaced": bench_time_displaced, "four_valued": bench_four_valued,
-              "correlations": bench_correlations, "zeeman": bench_zeeman}
+              "correlations": bench_correlations, "zeeman": bench_zeeman, "complex": bench_complex}
         print(json.dumps({args.profile_extra: fn[args.profile_extra](torch, pa)}))
         return
 
@@ -528,7 +553,7 @@ def main():
                                    "time_displaced": bench_time_displaced(torch, pa),
                                    "four_valued": bench_four_valued(torch, pa),
                                    "correlations": bench_correlations(torch, pa),
-                                   "zeeman": bench_zeeman(torch, pa)}
+                                   "zeeman": bench_zeeman(torch, pa), "complex": bench_complex(torch, pa)}
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out))
