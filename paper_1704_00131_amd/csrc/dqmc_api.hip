@@ -558,7 +558,6 @@ dqmc_status qr_udv(dqmc_ctx* c, double* M, const double* T_in, UDVp out) {
   return gemm(c, gemm_args(N, N, N, c->Rt, N, 0, T_in, N, 0, out.T, N));
 }
 
-// Right step: UDV of B(hi,0) from that of B(lo,0): M = (B_hi ... B_lo+1 Q) D.
 // Rotations of a complex field's images (k_crot): rows by diag(exp(i c_row eta)),
 // columns by diag(exp(-i c_col eta)); a zero coefficient skips that side.
 dqmc_status crot(dqmc_ctx* c, double* dst, const double* src, int tau, double coef_row, double coef_col) {
@@ -569,6 +568,7 @@ dqmc_status crot(dqmc_ctx* c, double* dst, const double* src, int tau, double co
   return DQMC_OK;
 }
 
+// Right step: UDV of B(hi,0) from that of B(lo,0): M = (B_hi ... B_lo+1 Q) D.
 dqmc_status right_step(dqmc_ctx* c, UDVp in, int lo, int hi, UDVp out) {
   const int N = c->N;
   const double* src = in.Q;
