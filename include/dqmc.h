@@ -313,6 +313,20 @@ dqmc_status dqmc_td_read_corr_bins(dqmc_ctx* ctx, double* sums_host, double* cou
  * merge with its LU solve and the precision check, section "Stabilization";
  * the events bracket the step's launch sequence). */
 typedef enum { DQMC_KERNEL_BLOCK_UPDATE = 0, DQMC_KERNEL_GEMM = 1, DQMC_KERNEL_STABILISE = 2 } dqmc_kernel;
+
+/* Kernel choice for the slices between stabilisations (Algorithm 1: the
+ * wraps, the sequential single flips and the equal-time estimators).  With
+ * enable = 1 a lattice of n <= 64 orbitals runs each chunk of n_wrap slices in
+ * one launch per chain, one workgroup per chain with G and the exponentials
+ * resident in LDS; 0 selects the blocked kernels (wrap products, 32-site
+ * block updates, one measurement launch per slice), which larger lattices
+ * always use, as do sweeps with the lattice-resolved equal-time correlations
+ * and sweeps whose block update is being timed; -1 (the default) takes the
+ * chunk kernel for batch groups of at least 16 chains and the blocked
+ * kernels otherwise (a lone chain on one workgroup leaves the chip idle).
+ * Both follow the same decisions and random numbers; G agrees up to
+ * rounding.  DQMC_E_ARG for other values. */
+dqmc_status dqmc_set_chunk_kernel(dqmc_ctx* ctx, int32_t enable);
 dqmc_status dqmc_timing_enable(dqmc_ctx* ctx, dqmc_kernel kernel, int32_t enable);
 dqmc_status dqmc_timing_read(dqmc_ctx* ctx, double* total_ms, uint64_t* launches, double* flops);
 
@@ -343,6 +357,8 @@ dqmc_status dqmc_batch_set_state(dqmc_batch* b, int32_t chain, const double* fie
 dqmc_status dqmc_batch_get_state(dqmc_batch* b, int32_t chain, double* field_host, uint64_t* sweep_counter);
 /* Storage fill and G(0) of every chain. */
 dqmc_status dqmc_batch_init(dqmc_batch* b);
+/* dqmc_set_chunk_kernel for every group of the batch; drops a captured graph. */
+dqmc_status dqmc_batch_set_chunk_kernel(dqmc_batch* b, int32_t enable);
 /* Autotuner: per group, times `trials` sweeps with each GEMM kernel (16 x 16
  * and 32 x 32 direct MFMA tiles, 64 x 64 LDS-staged tiles) and keeps the
  * fastest (the trial sweeps advance the chains like warm-up sweeps; a

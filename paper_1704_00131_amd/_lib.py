@@ -54,6 +54,8 @@ SIGNATURES = {
     "dqmc_sweep": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Stats)]),
     "dqmc_read_bins": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "dqmc_read_phase": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "dqmc_set_chunk_kernel": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "dqmc_batch_set_chunk_kernel": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "dqmc_reset_bins": (ctypes.c_int, [ctypes.c_void_p]),
     "dqmc_green_scratch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "dqmc_green_scratch_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,

@@ -55,6 +55,14 @@ class Batch:
 
     def autotune(self, trials=1):
         self._chk(self.lib.dqmc_batch_autotune(self.b, trials))
+        return self
+
+    def chunk_kernel(self, enable=True):
+        """Slices between stabilisations in one launch per chain (n <= 64):
+        True always, False never (the blocked kernels), None automatic (groups
+        of at least 16 chains)."""
+        self._chk(self.lib.dqmc_batch_set_chunk_kernel(self.b, -1 if enable is None else (1 if enable else 0)))
+        return self
 
     @property
     def n_groups(self):

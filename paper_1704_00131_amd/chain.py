@@ -238,6 +238,13 @@ class Chain:
         self._chk(self.lib.dqmc_td_read_corr_bins(self.ctx, out.ctypes.data, ctypes.byref(cnt)))
         return out, cnt.value
 
+    def chunk_kernel(self, enable=True):
+        """Slices between stabilisations in one launch with G in LDS (n <= 64):
+        True always, False never (the blocked kernels), None automatic (groups
+        of at least 16 chains; a lone chain takes the blocked kernels)."""
+        self._chk(self.lib.dqmc_set_chunk_kernel(self.ctx, -1 if enable is None else (1 if enable else 0)))
+        return self
+
     def timing(self, kernel: str = "block_update", enable: bool = True, every: int = 1):
         """Bracket launches of one kernel with HIP events: every launch, or every
         `every`-th one (a rotating sample) when every > 1."""

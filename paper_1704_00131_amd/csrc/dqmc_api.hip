@@ -22,6 +22,7 @@
 #include "timedisplaced.h"
 #include "correlations.h"
 #include "complex.h"
+#include "chunk.h"
 
 namespace {
 
@@ -102,6 +103,9 @@ struct dqmc_ctx {
   size_t cs = 0;
   const double *shared_lo = nullptr, *shared_hi = nullptr;
   int gemm_tile = 0;
+  // chunks of slices in one launch per chain with G in LDS (n <= kChunkMaxN):
+  // 1 always, 0 never, -1 for groups of at least kChunkMinChains chains
+  int fused = -1;
   std::vector<uint64_t> seeds;
   double* gbuf = nullptr;
   // optional per-launch event timing of one kernel (every timing_every-th launch)
@@ -512,6 +516,12 @@ dqmc_status set_lds_limits(dqmc_ctx* c) {
   HIPCHK((lds_limit_qr<16, 4, 8, 12>()));
   HIPCHK((lds_limit_qr<8, 4, 8, 16>()));
   HIPCHK(gemm64_set_lds());
+  if (!c->cplx && c->N <= kChunkMaxN) {
+    const void* fns[] = {reinterpret_cast<const void*>(k_chunk<1>), reinterpret_cast<const void*>(k_chunk<2>),
+                         reinterpret_cast<const void*>(k_chunk<3>), reinterpret_cast<const void*>(k_chunk<4>)};
+    HIPCHK(hipFuncSetAttribute(fns[chunk_np(c->N) / 16 - 1], hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)chunk_lds(c->N, 1)));
+  }
   if (c->cplx)
     HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(k_cupdate_slice),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)cupdate_lds(kCMaxN)));
@@ -778,7 +788,101 @@ dqmc_status pass_draws(dqmc_ctx* c, int dir) {
 // equal-time correlations on every slice, bit 3 = the lattice-resolved
 // time-displaced correlations in that pass.
 dqmc_status td_pass(dqmc_ctx* c);
+
+// The chunk kernel runs the sweep's slices between stabilisations when the
+// lattice fits its LDS, for the equal-time estimators and the time-displaced
+// pass (the lattice-resolved equal-time correlations take the blocked path),
+// unless it is switched off or the block update is being timed.
+// One workgroup per chain keeps a lone chain on one CU, where the blocked
+// kernels spread it over many: the automatic choice takes the chunk kernel
+// for groups of at least this many chains.
+constexpr int kChunkMinChains = 16;
+
+bool use_chunks(const dqmc_ctx* c, int meas) {
+  const bool on = c->fused == 1 || (c->fused == -1 && c->nch >= kChunkMinChains);
+  return on && !c->cplx && c->N <= kChunkMaxN && !(meas & 4) &&
+         !(c->timing && c->timing_kernel == DQMC_KERNEL_BLOCK_UPDATE);
+}
+
+template <int NT>
+void launch_chunk_nt(const ChunkArgs& a, dim3 grid, size_t lds, hipStream_t s) {
+  hipLaunchKernelGGL(k_chunk<NT>, grid, dim3(256), lds, s, a);
+}
+
+dqmc_status launch_chunk(dqmc_ctx* c, int tau0, int ntau, int dir, int measure, int skip_last) {
+  ChunkArgs a;
+  a.G = c->G; a.field = c->field;
+  a.E = c->E; a.Einv = c->Einv; a.Eh = c->Eh; a.Ehinv = c->Ehinv; a.K = c->Kd;
+  a.counters = c->counters; a.bins = c->bins; a.err = c->err_flag;
+  a.N = c->N; a.tau0 = tau0; a.ntau = ntau; a.dir = dir;
+  a.measure = measure; a.skip_last = skip_last;
+  a.sym = c->m.trotter == DQMC_TROTTER_SYM ? 1 : 0;
+  a.kind = (int)c->m.field; a.n_col = c->m.n_col;
+  a.coupling = c->m.coupling; a.alpha = c->m.alpha; a.prop_width = c->m.prop_width;
+  a.trK = c->trK; a.u_int = c->m.u_int;
+  a.f4 = field4_table();
+  a.cs = c->cs;
+  const dim3 grid = gridc(c, 1);
+  const size_t lds = chunk_lds(c->N, a.sym);
+  switch (chunk_np(c->N) / 16) {
+    case 1: launch_chunk_nt<1>(a, grid, lds, c->stream); break;
+    case 2: launch_chunk_nt<2>(a, grid, lds, c->stream); break;
+    case 3: launch_chunk_nt<3>(a, grid, lds, c->stream); break;
+    case 4: launch_chunk_nt<4>(a, grid, lds, c->stream); break;
+    default: return fail(c, DQMC_E_UNSUPPORTED, "lattice too large for the chunk kernel");
+  }
+  HIPCHK(hipGetLastError());
+  return DQMC_OK;
+}
+
+// One sweep (Algorithm 1) with the slices of every chunk in one launch: the
+// upward chunk k covers slices (k-1) n_wrap + 1 .. k n_wrap (measured but for
+// the last, which is measured after its stabilisation), the downward chunk k
+// slices (k+1) n_wrap .. k n_wrap + 1, each followed by the stabilisation step
+// of the blocked sweep.
+dqmc_status sweep_chunks(dqmc_ctx* c, int meas) {
+  const int nw = c->nw, nk = c->nk;
+  if (meas & 2) {
+    c->td_corr_now = (meas & 8) != 0;
+    const dqmc_status s = td_pass(c);
+    c->td_corr_now = false;
+    if (s) return s;
+  }
+  int hist = 0;
+  c->row_alt.clear();
+  c->Gcur = c->G;
+  for (int k = 1; k <= nk; ++k) {
+    if (dqmc_status s = launch_chunk(c, (k - 1) * nw + 1, nw, 0, meas & 1, 1)) return s;
+    if (dqmc_status s = timing_begin(c, DQMC_KERNEL_STABILISE)) return s;
+    UDVp prev = (k == 1) ? c->uid : c->slot(k - 1);
+    if (dqmc_status s = right_step(c, prev, (k - 1) * nw, k * nw, c->cur)) return s;
+    UDVp left = (k == nk) ? c->uid : c->slot(k);
+    if (dqmc_status s = merge(c, c->cur, left, c->Gs, nullptr)) return s;
+    if (dqmc_status s = copy_udv(c, c->slot(k), c->cur)) return s;
+    if (dqmc_status s = stabilise(c, hist++)) return s;
+    if (dqmc_status s = timing_end(c, DQMC_KERNEL_STABILISE)) return s;
+    if (meas & 1)
+      if (dqmc_status s = measure(c)) return s;
+  }
+  for (int k = nk - 1; k >= 0; --k) {
+    if (dqmc_status s = launch_chunk(c, (k + 1) * nw, nw, 1, meas & 1, 0)) return s;
+    if (dqmc_status s = timing_begin(c, DQMC_KERNEL_STABILISE)) return s;
+    UDVp prev = (k + 1 == nk) ? c->uid : c->slot(k + 1);
+    if (dqmc_status s = left_step(c, prev, k * nw, (k + 1) * nw, c->cur)) return s;
+    UDVp right = (k == 0) ? c->uid : c->slot(k);
+    if (dqmc_status s = merge(c, right, c->cur, c->Gs, nullptr)) return s;
+    if (dqmc_status s = copy_udv(c, c->slot(k), c->cur)) return s;
+    if (dqmc_status s = stabilise(c, hist++)) return s;
+    if (dqmc_status s = timing_end(c, DQMC_KERNEL_STABILISE)) return s;
+  }
+  hipLaunchKernelGGL(k_finish_sweep, gridc(c, 1), dim3(64), 0, c->stream, c->prec_hist, hist, c->prec_tot,
+                     c->m.prec_threshold, c->counters, c->err_flag, c->cs);
+  HIPCHK(hipGetLastError());
+  return DQMC_OK;
+}
+
 dqmc_status sweep_once(dqmc_ctx* c, int meas) {
+  if (use_chunks(c, meas)) return sweep_chunks(c, meas);
   const int L = c->L, nw = c->nw, nk = c->nk;
   if (meas & 2) {
     c->td_corr_now = (meas & 8) != 0;
@@ -1080,10 +1184,12 @@ dqmc_status td_measure(dqmc_ctx* c, int tau, const double* gt0, const double* h,
                        tau == 0 ? c->td_corr + (size_t)(c->L + 1) * td_corr_stride(c) : nullptr, c->cs);
     HIPCHK(hipGetLastError());
   }
-  const int nblk = (N + kTdRows - 1) / kTdRows;
+  // small lattices: one workgroup per chain (no partial records, no fences)
+  const int rows = N <= kTdSmallN ? N : kTdRows;
+  const int nblk = (N + rows - 1) / rows;
   const size_t off = (size_t)tau * kTdStride;
   hipLaunchKernelGGL(k_td_measure, gridc(c, (unsigned)nblk), dim3(256), 0, c->stream, gt0, h, gtt, c->kph, c->korb, N,
-                     c->tdpart, 1.0 / c->td_cells, c->a00, c->tdS + off, c->tdbins + off,
+                     rows, c->tdpart, 1.0 / c->td_cells, c->a00, c->tdS + off, c->tdbins + off,
                      c->tdbins + (size_t)(c->L + 1) * kTdStride, tau == 0 ? 1 : 0, c->cs);
   HIPCHK(hipGetLastError());
   return DQMC_OK;
@@ -1675,6 +1781,12 @@ dqmc_status dqmc_td_read_bins(dqmc_ctx* c, double* sums_host, double* count) {
   return DQMC_OK;
 }
 
+dqmc_status dqmc_set_chunk_kernel(dqmc_ctx* c, int32_t enable) {
+  if (!c || enable < -1 || enable > 1) return fail(c, DQMC_E_ARG, "bad arguments");
+  c->fused = enable;
+  return DQMC_OK;
+}
+
 dqmc_status dqmc_timing_enable(dqmc_ctx* c, dqmc_kernel kernel, int32_t enable) {
   if (!c || enable < 0 ||
       (kernel != DQMC_KERNEL_BLOCK_UPDATE && kernel != DQMC_KERNEL_GEMM && kernel != DQMC_KERNEL_STABILISE))
@@ -2046,6 +2158,14 @@ dqmc_status dqmc_batch_capture(dqmc_batch* b, int32_t sweeps_per_graph, int32_t 
 // the fastest is kept.  The
 // trial sweeps advance the chains like warm-up sweeps; a captured graph is
 // dropped (it would replay the old tiles).
+dqmc_status dqmc_batch_set_chunk_kernel(dqmc_batch* b, int32_t enable) {
+  if (!b || enable < -1 || enable > 1) return bfail(b, DQMC_E_ARG, "bad arguments");
+  for (dqmc_ctx* c : b->groups) c->fused = enable;
+  if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
+  if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+  return DQMC_OK;
+}
+
 dqmc_status dqmc_batch_autotune(dqmc_batch* b, int32_t trials) {
   if (!b || trials < 1) return bfail(b, DQMC_E_ARG, "bad arguments");
   for (dqmc_ctx* c : b->groups)

@@ -19,6 +19,7 @@
 
 constexpr int kTdMaxOrb = 4;          // orbitals per unit cell
 constexpr int kTdRows = 4;            // rows of the product per workgroup
+constexpr int kTdSmallN = 128;        // up to this n one workgroup takes all rows
 constexpr int kTdPart = 2 * kTdMaxOrb * kTdMaxOrb + 2 * kTdMaxOrb;   // doubles per partial record
 constexpr int kTdStride = 2 * kTdMaxOrb * kTdMaxOrb;                 // doubles per tau of S
 
@@ -70,19 +71,21 @@ __global__ __launch_bounds__(256) void k_td_rhs(double* R2, int ld_r, const doub
   }
 }
 
-// S_ab(K, tau) in one launch: every workgroup sums C_ab and A_a over
-// kTdRows rows and stores its partial record; the workgroup that finishes
-// last (a device-scope counter after the records, taken behind a release
-// fence and reset by that workgroup) adds the records in a fixed order and
-// forms S_ab(K, tau): out[0 .. kTdStride) (entry (a * kTdMaxOrb + b) * 2 +
-// {re, im}), also added to bins.  At tau = 0 it first stores A_a(0) in a00
-// (and counts one pass in *count).  Grid (ceil(n / kTdRows), chains), 256
+// S_ab(K, tau) in one launch: every workgroup sums C_ab and A_a over its
+// `rows` rows (wave w every fourth, its lanes the columns) and stores its
+// partial record; the workgroup that finishes last (a device-scope counter
+// after the records, taken behind a release fence by the writing wave and
+// reset by that workgroup) adds the records in a fixed order and forms
+// S_ab(K, tau): out[0 .. kTdStride) (entry (a * kTdMaxOrb + b) * 2 +
+// {re, im}), also added to bins.  With one workgroup per chain (rows = n)
+// there is no record exchange.  At tau = 0 it first stores A_a(0) in a00
+// (and counts one pass in *count).  Grid (ceil(n / rows), chains), 256
 // threads.  phase: [n][2] (re, im) of exp(-i K.R_x); orb: [n] orbital of each
 // site (< norb <= kTdMaxOrb); part: the records, then the counter.
 __global__ __launch_bounds__(256) void k_td_measure(const double* GT0, const double* H, const double* GTT,
-                                                    const double* phase, const int* orb, int n, double* part,
-                                                    double inv_cells, double* a00, double* out, double* bins,
-                                                    double* count, int first, size_t cs) {
+                                                    const double* phase, const int* orb, int n, int rows,
+                                                    double* part, double inv_cells, double* a00, double* out,
+                                                    double* bins, double* count, int first, size_t cs) {
   constexpr int kGroups = 256 / kTdPart;   // threads per record entry in the final sum
   __shared__ double red[4][kTdPart];
   __shared__ double gsum[kGroups][kTdPart];
@@ -97,17 +100,17 @@ __global__ __launch_bounds__(256) void k_td_measure(const double* GT0, const dou
   double acc[kTdPart];
 #pragma unroll
   for (int k = 0; k < kTdPart; ++k) acc[k] = 0.0;
-  const int x0 = blockIdx.x * kTdRows;
-  for (int dx = 0; dx < kTdRows; ++dx) {
-    const int x = x0 + dx;
-    if (x >= n) break;
+  // wave w takes rows x0 + w, x0 + w + 4, ... of the workgroup's rows, its
+  // lanes the columns y = lane, lane + 64, ...
+  const int x0 = blockIdx.x * rows, x1 = min(n, x0 + rows);
+  for (int x = x0 + w; x < x1; x += 4) {
     // row sum over y of conj(p_y) H_xy GT0_xy, split by the orbital of y
     double rr[kTdMaxOrb], ri[kTdMaxOrb];
 #pragma unroll
     for (int b = 0; b < kTdMaxOrb; ++b) { rr[b] = 0.0; ri[b] = 0.0; }
     const double* hx = H + (size_t)x * n;
     const double* gx = GT0 + (size_t)x * n;
-    for (int y = tid; y < n; y += 256) {
+    for (int y = lane; y < n; y += 64) {
       const double p = hx[y] * gx[y];
       const double cr = phase[2 * y], ci = -phase[2 * y + 1];
       const int ob = orb[y];
@@ -129,7 +132,7 @@ __global__ __launch_bounds__(256) void k_td_measure(const double* GT0, const dou
         acc[2 * (a * kTdMaxOrb + b) + 1] += s * (pr * ri[b] + pi * rr[b]);
       }
     }
-    if (tid == 0) {
+    if (lane == 0) {
       const double d = 1.0 - 2.0 * GTT[(size_t)x * n + x];
 #pragma unroll
       for (int a = 0; a < kTdMaxOrb; ++a) {
@@ -147,37 +150,45 @@ __global__ __launch_bounds__(256) void k_td_measure(const double* GT0, const dou
   }
   __syncthreads();
   unsigned int* counter = reinterpret_cast<unsigned int*>(part + (size_t)nblk * kTdPart);
-  if (tid < kTdPart) part[(size_t)blockIdx.x * kTdPart + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) last_s = (atomicAdd(counter, 1u) == (unsigned)nblk - 1u);
-  __syncthreads();
-  if (!last_s) return;
-  __threadfence();
-  // the records in a fixed order: group g adds records g, g + kGroups, ...,
-  // four loads in flight (four partial sums, combined in a fixed order)
-  if (tid < kGroups * kTdPart) {
-    const int k = tid % kTdPart, g = tid / kTdPart;
-    double s4[4] = {0.0, 0.0, 0.0, 0.0};
-    int b = g;
-    for (; b + 3 * kGroups < nblk; b += 4 * kGroups) {
-      double v[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) v[q] = __builtin_nontemporal_load(part + (size_t)(b + q * kGroups) * kTdPart + k);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) s4[q] += v[q];
+  if (nblk == 1) {
+    if (tid < kTdPart) tot[tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+    __syncthreads();
+  } else {
+    if (tid < kTdPart) part[(size_t)blockIdx.x * kTdPart + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+    // the record's writers (wave 0) release it, then one lane counts; the
+    // device-scope fences stay on one wave per workgroup
+    if (w == 0) {
+      __threadfence();
+      if (lane == 0) last_s = (atomicAdd(counter, 1u) == (unsigned)nblk - 1u);
     }
-    for (; b < nblk; b += kGroups) s4[0] += __builtin_nontemporal_load(part + (size_t)b * kTdPart + k);
-    gsum[g][k] = (s4[0] + s4[1]) + (s4[2] + s4[3]);
-  }
-  __syncthreads();
-  if (tid < kTdPart) {
-    double sg = 0.0;
+    __syncthreads();
+    if (!last_s) return;
+    __threadfence();
+    // the records in a fixed order: group g adds records g, g + kGroups, ...,
+    // four loads in flight (four partial sums, combined in a fixed order)
+    if (tid < kGroups * kTdPart) {
+      const int k = tid % kTdPart, g = tid / kTdPart;
+      double s4[4] = {0.0, 0.0, 0.0, 0.0};
+      int b = g;
+      for (; b + 3 * kGroups < nblk; b += 4 * kGroups) {
+        double v[4];
 #pragma unroll
-    for (int g = 0; g < kGroups; ++g) sg += gsum[g][tid];
-    tot[tid] = sg;
+        for (int q = 0; q < 4; ++q) v[q] = __builtin_nontemporal_load(part + (size_t)(b + q * kGroups) * kTdPart + k);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s4[q] += v[q];
+      }
+      for (; b < nblk; b += kGroups) s4[0] += __builtin_nontemporal_load(part + (size_t)b * kTdPart + k);
+      gsum[g][k] = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+    }
+    __syncthreads();
+    if (tid < kTdPart) {
+      double sg = 0.0;
+#pragma unroll
+      for (int g = 0; g < kGroups; ++g) sg += gsum[g][tid];
+      tot[tid] = sg;
+    }
+    __syncthreads();
   }
-  __syncthreads();
   const double* A = tot + 2 * kTdMaxOrb * kTdMaxOrb;
   if (first && tid < 2 * kTdMaxOrb) a00[tid] = A[tid];
   if (first && tid == 0) count[0] += 1.0;
@@ -194,5 +205,5 @@ __global__ __launch_bounds__(256) void k_td_measure(const double* GT0, const dou
     bins[2 * tid] += sr;
     bins[2 * tid + 1] += si;
   }
-  if (tid == 0) *counter = 0u;   // ready for the next tau (kernel boundaries order it)
+  if (tid == 0 && nblk > 1) *counter = 0u;   // ready for the next tau (kernel boundaries order it)
 }

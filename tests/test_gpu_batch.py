@@ -54,17 +54,23 @@ def _compare(b, oms, sweeps, graph=False):
             assert maxabs(bins, oc.bins) < 1e-9 * oc.bins[3]
 
 
-def test_batch_mixed_sizes_two_sweeps():
-    _log("batch mixed sizes")
+# `chunk` True runs groups of n <= 64 through the chunk kernel (the automatic
+# choice for groups of 16 or more chains), False through the blocked kernels.
+@pytest.mark.parametrize("chunk", [True, False])
+def test_batch_mixed_sizes_two_sweeps(chunk):
+    _log(f"batch mixed sizes chunk={chunk}")
     b, oms = _batch([("square", 4, 4, 0), ("honeycomb", 3, 3, 1), ("square", 6, 6, 2), ("square", 4, 4, 3),
                      ("honeycomb", 5, 5, 4)], beta=2.0, n_wrap=10)
+    b.chunk_kernel(chunk)
     _compare(b, oms, 2)
 
 
-def test_batch_graph_replay_asym():
-    _log("batch graph replay")
+@pytest.mark.parametrize("chunk", [True, False])
+def test_batch_graph_replay_asym(chunk):
+    _log(f"batch graph replay chunk={chunk}")
     b, oms = _batch([("square", 4, 4, 5), ("square", 6, 6, 6), ("honeycomb", 4, 4, 7)], beta=2.0, n_wrap=5,
                     trotter="asym")
+    b.chunk_kernel(chunk)
     _compare(b, oms, 3, graph=True)
 
 

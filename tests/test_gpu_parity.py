@@ -46,8 +46,9 @@ def test_green_scratch_and_logdet(kind, L1, L2, beta, trotter):
     assert abs(ch.logdet() - ostable.logdet_scratch(om, f)) < 1e-9 * max(1.0, abs(ostable.logdet_scratch(om, f)))
 
 
-def _trajectory(kind, L1, L2, U, beta, n_wrap, trotter, seed, sweeps, field="ising"):
+def _trajectory(kind, L1, L2, U, beta, n_wrap, trotter, seed, sweeps, field="ising", chunk=True):
     om, ch, _ = pair(kind, L1, L2, U, beta, 0.1, n_wrap, trotter=trotter, seed=seed, field=field)
+    ch.chunk_kernel(chunk)
     ch.random_field().init()
     f0, _ = ch.get_state()
     oc = osweep.Chain(om, f0).init()
@@ -69,11 +70,15 @@ def _trajectory(kind, L1, L2, U, beta, n_wrap, trotter, seed, sweeps, field="isi
     return ch, oc
 
 
-def test_sweep_parity_square4x4_full_run():
+# `chunk` True runs the slices of lattices with n <= 64 through the chunk
+# kernel (G in LDS, one workgroup per chain); False takes the blocked kernels
+# (the automatic choice for a lone chain).
+@pytest.mark.parametrize("chunk", [True, False])
+def test_sweep_parity_square4x4_full_run(chunk):
     """4x4 square, U=4, beta=2, L=20, symmetric split, seed 0: the full
     200-sweep run with measurements on every slice."""
-    _log("trajectory square 4x4 200 sweeps")
-    _trajectory("square", 4, 4, 4.0, 2.0, 10, "sym", 0, 200)
+    _log(f"trajectory square 4x4 200 sweeps chunk={chunk}")
+    _trajectory("square", 4, 4, 4.0, 2.0, 10, "sym", 0, 200, chunk=chunk)
 
 
 def test_sweep_parity_honeycomb_ragged():
@@ -82,18 +87,30 @@ def test_sweep_parity_honeycomb_ragged():
     _trajectory("honeycomb", 6, 6, 4.0, 4.0, 10, "asym", 5, 3)
 
 
-def test_sweep_parity_gauss_field():
-    _log("trajectory gauss 4x4 2 sweeps")
-    _trajectory("square", 4, 4, 4.0, 2.0, 5, "sym", 2, 2, field="gauss")
+@pytest.mark.parametrize("chunk", [True, False])
+def test_sweep_parity_gauss_field(chunk):
+    _log(f"trajectory gauss 4x4 2 sweeps chunk={chunk}")
+    _trajectory("square", 4, 4, 4.0, 2.0, 5, "sym", 2, 2, field="gauss", chunk=chunk)
 
 
-def test_sweep_parity_four_valued_field():
+@pytest.mark.parametrize("chunk", [True, False])
+def test_sweep_parity_four_valued_field(chunk):
     """The four-valued field of Eq. (HS_squares) (three-way proposals, gamma in
     the weight): 4x4 square for 20 sweeps and the ragged N = 72 honeycomb."""
-    _log("trajectory four-valued field square 4x4 20 sweeps")
-    _trajectory("square", 4, 4, 4.0, 2.0, 10, "sym", 4, 20, field="ising4")
-    _log("trajectory four-valued field honeycomb 6x6 2 sweeps")
-    _trajectory("honeycomb", 6, 6, 4.0, 4.0, 10, "asym", 8, 2, field="ising4")
+    _log(f"trajectory four-valued field square 4x4 20 sweeps chunk={chunk}")
+    _trajectory("square", 4, 4, 4.0, 2.0, 10, "sym", 4, 20, field="ising4", chunk=chunk)
+    _log(f"trajectory four-valued field honeycomb 6x6 2 sweeps chunk={chunk}")
+    _trajectory("honeycomb", 6, 6, 4.0, 4.0, 10, "asym", 8, 2, field="ising4", chunk=chunk)
+
+
+def test_sweep_parity_chunk_kernel_sizes():
+    """The chunk kernel at its largest lattice, 8x8 square (n = 64, 4 x 4 tiles
+    of 16), symmetric split, and on the ragged 5x5 honeycomb (n = 50) with the
+    asymmetric split, two sweeps each."""
+    _log("trajectory square 8x8 2 sweeps (chunk kernel)")
+    _trajectory("square", 8, 8, 4.0, 2.0, 10, "sym", 3, 2)
+    _log("trajectory honeycomb 5x5 3 sweeps (chunk kernel)")
+    _trajectory("honeycomb", 5, 5, 4.0, 2.0, 5, "asym", 6, 3)
 
 
 def test_sweep_parity_honeycomb12_one_sweep():
