@@ -1,8 +1,9 @@
 """Fock-space evaluation of Trotterised Hubbard expectation values (a pin).
 
 Independent of the oracle: the repulsive Hubbard Hamiltonian
-H = sum_sigma c^+ K c - h sum_i (n_i,up - n_i,dn) + (U/2) sum_i (n_i - 1)^2
-(h an optional Zeeman field, part of the one-body H_T) is built as a 4^N-dimensional
+H = sum_sigma c^+ K_sigma c - h sum_i (n_i,up - n_i,dn) + (U/2) sum_i (n_i - 1)^2
+(h an optional Zeeman field, part of the one-body H_T; K_up = K_dn = K unless
+a separate down-spin hopping is given) is built as a 4^N-dimensional
 matrix from Jordan-Wigner fermions, and the symmetric Trotter product
 S = exp(-dtau H_T/2) exp(-dtau H_U) exp(-dtau H_T/2) of the section
 "The partition function" gives
@@ -23,8 +24,9 @@ def _expmh(H, x):
 
 
 class Fock:
-    def __init__(self, K, U, h=0.0):
+    def __init__(self, K, U, h=0.0, K_dn=None):
         K = np.asarray(K, dtype=float)
+        Ks = (K, K if K_dn is None else np.asarray(K_dn, dtype=float))
         self.N = N = K.shape[0]
         nm = 2 * N
         dim = 2 ** nm
@@ -46,8 +48,8 @@ class Fock:
         for s in range(2):
             for i in range(N):
                 for j in range(N):
-                    if K[i, j] != 0.0:
-                        HT += K[i, j] * self.c[mode(i, s)].T @ self.c[mode(j, s)]
+                    if Ks[s][i, j] != 0.0:
+                        HT += Ks[s][i, j] * self.c[mode(i, s)].T @ self.c[mode(j, s)]
         self.n = [[self.c[mode(i, s)].T @ self.c[mode(i, s)] for s in range(2)] for i in range(N)]
         for i in range(N):
             HT -= h * (self.n[i][0] - self.n[i][1])
@@ -71,6 +73,9 @@ class Fock:
 
     def kinetic(self):
         return self.HT / self.N
+
+    def potential(self):
+        return self.HU / self.N
 
     def sz(self, i):
         return 0.5 * (self.n[i][0] - self.n[i][1])
