@@ -124,6 +124,35 @@ dqmc_status dqmc_query_sizes(const dqmc_model* model, dqmc_sizes* out);
 dqmc_status dqmc_create(const dqmc_model* model, const double* K, const int32_t* vertex_site,
                         dqmc_ctx** out);
 
+/* The M_z form with two flavours and two Green's functions (section "The
+ * M_z-Hubbard model on a square lattice", Eq. (hubbard_Mz)): per site one
+ * vertex coupled to n_up - n_dn, the field acting with +coupling on the up
+ * flavour and -coupling on the down flavour, each flavour with its own
+ * hopping matrix (K_up, K_dn: n*n host arrays, symmetric, copied), so a
+ * Zeeman field, a chemical potential or spin-dependent hopping.  The weight
+ * prod(vertex factors) det(1 + B_up(beta,0)) det(1 + B_dn(beta,0)) is real
+ * but may be negative (the sign problem): the chain samples its modulus
+ * (a flip is accepted iff u < |R|, R = vertex factor ratio x r_up x r_dn) and
+ * carries the sign relative to the starting configuration (dqmc_read_phase:
+ * out3_host[0] = the sign, [1] = 0, [2] = 2 once a negative sign was seen,
+ * else 0).  The bins hold sign-weighted sums with the sum of the signs in
+ * place of the count, of D = <n_up n_dn>, E_kin = (1/n) sum_f (Tr K_f -
+ * Tr(K_f G_f)) and E_pot = (U/2)(1/n) sum_i <(n_i - 1)^2> per site (the
+ * original frame).  The flavours are held as one 2n x 2n block-diagonal
+ * system: G is that image (4 n^2 doubles, G_up in the upper-left block, G_dn
+ * in the lower-right), the field stays n_slices*n doubles; take the buffer
+ * sizes from dqmc_ctx_sizes.  model: alpha = 0 and n_col = 1 (DQMC_E_ARG
+ * otherwise), field kinds Ising (the exact identity, coupling lambda with
+ * cosh(lambda) = exp(dtau U / 2)), four-valued or Gaussian; n <= 64
+ * (DQMC_E_UNSUPPORTED otherwise).  Single chains; the sweep with measure
+ * bit 0 and dqmc_green_scratch are built, every other entry point returns
+ * DQMC_E_UNSUPPORTED. */
+dqmc_status dqmc_create_mz(const dqmc_model* model, const double* K_up, const double* K_dn, dqmc_ctx** out);
+
+/* Byte sizes of the device buffers of a created context (those of
+ * dqmc_query_sizes for the model; the two-flavour context needs these). */
+dqmc_status dqmc_ctx_sizes(const dqmc_ctx* ctx, dqmc_sizes* out);
+
 /* Bind caller-owned device buffers (sizes from dqmc_query_sizes, 256-byte
  * aligned) and the hipStream_t on which all later work is enqueued (NULL = the
  * null stream).  Computes exp(+-dtau K) and exp(+-dtau K/2) on the device. */

@@ -55,6 +55,9 @@ SIGNATURES = {
     "dqmc_read_bins": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "dqmc_read_phase": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "dqmc_set_chunk_kernel": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "dqmc_create_mz": (ctypes.c_int, [ctypes.POINTER(Model), ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.POINTER(ctypes.c_void_p)]),
+    "dqmc_ctx_sizes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "dqmc_batch_set_chunk_kernel": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "dqmc_reset_bins": (ctypes.c_int, [ctypes.c_void_p]),
     "dqmc_green_scratch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),

@@ -47,24 +47,32 @@ def _dev_buffer(nbytes, device):
 class Chain:
     """One Markov chain bound to caller-owned torch device buffers."""
 
-    def __init__(self, model: Model, K: np.ndarray, device="cuda", stream=None):
+    def __init__(self, model: Model, K: np.ndarray, device="cuda", stream=None, K_dn=None):
+        """K_dn given: the M_z form with two flavours (K the up flavour's
+        hopping, K_dn the down flavour's)."""
         lib = _lib.load()
         self.lib = lib
         self.model = model
         self.N = model.n
-        # a complex field's matrices are held as their real 2n x 2n images
+        # a complex field's matrices, and the two flavours, are held as real
+        # 2n x 2n images
         self.complex = model.field == _lib.FIELD_ISING4_IMAG
-        self.Nd = 2 * self.N if self.complex else self.N
+        self.flavours = 2 if K_dn is not None else 1
+        self.Nd = 2 * self.N if (self.complex or self.flavours == 2) else self.N
         self.L = model.n_slices
         self.eq_shape = (0, 0)    # (n_cells, norb) once eq_setup has run; the library refuses reads before
         self.td_norb = 0          # orbitals per cell once td_setup has run; likewise
-        sizes = Sizes()
-        check(lib.dqmc_query_sizes(ctypes.byref(model), ctypes.byref(sizes)))
-        self.sizes = sizes
         Kc = np.ascontiguousarray(K, dtype=np.float64)
         ctx = ctypes.c_void_p()
-        check(lib.dqmc_create(ctypes.byref(model), Kc.ctypes.data, None, ctypes.byref(ctx)))
+        if K_dn is None:
+            check(lib.dqmc_create(ctypes.byref(model), Kc.ctypes.data, None, ctypes.byref(ctx)))
+        else:
+            Kd = np.ascontiguousarray(K_dn, dtype=np.float64)
+            check(lib.dqmc_create_mz(ctypes.byref(model), Kc.ctypes.data, Kd.ctypes.data, ctypes.byref(ctx)))
         self.ctx = ctx
+        sizes = Sizes()
+        check(lib.dqmc_ctx_sizes(ctx, ctypes.byref(sizes)), ctx)
+        self.sizes = sizes
         self.device = torch.device(device)
         self.G = _dev_buffer(sizes.G, self.device).view(-1)[: self.Nd * self.Nd].view(self.Nd, self.Nd)
         self.field = _dev_buffer(sizes.field, self.device)
@@ -118,6 +126,13 @@ class Chain:
         out = np.zeros(3)
         self._chk(self.lib.dqmc_read_phase(self.ctx, out.ctypes.data))
         return complex(out[0], out[1]), float(out[2])
+
+    def green_flavours(self, image=None):
+        """(G_up, G_dn) of a two-flavour chain: the diagonal blocks of its
+        2n x 2n image (default: the chain's G)."""
+        X = self.G if image is None else image
+        n = self.N
+        return X[:n, :n], X[n:, n:]
 
     def green_complex(self, image=None) -> torch.Tensor:
         """The complex n x n matrix whose real 2n x 2n image is `image` (default:

@@ -23,6 +23,7 @@
 #include "correlations.h"
 #include "complex.h"
 #include "chunk.h"
+#include "flavours.h"
 
 namespace {
 
@@ -47,6 +48,10 @@ struct dqmc_ctx {
   // field sites per slice; the complex field (cplx) runs on the real 2 Nf x 2 Nf
   // images of its complex matrices, so there N = 2 Nf
   int Nf = 0, cplx = 0;
+  // two flavours (the M_z form with two Green's functions) on the 2 Nf x 2 Nf
+  // block-diagonal system, the field expanded to [s, -s] per slice in field_x
+  int nfl = 1;
+  double* field_x = nullptr;
   double trK_field = 0.0;     // trace of the n x n hopping matrix (complex estimators)
   double* phase = nullptr;    // complex field: [re, im, max |phase - 1|] per chain
   std::vector<double> K;
@@ -195,6 +200,7 @@ size_t layout_chain(dqmc_ctx* c, double* base) {
   P(c->Mgj, 64 * N);
   P(c->Uinv, uinv_size(c));
   P(c->field_alt, (size_t)c->L * N);
+  P(c->field_x, c->nfl == 2 ? (size_t)c->L * N : 0);
   P(c->norms, N);
   double* pv = nullptr;
   double* mv = nullptr;
@@ -348,6 +354,12 @@ inline double* field_row(dqmc_ctx* c, int tau) {
   return base + (size_t)(tau - 1) * c->Nf;
 }
 
+// The N values that scale the rows or columns of slice tau's exp(V): the
+// field row, or for two flavours its expansion [s, -s].
+inline double* scale_row(dqmc_ctx* c, int tau) {
+  return c->nfl == 2 ? c->field_x + (size_t)(tau - 1) * c->N : field_row(c, tau);
+}
+
 // G(tau) = B_tau G(tau-1) B_tau^-1 = diag(v) E G Einv diag(1/v), v = exp(coupling s_tau),
 // from Gcur into dst (which may be Gcur itself)
 dqmc_status wrap_up(dqmc_ctx* c, int tau, double* dst) {
@@ -355,8 +367,8 @@ dqmc_status wrap_up(dqmc_ctx* c, int tau, double* dst) {
   if (dqmc_status s = gemm(c, gemm_args(N, N, N, c->E, N, 0, c->Gcur, N, 0, c->T1, N))) return s;
   GemmArgs g = gemm_args(N, N, N, c->T1, N, 0, c->Einv, N, 0, dst, N);
   c->Gcur = dst;
-  g.rs = field_row(c, tau); g.rs_mode = SC_EXP; g.rs_coef = c->m.coupling;
-  g.cs = field_row(c, tau); g.cs_mode = SC_EXP; g.cs_coef = -c->m.coupling;
+  g.rs = scale_row(c, tau); g.rs_mode = SC_EXP; g.rs_coef = c->m.coupling;
+  g.cs = scale_row(c, tau); g.cs_mode = SC_EXP; g.cs_coef = -c->m.coupling;
   return gemm(c, g);
 }
 
@@ -364,10 +376,10 @@ dqmc_status wrap_up(dqmc_ctx* c, int tau, double* dst) {
 dqmc_status wrap_down(dqmc_ctx* c, int tau, double* dst) {
   const int N = c->N;
   GemmArgs g1 = gemm_args(N, N, N, c->Gcur, N, 0, c->E, N, 0, c->T1, N);
-  g1.ks = field_row(c, tau); g1.ks_mode = SC_EXP; g1.ks_coef = c->m.coupling;
+  g1.ks = scale_row(c, tau); g1.ks_mode = SC_EXP; g1.ks_coef = c->m.coupling;
   if (dqmc_status s = gemm(c, g1)) return s;
   GemmArgs g2 = gemm_args(N, N, N, c->Einv, N, 0, c->T1, N, 0, dst, N);
-  g2.ks = field_row(c, tau); g2.ks_mode = SC_EXP; g2.ks_coef = -c->m.coupling;
+  g2.ks = scale_row(c, tau); g2.ks_mode = SC_EXP; g2.ks_coef = -c->m.coupling;
   if (dqmc_status s = gemm(c, g2)) return s;
   c->Gcur = dst;
   return DQMC_OK;
@@ -522,6 +534,9 @@ dqmc_status set_lds_limits(dqmc_ctx* c) {
     HIPCHK(hipFuncSetAttribute(fns[chunk_np(c->N) / 16 - 1], hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)chunk_lds(c->N, 1)));
   }
+  if (c->nfl == 2)
+    HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(k_fl2_update_slice),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)fl2_update_lds(kFl2MaxN)));
   if (c->cplx)
     HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(k_cupdate_slice),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)cupdate_lds(kCMaxN)));
@@ -586,7 +601,7 @@ dqmc_status right_step(dqmc_ctx* c, UDVp in, int lo, int hi, UDVp out) {
   int b = 0;
   for (int tau = lo + 1; tau <= hi; ++tau) {
     GemmArgs g = gemm_args(N, N, N, c->E, N, 0, src, N, 0, bufs[b], N);
-    if (!c->cplx) { g.rs = field_row(c, tau); g.rs_mode = SC_EXP; g.rs_coef = c->m.coupling; }
+    if (!c->cplx) { g.rs = scale_row(c, tau); g.rs_mode = SC_EXP; g.rs_coef = c->m.coupling; }
     if (tau == hi) { g.cs = in.D; g.cs_mode = SC_VAL; }
     if (dqmc_status s = gemm(c, g)) return s;
     // complex field: B_tau = diag(exp(i c eta)) E on the image, a row rotation
@@ -613,7 +628,7 @@ dqmc_status left_step(dqmc_ctx* c, UDVp in, int lo, int hi, UDVp out) {
       src = c->S[5];
     }
     GemmArgs g = gemm_args(N, N, N, c->E, N, 0, src, N, 0, bufs[b], N);
-    if (!c->cplx) { g.ks = field_row(c, tau); g.ks_mode = SC_EXP; g.ks_coef = c->m.coupling; }
+    if (!c->cplx) { g.ks = scale_row(c, tau); g.ks_mode = SC_EXP; g.ks_coef = c->m.coupling; }
     if (tau == lo + 1) { g.cs = in.D; g.cs_mode = SC_VAL; }
     if (dqmc_status s = gemm(c, g)) return s;
     src = bufs[b];
@@ -800,7 +815,7 @@ constexpr int kChunkMinChains = 16;
 
 bool use_chunks(const dqmc_ctx* c, int meas) {
   const bool on = c->fused == 1 || (c->fused == -1 && c->nch >= kChunkMinChains);
-  return on && !c->cplx && c->N <= kChunkMaxN && !(meas & 4) &&
+  return on && !c->cplx && c->nfl == 1 && c->N <= kChunkMaxN && !(meas & 4) &&
          !(c->timing && c->timing_kernel == DQMC_KERNEL_BLOCK_UPDATE);
 }
 
@@ -1027,6 +1042,84 @@ dqmc_status csweep_once(dqmc_ctx* c, int meas) {
   }
   hipLaunchKernelGGL(k_finish_sweep, gridc(c, 1), dim3(64), 0, c->stream, c->prec_hist, hist, c->prec_tot,
                      c->m.prec_threshold, c->counters, c->err_flag, c->cs);
+  HIPCHK(hipGetLastError());
+  return DQMC_OK;
+}
+
+// ------------------------------------------------ two-flavour sweep --
+// The sweep of Algorithm 1 for the M_z form with two Green's functions on
+// the 2n x 2n block-diagonal system: the wraps and the stabilisation of the
+// one-flavour sweep (with the expanded field rows), the flips of both
+// flavours in one workgroup per chain (k_fl2_update_slice), the sign-weighted
+// estimators (k_fl2_measure).
+dqmc_status fl2update(dqmc_ctx* c, int tau, int dir) {
+  hipLaunchKernelGGL(k_fl2_update_slice, gridc(c, 1), dim3(256), fl2_update_lds(c->Nf), c->stream, c->G, c->Nf,
+                     field_row(c, tau), scale_row(c, tau), tau, (unsigned long long)dir, c->m.coupling,
+                     (int)c->m.field, c->m.prop_width, field4_table(), c->counters, c->phase, c->cs);
+  HIPCHK(hipGetLastError());
+  return DQMC_OK;
+}
+
+dqmc_status fl2measure(dqmc_ctx* c) {
+  const int N = c->N;
+  const bool sym = c->m.trotter == DQMC_TROTTER_SYM;
+  if (sym)
+    if (dqmc_status s = gemm(c, gemm_args(N, N, N, c->Eh, N, 0, c->G, N, 0, c->T1, N))) return s;
+  hipLaunchKernelGGL(k_fl2_measure, gridc(c, 1), dim3(256), 0, c->stream, c->G, sym ? c->T1 : nullptr, c->Ehinv,
+                     c->Kd, c->Nf, sym ? 1 : 0, c->trK, c->m.u_int, c->phase, c->bins, c->err_flag, c->cs);
+  HIPCHK(hipGetLastError());
+  return DQMC_OK;
+}
+
+dqmc_status fl2sweep_once(dqmc_ctx* c, int meas) {
+  const int L = c->L, nw = c->nw, nk = c->nk;
+  int hist = 0;
+  c->row_alt.clear();
+  c->Gcur = c->G;
+  for (int tau = 1; tau <= L; ++tau) {
+    if (dqmc_status s = wrap_up(c, tau, c->G)) return s;
+    if (dqmc_status s = fl2update(c, tau, 0)) return s;
+    if (tau % nw == 0) {
+      const int k = tau / nw;
+      if (dqmc_status s = timing_begin(c, DQMC_KERNEL_STABILISE)) return s;
+      UDVp prev = (k == 1) ? c->uid : c->slot(k - 1);
+      if (dqmc_status s = right_step(c, prev, tau - nw, tau, c->cur)) return s;
+      UDVp left = (k == nk) ? c->uid : c->slot(k);
+      if (dqmc_status s = merge(c, c->cur, left, c->Gs, nullptr)) return s;
+      if (dqmc_status s = copy_udv(c, c->slot(k), c->cur)) return s;
+      if (dqmc_status s = stabilise(c, hist++)) return s;
+      if (dqmc_status s = timing_end(c, DQMC_KERNEL_STABILISE)) return s;
+    }
+    if (meas & 1)
+      if (dqmc_status s = fl2measure(c)) return s;
+  }
+  for (int tau = L; tau >= 1; --tau) {
+    if (dqmc_status s = fl2update(c, tau, 1)) return s;
+    if (meas & 1)
+      if (dqmc_status s = fl2measure(c)) return s;
+    if (dqmc_status s = wrap_down(c, tau, c->G)) return s;
+    if ((tau - 1) % nw == 0) {
+      const int k = (tau - 1) / nw;
+      if (dqmc_status s = timing_begin(c, DQMC_KERNEL_STABILISE)) return s;
+      UDVp prev = (k + 1 == nk) ? c->uid : c->slot(k + 1);
+      if (dqmc_status s = left_step(c, prev, tau - 1, tau - 1 + nw, c->cur)) return s;
+      UDVp right = (k == 0) ? c->uid : c->slot(k);
+      if (dqmc_status s = merge(c, right, c->cur, c->Gs, nullptr)) return s;
+      if (dqmc_status s = copy_udv(c, c->slot(k), c->cur)) return s;
+      if (dqmc_status s = stabilise(c, hist++)) return s;
+      if (dqmc_status s = timing_end(c, DQMC_KERNEL_STABILISE)) return s;
+    }
+  }
+  hipLaunchKernelGGL(k_finish_sweep, gridc(c, 1), dim3(64), 0, c->stream, c->prec_hist, hist, c->prec_tot,
+                     c->m.prec_threshold, c->counters, c->err_flag, c->cs);
+  HIPCHK(hipGetLastError());
+  return DQMC_OK;
+}
+
+dqmc_status expand_field(dqmc_ctx* c) {
+  if (c->nfl != 2) return DQMC_OK;
+  hipLaunchKernelGGL(k_expand_field, gridc(c, grid1((size_t)c->L * c->Nf)), dim3(256), 0, c->stream, c->field,
+                     c->field_x, c->L, c->Nf, c->cs);
   HIPCHK(hipGetLastError());
   return DQMC_OK;
 }
@@ -1371,6 +1464,57 @@ dqmc_status dqmc_create(const dqmc_model* m, const double* K, const int32_t* ver
   return DQMC_OK;
 }
 
+dqmc_status dqmc_create_mz(const dqmc_model* m, const double* K_up, const double* K_dn, dqmc_ctx** out) {
+  if (!out) return DQMC_E_ARG;
+  *out = nullptr;
+  if (check_model(m) != DQMC_OK || !K_up || !K_dn) return DQMC_E_ARG;
+  if (m->field == DQMC_FIELD_ISING4_IMAG || m->alpha != 0.0 || m->n_col != 1) return DQMC_E_ARG;
+  const int n = m->n;
+  if (n > kFl2MaxN) return DQMC_E_UNSUPPORTED;
+  for (const double* K : {K_up, K_dn})
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        const double a = K[(size_t)i * n + j], b = K[(size_t)j * n + i];
+        if (!std::isfinite(a) || a != b) return DQMC_E_ARG;
+      }
+  dqmc_ctx* c = new (std::nothrow) dqmc_ctx();
+  if (!c) return DQMC_E_NOMEM;
+  c->m = *m;
+  const int Nd = 2 * n;
+  c->N = Nd; c->Nf = n; c->nfl = 2;
+  c->L = m->n_slices; c->nw = m->n_wrap; c->nk = m->n_slices / m->n_wrap;
+  c->nb = 32;
+  c->K.assign((size_t)Nd * Nd, 0.0);
+  double tr = 0.0, n1 = 0.0;
+  for (int f = 0; f < 2; ++f) {
+    const double* K = f == 0 ? K_up : K_dn;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) c->K[(size_t)(i + f * n) * Nd + j + f * n] = K[(size_t)i * n + j];
+    for (int j = 0; j < n; ++j) {
+      double col = 0.0;
+      for (int i = 0; i < n; ++i) col += std::fabs(K[(size_t)i * n + j]);
+      n1 = std::max(n1, col);
+      tr += K[(size_t)j * n + j];
+    }
+  }
+  c->trK = tr; c->trK_field = tr; c->normK1 = n1;
+  *out = c;
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_ctx_sizes(const dqmc_ctx* c, dqmc_sizes* out) {
+  if (!c || !out) return DQMC_E_ARG;
+  dqmc_ctx tmp;
+  tmp.N = c->N; tmp.Nf = c->Nf; tmp.cplx = c->cplx; tmp.nfl = c->nfl;
+  tmp.L = c->L; tmp.nw = c->nw; tmp.nk = c->nk;
+  const size_t N = c->N;
+  out->G = N * N * sizeof(double);
+  out->field = (size_t)c->L * c->Nf * sizeof(double);
+  out->slots = (size_t)(c->nk + 1) * (2 * N * N + N) * sizeof(double);
+  out->work = layout_work(&tmp, false) * sizeof(double);
+  return DQMC_OK;
+}
+
 }  // extern "C"
 
 namespace {
@@ -1432,6 +1576,7 @@ dqmc_status dqmc_set_state(dqmc_ctx* c, const double* field_host, uint64_t sweep
       return fail(c, DQMC_E_ARG, "field values must be +-1 (Ising), eta(l) (four-valued) or finite (Gaussian)");
   }
   HIPCHK(hipMemcpyAsync(c->field, field_host, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  if (dqmc_status s = expand_field(c)) return s;
   unsigned long long ctr = sweep_counter;
   HIPCHK(hipMemcpyAsync(c->counters + 2, &ctr, sizeof(ctr), hipMemcpyHostToDevice, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
@@ -1461,6 +1606,7 @@ dqmc_status dqmc_random_field(dqmc_ctx* c) {
   hipLaunchKernelGGL(k_random_field, gridc(c, grid1(n)), dim3(256), 0, c->stream, c->field, c->L, c->Nf,
                      c->counters, kind, field4_table(), c->cs);
   HIPCHK(hipGetLastError());
+  if (dqmc_status s = expand_field(c)) return s;
   if (dqmc_status s = fill_small(c, reinterpret_cast<double*>(c->counters + 2), 1, 0.0)) return s;
   if (dqmc_status s = fill_small(c, reinterpret_cast<double*>(c->counters + 4), 1, 0.0)) return s;
   HIPCHK(hipStreamSynchronize(c->stream));
@@ -1495,13 +1641,16 @@ dqmc_status dqmc_sweep(dqmc_ctx* c, int32_t n_sweeps, int32_t meas, dqmc_stats* 
   if (!c->bound || !c->initialized || c->poisoned) return fail(c, DQMC_E_STATE, "context not initialised");
   if (meas & ~15) return fail(c, DQMC_E_ARG, "unknown measurement flags");
   if (c->cplx && (meas & ~1)) return fail(c, DQMC_E_UNSUPPORTED, "a complex field measures the estimators of bit 0 only");
+  if (c->nfl == 2 && (meas & ~1))
+    return fail(c, DQMC_E_UNSUPPORTED, "the two-flavour form measures the estimators of bit 0 only");
   if ((meas & 8) && (!(meas & 2) || c->eq_norb < 1 || td_corr_size(c) == 0))
     return fail(c, DQMC_E_STATE, "time-displaced correlations need bit 1 and dqmc_eq_setup");
   if ((meas & 2) && c->td_norb < 1) return fail(c, DQMC_E_STATE, "time-displaced measurement not set up");
   if ((meas & 4) && c->eq_norb < 1) return fail(c, DQMC_E_STATE, "lattice-resolved correlations not set up");
   const auto t0 = std::chrono::steady_clock::now();
   for (int s = 0; s < n_sweeps; ++s)
-    if (dqmc_status r = c->cplx ? csweep_once(c, meas) : sweep_once(c, meas)) return r;
+    if (dqmc_status r = c->cplx ? csweep_once(c, meas) : (c->nfl == 2 ? fl2sweep_once(c, meas) : sweep_once(c, meas)))
+      return r;
   if (dqmc_status r = read_flag(c)) return r;
   const auto t1 = std::chrono::steady_clock::now();
   if (st) {
@@ -1533,7 +1682,7 @@ dqmc_status dqmc_reset_bins(dqmc_ctx* c) {
 
 dqmc_status dqmc_read_phase(dqmc_ctx* c, double* out3) {
   if (!c || !out3) return DQMC_E_ARG;
-  if (!c->cplx) return fail(c, DQMC_E_UNSUPPORTED, "only a complex field carries a phase");
+  if (!c->cplx && c->nfl != 2) return fail(c, DQMC_E_UNSUPPORTED, "only a complex field or two flavours carry a phase");
   if (!c->bound) return fail(c, DQMC_E_STATE, "not bound");
   HIPCHK(hipMemcpyAsync(out3, c->phase, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
@@ -1592,7 +1741,7 @@ dqmc_status dqmc_ratio(dqmc_ctx* c, int32_t tau, int32_t site, double s_new, dou
   if (c->nch != 1) return fail(c, DQMC_E_UNSUPPORTED, "single chains only");
   if (tau > c->L || site >= c->N) return fail(c, DQMC_E_ARG, "tau or site out of range");
   if (!field_value_ok(c->m.field, s_new)) return fail(c, DQMC_E_ARG, "not a value of the field");
-  if (c->cplx) return fail(c, DQMC_E_UNSUPPORTED, "not built for a complex field");
+  if (c->cplx || c->nfl == 2) return fail(c, DQMC_E_UNSUPPORTED, "not built for a complex field or two flavours");
   if (dqmc_status s = dqmc_green_scratch(c, tau, c->Gs)) return s;
   hipLaunchKernelGGL(k_ratio, dim3(1), dim3(64), 0, c->stream, c->Gs, c->N, site,
                      c->field + (size_t)(tau - 1) * c->N, s_new, c->m.coupling, c->m.alpha, c->m.n_col,
@@ -1606,7 +1755,7 @@ dqmc_status dqmc_ratio(dqmc_ctx* c, int32_t tau, int32_t site, double s_new, dou
 dqmc_status dqmc_logdet(dqmc_ctx* c, double* logdet) {
   if (!c || !logdet) return DQMC_E_ARG;
   if (!c->bound) return fail(c, DQMC_E_STATE, "not bound");
-  if (c->cplx) return fail(c, DQMC_E_UNSUPPORTED, "not built for a complex field");
+  if (c->cplx || c->nfl == 2) return fail(c, DQMC_E_UNSUPPORTED, "not built for a complex field or two flavours");
   UDVp left = c->uid;
   UDVp lb[2] = {c->hA, c->hB};
   int q = 0;
@@ -1623,7 +1772,7 @@ dqmc_status dqmc_logdet(dqmc_ctx* c, double* logdet) {
 
 dqmc_status dqmc_grad_logdet(dqmc_ctx* c, double* grad_dev, double* prec) {
   if (!c || !grad_dev) return fail(c, DQMC_E_ARG, "null argument");
-  if (c->cplx) return fail(c, DQMC_E_UNSUPPORTED, "not built for a complex field");
+  if (c->cplx || c->nfl == 2) return fail(c, DQMC_E_UNSUPPORTED, "not built for a complex field or two flavours");
   if (!c->bound || !c->initialized || c->poisoned) return fail(c, DQMC_E_STATE, "context not initialised");
   if (dqmc_status s = grad_pass(c)) return s;
   HIPCHK(hipMemcpyAsync(grad_dev, c->grad, (size_t)c->L * c->N * sizeof(double), hipMemcpyDeviceToDevice,
@@ -1635,7 +1784,8 @@ dqmc_status dqmc_grad_logdet(dqmc_ctx* c, double* grad_dev, double* prec) {
 
 dqmc_status dqmc_langevin(dqmc_ctx* c, double eps, int32_t n_steps) {
   if (!c || n_steps < 0 || !(eps > 0.0) || !std::isfinite(eps)) return fail(c, DQMC_E_ARG, "bad arguments");
-  if (c->m.field != DQMC_FIELD_GAUSS) return fail(c, DQMC_E_UNSUPPORTED, "Langevin steps need a Gaussian field");
+  if (c->m.field != DQMC_FIELD_GAUSS || c->nfl == 2)
+    return fail(c, DQMC_E_UNSUPPORTED, "Langevin steps need a one-flavour Gaussian field");
   if (!c->bound || !c->initialized || c->poisoned) return fail(c, DQMC_E_STATE, "context not initialised");
   for (int k = 0; k < n_steps; ++k)
     if (dqmc_status s = langevin_once(c, eps)) return s;
@@ -1664,7 +1814,7 @@ dqmc_status dqmc_set_langevin_step(dqmc_ctx* c, uint64_t step) {
 dqmc_status dqmc_td_setup(dqmc_ctx* c, int32_t norb, const int32_t* orb_of, const double* phase, int32_t n_cells) {
   if (!c || !orb_of || !phase || norb < 1 || norb > kTdMaxOrb || n_cells < 1)
     return fail(c, DQMC_E_ARG, "bad arguments");
-  if (c->cplx) return fail(c, DQMC_E_UNSUPPORTED, "not built for a complex field");
+  if (c->cplx || c->nfl == 2) return fail(c, DQMC_E_UNSUPPORTED, "not built for a complex field or two flavours");
   if (!c->bound) return fail(c, DQMC_E_STATE, "not bound");
   for (int i = 0; i < c->N; ++i) {
     if (orb_of[i] < 0 || orb_of[i] >= norb) return fail(c, DQMC_E_ARG, "orbital index out of range");
@@ -1682,7 +1832,7 @@ dqmc_status dqmc_td_setup(dqmc_ctx* c, int32_t norb, const int32_t* orb_of, cons
 dqmc_status dqmc_eq_setup(dqmc_ctx* c, int32_t L1, int32_t L2, int32_t norb, const int32_t* site, const double* sign) {
   if (!c || !site || !sign || L1 < 1 || L2 < 1 || norb < 1 || norb > kEqMaxOrb)
     return fail(c, DQMC_E_ARG, "bad arguments");
-  if (c->cplx) return fail(c, DQMC_E_UNSUPPORTED, "not built for a complex field");
+  if (c->cplx || c->nfl == 2) return fail(c, DQMC_E_UNSUPPORTED, "not built for a complex field or two flavours");
   if (!c->bound) return fail(c, DQMC_E_STATE, "not bound");
   if ((int64_t)L1 * L2 * norb != c->N) return fail(c, DQMC_E_ARG, "L1 * L2 * norb must equal the number of orbitals");
   std::vector<char> seen(c->N, 0);
@@ -2397,6 +2547,7 @@ extern "C" {
 dqmc_status dqmc_green_scratch_noalloc(dqmc_ctx* c, const double* field_dev, int32_t tau, double* G_dev,
                                        void* hip_stream) {
   if (!c || !field_dev || !G_dev || tau < 0 || tau > c->L) return fail(c, DQMC_E_ARG, "bad arguments");
+  if (c->nfl == 2) return fail(c, DQMC_E_UNSUPPORTED, "not built for two flavours");
   // a host-side context of its own: model and hopping from c, every device
   // pointer inside the static array (c's own binding, if any, is untouched)
   dqmc_ctx t;

@@ -184,3 +184,28 @@ def test_complex_field_sizes_and_refusals(lib):
     out = np.zeros(3)
     assert lib.dqmc_read_phase(ctx, out.ctypes.data) == 2
     lib.dqmc_destroy(ctx)
+
+
+def test_two_flavour_create_sizes_and_refusals(lib):
+    """Host-only: the two-flavour context holds a 2n x 2n image of G and the
+    n-site field; alpha != 0, n_col != 1 or an imaginary field are argument
+    errors, more than 64 sites unsupported, an asymmetric hopping refused."""
+    from paper_1704_00131_amd._lib import Sizes
+    K = np.zeros((16, 16))
+    K[0, 1] = K[1, 0] = -1.0
+    m = _model(alpha=0.0, n_col=1)
+    ctx = ctypes.c_void_p()
+    assert lib.dqmc_create_mz(ctypes.byref(m), K.ctypes.data, (0.5 * K).ctypes.data, ctypes.byref(ctx)) == 0
+    s = Sizes()
+    assert lib.dqmc_ctx_sizes(ctx, ctypes.byref(s)) == 0
+    assert s.G == 32 * 32 * 8 and s.field == 20 * 16 * 8
+    lib.dqmc_destroy(ctx)
+    for bad in (dict(alpha=-0.5, n_col=1), dict(alpha=0.0, n_col=2), dict(alpha=0.0, n_col=1, field="ising4_imag")):
+        mb = _model(**bad)
+        assert lib.dqmc_create_mz(ctypes.byref(mb), K.ctypes.data, K.ctypes.data, ctypes.byref(ctx)) == 1
+    Ka = K.copy()
+    Ka[2, 3] = 1.0
+    assert lib.dqmc_create_mz(ctypes.byref(m), K.ctypes.data, Ka.ctypes.data, ctypes.byref(ctx)) == 1
+    big = _model(n=65, alpha=0.0, n_col=1)
+    K65 = np.zeros((65, 65))
+    assert lib.dqmc_create_mz(ctypes.byref(big), K65.ctypes.data, K65.ctypes.data, ctypes.byref(ctx)) == 2
