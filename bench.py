@@ -42,7 +42,8 @@ Prints one JSON line with
              (10x10, beta = 4); the time-displaced pass alone; the 12x12 chain
              with the paper's four-valued field, with the lattice-resolved
              equal-time correlations, and in the M_z form with a Zeeman field;
-             the complex (imaginary-coupling) formulation on the 8x8 square.
+             the complex (imaginary-coupling) formulation and the two-flavour
+             M_z form (chemical potential, t_up != t_dn) on the 8x8 square.
 """
 import argparse
 import hashlib
@@ -425,6 +426,34 @@ def bench_complex(torch, pa):
             "precision_phase": dev}
 
 
+def bench_two_flavour(torch, pa):
+    """The M_z form with two flavours and two Green's functions on the 8x8
+    square (n = 64, an image of 128): t_up = 1, t_dn = 0.7, chemical potential
+    0.5, U = 4, beta = 4, L = 40: three timed sweeps after one untimed, with the
+    average sign of the measurements."""
+    import numpy as np
+
+    from inputs import square_lattice
+    T = square_lattice(8, 8).K
+    n = T.shape[0]
+    K_up, K_dn = T - 0.5 * np.eye(n), 0.7 * T - 0.5 * np.eye(n)
+    beta, dtau, U = 4.0, 0.1, 4.0
+    m = pa.make_model(n, beta, dtau, 10, pa.hubbard_coupling(U, dtau), U=U, trotter="sym", seed=0, alpha=0.0,
+                      n_col=1)
+    ch = pa.Chain(m, K_up, K_dn=K_dn)
+    ch.random_field().init()
+    ch.sweep(1, measure=True)
+    ch.reset_bins()
+    st0 = ch.sweep(0, measure=True)
+    dt, st = _sync_time(torch, lambda: ch.sweep(3, measure=True))
+    bins = ch.read_bins()
+    ch.close()
+    props = st.proposals - st0.proposals
+    return {"n": n, "L": m.n_slices, "ms_per_sweep": 1e3 * dt / 3, "updates_per_s": props / dt,
+            "acceptance": (st.accepted - st0.accepted) / max(1, props), "prec_max": st.prec_max,
+            "average_sign": bins[3] / (3 * 2 * m.n_slices), "double_occupancy": bins[0] / bins[3]}
+
+
 def bench_correlations(torch, pa):
     """The honeycomb 12x12 chain of the headline workload with the
     lattice-resolved equal-time correlations (Green, SpinZ, SpinXY, Den by
@@ -458,7 +487,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--profile-extra", choices=["honeycomb12", "batched", "gradient", "time_displaced",
-                                                "four_valued", "correlations", "zeeman", "complex"],
+                                                "four_valued", "correlations", "zeeman", "complex",
+                                                "two_flavour"],
                     help="run only this extra workload and print its figures (for rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -476,7 +506,8 @@ def main():
     if args.profile_extra:
         fn = {"honeycomb12": bench_honeycomb12, "batched": bench_batched, "gradient": bench_gradient,
               "time_displaced": bench_time_displaced, "four_valued": bench_four_valued,
-              "correlations": bench_correlations, "zeeman": bench_zeeman, "complex": bench_complex}
+              "correlations": bench_correlations, "zeeman": bench_zeeman, "complex": bench_complex,
+              "two_flavour": bench_two_flavour}
         print(json.dumps({args.profile_extra: fn[args.profile_extra](torch, pa)}))
         return
 
@@ -553,7 +584,8 @@ def main():
                                    "time_displaced": bench_time_displaced(torch, pa),
                                    "four_valued": bench_four_valued(torch, pa),
                                    "correlations": bench_correlations(torch, pa),
-                                   "zeeman": bench_zeeman(torch, pa), "complex": bench_complex(torch, pa)}
+                                   "zeeman": bench_zeeman(torch, pa), "complex": bench_complex(torch, pa),
+                                   "two_flavour": bench_two_flavour(torch, pa)}
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out))
