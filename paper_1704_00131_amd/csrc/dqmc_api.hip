@@ -528,6 +528,8 @@ dqmc_status set_lds_limits(dqmc_ctx* c) {
   HIPCHK((lds_limit_qr<16, 4, 8, 12>()));
   HIPCHK((lds_limit_qr<8, 4, 8, 16>()));
   HIPCHK(gemm64_set_lds());
+  HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(k_accum_q), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)(sizeof(double) * 16 * (size_t)c->N)));
   if (!c->cplx && c->N <= kChunkMaxN) {
     const void* fns[] = {reinterpret_cast<const void*>(k_chunk<1>), reinterpret_cast<const void*>(k_chunk<2>),
                          reinterpret_cast<const void*>(k_chunk<3>), reinterpret_cast<const void*>(k_chunk<4>)};
@@ -564,19 +566,11 @@ dqmc_status qr_udv(dqmc_ctx* c, double* M, const double* T_in, UDVp out) {
     double* VT = c->VTall + (size_t)j0 * N;
     if (dqmc_status s = launch_qr_panel(c, Ap, j0, nbw, V, VT)) return s;
   }
-  // explicit Q by backward accumulation of the block reflectors
-  hipLaunchKernelGGL(k_set_identity, gridc(c, grid1((size_t)N * N)), dim3(256), 0, c->stream, out.Q, N, N, c->cs);
+  // explicit Q by backward accumulation of the block reflectors, every
+  // 16-column slab through all panels in one launch
+  hipLaunchKernelGGL(k_accum_q, gridc(c, (unsigned)((N + 15) / 16)), dim3(256), sizeof(double) * 16 * (size_t)N,
+                     c->stream, c->Vall, c->VTall, out.Q, N, nb, c->cs);
   HIPCHK(hipGetLastError());
-  const int last = ((N - 1) / nb) * nb;
-  for (int j0 = last; j0 >= 0; j0 -= nb) {
-    const int nbw = std::min(nb, N - j0), h = N - j0;
-    double* V = c->Vall + (size_t)j0 * N;
-    double* VT = c->VTall + (size_t)j0 * N;
-    double* Qs = out.Q + (size_t)j0 * N + j0;
-    hipLaunchKernelGGL(k_apply_wy, gridc(c, (unsigned)((h + 15) / 16)), dim3(256), 0, c->stream, VT, V, nbw, Qs, N,
-                       h, h, nbw, c->cs, c->cs);
-    HIPCHK(hipGetLastError());
-  }
   hipLaunchKernelGGL(k_build_rt, gridc(c, grid1((size_t)N * N)), dim3(256), 0, c->stream, Ap, c->piv, N, c->Rt,
                      out.D, c->err_flag, c->cs);
   HIPCHK(hipGetLastError());

@@ -218,6 +218,44 @@ __device__ __forceinline__ void apply_wy_slab(const double* P, const double* S, 
   }
 }
 
+// Explicit Q of a QR factorisation in one launch: Q = H_0 H_1 ... H_last I
+// by backward accumulation, every workgroup one 16-column slab of Q (grid
+// (ceil(n / 16), chains)) held in LDS (n x 16 doubles, dynamic) from the
+// identity columns to the end.  The block reflector of the panel at column
+// j0 acts on rows j0.. of the slab (apply_wy_slab with (VT, V) of that
+// panel, stored h x nbw at Vall + j0 n); the slab's columns left of j0 are
+// still identity columns then (only later panels in this order touch them)
+// and come out unchanged, and panels starting right of the slab are skipped.
+__global__ __launch_bounds__(256) void k_accum_q(const double* Vall, const double* VTall, double* Q, int n, int nb,
+                                                 size_t cs) {
+  extern __shared__ double qs[];
+  __shared__ double zp[4][2][4][64];
+  __shared__ double Zs[32][17];
+  {
+    const size_t co = (size_t)blockIdx.y * cs;
+    Vall += co; VTall += co; Q += co;
+  }
+  const int tid = threadIdx.x;
+  const int c0 = blockIdx.x * 16, ncol = min(16, n - c0);
+  for (int e = tid; e < n * 16; e += 256) {
+    const int r = e >> 4, c = e & 15;
+    qs[e] = (c < ncol && r == c0 + c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int last = ((n - 1) / nb) * nb;
+  for (int j0 = last; j0 >= 0; j0 -= nb) {
+    if (j0 > c0 + ncol - 1) continue;   // uniform
+    const int nbw = min(nb, n - j0), h = n - j0;
+    apply_wy_slab(VTall + (size_t)j0 * n, Vall + (size_t)j0 * n, nbw, qs + (size_t)j0 * 16, 16, h, ncol, nbw, 0,
+                  zp, Zs);
+    __syncthreads();
+  }
+  for (int e = tid; e < n * 16; e += 256) {
+    const int r = e >> 4, c = e & 15;
+    if (c < ncol) Q[(size_t)r * n + c0 + c] = qs[e];
+  }
+}
+
 // One launch of apply_wy_slab per 16 columns of C (grid (slabs, chains)).
 __global__ __launch_bounds__(256) void k_apply_wy(const double* P, const double* S, int ldps, double* C, int ldc,
                                                   int h, int ncol, int nbw, size_t cs_ps, size_t cs_c) {
