@@ -653,12 +653,15 @@ dqmc_status lu_solve(dqmc_ctx* c, double* XA, int nrhs, int ld, double* logdet) 
     q.ncols = ncols;
     if (dqmc_status st = launch_lu_step(c, XA, ld, q)) return st;
   }
-  // back substitution: the diagonal blocks' inverses, then every 16-column
-  // slab of the right-hand sides through the whole block recursion at once
-  const int nblk = (N + nb - 1) / nb;
-  hipLaunchKernelGGL(k_lu_diag_inv, gridc(c, (unsigned)nblk), dim3(256), 0, c->stream, XA, N, ld, nb, c->Uinv, c->cs);
+  // back substitution: the inverses of U's 32 x 32 diagonal blocks (U is
+  // upper triangular, so any diagonal block is; 32 rows per step halve the
+  // dependent steps of 16-column panels), then every 16-column slab of the
+  // right-hand sides through the whole block recursion at once
+  constexpr int bs = 32;
+  const int nblk = (N + bs - 1) / bs;
+  hipLaunchKernelGGL(k_lu_diag_inv, gridc(c, (unsigned)nblk), dim3(256), 0, c->stream, XA, N, ld, bs, c->Uinv, c->cs);
   hipLaunchKernelGGL(k_lu_back, gridc(c, (unsigned)((nrhs + kBackCols - 1) / kBackCols)), dim3(256), 0, c->stream, XA,
-                     N, ld, nb, nrhs, c->Uinv, c->cs);
+                     N, ld, bs, nrhs, c->Uinv, c->cs);
   HIPCHK(hipGetLastError());
   if (logdet) {
     hipLaunchKernelGGL(k_logabs_diag, gridc(c, 1), dim3(256), 0, c->stream, XA, N, ld, logdet, c->cs);
