@@ -13,4 +13,4 @@ follows; where the paper is silent the reading taken is stated in the
 docstring.
 """
 from . import philox, hubbard, stable, sweep, measure, exact_small, gradient, timedisplaced  # noqa: F401
-from . import complex_field, mz_flavours  # noqa: F401
+from . import complex_field, mz_flavours, vertices  # noqa: F401
