@@ -142,7 +142,8 @@ class VertexModel(hubbard.Model):
         s = field[tau - 1, k]
         up = field[tau % self.L, k]
         dn = field[(tau - 2) % self.L, k]
-        loc = self.Kt * (up + dn) + self.dtJ * sum(field[tau - 1, j] for j in self.nbr[k])
+        # with a single slice the spin's temporal bond is to itself: a constant
+        loc = (self.Kt * (up + dn) if self.L > 1 else 0.0) + self.dtJ * sum(field[tau - 1, j] for j in self.nbr[k])
         return float(np.exp(-2.0 * s * loc))
 
 

@@ -244,3 +244,20 @@ def test_chain_samples_the_weight():
     q = np.array([np.exp(vx.log_weight(m, f)) for f in fields])
     q /= q.sum()
     assert np.sum((counts - n * q) ** 2 / (n * q)) / (q.size - 1) > 5.0
+
+
+@pytest.mark.parametrize("L", [1, 2, 3])
+def test_s0_ratio_equals_the_action_difference(L):
+    """The local S0 ratio of a flip equals exp(S0(C) - S0(C')) of the whole
+    action (periodic in tau) for every spin and slice, also with one slice,
+    where the spin's temporal bond joins it to itself and does not change."""
+    m = vx.bond_ising_model(4, [(0, 1), (1, 2), (2, 3)], 1.0, 2.0, 0.6, 0.7, 0.45, 0.3 * L, 0.3, 1,
+                            pairs=[(0, 1), (1, 2), (0, 2)])
+    rng = np.random.default_rng(L)
+    f = np.where(rng.random((m.L, m.M)) < 0.5, 1.0, -1.0)
+    for tau in range(1, m.L + 1):
+        for k in range(m.M):
+            g = f.copy()
+            g[tau - 1, k] = -g[tau - 1, k]
+            want = np.exp(m.S0(f) - m.S0(g))
+            assert abs(m.s0_ratio(f, tau, k) - want) < 1e-13 * want
