@@ -454,6 +454,35 @@ def bench_two_flavour(torch, pa):
             "average_sign": bins[3] / (3 * 2 * m.n_slices), "double_occupancy": bins[0] / bins[3]}
 
 
+def bench_vertices(torch, pa):
+    """General operator vertices: the bond-Ising example of Eq.
+    (hubbard_sun_Ising) on the 8x8 square (n = 64): an Ising spin on each of
+    the 128 bonds coupled to the bond hopping (g = -dtau xi, xi = 0.5) with
+    transverse field h = 1 and a coupling J = 0.2 between bonds that share a
+    site, then the Hubbard U = 4 on the 64 sites through the two-valued field
+    (192 vertices per slice), beta = 4, L = 40: three timed sweeps after one
+    untimed."""
+    from inputs import bonds_of, bonds_sharing_a_site, square_lattice
+    lat = square_lattice(8, 8)
+    beta, dtau, U, xi = 4.0, 0.1, 4.0, 0.5
+    bonds = bonds_of(lat.K)
+    lam = pa.hubbard_coupling(U, dtau)
+    vs = [(b, [[0.0, 1.0], [1.0, 0.0]], -dtau * xi, 0.0, True) for b in bonds]
+    vs += [((i,), [[1.0]], lam, -0.5, False) for i in range(lat.n)]
+    pairs = bonds_sharing_a_site(bonds)
+    m = pa.make_model(lat.n, beta, dtau, 10, 0.0, U=U, trotter="sym", seed=0, alpha=0.0, n_col=2)
+    ch = pa.Chain(m, lat.K, vertices=vs, h=1.0, J=0.2, pairs=pairs)
+    ch.random_field().init()
+    ch.sweep(1, measure=True)
+    st0 = ch.sweep(0, measure=True)
+    dt, st = _sync_time(torch, lambda: ch.sweep(3, measure=True))
+    ch.close()
+    props = st.proposals - st0.proposals
+    return {"n": lat.n, "vertices": len(vs), "L": m.n_slices, "ms_per_sweep": 1e3 * dt / 3,
+            "updates_per_s": props / dt, "acceptance": (st.accepted - st0.accepted) / max(1, props),
+            "prec_max": st.prec_max}
+
+
 def bench_correlations(torch, pa):
     """The honeycomb 12x12 chain of the headline workload with the
     lattice-resolved equal-time correlations (Green, SpinZ, SpinXY, Den by
@@ -488,7 +517,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--profile-extra", choices=["honeycomb12", "batched", "gradient", "time_displaced",
                                                 "four_valued", "correlations", "zeeman", "complex",
-                                                "two_flavour"],
+                                                "two_flavour", "vertices"],
                     help="run only this extra workload and print its figures (for rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -507,7 +536,7 @@ def main():
         fn = {"honeycomb12": bench_honeycomb12, "batched": bench_batched, "gradient": bench_gradient,
               "time_displaced": bench_time_displaced, "four_valued": bench_four_valued,
               "correlations": bench_correlations, "zeeman": bench_zeeman, "complex": bench_complex,
-              "two_flavour": bench_two_flavour}
+              "two_flavour": bench_two_flavour, "vertices": bench_vertices}
         print(json.dumps({args.profile_extra: fn[args.profile_extra](torch, pa)}))
         return
 
@@ -585,7 +614,8 @@ def main():
                                    "four_valued": bench_four_valued(torch, pa),
                                    "correlations": bench_correlations(torch, pa),
                                    "zeeman": bench_zeeman(torch, pa), "complex": bench_complex(torch, pa),
-                                   "two_flavour": bench_two_flavour(torch, pa)}
+                                   "two_flavour": bench_two_flavour(torch, pa),
+                                   "vertices": bench_vertices(torch, pa)}
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out))

@@ -149,8 +149,57 @@ dqmc_status dqmc_create(const dqmc_model* model, const double* K, const int32_t*
  * DQMC_E_UNSUPPORTED. */
 dqmc_status dqmc_create_mz(const dqmc_model* model, const double* K_up, const double* K_dn, dqmc_ctx** out);
 
+/* One operator vertex (section "Definition of the Hamiltonian", table
+ * "operator"): X = P^T O P on n_orb = |P| orbitals orb[0..n_orb-1] (1 or 2,
+ * distinct), O a real symmetric n_orb x n_orb matrix (row-major in O[0..3];
+ * for n_orb = 1 only O[0] is read), so exp(g s X) = P^T exp(g s O) P +
+ * (1 - P^T P).  ising = 0: a two-valued HS field of Eq. (general_ham_v),
+ * s = +-1, weight factor exp(n_col g alpha s); ising = 1: an Ising spin
+ * Z_k of Eq. (general_ham_i), whose own dynamics enters through S0. */
+typedef struct {
+  int32_t n_orb;
+  int32_t orb[2];
+  int32_t ising;
+  double g;
+  double alpha;
+  double O[4];
+} dqmc_vertex;
+
+/* General operator vertices and Ising spins with their own action
+ * (Eqs. (general_ham_v), (general_ham_i) and (partition_2), section
+ * "Sampling of e^{-S_{0,I}}").  The slice propagator sampled is
+ * B_tau = E_0 E_1 ... E_{M-1} exp(-dtau K), E_k = exp(g_k s_{k,tau} X_k), the
+ * weight exp(-S0) exp(n_col sum g_k alpha_k s_{k,tau}) det(1 + B(beta,0))^n_col
+ * with, for the Ising spins (transverse field h > 0 and coupling J between
+ * the listed pairs), exp(-S0) = prod exp(Kt s_{k,tau} s_{k,tau+1})
+ * prod_pairs exp(dtau J s_{k,tau} s_{k',tau}), Kt = -ln(tanh(dtau h)) / 2,
+ * periodic in tau.  The flips of a slice take its vertices in a fixed order:
+ * upward M-1 down to 0, downward 0 up to M-1, each in the frame where E_k is
+ * the leftmost factor of the slice (G <- E_k G E_k^-1 before it in the
+ * upward pass, G <- E_k^-1 G E_k after it in the downward pass); a flip
+ * s -> -s with delta = exp(-2 g s O) - 1 has the ratio
+ * det(1 + delta (1 - G)_PP)^n_col exp(-2 n_col g alpha s) times the ratio of
+ * exp(-S0), is accepted iff u < R, and updates G <- G - G[:,P] (1 + delta
+ * (1 - G)_PP)^-1 delta (1 - G)[P,:].  K: n*n host array, symmetric, copied.
+ * vertices: n_vertices (= M) host records, copied; pairs: n_pairs pairs of
+ * Ising vertex indices (2 n_pairs int32).  The field is [n_slices][M],
+ * +-1 per vertex; G is n x n.  model: field kind Ising (DQMC_E_ARG
+ * otherwise); coupling and alpha are ignored (per vertex here), u_int enters
+ * the estimator E_pot = u_int D only.  n <= 64, M <= 512, n_orb 1 or 2 and
+ * n_pairs <= 1024 (DQMC_E_UNSUPPORTED otherwise); an O that is not symmetric, an orbital out
+ * of range, a pair that is not two distinct Ising vertices, or h <= 0 with
+ * an Ising vertex is DQMC_E_ARG.  Single chains; take the buffer sizes from
+ * dqmc_ctx_sizes.  The sweep with measure bit 0 (the estimators of the
+ * one-flavour sweep on G(tau)), dqmc_green_scratch and dqmc_logdet are
+ * built; dqmc_ratio, the gradient, Langevin, the correlation set-ups and
+ * the allocation-free recomputation return DQMC_E_UNSUPPORTED. */
+dqmc_status dqmc_create_vertices(const dqmc_model* model, const double* K, int32_t n_vertices,
+                                 const dqmc_vertex* vertices, double h, double J, int32_t n_pairs,
+                                 const int32_t* pairs, dqmc_ctx** out);
+
 /* Byte sizes of the device buffers of a created context (those of
- * dqmc_query_sizes for the model; the two-flavour context needs these). */
+ * dqmc_query_sizes for the model; the two-flavour and vertex contexts need
+ * these). */
 dqmc_status dqmc_ctx_sizes(const dqmc_ctx* ctx, dqmc_sizes* out);
 
 /* Bind caller-owned device buffers (sizes from dqmc_query_sizes, 256-byte

@@ -6,5 +6,5 @@ the method's arithmetic (no Hubbard-Stratonovich constants, no matrix
 exponentials, no Green's functions), so that the oracle and the GPU path stay
 independent of each other.
 """
-from .lattices import Lattice, square_lattice, honeycomb_lattice  # noqa: F401
+from .lattices import Lattice, bonds_of, bonds_sharing_a_site, honeycomb_lattice, square_lattice  # noqa: F401
 from .workloads import WORKLOADS, Workload, batched_chain_layout  # noqa: F401

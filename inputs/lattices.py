@@ -57,6 +57,20 @@ class Lattice:
         return np.where((i1 + i2) % 2 == 0, 1.0, -1.0)
 
 
+def bonds_of(K: np.ndarray):
+    """The bonds of a hopping matrix: pairs (a, b), a < b, with K[a, b] != 0,
+    in row-major order (the structure of the bond vertices of the
+    transverse-Ising example, Eq. (hubbard_sun_Ising))."""
+    n = K.shape[0]
+    return [(a, b) for a in range(n) for b in range(a + 1, n) if K[a, b] != 0.0]
+
+
+def bonds_sharing_a_site(bonds):
+    """Pairs (i, j), i < j, of bond indices whose bonds share a site."""
+    return [(i, j) for i in range(len(bonds)) for j in range(i + 1, len(bonds))
+            if set(bonds[i]) & set(bonds[j])]
+
+
 def _cell(i1, i2, L1, L2):
     return (i1 % L1) + L1 * (i2 % L2)
 

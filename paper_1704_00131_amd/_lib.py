@@ -35,6 +35,11 @@ class Buffers(ctypes.Structure):
                 ("slots", ctypes.c_void_p), ("work", ctypes.c_void_p)]
 
 
+class Vertex(ctypes.Structure):
+    _fields_ = [("n_orb", ctypes.c_int32), ("orb", ctypes.c_int32 * 2), ("ising", ctypes.c_int32),
+                ("g", ctypes.c_double), ("alpha", ctypes.c_double), ("O", ctypes.c_double * 4)]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("proposals", ctypes.c_uint64), ("accepted", ctypes.c_uint64),
                 ("prec_mean", ctypes.c_double), ("prec_max", ctypes.c_double),
@@ -58,6 +63,9 @@ SIGNATURES = {
     "dqmc_create_mz": (ctypes.c_int, [ctypes.POINTER(Model), ctypes.c_void_p, ctypes.c_void_p,
                                       ctypes.POINTER(ctypes.c_void_p)]),
     "dqmc_ctx_sizes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "dqmc_create_vertices": (ctypes.c_int, [ctypes.POINTER(Model), ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                            ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_void_p,
+                                            ctypes.POINTER(ctypes.c_void_p)]),
     "dqmc_batch_set_chunk_kernel": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "dqmc_reset_bins": (ctypes.c_int, [ctypes.c_void_p]),
     "dqmc_green_scratch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),

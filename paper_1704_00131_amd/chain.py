@@ -40,6 +40,26 @@ def make_model(n, beta, dtau, n_wrap, coupling, U=0.0, field="ising", trotter="s
                  prec_threshold=prec_threshold, prop_width=prop_width, seed=seed)
 
 
+def make_vertices(vertices) -> ctypes.Array:
+    """An array of vertex records from (orbitals, O, g, alpha, ising) tuples:
+    X = P^T O P on one or two orbitals, a two-valued HS field (ising False)
+    or an Ising spin with its own action (ising True)."""
+    arr = (_lib.Vertex * len(vertices))()
+    for k, (orbs, O, g, alpha, ising) in enumerate(vertices):
+        orbs = [int(o) for o in orbs]
+        Om = np.asarray(O, dtype=np.float64).reshape(len(orbs), len(orbs))
+        arr[k].n_orb = len(orbs)
+        arr[k].orb[0] = orbs[0]
+        arr[k].orb[1] = orbs[1] if len(orbs) > 1 else 0
+        arr[k].ising = 1 if ising else 0
+        arr[k].g = float(g)
+        arr[k].alpha = float(alpha)
+        flat = list(Om.ravel()) + [0.0] * (4 - Om.size)
+        for a in range(4):
+            arr[k].O[a] = float(flat[a])
+    return arr
+
+
 def _dev_buffer(nbytes, device):
     return torch.empty(max(1, (nbytes + 7) // 8), dtype=torch.float64, device=device)
 
@@ -47,9 +67,13 @@ def _dev_buffer(nbytes, device):
 class Chain:
     """One Markov chain bound to caller-owned torch device buffers."""
 
-    def __init__(self, model: Model, K: np.ndarray, device="cuda", stream=None, K_dn=None):
+    def __init__(self, model: Model, K: np.ndarray, device="cuda", stream=None, K_dn=None, vertices=None,
+                 h=0.0, J=0.0, pairs=()):
         """K_dn given: the M_z form with two flavours (K the up flavour's
-        hopping, K_dn the down flavour's)."""
+        hopping, K_dn the down flavour's).  vertices given: general operator
+        vertices ((orbitals, O, g, alpha, ising) tuples, see make_vertices),
+        the Ising spins' transverse field h and coupling J between the
+        listed pairs of vertex indices; the field has one value per vertex."""
         lib = _lib.load()
         self.lib = lib
         self.model = model
@@ -60,11 +84,18 @@ class Chain:
         self.flavours = 2 if K_dn is not None else 1
         self.Nd = 2 * self.N if (self.complex or self.flavours == 2) else self.N
         self.L = model.n_slices
+        self.Mf = len(vertices) if vertices is not None else self.N   # field values per slice
         self.eq_shape = (0, 0)    # (n_cells, norb) once eq_setup has run; the library refuses reads before
         self.td_norb = 0          # orbitals per cell once td_setup has run; likewise
         Kc = np.ascontiguousarray(K, dtype=np.float64)
         ctx = ctypes.c_void_p()
-        if K_dn is None:
+        if vertices is not None:
+            vx = make_vertices(vertices)
+            pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+            check(lib.dqmc_create_vertices(ctypes.byref(model), Kc.ctypes.data, len(vertices), ctypes.addressof(vx),
+                                           float(h), float(J), pr.shape[0], pr.ctypes.data if pr.size else None,
+                                           ctypes.byref(ctx)))
+        elif K_dn is None:
             check(lib.dqmc_create(ctypes.byref(model), Kc.ctypes.data, None, ctypes.byref(ctx)))
         else:
             Kd = np.ascontiguousarray(K_dn, dtype=np.float64)
@@ -90,12 +121,12 @@ class Chain:
         return self
 
     def set_state(self, field: np.ndarray, sweep_counter: int = 0):
-        f = np.ascontiguousarray(field, dtype=np.float64).reshape(self.L, self.N)
+        f = np.ascontiguousarray(field, dtype=np.float64).reshape(self.L, self.Mf)
         self._chk(self.lib.dqmc_set_state(self.ctx, f.ctypes.data, sweep_counter))
         return self
 
     def get_state(self):
-        f = np.empty((self.L, self.N))
+        f = np.empty((self.L, self.Mf))
         ctr = ctypes.c_uint64()
         self._chk(self.lib.dqmc_get_state(self.ctx, f.ctypes.data, ctypes.byref(ctr)))
         return f, ctr.value

@@ -24,6 +24,7 @@
 #include "complex.h"
 #include "chunk.h"
 #include "flavours.h"
+#include "vertices.h"
 
 namespace {
 
@@ -53,6 +54,12 @@ struct dqmc_ctx {
   int nfl = 1;
   double* field_x = nullptr;
   double trK_field = 0.0;     // trace of the n x n hopping matrix (complex estimators)
+  // general operator vertices (nvx > 0): the field is [L][nvx], one value per
+  // vertex; records of kVxRec doubles and the Ising partner lists (shared)
+  int nvx = 0, nvx_nbr = 0;
+  std::vector<double> vx_rec, vx_nbr;
+  double *vtab = nullptr, *vnbr = nullptr;
+  double vx_Kt = 0.0, vx_dtJ = 0.0;
   double* phase = nullptr;    // complex field: [re, im, max |phase - 1|] per chain
   std::vector<double> K;
   double trK = 0.0, normK1 = 0.0;
@@ -181,6 +188,10 @@ size_t layout_shared(dqmc_ctx* c, double* base) {
   double* es = nullptr;
   P(es, N / 2 + 1);
   if (base) c->eq_site = reinterpret_cast<int*>(es);
+  if (c->nvx > 0) {
+    P(c->vtab, (size_t)c->nvx * kVxRec);
+    P(c->vnbr, (size_t)std::max(1, c->nvx_nbr));
+  }
   if (base) { c->shared_lo = base; c->shared_hi = base + l.off; }
   return l.off;
 }
@@ -542,6 +553,9 @@ dqmc_status set_lds_limits(dqmc_ctx* c) {
   if (c->cplx)
     HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(k_cupdate_slice),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)cupdate_lds(kCMaxN)));
+  if (c->nvx)
+    HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(k_vx_slice), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)vx_slice_lds(kVxMaxN, kVxMaxM, kVxMaxNbr)));
   return DQMC_OK;
 }
 
@@ -587,6 +601,16 @@ dqmc_status crot(dqmc_ctx* c, double* dst, const double* src, int tau, double co
   return DQMC_OK;
 }
 
+// The vertex factors of slice tau on the rows (k_vx_rows): order 0 applies
+// exp(V_tau), order 1 its transpose.
+dqmc_status vx_rows(dqmc_ctx* c, const double* src, double* dst, int tau, int order) {
+  hipLaunchKernelGGL(k_vx_rows, gridc(c, 1), dim3(256), vx_rows_lds(c->N, c->nvx), c->stream, src, dst, c->N, c->vtab,
+                     c->nvx,
+                     c->field + (size_t)(tau - 1) * c->Nf, order, c->cs);
+  HIPCHK(hipGetLastError());
+  return DQMC_OK;
+}
+
 // Right step: UDV of B(hi,0) from that of B(lo,0): M = (B_hi ... B_lo+1 Q) D.
 dqmc_status right_step(dqmc_ctx* c, UDVp in, int lo, int hi, UDVp out) {
   const int N = c->N;
@@ -595,9 +619,12 @@ dqmc_status right_step(dqmc_ctx* c, UDVp in, int lo, int hi, UDVp out) {
   int b = 0;
   for (int tau = lo + 1; tau <= hi; ++tau) {
     GemmArgs g = gemm_args(N, N, N, c->E, N, 0, src, N, 0, bufs[b], N);
-    if (!c->cplx) { g.rs = scale_row(c, tau); g.rs_mode = SC_EXP; g.rs_coef = c->m.coupling; }
+    if (!c->cplx && !c->nvx) { g.rs = scale_row(c, tau); g.rs_mode = SC_EXP; g.rs_coef = c->m.coupling; }
     if (tau == hi) { g.cs = in.D; g.cs_mode = SC_VAL; }
     if (dqmc_status s = gemm(c, g)) return s;
+    // general vertices: B_tau = exp(V_tau) exp(-dtau K), the vertex factors on the rows
+    if (c->nvx)
+      if (dqmc_status s = vx_rows(c, bufs[b], bufs[b], tau, 0)) return s;
     // complex field: B_tau = diag(exp(i c eta)) E on the image, a row rotation
     if (c->cplx)
       if (dqmc_status s = crot(c, bufs[b], bufs[b], tau, c->m.coupling, 0.0)) return s;
@@ -621,8 +648,13 @@ dqmc_status left_step(dqmc_ctx* c, UDVp in, int lo, int hi, UDVp out) {
       if (dqmc_status s = crot(c, c->S[5], src, tau, -c->m.coupling, 0.0)) return s;
       src = c->S[5];
     }
+    // general vertices: B_tau^T = exp(-dtau K) exp(V_tau)^T, the vertex factors first
+    if (c->nvx) {
+      if (dqmc_status s = vx_rows(c, src, c->S[5], tau, 1)) return s;
+      src = c->S[5];
+    }
     GemmArgs g = gemm_args(N, N, N, c->E, N, 0, src, N, 0, bufs[b], N);
-    if (!c->cplx) { g.ks = scale_row(c, tau); g.ks_mode = SC_EXP; g.ks_coef = c->m.coupling; }
+    if (!c->cplx && !c->nvx) { g.ks = scale_row(c, tau); g.ks_mode = SC_EXP; g.ks_coef = c->m.coupling; }
     if (tau == lo + 1) { g.cs = in.D; g.cs_mode = SC_VAL; }
     if (dqmc_status s = gemm(c, g)) return s;
     src = bufs[b];
@@ -812,7 +844,7 @@ constexpr int kChunkMinChains = 16;
 
 bool use_chunks(const dqmc_ctx* c, int meas) {
   const bool on = c->fused == 1 || (c->fused == -1 && c->nch >= kChunkMinChains);
-  return on && !c->cplx && c->nfl == 1 && c->N <= kChunkMaxN && !(meas & 4) &&
+  return on && !c->cplx && c->nfl == 1 && !c->nvx && c->N <= kChunkMaxN && !(meas & 4) &&
          !(c->timing && c->timing_kernel == DQMC_KERNEL_BLOCK_UPDATE);
 }
 
@@ -1095,6 +1127,73 @@ dqmc_status fl2sweep_once(dqmc_ctx* c, int meas) {
     if (meas & 1)
       if (dqmc_status s = fl2measure(c)) return s;
     if (dqmc_status s = wrap_down(c, tau, c->G)) return s;
+    if ((tau - 1) % nw == 0) {
+      const int k = (tau - 1) / nw;
+      if (dqmc_status s = timing_begin(c, DQMC_KERNEL_STABILISE)) return s;
+      UDVp prev = (k + 1 == nk) ? c->uid : c->slot(k + 1);
+      if (dqmc_status s = left_step(c, prev, tau - 1, tau - 1 + nw, c->cur)) return s;
+      UDVp right = (k == 0) ? c->uid : c->slot(k);
+      if (dqmc_status s = merge(c, right, c->cur, c->Gs, nullptr)) return s;
+      if (dqmc_status s = copy_udv(c, c->slot(k), c->cur)) return s;
+      if (dqmc_status s = stabilise(c, hist++)) return s;
+      if (dqmc_status s = timing_end(c, DQMC_KERNEL_STABILISE)) return s;
+    }
+  }
+  hipLaunchKernelGGL(k_finish_sweep, gridc(c, 1), dim3(64), 0, c->stream, c->prec_hist, hist, c->prec_tot,
+                     c->m.prec_threshold, c->counters, c->err_flag, c->cs);
+  HIPCHK(hipGetLastError());
+  return DQMC_OK;
+}
+
+// ------------------------------------------------ general-vertex sweep --
+// The sweep of Algorithm 1 with general operator vertices and Ising spins
+// (section "Definition of the Hamiltonian"): the kinetic wraps as plain
+// products, the flips of a slice with the partial wraps E_k G E_k^-1 in one
+// workgroup per chain (k_vx_slice), the stabilisation with the vertex factors
+// applied by k_vx_rows, the estimators of the one-flavour sweep.
+dqmc_status vx_wrap(dqmc_ctx* c, bool up) {
+  const int N = c->N;
+  const double* A = up ? c->E : c->Einv;
+  const double* B = up ? c->Einv : c->E;
+  if (dqmc_status s = gemm(c, gemm_args(N, N, N, A, N, 0, c->G, N, 0, c->T1, N))) return s;
+  return gemm(c, gemm_args(N, N, N, c->T1, N, 0, B, N, 0, c->G, N));
+}
+
+dqmc_status vx_slice(dqmc_ctx* c, int tau, int dir) {
+  hipLaunchKernelGGL(k_vx_slice, gridc(c, 1), dim3(256), vx_slice_lds(c->N, c->nvx, c->nvx_nbr), c->stream, c->G,
+                     c->N, c->field, c->L, tau, (unsigned long long)dir, c->vtab, c->vnbr, c->nvx_nbr, c->nvx,
+                     c->vx_Kt, c->vx_dtJ, c->m.n_col, c->counters, c->cs);
+  HIPCHK(hipGetLastError());
+  return DQMC_OK;
+}
+
+dqmc_status vx_sweep_once(dqmc_ctx* c, int meas) {
+  const int L = c->L, nw = c->nw, nk = c->nk;
+  int hist = 0;
+  c->row_alt.clear();
+  c->Gcur = c->G;
+  for (int tau = 1; tau <= L; ++tau) {
+    if (dqmc_status s = vx_wrap(c, true)) return s;
+    if (dqmc_status s = vx_slice(c, tau, 0)) return s;
+    if (tau % nw == 0) {
+      const int k = tau / nw;
+      if (dqmc_status s = timing_begin(c, DQMC_KERNEL_STABILISE)) return s;
+      UDVp prev = (k == 1) ? c->uid : c->slot(k - 1);
+      if (dqmc_status s = right_step(c, prev, tau - nw, tau, c->cur)) return s;
+      UDVp left = (k == nk) ? c->uid : c->slot(k);
+      if (dqmc_status s = merge(c, c->cur, left, c->Gs, nullptr)) return s;
+      if (dqmc_status s = copy_udv(c, c->slot(k), c->cur)) return s;
+      if (dqmc_status s = stabilise(c, hist++)) return s;
+      if (dqmc_status s = timing_end(c, DQMC_KERNEL_STABILISE)) return s;
+    }
+    if (meas & 1)
+      if (dqmc_status s = measure(c)) return s;
+  }
+  for (int tau = L; tau >= 1; --tau) {
+    if (meas & 1)
+      if (dqmc_status s = measure(c)) return s;
+    if (dqmc_status s = vx_slice(c, tau, 1)) return s;
+    if (dqmc_status s = vx_wrap(c, false)) return s;
     if ((tau - 1) % nw == 0) {
       const int k = (tau - 1) / nw;
       if (dqmc_status s = timing_begin(c, DQMC_KERNEL_STABILISE)) return s;
@@ -1499,10 +1598,84 @@ dqmc_status dqmc_create_mz(const dqmc_model* m, const double* K_up, const double
   return DQMC_OK;
 }
 
+dqmc_status dqmc_create_vertices(const dqmc_model* m, const double* K, int32_t n_vertices, const dqmc_vertex* v,
+                                 double h, double J, int32_t n_pairs, const int32_t* pairs, dqmc_ctx** out) {
+  if (!out) return DQMC_E_ARG;
+  *out = nullptr;
+  if (check_model(m) != DQMC_OK || !K || !v || n_vertices < 1 || n_pairs < 0 || (n_pairs > 0 && !pairs))
+    return DQMC_E_ARG;
+  if (m->field != DQMC_FIELD_ISING) return DQMC_E_ARG;
+  if (!std::isfinite(h) || h < 0.0 || !std::isfinite(J)) return DQMC_E_ARG;
+  const int n = m->n, M = n_vertices;
+  if (n > kVxMaxN || M > kVxMaxM) return DQMC_E_UNSUPPORTED;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      const double a = K[(size_t)i * n + j], b = K[(size_t)j * n + i];
+      if (!std::isfinite(a) || a != b) return DQMC_E_ARG;
+    }
+  bool any_ising = false;
+  for (int k = 0; k < M; ++k) {
+    const dqmc_vertex& x = v[k];
+    if (x.n_orb < 1 || x.n_orb > 2) return DQMC_E_UNSUPPORTED;
+    for (int a = 0; a < x.n_orb; ++a)
+      if (x.orb[a] < 0 || x.orb[a] >= n) return DQMC_E_ARG;
+    if (x.n_orb == 2 && x.orb[0] == x.orb[1]) return DQMC_E_ARG;
+    if (x.ising != 0 && x.ising != 1) return DQMC_E_ARG;
+    if (!std::isfinite(x.g) || !std::isfinite(x.alpha)) return DQMC_E_ARG;
+    for (int a = 0; a < 4; ++a)
+      if (!std::isfinite(x.O[a])) return DQMC_E_ARG;
+    if (x.n_orb == 2 && x.O[1] != x.O[2]) return DQMC_E_ARG;
+    any_ising = any_ising || x.ising;
+  }
+  // an Ising spin with a transverse field needs h > 0 (Kt = -ln tanh(dtau h) / 2)
+  if (any_ising && !(h > 0.0)) return DQMC_E_ARG;
+  std::vector<std::vector<int>> nbr(M);
+  for (int p = 0; p < n_pairs; ++p) {
+    const int a = pairs[2 * p], b = pairs[2 * p + 1];
+    if (a < 0 || a >= M || b < 0 || b >= M || a == b || !v[a].ising || !v[b].ising) return DQMC_E_ARG;
+    nbr[a].push_back(b);
+    nbr[b].push_back(a);
+  }
+  if (2 * (int64_t)n_pairs > kVxMaxNbr) return DQMC_E_UNSUPPORTED;
+  dqmc_ctx* c = new (std::nothrow) dqmc_ctx();
+  if (!c) return DQMC_E_NOMEM;
+  c->m = *m;
+  c->m.coupling = 0.0;
+  c->N = n; c->Nf = M; c->nvx = M;
+  c->L = m->n_slices; c->nw = m->n_wrap; c->nk = m->n_slices / m->n_wrap;
+  c->nb = 32;
+  c->K.assign(K, K + (size_t)n * n);
+  double tr = 0.0, n1 = 0.0;
+  for (int j = 0; j < n; ++j) {
+    double col = 0.0;
+    for (int i = 0; i < n; ++i) col += std::fabs(K[(size_t)i * n + j]);
+    n1 = std::max(n1, col);
+    tr += K[(size_t)j * n + j];
+  }
+  c->trK = tr; c->trK_field = tr; c->normK1 = n1;
+  c->vx_Kt = any_ising ? -0.5 * std::log(std::tanh(m->dtau * h)) : 0.0;
+  c->vx_dtJ = m->dtau * J;
+  c->vx_rec.assign((size_t)M * kVxRec, 0.0);
+  for (int k = 0; k < M; ++k) {
+    const dqmc_vertex& x = v[k];
+    double* r = c->vx_rec.data() + (size_t)k * kVxRec;
+    r[0] = x.n_orb; r[1] = x.orb[0]; r[2] = x.n_orb == 2 ? x.orb[1] : x.orb[0]; r[3] = x.ising;
+    r[4] = x.g; r[5] = x.alpha;
+    r[6] = x.O[0]; r[7] = x.n_orb == 2 ? x.O[1] : 0.0; r[8] = x.n_orb == 2 ? x.O[2] : 0.0;
+    r[9] = x.n_orb == 2 ? x.O[3] : 0.0;
+    r[10] = (double)c->vx_nbr.size(); r[11] = (double)nbr[k].size();
+    for (int b : nbr[k]) c->vx_nbr.push_back((double)b);
+  }
+  c->nvx_nbr = (int)c->vx_nbr.size();
+  *out = c;
+  return DQMC_OK;
+}
+
 dqmc_status dqmc_ctx_sizes(const dqmc_ctx* c, dqmc_sizes* out) {
   if (!c || !out) return DQMC_E_ARG;
   dqmc_ctx tmp;
   tmp.N = c->N; tmp.Nf = c->Nf; tmp.cplx = c->cplx; tmp.nfl = c->nfl;
+  tmp.nvx = c->nvx; tmp.nvx_nbr = c->nvx_nbr;
   tmp.L = c->L; tmp.nw = c->nw; tmp.nk = c->nk;
   const size_t N = c->N;
   out->G = N * N * sizeof(double);
@@ -1522,6 +1695,13 @@ dqmc_status setup_device(dqmc_ctx* c) {
   const int N = c->N;
   if (dqmc_status s = set_lds_limits(c)) return s;
   HIPCHK(hipMemcpyAsync(c->Kd, c->K.data(), sizeof(double) * N * N, hipMemcpyHostToDevice, c->stream));
+  if (c->nvx) {
+    HIPCHK(hipMemcpyAsync(c->vtab, c->vx_rec.data(), sizeof(double) * c->vx_rec.size(), hipMemcpyHostToDevice,
+                          c->stream));
+    if (c->nvx_nbr)
+      HIPCHK(hipMemcpyAsync(c->vnbr, c->vx_nbr.data(), sizeof(double) * c->vx_nbr.size(), hipMemcpyHostToDevice,
+                            c->stream));
+  }
   if (dqmc_status s = expm(c, -c->m.dtau, c->E)) return s;
   if (dqmc_status s = expm(c, +c->m.dtau, c->Einv)) return s;
   if (dqmc_status s = expm(c, -0.5 * c->m.dtau, c->Eh)) return s;
@@ -1640,13 +1820,18 @@ dqmc_status dqmc_sweep(dqmc_ctx* c, int32_t n_sweeps, int32_t meas, dqmc_stats* 
   if (c->cplx && (meas & ~1)) return fail(c, DQMC_E_UNSUPPORTED, "a complex field measures the estimators of bit 0 only");
   if (c->nfl == 2 && (meas & ~1))
     return fail(c, DQMC_E_UNSUPPORTED, "the two-flavour form measures the estimators of bit 0 only");
+  if (c->nvx && (meas & ~1))
+    return fail(c, DQMC_E_UNSUPPORTED, "general vertices measure the estimators of bit 0 only");
   if ((meas & 8) && (!(meas & 2) || c->eq_norb < 1 || td_corr_size(c) == 0))
     return fail(c, DQMC_E_STATE, "time-displaced correlations need bit 1 and dqmc_eq_setup");
   if ((meas & 2) && c->td_norb < 1) return fail(c, DQMC_E_STATE, "time-displaced measurement not set up");
   if ((meas & 4) && c->eq_norb < 1) return fail(c, DQMC_E_STATE, "lattice-resolved correlations not set up");
   const auto t0 = std::chrono::steady_clock::now();
   for (int s = 0; s < n_sweeps; ++s)
-    if (dqmc_status r = c->cplx ? csweep_once(c, meas) : (c->nfl == 2 ? fl2sweep_once(c, meas) : sweep_once(c, meas)))
+    if (dqmc_status r = c->cplx       ? csweep_once(c, meas)
+                        : c->nfl == 2 ? fl2sweep_once(c, meas)
+                        : c->nvx      ? vx_sweep_once(c, meas)
+                                      : sweep_once(c, meas))
       return r;
   if (dqmc_status r = read_flag(c)) return r;
   const auto t1 = std::chrono::steady_clock::now();
@@ -1738,7 +1923,8 @@ dqmc_status dqmc_ratio(dqmc_ctx* c, int32_t tau, int32_t site, double s_new, dou
   if (c->nch != 1) return fail(c, DQMC_E_UNSUPPORTED, "single chains only");
   if (tau > c->L || site >= c->N) return fail(c, DQMC_E_ARG, "tau or site out of range");
   if (!field_value_ok(c->m.field, s_new)) return fail(c, DQMC_E_ARG, "not a value of the field");
-  if (c->cplx || c->nfl == 2) return fail(c, DQMC_E_UNSUPPORTED, "not built for a complex field or two flavours");
+  if (c->cplx || c->nfl == 2 || c->nvx)
+    return fail(c, DQMC_E_UNSUPPORTED, "not built for a complex field, two flavours or general vertices");
   if (dqmc_status s = dqmc_green_scratch(c, tau, c->Gs)) return s;
   hipLaunchKernelGGL(k_ratio, dim3(1), dim3(64), 0, c->stream, c->Gs, c->N, site,
                      c->field + (size_t)(tau - 1) * c->N, s_new, c->m.coupling, c->m.alpha, c->m.n_col,
@@ -1769,7 +1955,8 @@ dqmc_status dqmc_logdet(dqmc_ctx* c, double* logdet) {
 
 dqmc_status dqmc_grad_logdet(dqmc_ctx* c, double* grad_dev, double* prec) {
   if (!c || !grad_dev) return fail(c, DQMC_E_ARG, "null argument");
-  if (c->cplx || c->nfl == 2) return fail(c, DQMC_E_UNSUPPORTED, "not built for a complex field or two flavours");
+  if (c->cplx || c->nfl == 2 || c->nvx)
+    return fail(c, DQMC_E_UNSUPPORTED, "not built for a complex field, two flavours or general vertices");
   if (!c->bound || !c->initialized || c->poisoned) return fail(c, DQMC_E_STATE, "context not initialised");
   if (dqmc_status s = grad_pass(c)) return s;
   HIPCHK(hipMemcpyAsync(grad_dev, c->grad, (size_t)c->L * c->N * sizeof(double), hipMemcpyDeviceToDevice,
@@ -1811,7 +1998,8 @@ dqmc_status dqmc_set_langevin_step(dqmc_ctx* c, uint64_t step) {
 dqmc_status dqmc_td_setup(dqmc_ctx* c, int32_t norb, const int32_t* orb_of, const double* phase, int32_t n_cells) {
   if (!c || !orb_of || !phase || norb < 1 || norb > kTdMaxOrb || n_cells < 1)
     return fail(c, DQMC_E_ARG, "bad arguments");
-  if (c->cplx || c->nfl == 2) return fail(c, DQMC_E_UNSUPPORTED, "not built for a complex field or two flavours");
+  if (c->cplx || c->nfl == 2 || c->nvx)
+    return fail(c, DQMC_E_UNSUPPORTED, "not built for a complex field, two flavours or general vertices");
   if (!c->bound) return fail(c, DQMC_E_STATE, "not bound");
   for (int i = 0; i < c->N; ++i) {
     if (orb_of[i] < 0 || orb_of[i] >= norb) return fail(c, DQMC_E_ARG, "orbital index out of range");
@@ -1829,7 +2017,8 @@ dqmc_status dqmc_td_setup(dqmc_ctx* c, int32_t norb, const int32_t* orb_of, cons
 dqmc_status dqmc_eq_setup(dqmc_ctx* c, int32_t L1, int32_t L2, int32_t norb, const int32_t* site, const double* sign) {
   if (!c || !site || !sign || L1 < 1 || L2 < 1 || norb < 1 || norb > kEqMaxOrb)
     return fail(c, DQMC_E_ARG, "bad arguments");
-  if (c->cplx || c->nfl == 2) return fail(c, DQMC_E_UNSUPPORTED, "not built for a complex field or two flavours");
+  if (c->cplx || c->nfl == 2 || c->nvx)
+    return fail(c, DQMC_E_UNSUPPORTED, "not built for a complex field, two flavours or general vertices");
   if (!c->bound) return fail(c, DQMC_E_STATE, "not bound");
   if ((int64_t)L1 * L2 * norb != c->N) return fail(c, DQMC_E_ARG, "L1 * L2 * norb must equal the number of orbitals");
   std::vector<char> seen(c->N, 0);
@@ -2544,7 +2733,7 @@ extern "C" {
 dqmc_status dqmc_green_scratch_noalloc(dqmc_ctx* c, const double* field_dev, int32_t tau, double* G_dev,
                                        void* hip_stream) {
   if (!c || !field_dev || !G_dev || tau < 0 || tau > c->L) return fail(c, DQMC_E_ARG, "bad arguments");
-  if (c->nfl == 2) return fail(c, DQMC_E_UNSUPPORTED, "not built for two flavours");
+  if (c->nfl == 2 || c->nvx) return fail(c, DQMC_E_UNSUPPORTED, "not built for two flavours or general vertices");
   // a host-side context of its own: model and hopping from c, every device
   // pointer inside the static array (c's own binding, if any, is untouched)
   dqmc_ctx t;

@@ -209,3 +209,66 @@ def test_two_flavour_create_sizes_and_refusals(lib):
     big = _model(n=65, alpha=0.0, n_col=1)
     K65 = np.zeros((65, 65))
     assert lib.dqmc_create_mz(ctypes.byref(big), K65.ctypes.data, K65.ctypes.data, ctypes.byref(ctx)) == 2
+
+
+def test_vertex_create_sizes_and_refusals(lib):
+    """Host-only: the vertex context holds an n x n G and a field of one value
+    per vertex and slice; an asymmetric O, an orbital out of range, a pair
+    that is not two distinct Ising vertices, h = 0 with an Ising vertex or a
+    field kind other than Ising are argument errors; more than 64 orbitals,
+    more than 512 vertices, more than 1024 pairs or three orbitals per vertex
+    are unsupported."""
+    from paper_1704_00131_amd import make_vertices
+    from paper_1704_00131_amd._lib import Sizes
+    n = 6
+    K = np.zeros((n, n))
+    for a in range(n - 1):
+        K[a, a + 1] = K[a + 1, a] = -1.0
+    X = [[0.0, 1.0], [1.0, 0.0]]
+    good = [((a, a + 1), X, -0.05, 0.0, True) for a in range(n - 1)] + [((i,), [[1.0]], 0.7, -0.5, False)
+                                                                        for i in range(n)]
+    pairs = np.array([[0, 1], [1, 2]], dtype=np.int32)
+    m = _model(n=n, alpha=0.0)
+
+    def create(mm, vs, h=0.5, J=0.3, pr=pairs, KK=K):
+        arr = make_vertices(vs)
+        ctx = ctypes.c_void_p()
+        p = np.ascontiguousarray(pr, dtype=np.int32).reshape(-1, 2)
+        st = lib.dqmc_create_vertices(ctypes.byref(mm), KK.ctypes.data, len(vs), ctypes.addressof(arr), h, J,
+                                      p.shape[0], p.ctypes.data if p.size else None, ctypes.byref(ctx))
+        return st, ctx
+
+    st, ctx = create(m, good)
+    assert st == 0
+    s = Sizes()
+    assert lib.dqmc_ctx_sizes(ctx, ctypes.byref(s)) == 0
+    assert s.G == n * n * 8 and s.field == 20 * len(good) * 8
+    assert s.slots == 3 * (2 * n * n + n) * 8
+    lib.dqmc_destroy(ctx)
+    # HS vertices only: h is not needed
+    assert create(m, good[n - 1:], h=0.0, pr=np.zeros((0, 2)))[0] == 0
+    bad_O = list(good)
+    bad_O[0] = ((0, 1), [[0.0, 1.0], [0.5, 0.0]], -0.05, 0.0, True)
+    out_of_range = list(good)
+    out_of_range[-1] = ((n,), [[1.0]], 0.7, -0.5, False)
+    same_orb = list(good)
+    same_orb[0] = ((2, 2), X, -0.05, 0.0, True)
+    for vs, kw in ((bad_O, {}), (out_of_range, {}), (same_orb, {}), (good, dict(h=0.0)),
+                   (good, dict(pr=[[0, 0]])), (good, dict(pr=[[0, n + 1]])), (good, dict(pr=[[0, len(good)]]))):
+        assert create(m, vs, **kw)[0] == 1, (vs[:1], kw)
+    assert create(_model(n=n, alpha=0.0, field="gauss"), good)[0] == 1
+    Ka = K.copy()
+    Ka[0, 2] = 1.0
+    assert create(m, good, KK=Ka)[0] == 1
+    K65 = np.zeros((65, 65))
+    assert create(_model(n=65, alpha=0.0), [((0,), [[1.0]], 0.5, 0.0, False)], pr=np.zeros((0, 2)), KK=K65)[0] == 2
+    many = [((i % n,), [[1.0]], 0.5, 0.0, False) for i in range(513)]
+    assert create(m, many, pr=np.zeros((0, 2)))[0] == 2
+    # more than 2048 partner entries (2 per pair)
+    assert create(m, good, pr=np.tile([[0, 1]], (1025, 1)))[0] == 2
+    assert create(m, good, pr=np.tile([[0, 1]], (1024, 1)))[0] == 0
+    arr = make_vertices(good)
+    arr[0].n_orb = 3
+    ctx = ctypes.c_void_p()
+    assert lib.dqmc_create_vertices(ctypes.byref(m), K.ctypes.data, len(good), ctypes.addressof(arr), 0.5, 0.3, 2,
+                                    pairs.ctypes.data, ctypes.byref(ctx)) == 2

@@ -1,0 +1,175 @@
+"""Parity of the general-vertex chain (operator vertices X = P^T O P on one or
+two orbitals, Ising spins with their own action S0) with the oracle's
+VertexChain (section "Definition of the Hamiltonian", Eqs. (general_ham_v)
+and (general_ham_i); section "Sampling of e^{-S_{0,I}}"; the bond-Ising
+example of Eq. (hubbard_sun_Ising)).
+
+Each test starts both sides from the library's seeded field and compares,
+after every sweep, the field decisions bit-exactly, G element by element
+(1e-9), the proposal and acceptance counts exactly; at the end the bins of
+the equal-time estimators (1e-9 per measurement) and the precision of the
+stabilisations."""
+import numpy as np
+import pytest
+
+from gpu_util import maxabs
+from inputs import bonds_of, bonds_sharing_a_site, square_lattice
+from oracle import hubbard
+from oracle import stable
+from oracle import vertices as vx
+
+pytestmark = pytest.mark.gpu
+
+TOL_G = 1e-9
+X = [[0.0, 1.0], [1.0, 0.0]]
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def _bond_ising(K, U, xi, dtau, extra=()):
+    """Ising spins on the bonds of K coupled to the bond hopping (g = -dtau xi),
+    then the Hubbard interaction on every site through the two-valued field
+    (alpha = -1/2), then any extra vertices."""
+    vs = [((a, b), X, -dtau * xi, 0.0, True) for a, b in bonds_of(K)]
+    if U > 0.0:
+        lam = hubbard.ising_coupling(U, dtau)
+        vs += [((i,), [[1.0]], lam, -0.5, False) for i in range(K.shape[0])]
+    return vs + list(extra)
+
+
+def _pair(K, vlist, beta, dtau, n_wrap, U=0.0, h=0.0, J=0.0, pairs=(), n_col=2, trotter="asym", seed=0):
+    import paper_1704_00131_amd as pa
+    om = vx.vertex_model(K, [vx.Vertex(P=p, O=O, g=g, alpha=a, ising=i) for (p, O, g, a, i) in vlist], beta, dtau,
+                         n_wrap, U=U, h=h, J=J, pairs=pairs, n_col=n_col, trotter=trotter, seed=seed)
+    pm = pa.make_model(K.shape[0], beta, dtau, n_wrap, 0.0, U=U, field="ising", trotter=trotter, seed=seed,
+                       alpha=0.0, n_col=n_col)
+    return om, pa.Chain(pm, K, vertices=vlist, h=h, J=J, pairs=pairs)
+
+
+def _trajectory(om, ch, sweeps):
+    ch.random_field().init()
+    f0, _ = ch.get_state()
+    assert f0.shape == (om.L, om.M)
+    assert np.array_equal(f0, vx.init_field(om))
+    oc = vx.VertexChain(om, f0).init()
+    assert maxabs(ch.G.cpu().numpy(), oc.G) < 1e-10
+    for s in range(sweeps):
+        st = ch.sweep(1, measure=True)
+        oc.sweep(measure=True)
+        f, ctr = ch.get_state()
+        assert oc.min_tie > 1e-9, "near-tie in the oracle's decisions; pick another seed"
+        assert ctr == s + 1
+        assert np.array_equal(f, oc.field), f"field differs after sweep {s}"
+        assert maxabs(ch.G.cpu().numpy(), oc.G) < TOL_G, f"G differs after sweep {s}"
+        assert st.accepted == oc.accepted and st.proposals == oc.proposals
+    bins = ch.read_bins()
+    n_meas = 2 * om.L * sweeps
+    assert bins[3] == n_meas
+    assert maxabs(bins, oc.bins) < TOL_G * n_meas
+    assert st.prec_max < max(1e-8, 10.0 * max(oc.prec))
+    assert 0 < oc.accepted < oc.proposals
+    return ch, oc
+
+
+def _chain_K(n, t=1.0, periodic=False):
+    K = np.zeros((n, n))
+    for a in range(n - (0 if periodic else 1)):
+        b = (a + 1) % n
+        K[a, b] = K[b, a] = -t
+    return K
+
+
+def test_bond_ising_chain_with_hubbard():
+    """6-site open chain: Ising spins on the 5 bonds (xi = 0.7) with a
+    transverse field and a coupling J between neighbouring bond spins, the
+    Hubbard U on the sites: 11 vertices, 3 sweeps."""
+    _log("vertices: bond-Ising chain 6 sites 3 sweeps")
+    K = _chain_K(6)
+    dtau = 0.1
+    vs = _bond_ising(K, 2.0, 0.7, dtau)
+    pairs = [(0, 1), (1, 2), (2, 3), (3, 4)]
+    om, ch = _pair(K, vs, 1.0, dtau, 5, U=2.0, h=1.0, J=0.4, pairs=pairs, seed=3)
+    _trajectory(om, ch, 3)
+
+
+def test_bond_ising_square_4x4_symmetric_split():
+    """4x4 periodic square: 32 bond spins coupled to the hopping and to each
+    other where two bonds share a site (6 partners each), 16 Hubbard
+    vertices, the symmetric split in the estimators, 2 sweeps."""
+    _log("vertices: bond-Ising square 4x4 2 sweeps")
+    K = square_lattice(4, 4).K
+    dtau = 0.1
+    vs = _bond_ising(K, 4.0, 0.5, dtau)
+    pairs = bonds_sharing_a_site(bonds_of(K))
+    om, ch = _pair(K, vs, 1.0, dtau, 10, U=4.0, h=0.8, J=0.3, pairs=pairs, trotter="sym", seed=5)
+    _trajectory(om, ch, 2)
+
+
+def test_general_two_orbital_operators_one_colour():
+    """Two-orbital HS vertices with general symmetric O (diagonal and
+    off-diagonal parts) and alpha != 0, one colour, on a 5-site ring, next to
+    single-orbital ones with O != 1: 3 sweeps."""
+    _log("vertices: general two-orbital operators ring 5 sites")
+    K = _chain_K(5, periodic=True) - 0.3 * np.eye(5)
+    O2 = [[0.4, 0.9], [0.9, -0.2]]
+    vs = [((a, (a + 2) % 5), O2, 0.35, 0.25, False) for a in range(5)] + \
+         [((i,), [[0.8]], 0.5, -0.3, False) for i in range(5)]
+    om, ch = _pair(K, vs, 0.8, 0.1, 4, n_col=1, seed=7)
+    _trajectory(om, ch, 3)
+
+
+def test_single_slice_and_single_vertex():
+    """Degenerate sizes: one slice (the spin's temporal bond is to itself)
+    with bond spins, then a lone vertex on a 3-site chain."""
+    _log("vertices: single slice, single vertex")
+    K = _chain_K(4)
+    vs = _bond_ising(K, 1.0, 0.6, 0.2)
+    om, ch = _pair(K, vs, 0.2, 0.2, 1, U=1.0, h=0.7, J=0.5, pairs=[(0, 1), (1, 2)], seed=11)
+    _trajectory(om, ch, 4)
+    om, ch = _pair(_chain_K(3), [((0, 1), X, -0.3, 0.0, True)], 0.6, 0.1, 3, h=0.5, seed=2)
+    _trajectory(om, ch, 4)
+
+
+def test_ragged_and_largest():
+    """6x6 square (n = 36, ragged against the 32-wide tiles) with bond spins
+    only, then the largest, 8x8 (n = 64, 128 bond spins and 64 Hubbard
+    vertices), one sweep each."""
+    _log("vertices: square 6x6 bond spins 1 sweep")
+    K = square_lattice(6, 6).K
+    om, ch = _pair(K, _bond_ising(K, 0.0, 0.8, 0.1), 0.6, 0.1, 3, h=1.0, J=0.2,
+                   pairs=[(2 * k, 2 * k + 1) for k in range(30)], seed=13)
+    _trajectory(om, ch, 1)
+    _log("vertices: square 8x8 bond spins + Hubbard 1 sweep")
+    K = square_lattice(8, 8).K
+    om, ch = _pair(K, _bond_ising(K, 3.0, 0.4, 0.1), 0.5, 0.1, 5, U=3.0, h=1.0, seed=17)
+    _trajectory(om, ch, 1)
+
+
+def test_green_scratch_logdet_and_refusals():
+    import paper_1704_00131_amd as pa
+    _log("vertices: green scratch, logdet, refusals")
+    K = _chain_K(6)
+    dtau = 0.1
+    vs = _bond_ising(K, 2.0, 0.7, dtau)
+    om, ch = _pair(K, vs, 1.0, dtau, 5, U=2.0, h=1.0, J=0.4, pairs=[(0, 1)], seed=19)
+    ch.random_field()
+    f, _ = ch.get_state()
+    for tau in (0, 3, 5, 10):
+        G = ch.green_scratch(tau).cpu().numpy()
+        assert maxabs(G, stable.green_scratch(om, f, tau)) < 1e-10
+    assert abs(ch.logdet() - stable.logdet_scratch(om, f)) < 1e-9
+    # a field set from the host is used as given
+    f2 = f.copy()
+    f2[3, 2] = -f2[3, 2]
+    ch.set_state(f2, 0)
+    assert maxabs(ch.green_scratch(4).cpu().numpy(), stable.green_scratch(om, f2, 4)) < 1e-10
+    with pytest.raises(pa.DQMCError, match="DQMC_E_ARG"):
+        ch.set_state(np.where(f2 > 0, 0.5, -1.0), 0)
+    ch.init()
+    for call in (lambda: ch.grad_logdet(), lambda: ch.ratio(1, 0, -1.0), lambda: ch.read_phase(),
+                 lambda: ch.sweep(1, measure=True, time_displaced=True)):
+        with pytest.raises(pa.DQMCError, match="DQMC_E_UNSUPPORTED"):
+            call()
+    ch.sweep(1, measure=True)
