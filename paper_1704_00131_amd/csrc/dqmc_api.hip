@@ -541,6 +541,12 @@ dqmc_status set_lds_limits(dqmc_ctx* c) {
   HIPCHK(gemm64_set_lds());
   HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(k_accum_q), hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)(sizeof(double) * 16 * (size_t)c->N)));
+  if (c->N <= kAccumWideMaxN) {
+    HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(k_accum_q_wide<1>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)accum_q_lds<1>(c->N)));
+    HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(k_accum_q_wide<2>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)accum_q_lds<2>(c->N)));
+  }
   if (!c->cplx && c->N <= kChunkMaxN) {
     const void* fns[] = {reinterpret_cast<const void*>(k_chunk<1>), reinterpret_cast<const void*>(k_chunk<2>),
                          reinterpret_cast<const void*>(k_chunk<3>), reinterpret_cast<const void*>(k_chunk<4>)};
@@ -582,8 +588,17 @@ dqmc_status qr_udv(dqmc_ctx* c, double* M, const double* T_in, UDVp out) {
   }
   // explicit Q by backward accumulation of the block reflectors, every
   // 16-column slab through all panels in one launch
-  hipLaunchKernelGGL(k_accum_q, gridc(c, (unsigned)((N + 15) / 16)), dim3(256), sizeof(double) * 16 * (size_t)N,
-                     c->stream, c->Vall, c->VTall, out.Q, N, nb, c->cs);
+  if (N <= kAccumWideMaxN) {
+    if (nb > 16)
+      hipLaunchKernelGGL(k_accum_q_wide<2>, gridc(c, (unsigned)((N + 15) / 16)), dim3(64 * kAccumWaves),
+                         accum_q_lds<2>(N), c->stream, c->Vall, c->VTall, out.Q, N, nb, c->cs);
+    else
+      hipLaunchKernelGGL(k_accum_q_wide<1>, gridc(c, (unsigned)((N + 15) / 16)), dim3(64 * kAccumWaves),
+                         accum_q_lds<1>(N), c->stream, c->Vall, c->VTall, out.Q, N, nb, c->cs);
+  } else {
+    hipLaunchKernelGGL(k_accum_q, gridc(c, (unsigned)((N + 15) / 16)), dim3(256), sizeof(double) * 16 * (size_t)N,
+                       c->stream, c->Vall, c->VTall, out.Q, N, nb, c->cs);
+  }
   HIPCHK(hipGetLastError());
   hipLaunchKernelGGL(k_build_rt, gridc(c, grid1((size_t)N * N)), dim3(256), 0, c->stream, Ap, c->piv, N, c->Rt,
                      out.D, c->err_flag, c->cs);

@@ -218,6 +218,97 @@ __device__ __forceinline__ void apply_wy_slab(const double* P, const double* S, 
   }
 }
 
+// C <- C - P (S^T C) for one 16-column slab C (h rows, leading dimension
+// ldc, columns >= ncol inert) and P, S: h x nbw (leading dimension ldps,
+// nbw <= 16 KT), by a workgroup of NW waves.  Each wave takes an NW-th of
+// the rows for S^T C and every NW-th 16-row tile for the update; every load
+// of a phase is issued in one round (UZ k-steps, UC row tiles) while
+// h <= 4 NW UZ, so a phase costs one memory latency.  zp: NW x KT x 4 x 64 doubles
+// of LDS for the per-wave partial products; Zs: the reduced S^T C.  The
+// caller puts a barrier between two calls on the same slab.
+template <int NW, int KT, int UZ, int UC>
+__device__ __forceinline__ void apply_wy_wide(const double* P, const double* S, int ldps, double* C, int ldc, int h,
+                                              int ncol, int nbw, double* zp, double (*Zs)[17]) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int m16 = lane & 15, kk = lane >> 4;
+  const int colc = min(m16, ncol - 1);
+  const bool cin = m16 < ncol;
+  const int kq = ((h + 4 * NW - 1) / (4 * NW)) * 4;
+  const int kb = w * kq, ke = min(h, kb + kq);
+  v4d z[KT];
+#pragma unroll
+  for (int t = 0; t < KT; ++t) z[t] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int kc = kb; kc < ke; kc += 4 * UZ) {
+    double a[UZ][KT], b[UZ];
+#pragma unroll
+    for (int u = 0; u < UZ; ++u) {
+      const int rc = min(kc + 4 * u + kk, h - 1);
+#pragma unroll
+      for (int t = 0; t < KT; ++t) a[u][t] = S[(size_t)rc * ldps + min(t * 16 + m16, nbw - 1)];
+      b[u] = C[(size_t)rc * ldc + colc];
+    }
+#pragma unroll
+    for (int u = 0; u < UZ; ++u) {
+      const bool rin = kc + 4 * u + kk < ke;
+#pragma unroll
+      for (int t = 0; t < KT; ++t) a[u][t] = (rin && t * 16 + m16 < nbw) ? a[u][t] : 0.0;
+      b[u] = (rin && cin) ? b[u] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < UZ; ++u)
+#pragma unroll
+      for (int t = 0; t < KT; ++t) z[t] = mfma_f64_16x16x4(a[u][t], b[u], z[t]);
+  }
+#pragma unroll
+  for (int t = 0; t < KT; ++t)
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) zp[((w * KT + t) * 4 + rr) * 64 + lane] = z[t][rr];
+  __syncthreads();
+  if (w < 4 * KT) {   // wave (t, rr) sums the NW partials of its D register
+    const int t = w >> 2, rr = w & 3;
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) v += zp[((q * KT + t) * 4 + rr) * 64 + lane];
+    Zs[t * 16 + kk + 4 * rr][m16] = v;   // D layout: row kk + 4 rr, column m16 of tile t
+  }
+  __syncthreads();
+  double zb[4 * KT];
+#pragma unroll
+  for (int k = 0; k < 4 * KT; ++k) zb[k] = (4 * k + kk < nbw) ? Zs[4 * k + kk][m16] : 0.0;
+  const int nrt = (h + 15) / 16;
+  for (int tr0 = w; tr0 < nrt; tr0 += NW * UC) {
+    v4d acc[UC];
+    double pa[UC][4 * KT];
+#pragma unroll
+    for (int q = 0; q < UC; ++q) {
+      const int r0 = (tr0 + NW * q) * 16, pr = min(r0 + m16, h - 1);
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) acc[q][rr] = C[(size_t)min(r0 + kk + 4 * rr, h - 1) * ldc + colc];
+#pragma unroll
+      for (int k = 0; k < 4 * KT; ++k) pa[q][k] = P[(size_t)pr * ldps + min(4 * k + kk, nbw - 1)];
+    }
+#pragma unroll
+    for (int q = 0; q < UC; ++q)
+#pragma unroll
+      for (int k = 0; k < 4 * KT; ++k) pa[q][k] = (4 * k + kk < nbw) ? -pa[q][k] : 0.0;
+#pragma unroll
+    for (int k = 0; k < 4 * KT; ++k)
+#pragma unroll
+      for (int q = 0; q < UC; ++q) acc[q] = mfma_f64_16x16x4(pa[q][k], zb[k], acc[q]);
+    if (cin) {
+#pragma unroll
+      for (int q = 0; q < UC; ++q) {
+        if (tr0 + NW * q >= nrt) break;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const int r = (tr0 + NW * q) * 16 + kk + 4 * rr;
+          if (r < h) C[(size_t)r * ldc + m16] = acc[q][rr];
+        }
+      }
+    }
+  }
+}
+
 // Explicit Q of a QR factorisation in one launch: Q = H_0 H_1 ... H_last I
 // by backward accumulation, every workgroup one 16-column slab of Q (grid
 // (ceil(n / 16), chains)) held in LDS (n x 16 doubles, dynamic) from the
@@ -251,6 +342,48 @@ __global__ __launch_bounds__(256) void k_accum_q(const double* Vall, const doubl
     __syncthreads();
   }
   for (int e = tid; e < n * 16; e += 256) {
+    const int r = e >> 4, c = e & 15;
+    if (c < ncol) Q[(size_t)r * n + c0 + c] = qs[e];
+  }
+}
+
+// k_accum_q with 16 waves per slab (blockDim 1024) and apply_wy_wide: the
+// panels' applications stay sequential per slab, but each costs about two
+// memory latencies instead of one per 6 k-steps and per 2 row tiles.
+// Dynamic LDS: the slab (n x 16) and the per-wave partials (16 KT x 4 x 64).
+constexpr int kAccumWaves = 16;
+constexpr int kAccumWideMaxN = 960;   // the slab and the partials within the LDS of one workgroup
+template <int KT>
+__host__ __device__ inline size_t accum_q_lds(int n) {
+  return sizeof(double) * (16 * (size_t)n + (size_t)kAccumWaves * KT * 4 * 64);
+}
+
+template <int KT>
+__global__ __launch_bounds__(1024) void k_accum_q_wide(const double* Vall, const double* VTall, double* Q, int n,
+                                                       int nb, size_t cs) {
+  extern __shared__ double qs[];
+  __shared__ double Zs[32][17];
+  double* zp = qs + 16 * (size_t)n;
+  {
+    const size_t co = (size_t)blockIdx.y * cs;
+    Vall += co; VTall += co; Q += co;
+  }
+  const int tid = threadIdx.x;
+  const int c0 = blockIdx.x * 16, ncol = min(16, n - c0);
+  for (int e = tid; e < n * 16; e += 1024) {
+    const int r = e >> 4, c = e & 15;
+    qs[e] = (c < ncol && r == c0 + c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int last = ((n - 1) / nb) * nb;
+  for (int j0 = last; j0 >= 0; j0 -= nb) {
+    if (j0 > c0 + ncol - 1) continue;   // uniform
+    const int nbw = min(nb, n - j0), h = n - j0;
+    apply_wy_wide<kAccumWaves, KT, 16 / KT, 4 / KT>(VTall + (size_t)j0 * n, Vall + (size_t)j0 * n, nbw, qs + (size_t)j0 * 16, 16,
+                                          h, ncol, nbw, zp, Zs);
+    __syncthreads();
+  }
+  for (int e = tid; e < n * 16; e += 1024) {
     const int r = e >> 4, c = e & 15;
     if (c < ncol) Q[(size_t)r * n + c0 + c] = qs[e];
   }
