@@ -127,8 +127,16 @@ struct dqmc_ctx {
   std::vector<hipEvent_t> ev;
   size_t ev_used = 0;
   double timed_flops = 0.0;
+  // single chains: a second stream (default priority) on which the
+  // time-displaced pass runs the next checkpoint's QR beside the current
+  // re-anchoring, joined by events
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev[3] = {};
   ~dqmc_ctx() {
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : fork_ev)
+      if (e) (void)hipEventDestroy(e);
+    if (side) (void)hipStreamDestroy(side);
   }
 
   UDVp slot(int k) const {
@@ -1367,12 +1375,12 @@ dqmc_status td_measure(dqmc_ctx* c, int tau, const double* gt0, const double* h,
     // e^{-dtau K/2} (.) e^{+dtau K/2} of GT0 and GTT, e^{+dtau K/2} H e^{-dtau K/2}:
     // the three left products in one launch, then the three right products
     GemmArgs gl[3] = {gemm_args(N, N, N, c->Eh, N, 0, gt0, N, 0, c->T1, N),
-                      gemm_args(N, N, N, c->Ehinv, N, 0, h, N, 0, c->Zq, N),
-                      gemm_args(N, N, N, c->Eh, N, 0, gtt, N, 0, c->Rt, N)};
+                      gemm_args(N, N, N, c->Ehinv, N, 0, h, N, 0, c->S[0], N),
+                      gemm_args(N, N, N, c->Eh, N, 0, gtt, N, 0, c->S[1], N)};
     if (dqmc_status s = gemm_group(c, gl, 3)) return s;
     GemmArgs gr[3] = {gemm_args(N, N, N, c->T1, N, 0, c->Ehinv, N, 0, c->Gs, N),
-                      gemm_args(N, N, N, c->Zq, N, 0, c->Eh, N, 0, c->X, N),
-                      gemm_args(N, N, N, c->Rt, N, 0, c->Ehinv, N, 0, c->RHS, N)};
+                      gemm_args(N, N, N, c->S[0], N, 0, c->Eh, N, 0, c->X, N),
+                      gemm_args(N, N, N, c->S[1], N, 0, c->Ehinv, N, 0, c->RHS, N)};
     if (dqmc_status s = gemm_group(c, gr, 3)) return s;
     gt0 = c->Gs; h = c->X; gtt = c->RHS;
   }
@@ -1418,9 +1426,35 @@ dqmc_status td_pass(dqmc_ctx* c) {
   double *gt0 = c->TD[0], *gt0_alt = c->TD[1], *h = c->TD[2], *h_alt = c->TD[3];
   c->Gcur = c->G2;
   if (dqmc_status s = td_measure(c, 0, gt0, h, c->G2)) return s;
-  UDVp right = c->uid;
+  // The right forms of the checkpoints depend only on the field: right_k
+  // (in bufs[(k - 1) & 1]) is computed on the second stream while the main
+  // stream re-anchors at checkpoint k - 1 and propagates (a single chain not
+  // under graph capture; otherwise in line).  The QR of right_k reads
+  // S[2..4], Zq, norms, piv, Vall, VTall, Rt and writes bufs[(k - 1) & 1],
+  // none of which the main stream touches in this pass; it waits for the
+  // main stream's re-anchoring at k - 2, the last reader of that buffer.
   UDVp bufs[2] = {c->hA, c->hB};
-  int b = 0;
+  bool fork = c->side != nullptr && c->nch == 1;
+  if (fork) {
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIPCHK(hipStreamIsCapturing(c->stream, &cap));
+    fork = cap == hipStreamCaptureStatusNone;
+  }
+  auto right_of = [&](int k) { return k == 0 ? c->uid : bufs[(k - 1) & 1]; };
+  // enqueue right_k after the main stream's work so far
+  auto launch_right = [&](int k) -> dqmc_status {
+    if (!fork) return right_step(c, right_of(k - 1), (k - 1) * nw, k * nw, bufs[(k - 1) & 1]);
+    HIPCHK(hipEventRecord(c->fork_ev[2], c->stream));
+    HIPCHK(hipStreamWaitEvent(c->side, c->fork_ev[2], 0));
+    hipStream_t main = c->stream;
+    c->stream = c->side;
+    const dqmc_status s = right_step(c, right_of(k - 1), (k - 1) * nw, k * nw, bufs[(k - 1) & 1]);
+    c->stream = main;
+    if (s) return s;
+    HIPCHK(hipEventRecord(c->fork_ev[(k - 1) & 1], c->side));
+    return DQMC_OK;
+  };
+  if (dqmc_status s = launch_right(1)) return s;
   for (int tau = 1; tau <= L; ++tau) {
     // three independent left products in one launch: E GTT (first half of
     // the wrap), B_tau GT0 and B_tau^-T H; then the wrap's second half
@@ -1439,11 +1473,11 @@ dqmc_status td_pass(dqmc_ctx* c) {
     std::swap(h, h_alt);
     if (tau % nw == 0) {
       const int k = tau / nw;
-      if (dqmc_status s = right_step(c, right, tau - nw, tau, bufs[b])) return s;
-      right = bufs[b];
-      b ^= 1;
+      if (fork) HIPCHK(hipStreamWaitEvent(c->stream, c->fork_ev[(k - 1) & 1], 0));
+      if (k < nk)
+        if (dqmc_status s = launch_right(k + 1)) return s;
       UDVp left = (k == nk) ? c->uid : c->slot(k);
-      if (dqmc_status s = td_anchor(c, right, left, gt0, h)) return s;
+      if (dqmc_status s = td_anchor(c, right_of(k), left, gt0, h)) return s;
     }
     if (dqmc_status s = td_measure(c, tau, gt0, h, c->G2)) return s;
   }
@@ -1730,6 +1764,10 @@ dqmc_status setup_device(dqmc_ctx* c) {
   if (dqmc_status s = fill_small(c, c->mpart, 4 * (size_t)((N + kMeasRows - 1) / kMeasRows) + 4, 0.0)) return s;
   if (dqmc_status s = fill_small(c, c->tdpart, td_part_size(c), 0.0)) return s;
   if (c->seeds.empty()) c->seeds.assign(c->nch, c->m.seed);
+  if (c->nch == 1 && !c->side) {
+    HIPCHK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+    for (hipEvent_t& e : c->fork_ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
   // chain keys: host -> staging buffer -> counters[3] of every chain
   HIPCHK(hipMemcpyAsync(c->gbuf, c->seeds.data(), sizeof(uint64_t) * c->nch, hipMemcpyHostToDevice, c->stream));
   hipLaunchKernelGGL(k_scatter, dim3(1, c->nch), dim3(64), 0, c->stream, reinterpret_cast<double*>(c->counters + 3),
