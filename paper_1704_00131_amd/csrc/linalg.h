@@ -264,8 +264,8 @@ __device__ __forceinline__ void apply_wy_wide(const double* P, const double* S, 
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) zp[((w * KT + t) * 4 + rr) * 64 + lane] = z[t][rr];
   __syncthreads();
-  if (w < 4 * KT) {   // wave (t, rr) sums the NW partials of its D register
-    const int t = w >> 2, rr = w & 3;
+  for (int p = w; p < 4 * KT; p += NW) {   // wave p sums the NW partials of D register (t, rr) = (p / 4, p % 4)
+    const int t = p >> 2, rr = p & 3;
     double v = 0.0;
 #pragma unroll
     for (int q = 0; q < NW; ++q) v += zp[((q * KT + t) * 4 + rr) * 64 + lane];
@@ -456,7 +456,9 @@ __global__ __launch_bounds__(256) void k_qr_panel(double* A, int n, int j0, int 
   }
   const int h = n - j0, tid = threadIdx.x, lane = tid & 63;
   if (blockIdx.x > 0) {   // trailing columns: the previous panel's block reflector
-    apply_wy_slab(Vp, VTp, NBW, At, n, h + NBW, ntr, NBW, blockIdx.x - 1, zp, Zs);
+    const int c0 = 16 * ((int)blockIdx.x - 1);
+    apply_wy_wide<4, (NBW + 15) / 16, 12 / ((NBW + 15) / 16), 3>(Vp, VTp, NBW, At + c0, n, h + NBW, ntr - c0, NBW,
+                                                                &zp[0][0][0][0], Zs);
     return;
   }
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -487,7 +489,9 @@ __global__ __launch_bounds__(256) void k_qr_panel(double* A, int n, int j0, int 
       top[r * PV + q] = (q < nbw) ? A[(size_t)(j0 - NBW + r) * n + j0 + q] : 0.0;
     }
     __syncthreads();
-    for (int bx = 0; bx * 16 < NBW; ++bx) apply_wy_slab(Vp, VTp, NBW, top, PV, h + NBW, nbw, NBW, bx, zp, Zs);
+    for (int c0 = 0; c0 < nbw; c0 += 16)   // uniform
+      apply_wy_wide<4, (NBW + 15) / 16, 12 / ((NBW + 15) / 16), 3>(Vp, VTp, NBW, top + c0, PV, h + NBW, nbw - c0,
+                                                                  NBW, &zp[0][0][0][0], Zs);
     __syncthreads();
     for (int e = tid; e < NBW * NBW; e += 256) {
       const int r = e / NBW, q = e % NBW;
@@ -919,34 +923,53 @@ __device__ __forceinline__ void lu_prev_slab(double* XA, int n, int ld, int j0p,
   double ub[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) ub[q] = (4 * q + kk < nbp) ? sh.u12[4 * q + kk][m16] : 0.0;
+  // UT row tiles of a wave per round, all their loads issued together
+  constexpr int UT = 4;
   const int nrt = (hb + 15) / 16;
-  for (int t = w; t < nrt; t += 4) {
-    const int r0 = jb + 16 * t;
-    v4d acc;
+  for (int t0 = w; t0 < nrt; t0 += 4 * UT) {
+    v4d acc[UT];
+    double av[UT][8];
 #pragma unroll
-    for (int rr = 0; rr < 4; ++rr) {
-      const int row = r0 + kk + 4 * rr, rowc = min(row, n - 1);
-      const int mi = odmap[rowc - jb];
-      const double g = XA[(size_t)rowc * ld + colc];
-      acc[rr] = (mi >= 0) ? sh.mv[mi][m16] : g;
+    for (int u = 0; u < UT; ++u) {
+      const int r0 = jb + 16 * (t0 + 4 * u);
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int rowc = min(r0 + kk + 4 * rr, n - 1);
+        acc[u][rr] = XA[(size_t)rowc * ld + colc];
+      }
+      const double* Mrow = Mp + (size_t)min(r0 + m16, n - 1) * 32;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) av[u][q] = (4 * q < nbp) ? Mrow[4 * q + kk] : 0.0;
     }
-    const double* Mrow = Mp + (size_t)min(r0 + m16, n - 1) * 32;
-    double av[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) av[q] = Mrow[4 * q + kk];
+    for (int u = 0; u < UT; ++u) {
+      const int r0 = jb + 16 * (t0 + 4 * u);
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int rowc = min(r0 + kk + 4 * rr, n - 1);
+        const int mi = odmap[rowc - jb];
+        acc[u][rr] = (mi >= 0) ? sh.mv[mi][m16] : acc[u][rr];
+      }
+    }
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       if (4 * q >= nbp) break;   // uniform
-      acc = mfma_f64_16x16x4((4 * q + kk < nbp) ? -av[q] : 0.0, ub[q], acc);
+#pragma unroll
+      for (int u = 0; u < UT; ++u) acc[u] = mfma_f64_16x16x4((4 * q + kk < nbp) ? -av[u][q] : 0.0, ub[q], acc[u]);
     }
 #pragma unroll
-    for (int rr = 0; rr < 4; ++rr) {
-      const int row = r0 + kk + 4 * rr;
-      if (row >= n) continue;
-      if (TO_STAGE) {
-        if (scol + m16 < scols) stage[(row - jb) * PS + scol + m16] = cin ? acc[rr] : 0.0;
+    for (int u = 0; u < UT; ++u) {
+      if (t0 + 4 * u >= nrt) break;   // uniform
+      const int r0 = jb + 16 * (t0 + 4 * u);
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int row = r0 + kk + 4 * rr;
+        if (row >= n) continue;
+        if (TO_STAGE) {
+          if (scol + m16 < scols) stage[(row - jb) * PS + scol + m16] = cin ? acc[u][rr] : 0.0;
+        }
+        else if (cin) XA[(size_t)row * ld + col] = acc[u][rr];
       }
-      else if (cin) XA[(size_t)row * ld + col] = acc[rr];
     }
   }
   // U12 over the previous panel's rows
