@@ -549,6 +549,9 @@ dqmc_status set_lds_limits(dqmc_ctx* c) {
   HIPCHK(gemm64_set_lds());
   HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(k_accum_q), hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)(sizeof(double) * 16 * (size_t)c->N)));
+  if (c->N <= kBackWideMaxN)
+    HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(k_lu_back_wide),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)back_wide_lds(c->N)));
   if (c->N <= kAccumWideMaxN) {
     HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(k_accum_q_wide<1>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)accum_q_lds<1>(c->N)));
@@ -715,8 +718,12 @@ dqmc_status lu_solve(dqmc_ctx* c, double* XA, int nrhs, int ld, double* logdet) 
   constexpr int bs = 32;
   const int nblk = (N + bs - 1) / bs;
   hipLaunchKernelGGL(k_lu_diag_inv, gridc(c, (unsigned)nblk), dim3(256), 0, c->stream, XA, N, ld, bs, c->Uinv, c->cs);
-  hipLaunchKernelGGL(k_lu_back, gridc(c, (unsigned)((nrhs + kBackCols - 1) / kBackCols)), dim3(256), 0, c->stream, XA,
-                     N, ld, bs, nrhs, c->Uinv, c->cs);
+  if (N <= kBackWideMaxN)
+    hipLaunchKernelGGL(k_lu_back_wide, gridc(c, (unsigned)((nrhs + kBackCols - 1) / kBackCols)), dim3(64 * kBackWaves),
+                       back_wide_lds(N), c->stream, XA, N, ld, bs, nrhs, c->Uinv, c->cs);
+  else
+    hipLaunchKernelGGL(k_lu_back, gridc(c, (unsigned)((nrhs + kBackCols - 1) / kBackCols)), dim3(256), 0, c->stream,
+                       XA, N, ld, bs, nrhs, c->Uinv, c->cs);
   HIPCHK(hipGetLastError());
   if (logdet) {
     hipLaunchKernelGGL(k_logabs_diag, gridc(c, 1), dim3(256), 0, c->stream, XA, N, ld, logdet, c->cs);

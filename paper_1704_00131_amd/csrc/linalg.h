@@ -1143,6 +1143,95 @@ __global__ __launch_bounds__(256) void k_lu_back(double* XA, int n, int ld, int 
   }
 }
 
+// k_lu_back for n <= kBackWideMaxN with eight waves and the slab of right-
+// hand sides held in LDS (n x 16, rows of 17) from start to end: each block
+// step issues its loads of U's columns above the block and of U_bb^-1 before
+// Y_b is formed (they do not depend on it), so a step costs one global
+// latency and two barriers.  The products and their order are those of
+// k_lu_back.  Dynamic LDS: back_wide_lds(n).
+constexpr int kBackWaves = 8, kBackWideMaxN = 768, kBackRS = kBackCols + 1;
+__host__ __device__ inline size_t back_wide_lds(int n) { return sizeof(double) * (size_t)n * kBackRS; }
+
+__global__ __launch_bounds__(64 * kBackWaves) void k_lu_back_wide(double* XA, int n, int ld, int nb, int nrhs,
+                                                                  const double* Uinv, size_t cs) {
+  extern __shared__ double Rs[];               // Rs[r * kBackRS + q] = R[r][c0 + q]
+  __shared__ double Yb[32][kBackCols + 1];     // Y_b = U_bb^-1 R_b
+  constexpr int UT = (kBackWideMaxN / 16 + kBackWaves - 1) / kBackWaves;   // row tiles above a block per wave
+  XA += (size_t)blockIdx.y * cs;
+  Uinv += (size_t)blockIdx.y * cs;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int m16 = lane & 15, kk = lane >> 4;
+  const int c0 = blockIdx.x * kBackCols, col = c0 + m16;
+  const bool cin = col < nrhs;
+  double* R = XA + n;
+  for (int e = tid; e < n * kBackCols; e += 64 * kBackWaves) {
+    const int r = e / kBackCols, q = e % kBackCols;
+    Rs[r * kBackRS + q] = (c0 + q < nrhs) ? R[(size_t)r * ld + c0 + q] : 0.0;
+  }
+  __syncthreads();
+  const int nblk = (n + nb - 1) / nb;
+  for (int b = nblk - 1; b >= 0; --b) {
+    const int j0 = b * nb, nbw = min(nb, n - j0);
+    // loads that do not depend on Y_b: U[rows above, block] and U_bb^-1
+    double ua[UT][8];
+#pragma unroll
+    for (int u = 0; u < UT; ++u) {
+      const int ra = (w + kBackWaves * u) * 16 + m16;
+      const double* Urow = XA + (size_t)min(ra, n - 1) * ld + j0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) ua[u][q] = Urow[min(4 * q + kk, nbw - 1)];
+    }
+    if (w < 2) {
+      const double* Ui = Uinv + (size_t)b * 1024;
+      double ui[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) ui[q] = Ui[(w * 16 + m16) * 32 + 4 * q + kk];
+      v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int k = 4 * q + kk;
+        acc = mfma_f64_16x16x4(ui[q], k < nbw ? Rs[(j0 + k) * kBackRS + m16] : 0.0, acc);
+      }
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) Yb[w * 16 + kk + 4 * rr][m16] = acc[rr];
+    }
+    __syncthreads();
+    // R[0:j0, slab] -= U[0:j0, block] Y_b in 16-row tiles (rows past j0 of
+    // the last tile, with 8-column panels, are left alone); Y_b into its rows
+#pragma unroll
+    for (int u = 0; u < UT; ++u) {
+      const int t = w + kBackWaves * u;
+      if (t * 16 >= j0) break;   // uniform
+      const int ra = t * 16 + m16;
+      v4d acc;
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) acc[rr] = Rs[min(t * 16 + kk + 4 * rr, n - 1) * kBackRS + m16];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        if (4 * q >= nbw) break;   // uniform
+        const int k = 4 * q + kk;
+        const double a = (k < nbw && ra < j0) ? -ua[u][q] : 0.0;
+        acc = mfma_f64_16x16x4(a, Yb[k][m16], acc);
+      }
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int row = t * 16 + kk + 4 * rr;
+        if (row < j0) Rs[row * kBackRS + m16] = acc[rr];
+      }
+    }
+    for (int e = tid; e < nbw * kBackCols; e += 64 * kBackWaves) {
+      const int r = e / kBackCols, q = e % kBackCols;
+      Rs[(j0 + r) * kBackRS + q] = Yb[r][q];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < n * kBackCols; e += 64 * kBackWaves) {
+    const int r = e / kBackCols, q = e % kBackCols;
+    if (c0 + q < nrhs) R[(size_t)r * ld + c0 + q] = Rs[r * kBackRS + q];
+  }
+  (void)cin;
+}
+
 // out += sum_i log|U_ii| (one workgroup)
 __global__ __launch_bounds__(256) void k_logabs_diag(const double* U, int n, int ld, double* out, size_t cs) {
   __shared__ double red[8];
