@@ -113,6 +113,18 @@ def test_sweep_parity_chunk_kernel_sizes():
     _trajectory("honeycomb", 5, 5, 4.0, 2.0, 5, "asym", 6, 3)
 
 
+def test_sweep_parity_four_valued_honeycomb12_one_sweep():
+    """The four-valued workload at full size: honeycomb 12x12 (N = 288), U=4,
+    beta=10, L=100, one sweep (57,600 three-way proposals; the oracle takes
+    about 25 s), at n_wrap = 5: with this field's larger vertex factors a
+    10-slice chunk already costs accuracy in the recomputation itself (the
+    oracle's own G(0) from 10-slice and 2-slice chunks differ by 1e-9, from
+    5-slice and 2-slice chunks by 5e-12), so the paper's rule of choosing the
+    interval by the precision it gives sets n_wrap = 5 here."""
+    _log("trajectory four-valued field honeycomb 12x12 n_wrap 5 1 sweep")
+    _trajectory("honeycomb", 12, 12, 4.0, 10.0, 5, "asym", 0, 1, field="ising4")
+
+
 def test_sweep_parity_honeycomb12_one_sweep():
     """Honeycomb 12x12 (N = 288), U=4, beta=10, L=100: one sweep."""
     _log("trajectory honeycomb 12x12 1 sweep")
