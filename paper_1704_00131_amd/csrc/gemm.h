@@ -410,11 +410,12 @@ static inline hipError_t launch_gemm(const GemmArgs& g, hipStream_t s) {
   }
   const int t32 = ((g.M + 31) / 32) * ((g.N + 31) / 32);
   const bool use32 = g.tile == 32 || (g.tile == 0 && (long long)t32 * nch >= 192);
-  // long K on few workgroups: eight waves split K (32 x 32 tiles with loads
-  // two steps ahead), which measured 10-25% faster at N = 288 and 648
+  // long K on few workgroups: eight waves split K, which measured 10-25%
+  // faster than four at N = 288 and 648; one K-step per load round (27.0
+  // against 27.9 us for two at N = 648)
   const bool deep = nch == 1 && g.K >= 128;
   if (use32) {
-    if (deep) hipLaunchKernelGGL((k_gemm<32, 2, 8>), dim3(t32, nch), dim3(512), 0, s, g);
+    if (deep) hipLaunchKernelGGL((k_gemm<32, 1, 8>), dim3(t32, nch), dim3(512), 0, s, g);
     else hipLaunchKernelGGL((k_gemm<32, 1, 4>), dim3(t32, nch), dim3(256), 0, s, g);
   } else {
     const int t16 = ((g.M + 15) / 16) * ((g.N + 15) / 16);
