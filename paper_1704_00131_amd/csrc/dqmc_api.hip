@@ -549,10 +549,10 @@ dqmc_status set_lds_limits(dqmc_ctx* c) {
   HIPCHK(gemm64_set_lds());
   HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(k_accum_q), hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)(sizeof(double) * 16 * (size_t)c->N)));
-  if (c->N <= kBackWideMaxN)
+  if (c->N > 384 && c->N <= kBackWideMaxN)
     HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(k_lu_back_wide),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)back_wide_lds(c->N)));
-  if (c->N <= kAccumWideMaxN) {
+  if (c->N > 384 && c->N <= kAccumWideMaxN) {
     HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(k_accum_q_wide<1>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)accum_q_lds<1>(c->N)));
     HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(k_accum_q_wide<2>),
@@ -599,7 +599,9 @@ dqmc_status qr_udv(dqmc_ctx* c, double* M, const double* T_in, UDVp out) {
   }
   // explicit Q by backward accumulation of the block reflectors, every
   // 16-column slab through all panels in one launch
-  if (N <= kAccumWideMaxN) {
+  // the sixteen-wave accumulation pays where panels are 16 wide (N > 384)
+  // and a lone chain leaves the chip idle; batches keep the four-wave kernel
+  if (N > 384 && N <= kAccumWideMaxN && c->nch == 1) {
     if (nb > 16)
       hipLaunchKernelGGL(k_accum_q_wide<2>, gridc(c, (unsigned)((N + 15) / 16)), dim3(64 * kAccumWaves),
                          accum_q_lds<2>(N), c->stream, c->Vall, c->VTall, out.Q, N, nb, c->cs);
@@ -718,7 +720,7 @@ dqmc_status lu_solve(dqmc_ctx* c, double* XA, int nrhs, int ld, double* logdet) 
   constexpr int bs = 32;
   const int nblk = (N + bs - 1) / bs;
   hipLaunchKernelGGL(k_lu_diag_inv, gridc(c, (unsigned)nblk), dim3(256), 0, c->stream, XA, N, ld, bs, c->Uinv, c->cs);
-  if (N <= kBackWideMaxN)
+  if (N > 384 && N <= kBackWideMaxN && c->nch == 1)   // likewise
     hipLaunchKernelGGL(k_lu_back_wide, gridc(c, (unsigned)((nrhs + kBackCols - 1) / kBackCols)), dim3(64 * kBackWaves),
                        back_wide_lds(N), c->stream, XA, N, ld, bs, nrhs, c->Uinv, c->cs);
   else

@@ -456,9 +456,13 @@ __global__ __launch_bounds__(256) void k_qr_panel(double* A, int n, int j0, int 
   }
   const int h = n - j0, tid = threadIdx.x, lane = tid & 63;
   if (blockIdx.x > 0) {   // trailing columns: the previous panel's block reflector
-    const int c0 = 16 * ((int)blockIdx.x - 1);
-    apply_wy_wide<4, (NBW + 15) / 16, 12 / ((NBW + 15) / 16), 3>(Vp, VTp, NBW, At + c0, n, h + NBW, ntr - c0, NBW,
-                                                                &zp[0][0][0][0], Zs);
+    if constexpr (NBW > 16) {
+      apply_wy_slab(Vp, VTp, NBW, At, n, h + NBW, ntr, NBW, blockIdx.x - 1, zp, Zs);
+    } else {
+      const int c0 = 16 * ((int)blockIdx.x - 1);
+      apply_wy_wide<4, (NBW + 15) / 16, 12 / ((NBW + 15) / 16), 3>(Vp, VTp, NBW, At + c0, n, h + NBW, ntr - c0, NBW,
+                                                                  &zp[0][0][0][0], Zs);
+    }
     return;
   }
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -489,9 +493,13 @@ __global__ __launch_bounds__(256) void k_qr_panel(double* A, int n, int j0, int 
       top[r * PV + q] = (q < nbw) ? A[(size_t)(j0 - NBW + r) * n + j0 + q] : 0.0;
     }
     __syncthreads();
-    for (int c0 = 0; c0 < nbw; c0 += 16)   // uniform
-      apply_wy_wide<4, (NBW + 15) / 16, 12 / ((NBW + 15) / 16), 3>(Vp, VTp, NBW, top + c0, PV, h + NBW, nbw - c0,
-                                                                  NBW, &zp[0][0][0][0], Zs);
+    if constexpr (NBW > 16) {
+      for (int bx = 0; bx * 16 < NBW; ++bx) apply_wy_slab(Vp, VTp, NBW, top, PV, h + NBW, nbw, NBW, bx, zp, Zs);
+    } else {
+      for (int c0 = 0; c0 < nbw; c0 += 16)   // uniform
+        apply_wy_wide<4, (NBW + 15) / 16, 12 / ((NBW + 15) / 16), 3>(Vp, VTp, NBW, top + c0, PV, h + NBW, nbw - c0,
+                                                                    NBW, &zp[0][0][0][0], Zs);
+    }
     __syncthreads();
     for (int e = tid; e < NBW * NBW; e += 256) {
       const int r = e / NBW, q = e % NBW;
@@ -867,7 +875,8 @@ __device__ __forceinline__ void lu_panel_factor(double* XA, int n, int ld, int j
 // interchanges as lu_panel_factor lists them (movesp).  The updated rows below go
 // back to XA, or, for the panel of this launch, to its LDS stage (row r at
 // stage + (r - jb) PS, column c - c0 + scol; zero past ncols).  Every thread
-// of the workgroup calls it.
+// of the workgroup calls it.  NBWP: the panel width of the launch (it sets how
+// many row tiles a wave loads at once).
 struct LuPrevShared {
   __attribute__((aligned(16))) double lr[32][34];   // lr[k][r] = L11[31 - r][31 - k]
   double u12[32][17];                                // U12 of the slab
@@ -875,7 +884,7 @@ struct LuPrevShared {
   int srcrow[32], od[32], os[32], nout;
 };
 
-template <bool TO_STAGE>
+template <bool TO_STAGE, int NBWP>
 __device__ __forceinline__ void lu_prev_slab(double* XA, int n, int ld, int j0p, int nbp, int c0, int ncols,
                                              const double* Mp, const int* movesp, LuPrevShared& sh, short* odmap,
                                              double* stage, int PS, int scol, int scols) {
@@ -923,8 +932,11 @@ __device__ __forceinline__ void lu_prev_slab(double* XA, int n, int ld, int j0p,
   double ub[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) ub[q] = (4 * q + kk < nbp) ? sh.u12[4 * q + kk][m16] : 0.0;
-  // UT row tiles of a wave per round, all their loads issued together
-  constexpr int UT = 4;
+  // UT row tiles of a wave per round, all their loads issued together: four
+  // for the tall 16-wide panels of large N, where one workgroup's latency
+  // sets the pace; one for 32-wide panels (batches of small lattices), where
+  // the registers of four cost more occupancy than they save
+  constexpr int UT = NBWP == 16 ? 4 : 1;
   const int nrt = (hb + 15) / 16;
   for (int t0 = w; t0 < nrt; t0 += 4 * UT) {
     v4d acc[UT];
@@ -1010,7 +1022,8 @@ __global__ __launch_bounds__(256) void k_lu_step(double* XA, int n, int ld, int 
   }
   const int tslab = (int)blockIdx.x - (has_panel ? 1 : 0);
   if (tslab >= 0) {   // trailing columns: the previous panel's step
-    lu_prev_slab<false>(XA, n, ld, j0p, nbp, tstart + 16 * tslab, ncols, Mp, movesp, ps, odmap, nullptr, 0, 0, 0);
+    lu_prev_slab<false, NBW>(XA, n, ld, j0p, nbp, tstart + 16 * tslab, ncols, Mp, movesp, ps, odmap, nullptr, 0, 0,
+                             0);
     return;
   }
   const int h = n - j0, tid = threadIdx.x;
@@ -1018,7 +1031,7 @@ __global__ __launch_bounds__(256) void k_lu_step(double* XA, int n, int ld, int 
   if (Mp) {
     // the previous panel's step on this panel's columns, straight into the stage
     for (int c0 = 0; c0 < NBW; c0 += 16)
-      lu_prev_slab<true>(XA, n, ld, j0p, nbp, j0 + c0, j0 + nbw, Mp, movesp, ps, odmap, stage, PS, c0, NBW);
+      lu_prev_slab<true, NBW>(XA, n, ld, j0p, nbp, j0 + c0, j0 + nbw, Mp, movesp, ps, odmap, stage, PS, c0, NBW);
   } else {
     // the panel through LDS: coalesced loads (consecutive threads along a row),
     // all issued before the stores, zeros outside the panel

@@ -106,6 +106,8 @@ def mfma(out, db, n, workload, command):
     per = {}
     for name, disp, dur, cname, val in rows:
         key = name.split("(")[0]
+        if key.startswith("void "):   # template instances are listed with their return type
+            key = key[5:]
         d = per.setdefault(key, {}).setdefault(disp, {"duration_ns": dur})
         d[cname] = d.get(cname, 0.0) + val
     kernels = []

@@ -120,6 +120,21 @@ def test_general_two_orbital_operators_one_colour():
     _trajectory(om, ch, 3)
 
 
+def test_site_ising_spins_coupled_to_the_density():
+    """Single-orbital Ising spins: a spin on every site of a 6-site ring
+    coupled to the site density (O = 0.6, g = -dtau), with a transverse field
+    and J between neighbouring spins, then Hubbard vertices on the same
+    sites: 3 sweeps."""
+    _log("vertices: site Ising spins on a ring")
+    K = _chain_K(6, periodic=True)
+    dtau = 0.1
+    vs = [((i,), [[0.6]], -dtau, 0.0, True) for i in range(6)]
+    vs += [((i,), [[1.0]], hubbard.ising_coupling(3.0, dtau), -0.5, False) for i in range(6)]
+    pairs = [(i, (i + 1) % 6) for i in range(6)]
+    om, ch = _pair(K, vs, 0.8, dtau, 4, U=3.0, h=0.9, J=0.35, pairs=pairs, seed=23)
+    _trajectory(om, ch, 3)
+
+
 def test_single_slice_and_single_vertex():
     """Degenerate sizes: one slice (the spin's temporal bond is to itself)
     with bond spins, then a lone vertex on a 3-site chain."""
