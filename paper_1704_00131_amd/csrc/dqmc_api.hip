@@ -132,11 +132,26 @@ struct dqmc_ctx {
   // re-anchoring, joined by events
   hipStream_t side = nullptr;
   hipEvent_t fork_ev[3] = {};
+  // single chains of the one-flavour real sweep: the time-displaced pass at
+  // the start of a sweep runs on the second stream beside the sweep itself,
+  // as a context of its own over the shadow part of the work buffer (its
+  // scratch), reading the chain's G, field and stored left forms; it records
+  // td_ev[0] once it has read G, td_ev[k] once it has re-anchored at
+  // checkpoint k (the last read of slot k) and td_ev[nk] at its end
+  bool no_shadow = false;            // contexts that never run it that way
+  double* shadow_base = nullptr;
+  dqmc_ctx* tdc = nullptr;
+  hipStream_t side2 = nullptr;       // the pass's own second stream for its checkpoint QRs
+  std::vector<hipEvent_t> td_ev;
+  std::vector<hipEvent_t>* td_sync = nullptr;   // in the pass's context: the events it records
   ~dqmc_ctx() {
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     for (hipEvent_t e : fork_ev)
       if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : td_ev) (void)hipEventDestroy(e);
+    delete tdc;
     if (side) (void)hipStreamDestroy(side);
+    if (side2) (void)hipStreamDestroy(side2);
   }
 
   UDVp slot(int k) const {
@@ -253,10 +268,23 @@ size_t layout_chain(dqmc_ctx* c, double* base) {
   return l.off;
 }
 
+inline bool wants_shadow(const dqmc_ctx* c) {
+  return c->nch == 1 && !c->cplx && c->nfl == 1 && !c->nvx && !c->no_shadow;
+}
+
+// Shared part, the chain's scratch and, for a single chain of the one-flavour
+// real sweep, a second copy of the chain's scratch for the time-displaced
+// pass that runs beside the sweep (shadow_base).
 size_t layout_work(dqmc_ctx* c, bool assign) {
   const size_t sh = layout_shared(c, assign ? c->work : nullptr);
   const size_t ch = layout_chain(c, assign ? c->work + sh : nullptr);
-  return sh + ch;
+  size_t total = sh + ch;
+  if (wants_shadow(c)) {
+    total = (total + 31) & ~size_t(31);
+    if (assign) c->shadow_base = c->work + total;
+    total += ch;
+  }
+  return total;
 }
 
 inline unsigned grid1(size_t n, unsigned bs = 256) { return (unsigned)((n + bs - 1) / bs); }
@@ -957,12 +985,24 @@ dqmc_status sweep_chunks(dqmc_ctx* c, int meas) {
   return DQMC_OK;
 }
 
+dqmc_status td_pass_async(dqmc_ctx* c);
+
+// The second stream serves a single chain whose stream is not being captured
+// into a graph.
+bool side_ok(dqmc_ctx* c) {
+  if (!c->side || c->nch != 1) return false;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(c->stream, &cap) != hipSuccess) return false;
+  return cap == hipStreamCaptureStatusNone;
+}
+
 dqmc_status sweep_once(dqmc_ctx* c, int meas) {
   if (use_chunks(c, meas)) return sweep_chunks(c, meas);
   const int L = c->L, nw = c->nw, nk = c->nk;
+  const bool async_td = (meas & 2) && c->tdc && c->shadow_base && c->side2 && side_ok(c);
   if (meas & 2) {
     c->td_corr_now = (meas & 8) != 0;
-    const dqmc_status s = td_pass(c);
+    const dqmc_status s = async_td ? td_pass_async(c) : td_pass(c);
     c->td_corr_now = false;
     if (s) return s;
   }
@@ -980,6 +1020,8 @@ dqmc_status sweep_once(dqmc_ctx* c, int meas) {
       if (dqmc_status s = right_step(c, prev, tau - nw, tau, c->cur)) return s;
       UDVp left = (k == nk) ? c->uid : c->slot(k);
       if (dqmc_status s = merge(c, c->cur, left, c->Gs, nullptr)) return s;
+      // the time-displaced pass beside the sweep reads slot k until it has re-anchored there
+      if (async_td && k < nk) HIPCHK(hipStreamWaitEvent(c->stream, c->td_ev[k], 0));
       if (dqmc_status s = copy_udv(c, c->slot(k), c->cur)) return s;
       if (dqmc_status s = stabilise(c, hist++)) return s;
       if (dqmc_status s = timing_end(c, DQMC_KERNEL_STABILISE)) return s;
@@ -989,6 +1031,8 @@ dqmc_status sweep_once(dqmc_ctx* c, int meas) {
     if (meas & 4)
       if (dqmc_status s = eq_measure(c, (meas & 1) != 0)) return s;
   }
+  // the downward pass writes the field rows back, which that pass reads to its end
+  if (async_td) HIPCHK(hipStreamWaitEvent(c->stream, c->td_ev[nk], 0));
   if (dqmc_status s = pass_draws(c, 1)) return s;
   for (int tau = L; tau >= 1; --tau) {
     if (dqmc_status s = update_slice(c, tau)) return s;
@@ -1432,6 +1476,7 @@ dqmc_status td_pass(dqmc_ctx* c) {
   hipLaunchKernelGGL(k_td_init, dim3(t, t, (unsigned)c->nch), dim3(256), 0, c->stream, c->G, c->TD[0], c->TD[2], N,
                      c->cs);
   HIPCHK(hipGetLastError());
+  if (c->td_sync) HIPCHK(hipEventRecord((*c->td_sync)[0], c->stream));   // G is read
   double *gt0 = c->TD[0], *gt0_alt = c->TD[1], *h = c->TD[2], *h_alt = c->TD[3];
   c->Gcur = c->G2;
   if (dqmc_status s = td_measure(c, 0, gt0, h, c->G2)) return s;
@@ -1487,10 +1532,40 @@ dqmc_status td_pass(dqmc_ctx* c) {
         if (dqmc_status s = launch_right(k + 1)) return s;
       UDVp left = (k == nk) ? c->uid : c->slot(k);
       if (dqmc_status s = td_anchor(c, right_of(k), left, gt0, h)) return s;
+      if (c->td_sync && k < nk) HIPCHK(hipEventRecord((*c->td_sync)[k], c->stream));   // slot k is read
     }
     if (dqmc_status s = td_measure(c, tau, gt0, h, c->G2)) return s;
   }
+  if (c->td_sync) HIPCHK(hipEventRecord((*c->td_sync)[nk], c->stream));
   c->Gcur = c->G;
+  return DQMC_OK;
+}
+
+// The time-displaced pass of a single chain on the second stream, beside the
+// sweep (which then waits for td_ev[0] before it overwrites G, for td_ev[k]
+// before it stores its right form in slot k, and for td_ev[nk] before the
+// downward pass writes the field back).  The pass runs in the chain's shadow
+// context: the chain's G, field, left forms and bins, its own scratch.
+dqmc_status td_pass_async(dqmc_ctx* c) {
+  dqmc_ctx* t = c->tdc;
+  t->m = c->m;
+  t->gemm_tile = c->gemm_tile;
+  t->td_norb = c->td_norb; t->td_cells = c->td_cells; t->td_corr_now = c->td_corr_now;
+  t->eq_L1 = c->eq_L1; t->eq_L2 = c->eq_L2; t->eq_norb = c->eq_norb;
+  HIPCHK(hipEventRecord(c->fork_ev[2], c->stream));
+  HIPCHK(hipStreamWaitEvent(c->side, c->fork_ev[2], 0));
+  t->stream = c->side;
+  t->side = c->side2;
+  t->td_sync = &c->td_ev;
+  const dqmc_status s = td_pass(t);
+  t->side = nullptr;     // owned by c
+  t->td_sync = nullptr;
+  t->stream = c->stream;
+  if (s) {
+    c->err = t->err;
+    return s;
+  }
+  HIPCHK(hipStreamWaitEvent(c->stream, c->td_ev[0], 0));
   return DQMC_OK;
 }
 
@@ -1747,6 +1822,44 @@ dqmc_status dqmc_ctx_sizes(const dqmc_ctx* c, dqmc_sizes* out) {
 
 namespace {
 
+// The context of the time-displaced pass that runs beside the sweep of a
+// single chain: the model and sizes of c, its scratch in the shadow part of
+// the work buffer, c's shared matrices, c's G, field and stored forms (read
+// only) and c's time-displaced bins, precision record and error flag.
+dqmc_status shadow_setup(dqmc_ctx* c) {
+  if (!c->shadow_base) return fail(c, DQMC_E_STATE, "no shadow part in the work buffer");
+  if (!c->tdc) {
+    c->tdc = new (std::nothrow) dqmc_ctx();
+    if (!c->tdc) return fail(c, DQMC_E_NOMEM, "no host memory for the time-displaced pass's context");
+  }
+  dqmc_ctx* t = c->tdc;
+  t->m = c->m;
+  t->N = c->N; t->L = c->L; t->nw = c->nw; t->nk = c->nk; t->nb = c->nb; t->Nf = c->Nf;
+  t->K = c->K; t->trK = c->trK; t->normK1 = c->normK1; t->trK_field = c->trK_field;
+  t->nch = 1; t->cs = 0; t->no_shadow = true;
+  layout_chain(t, c->shadow_base);
+  if (!t->XA || !t->tdpart || !t->TD[3] || !t->Uinv)
+    return fail(c, DQMC_E_STATE, "the time-displaced pass's scratch is not laid out");
+  t->E = c->E; t->Einv = c->Einv; t->Eh = c->Eh; t->Ehinv = c->Ehinv; t->Kd = c->Kd; t->uid = c->uid;
+  t->gbuf = c->gbuf; t->kph = c->kph; t->korb = c->korb; t->eq_sign = c->eq_sign; t->eq_site = c->eq_site;
+  t->shared_lo = c->shared_lo; t->shared_hi = c->shared_hi;
+  t->G = c->G; t->field = c->field; t->slots = c->slots; t->work = c->work;
+  t->tdS = c->tdS; t->tdbins = c->tdbins; t->td_corr = c->td_corr; t->td_g00 = c->td_g00; t->gprec = c->gprec;
+  t->err_flag = c->err_flag;
+  t->stream = c->stream;
+  t->bound = true;
+  for (hipEvent_t& e : t->fork_ev)
+    if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  while ((int)c->td_ev.size() < c->nk + 1) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    c->td_ev.push_back(e);
+  }
+  if (!c->side2) HIPCHK(hipStreamCreateWithFlags(&c->side2, hipStreamNonBlocking));
+  // the completion counter of the estimator's partial records starts at zero
+  return fill_small(t, t->tdpart, td_part_size(t), 0.0);
+}
+
 // Device-side set-up of a bound context (one chain or a group of chains):
 // exponentials, identity UDV, zeroed counters and the chains' Philox keys.
 dqmc_status setup_device(dqmc_ctx* c) {
@@ -1777,6 +1890,8 @@ dqmc_status setup_device(dqmc_ctx* c) {
     HIPCHK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
     for (hipEvent_t& e : c->fork_ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   }
+  if (wants_shadow(c))
+    if (dqmc_status s = shadow_setup(c)) return s;
   // chain keys: host -> staging buffer -> counters[3] of every chain
   HIPCHK(hipMemcpyAsync(c->gbuf, c->seeds.data(), sizeof(uint64_t) * c->nch, hipMemcpyHostToDevice, c->stream));
   hipLaunchKernelGGL(k_scatter, dim3(1, c->nch), dim3(64), 0, c->stream, reinterpret_cast<double*>(c->counters + 3),
@@ -2388,6 +2503,7 @@ dqmc_status dqmc_batch_create(int32_t n_chains, const dqmc_model* models, const 
       dqmc_status s = dqmc_create(&models[i], K[i], nullptr, &c);
       if (s != DQMC_OK) { delete b; return s; }
       c->nch = 0;
+      c->no_shadow = true;   // a group's buffers are laid out by place_group, without a shadow part
       b->groups.push_back(c);
       first_of.push_back(i);
       g = (int)first_of.size() - 1;
@@ -2799,6 +2915,7 @@ dqmc_status dqmc_green_scratch_noalloc(dqmc_ctx* c, const double* field_dev, int
   // a host-side context of its own: model and hopping from c, every device
   // pointer inside the static array (c's own binding, if any, is untouched)
   dqmc_ctx t;
+  t.no_shadow = true;
   t.m = c->m;
   t.N = c->N; t.L = c->L; t.nw = c->nw; t.nk = c->nk; t.nb = c->nb;
   t.Nf = c->Nf; t.cplx = c->cplx; t.trK_field = c->trK_field;
