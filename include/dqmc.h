@@ -428,7 +428,11 @@ dqmc_status dqmc_batch_create(int32_t n_chains, const dqmc_model* models, const 
 /* Bytes of the single caller-owned device buffer that holds every chain. */
 dqmc_status dqmc_batch_query_size(const dqmc_batch* b, size_t* work_bytes);
 /* Bind that buffer (256-byte aligned) and the stream; computes the
- * exponentials once per group. */
+ * exponentials once per group.  With more than one group it also creates one
+ * stream per group (default priority, owned by the batch and destroyed with
+ * it): sweeps and captures run each group on its own stream, forked from the
+ * bound stream and joined back into it, so every call still completes in the
+ * bound stream's order. */
 dqmc_status dqmc_batch_bind(dqmc_batch* b, void* work, void* hip_stream);
 dqmc_status dqmc_batch_random_fields(dqmc_batch* b);
 dqmc_status dqmc_batch_set_state(dqmc_batch* b, int32_t chain, const double* field_host, uint64_t sweep_counter);

@@ -2387,11 +2387,19 @@ struct dqmc_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   int graph_sweeps = 0, graph_measure = -1;
+  // with several groups, one stream per group (default priority) and the
+  // events that fork it from the batch stream and join it back
+  std::vector<hipStream_t> gstream;
+  std::vector<hipEvent_t> gjoin;
+  hipEvent_t gfork = nullptr;
   std::string err;
   ~dqmc_batch() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
     for (dqmc_ctx* g : groups) delete g;
+    for (hipEvent_t e : gjoin) (void)hipEventDestroy(e);
+    if (gfork) (void)hipEventDestroy(gfork);
+    for (hipStream_t s : gstream) (void)hipStreamDestroy(s);
   }
 };
 
@@ -2473,6 +2481,42 @@ bool layout_ok(const dqmc_ctx* c, const double* lo, const double* hi) {
   return ok;
 }
 
+// Sweep flags of one group for a batch call's measure flags: bit 0 the
+// equal-time estimators, bit 1 the time-displaced pass and bit 2 the
+// lattice-resolved correlations, each where the group has been set up for it.
+int group_flags(const dqmc_ctx* c, int measure) {
+  return (measure & 1) | (((measure & 2) && c->td_norb > 0) ? 2 : 0) | (((measure & 4) && c->eq_norb > 0) ? 4 : 0);
+}
+
+// One sweep of every group.  Groups touch disjoint parts of the work buffer,
+// so with several groups each sweeps on a stream of its own, forked from the
+// batch stream and joined back into it by events (a capture records them as
+// parallel branches); the launches of one group then fill the CUs that
+// another group's latency-bound steps leave idle.
+dqmc_status sweep_groups(dqmc_batch* b, int measure) {
+  if (b->gstream.size() != b->groups.size()) {
+    for (dqmc_ctx* c : b->groups)
+      if (dqmc_status r = sweep_once(c, group_flags(c, measure))) return bfail(b, r, c->err);
+    return DQMC_OK;
+  }
+  BHIPCHK_(hipEventRecord(b->gfork, b->stream));
+  dqmc_status first = DQMC_OK;
+  std::string why;
+  for (size_t g = 0; g < b->groups.size(); ++g) {
+    dqmc_ctx* c = b->groups[g];
+    BHIPCHK_(hipStreamWaitEvent(b->gstream[g], b->gfork, 0));
+    c->stream = b->gstream[g];
+    const dqmc_status r = sweep_once(c, group_flags(c, measure));
+    c->stream = b->stream;
+    if (r && !first) { first = r; why = c->err; }
+    // joined even after a failure, so that a capture stays well formed
+    BHIPCHK_(hipEventRecord(b->gjoin[g], b->gstream[g]));
+    BHIPCHK_(hipStreamWaitEvent(b->stream, b->gjoin[g], 0));
+    if (r) break;
+  }
+  return first ? bfail(b, first, why) : DQMC_OK;
+}
+
 dqmc_status batch_flags(dqmc_batch* b) {
   for (dqmc_ctx* g : b->groups)
     if (dqmc_status s = read_flag(g)) return bfail(b, s, g->err);
@@ -2547,6 +2591,17 @@ dqmc_status dqmc_batch_bind(dqmc_batch* b, void* work, void* stream) {
   }
   for (dqmc_ctx* c : b->groups)
     if (dqmc_status s = setup_device(c)) return bfail(b, s, c->err);
+  if (b->groups.size() > 1 && b->gstream.empty()) {
+    BHIPCHK_(hipEventCreateWithFlags(&b->gfork, hipEventDisableTiming));
+    for (size_t g = 0; g < b->groups.size(); ++g) {
+      hipStream_t st = nullptr;
+      hipEvent_t ev = nullptr;
+      BHIPCHK_(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+      b->gstream.push_back(st);
+      BHIPCHK_(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+      b->gjoin.push_back(ev);
+    }
+  }
   b->bound = true;
   return DQMC_OK;
 }
@@ -2600,13 +2655,6 @@ dqmc_status dqmc_batch_init(dqmc_batch* b) {
   return DQMC_OK;
 }
 
-// Sweep flags of one group for a batch call's measure flags: bit 0 the
-// equal-time estimators, bit 1 the time-displaced pass and bit 2 the
-// lattice-resolved correlations, each where the group has been set up for it.
-int group_flags(const dqmc_ctx* c, int measure) {
-  return (measure & 1) | (((measure & 2) && c->td_norb > 0) ? 2 : 0) | (((measure & 4) && c->eq_norb > 0) ? 4 : 0);
-}
-
 dqmc_status dqmc_batch_sweep(dqmc_batch* b, int32_t n_sweeps, int32_t measure, dqmc_stats* st) {
   if (!b || n_sweeps < 0) return bfail(b, DQMC_E_ARG, "bad arguments");
   if (measure & ~7) return bfail(b, DQMC_E_ARG, "unknown measurement flags");
@@ -2621,8 +2669,7 @@ dqmc_status dqmc_batch_sweep(dqmc_batch* b, int32_t n_sweeps, int32_t measure, d
     }
   }
   for (int s = 0; s < left; ++s)
-    for (dqmc_ctx* c : b->groups)
-      if (dqmc_status r = sweep_once(c, group_flags(c, measure))) return bfail(b, r, c->err);
+    if (dqmc_status r = sweep_groups(b, measure)) return r;
   if (dqmc_status r = batch_flags(b)) return r;
   const auto t1 = std::chrono::steady_clock::now();
   if (st) {
@@ -2655,9 +2702,7 @@ dqmc_status dqmc_batch_capture(dqmc_batch* b, int32_t sweeps_per_graph, int32_t 
   if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
   BHIPCHK_(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
   dqmc_status st = DQMC_OK;
-  for (int s = 0; s < sweeps_per_graph && st == DQMC_OK; ++s)
-    for (dqmc_ctx* c : b->groups)
-      if ((st = sweep_once(c, group_flags(c, measure))) != DQMC_OK) break;
+  for (int s = 0; s < sweeps_per_graph && st == DQMC_OK; ++s) st = sweep_groups(b, measure);
   hipError_t ce = hipStreamEndCapture(b->stream, &b->graph);
   if (st != DQMC_OK) return bfail(b, st, "capture failed");
   BHIPCHK_(ce);
