@@ -29,6 +29,10 @@
 namespace {
 
 constexpr int kBlock = 32;   // sites per decision block
+// largest N with 32-column QR and LU panels: above it 16-column panels and,
+// for single chains, the latency-oriented accumulation and back substitution
+// (honeycomb 12x12, N = 288: 47.0 -> 46.4 ms per sweep)
+constexpr int kNarrowMaxN = 256;
 
 struct UDVp { double* Q; double* D; double* T; };
 
@@ -480,7 +484,7 @@ void qr_panel_launch(dqmc_ctx* c, double* Ap, int j0, int nbw, double* V, double
 }
 
 // rows per lane = ceil(h / 64), rounded up to the instantiated counts; the
-// panel width is 32 for N <= 384, 16 for N <= 768, 8 above (set in create)
+// panel width is 32 for N <= kNarrowMaxN, 16 for N <= 768, 8 above (set in create)
 dqmc_status launch_qr_panel(dqmc_ctx* c, double* Ap, int j0, int nbw, double* V, double* VT) {
   const int rows = (c->N - j0 + 63) / 64;
   if (c->nb == 32 && rows <= 2) qr_panel_launch<32, 2>(c, Ap, j0, nbw, V, VT);
@@ -555,7 +559,7 @@ hipError_t lds_limit_qr() {
 
 template <int NBW, int MR>
 hipError_t lds_limit_lu() {
-  // the staged panel: at most 384 x 33, 768 x 17 or 1024 x 9 doubles (about
+  // the staged panel: at most 256 x 33, 768 x 17 or 1024 x 9 doubles (about
   // 104 KB), beside about 24 KB of static LDS
   return hipFuncSetAttribute(reinterpret_cast<const void*>(k_lu_step<NBW, MR>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, 108 * 1024);
@@ -577,10 +581,10 @@ dqmc_status set_lds_limits(dqmc_ctx* c) {
   HIPCHK(gemm64_set_lds());
   HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(k_accum_q), hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)(sizeof(double) * 16 * (size_t)c->N)));
-  if (c->N > 384 && c->N <= kBackWideMaxN)
+  if (c->N > kNarrowMaxN && c->N <= kBackWideMaxN)
     HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(k_lu_back_wide),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)back_wide_lds(c->N)));
-  if (c->N > 384 && c->N <= kAccumWideMaxN) {
+  if (c->N > kNarrowMaxN && c->N <= kAccumWideMaxN) {
     HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(k_accum_q_wide<1>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)accum_q_lds<1>(c->N)));
     HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(k_accum_q_wide<2>),
@@ -627,9 +631,9 @@ dqmc_status qr_udv(dqmc_ctx* c, double* M, const double* T_in, UDVp out) {
   }
   // explicit Q by backward accumulation of the block reflectors, every
   // 16-column slab through all panels in one launch
-  // the sixteen-wave accumulation pays where panels are 16 wide (N > 384)
+  // the sixteen-wave accumulation pays where panels are 16 wide (N > kNarrowMaxN)
   // and a lone chain leaves the chip idle; batches keep the four-wave kernel
-  if (N > 384 && N <= kAccumWideMaxN && c->nch == 1) {
+  if (N > kNarrowMaxN && N <= kAccumWideMaxN && c->nch == 1) {
     if (nb > 16)
       hipLaunchKernelGGL(k_accum_q_wide<2>, gridc(c, (unsigned)((N + 15) / 16)), dim3(64 * kAccumWaves),
                          accum_q_lds<2>(N), c->stream, c->Vall, c->VTall, out.Q, N, nb, c->cs);
@@ -748,7 +752,7 @@ dqmc_status lu_solve(dqmc_ctx* c, double* XA, int nrhs, int ld, double* logdet) 
   constexpr int bs = 32;
   const int nblk = (N + bs - 1) / bs;
   hipLaunchKernelGGL(k_lu_diag_inv, gridc(c, (unsigned)nblk), dim3(256), 0, c->stream, XA, N, ld, bs, c->Uinv, c->cs);
-  if (N > 384 && N <= kBackWideMaxN && c->nch == 1)   // likewise
+  if (N > kNarrowMaxN && N <= kBackWideMaxN && c->nch == 1)   // likewise
     hipLaunchKernelGGL(k_lu_back_wide, gridc(c, (unsigned)((nrhs + kBackCols - 1) / kBackCols)), dim3(64 * kBackWaves),
                        back_wide_lds(N), c->stream, XA, N, ld, bs, nrhs, c->Uinv, c->cs);
   else
@@ -1674,7 +1678,7 @@ dqmc_status dqmc_create(const dqmc_model* m, const double* K, const int32_t* ver
   c->L = m->n_slices; c->nw = m->n_wrap; c->nk = m->n_slices / m->n_wrap;
   // panel width: the register panels hold up to 48 rows per thread in
   // 256/nb row groups
-  c->nb = (Nd <= 8 * 48) ? 32 : (Nd <= 16 * 48 ? 16 : 8);
+  c->nb = (Nd <= kNarrowMaxN) ? 32 : (Nd <= 16 * 48 ? 16 : 8);
   c->K.assign((size_t)Nd * Nd, 0.0);
   for (int i = 0; i < N; ++i)
     for (int j = 0; j < N; ++j) {
