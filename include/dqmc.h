@@ -442,11 +442,12 @@ dqmc_status dqmc_batch_init(dqmc_batch* b);
 /* dqmc_set_chunk_kernel for every group of the batch; drops a captured graph. */
 dqmc_status dqmc_batch_set_chunk_kernel(dqmc_batch* b, int32_t enable);
 /* Autotuner: per group, times `trials` sweeps with each GEMM kernel (16 x 16
- * and 32 x 32 direct MFMA tiles, 64 x 64 LDS-staged tiles) and keeps the
- * fastest (the trial sweeps advance the chains like warm-up sweeps; a
- * captured graph is dropped). */
+ * and 32 x 32 direct MFMA tiles, 32 x 32 and 64 x 64 LDS-staged tiles) and
+ * keeps the fastest (the trial sweeps advance the chains like warm-up sweeps;
+ * a captured graph is dropped). */
 dqmc_status dqmc_batch_autotune(dqmc_batch* b, int32_t trials);
-/* The GEMM tile chosen for a chain's group (0 = size-based default). */
+/* The GEMM kernel chosen for a chain's group: 16 or 32 (direct tiles), 33
+ * (32 x 32 LDS-staged), 64 (64 x 64 LDS-staged), 0 = size-based default. */
 dqmc_status dqmc_batch_tuning(const dqmc_batch* b, int32_t chain, int32_t* gemm_tile);
 /* Record `sweeps_per_graph` sweeps of the whole batch into a hipGraph; later
  * dqmc_batch_sweep calls with the same measure flags replay it.  measure:

@@ -2738,7 +2738,7 @@ dqmc_status dqmc_batch_autotune(dqmc_batch* b, int32_t trials) {
   hipEvent_t e0, e1;
   BHIPCHK_(hipEventCreate(&e0));
   BHIPCHK_(hipEventCreate(&e1));
-  const int cands[3] = {16, 32, 64};
+  const int cands[4] = {16, 32, 33, 64};
   for (dqmc_ctx* c : b->groups) {
     float best = 0.0f;
     int pick = 0;

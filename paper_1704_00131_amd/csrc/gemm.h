@@ -335,6 +335,130 @@ __global__ __launch_bounds__(256) void k_gemm64_group(GemmGroup gg, int ntiles) 
   gemm64_tile<TA, TB>(gg.g[blockIdx.z], ntiles);
 }
 
+// 32 x 32 tiles staged through LDS like the 64 x 64 kernel (K in steps of
+// 32), on v_mfma_f64_4x4x4f64, with the operands of K-step t + 2 loaded while
+// the MFMAs of step t run (two register sets, two LDS buffers).  Wave (wr, wc)
+// owns the 16 x 16 quarter (wr, wc): four 4 x 16 strips, acc[r] in lane l is
+// D[m0 + 16 wr + 4 r + l / 16][n0 + 16 wc + l % 16].  LDS strides as for the
+// 64 x 64 kernel: rows of 32 k padded by 4; the column-contiguous layouts by 8
+// or 16, so that the four k rows a wave reads fall on different banks.
+constexpr int kL32 = 32, kL32K = 32;
+constexpr int kL32SA = kL32K + 4;    // A row-major [i][k]
+constexpr int kL32SAt = kL32 + 8;    // A^T        [k][i]
+constexpr int kL32SB = kL32 + 16;    // B row-major [k][j]
+constexpr int kL32SBt = kL32K + 4;   // B^T        [j][k]
+constexpr int kL32Asz = (kL32 * kL32SA > kL32K * kL32SAt) ? kL32 * kL32SA : kL32K * kL32SAt;
+constexpr int kL32Bsz = (kL32K * kL32SB > kL32 * kL32SBt) ? kL32K * kL32SB : kL32 * kL32SBt;
+
+// Unconditional loads of one K-step from clamped addresses (four of A and four
+// of B per thread, coalesced along the contiguous index).
+template <int TA, int TB>
+__device__ __forceinline__ void gemm32l_load(const GemmArgs& g, int m0, int n0, int k0, double (&ra)[4],
+                                             double (&rb)[4]) {
+  const int t = threadIdx.x, a = t >> 5, b = t & 31;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    ra[q] = TA ? g.A[(size_t)min(k0 + a + 8 * q, g.K - 1) * g.lda + min(m0 + b, g.M - 1)]
+               : g.A[(size_t)min(m0 + a + 8 * q, g.M - 1) * g.lda + min(k0 + b, g.K - 1)];
+    rb[q] = TB ? g.B[(size_t)min(n0 + a + 8 * q, g.N - 1) * g.ldb + min(k0 + b, g.K - 1)]
+               : g.B[(size_t)min(k0 + a + 8 * q, g.K - 1) * g.ldb + min(n0 + b, g.N - 1)];
+  }
+}
+
+// Zero outside the matrices, apply the k scaling, store into one LDS buffer.
+template <int TA, int TB>
+__device__ __forceinline__ void gemm32l_store(const GemmArgs& g, int m0, int n0, int k0, double (&ra)[4],
+                                              double (&rb)[4], double* As, double* Bs) {
+  const int t = threadIdx.x, a = t >> 5, b = t & 31;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int ai = TA ? m0 + b : m0 + a + 8 * q, ak = TA ? k0 + a + 8 * q : k0 + b;
+    const double ksc = (g.ks_mode && ak < g.K) ? scale_of(g.ks_mode, g.ks, g.ks_coef, ak) : 1.0;
+    const double av = (ai < g.M && ak < g.K) ? ra[q] * ksc : 0.0;
+    const int bj = TB ? n0 + a + 8 * q : n0 + b, bk = TB ? k0 + b : k0 + a + 8 * q;
+    const double bv = (bj < g.N && bk < g.K) ? rb[q] : 0.0;
+    if (TA) As[(a + 8 * q) * kL32SAt + b] = av;    // [k][i]
+    else As[(a + 8 * q) * kL32SA + b] = av;        // [i][k]
+    if (TB) Bs[(a + 8 * q) * kL32SBt + b] = bv;    // [j][k]
+    else Bs[(a + 8 * q) * kL32SB + b] = bv;        // [k][j]
+  }
+}
+
+template <int TA, int TB>
+__device__ __forceinline__ void gemm32l_tile(GemmArgs g, int ntiles) {
+  // physical workgroup -> logical tile: each XCD gets a contiguous range
+  const int per = (ntiles + kGXcd - 1) / kGXcd;
+  const int tile = (blockIdx.x % kGXcd) * per + blockIdx.x / kGXcd;
+  if (tile >= ntiles) return;
+  if (g.cstride) {
+    const size_t co = (size_t)blockIdx.y * g.cstride;
+    if (g.pc & PC_A) g.A += co;
+    if (g.pc & PC_B) g.B += co;
+    if (g.pc & PC_C) g.C += co;
+    if (g.pc & PC_RS) g.rs += co;
+    if (g.pc & PC_CS) g.cs += co;
+    if (g.pc & PC_KS) g.ks += co;
+  }
+  __shared__ double sl[2][kL32Asz + kL32Bsz];
+  const int tilesN = (g.N + kL32 - 1) / kL32;
+  const int m0 = (tile / tilesN) * kL32, n0 = (tile % tilesN) * kL32;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = w >> 1, wc = w & 1, lk = lane >> 4;
+  const int ia = wr * 16 + (lane & 3);   // A row of strip 0
+  const int jb = wc * 16 + (lane & 15);  // B column
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const int nt = (g.K + kL32K - 1) / kL32K;
+  auto mfmas = [&](const double* A_) {
+    const double* B_ = A_ + kL32Asz;
+#pragma unroll
+    for (int k4 = 0; k4 < kL32K; k4 += 4) {
+      const int k = k4 + lk;
+      const double bv = TB ? B_[jb * kL32SBt + k] : B_[k * kL32SB + jb];
+      double av[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) av[r] = TA ? A_[k * kL32SAt + ia + 4 * r] : A_[(ia + 4 * r) * kL32SA + k];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[r] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[r], bv, acc[r], 0, 0, 0);
+    }
+  };
+  // step t lives in buffer t % 2; register set 0 carries the even steps
+  double ra0[4], rb0[4], ra1[4], rb1[4];
+  gemm32l_load<TA, TB>(g, m0, n0, 0, ra0, rb0);
+  if (nt > 1) gemm32l_load<TA, TB>(g, m0, n0, kL32K, ra1, rb1);
+  gemm32l_store<TA, TB>(g, m0, n0, 0, ra0, rb0, sl[0], sl[0] + kL32Asz);
+  __syncthreads();
+  for (int t = 0; t < nt; t += 2) {
+    if (t + 2 < nt) gemm32l_load<TA, TB>(g, m0, n0, (t + 2) * kL32K, ra0, rb0);
+    mfmas(sl[0]);
+    if (t + 1 < nt) gemm32l_store<TA, TB>(g, m0, n0, (t + 1) * kL32K, ra1, rb1, sl[1], sl[1] + kL32Asz);
+    __syncthreads();
+    if (t + 1 >= nt) break;
+    if (t + 3 < nt) gemm32l_load<TA, TB>(g, m0, n0, (t + 3) * kL32K, ra1, rb1);
+    mfmas(sl[1]);
+    if (t + 2 < nt) gemm32l_store<TA, TB>(g, m0, n0, (t + 2) * kL32K, ra0, rb0, sl[0], sl[0] + kL32Asz);
+    __syncthreads();
+  }
+  const int col = n0 + jb;
+  if (col >= g.N) return;
+  const double cf = g.cs_mode ? scale_of(g.cs_mode, g.cs, g.cs_coef, col) : 1.0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = m0 + wr * 16 + 4 * r + lk;
+    if (row >= g.M) continue;
+    const double rf = g.rs_mode ? scale_of(g.rs_mode, g.rs, g.rs_coef, row) : 1.0;
+    double v = g.alpha * (rf * acc[r] * cf);
+    double* cp = g.C + (size_t)row * g.ldc + col;
+    if (g.beta != 0.0) v += g.beta * (*cp);
+    if (row == col) v += g.diag_add;
+    *cp = v;
+  }
+}
+
+template <int TA, int TB>
+__global__ __launch_bounds__(256) void k_gemm32l(GemmArgs g, int ntiles) {
+  gemm32l_tile<TA, TB>(g, ntiles);
+}
+
 __host__ __device__ inline GemmArgs gemm_args(int M, int N, int K, const double* A, int lda, int transA,
                                             const double* B, int ldb, int transB, double* C, int ldc,
                                             double alpha = 1.0, double beta = 0.0) {
@@ -392,12 +516,25 @@ static inline hipError_t launch_gemm_group(const GemmGroup& gg, int count, hipSt
   return hipGetLastError();
 }
 
-// Tile choice: g.tile = 16, 32 or 64 forces it (64: the LDS-staged kernel, an
-// autotuner candidate); 0 picks 32 x 32 tiles once there are enough of them
-// (over all chains) to cover the chip, else 16 x 16.
+// Tile choice: g.tile = 16, 32, 33 or 64 forces it (33: the LDS-staged
+// 32 x 32 kernel, 64: the LDS-staged 64 x 64 kernel, both autotuner
+// candidates); 0 picks the LDS-staged 32 x 32 kernel for batched products
+// with M, N and K of at least 96 (14.6 against 17.1 us for the direct 32 x 32
+// kernel and 15.2 us for 16 x 16 tiles over 64 chains of N = 100; at N = 64
+// and below the direct kernels are faster), else 32 x 32 direct tiles once
+// there are enough of them (over all chains) to cover the chip, else 16 x 16.
 static inline hipError_t launch_gemm(const GemmArgs& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
   const int nch = g.nch > 0 ? g.nch : 1;
+  if (g.tile == 33 || (g.tile == 0 && nch > 1 && g.M >= 96 && g.N >= 96 && g.K >= 96)) {
+    const int t = ((g.M + 31) / 32) * ((g.N + 31) / 32);
+    const dim3 grid((unsigned)(((t + kGXcd - 1) / kGXcd) * kGXcd), nch);
+    if (!g.transA && !g.transB) hipLaunchKernelGGL((k_gemm32l<0, 0>), grid, dim3(256), 0, s, g, t);
+    else if (!g.transA) hipLaunchKernelGGL((k_gemm32l<0, 1>), grid, dim3(256), 0, s, g, t);
+    else if (!g.transB) hipLaunchKernelGGL((k_gemm32l<1, 0>), grid, dim3(256), 0, s, g, t);
+    else hipLaunchKernelGGL((k_gemm32l<1, 1>), grid, dim3(256), 0, s, g, t);
+    return hipGetLastError();
+  }
   const int t64 = ((g.M + 63) / 64) * ((g.N + 63) / 64);
   if (g.tile == 64) {
     const unsigned blocks = (unsigned)(((t64 + kGXcd - 1) / kGXcd) * kGXcd);

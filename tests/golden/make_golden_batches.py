@@ -6,8 +6,8 @@ from the oracle only (never from the HIP path).
 c3 -> batched512_U4_b8_chains.npz: chains {0, 1, 255, 256, 383, 384, 511} of
 the 512-chain mixed batch (256 x 8x8, 128 x 6x6, 128 x 10x10; U = 4,
 beta = 8, dtau = 0.1, L = 80, n_wrap = 10, two-valued field, symmetric split,
-seed = chain index) after the sweeps the batch workload runs: three
-unmeasured sweeps (the autotuner's trials: one per GEMM tile) and one sweep
+seed = chain index) after the sweeps the batch workload runs: four
+unmeasured sweeps (the autotuner's trials: one per GEMM kernel) and one sweep
 with the equal-time estimators (the captured sweep).  Per chain: the field
 (signs, bit-packed), the diagonal of G(0) and 8 of its rows, the bin sums,
 the counts and the smallest |R - u| (near-tie guard).
@@ -51,7 +51,7 @@ def make_c3():
         f0 = hubbard.init_field(m)
         ch = sweep.Chain(m, f0).init()
         t0 = time.time()
-        for _ in range(3):
+        for _ in range(4):
             ch.sweep(measure=False)
         ch.sweep(measure=True)
         rows = g_rows(m.N)

@@ -7,7 +7,7 @@ runs it.
 - honeycomb 18x18 (N = 648, L = 200): one sweep with the equal-time
   estimators and the time-displaced pass; decisions bit-exact over all
   259,200 proposals, G(0) on its diagonal and 24 rows to 1e-9, bins;
-- the 512-chain mixed batch: autotuned (three trial sweeps), one captured
+- the 512-chain mixed batch: autotuned (four trial sweeps), one captured
   sweep replayed; seven chains across the three sizes and the group borders;
 - the 64-chain Gaussian batch (10x10, L = 40): gradients of six chains at
   every fourth slice, then one Monte Carlo step (a local sweep and ten
@@ -91,7 +91,7 @@ def test_batch512_sampled_chains_match_oracle():
         assert float(g["min_tie_%d" % c]) > 1e-9
         f, ctr = b.get_state(c)
         G, bins, st = b.read_chain(c)
-        assert ctr == 4, f"chain {c}"
+        assert ctr == 5, f"chain {c}"
         assert np.array_equal(_bits(f), g["field_bits_%d" % c]), f"chain {c}"
         assert [st.proposals, st.accepted] == list(g["counts_%d" % c]), f"chain {c}"
         assert maxabs(np.diag(G), g["G_diag_%d" % c]) < 1e-9, f"chain {c}"
