@@ -61,8 +61,9 @@ FP64_PEAK_TFLOPS = 78.6
 KERNEL_SRC = os.path.join(ROOT, "paper_1704_00131_amd", "csrc", "update.h")
 PMC_SUMMARY = {288: os.path.join(ROOT, "profiles", "block_update_pmc_honeycomb12.json"),
                648: os.path.join(ROOT, "profiles", "block_update_pmc_honeycomb18.json")}
-# event sample period, coprime with the block launches per slice (21 at N = 648, 9 at N = 288)
-TIMING_EVERY = 10
+# event sample period, coprime with the block launches per slice (21 at N = 648, 9 at N = 288);
+# each sampled launch costs its events about 2.7 us inside the timed sweeps
+TIMING_EVERY = 40
 KPOINT = (4.0 * 3.141592653589793 / 3.0, 0.0)
 
 

@@ -29,10 +29,13 @@
 namespace {
 
 constexpr int kBlock = 32;   // sites per decision block
-// largest N with 32-column QR and LU panels: above it 16-column panels and,
-// for single chains, the latency-oriented accumulation and back substitution
-// (honeycomb 12x12, N = 288: 47.0 -> 46.4 ms per sweep)
+// largest N with 32-column QR and LU panels (honeycomb 12x12, N = 288:
+// 47.0 -> 45.7 ms per sweep with 16-column panels)
 constexpr int kNarrowMaxN = 256;
+// smallest N above which a single chain takes the latency-oriented Q
+// accumulation and back substitution (at N = 288 they took 118 and 70 us
+// against 59 and 57 us for the four-wave kernels)
+constexpr int kWideMinN = 384;
 
 struct UDVp { double* Q; double* D; double* T; };
 
@@ -581,10 +584,10 @@ dqmc_status set_lds_limits(dqmc_ctx* c) {
   HIPCHK(gemm64_set_lds());
   HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(k_accum_q), hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)(sizeof(double) * 16 * (size_t)c->N)));
-  if (c->N > kNarrowMaxN && c->N <= kBackWideMaxN)
+  if (c->N > kWideMinN && c->N <= kBackWideMaxN)
     HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(k_lu_back_wide),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)back_wide_lds(c->N)));
-  if (c->N > kNarrowMaxN && c->N <= kAccumWideMaxN) {
+  if (c->N > kWideMinN && c->N <= kAccumWideMaxN) {
     HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(k_accum_q_wide<1>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)accum_q_lds<1>(c->N)));
     HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(k_accum_q_wide<2>),
@@ -631,9 +634,9 @@ dqmc_status qr_udv(dqmc_ctx* c, double* M, const double* T_in, UDVp out) {
   }
   // explicit Q by backward accumulation of the block reflectors, every
   // 16-column slab through all panels in one launch
-  // the sixteen-wave accumulation pays where panels are 16 wide (N > kNarrowMaxN)
+  // the sixteen-wave accumulation pays for the tall 16-wide panels of large N
   // and a lone chain leaves the chip idle; batches keep the four-wave kernel
-  if (N > kNarrowMaxN && N <= kAccumWideMaxN && c->nch == 1) {
+  if (N > kWideMinN && N <= kAccumWideMaxN && c->nch == 1) {
     if (nb > 16)
       hipLaunchKernelGGL(k_accum_q_wide<2>, gridc(c, (unsigned)((N + 15) / 16)), dim3(64 * kAccumWaves),
                          accum_q_lds<2>(N), c->stream, c->Vall, c->VTall, out.Q, N, nb, c->cs);
@@ -752,7 +755,7 @@ dqmc_status lu_solve(dqmc_ctx* c, double* XA, int nrhs, int ld, double* logdet) 
   constexpr int bs = 32;
   const int nblk = (N + bs - 1) / bs;
   hipLaunchKernelGGL(k_lu_diag_inv, gridc(c, (unsigned)nblk), dim3(256), 0, c->stream, XA, N, ld, bs, c->Uinv, c->cs);
-  if (N > kNarrowMaxN && N <= kBackWideMaxN && c->nch == 1)   // likewise
+  if (N > kWideMinN && N <= kBackWideMaxN && c->nch == 1)   // likewise
     hipLaunchKernelGGL(k_lu_back_wide, gridc(c, (unsigned)((nrhs + kBackCols - 1) / kBackCols)), dim3(64 * kBackWaves),
                        back_wide_lds(N), c->stream, XA, N, ld, bs, nrhs, c->Uinv, c->cs);
   else
