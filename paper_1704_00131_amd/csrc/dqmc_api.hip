@@ -1556,7 +1556,10 @@ dqmc_status td_pass(dqmc_ctx* c) {
 dqmc_status td_pass_async(dqmc_ctx* c) {
   dqmc_ctx* t = c->tdc;
   t->m = c->m;
-  t->gemm_tile = c->gemm_tile;
+  // beside the sweep the grouped products take the direct 32 x 32 kernel
+  // rather than the LDS-staged 64 x 64 one (18x18 sweep with its pass 289 ->
+  // 287 ms; alone the 64 x 64 tiles are faster)
+  t->gemm_tile = 32;
   t->td_norb = c->td_norb; t->td_cells = c->td_cells; t->td_corr_now = c->td_corr_now;
   t->eq_L1 = c->eq_L1; t->eq_L2 = c->eq_L2; t->eq_norb = c->eq_norb;
   HIPCHK(hipEventRecord(c->fork_ev[2], c->stream));
