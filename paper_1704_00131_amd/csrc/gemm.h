@@ -493,11 +493,14 @@ static inline hipError_t launch_gemm_group(const GemmGroup& gg, int count, hipSt
   const GemmArgs& g = gg.g[0];
   if (g.M <= 0 || g.N <= 0 || count < 1 || count > 3) return hipSuccess;
   const int nch = g.nch > 0 ? g.nch : 1;
-  // enough 64 x 64 tiles over the group to cover the chip: the LDS-staged kernel
+  // a single chain with enough 64 x 64 tiles over the group to cover the
+  // chip: the LDS-staged kernel (over many chains of small lattices the direct
+  // tiles are faster: 12.9 against 43.5 us for one product over 256 chains of
+  // N = 64)
   bool plain = true;
   for (int i = 0; i < count; ++i) plain = plain && !gg.g[i].transA && !gg.g[i].transB;
   const int t64 = ((g.M + 63) / 64) * ((g.N + 63) / 64);
-  if (plain && g.tile != 16 && g.tile != 32 && (long long)t64 * nch * count >= 240) {
+  if (plain && (g.tile == 64 || (g.tile == 0 && nch == 1 && (long long)t64 * count >= 240))) {
     const unsigned blocks = (unsigned)(((t64 + kGXcd - 1) / kGXcd) * kGXcd);
     hipLaunchKernelGGL((k_gemm64_group<0, 0>), dim3(blocks, nch, count), dim3(256), gemm64_lds(), s, gg, t64);
     return hipGetLastError();
