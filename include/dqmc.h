@@ -441,6 +441,11 @@ dqmc_status dqmc_batch_get_state(dqmc_batch* b, int32_t chain, double* field_hos
 dqmc_status dqmc_batch_init(dqmc_batch* b);
 /* dqmc_set_chunk_kernel for every group of the batch; drops a captured graph. */
 dqmc_status dqmc_batch_set_chunk_kernel(dqmc_batch* b, int32_t enable);
+/* With more than one group: 1 (the default) sweeps the groups side by side,
+ * each on its own stream; 0 one after the other on the bound stream.  The
+ * groups share no memory, so the results are bit-identical either way.  Drops
+ * a captured graph.  DQMC_E_ARG for other values. */
+dqmc_status dqmc_batch_set_side_by_side(dqmc_batch* b, int32_t enable);
 /* Autotuner: per group, times `trials` sweeps with each GEMM kernel (16 x 16
  * and 32 x 32 direct MFMA tiles, 32 x 32 and 64 x 64 LDS-staged tiles) and
  * keeps the fastest (the trial sweeps advance the chains like warm-up sweeps;

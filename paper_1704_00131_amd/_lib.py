@@ -67,6 +67,7 @@ SIGNATURES = {
                                             ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_void_p,
                                             ctypes.POINTER(ctypes.c_void_p)]),
     "dqmc_batch_set_chunk_kernel": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "dqmc_batch_set_side_by_side": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "dqmc_reset_bins": (ctypes.c_int, [ctypes.c_void_p]),
     "dqmc_green_scratch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "dqmc_green_scratch_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,

@@ -64,6 +64,12 @@ class Batch:
         self._chk(self.lib.dqmc_batch_set_chunk_kernel(self.b, -1 if enable is None else (1 if enable else 0)))
         return self
 
+    def side_by_side(self, enable=True):
+        """Groups on streams of their own (True, the default) or one after the
+        other on the bound stream (False); the results are bit-identical."""
+        self._chk(self.lib.dqmc_batch_set_side_by_side(self.b, 1 if enable else 0))
+        return self
+
     @property
     def n_groups(self):
         return self.lib.dqmc_batch_groups(self.b)

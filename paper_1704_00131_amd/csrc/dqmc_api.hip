@@ -2402,6 +2402,7 @@ struct dqmc_batch {
   std::vector<hipStream_t> gstream;
   std::vector<hipEvent_t> gjoin;
   hipEvent_t gfork = nullptr;
+  bool side_by_side = true;   // dqmc_batch_set_side_by_side
   std::string err;
   ~dqmc_batch() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
@@ -2504,7 +2505,7 @@ int group_flags(const dqmc_ctx* c, int measure) {
 // parallel branches); the launches of one group then fill the CUs that
 // another group's latency-bound steps leave idle.
 dqmc_status sweep_groups(dqmc_batch* b, int measure) {
-  if (b->gstream.size() != b->groups.size()) {
+  if (!b->side_by_side || b->gstream.size() != b->groups.size()) {
     for (dqmc_ctx* c : b->groups)
       if (dqmc_status r = sweep_once(c, group_flags(c, measure))) return bfail(b, r, c->err);
     return DQMC_OK;
@@ -2727,6 +2728,14 @@ dqmc_status dqmc_batch_capture(dqmc_batch* b, int32_t sweeps_per_graph, int32_t 
 // the fastest is kept.  The
 // trial sweeps advance the chains like warm-up sweeps; a captured graph is
 // dropped (it would replay the old tiles).
+dqmc_status dqmc_batch_set_side_by_side(dqmc_batch* b, int32_t enable) {
+  if (!b || enable < 0 || enable > 1) return bfail(b, DQMC_E_ARG, "bad arguments");
+  b->side_by_side = enable != 0;
+  if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
+  if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+  return DQMC_OK;
+}
+
 dqmc_status dqmc_batch_set_chunk_kernel(dqmc_batch* b, int32_t enable) {
   if (!b || enable < -1 || enable > 1) return bfail(b, DQMC_E_ARG, "bad arguments");
   for (dqmc_ctx* c : b->groups) c->fused = enable;

@@ -211,3 +211,35 @@ def test_batch_time_displaced_pass(graph, trotter):
         else:
             with pytest.raises(DQMCError):
                 b.td_read_bins(i)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_groups_side_by_side_are_bit_identical(graph):
+    """Four groups (8x8 x 20 chains on the chunk kernel, 6x6, 10x10 and a
+    honeycomb 5x5 chain) swept side by side on their own streams and one
+    after the other: fields, G, bins and counts agree bit for bit, plain and
+    replayed from a captured graph."""
+    _log(f"batch groups side by side graph={graph}")
+    specs = [("square", 8, 8, s) for s in range(20)] + [("square", 6, 6, 40), ("square", 6, 6, 41),
+                                                        ("square", 10, 10, 50), ("honeycomb", 5, 5, 60)]
+    a, _ = _batch(specs, 2.0, 10)
+    b, _ = _batch(specs, 2.0, 10)
+    assert a.n_groups == 4
+    b.side_by_side(False)
+    for x in (a, b):
+        x.random_fields().init()
+        if graph:
+            x.capture(1, measure=True)
+        x.sweep(2, measure=True)
+    for i in (0, 19, 20, 21, 22, 23):
+        fa, ca = a.get_state(i)
+        fb, cb = b.get_state(i)
+        assert ca == cb == 2
+        assert np.array_equal(fa, fb), f"chain {i}"
+        Ga, ba, sa = a.read_chain(i)
+        Gb, bb, sb = b.read_chain(i)
+        assert np.array_equal(Ga, Gb), f"chain {i}"
+        assert np.array_equal(ba, bb), f"chain {i}"
+        assert (sa.proposals, sa.accepted) == (sb.proposals, sb.accepted)
+    a.close()
+    b.close()
