@@ -447,6 +447,9 @@ dqmc_status update_slice(dqmc_ctx* c, int tau) {
   c->row_alt[tau - 1] ^= 1;
   double* fout = field_row(c, tau);
   const int tiles = ((N + 31) / 32) * ((N + 31) / 32);
+  // a single large chain: 64-row tiles, one workgroup per CU at N = 648
+  const bool tall = c->nch == 1 && N > kWideMinN;
+  const int tiles64 = ((N + 63) / 64) * ((N + 31) / 32);
   for (int s0 = 0; s0 < N; s0 += kBlock) {
     BlockArgs a;
     a.Gin = c->Gcur;
@@ -457,7 +460,11 @@ dqmc_status update_slice(dqmc_ctx* c, int tau) {
     a.counters = c->counters;
     a.cs = c->cs;
     if (dqmc_status s = timing_begin(c, DQMC_KERNEL_BLOCK_UPDATE)) return s;
-    if (c->m.n_col == 2)
+    if (tall && c->m.n_col == 2)
+      hipLaunchKernelGGL((k_block_update<2, 64>), gridc(c, tiles64), dim3(512), 0, c->stream, a);
+    else if (tall)
+      hipLaunchKernelGGL((k_block_update<1, 64>), gridc(c, tiles64), dim3(512), 0, c->stream, a);
+    else if (c->m.n_col == 2)
       hipLaunchKernelGGL(k_block_update<2>, gridc(c, tiles), dim3(256), 0, c->stream, a);
     else
       hipLaunchKernelGGL(k_block_update<1>, gridc(c, tiles), dim3(256), 0, c->stream, a);

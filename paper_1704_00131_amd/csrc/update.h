@@ -126,9 +126,14 @@ __device__ __forceinline__ double ipow(double r, int n) {
 // are visible; they read it with acquire.  One MFMA product on all four waves
 // finishes the tile.  Workgroup 0 also writes the block's field values and
 // the counters.
-template <int NCOL>
-__global__ __launch_bounds__(256) void k_block_update(BlockArgs a) {
-  __shared__ double AB[2][32][33];   // rows of X and of Z^T, for the product
+//
+// TR = 64: tiles of 64 rows and 32 columns on eight waves (wave 3 solves the
+// rows I+32.. of X), so that a single chain of N = 648 needs 231 workgroups,
+// one per CU, instead of 441, which put two on most CUs.
+template <int NCOL, int TR = 32>
+__global__ __launch_bounds__(8 * TR) void k_block_update(BlockArgs a) {
+  // rows of X (and, for TR = 64, of its second half in AB[2]) and of Z^T
+  __shared__ double AB[TR == 64 ? 3 : 2][32][33];
   // columns of c, each split by row parity: colc[i][(x & 1) * 16 + (x >> 1)] = c[x][i]
   __shared__ __attribute__((aligned(16))) double colc[32][32];
   __shared__ double gam[32];
@@ -142,7 +147,7 @@ __global__ __launch_bounds__(256) void k_block_update(BlockArgs a) {
     a.Gin += co; a.Gout += co; a.field_in += co; a.field_out += co; a.draws += co;
     a.counters = reinterpret_cast<unsigned long long*>(reinterpret_cast<double*>(a.counters) + co);
   }
-  const int I0 = (blockIdx.x / tilesN) << 5, J0 = (blockIdx.x % tilesN) << 5;
+  const int I0 = (blockIdx.x / tilesN) * TR, J0 = (blockIdx.x % tilesN) << 5;
   const int wr = w >> 1, wc = w & 1;
   // this thread's four output elements of Gin, fetched early
   const int col = J0 + wc * 16 + (lane & 15);
@@ -177,17 +182,19 @@ __global__ __launch_bounds__(256) void k_block_update(BlockArgs a) {
       const int e = 64 * j + lane, rr = e >> 5, cc = e & 31;
       AB[1][rr][cc] = (rr < bb && cc < bb) ? c[j] : 0.0;
     }
-  } else if (w == 1) {
-    // right-hand side of X, Gin[I0+r][s0+k], through LDS: two rows per load
+  } else if (w == 1 || (TR == 64 && w == 3)) {
+    // right-hand side of X, Gin[r0+r][s0+k], through LDS: two rows per load
+    const int r0 = (w == 1) ? I0 : I0 + 32;
+    double (*st)[33] = AB[(w == 1) ? 0 : TR / 32];
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       const int e = 64 * j + lane, rr = e >> 5, cc = e & 31;
-      R[j] = a.Gin[(size_t)min(I0 + rr, N - 1) * N + s0 + min(cc, bb - 1)];
+      R[j] = a.Gin[(size_t)min(r0 + rr, N - 1) * N + s0 + min(cc, bb - 1)];
     }
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       const int e = 64 * j + lane, rr = e >> 5, cc = e & 31;
-      AB[0][rr][cc] = (I0 + rr < N && cc < bb) ? R[j] : 0.0;
+      st[rr][cc] = (r0 + rr < N && cc < bb) ? R[j] : 0.0;
     }
   } else if (w == 2) {
     // right-hand side of Z^T: delta - Gin[s0+k][J0+fr]
@@ -242,11 +249,12 @@ __global__ __launch_bounds__(256) void k_block_update(BlockArgs a) {
     __hip_atomic_store(&vis, bb + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     if (lane == 0) nacc_s = nacc;
     if (blockIdx.x == 0 && lane < bb) a.field_out[s0 + lane] = myacc ? snew : sold;
-  } else if (w == 1) {
+  } else if (w == 1 || (TR == 64 && w == 3)) {
     // X, left-looking: step k needs column k and gamma_m for m < k (vis > k).
     // P[j] = gamma_m X[fr][m] for the final entries m = 2 j + sub, else 0.
+    double (*st)[33] = AB[(w == 1) ? 0 : TR / 32];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) R[j] = AB[0][fr][2 * j + sub];
+    for (int j = 0; j < 16; ++j) R[j] = st[fr][2 * j + sub];
     double P[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) P[j] = 0.0;
@@ -267,7 +275,7 @@ __global__ __launch_bounds__(256) void k_block_update(BlockArgs a) {
       }
     }
 #pragma unroll
-    for (int j = 0; j < 16; ++j) AB[0][fr][2 * j + sub] = R[j];
+    for (int j = 0; j < 16; ++j) st[fr][2 * j + sub] = R[j];
   } else if (w == 2) {
     // Z^T, right-looking: step m needs column m and gamma_m (vis > m + 1),
     // fetched together; the last step would only touch entries past the
@@ -308,7 +316,7 @@ __global__ __launch_bounds__(256) void k_block_update(BlockArgs a) {
 #pragma unroll
   for (int k0 = 0; k0 < 32; k0 += 4) {
     const int k = k0 + (lane >> 4);
-    const double av_ = AB[0][wr * 16 + (lane & 15)][k] * gam[k];
+    const double av_ = AB[(wr >= 2) ? 2 : 0][(wr & 1) * 16 + (lane & 15)][k] * gam[k];
     const double bv_ = AB[1][wc * 16 + (lane & 15)][k];
     acc2 = mfma_f64_16x16x4(av_, bv_, acc2);
   }
