@@ -447,8 +447,9 @@ dqmc_status update_slice(dqmc_ctx* c, int tau) {
   c->row_alt[tau - 1] ^= 1;
   double* fout = field_row(c, tau);
   const int tiles = ((N + 31) / 32) * ((N + 31) / 32);
-  // a single large chain: 64-row tiles, one workgroup per CU at N = 648
-  const bool tall = c->nch == 1 && N > kWideMinN;
+  // a single large chain: 64-row tiles, one workgroup per CU at N = 648;
+  // batches of N >= 96: half the workgroups repeating each block's decisions
+  const bool tall = (c->nch == 1 && N > kWideMinN) || (c->nch > 1 && N >= 96);
   const int tiles64 = ((N + 63) / 64) * ((N + 31) / 32);
   for (int s0 = 0; s0 < N; s0 += kBlock) {
     BlockArgs a;
