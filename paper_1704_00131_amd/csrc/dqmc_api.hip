@@ -448,9 +448,12 @@ dqmc_status update_slice(dqmc_ctx* c, int tau) {
   double* fout = field_row(c, tau);
   const int tiles = ((N + 31) / 32) * ((N + 31) / 32);
   // a single large chain: 64-row tiles, one workgroup per CU at N = 648;
-  // batches of N >= 96: half the workgroups repeating each block's decisions
-  const bool tall = (c->nch == 1 && N > kWideMinN) || (c->nch > 1 && N >= 96);
+  // batches of N >= 96: 128-row tiles, a quarter of the workgroups repeating
+  // each block's decisions
+  const bool tall = c->nch == 1 && N > kWideMinN;
+  const bool tall4 = c->nch > 1 && N >= 96;
   const int tiles64 = ((N + 63) / 64) * ((N + 31) / 32);
+  const int tiles128 = ((N + 127) / 128) * ((N + 31) / 32);
   for (int s0 = 0; s0 < N; s0 += kBlock) {
     BlockArgs a;
     a.Gin = c->Gcur;
@@ -461,7 +464,11 @@ dqmc_status update_slice(dqmc_ctx* c, int tau) {
     a.counters = c->counters;
     a.cs = c->cs;
     if (dqmc_status s = timing_begin(c, DQMC_KERNEL_BLOCK_UPDATE)) return s;
-    if (tall && c->m.n_col == 2)
+    if (tall4 && c->m.n_col == 2)
+      hipLaunchKernelGGL((k_block_update<2, 128>), gridc(c, tiles128), dim3(1024), 0, c->stream, a);
+    else if (tall4)
+      hipLaunchKernelGGL((k_block_update<1, 128>), gridc(c, tiles128), dim3(1024), 0, c->stream, a);
+    else if (tall && c->m.n_col == 2)
       hipLaunchKernelGGL((k_block_update<2, 64>), gridc(c, tiles64), dim3(512), 0, c->stream, a);
     else if (tall)
       hipLaunchKernelGGL((k_block_update<1, 64>), gridc(c, tiles64), dim3(512), 0, c->stream, a);

@@ -127,13 +127,16 @@ __device__ __forceinline__ double ipow(double r, int n) {
 // finishes the tile.  Workgroup 0 also writes the block's field values and
 // the counters.
 //
-// TR = 64: tiles of 64 rows and 32 columns on eight waves (wave 3 solves the
-// rows I+32.. of X), so that a single chain of N = 648 needs 231 workgroups,
-// one per CU, instead of 441, which put two on most CUs.
+// TR = 64 or 128: tiles of TR rows and 32 columns on TR / 8 waves, the odd
+// waves 1, 3, 5, 7 solving the rows of X in groups of 32 (so that a single
+// chain of N = 648 needs 231 workgroups, one per CU, instead of 441, which put
+// two on most CUs; and a batch repeats each block's decisions in fewer
+// workgroups).
 template <int NCOL, int TR = 32>
 __global__ __launch_bounds__(8 * TR) void k_block_update(BlockArgs a) {
-  // rows of X (and, for TR = 64, of its second half in AB[2]) and of Z^T
-  __shared__ double AB[TR == 64 ? 3 : 2][32][33];
+  // rows of X for row group 0 in AB[0], of Z^T in AB[1], of X for row group
+  // g >= 1 in AB[g + 1]
+  __shared__ double AB[TR / 32 + 1][32][33];
   // columns of c, each split by row parity: colc[i][(x & 1) * 16 + (x >> 1)] = c[x][i]
   __shared__ __attribute__((aligned(16))) double colc[32][32];
   __shared__ double gam[32];
@@ -182,10 +185,10 @@ __global__ __launch_bounds__(8 * TR) void k_block_update(BlockArgs a) {
       const int e = 64 * j + lane, rr = e >> 5, cc = e & 31;
       AB[1][rr][cc] = (rr < bb && cc < bb) ? c[j] : 0.0;
     }
-  } else if (w == 1 || (TR == 64 && w == 3)) {
+  } else if ((w & 1) && (w >> 1) < TR / 32) {
     // right-hand side of X, Gin[r0+r][s0+k], through LDS: two rows per load
-    const int r0 = (w == 1) ? I0 : I0 + 32;
-    double (*st)[33] = AB[(w == 1) ? 0 : TR / 32];
+    const int xg = w >> 1, r0 = I0 + 32 * xg;
+    double (*st)[33] = AB[xg == 0 ? 0 : xg + 1];
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       const int e = 64 * j + lane, rr = e >> 5, cc = e & 31;
@@ -249,10 +252,11 @@ __global__ __launch_bounds__(8 * TR) void k_block_update(BlockArgs a) {
     __hip_atomic_store(&vis, bb + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     if (lane == 0) nacc_s = nacc;
     if (blockIdx.x == 0 && lane < bb) a.field_out[s0 + lane] = myacc ? snew : sold;
-  } else if (w == 1 || (TR == 64 && w == 3)) {
+  } else if ((w & 1) && (w >> 1) < TR / 32) {
     // X, left-looking: step k needs column k and gamma_m for m < k (vis > k).
     // P[j] = gamma_m X[fr][m] for the final entries m = 2 j + sub, else 0.
-    double (*st)[33] = AB[(w == 1) ? 0 : TR / 32];
+    const int xg = w >> 1;
+    double (*st)[33] = AB[xg == 0 ? 0 : xg + 1];
 #pragma unroll
     for (int j = 0; j < 16; ++j) R[j] = st[fr][2 * j + sub];
     double P[16];
@@ -316,7 +320,7 @@ __global__ __launch_bounds__(8 * TR) void k_block_update(BlockArgs a) {
 #pragma unroll
   for (int k0 = 0; k0 < 32; k0 += 4) {
     const int k = k0 + (lane >> 4);
-    const double av_ = AB[(wr >= 2) ? 2 : 0][(wr & 1) * 16 + (lane & 15)][k] * gam[k];
+    const double av_ = AB[(wr >> 1) == 0 ? 0 : (wr >> 1) + 1][(wr & 1) * 16 + (lane & 15)][k] * gam[k];
     const double bv_ = AB[1][wc * 16 + (lane & 15)][k];
     acc2 = mfma_f64_16x16x4(av_, bv_, acc2);
   }
