@@ -34,9 +34,15 @@ struct GemmArgs {
 };
 enum { PC_A = 1, PC_B = 2, PC_C = 4, PC_RS = 8, PC_CS = 16, PC_KS = 32 };
 
-template <int TILE, int UNR, int WV>
+// TA, TB, KS: the transposes and whether the k scaling is present, fixed at
+// compile time (0 or 1) or read from g (-1); the fixed forms keep the runtime
+// selects out of the K loop (23.0 against 25.9 us for a 648^3 product).
+template <int TILE, int UNR, int WV, int TA = -1, int TB = -1, int KS = -1>
 __device__ __forceinline__ void gemm_tile(GemmArgs g) {
   constexpr int NB = TILE / 16;
+  const bool ta = TA < 0 ? g.transA != 0 : TA != 0;
+  const bool tb = TB < 0 ? g.transB != 0 : TB != 0;
+  const bool ksm = KS < 0 ? g.ks_mode != 0 : KS != 0;
   if (g.cstride) {
     const size_t co = (size_t)blockIdx.y * g.cstride;
     if (g.pc & PC_A) g.A += co;
@@ -72,19 +78,19 @@ __device__ __forceinline__ void gemm_tile(GemmArgs g) {
 #pragma unroll
       for (int a = 0; a < NB; ++a) {
         const int row = min(i0 + a * 16 + l16, g.M - 1);
-        av[u][a] = g.transA ? g.A[(size_t)kk * g.lda + row] : g.A[(size_t)row * g.lda + kk];
+        av[u][a] = ta ? g.A[(size_t)kk * g.lda + row] : g.A[(size_t)row * g.lda + kk];
       }
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         const int col = min(j0 + b * 16 + l16, g.N - 1);
-        bv[u][b] = g.transB ? g.B[(size_t)col * g.ldb + kk] : g.B[(size_t)kk * g.ldb + col];
+        bv[u][b] = tb ? g.B[(size_t)col * g.ldb + kk] : g.B[(size_t)kk * g.ldb + col];
       }
     }
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
       const int k = kc + 4 * u + lk;
       const bool kin = k < ke;
-      const double ksc = (kin && g.ks_mode) ? scale_of(g.ks_mode, g.ks, g.ks_coef, k) : 1.0;
+      const double ksc = (kin && ksm) ? scale_of(g.ks_mode, g.ks, g.ks_coef, k) : 1.0;
 #pragma unroll
       for (int a = 0; a < NB; ++a) av[u][a] = (kin && i0 + a * 16 + l16 < g.M) ? av[u][a] * ksc : 0.0;
 #pragma unroll
@@ -133,9 +139,25 @@ __device__ __forceinline__ void gemm_tile(GemmArgs g) {
     }
 }
 
-template <int TILE, int UNR, int WV>
+template <int TILE, int UNR, int WV, int TA, int TB, int KS>
 __global__ __launch_bounds__(64 * WV) void k_gemm(GemmArgs g) {
-  gemm_tile<TILE, UNR, WV>(g);
+  gemm_tile<TILE, UNR, WV, TA, TB, KS>(g);
+}
+
+// k_gemm with the transposes and the k scaling of g fixed at compile time.
+template <int TILE, int UNR, int WV>
+static inline void launch_direct(const GemmArgs& g, dim3 grid, hipStream_t s) {
+  const dim3 block(64 * WV);
+  switch ((g.transA ? 1 : 0) | (g.transB ? 2 : 0) | (g.ks_mode ? 4 : 0)) {
+    case 0: hipLaunchKernelGGL((k_gemm<TILE, UNR, WV, 0, 0, 0>), grid, block, 0, s, g); break;
+    case 1: hipLaunchKernelGGL((k_gemm<TILE, UNR, WV, 1, 0, 0>), grid, block, 0, s, g); break;
+    case 2: hipLaunchKernelGGL((k_gemm<TILE, UNR, WV, 0, 1, 0>), grid, block, 0, s, g); break;
+    case 3: hipLaunchKernelGGL((k_gemm<TILE, UNR, WV, 1, 1, 0>), grid, block, 0, s, g); break;
+    case 4: hipLaunchKernelGGL((k_gemm<TILE, UNR, WV, 0, 0, 1>), grid, block, 0, s, g); break;
+    case 5: hipLaunchKernelGGL((k_gemm<TILE, UNR, WV, 1, 0, 1>), grid, block, 0, s, g); break;
+    case 6: hipLaunchKernelGGL((k_gemm<TILE, UNR, WV, 0, 1, 1>), grid, block, 0, s, g); break;
+    default: hipLaunchKernelGGL((k_gemm<TILE, UNR, WV, 1, 1, 1>), grid, block, 0, s, g); break;
+  }
 }
 
 // Up to three independent products of the same M x N shape in one launch
@@ -559,11 +581,11 @@ static inline hipError_t launch_gemm(const GemmArgs& g, hipStream_t s) {
   // against 27.9 us for two at N = 648)
   const bool deep = nch == 1 && g.K >= 128;
   if (use32) {
-    if (deep) hipLaunchKernelGGL((k_gemm<32, 1, 8>), dim3(t32, nch), dim3(512), 0, s, g);
-    else hipLaunchKernelGGL((k_gemm<32, 1, 4>), dim3(t32, nch), dim3(256), 0, s, g);
+    if (deep) launch_direct<32, 1, 8>(g, dim3(t32, nch), s);
+    else launch_direct<32, 1, 4>(g, dim3(t32, nch), s);
   } else {
-    if (deep) hipLaunchKernelGGL((k_gemm<16, 1, 8>), dim3(t16, nch), dim3(512), 0, s, g);
-    else hipLaunchKernelGGL((k_gemm<16, 1, 4>), dim3(t16, nch), dim3(256), 0, s, g);
+    if (deep) launch_direct<16, 1, 8>(g, dim3(t16, nch), s);
+    else launch_direct<16, 1, 4>(g, dim3(t16, nch), s);
   }
   return hipGetLastError();
 }
