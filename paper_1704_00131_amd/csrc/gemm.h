@@ -164,9 +164,31 @@ static inline void launch_direct(const GemmArgs& g, dim3 grid, hipStream_t s) {
 // (blockIdx.z picks the product), so small products fill more of the chip.
 struct GemmGroup { GemmArgs g[3]; };
 
-template <int TILE, int UNR, int WV>
+template <int TILE, int UNR, int WV, int TA, int TB, int KS>
 __global__ __launch_bounds__(64 * WV) void k_gemm_group(GemmGroup gg) {
-  gemm_tile<TILE, UNR, WV>(gg.g[blockIdx.z]);
+  gemm_tile<TILE, UNR, WV, TA, TB, KS>(gg.g[blockIdx.z]);
+}
+
+// k_gemm_group with the transposes and the k scaling fixed at compile time
+// when all products of the group agree on them, else read per product.
+template <int TILE, int UNR, int WV>
+static inline void launch_group_direct(const GemmGroup& gg, int count, dim3 grid, hipStream_t s) {
+  const dim3 block(64 * WV);
+  auto code_of = [](const GemmArgs& g) { return (g.transA ? 1 : 0) | (g.transB ? 2 : 0) | (g.ks_mode ? 4 : 0); };
+  int code = code_of(gg.g[0]);
+  for (int i = 1; i < count; ++i)
+    if (code_of(gg.g[i]) != code) code = 8;
+  switch (code) {
+    case 0: hipLaunchKernelGGL((k_gemm_group<TILE, UNR, WV, 0, 0, 0>), grid, block, 0, s, gg); break;
+    case 1: hipLaunchKernelGGL((k_gemm_group<TILE, UNR, WV, 1, 0, 0>), grid, block, 0, s, gg); break;
+    case 2: hipLaunchKernelGGL((k_gemm_group<TILE, UNR, WV, 0, 1, 0>), grid, block, 0, s, gg); break;
+    case 3: hipLaunchKernelGGL((k_gemm_group<TILE, UNR, WV, 1, 1, 0>), grid, block, 0, s, gg); break;
+    case 4: hipLaunchKernelGGL((k_gemm_group<TILE, UNR, WV, 0, 0, 1>), grid, block, 0, s, gg); break;
+    case 5: hipLaunchKernelGGL((k_gemm_group<TILE, UNR, WV, 1, 0, 1>), grid, block, 0, s, gg); break;
+    case 6: hipLaunchKernelGGL((k_gemm_group<TILE, UNR, WV, 0, 1, 1>), grid, block, 0, s, gg); break;
+    case 7: hipLaunchKernelGGL((k_gemm_group<TILE, UNR, WV, 1, 1, 1>), grid, block, 0, s, gg); break;
+    default: hipLaunchKernelGGL((k_gemm_group<TILE, UNR, WV, -1, -1, -1>), grid, block, 0, s, gg); break;
+  }
 }
 
 // Large products: a 64 x 64 tile per workgroup, K in steps of 32 staged
@@ -531,12 +553,12 @@ static inline hipError_t launch_gemm_group(const GemmGroup& gg, int count, hipSt
   const bool use32 = g.tile == 32 || (g.tile != 16 && (long long)t32 * nch * count >= 192);
   const bool deep = nch == 1 && g.K >= 128;
   if (use32) {
-    if (deep) hipLaunchKernelGGL((k_gemm_group<32, 2, 8>), dim3(t32, nch, count), dim3(512), 0, s, gg);
-    else hipLaunchKernelGGL((k_gemm_group<32, 1, 4>), dim3(t32, nch, count), dim3(256), 0, s, gg);
+    if (deep) launch_group_direct<32, 2, 8>(gg, count, dim3(t32, nch, count), s);
+    else launch_group_direct<32, 1, 4>(gg, count, dim3(t32, nch, count), s);
   } else {
     const int t16 = ((g.M + 15) / 16) * ((g.N + 15) / 16);
-    if (deep) hipLaunchKernelGGL((k_gemm_group<16, 1, 8>), dim3(t16, nch, count), dim3(512), 0, s, gg);
-    else hipLaunchKernelGGL((k_gemm_group<16, 1, 4>), dim3(t16, nch, count), dim3(256), 0, s, gg);
+    if (deep) launch_group_direct<16, 1, 8>(gg, count, dim3(t16, nch, count), s);
+    else launch_group_direct<16, 1, 4>(gg, count, dim3(t16, nch, count), s);
   }
   return hipGetLastError();
 }
