@@ -36,7 +36,11 @@ enum { PC_A = 1, PC_B = 2, PC_C = 4, PC_RS = 8, PC_CS = 16, PC_KS = 32 };
 
 // TA, TB, KS: the transposes and whether the k scaling is present, fixed at
 // compile time (0 or 1) or read from g (-1); the fixed forms keep the runtime
-// selects out of the K loop (23.0 against 25.9 us for a 648^3 product).
+// selects out of the K loop (a 648^3 product: 24.8 against 25.9 us on 32 x 32
+// tiles, 36.0 against 39.4 us on 16 x 16 tiles).  With KS = 1 each wave first
+// evaluates the k scaling of its K range once into LDS (an exponential of the
+// field for the downward wrap and the left chunk products), instead of every
+// lane evaluating it at every step.
 template <int TILE, int UNR, int WV, int TA = -1, int TB = -1, int KS = -1>
 __device__ __forceinline__ void gemm_tile(GemmArgs g) {
   constexpr int NB = TILE / 16;
@@ -60,6 +64,17 @@ __device__ __forceinline__ void gemm_tile(GemmArgs g) {
   // contiguous K range of this wave, a multiple of 4 long
   const int kq = ((g.K + 4 * WV - 1) / (4 * WV)) * 4;
   const int kb = w * kq, ke = min(g.K, kb + kq);
+  const double* kst = nullptr;   // the k scaling of this wave's range, when staged
+  if constexpr (KS == 1) {
+    constexpr int KSMAX = 1024 / WV;
+    __shared__ double ksh[WV][KSMAX];
+    if (kq <= KSMAX) {   // uniform
+      for (int e = lane; e < kq; e += 64)
+        ksh[w][e] = (kb + e < ke) ? scale_of(g.ks_mode, g.ks, g.ks_coef, kb + e) : 1.0;
+      kst = ksh[w];
+    }
+    __syncthreads();
+  }
   v4d acc[NB][NB];
 #pragma unroll
   for (int a = 0; a < NB; ++a)
@@ -90,7 +105,8 @@ __device__ __forceinline__ void gemm_tile(GemmArgs g) {
     for (int u = 0; u < UNR; ++u) {
       const int k = kc + 4 * u + lk;
       const bool kin = k < ke;
-      const double ksc = (kin && ksm) ? scale_of(g.ks_mode, g.ks, g.ks_coef, k) : 1.0;
+      const double ksc =
+          (kin && ksm) ? (kst ? kst[k - kb] : scale_of(g.ks_mode, g.ks, g.ks_coef, k)) : 1.0;
 #pragma unroll
       for (int a = 0; a < NB; ++a) av[u][a] = (kin && i0 + a * 16 + l16 < g.M) ? av[u][a] * ksc : 0.0;
 #pragma unroll
