@@ -425,15 +425,17 @@ __device__ __forceinline__ void gemm32l_load(const GemmArgs& g, int m0, int n0, 
   }
 }
 
-// Zero outside the matrices, apply the k scaling, store into one LDS buffer.
+// Zero outside the matrices, apply the k scaling (from ksl when staged),
+// store into one LDS buffer.
 template <int TA, int TB>
 __device__ __forceinline__ void gemm32l_store(const GemmArgs& g, int m0, int n0, int k0, double (&ra)[4],
-                                              double (&rb)[4], double* As, double* Bs) {
+                                              double (&rb)[4], double* As, double* Bs, const double* ksl) {
   const int t = threadIdx.x, a = t >> 5, b = t & 31;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int ai = TA ? m0 + b : m0 + a + 8 * q, ak = TA ? k0 + a + 8 * q : k0 + b;
-    const double ksc = (g.ks_mode && ak < g.K) ? scale_of(g.ks_mode, g.ks, g.ks_coef, ak) : 1.0;
+    const double ksc =
+        (g.ks_mode && ak < g.K) ? (ksl ? ksl[ak] : scale_of(g.ks_mode, g.ks, g.ks_coef, ak)) : 1.0;
     const double av = (ai < g.M && ak < g.K) ? ra[q] * ksc : 0.0;
     const int bj = TB ? n0 + a + 8 * q : n0 + b, bk = TB ? k0 + b : k0 + a + 8 * q;
     const double bv = (bj < g.N && bk < g.K) ? rb[q] : 0.0;
@@ -460,6 +462,15 @@ __device__ __forceinline__ void gemm32l_tile(GemmArgs g, int ntiles) {
     if (g.pc & PC_KS) g.ks += co;
   }
   __shared__ double sl[2][kL32Asz + kL32Bsz];
+  // the k scaling, evaluated once per workgroup (K <= 512, keeping four
+  // workgroups per CU in LDS), not once per staged element
+  __shared__ double ksl[512];
+  const double* ks_staged = nullptr;
+  if (g.ks_mode && g.K <= 512) {   // uniform
+    for (int e = threadIdx.x; e < g.K; e += 256) ksl[e] = scale_of(g.ks_mode, g.ks, g.ks_coef, e);
+    __syncthreads();
+    ks_staged = ksl;
+  }
   const int tilesN = (g.N + kL32 - 1) / kL32;
   const int m0 = (tile / tilesN) * kL32, n0 = (tile % tilesN) * kL32;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -485,17 +496,17 @@ __device__ __forceinline__ void gemm32l_tile(GemmArgs g, int ntiles) {
   double ra0[4], rb0[4], ra1[4], rb1[4];
   gemm32l_load<TA, TB>(g, m0, n0, 0, ra0, rb0);
   if (nt > 1) gemm32l_load<TA, TB>(g, m0, n0, kL32K, ra1, rb1);
-  gemm32l_store<TA, TB>(g, m0, n0, 0, ra0, rb0, sl[0], sl[0] + kL32Asz);
+  gemm32l_store<TA, TB>(g, m0, n0, 0, ra0, rb0, sl[0], sl[0] + kL32Asz, ks_staged);
   __syncthreads();
   for (int t = 0; t < nt; t += 2) {
     if (t + 2 < nt) gemm32l_load<TA, TB>(g, m0, n0, (t + 2) * kL32K, ra0, rb0);
     mfmas(sl[0]);
-    if (t + 1 < nt) gemm32l_store<TA, TB>(g, m0, n0, (t + 1) * kL32K, ra1, rb1, sl[1], sl[1] + kL32Asz);
+    if (t + 1 < nt) gemm32l_store<TA, TB>(g, m0, n0, (t + 1) * kL32K, ra1, rb1, sl[1], sl[1] + kL32Asz, ks_staged);
     __syncthreads();
     if (t + 1 >= nt) break;
     if (t + 3 < nt) gemm32l_load<TA, TB>(g, m0, n0, (t + 3) * kL32K, ra1, rb1);
     mfmas(sl[1]);
-    if (t + 2 < nt) gemm32l_store<TA, TB>(g, m0, n0, (t + 2) * kL32K, ra0, rb0, sl[0], sl[0] + kL32Asz);
+    if (t + 2 < nt) gemm32l_store<TA, TB>(g, m0, n0, (t + 2) * kL32K, ra0, rb0, sl[0], sl[0] + kL32Asz, ks_staged);
     __syncthreads();
   }
   const int col = n0 + jb;
