@@ -605,8 +605,9 @@ dqmc_status set_lds_limits(dqmc_ctx* c) {
   if (c->N > kWideMinN && c->N <= kAccumWideMaxN) {
     HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(k_accum_q_wide<1>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)accum_q_lds<1>(c->N)));
-    HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(k_accum_q_wide<2>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)accum_q_lds<2>(c->N)));
+    if (c->N <= kAccumPairMaxN)
+      HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(k_accum_q_wide<2>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)accum_q_lds<2>(c->N)));
   }
   if (!c->cplx && c->N <= kChunkMaxN) {
     const void* fns[] = {reinterpret_cast<const void*>(k_chunk<1>), reinterpret_cast<const void*>(k_chunk<2>),
@@ -652,10 +653,17 @@ dqmc_status qr_udv(dqmc_ctx* c, double* M, const double* T_in, UDVp out) {
   // the sixteen-wave accumulation pays for the tall 16-wide panels of large N
   // and a lone chain leaves the chip idle; batches keep the four-wave kernel
   if (N > kWideMinN && N <= kAccumWideMaxN && c->nch == 1) {
-    if (nb > 16)
+    if (nb > 16) {
       hipLaunchKernelGGL(k_accum_q_wide<2>, gridc(c, (unsigned)((N + 15) / 16)), dim3(64 * kAccumWaves),
                          accum_q_lds<2>(N), c->stream, c->Vall, c->VTall, out.Q, N, nb, c->cs);
-    else
+    } else if (N <= kAccumPairMaxN) {
+      // pairs of 16-column panels joined into 32-column blocks (in Zq and Rt,
+      // both free here): 21 dependent steps instead of 41 at N = 648
+      hipLaunchKernelGGL(k_wy_pair, gridc(c, (unsigned)((N + 31) / 32)), dim3(64 * kPairWaves), 0, c->stream, c->Vall, c->VTall,
+                         c->Zq, c->Rt, N, c->cs);
+      hipLaunchKernelGGL(k_accum_q_wide<2>, gridc(c, (unsigned)((N + 15) / 16)), dim3(64 * kAccumWaves),
+                         accum_q_lds<2>(N), c->stream, c->Zq, c->Rt, out.Q, N, 32, c->cs);
+    } else
       hipLaunchKernelGGL(k_accum_q_wide<1>, gridc(c, (unsigned)((N + 15) / 16)), dim3(64 * kAccumWaves),
                          accum_q_lds<1>(N), c->stream, c->Vall, c->VTall, out.Q, N, nb, c->cs);
   } else {

@@ -353,6 +353,7 @@ __global__ __launch_bounds__(256) void k_accum_q(const double* Vall, const doubl
 // Dynamic LDS: the slab (n x 16) and the per-wave partials (16 KT x 4 x 64).
 constexpr int kAccumWaves = 16;
 constexpr int kAccumWideMaxN = 960;   // the slab and the partials within the LDS of one workgroup
+constexpr int kAccumPairMaxN = 728;   // likewise with 32-column blocks (KT = 2)
 template <int KT>
 __host__ __device__ inline size_t accum_q_lds(int n) {
   return sizeof(double) * (16 * (size_t)n + (size_t)kAccumWaves * KT * 4 * 64);
@@ -386,6 +387,111 @@ __global__ __launch_bounds__(1024) void k_accum_q_wide(const double* Vall, const
   for (int e = tid; e < n * 16; e += 1024) {
     const int r = e >> 4, c = e & 15;
     if (c < ncol) Q[(size_t)r * n + c0 + c] = qs[e];
+  }
+}
+
+// Two consecutive block reflectors of 16-column panels as one block of up to
+// 32 columns, so that the backward accumulation of Q takes half the dependent
+// steps.  With H_a = I - P_a S_a^T, H_b = I - P_b S_b^T (P = V T, S = V;
+// panel b starts 16 rows below panel a):
+//   H_a H_b = I - [P_a, P_b - P_a (S_a^T P_b)] [S_a, S_b]^T.
+// Block k is written at column j0 = 32 k in the panels' own layout (height
+// n - j0, leading dimension its width min(32, n - j0)); a lone last panel is
+// copied.  Grid (ceil(n / 32), chains), 1024 threads: M = S_a^T P_b with
+// every wave's loads issued in one round (rows up to 16 x 4 x kPairUZ), then
+// the new columns P_b - P_a M by MFMA, 16 rows per tile.
+constexpr int kPairWaves = 16, kPairUZ = 12;
+__global__ __launch_bounds__(1024) void k_wy_pair(const double* Vall, const double* VTall, double* Sout, double* Pout,
+                                                  int n, size_t cs) {
+  __shared__ double Mz[kPairWaves][4][64];   // per-wave partials of M in the MFMA D layout
+  __shared__ double Ms[16][17];
+  {
+    const size_t co = (size_t)blockIdx.y * cs;
+    Vall += co; VTall += co; Sout += co; Pout += co;
+  }
+  const int j0 = 32 * blockIdx.x, ha = n - j0, wc = min(32, ha);
+  const int nbwa = min(16, ha), nbwb = wc - nbwa, hb = ha - 16;
+  const double* Va = Vall + (size_t)j0 * n;
+  const double* Pa = VTall + (size_t)j0 * n;
+  double* S = Sout + (size_t)j0 * n;
+  double* P = Pout + (size_t)j0 * n;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (nbwb <= 0) {   // uniform: a lone panel keeps its layout (width nbwa)
+    for (int e = tid; e < ha * nbwa; e += 1024) {
+      S[e] = Va[e];
+      P[e] = Pa[e];
+    }
+    return;
+  }
+  const double* Vb = Vall + (size_t)(j0 + 16) * n;
+  const double* Pb = VTall + (size_t)(j0 + 16) * n;
+  const int m16 = lane & 15, kk = lane >> 4, cb = min(m16, nbwb - 1);
+  // M = S_a^T P_b over the rows of panel b (row r of b is row r + 16 of a)
+  {
+    const int kq = ((hb + 4 * kPairWaves - 1) / (4 * kPairWaves)) * 4;
+    const int kb = w * kq, ke = min(hb, kb + kq);
+    v4d z = {0.0, 0.0, 0.0, 0.0};
+    for (int kc = kb; kc < ke; kc += 4 * kPairUZ) {   // uniform; one round while hb <= 16 * 4 * kPairUZ
+      double a[kPairUZ], bv[kPairUZ];
+#pragma unroll
+      for (int u = 0; u < kPairUZ; ++u) {
+        const int rc = min(kc + 4 * u + kk, hb - 1);
+        a[u] = Va[(size_t)(rc + 16) * 16 + m16];
+        bv[u] = Pb[(size_t)rc * nbwb + cb];
+      }
+#pragma unroll
+      for (int u = 0; u < kPairUZ; ++u) {
+        const bool rin = kc + 4 * u + kk < ke;
+        z = mfma_f64_16x16x4(rin ? a[u] : 0.0, (rin && m16 < nbwb) ? bv[u] : 0.0, z);
+      }
+    }
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) Mz[w][rr][lane] = z[rr];
+  }
+  // meanwhile-independent copies: S = [S_a, S_b shifted down 16 rows], P's first 16 columns
+  for (int e = tid; e < ha * 16; e += 1024) {
+    const int r = e >> 4, q = e & 15;
+    S[(size_t)r * wc + q] = Va[e];
+    P[(size_t)r * wc + q] = Pa[e];
+    if (q < nbwb) S[(size_t)r * wc + 16 + q] = r >= 16 ? Vb[(size_t)(r - 16) * nbwb + q] : 0.0;
+  }
+  __syncthreads();
+  if (w == 0) {
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      double v = 0.0;
+#pragma unroll
+      for (int q = 0; q < kPairWaves; ++q) v += Mz[q][rr][lane];
+      Ms[kk + 4 * rr][m16] = v;
+    }
+  }
+  __syncthreads();
+  // P's last columns: P_b (shifted) - P_a M, one 16-row tile per wave and step
+  double mb[4];
+#pragma unroll
+  for (int k4 = 0; k4 < 4; ++k4) mb[k4] = -Ms[4 * k4 + kk][m16];
+  const int nrt = (ha + 15) / 16;
+  for (int t = w; t < nrt; t += kPairWaves) {   // uniform
+    v4d acc;
+    double pa[4];
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const int r = 16 * t + kk + 4 * rr, rb = min(max(r - 16, 0), hb - 1);
+      const double v = Pb[(size_t)rb * nbwb + cb];
+      acc[rr] = (r >= 16 && r < ha && m16 < nbwb) ? v : 0.0;
+    }
+    const int ra = min(16 * t + m16, ha - 1);
+#pragma unroll
+    for (int k4 = 0; k4 < 4; ++k4) pa[k4] = Pa[(size_t)ra * 16 + 4 * k4 + kk];
+#pragma unroll
+    for (int k4 = 0; k4 < 4; ++k4) acc = mfma_f64_16x16x4(pa[k4], mb[k4], acc);
+    if (m16 < nbwb) {
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int r = 16 * t + kk + 4 * rr;
+        if (r < ha) P[(size_t)r * wc + 16 + m16] = acc[rr];
+      }
+    }
   }
 }
 
