@@ -125,6 +125,17 @@ def test_sweep_parity_four_valued_honeycomb12_one_sweep():
     _trajectory("honeycomb", 12, 12, 4.0, 10.0, 5, "asym", 0, 1, field="ising4")
 
 
+@pytest.mark.parametrize("kind,L1,L2", [("square", 21, 21), ("honeycomb", 15, 15)])
+def test_sweep_parity_wide_ragged_one_sweep(kind, L1, L2):
+    """Lattices above N = 384 (the single-chain path of 64-row update tiles,
+    sixteen-wave Q accumulation over pairs of 16-column reflectors and the
+    LDS-resident back substitution) with ragged ends: N = 441 (the last pair
+    of panels has a 9-column second panel) and N = 450 (a lone 2-column last
+    panel); U=4, beta=1, L=10, n_wrap=5, one sweep."""
+    _log(f"trajectory {kind} {L1}x{L2} 1 sweep")
+    _trajectory(kind, L1, L2, 4.0, 1.0, 5, "asym", 0, 1)
+
+
 def test_sweep_parity_honeycomb12_one_sweep():
     """Honeycomb 12x12 (N = 288), U=4, beta=10, L=100: one sweep."""
     _log("trajectory honeycomb 12x12 1 sweep")
