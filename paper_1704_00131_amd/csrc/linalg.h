@@ -1268,7 +1268,7 @@ __global__ __launch_bounds__(256) void k_lu_back(double* XA, int n, int ld, int 
 // Y_b is formed (they do not depend on it), so a step costs one global
 // latency and two barriers.  The products and their order are those of
 // k_lu_back.  Dynamic LDS: back_wide_lds(n).
-constexpr int kBackWaves = 8, kBackWideMaxN = 768, kBackRS = kBackCols + 1;
+constexpr int kBackWaves = 16, kBackWideMaxN = 768, kBackRS = kBackCols + 1;
 __host__ __device__ inline size_t back_wide_lds(int n) { return sizeof(double) * (size_t)n * kBackRS; }
 
 __global__ __launch_bounds__(64 * kBackWaves) void k_lu_back_wide(double* XA, int n, int ld, int nb, int nrhs,
