@@ -834,7 +834,7 @@ dqmc_status copy_udv(dqmc_ctx* c, UDVp dst, UDVp src) {
 
 dqmc_status stabilise(dqmc_ctx* c, int hist_index) {
   const size_t NN = (size_t)c->N * c->N;
-  hipLaunchKernelGGL(k_prec_replace, gridc(c, (unsigned)std::min<size_t>(grid1(NN), 1024)), dim3(256), 0, c->stream,
+  hipLaunchKernelGGL(k_prec_replace, gridc(c, prec_grid(NN)), dim3(256), 0, c->stream,
                      c->Gcur, c->G, c->Gs, NN, c->prec_hist + hist_index, c->err_flag, c->cs);
   HIPCHK(hipGetLastError());
   c->Gcur = c->G;
@@ -1383,7 +1383,7 @@ dqmc_status grad_pass(dqmc_ctx* c) {
       b ^= 1;
       UDVp left = (k == nk) ? c->uid : c->slot(k);
       if (dqmc_status s = merge(c, right, left, c->Gs, nullptr)) return s;
-      hipLaunchKernelGGL(k_prec_replace, gridc(c, (unsigned)std::min<size_t>(grid1(NN), 1024)), dim3(256), 0,
+      hipLaunchKernelGGL(k_prec_replace, gridc(c, prec_grid(NN)), dim3(256), 0,
                          c->stream, c->G2, c->G2, c->Gs, NN, c->gprec, c->err_flag, c->cs);
       HIPCHK(hipGetLastError());
     }
@@ -1429,7 +1429,7 @@ dqmc_status td_anchor(dqmc_ctx* c, UDVp R, UDVp Lf, double* gt0, double* h) {
                      N, c->cs, is_shared(c, R.Q) ? (size_t)0 : c->cs);
   HIPCHK(hipGetLastError());
   if (dqmc_status s = lu_solve(c, c->XA, 2 * N, ld, nullptr)) return s;
-  const unsigned pg = (unsigned)std::min<size_t>(grid1(NN), 1024);
+  const unsigned pg = prec_grid(NN);
   GemmArgs g3 = gemm_args(N, N, N, Lf.Q, N, 0, c->XA + N, ld, 0, c->Gs, N);
   g3.ks = Lf.D; g3.ks_mode = SC_INV_BIG;
   if (dqmc_status s = gemm(c, g3)) return s;

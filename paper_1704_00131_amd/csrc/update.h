@@ -442,6 +442,14 @@ __global__ void k_ratio(const double* G, int N, int site, const double* field_ro
 }
 
 // max |Gw - Gs| into prec_slot (zero on entry), G <- Gs, NaN/Inf check.
+// Each workgroup takes kPrecPer x 256 consecutive elements per round (all of
+// a thread's loads in flight together), so that few workgroups, and few
+// atomics on the one slot, cover the matrix: prec_grid(count) of them.
+constexpr int kPrecPer = 8;
+inline unsigned prec_grid(size_t count) {
+  const size_t g = (count + 256 * kPrecPer - 1) / (256 * kPrecPer);
+  return (unsigned)(g < 1024 ? (g > 0 ? g : 1) : 1024);
+}
 __global__ __launch_bounds__(256) void k_prec_replace(const double* Gw, double* G, const double* Gs, size_t count,
                                                       double* prec_slot, int* err, size_t cs) {
   __shared__ double red[8];
@@ -451,12 +459,22 @@ __global__ __launch_bounds__(256) void k_prec_replace(const double* Gw, double* 
     err = reinterpret_cast<int*>(reinterpret_cast<double*>(err) + co);
   }
   double m = 0.0, bad = 0.0;
-  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (size_t)gridDim.x * 256) {
-    const double gs = Gs[e];
-    const double d = fabs(Gw[e] - gs);
-    m = fmax(m, d);
-    if (!isfinite(gs)) bad = 1.0;
-    G[e] = gs;
+  for (size_t e0 = (size_t)blockIdx.x * 256 * kPrecPer + threadIdx.x; e0 < count;
+       e0 += (size_t)gridDim.x * 256 * kPrecPer) {
+    double gs[kPrecPer], gw[kPrecPer];
+#pragma unroll
+    for (int u = 0; u < kPrecPer; ++u) {
+      const size_t e = e0 + 256 * (size_t)u;
+      gs[u] = e < count ? Gs[e] : 0.0;
+      gw[u] = e < count ? Gw[e] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kPrecPer; ++u) {
+      const size_t e = e0 + 256 * (size_t)u;
+      m = fmax(m, fabs(gw[u] - gs[u]));
+      if (!isfinite(gs[u])) bad = 1.0;
+      if (e < count) G[e] = gs[u];
+    }
   }
   m = block_max<256>(m, red);
   bad = block_max<256>(bad, red);
