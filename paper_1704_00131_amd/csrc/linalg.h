@@ -78,38 +78,66 @@ constexpr int kColRows = 16;
 __global__ __launch_bounds__(256) void k_colnorm_part(const double* M, int n, double* part, size_t cs) {
   M += (size_t)blockIdx.y * cs;
   part += (size_t)blockIdx.y * cs;
-  const int r0 = blockIdx.x * kColRows, r1 = min(n, r0 + kColRows);
+  const int r0 = blockIdx.x * kColRows;
   for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    double x[kColRows];   // every row's load in flight before the sum
+#pragma unroll
+    for (int r = 0; r < kColRows; ++r) x[r] = M[(size_t)min(r0 + r, n - 1) * n + j];
     double s = 0.0;
-    for (int r = r0; r < r1; ++r) { const double x = M[(size_t)r * n + j]; s += x * x; }
+#pragma unroll
+    for (int r = 0; r < kColRows; ++r)
+      if (r0 + r < n) s += x[r] * x[r];
     part[(size_t)blockIdx.x * n + j] = s;
   }
 }
 
-// piv[p] = index of the column with the p-th largest 2-norm (ties: lower index)
+// piv[p] = index of the column with the p-th largest 2-norm (ties: lower
+// index): the partial sums added in row-block order, then a bitonic sort of
+// (norm descending, index ascending) pairs in LDS, one per thread (n <= 1024;
+// the padding sorts last).  The order is total, so the result is the unique
+// sorted permutation.
 __global__ __launch_bounds__(1024) void k_colnorm_order(const double* part, int nblk, int n, double* norms, int* piv,
                                                         size_t cs) {
-  __shared__ double sn[1024];   // n <= 1024: the norms, read back as LDS broadcasts by the ranking
+  __shared__ double sk[1024];
+  __shared__ int si[1024];
   part += (size_t)blockIdx.y * cs;
   norms += (size_t)blockIdx.y * cs;
   piv = reinterpret_cast<int*>(reinterpret_cast<double*>(piv) + (size_t)blockIdx.y * cs);
-  for (int j = threadIdx.x; j < n; j += blockDim.x) {
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * n + j];
-    s = (s == s) ? s : INFINITY;   // a NaN column sorts first; ranks stay a permutation
-    norms[j] = s;
-    sn[j] = s;
-  }
-  __syncthreads();
-  for (int j = threadIdx.x; j < n; j += blockDim.x) {
-    const double v = sn[j];
-    int rank = 0;
-    for (int i = 0; i < n; ++i) {
-      const double u = sn[i];
-      rank += (u > v) || (u == v && i < j);
+  const int t = threadIdx.x;
+  double s = -1.0;
+  if (t < n) {
+    s = 0.0;
+    constexpr int U = 8;
+    for (int b0 = 0; b0 < nblk; b0 += U) {
+      double x[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) x[u] = part[(size_t)min(b0 + u, nblk - 1) * n + t];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (b0 + u < nblk) s += x[u];
     }
-    piv[rank] = j;
+    s = (s == s) ? s : INFINITY;   // a NaN column sorts first; the order stays a permutation
+    norms[t] = s;
   }
+  sk[t] = s;
+  si[t] = t;
+  __syncthreads();
+  for (int k = 2; k <= 1024; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const int p = t ^ j;
+      if (p > t) {
+        const double ka = sk[t], kb = sk[p];
+        const int ia = si[t], ib = si[p];
+        const bool b_first = (kb > ka) || (kb == ka && ib < ia);
+        if (b_first == ((t & k) == 0)) {
+          sk[t] = kb; sk[p] = ka;
+          si[t] = ib; si[p] = ia;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (t < n) piv[t] = si[t];
 }
 
 __global__ void k_permute_cols(double* dst, const double* src, const int* piv, int n, size_t cs) {
