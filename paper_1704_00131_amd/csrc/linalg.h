@@ -1046,6 +1046,11 @@ __device__ __forceinline__ void lu_prev_slab(double* XA, int n, int ld, int j0p,
   }
   __syncthreads();
   if (tid < sh.nout) odmap[sh.od[tid] - jb] = (short)tid;
+  // the rows moved out of the panel, every thread one entry (all in flight)
+  for (int e = tid; e < sh.nout * 16; e += 256) {
+    const int i = e >> 4, q = e & 15;
+    sh.mv[i][q] = XA[(size_t)sh.os[i] * ld + min(c0 + q, ncols - 1)];
+  }
   if (tid < 16) {
     // the slab's panel rows (reversed: x[31 - k] is row j0p + k), solved with L11
     const int col = c0 + tid, colc = min(col, ncols - 1);
@@ -1054,7 +1059,6 @@ __device__ __forceinline__ void lu_prev_slab(double* XA, int n, int ld, int j0p,
     for (int k = 0; k < 32; ++k) x[31 - k] = XA[(size_t)sh.srcrow[k] * ld + colc];
 #pragma unroll
     for (int k = 0; k < 32; ++k) x[31 - k] = (k < nbp) ? x[31 - k] : 0.0;
-    for (int i = 0; i < sh.nout; ++i) sh.mv[i][tid] = XA[(size_t)sh.os[i] * ld + colc];
     tri_solve_back<true>(x, sh.lr, nullptr);
 #pragma unroll
     for (int k = 0; k < 32; ++k) sh.u12[31 - k][tid] = x[k];
